@@ -1,0 +1,310 @@
+"""Plain FP64 CPU oracle for the adjoint-guided wave-propagation hot path.
+
+TEST INFRASTRUCTURE ONLY: only the test suite, the smoke check and the
+benchmark's CPU-baseline leg import this package.  It shares no code with the
+HIP library (``paper_1511_03645_amd``) and never imports it.
+
+Pieces and the passages of Davis & LeVeque (arXiv:1511.03645) they follow:
+
+* ``run``            – uniform-grid time stepping (Sec. 3 wave propagation;
+                       C code in ``wp_oracle.c``), forward acoustics in wave
+                       form, time-reversed adjoint in f-wave form (Sec. 2, 4),
+                       shallow water and its linearised adjoint (Sec. 5.3).
+* ``phi``            – target functional's weight, an indicator sampled at cell
+                       centres (eq. phi_1d/delta_1d, phi_2d/delta_2d,
+                       phi_Alaska/delta_Alaska).
+* ``functional``     – J = int phi^T q dx (eq. J_general), exactly rounded sum.
+* ``inner_integral`` – int qhat^T q dx, constant in t (eq. q_equality, eq. J).
+* ``snapshot_window``/``flag`` – the adjoint-guided flag: max over the saved
+                       adjoint snapshots bracketing the time window of
+                       |qhat^T q|, against a tolerance (Sec. 4; Sec. 5.1.2 time
+                       range), with bilinear interpolation from the adjoint
+                       grid (Sec. 4).
+* ``amr``            – coarse/fine transfer, Berger-Oliger stepping and
+                       Berger-Rigoutsos clustering (Sec. 3), in ``oracle.amr``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KIND_INDEX = {"acoustics_fwd": 0, "acoustics_adj": 1, "swe": 2, "lswe_adj": 3}
+
+
+def build(force=True):
+    """Compile the C oracle (gcc, FP64, no contraction, no fast-math)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-std=c11", "-Wall", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.or_run.restype = ctypes.c_double
+        L.or_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                             dp, dp, dp, ctypes.c_int, dp]
+        L.or_patch_step.restype = ctypes.c_double
+        L.or_patch_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, dp, dp, dp,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_fill_ghosts.restype = None
+        L.or_fill_ghosts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ip,
+                                     ctypes.c_int, ctypes.c_int]
+        L.or_make_aux.restype = None
+        L.or_make_aux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
+                                  ctypes.c_double, dp]
+        L.or_rp.restype = None
+        L.or_rp.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double]
+        L.or_tsplit.restype = None
+        L.or_tsplit.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+def riemann(which, direction, ql, qr, al, ar, g=9.81):
+    """One normal Riemann solve of solver `which` at one edge: returns
+    (waves [3][3], speeds [3], amdq [3], apdq [3]).  aux vectors are
+    acoustics (Z, c, rho, K), swe (B,), lswe (hbar, c)."""
+    a = [np.ascontiguousarray(np.resize(np.asarray(v, dtype=np.float64), 4)) for v in (ql, qr, al, ar)]
+    wave = np.zeros((3, 3)); s = np.zeros(3); am = np.zeros(3); ap = np.zeros(3)
+    lib().or_rp(KIND_INDEX[which], direction, *(_dp(v) for v in a), _dp(wave), _dp(s), _dp(am), _dp(ap), g)
+    return wave, s, am, ap
+
+
+def transverse_split(which, tdir, d, alo, aown, ahi, ql=(0, 0, 0), qr=(0, 0, 0), al=(0,), ar=(0,), g=9.81):
+    """Transverse split of fluctuation d living in cell `own` along tdir:
+    returns (B-d, B+d)."""
+    a = [np.ascontiguousarray(np.resize(np.asarray(v, dtype=np.float64), 4))
+         for v in (d, alo, aown, ahi, ql, qr, al, ar)]
+    bm = np.zeros(3); bp = np.zeros(3)
+    lib().or_tsplit(KIND_INDEX[which], tdir, *(_dp(v) for v in a), _dp(bm), _dp(bp), g)
+    return bm, bp
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def set_threads(n):
+    """Number of OpenMP threads the C oracle uses (its row loops)."""
+    os.environ["OMP_NUM_THREADS"] = str(n)
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(ctypes.c_int(n))
+    except OSError:
+        pass
+
+
+# ---------------------------------------------------------------------------
+# uniform-grid time stepping
+# ---------------------------------------------------------------------------
+def run(cfg, which, q, nsteps, dt=None, snap_every=0, order=None, limiter=None,
+        transverse=None, bc=None):
+    """Advance the interior state q ([m][ny][nx]) by `nsteps` steps of size dt.
+
+    which: 'acoustics_fwd' | 'acoustics_adj' | 'swe' | 'lswe_adj'.
+    Returns (q_new, snaps or None, max Courant number).  Snapshots (every
+    `snap_every` steps, step 0 included) are [nsnap][m][ny][nx].
+    """
+    L = lib()
+    dim = 1 if cfg["kind"] == "acoustics1d" else 2
+    nx, ny = cfg["nx"], (1 if dim == 1 else cfg["ny"])
+    m = 2 if dim == 1 else 3
+    q = np.ascontiguousarray(np.array(q, dtype=np.float64).reshape(m, ny, nx))
+    dt = cfg["dt"] if dt is None else dt
+    w = KIND_INDEX[which]
+    if which.startswith("acoustics"):
+        c1 = np.ascontiguousarray(cfg["rho"], dtype=np.float64).reshape(ny, nx)
+        c2 = np.ascontiguousarray(cfg["K"], dtype=np.float64).reshape(ny, nx)
+    else:
+        c1 = np.ascontiguousarray(cfg["B"], dtype=np.float64).reshape(ny, nx)
+        c2 = c1
+    bcs = np.array(cfg["bc"] if bc is None else bc, dtype=np.int32)
+    snaps = None
+    if snap_every:
+        ns = nsteps // snap_every + 1
+        snaps = np.zeros((ns, m, ny, nx))
+    cfl = L.or_run(w, dim, nx, ny, cfg["dx"], cfg["dy"], dt, nsteps, _ip(bcs),
+                   cfg["order"] if order is None else order,
+                   cfg["limiter"] if limiter is None else limiter,
+                   cfg["transverse"] if transverse is None else transverse,
+                   cfg.get("g", 9.81), _dp(c1), _dp(c2), _dp(q), snap_every,
+                   _dp(snaps) if snaps is not None else ctypes.POINTER(ctypes.c_double)())
+    if cfl < 0:
+        raise FloatingPointError("oracle: non-finite state")
+    return q, snaps, cfl
+
+
+def adjoint_run(cfg, nsteps=None, snap_every=None, **kw):
+    """Time-reversed adjoint (Sec. 4): qtilde(x,0) = phi, solved forward with
+    flux -A^T qtilde; returns the snapshots qtilde(., n ds), which are
+    qhat(., t_f - n ds)."""
+    which = "lswe_adj" if cfg["kind"] == "swe2d" else "acoustics_adj"
+    q0 = phi(cfg)
+    nsteps = cfg["nsteps"] if nsteps is None else nsteps
+    snap_every = cfg["snap_every"] if snap_every is None else snap_every
+    _, snaps, cfl = run(cfg, which, q0, nsteps, snap_every=snap_every, **kw)
+    return snaps, cfl
+
+
+# ---------------------------------------------------------------------------
+# functional and inner products
+# ---------------------------------------------------------------------------
+def centres(cfg):
+    nx = cfg["nx"]
+    ny = 1 if cfg["kind"] == "acoustics1d" else cfg["ny"]
+    x = cfg["xlo"] + (np.arange(nx) + 0.5) * cfg["dx"]
+    y = cfg["ylo"] + (np.arange(ny) + 0.5) * cfg["dy"]
+    return x, y
+
+
+def phi(cfg):
+    """phi = I(x) e_component: the indicator of the target region sampled at
+    cell centres (closed set), eq. phi_1d/delta_1d, phi_2d/delta_2d,
+    phi_Alaska/delta_Alaska, with the scale factor 1."""
+    f = cfg["functional"]
+    x, y = centres(cfg)
+    X, Y = np.meshgrid(x, y)
+    if f["kind"] == "interval":
+        ind = (X >= f["x0"]) & (X <= f["x1"])
+    elif f["kind"] == "box":
+        ind = (X >= f["x0"]) & (X <= f["x1"]) & (Y >= f["y0"]) & (Y <= f["y1"])
+    elif f["kind"] == "disc":
+        dxc = X - f["cx"]
+        dyc = Y - f["cy"]
+        ind = dxc * dxc + dyc * dyc <= f["r"] * f["r"]
+    else:
+        raise ValueError(f["kind"])
+    m = 2 if cfg["kind"] == "acoustics1d" else 3
+    out = np.zeros((m,) + X.shape)
+    out[f["component"]] = ind.astype(np.float64)
+    return out
+
+
+def cell_area(cfg):
+    return cfg["dx"] if cfg["kind"] == "acoustics1d" else cfg["dx"] * cfg["dy"]
+
+
+def inner_integral(a, b, dA):
+    """sum over cells of a^T b * dA, exactly rounded (math.fsum)."""
+    return math.fsum((np.asarray(a, dtype=np.float64) * np.asarray(b, dtype=np.float64)).ravel().tolist()) * dA
+
+
+def functional(cfg, q):
+    """J = int phi^T q dx (eq. J_general)."""
+    return inner_integral(phi(cfg), q, cell_area(cfg))
+
+
+# ---------------------------------------------------------------------------
+# adjoint-guided flagging
+# ---------------------------------------------------------------------------
+WINDOW_SLACK = 1e-9
+
+
+def snapshot_window(t, t_s, t_f, ds, nsnap):
+    """Snapshot indices whose adjoint times bracket the window (Sec. 4 and
+    Sec. 5.1.2).  Snapshot n holds qhat at tau_n = t_f - n ds.  The window
+    is tau in [t, T], T = min(t + t_f - t_s, t_f) (the reading of the time-range
+    derivation; the printed bounds are reversed).  Returned: the inclusive range
+    from the snapshot with the smallest tau >= T up to the one with the largest
+    tau <= t, so both snapshots bracketing each end are included.  Times within
+    1e-9 ds of a snapshot time count as that snapshot's time.
+    """
+    T = min(t + t_f - t_s, t_f)
+    n_hi = math.ceil((t_f - t) / ds - WINDOW_SLACK)
+    n_lo = math.floor((t_f - T) / ds + WINDOW_SLACK)
+    n_lo = max(n_lo, 0)
+    n_hi = max(n_hi, n_lo)
+    if n_hi > nsnap - 1:
+        raise IndexError("flag window reaches before the first stored adjoint time")
+    return n_lo, n_hi
+
+
+def bilinear_weights(n_fine, ratio):
+    """Index and weight of the adjoint-grid cell centres bracketing each fine
+    cell centre when the fine grid refines the adjoint grid by `ratio`
+    (Sec. 4 bilinear interpolation).  Exact in FP64 for power-of-two ratios
+    and clamped at the domain edge."""
+    I = np.arange(n_fine)
+    num = 2 * I + 1 - ratio          # 2*ratio*(fractional coarse index)
+    n_c = n_fine // ratio
+    i0 = np.floor_divide(num, 2 * ratio)
+    i0 = np.clip(i0, 0, max(n_c - 2, 0))
+    w = (num - 2 * ratio * i0) / (2.0 * ratio)
+    w = np.clip(w, 0.0, 1.0)
+    if n_c == 1:
+        w = np.zeros_like(w)
+    return i0, w
+
+
+def interp_snapshot(snap, ratio):
+    """Bilinear interpolation of an adjoint snapshot [m][NY][NX] to the cell
+    centres of a grid refined by `ratio` (identity for ratio 1)."""
+    if ratio == 1:
+        return snap
+    m, NY, NX = snap.shape
+    i0, wx = bilinear_weights(NX * ratio, ratio)
+    j0, wy = bilinear_weights(NY * ratio, ratio)
+    i1 = np.minimum(i0 + 1, NX - 1)
+    j1 = np.minimum(j0 + 1, NY - 1)
+    out = np.empty((m, NY * ratio, NX * ratio))
+    WX = wx[None, :]
+    WY = wy[:, None]
+    for k in range(m):
+        s = snap[k]
+        q00 = s[np.ix_(j0, i0)]
+        q10 = s[np.ix_(j0, i1)]
+        q01 = s[np.ix_(j1, i0)]
+        q11 = s[np.ix_(j1, i1)]
+        out[k] = ((1 - WX) * (1 - WY) * q00 + WX * (1 - WY) * q10) + ((1 - WX) * WY * q01 + WX * WY * q11)
+    return out
+
+
+def flag_measure(q, snaps, n_lo, n_hi, ratio=1, region=None):
+    """m(x) = max over snapshots n_lo..n_hi of |qhat_n(x)^T q(x)| (Sec. 4,
+    Sec. 5.1.2), qhat bilinear from the adjoint grid.  `region` =
+    (i0, j0, nx, ny) restricts to a sub-box of the refined grid."""
+    mval = None
+    for n in range(n_lo, n_hi + 1):
+        qh = interp_snapshot(snaps[n], ratio)
+        if region is not None:
+            i0, j0, nx, ny = region
+            qh = qh[:, j0:j0 + ny, i0:i0 + nx]
+        ip = np.abs(np.sum(qh * q, axis=0))
+        mval = ip if mval is None else np.maximum(mval, ip)
+    return mval
+
+
+def flag(q, snaps, t, t_s, t_f, ds, tol, ratio=1, region=None):
+    """Flags (uint8) and the measure m(x); a cell is flagged iff m > tol
+    (strict, as "exceeds" in Sec. 5.1)."""
+    n_lo, n_hi = snapshot_window(t, t_s, t_f, ds, len(snaps))
+    mval = flag_measure(q, snaps, n_lo, n_hi, ratio, region)
+    return (mval > tol).astype(np.uint8), mval

@@ -1,0 +1,184 @@
+"""Pins of the oracle's functional, window and flag definitions.
+
+* brute force on tiny grids (enumerate snapshot times, interpolate by the
+  explicit bilinear formula, take the max) against the vectorised oracle;
+* the window algebra of the time-range derivation (Sec. 5.1.2);
+* the paper's 1D example (Sec. 5.1, fixture tests/golden/sec51_acoustics_1d.json):
+  the stated sound speeds, the hump splitting into equal halves, transmission
+  and reflection at the interface, and the inner product selecting only the
+  waves that reach the target (Sec. 5.1.1).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "sec51_acoustics_1d.json")
+
+
+def _brute_window(t, t_s, t_f, ds, nsnap):
+    taus = [t_f - n * ds for n in range(nsnap)]
+    eps = 1e-9 * ds
+    T = min(t + t_f - t_s, t_f)
+    lower = max(tau for tau in taus if tau <= t + eps)      # brackets t from below
+    upper = min(tau for tau in taus if tau >= T - eps)      # brackets T from above
+    return [n for n, tau in enumerate(taus) if lower - eps <= tau <= upper + eps]
+
+
+@pytest.mark.parametrize("t,t_s,t_f,ds", [(0.0, 1.0, 1.0, 0.1), (0.35, 1.0, 1.0, 0.1), (0.3, 1.0, 1.0, 0.1),
+                                          (0.05, 0.5, 1.0, 0.1), (0.55, 0.2, 1.0, 0.1), (0.999, 1.0, 1.0, 0.1),
+                                          (2.6, 18.0, 20.0, 0.1), (18.5, 18.0, 20.0, 0.1)])
+def test_window_matches_brute_force(t, t_s, t_f, ds):
+    nsnap = int(round(t_f / ds)) + 1
+    lo, hi = oracle.snapshot_window(t, t_s, t_f, ds, nsnap)
+    assert list(range(lo, hi + 1)) == _brute_window(t, t_s, t_f, ds, nsnap)
+
+
+def test_window_covers_the_time_range_derivation():
+    """For each target time that in [t_s, t_f], the adjoint time
+    tau = t_f - that + t (Sec. 5.1.2) lies inside the selected bracket."""
+    t_f, t_s, ds = 20.0, 18.0, 0.1
+    nsnap = 201
+    for t in np.linspace(0.0, 19.95, 57):
+        lo, hi = oracle.snapshot_window(t, t_s, t_f, ds, nsnap)
+        tau_hi, tau_lo = t_f - lo * ds, t_f - hi * ds
+        for that in np.linspace(max(t_s, t), t_f, 11):
+            tau = t_f - that + t
+            assert tau_lo - 1e-12 <= tau <= tau_hi + 1e-12
+
+
+def test_window_out_of_range_raises():
+    with pytest.raises(IndexError):
+        oracle.snapshot_window(-0.5, 1.0, 1.0, 0.1, 11)
+
+
+def _brute_bilinear(snap, ratio, I, J):
+    m, NY, NX = snap.shape
+    fx = (I + 0.5) / ratio - 0.5
+    fy = (J + 0.5) / ratio - 0.5
+    i0 = min(max(int(math.floor(fx)), 0), NX - 2)
+    j0 = min(max(int(math.floor(fy)), 0), NY - 2)
+    wx = min(max(fx - i0, 0.0), 1.0)
+    wy = min(max(fy - j0, 0.0), 1.0)
+    return np.array([(1 - wx) * (1 - wy) * snap[k, j0, i0] + wx * (1 - wy) * snap[k, j0, i0 + 1]
+                     + (1 - wx) * wy * snap[k, j0 + 1, i0] + wx * wy * snap[k, j0 + 1, i0 + 1]
+                     for k in range(m)])
+
+
+@pytest.mark.parametrize("ratio", [1, 2, 4, 16])
+def test_flag_matches_brute_force(ratio):
+    rng = np.random.default_rng(ratio)
+    NX, NY = 5, 4
+    nsnap, ds, t_f = 7, 0.25, 1.5
+    snaps = rng.uniform(-1, 1, (nsnap, 3, NY, NX))
+    q = rng.uniform(-1, 1, (3, NY * ratio, NX * ratio))
+    for t, t_s in ((0.3, 1.5), (0.5, 1.0), (0.0, 0.2)):
+        fl, mval = oracle.flag(q, snaps, t, t_s, t_f, ds, tol=0.3, ratio=ratio)
+        idx = _brute_window(t, t_s, t_f, ds, nsnap)
+        for J in range(NY * ratio):
+            for I in range(NX * ratio):
+                best = max(abs(float(np.dot(_brute_bilinear(snaps[n], ratio, I, J), q[:, J, I]))) for n in idx)
+                assert abs(best - mval[J, I]) <= 1e-15 * max(1.0, best)
+                if abs(best - 0.3) > 1e-12:
+                    assert fl[J, I] == (best > 0.3)
+
+
+def test_bilinear_reproduces_linear_fields_and_identity():
+    NX, NY = 6, 5
+    X, Y = np.meshgrid(np.arange(NX) + 0.5, np.arange(NY) + 0.5)
+    snap = np.stack([2.0 * X - 3.0 * Y + 1.0, X, Y])
+    assert np.array_equal(oracle.interp_snapshot(snap, 1), snap)
+    r = 4
+    f = oracle.interp_snapshot(snap, r)
+    Xf, Yf = np.meshgrid((np.arange(NX * r) + 0.5) / r, (np.arange(NY * r) + 0.5) / r)
+    inside = (Xf >= 0.5) & (Xf <= NX - 0.5) & (Yf >= 0.5) & (Yf <= NY - 0.5)
+    assert np.abs(f[0] - (2 * Xf - 3 * Yf + 1))[inside].max() < 1e-13
+
+
+def test_functional_phi_sampling():
+    cfg = dict(kind="acoustics2d", nx=8, ny=8, xlo=0.0, xhi=8.0, ylo=0.0, yhi=8.0, dx=1.0, dy=1.0,
+               functional=dict(kind="disc", cx=4.0, cy=4.0, r=1.6, x0=0, x1=0, y0=0, y1=0, component=0))
+    ph = oracle.phi(cfg)
+    # centres at k + 0.5: within radius 1.6 of (4,4): the 4 centres at distance
+    # sqrt(0.5) and 8 at sqrt(2.5); sqrt(4.5) > 1.6 excluded
+    assert ph[0].sum() == 12 and ph[1:].sum() == 0
+    q = np.zeros((3, 8, 8)); q[0] = 2.0
+    assert oracle.functional(cfg, q) == 24.0
+
+
+# ---------------------------------------------------------------------------
+# the paper's 1D example (Sec. 5.1)
+# ---------------------------------------------------------------------------
+def _sec51(t_end, hump=True):
+    g = json.load(open(GOLDEN))
+    a, b = g["domain"]
+    n = g["cells"]
+    dx = (b - a) / n
+    x = a + (np.arange(n) + 0.5) * dx
+    rho = np.where(x < g["interface"], g["rho_left"], g["rho_right"])
+    K = np.full(n, g["K"])
+    cfg = dict(kind="acoustics1d", nx=n, ny=1, xlo=a, xhi=b, ylo=0, yhi=1, dx=dx, dy=1.0,
+               rho=rho.reshape(1, n), K=K.reshape(1, n), bc=[1, 1, 1, 1], order=2, limiter=1, transverse=0,
+               functional=dict(kind="interval", x0=g["target_interval"][0], x1=g["target_interval"][1],
+                               y0=0, y1=0, cx=0, cy=0, r=0, component=0))
+    cmax = 1.0
+    steps = int(math.ceil(t_end / (0.9 * dx / cmax)))
+    q0 = np.stack([np.exp(-g["beta"] * (x - g["hump_centre"]) ** 2), np.zeros(n)]).reshape(2, 1, n)
+    return g, cfg, x, q0, steps
+
+
+def test_sec51_stated_sound_speeds():
+    g = json.load(open(GOLDEN))
+    assert math.sqrt(g["K"] / g["rho_left"]) == g["stated"]["sound_speed_left"]
+    assert math.sqrt(g["K"] / g["rho_right"]) == g["stated"]["sound_speed_right"]
+
+
+def test_sec51_hump_splits_into_equal_halves_then_transmits_and_reflects():
+    g, cfg, x, q0, _ = _sec51(1.0)
+    t1 = 1.0
+    steps = int(math.ceil(t1 / (0.9 * cfg["dx"])))
+    q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, steps, dt=t1 / steps)
+    p = q[0, 0]
+    left, right = p[x < -2], p[x > -2]
+    # equal halves of amplitude 1/2 at x = -3 and x = -1
+    assert abs(left.max() - 0.5) < 0.01 and abs(right.max() - 0.5) < 0.01
+    assert abs(x[x < -2][left.argmax()] + 3.0) < 0.02 and abs(x[x > -2][right.argmax()] + 1.0) < 0.02
+    # t = 3.5: the right-going half has crossed x = 0 where Z goes from 1 to 2:
+    # transmitted pressure (1/2)(4/3) f(2x ...) -- half the width, so area
+    # (1/2)(4/3)(1/2) sqrt(pi/beta), centred at 0.75; reflected (1/2)(1/3) f,
+    # area (1/6) sqrt(pi/beta), centred at -1.5
+    t2 = 3.5
+    steps = int(math.ceil(t2 / (0.9 * cfg["dx"])))
+    q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, steps, dt=t2 / steps)
+    p = q[0, 0]
+    area = math.sqrt(math.pi / g["beta"])
+    tr = p[x > 0]
+    assert abs(tr.sum() * cfg["dx"] - area / 3.0) < 2e-3 * area
+    assert abs(x[x > 0][tr.argmax()] - 0.75) < 0.02
+    sel = (x > -2.5) & (x < 0)
+    assert abs(p[sel].sum() * cfg["dx"] - area / 6.0) < 2e-3 * area
+    assert abs(x[sel][p[sel].argmax()] + 1.5) < 0.02
+
+
+def test_sec51_inner_product_selects_waves_reaching_target():
+    """Sec. 5.1.1: at t = 1 only the right-going half (which later reaches the
+    target through the interface) overlaps the adjoint; the left-going half
+    does not."""
+    g, cfg, x, q0, _ = _sec51(0.0)
+    t_f = 6.1     # transmitted pulse (speed 1/2 beyond x = 0) centred on [1.8, 2.3]
+    ds = 0.1
+    per = int(math.ceil(ds / (0.9 * cfg["dx"])))
+    dt = ds / per
+    nsteps = per * int(round(t_f / ds))
+    snaps, _ = oracle.adjoint_run(cfg, nsteps=nsteps, snap_every=per, dt=dt)
+    n1 = int(round(1.0 / dt))
+    q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, n1, dt=dt)
+    fl, mval = oracle.flag(q, snaps, n1 * dt, t_f, t_f, ds, tol=1e-3)
+    flagged = x[fl[0] == 1]
+    assert flagged.size > 0
+    assert flagged.min() > -1.6 and flagged.max() < -0.4
+    assert not np.any(fl[0][(x > -3.5) & (x < -2.5)])

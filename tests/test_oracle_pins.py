@@ -1,0 +1,490 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed-form
+solutions (d'Alembert, the two-material transmission/reflection solution, the
+exact Riemann solution), exact discrete identities (translation at Courant
+number 1, conservation, the adjoint identity of eq. q_equality / eq. J at first
+order, the change of variables that maps the time-reversed adjoint onto forward
+acoustics), symmetries, and the lake at rest.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import oracle
+
+BC_EXTRAP, BC_WALL, BC_PERIODIC = 0, 1, 2
+
+
+def mk(kind="acoustics1d", nx=64, ny=1, xlo=-1.0, xhi=1.0, ylo=-1.0, yhi=1.0, rho=None, K=None, B=None,
+       bc=(BC_PERIODIC,) * 4, order=2, limiter=1, transverse=1, dt=None, g=9.81):
+    dx = (xhi - xlo) / nx
+    dy = (yhi - ylo) / ny if kind != "acoustics1d" else 1.0
+    shape = (1, nx) if kind == "acoustics1d" else (ny, nx)
+    cfg = dict(kind=kind, nx=nx, ny=ny, xlo=xlo, xhi=xhi, ylo=ylo, yhi=yhi, dx=dx, dy=dy,
+               bc=list(bc), order=order, limiter=limiter, transverse=transverse, dt=dt, g=g)
+    if kind.startswith("acoustics"):
+        cfg["rho"] = np.ones(shape) if rho is None else np.asarray(rho, dtype=float).reshape(shape)
+        cfg["K"] = np.ones(shape) if K is None else np.asarray(K, dtype=float).reshape(shape)
+    else:
+        cfg["B"] = np.asarray(B, dtype=float).reshape(shape)
+    return cfg
+
+
+def xc(cfg):
+    return cfg["xlo"] + (np.arange(cfg["nx"]) + 0.5) * cfg["dx"]
+
+
+# ---------------------------------------------------------------------------
+# P1: the normal solvers
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(5))
+def test_forward_riemann_middle_state_is_exact(seed):
+    """W1 + W2 = dQ and Q_l + W1 is the exact two-material middle state
+    (pressure and velocity continuous across the material interface)."""
+    rng = np.random.default_rng(seed)
+    pl, ul, pr, ur = rng.uniform(-1, 1, 4)
+    rl, Kl, rr, Kr = rng.uniform(0.5, 4, 4)
+    Zl, cl, Zr, cr = math.sqrt(rl * Kl), math.sqrt(Kl / rl), math.sqrt(rr * Kr), math.sqrt(Kr / rr)
+    w, s, am, ap = oracle.riemann("acoustics_fwd", 0, [pl, ul, 0], [pr, ur, 0], [Zl, cl, rl, Kl], [Zr, cr, rr, Kr])
+    assert np.allclose(w[0] + w[1], [pr - pl, ur - ul, 0], rtol=0, atol=1e-14)
+    um = (pl - pr + Zl * ul + Zr * ur) / (Zl + Zr)
+    pm = pl - Zl * (um - ul)
+    assert abs(pl + w[0][0] - pm) < 1e-14 and abs(ul + w[0][1] - um) < 1e-14
+    # the right state is reached from the middle state by the second wave
+    assert abs(pm + w[1][0] - pr) < 1e-14 and abs(um + w[1][1] - ur) < 1e-14
+    assert s[0] == -cl and s[1] == cr
+    assert np.allclose(am, -cl * w[0], atol=1e-15) and np.allclose(ap, cr * w[1], atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_adjoint_fwaves_split_the_reversed_flux(seed):
+    """The f-waves sum to the jump of the reversed adjoint flux -A^T q and each
+    is an eigenvector of that cell's -A^T with the stated speed."""
+    rng = np.random.default_rng(seed)
+    ql, qr = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+    rl, Kl, rr, Kr = rng.uniform(0.5, 4, 4)
+    al = [math.sqrt(rl * Kl), math.sqrt(Kl / rl), rl, Kl]
+    ar = [math.sqrt(rr * Kr), math.sqrt(Kr / rr), rr, Kr]
+    for d in (0, 1):
+        n = 1 + d
+        w, s, am, ap = oracle.riemann("acoustics_adj", d, ql, qr, al, ar)
+
+        def flux(q, rho, K):
+            A = np.zeros((3, 3))
+            A[0, n] = 1.0 / rho   # (A^T) row p: u/rho (x) or v/rho (y)
+            A[n, 0] = K
+            return -A @ q, -A
+        fl, Ml = flux(ql, rl, Kl)
+        fr, Mr = flux(qr, rr, Kr)
+        assert np.allclose(w[0] + w[1], fr - fl, atol=1e-14)
+        assert np.allclose(Ml @ w[0], s[0] * w[0], atol=1e-13)
+        assert np.allclose(Mr @ w[1], s[1] * w[1], atol=1e-13)
+        assert s[0] < 0 < s[1]
+
+
+def test_adjoint_is_transpose_of_forward_at_first_order():
+    """At first order the reversed-adjoint step matrix is the transpose of the
+    forward step matrix (so the discrete identity of eq. q_equality holds to
+    round-off), for a random three-material medium with periodic edges."""
+    rng = np.random.default_rng(7)
+    nx = 24
+    rho = rng.uniform(0.5, 2, nx)
+    K = rng.uniform(0.5, 4, nx)
+    cfg = mk(nx=nx, rho=rho, K=K, order=1)
+    cmax = float(np.sqrt(K / rho).max())
+    dt = 0.9 * cfg["dx"] / cmax
+    n = 2 * nx
+    M = np.zeros((n, n))
+    Ma = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n); e[k] = 1.0
+        M[:, k] = oracle.run(cfg, "acoustics_fwd", e, 1, dt=dt)[0].ravel()
+        Ma[:, k] = oracle.run(cfg, "acoustics_adj", e, 1, dt=dt)[0].ravel()
+    assert np.abs(Ma - M.T).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P2: exact translation at Courant number 1
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which,sign", [("acoustics_fwd", 1.0), ("acoustics_adj", -1.0)])
+def test_courant_one_translates_exactly(which, sign):
+    """With c = 1 and dt = dx (both exact binary fractions) the MC-limited
+    method shifts a characteristic field by exactly one cell per step."""
+    nx = 64
+    cfg = mk(nx=nx, xlo=0.0, xhi=1.0)
+    dt = cfg["dx"]
+    p = np.zeros(nx); p[10:20] = 1.0; p[30:33] = 2.0
+    # right-going field: forward (Z, 1) with Z = 1 -> u = p;
+    # reversed adjoint right-going eigenvector (1, -Z) -> u = -p
+    q0 = np.stack([p, sign * p]).reshape(2, 1, nx)
+    q, _, cfl = oracle.run(cfg, which, q0, 7, dt=dt)
+    assert cfl == 1.0
+    assert np.array_equal(q[0, 0], np.roll(p, 7)) and np.array_equal(q[1, 0], sign * np.roll(p, 7))
+
+
+def test_courant_one_translates_exactly_2d():
+    nx = ny = 32
+    cfg = mk("acoustics2d", nx=nx, ny=ny, xlo=0, xhi=1, ylo=0, yhi=1)
+    dt = cfg["dx"]
+    p = np.zeros((ny, nx)); p[:, 5:9] = 1.0
+    q0 = np.stack([p, p, np.zeros_like(p)])
+    q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, 5, dt=dt)
+    assert np.array_equal(q[0], np.roll(p, 5, axis=1)) and np.array_equal(q[2], np.zeros_like(p))
+    # the same pulse moving in y
+    q0 = np.stack([p.T, np.zeros_like(p), p.T])
+    q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, 5, dt=dt)
+    assert np.array_equal(q[0], np.roll(p.T, 5, axis=0))
+
+
+# ---------------------------------------------------------------------------
+# P3/P4: convergence to closed-form solutions
+# ---------------------------------------------------------------------------
+def _l1(a, b, dx):
+    return float(np.sum(np.abs(a - b)) * dx)
+
+
+def test_dalembert_convergence_second_order():
+    """Constant coefficients: p = (p0(x-ct) + p0(x+ct))/2 (u0 = 0)."""
+    errs = []
+    T = 0.5
+    for nx in (100, 200, 400):
+        cfg = mk(nx=nx, xlo=-1.0, xhi=1.0, rho=np.full(nx, 1.0), K=np.full(nx, 4.0))   # c = 2, Z = 2
+        x = xc(cfg)
+        p0 = lambda s: np.exp(-50.0 * ((s + 1.0) % 2.0 - 1.0) ** 2)
+        steps = int(math.ceil(T / (0.8 * cfg["dx"] / 2.0)))
+        dt = T / steps
+        q0 = np.stack([p0(x), np.zeros(nx)]).reshape(2, 1, nx)
+        q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, steps, dt=dt)
+        pex = 0.5 * (p0(x - 2 * T) + p0(x + 2 * T))
+        uex = 0.5 * (p0(x - 2 * T) - p0(x + 2 * T)) / 2.0
+        errs.append(_l1(q[0, 0], pex, cfg["dx"]) + _l1(q[1, 0], uex, cfg["dx"]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 2e-3 and min(orders) > 1.5, (errs, orders)
+
+
+def _two_material_exact(x, t):
+    """rho = 1, K = 1 | 4 (c = 1 | 2, Z = 1 | 2) split at x = 0;
+    p0 = exp(-100(x+2)^2), u0 = 0.  Transmission 2Z_r/(Z_l+Z_r) = 4/3,
+    reflection (Z_r - Z_l)/(Z_l+Z_r) = 1/3."""
+    f = lambda s: np.exp(-100.0 * (s + 2.0) ** 2)
+    p = np.where(x < 0, 0.5 * f(x - t) * (x - t < 0) + 0.5 * f(x + t) + 0.5 / 3.0 * f(-x - t),
+                 0.5 * 4.0 / 3.0 * f(x / 2.0 - t))
+    return p
+
+
+def test_two_material_transmission_reflection_convergence():
+    errs = []
+    T = 3.5
+    for nx in (500, 1000, 2000):
+        x = -5.0 + (np.arange(nx) + 0.5) * (10.0 / nx)
+        cfg = mk(nx=nx, xlo=-5.0, xhi=5.0, rho=np.ones(nx), K=np.where(x < 0, 1.0, 4.0),
+                 bc=(BC_EXTRAP,) * 4)
+        steps = int(math.ceil(T / (0.9 * cfg["dx"] / 2.0)))
+        q0 = np.stack([np.exp(-100 * (x + 2) ** 2), np.zeros(nx)]).reshape(2, 1, nx)
+        q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, steps, dt=T / steps)
+        errs.append(_l1(q[0, 0], _two_material_exact(x, T), cfg["dx"]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 2e-3 and min(orders) > 1.2, (errs, orders)
+
+
+def test_two_material_riemann_problem_converges():
+    """Discontinuous data: the exact self-similar three-state solution."""
+    errs = []
+    T = 0.5
+    pl, ul, pr, ur = 1.0, 0.2, -0.5, 0.0
+    Zl, cl, Zr, cr = 1.0, 1.0, 2.0, 2.0
+    um = (pl - pr + Zl * ul + Zr * ur) / (Zl + Zr)
+    pm = pl - Zl * (um - ul)
+    for nx in (200, 400, 800, 1600):
+        x = -2.0 + (np.arange(nx) + 0.5) * (4.0 / nx)
+        cfg = mk(nx=nx, xlo=-2.0, xhi=2.0, rho=np.ones(nx), K=np.where(x < 0, 1.0, 4.0), bc=(BC_EXTRAP,) * 4)
+        steps = int(math.ceil(T / (0.9 * cfg["dx"] / 2.0)))
+        q0 = np.stack([np.where(x < 0, pl, pr), np.where(x < 0, ul, ur)]).reshape(2, 1, nx)
+        q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, steps, dt=T / steps)
+        pex = np.where(x < -cl * T, pl, np.where(x < cr * T, pm, pr))
+        uex = np.where(x < -cl * T, ul, np.where(x < cr * T, um, ur))
+        errs.append(_l1(q[0, 0], pex, cfg["dx"]) + _l1(q[1, 0], uex, cfg["dx"]))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(e1 > e2 for e1, e2 in zip(errs, errs[1:])) and np.mean(orders) > 0.5, (errs, orders)
+
+
+# ---------------------------------------------------------------------------
+# P5/P13: the adjoint identity (eq. q_equality, eq. J)
+# ---------------------------------------------------------------------------
+def _identity_series(cfg, q0, qh0, nsteps, dt, **kw):
+    _, fs, _ = oracle.run(cfg, "acoustics_fwd", q0, nsteps, dt=dt, snap_every=1, **kw)
+    _, as_, _ = oracle.run(cfg, "acoustics_adj", qh0, nsteps, dt=dt, snap_every=1, **kw)
+    dA = cfg["dx"] * (cfg["dy"] if cfg["kind"] != "acoustics1d" else 1.0)
+    return np.array([oracle.inner_integral(as_[nsteps - n], fs[n], dA) for n in range(nsteps + 1)])
+
+
+def test_first_order_adjoint_identity_1d_roundoff():
+    rng = np.random.default_rng(3)
+    nx = 96
+    idx = np.arange(nx) * 3 // nx
+    rho = np.array(rng.uniform(0.5, 2, 3))[idx]
+    K = np.array(rng.uniform(0.5, 4, 3))[idx]
+    cfg = mk(nx=nx, rho=rho, K=K, order=1)
+    dt = 0.9 * cfg["dx"] / float(np.sqrt(K / rho).max())
+    q0 = rng.uniform(-1, 1, (2, 1, nx))
+    qh0 = rng.uniform(-1, 1, (2, 1, nx))
+    I = _identity_series(cfg, q0, qh0, 60, dt)
+    assert np.ptp(I) < 1e-14 * np.abs(I).max() * 60
+
+
+def test_first_order_adjoint_identity_2d_roundoff():
+    """2D unsplit first order: the identity holds to round-off for random media
+    without transverse terms, and with transverse terms for constant
+    coefficients (the reversed-adjoint step is then the transpose of the
+    forward step)."""
+    rng = np.random.default_rng(5)
+    nx = ny = 20
+    from wp_synth import random_media
+    rho, K = random_media(ny, nx, seed=11)
+    for transverse, (r, k) in ((0, (rho, K)), (1, (np.full((ny, nx), 1.3), np.full((ny, nx), 2.2)))):
+        cfg = mk("acoustics2d", nx=nx, ny=ny, rho=r, K=k, order=1, transverse=transverse)
+        dt = 0.45 * cfg["dx"] / float(np.sqrt(k / r).max())
+        q0 = rng.uniform(-1, 1, (3, ny, nx))
+        qh0 = rng.uniform(-1, 1, (3, ny, nx))
+        I = _identity_series(cfg, q0, qh0, 30, dt)
+        assert np.ptp(I) < 1e-13 * np.abs(I).max(), (transverse, np.ptp(I))
+
+
+def test_identity_drift_converges_2d_variable_coefficients():
+    """With a material interface and transverse splitting the discrete adjoint
+    is not the transpose of the forward step (the paper's adjoint is a
+    discretisation of the continuous adjoint, not the discrete adjoint), so
+    the identity holds up to truncation error: its relative drift over a fixed
+    time must shrink under refinement."""
+    drifts = []
+    for n in (20, 40, 80):
+        x = -1 + (np.arange(n) + 0.5) * (2 / n)
+        X, Y = np.meshgrid(x, x)
+        cfg = mk("acoustics2d", nx=n, ny=n, rho=np.ones((n, n)), K=np.where(X < 0, 1.0, 4.0), order=1)
+        T = 0.4
+        steps = int(round(T / (0.45 * cfg["dx"] / 2.0)))
+        q0 = np.stack([np.exp(-20 * ((X + 0.3) ** 2 + Y ** 2)), 0 * X, 0 * X])
+        qh0 = np.stack([np.exp(-20 * ((X - 0.3) ** 2 + (Y - 0.1) ** 2)), 0 * X, 0 * X])
+        I = _identity_series(cfg, q0, qh0, steps, T / steps)
+        drifts.append(np.ptp(I) / np.abs(I).max())
+    assert drifts[0] > 2 * drifts[1] > 4 * drifts[2], drifts
+
+
+def test_identity_and_functional_converge_to_exact_J():
+    """Two-material 1D: J(t_f) = int_1^1.5 p(x, 2.6) dx has a closed form from
+    the transmitted half-pulse; J from the forward run and the integral
+    int qhat(x,0)^T q(x,0) dx from the adjoint run both converge to it."""
+    tf = 2.6
+    Jex = (4.0 / 3.0) * (math.sqrt(math.pi) / 20.0) * (erf(1.5) + erf(1.0))
+    errs_f, errs_a = [], []
+    for n in (500, 1000, 2000):
+        x = -5.0 + (np.arange(n) + 0.5) * (10.0 / n)
+        cfg = mk(nx=n, xlo=-5.0, xhi=5.0, rho=np.ones(n), K=np.where(x < 0, 1.0, 4.0), bc=(BC_EXTRAP,) * 4)
+        cfg["functional"] = dict(kind="interval", x0=1.0, x1=1.5, y0=0, y1=0, cx=0, cy=0, r=0, component=0)
+        steps = int(math.ceil(tf / (0.9 * cfg["dx"] / 2.0)))
+        dt = tf / steps
+        q0 = np.stack([np.exp(-100 * (x + 2) ** 2), np.zeros(n)]).reshape(2, 1, n)
+        qf, _, _ = oracle.run(cfg, "acoustics_fwd", q0, steps, dt=dt)
+        qa, _, _ = oracle.run(cfg, "acoustics_adj", oracle.phi(cfg), steps, dt=dt)
+        errs_f.append(abs(oracle.functional(cfg, qf) - Jex))
+        errs_a.append(abs(oracle.inner_integral(qa, q0, cfg["dx"]) - Jex))
+    assert errs_f[-1] < 0.05 * Jex and errs_a[-1] < 0.05 * Jex
+    assert errs_f[0] > errs_f[-1] and errs_a[0] > errs_a[-1]
+
+
+# ---------------------------------------------------------------------------
+# P6: the reversed adjoint in (K p, -u/rho) is forward acoustics
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("order,varying", [(1, True), (2, False)])
+def test_reversed_adjoint_maps_to_forward(order, varying):
+    rng = np.random.default_rng(9)
+    nx = 80
+    if varying:
+        idx = np.arange(nx) * 4 // nx
+        rho = np.array(rng.uniform(0.5, 2, 4))[idx]
+        K = np.array(rng.uniform(0.5, 4, 4))[idx]
+    else:
+        rho, K = np.full(nx, 1.5), np.full(nx, 2.5)
+    cfg = mk(nx=nx, rho=rho, K=K, order=order)
+    dt = 0.9 * cfg["dx"] / float(np.sqrt(K / rho).max())
+    qt = rng.uniform(-1, 1, (2, 1, nx))
+    qa, _, _ = oracle.run(cfg, "acoustics_adj", qt, 40, dt=dt)
+    w0 = np.stack([K * qt[0, 0], -qt[1, 0] / rho]).reshape(2, 1, nx)
+    qf, _, _ = oracle.run(cfg, "acoustics_fwd", w0, 40, dt=dt)
+    assert np.abs(qf[0, 0] - K * qa[0, 0]).max() < 1e-12
+    assert np.abs(qf[1, 0] + qa[1, 0] / rho).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P7: transverse terms -- reduction to 1D, transposition, square symmetry
+# ---------------------------------------------------------------------------
+def test_y_invariant_2d_reproduces_1d():
+    nx, ny = 40, 6
+    x = -1 + (np.arange(nx) + 0.5) * (2 / nx)
+    rho1, K1 = np.where(x < 0.1, 1.0, 2.0), np.where(x < 0.3, 1.0, 3.0)
+    cfg1 = mk(nx=nx, rho=rho1, K=K1, bc=(BC_EXTRAP,) * 4)
+    cfg2 = mk("acoustics2d", nx=nx, ny=ny, rho=np.tile(rho1, (ny, 1)), K=np.tile(K1, (ny, 1)),
+              bc=(BC_EXTRAP,) * 4, ylo=0, yhi=ny * 2 / nx)
+    dt = 0.8 * cfg1["dx"] / 2.0
+    p = np.exp(-30 * x ** 2)
+    for which in ("acoustics_fwd", "acoustics_adj"):
+        q1, _, _ = oracle.run(cfg1, which, np.stack([p, 0.3 * p]).reshape(2, 1, nx), 25, dt=dt)
+        q2, _, _ = oracle.run(cfg2, which, np.stack([np.tile(p, (ny, 1)), np.tile(0.3 * p, (ny, 1)),
+                                                      np.zeros((ny, nx))]), 25, dt=dt)
+        for j in range(ny):
+            assert np.abs(q2[0, j] - q1[0, 0]).max() < 1e-15
+            assert np.abs(q2[1, j] - q1[1, 0]).max() < 1e-15
+        assert np.abs(q2[2]).max() == 0.0
+
+
+@pytest.mark.parametrize("which", ["acoustics_fwd", "acoustics_adj"])
+def test_transposed_problem_gives_transposed_result(which):
+    from wp_synth import random_media, random_state
+    n = 24
+    rho, K = random_media(n, n, seed=4)
+    q0 = random_state(3, n, n, seed=6)
+    cfg = mk("acoustics2d", nx=n, ny=n, rho=rho, K=K, bc=(BC_EXTRAP, BC_WALL, BC_PERIODIC, BC_PERIODIC))
+    cfgT = mk("acoustics2d", nx=n, ny=n, rho=rho.T, K=K.T, bc=(BC_PERIODIC, BC_PERIODIC, BC_EXTRAP, BC_WALL))
+    dt = 0.4 * cfg["dx"] / float(np.sqrt(K / rho).max())
+    q, _, _ = oracle.run(cfg, which, q0, 20, dt=dt)
+    qT, _, _ = oracle.run(cfgT, which, np.stack([q0[0].T, q0[2].T, q0[1].T]), 20, dt=dt)
+    assert np.abs(qT[0] - q[0].T).max() < 1e-13
+    assert np.abs(qT[1] - q[2].T).max() < 1e-13
+    assert np.abs(qT[2] - q[1].T).max() < 1e-13
+
+
+def test_radial_pulse_keeps_square_symmetry():
+    n = 40
+    cfg = mk("acoustics2d", nx=n, ny=n, bc=(BC_EXTRAP,) * 4, K=np.full((n, n), 2.0))
+    x = -1 + (np.arange(n) + 0.5) * (2 / n)
+    X, Y = np.meshgrid(x, x)
+    q0 = np.stack([np.exp(-20 * (X ** 2 + Y ** 2)), np.zeros((n, n)), np.zeros((n, n))])
+    dt = 0.6 * cfg["dx"] / math.sqrt(2.0)
+    q, _, _ = oracle.run(cfg, "acoustics_fwd", q0, 30, dt=dt)
+    p, u, v = q
+    tol = 1e-14
+    assert np.abs(p - p.T).max() < tol and np.abs(p - p[:, ::-1]).max() < tol and np.abs(p - p[::-1, :]).max() < tol
+    assert np.abs(u - v.T).max() < tol and np.abs(u + u[:, ::-1]).max() < tol
+
+
+@pytest.mark.parametrize("which", ["acoustics_fwd", "acoustics_adj"])
+def test_transverse_split_constant_coefficients_closed_form(which):
+    """Constant coefficients: B-d = R Lambda^- R^{-1} d, B+d = R Lambda^+ R^{-1} d
+    with B the y-matrix (Sec. 5.2) of the forward, or -B^T for the adjoint."""
+    rho, K = 1.7, 2.9
+    Z, c = math.sqrt(rho * K), math.sqrt(K / rho)
+    a = [Z, c, rho, K]
+    Bm = np.zeros((3, 3)); Bm[0, 2] = K; Bm[2, 0] = 1 / rho
+    if which == "acoustics_adj":
+        Bm = -Bm.T
+    lam, R = np.linalg.eig(Bm)
+    Rinv = np.linalg.inv(R)
+    d = np.array([0.3, -0.7, 0.45])
+    Bminus = (R @ np.diag(np.minimum(lam, 0)) @ Rinv @ d).real
+    Bplus = (R @ np.diag(np.maximum(lam, 0)) @ Rinv @ d).real
+    bm, bp = oracle.transverse_split(which, 1, d, a, a, a)
+    assert np.allclose(bm, Bminus, atol=1e-14) and np.allclose(bp, Bplus, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# P8: conservation
+# ---------------------------------------------------------------------------
+def test_conservation():
+    from wp_synth import random_media, random_state
+    n = 24
+    rho, K = random_media(n, n, seed=12)
+    q0 = random_state(3, n, n, seed=13)
+    dt = 0.4 * (2 / n) / float(np.sqrt(K / rho).max())
+    cfg = mk("acoustics2d", nx=n, ny=n, rho=rho, K=K)
+    # f-wave adjoint: conservative for any coefficients
+    q, _, _ = oracle.run(cfg, "acoustics_adj", q0, 40, dt=dt)
+    assert np.abs(q.sum(axis=(1, 2)) - q0.sum(axis=(1, 2))).max() < 1e-12
+    # forward with constant coefficients
+    cfgc = mk("acoustics2d", nx=n, ny=n, rho=np.full((n, n), 1.3), K=np.full((n, n), 2.2))
+    q, _, _ = oracle.run(cfgc, "acoustics_fwd", q0, 40, dt=dt)
+    assert np.abs(q.sum(axis=(1, 2)) - q0.sum(axis=(1, 2))).max() < 1e-12
+    # forward, variable coefficients, first order: sum p/K and sum rho u conserved (1D)
+    x1 = np.arange(n)
+    rho1, K1 = rho[n // 2], K[n // 2]
+    cfg1 = mk(nx=n, rho=rho1, K=K1, order=1)
+    q1 = random_state(2, 1, n, seed=14)
+    qq, _, _ = oracle.run(cfg1, "acoustics_fwd", q1, 40, dt=dt)
+    assert abs((qq[0, 0] / K1).sum() - (q1[0, 0] / K1).sum()) < 1e-12
+    assert abs((qq[1, 0] * rho1).sum() - (q1[1, 0] * rho1).sum()) < 1e-12
+    del x1
+
+
+# ---------------------------------------------------------------------------
+# P9: shallow water
+# ---------------------------------------------------------------------------
+def _swe_cfg(n=32, bc=(BC_EXTRAP,) * 4):
+    from wp_synth import swe2d
+    return swe2d(n=n, seed=3)
+
+
+def test_swe_lake_at_rest_is_bitwise_still():
+    cfg = _swe_cfg(48)
+    q0 = np.zeros((3, 48, 48))
+    q, _, _ = oracle.run(cfg, "swe", q0, 20)
+    assert np.array_equal(q, q0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_swe_fwaves_split_flux_difference_and_are_eigenvectors(seed):
+    """sum of f-waves = df - Psi dx with f = (hu, hu^2 + g h^2/2, huv) and
+    Psi dx = -g hbar dB; each f-wave is an eigenvector of the flux Jacobian at
+    the Roe-averaged state with the stated speed (Roe property)."""
+    rng = np.random.default_rng(seed)
+    g = 9.81
+    Bl, Br = -rng.uniform(100, 4000, 2)
+    hl, hr = -Bl + rng.uniform(-1, 1), -Br + rng.uniform(-1, 1)
+    ul, vl, ur, vr = rng.uniform(-0.5, 0.5, 4)
+    ql = [hl + Bl, hl * ul, hl * vl]
+    qr = [hr + Br, hr * ur, hr * vr]
+    w, s, am, ap = oracle.riemann("swe", 0, ql, qr, [Bl], [Br], g=g)
+    f = lambda h, u, v: np.array([h * u, h * u * u + 0.5 * g * h * h, h * u * v])
+    hb = 0.5 * (hl + hr)
+    target = f(hr, ur, vr) - f(hl, ul, vl) + np.array([0, g * hb * (Br - Bl), 0])
+    assert np.allclose(w.sum(axis=0), target, rtol=1e-11, atol=1e-9)
+    sl, sr = math.sqrt(hl), math.sqrt(hr)
+    uh = (sl * ul + sr * ur) / (sl + sr)
+    vh = (sl * vl + sr * vr) / (sl + sr)
+    A = np.array([[0, 1, 0], [g * hb - uh * uh, 2 * uh, 0], [-uh * vh, vh, uh]])
+    for p in range(3):
+        assert np.allclose(A @ w[p], s[p] * w[p], rtol=1e-10, atol=1e-9 * np.abs(w[p]).max() + 1e-14)
+    assert np.allclose(am + ap, w.sum(axis=0), atol=1e-9)
+
+
+def test_swe_conserves_mass():
+    cfg = _swe_cfg(32)
+    cfg = dict(cfg, bc=[BC_PERIODIC] * 4, B=np.full((32, 32), -3000.0))
+    from wp_synth import random_state
+    q0 = random_state(3, 32, 32, seed=21)
+    q0[0] *= 0.5
+    q0[1:] *= 50.0
+    q, _, _ = oracle.run(cfg, "swe", q0, 30)
+    assert abs(q[0].sum() - q0[0].sum()) < 1e-9
+
+
+def test_lswe_adjoint_fwaves_and_identity():
+    """Linearised shallow water (Sec. 5.3): first-order reversed adjoint is the
+    transpose of the first-order forward linearised step, checked through the
+    acoustics correspondence eta ~ p, hbar g ~ K, 1 ~ 1/rho: the f-wave split
+    sums to the reversed flux jump and its vectors are eigenvectors."""
+    rng = np.random.default_rng(2)
+    g = 9.81
+    for d in (0, 1):
+        n = 1 + d
+        hl, hr = rng.uniform(200, 4000, 2)
+        ql, qr = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        w, s, am, ap = oracle.riemann("lswe_adj", d, ql, qr, [hl, math.sqrt(g * hl)], [hr, math.sqrt(g * hr)], g=g)
+
+        def M(h):
+            A = np.zeros((3, 3)); A[0, n] = 1.0; A[n, 0] = g * h   # A (x) or B (y)
+            return -A.T
+        assert np.allclose(w[0] + w[1], M(hr) @ qr - M(hl) @ ql, rtol=1e-12, atol=1e-10)
+        assert np.allclose(M(hl) @ w[0], s[0] * w[0], rtol=1e-12, atol=1e-9)
+        assert np.allclose(M(hr) @ w[1], s[1] * w[1], rtol=1e-12, atol=1e-9)
