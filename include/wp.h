@@ -1,0 +1,262 @@
+/*
+ * wp.h -- C ABI of the wave-propagation patch library for AMD MI355X (gfx950).
+ *
+ * The library implements the data-parallel hot path of adjoint-guided
+ * block-structured AMR for linear and shallow-water wave propagation
+ * (Davis & LeVeque, "Adjoint methods for guiding adaptive mesh refinement in
+ * wave propagation problems", arXiv:1511.03645):
+ *   - the high-resolution wave-propagation patch update (Sec. 3): a Riemann
+ *     solve at every cell edge into waves and speeds, MC-limited second-order
+ *     correction fluxes, transverse propagation in 2D, fluctuation-form update;
+ *   - the same update for the time-reversed adjoint (Sec. 2 adjoint equation,
+ *     Sec. 4 time reversal), with snapshots kept in device memory;
+ *   - the adjoint inner-product flag (Sec. 4; Sec. 5.1.2 time range);
+ *   - ghost cells from physical boundaries (Sec. 5.1, 5.2), same-level
+ *     neighbours or coarse space-time interpolation (Sec. 3), Berger-Oliger
+ *     stepping and Berger-Rigoutsos regridding (Sec. 3).
+ *
+ * Conventions
+ *   - Every call returns an int status: WP_OK (0) or a negative wp_status.
+ *     wp_last_error() gives a message for the last failure on a handle.
+ *   - Grids: level l has nx_l x ny_l cells covering the whole domain
+ *     (nx_0 = grid.nx0, nx_{l+1} = nx_l * ratio[l]); cell (i, j) has centre
+ *     (xlo + (i + 1/2) dx_l, ylo + (j + 1/2) dy_l).  Patches are boxes of cells
+ *     (ilo, jlo, nx, ny) in their level's index space.
+ *   - State arrays exchanged with the caller are component-major, row-major
+ *     with x fastest: [m][ny][nx], m = 2 (1D acoustics p, u), 3 (2D acoustics
+ *     p, u, v; shallow water eta, hu, hv).  Element type: double for
+ *     WP_FP64, float for WP_FP32; WP_MIXED (shallow water only) uses double
+ *     for eta and float for hu, hv (eta block first, then hu, hv).
+ *   - Host pointers passed in are read before the call returns; the caller
+ *     keeps ownership.  Device pointers passed in are borrowed for the call.
+ *   - Device memory is owned by the library.  It is obtained from the
+ *     caller's wp_allocator if one is given (the Python layer backs it with
+ *     the PyTorch caching allocator), else with hipMalloc.
+ *   - All device work is enqueued on the HIP stream given at creation (or by
+ *     wp_set_stream).  Calls that return data to host memory synchronise that
+ *     stream.
+ *   - Conditions detected on the device (a Courant number above
+ *     problem.cfl_max for shallow water, a non-finite value in a step's
+ *     output) are latched in a device status word and reported as WP_ECFL or
+ *     WP_ENONFINITE by the next call that synchronises (wp_sync, wp_get_state,
+ *     wp_functional_value, ...).  Such a step has already been applied.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef WP_H
+#define WP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WP_MAX_LEVELS 6
+
+typedef enum {
+    WP_OK = 0,
+    WP_EINVAL = -1,      /* invalid argument or unsupported combination */
+    WP_ENOMEM = -2,      /* device allocation failed */
+    WP_EDEVICE = -3,     /* a HIP runtime call failed */
+    WP_ECFL = -4,        /* Courant number above problem.cfl_max */
+    WP_ENONFINITE = -5,  /* NaN or Inf produced */
+    WP_ERANGE = -6,      /* time or index outside the stored adjoint snapshots */
+    WP_ESTATE = -7       /* call out of order (e.g. flag before adjoint run) */
+} wp_status;
+
+typedef enum { WP_ACOUSTICS_1D = 1, WP_ACOUSTICS_2D = 2, WP_SWE_2D = 3 } wp_kind;
+typedef enum { WP_BC_EXTRAP = 0, WP_BC_WALL = 1, WP_BC_PERIODIC = 2 } wp_bc;
+typedef enum { WP_FP64 = 64, WP_FP32 = 32, WP_MIXED = 16 } wp_precision;
+typedef enum { WP_FUNC_INTERVAL = 0, WP_FUNC_BOX = 1, WP_FUNC_DISC = 2 } wp_functional_kind;
+
+/* The PDE and the method options (Sec. 2, 3, 5).
+ *   kind       equation family
+ *   bc[4]      boundary type at x = xlo, x = xhi, y = ylo, y = yhi.
+ *              Extrapolation (zero-order, outflow), wall (mirror, normal
+ *              velocity negated), periodic.  The adjoint run uses the same
+ *              type on each side (walls for walls, Sec. 5.1/5.2.1; outflow
+ *              for outflow, Sec. 5.2.3).
+ *   order      1: Godunov fluctuations only; 2: with correction fluxes
+ *   limiter    0: none (Lax-Wendroff), 1: MC
+ *   transverse 0/1: transverse Riemann propagation in 2D (Sec. 3)
+ *   precision  WP_FP64, WP_FP32 (acoustics), WP_MIXED (shallow water: eta and
+ *              the well-balanced source term in FP64, the rest in FP32)
+ *   cfl_max    largest Courant number accepted
+ *   g          gravitational acceleration (shallow water)            */
+typedef struct {
+    int kind;
+    int bc[4];
+    int order;
+    int limiter;
+    int transverse;
+    int precision;
+    double cfl_max;
+    double g;
+} wp_problem;
+
+/* Coefficients on the level-0 grid, host arrays [ny0][nx0] (Sec. 5.1/5.2:
+ * A(x) = [[0, K], [1/rho, 0]]; Sec. 5.3: bathymetry B, depth h = eta - B).
+ * Acoustics media are piecewise constant: at most 16 distinct (rho, K)
+ * pairs; a cell of a finer level has the medium of the level-0 cell that
+ * contains it.  Shallow water uses a single level. */
+typedef struct {
+    const double *rho;
+    const double *K;
+    const double *B;
+} wp_coefficients;
+
+/* Domain and refinement hierarchy (Sec. 3): num_levels levels, ratio[l]
+ * refining level l to level l+1 in space and in time. */
+typedef struct {
+    double xlo, xhi, ylo, yhi;
+    int nx0, ny0;
+    int num_levels;
+    int ratio[WP_MAX_LEVELS];
+} wp_grid;
+
+typedef struct {
+    int ilo, jlo, nx, ny;
+} wp_patch;
+
+/* Target functional J = int phi^T q(x, t_f) dx (eq. J_general) with
+ * phi = I(x) e_component, I the indicator of an interval [x0, x1] (1D), a
+ * box [x0,x1]x[y0,y1] or a disc of centre (cx, cy) and radius r, each a
+ * closed set sampled at level-0 cell centres (eq. delta_1d, delta_2d,
+ * delta_Alaska). */
+typedef struct {
+    int kind;
+    int component;
+    double x0, x1, y0, y1, cx, cy, r;
+} wp_functional;
+
+/* Adjoint run: nsteps steps of size dt on the level-0 grid; qtilde is
+ * stored every snap_every steps, step 0 included (Sec. 4), so snapshot n
+ * holds qhat at tau_n = t_f - n * snap_every * dt with t_f = nsteps * dt. */
+typedef struct {
+    double dt;
+    int nsteps;
+    int snap_every;
+} wp_snapshot_spec;
+
+/* Optional device allocator: alloc(bytes, user) returns device memory
+ * (256-byte aligned) or NULL; free(ptr, user) releases it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} wp_allocator;
+
+typedef struct wp_ctx wp_ctx;
+
+/* Create a solver instance: validates the arguments, uploads the
+ * coefficients, allocates one state canvas pair per level and sets level 0
+ * to a single patch covering the domain (finer levels start empty).
+ * stream: a hipStream_t (NULL: the null stream).  On failure *out is NULL. */
+int wp_create(const wp_problem *problem, const wp_coefficients *coef, const wp_grid *grid,
+              const wp_allocator *alloc, void *stream, wp_ctx **out);
+void wp_destroy(wp_ctx *ctx);
+const char *wp_last_error(const wp_ctx *ctx);
+const char *wp_status_string(int status);
+int wp_set_stream(wp_ctx *ctx, void *stream);
+
+/* Number of cells and patches of a level; level l canvas size. */
+int wp_level_info(const wp_ctx *ctx, int level, int *nx, int *ny, int *npatches);
+
+/* Copy a state into (set) or out of (get) a level.  patch = -1 addresses the
+ * whole level canvas ([m][ny_l][nx_l]); patch = k the k-th patch of the level
+ * ([m][ny][nx] of its box).  on_device: src/dst is device memory. */
+int wp_set_state(wp_ctx *ctx, int level, int patch, const void *src, int on_device);
+int wp_get_state(wp_ctx *ctx, int level, int patch, void *dst, int on_device);
+
+/* Advance every patch of `level` by one step of size dt (Sec. 3 wave
+ * propagation).  Ghost cells come from physical boundaries, from same-level
+ * patches, and for level > 0 from the level below, interpolated in space
+ * and linearly in time between the two coarse times bracketing the level's
+ * time (Sec. 3).  Fails with WP_ECFL, without changing the state, if the
+ * Courant number known from the coefficients exceeds problem.cfl_max. */
+int wp_step_patches(wp_ctx *ctx, int level, double dt);
+
+/* Berger-Oliger time stepping (Sec. 3): nsteps coarse steps of size dt0; each
+ * coarse step advances level 0 once, then recursively ratio[l] steps of
+ * level l+1 of size dt_l / ratio[l], then averages level l+1 onto the level-l
+ * cells it covers.  With one level this is nsteps calls of wp_step_patches. */
+int wp_advance(wp_ctx *ctx, int nsteps, double dt0);
+
+/* Time-reversed adjoint (Sec. 2, 4): qtilde(x, 0) = phi from the functional,
+ * solved forward in time with flux -A^T qtilde on the level-0 grid, the same
+ * boundary types as the forward problem.  Snapshots are kept in device
+ * memory; any previous adjoint run is replaced. */
+int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *snaps);
+int wp_num_snapshots(const wp_ctx *ctx);
+int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device);
+
+/* Adjoint-guided flag (Sec. 4; Sec. 5.1.2) on every patch of `level` at
+ * forward time t: m(x) = max over the snapshots bracketing the window
+ * [t, min(t + t_f - t_s, t_f)] of |qhat_n(x)^T q(x, t)|, qhat bilinear from the
+ * adjoint grid to the level's cell centres (computed in FP64); a cell is
+ * flagged iff m > tol.  Snapshot n holds tau_n = t_f - n * ds; times within
+ * 1e-9 ds of a snapshot time count as that time.  flags (optional,
+ * [ny_l][nx_l] uint8, 0 outside the level's patches) is device or host
+ * memory per on_device; *nflagged (optional) receives the count.
+ * WP_ERANGE if the window reaches before the earliest snapshot. */
+int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, double t_f,
+                    uint8_t *flags, int on_device, int64_t *nflagged);
+
+/* Replace the patches of level+1 (Sec. 3 regridding).  patches != NULL: the
+ * given boxes (level+1 index space; must be disjoint and properly nested in
+ * level's patches shrunk by one level cell, except along the physical
+ * boundary).  patches == NULL: Berger-Rigoutsos clustering of the current
+ * flags of `level` (from the last wp_flag_adjoint on it), after dilating them
+ * by `buffer` cells, with efficiency cutoff 0.7 and sides of at most 64
+ * level+1 cells.  New fine cells take the old level+1 data where an old patch
+ * covered them, else space interpolation from level.  Sets level+1's time to
+ * level's. */
+int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int npatches, int buffer);
+int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int cap, int *npatches);
+
+/* J = sum over level-0 cells of phi^T q dx dy (which = 0), or the inner
+ * product integral sum qhat_n^T q dx dy with snapshot n (which = 1; eq. J,
+ * constant in t), both accumulated in FP64 with compensated summation. */
+int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int which, int snapshot, double *out);
+
+/* Current time of a level; largest Courant number of the last step. */
+int wp_get_time(const wp_ctx *ctx, int level, double *t);
+int wp_set_time(wp_ctx *ctx, int level, double t);
+
+/* Wait for all work of the handle and report latched device conditions. */
+int wp_sync(wp_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent single-level acoustics instances of the same
+ * precision advanced together, every step of every instance in one launch.
+ * ---------------------------------------------------------------------- */
+typedef struct wp_batch wp_batch;
+
+/* Build a batch over n instances (each created with one level and already
+ * holding its state).  dts[k]: the fixed step of instance k.  The
+ * instances stay owned by the caller and must outlive the batch. */
+int wp_batch_create(wp_ctx *const *instances, int n, const double *dts, wp_batch **out);
+void wp_batch_destroy(wp_batch *b);
+/* nsteps steps of every instance, forward (adjoint = 0) or of the adjoint
+ * states set up by wp_batch_adjoint_begin (adjoint = 1). */
+int wp_batch_step(wp_batch *b, int nsteps, int adjoint);
+/* Adjoint runs of every instance in the batch: J[k], snapshot spec with
+ * per-instance dt from the batch; every instance runs spec->nsteps steps. */
+int wp_batch_adjoint_run(wp_batch *b, const wp_functional *J, int nsteps, int snap_every);
+const char *wp_batch_last_error(const wp_batch *b);
+
+/* Tile shape of the patch-update kernels: rows per tile for the 2D
+ * kernels (0: the built-in choice).  Exposed for the autotuner. */
+int wp_set_tile_rows(wp_ctx *ctx, int rows);
+int wp_get_tile_rows(const wp_ctx *ctx, int *rows);
+
+/* Capture `nsteps` single-level steps of size dt into a HIP graph and replay
+ * it `replays` times (the launch sequence is identical to nsteps calls of
+ * wp_step_patches on level 0). */
+int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WP_H */

@@ -1,0 +1,285 @@
+// Adjoint inner-product flag kernel (Davis & LeVeque Sec. 4 and Sec. 5.1.2)
+// and compensated FP64 reductions for the functional J (eq. J_general) and
+// the inner-product integral (eq. q_equality / eq. J).
+#include "wp_internal.h"
+
+namespace wp {
+namespace {
+
+// FP64 products and sums in the flag measure are rounded exactly as written
+// (no contraction), so flags do not depend on instruction selection.
+#pragma clang fp contract(off)
+
+// Index and weight of the adjoint-grid cell centres bracketing fine cell i
+// when the fine grid refines the adjoint grid by `ratio`; exact for
+// power-of-two ratios, clamped at the domain edge.
+__device__ __forceinline__ void bracket(int i, int ratio, int N, int &i0, double &w)
+{
+    if (ratio == 1) {
+        i0 = i;
+        w = 0.0;
+        return;
+    }
+    const int num = 2 * i + 1 - ratio;
+    int f = num >= 0 ? num / (2 * ratio) : -((-num + 2 * ratio - 1) / (2 * ratio));
+    f = min(max(f, 0), max(N - 2, 0));
+    double ww = (double)(num - 2 * ratio * f) / (double)(2 * ratio);
+    w = fmin(fmax(ww, 0.0), 1.0);
+    if (N == 1) w = 0.0;
+    i0 = f;
+}
+
+template <typename TH>
+__device__ __forceinline__ double interp(const TH *s, int NX, int NY, int ratio, int i0, double wx, int j0, double wy)
+{
+    if (ratio == 1) return (double)s[(long long)j0 * NX + i0];
+    const int i1 = min(i0 + 1, NX - 1), j1 = min(j0 + 1, NY - 1);
+    const double q00 = s[(long long)j0 * NX + i0], q10 = s[(long long)j0 * NX + i1];
+    const double q01 = s[(long long)j1 * NX + i0], q11 = s[(long long)j1 * NX + i1];
+    const double a = (1.0 - wx) * (1.0 - wy) * q00 + wx * (1.0 - wy) * q10;
+    const double b = (1.0 - wx) * wy * q01 + wx * wy * q11;
+    return a + b;
+}
+
+template <typename TQ, typename TH>
+__global__ __launch_bounds__(256) void flag_kernel(const TQ *__restrict__ q, long long cs, int nx, int m,
+                                                   const TH *__restrict__ snaps, long long sstride, long long hcs,
+                                                   int NX, int NY, int ratio, int n_lo, int n_hi, double tol,
+                                                   const Tile *__restrict__ tiles, uint8_t *__restrict__ flags,
+                                                   unsigned long long *__restrict__ count)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const int ncell = tl.ni * tl.nj;
+    unsigned long long local = 0;
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int i = tl.i0 + k % tl.ni, j = tl.j0 + k / tl.ni;
+        const long long idx = (long long)j * nx + i;
+        int i0, j0;
+        double wx, wy;
+        bracket(i, ratio, NX, i0, wx);
+        bracket(j, ratio, NY, j0, wy);
+        double qv[3];
+        for (int c = 0; c < m; ++c) qv[c] = (double)q[idx + c * cs];
+        double best = 0.0;
+        for (int n = n_lo; n <= n_hi; ++n) {
+            const TH *sn = snaps + (long long)n * sstride;
+            double ip = interp(sn, NX, NY, ratio, i0, wx, j0, wy) * qv[0];
+            for (int c = 1; c < m; ++c) ip = ip + interp(sn + c * hcs, NX, NY, ratio, i0, wx, j0, wy) * qv[c];
+            best = fmax(best, fabs(ip));
+        }
+        const uint8_t f = best > tol ? 1 : 0;
+        flags[idx] = f;
+        local += f;
+    }
+    // wave-level sum then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+}
+
+__global__ __launch_bounds__(256) void flag_mixed_kernel(const double *__restrict__ eta, const float *__restrict__ hu,
+                                                         const float *__restrict__ hv, int nx,
+                                                         const float *__restrict__ snaps, long long sstride,
+                                                         long long hcs, int n_lo, int n_hi, double tol,
+                                                         const Tile *__restrict__ tiles, uint8_t *__restrict__ flags,
+                                                         unsigned long long *__restrict__ count)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const int ncell = tl.ni * tl.nj;
+    unsigned long long local = 0;
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
+        const int i = tl.i0 + k % tl.ni, j = tl.j0 + k / tl.ni;
+        const long long idx = (long long)j * nx + i;
+        const double a = eta[idx], b = hu[idx], c = hv[idx];
+        double best = 0.0;
+        for (int n = n_lo; n <= n_hi; ++n) {
+            const float *sn = snaps + (long long)n * sstride;
+            double ip = (double)sn[idx] * a;
+            ip = ip + (double)sn[idx + hcs] * b;
+            ip = ip + (double)sn[idx + 2 * hcs] * c;
+            best = fmax(best, fabs(ip));
+        }
+        const uint8_t f = best > tol ? 1 : 0;
+        flags[idx] = f;
+        local += f;
+    }
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+}
+
+// ---------------------------------------------------------------------------
+// compensated reductions
+// ---------------------------------------------------------------------------
+struct KSum {
+    double s, c;
+};
+
+__device__ __forceinline__ void kadd(KSum &a, double x)
+{
+    const double t = a.s + x;
+    if (fabs(a.s) >= fabs(x))
+        a.c += (a.s - t) + x;
+    else
+        a.c += (x - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void kmerge(KSum &a, const KSum &b)
+{
+    kadd(a, b.s);
+    a.c += b.c;
+}
+
+template <int NT>
+__device__ __forceinline__ KSum block_reduce(KSum v)
+{
+    __shared__ double ss[NT], sc[NT];
+    ss[threadIdx.x] = v.s;
+    sc[threadIdx.x] = v.c;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            KSum a{ss[threadIdx.x], sc[threadIdx.x]};
+            KSum b{ss[threadIdx.x + w], sc[threadIdx.x + w]};
+            kmerge(a, b);
+            ss[threadIdx.x] = a.s;
+            sc[threadIdx.x] = a.c;
+        }
+        __syncthreads();
+    }
+    return KSum{ss[0], sc[0]};
+}
+
+template <typename TA>
+__global__ __launch_bounds__(256) void sum_indicator_kernel(const TA *__restrict__ a, long long cs, long long n,
+                                                            int comp, const uint8_t *__restrict__ ind,
+                                                            double *__restrict__ partials)
+{
+    KSum acc{0.0, 0.0};
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        if (ind[i]) kadd(acc, (double)a[comp * cs + i]);
+    KSum r = block_reduce<256>(acc);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = r.s;
+        partials[2 * blockIdx.x + 1] = r.c;
+    }
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void sum_dot_kernel(const TA *__restrict__ a, long long acs,
+                                                      const TB *__restrict__ b, long long bcs, long long n, int m,
+                                                      double *__restrict__ partials)
+{
+    KSum acc{0.0, 0.0};
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        for (int c = 0; c < m; ++c) kadd(acc, (double)a[c * acs + i] * (double)b[c * bcs + i]);
+    KSum r = block_reduce<256>(acc);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = r.s;
+        partials[2 * blockIdx.x + 1] = r.c;
+    }
+}
+
+__global__ __launch_bounds__(256) void sum_dot_mixed_kernel(const double *__restrict__ eta,
+                                                            const float *__restrict__ hu,
+                                                            const float *__restrict__ hv, long long cs,
+                                                            const float *__restrict__ b, long long bcs, long long n,
+                                                            double *__restrict__ partials)
+{
+    KSum acc{0.0, 0.0};
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        kadd(acc, eta[i] * (double)b[i]);
+        kadd(acc, (double)hu[i] * (double)b[bcs + i]);
+        kadd(acc, (double)hv[i] * (double)b[2 * bcs + i]);
+    }
+    KSum r = block_reduce<256>(acc);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = r.s;
+        partials[2 * blockIdx.x + 1] = r.c;
+    }
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ partials, int nb,
+                                                     double *__restrict__ out)
+{
+    KSum acc{0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += 256) kmerge(acc, KSum{partials[2 * i], partials[2 * i + 1]});
+    KSum r = block_reduce<256>(acc);
+    if (threadIdx.x == 0) out[0] = r.s + r.c;
+}
+
+__global__ void fill_u8_kernel(uint8_t *p, long long n, uint8_t v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+template <typename TQ, typename TH>
+void launch_flag(const TQ *q, long long cs, int nx, int ny, int m, const TH *snaps, long long snap_stride,
+                 long long hcs, int NX, int NY, int ratio, int n_lo, int n_hi, double tol, const Tile *tiles,
+                 int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s)
+{
+    (void)ny;
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((flag_kernel<TQ, TH>), dim3(ntiles), dim3(256), 0, s, q, cs, nx, m, snaps, snap_stride, hcs,
+                       NX, NY, ratio, n_lo, n_hi, tol, tiles, flags, count);
+}
+
+void launch_flag_mixed(const double *eta, const float *hu, const float *hv, long long cs, int nx, int ny,
+                       const float *snaps, long long snap_stride, long long hcs, int n_lo, int n_hi, double tol,
+                       const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s)
+{
+    (void)cs;
+    (void)ny;
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(flag_mixed_kernel, dim3(ntiles), dim3(256), 0, s, eta, hu, hv, nx, snaps, snap_stride, hcs,
+                       n_lo, n_hi, tol, tiles, flags, count);
+}
+
+template <typename TA>
+void launch_sum_indicator(const TA *a, long long cs, long long n, int comp, const uint8_t *ind, double *partials,
+                          int nblocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((sum_indicator_kernel<TA>), dim3(nblocks), dim3(256), 0, s, a, cs, n, comp, ind, partials);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+}
+
+template <typename TA, typename TB>
+void launch_sum_dot(const TA *a, long long acs, const TB *b, long long bcs, long long n, int m, double *partials,
+                    int nblocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((sum_dot_kernel<TA, TB>), dim3(nblocks), dim3(256), 0, s, a, acs, b, bcs, n, m, partials);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+}
+
+void launch_sum_dot_mixed(const double *eta, const float *hu, const float *hv, long long cs, const float *b,
+                          long long bcs, long long n, double *partials, int nblocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_dot_mixed_kernel, dim3(nblocks), dim3(256), 0, s, eta, hu, hv, cs, b, bcs, n, partials);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+}
+
+void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s)
+{
+    if (n <= 0) return;
+    const long long nb = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+}
+
+template void launch_flag<double, double>(const double *, long long, int, int, int, const double *, long long,
+                                          long long, int, int, int, int, int, double, const Tile *, int, uint8_t *,
+                                          unsigned long long *, hipStream_t);
+template void launch_flag<float, float>(const float *, long long, int, int, int, const float *, long long, long long,
+                                        int, int, int, int, int, double, const Tile *, int, uint8_t *,
+                                        unsigned long long *, hipStream_t);
+template void launch_sum_indicator<double>(const double *, long long, long long, int, const uint8_t *, double *, int,
+                                           double *, hipStream_t);
+template void launch_sum_indicator<float>(const float *, long long, long long, int, const uint8_t *, double *, int,
+                                          double *, hipStream_t);
+template void launch_sum_dot<double, double>(const double *, long long, const double *, long long, long long, int,
+                                             double *, int, double *, hipStream_t);
+template void launch_sum_dot<float, float>(const float *, long long, const float *, long long, long long, int,
+                                           double *, int, double *, hipStream_t);
+
+}  // namespace wp

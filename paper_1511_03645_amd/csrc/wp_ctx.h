@@ -1,0 +1,102 @@
+// Handle layout shared by the host translation units of the library.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "wp_internal.h"
+
+constexpr int RED_BLOCKS = 1024;
+
+// One refinement level: a canvas covering the whole domain at the level's
+// resolution (double-buffered), the patches that are active on it and the
+// tile tables of its launches.
+struct Level {
+    int nx = 0, ny = 0;
+    double dx = 0.0, dy = 0.0;
+    int ratio = 1;                       // refinement relative to the level below
+    void *q[2] = {nullptr, nullptr};     // state canvases
+    int cur = 0;                         // index of the current canvas
+    uint8_t *mat = nullptr;              // acoustics material index per cell
+    uint8_t *flags = nullptr;            // flag canvas
+    bool flags_valid = false;
+    std::vector<wp_patch> patches;
+    std::vector<wp::Tile> tiles_host;
+    wp::Tile *tiles_dev = nullptr;
+    int ntiles = 0;
+    wp::Tile *ftiles_dev = nullptr;      // flag / reduction tiles
+    int nftiles = 0;
+    double t = 0.0;
+    void *inst = nullptr;                // device instance descriptor
+    double inst_dt = -1.0;
+    alignas(16) unsigned char inst_host[256];
+    // AMR: cells of the ghost ring (inside the domain, outside every patch,
+    // within two cells of one) filled from the level below before each step
+    int *ring_dev = nullptr;
+    long long nring = 0;
+    void *coarse_old = nullptr;          // level below at the start of its step
+    double t_coarse_old = 0.0, t_coarse_new = 0.0;
+};
+
+struct wp_ctx {
+    wp_problem prob{};
+    wp_grid grid{};
+    wp_allocator alloc{};
+    bool has_alloc = false;
+    hipStream_t stream = nullptr;
+    bool kind2d = true, is_acoustics = true;
+    int m = 3, esz = 8;
+    std::vector<void *> owned;
+    std::vector<Level> L;
+    Level adj;                           // adjoint grid (level-0 resolution)
+    // acoustics media
+    int nmat = 0;
+    std::vector<double> rho, K;
+    std::vector<uint8_t> mat0;
+    double cmax = 0.0;
+    void *mtab = nullptr, *ptab = nullptr;
+    // shallow water
+    void *Bdev = nullptr;                // bathymetry (FP64)
+    void *cbar = nullptr;                // sqrt(-g B) in the adjoint precision
+    void *swe_inst = nullptr, *swe_adj_inst = nullptr;
+    double swe_inst_dt = -1.0, swe_adj_inst_dt = -1.0;
+    double last_cfl = 0.0;
+    // adjoint snapshots
+    void *snaps = nullptr;
+    size_t snaps_cap = 0, snap_bytes = 0;
+    int nsnap = 0;
+    double snap_ds = 0.0, adj_tf = 0.0;
+    // device scratch
+    int *status = nullptr;
+    unsigned long long *count = nullptr;
+    double *partials = nullptr, *red_out = nullptr;
+    unsigned *cflbits = nullptr;
+    uint8_t *ind_dev = nullptr;
+    std::string err;
+    int tile_rows = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0;
+    double graph_dt = 0.0;
+    int graph_parity = -1;
+    size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
+};
+
+int wp_fail(wp_ctx *ctx, int code, const char *fmt, ...);
+void *wp_dalloc(wp_ctx *ctx, size_t bytes);
+void wp_dfree(wp_ctx *ctx, void *p);
+std::vector<wp::Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, int rows, int width, bool xcd_order);
+int wp_upload_tiles(wp_ctx *ctx, Level &lv);
+int wp_default_rows(const wp_ctx *ctx, const Level &lv);
+int wp_alloc_level(wp_ctx *ctx, Level &lv);
+int wp_check_status(wp_ctx *ctx);
+int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt);
+int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint);
+int wp_build_indicator(wp_ctx *ctx, const wp_functional *J, std::vector<uint8_t> &ind);
+int wp_ensure_adjoint_level(wp_ctx *ctx);
+int wp_window(wp_ctx *ctx, double t, double t_s, double t_f, int &n_lo, int &n_hi);
+// shallow water (swe_host.hip)
+int wp_swe_init(wp_ctx *ctx, const wp_coefficients *coef);
+int wp_swe_adj_init(wp_ctx *ctx);
+int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint);
+// refinement (amr_host.hip)
+int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t);

@@ -1,0 +1,809 @@
+// Host side of the C ABI (include/wp.h): handles, device memory, tile
+// tables, time stepping, the adjoint run and its snapshot store, flagging
+// and functionals.  Kernels live in acoustics.hip, swe.hip, flag_reduce.hip
+// and amr.hip; Berger-Rigoutsos clustering in cluster.cpp.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "wp_ctx.h"
+
+using namespace wp;
+
+// ---------------------------------------------------------------------------
+// errors and memory
+// ---------------------------------------------------------------------------
+int wp_fail(wp_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+void *wp_dalloc(wp_ctx *ctx, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (ctx->has_alloc) {
+        p = ctx->alloc.alloc(bytes, ctx->alloc.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p) ctx->owned.push_back(p);
+    return p;
+}
+
+void wp_dfree(wp_ctx *ctx, void *p)
+{
+    if (!p) return;
+    auto it = std::find(ctx->owned.begin(), ctx->owned.end(), p);
+    if (it != ctx->owned.end()) ctx->owned.erase(it);
+    if (ctx->has_alloc)
+        ctx->alloc.free(p, ctx->alloc.user);
+    else
+        (void)hipFree(p);
+}
+
+static size_t state_bytes(const wp_ctx *ctx, long long cells)
+{
+    if (ctx->prob.precision == WP_MIXED) return (size_t)cells * (8 + 4 + 4);
+    return (size_t)cells * ctx->m * ctx->esz;
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+// ---------------------------------------------------------------------------
+// Tiles of the 2D step kernels: strips of STRIP columns and `rows` rows over
+// every patch.  Ordered so that the workgroups the hardware places on one XCD
+// (workgroup ids congruent mod 8) receive one contiguous, column-major run of
+// tiles, keeping vertically adjacent tiles -- which share halo rows -- in the
+// same L2.
+std::vector<Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, int rows, int width, bool xcd_order)
+{
+    std::vector<Tile> t;
+    for (const auto &p : patches)
+        for (int i = 0; i < p.nx; i += width)
+            for (int j = 0; j < p.ny; j += rows)
+                t.push_back(Tile{inst, p.ilo + i, p.jlo + j, std::min(width, p.nx - i), std::min(rows, p.ny - j)});
+    if (!xcd_order || t.size() < 16) return t;
+    const size_t n = t.size(), nx = 8;
+    std::vector<Tile> o(n);
+    const size_t chunk = (n + nx - 1) / nx;
+    size_t k = 0;
+    for (size_t r = 0; r < chunk; ++r)
+        for (size_t x = 0; x < nx; ++x) {
+            const size_t src = x * chunk + r;
+            if (src < n) o[k++] = t[src];
+        }
+    o.resize(k);
+    return o;
+}
+
+int wp_upload_tiles(wp_ctx *ctx, Level &lv)
+{
+    const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
+    const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, lv);
+    lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, true);
+    // flag / reduction tiles: larger blocks of whole patches
+    std::vector<Tile> ft = wp_make_tiles(lv.patches, 0, 16, 64, false);
+    if (lv.tiles_dev) wp_dfree(ctx, lv.tiles_dev);
+    if (lv.ftiles_dev) wp_dfree(ctx, lv.ftiles_dev);
+    lv.tiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, lv.tiles_host.size()));
+    lv.ftiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, ft.size()));
+    if (!lv.tiles_dev || !lv.ftiles_dev) return wp_fail(ctx, WP_ENOMEM, "tile table allocation failed");
+    lv.ntiles = (int)lv.tiles_host.size();
+    lv.nftiles = (int)ft.size();
+    if (lv.ntiles && hipMemcpy(lv.tiles_dev, lv.tiles_host.data(), sizeof(Tile) * lv.ntiles, hipMemcpyHostToDevice) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "tile upload failed");
+    if (lv.nftiles && hipMemcpy(lv.ftiles_dev, ft.data(), sizeof(Tile) * lv.nftiles, hipMemcpyHostToDevice) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "tile upload failed");
+    return WP_OK;
+}
+
+int wp_default_rows(const wp_ctx *ctx, const Level &lv)
+{
+    (void)ctx;
+    // enough strips to give every SIMD several waves on small grids, long
+    // marches (little halo re-read) on large ones
+    const long long cells = (long long)lv.nx * lv.ny;
+    if (cells <= (1LL << 18)) return 8;
+    if (cells <= (1LL << 21)) return 16;
+    return 32;
+}
+
+// ---------------------------------------------------------------------------
+// creation
+// ---------------------------------------------------------------------------
+static int build_materials(wp_ctx *ctx, const wp_coefficients *coef)
+{
+    const int nx = ctx->grid.nx0, ny = ctx->kind2d ? ctx->grid.ny0 : 1;
+    std::map<std::pair<double, double>, int> ids;
+    std::vector<uint8_t> mat((size_t)nx * ny);
+    for (long long k = 0; k < (long long)nx * ny; ++k) {
+        const double r = coef->rho[k], K = coef->K[k];
+        if (!(r > 0.0) || !(K > 0.0) || !std::isfinite(r) || !std::isfinite(K))
+            return wp_fail(ctx, WP_EINVAL, "rho and K must be positive and finite (cell %lld)", k);
+        auto key = std::make_pair(r, K);
+        auto it = ids.find(key);
+        int id;
+        if (it == ids.end()) {
+            id = (int)ids.size();
+            if (id >= MAXMAT) return wp_fail(ctx, WP_EINVAL, "more than %d distinct (rho, K) pairs", MAXMAT);
+            ids[key] = id;
+            ctx->rho.push_back(r);
+            ctx->K.push_back(K);
+        } else {
+            id = it->second;
+        }
+        mat[k] = (uint8_t)id;
+    }
+    ctx->nmat = (int)ids.size();
+    ctx->mat0 = mat;
+    ctx->cmax = 0.0;
+    for (int a = 0; a < ctx->nmat; ++a) ctx->cmax = std::max(ctx->cmax, std::sqrt(ctx->K[a] / ctx->rho[a]));
+    // material and pair tables in the state precision
+    const int nm = ctx->nmat;
+    std::vector<double> mt(nm * 4), pt(nm * nm * 3);
+    std::vector<double> Z(nm), c(nm);
+    for (int a = 0; a < nm; ++a) {
+        Z[a] = std::sqrt(ctx->rho[a] * ctx->K[a]);
+        c[a] = std::sqrt(ctx->K[a] / ctx->rho[a]);
+        mt[a * 4 + 0] = Z[a];
+        mt[a * 4 + 1] = c[a];
+        mt[a * 4 + 2] = ctx->K[a];
+        mt[a * 4 + 3] = 1.0 / ctx->rho[a];
+    }
+    for (int a = 0; a < nm; ++a)
+        for (int b = 0; b < nm; ++b) {
+            double *p = &pt[(a * nm + b) * 3];
+            p[0] = 1.0 / (Z[a] + Z[b]);
+            p[1] = (Z[a] * Z[b] + 1.0) / (Z[a] * Z[a] + 1.0);   // wave 1, upwind edge to the right
+            p[2] = (Z[a] * Z[b] + 1.0) / (Z[b] * Z[b] + 1.0);   // wave 2, upwind edge to the left
+        }
+    ctx->mtab = wp_dalloc(ctx, mt.size() * ctx->esz);
+    ctx->ptab = wp_dalloc(ctx, pt.size() * ctx->esz);
+    if (!ctx->mtab || !ctx->ptab) return wp_fail(ctx, WP_ENOMEM, "material tables");
+    if (ctx->esz == 8) {
+        if (hipMemcpy(ctx->mtab, mt.data(), mt.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ctx->ptab, pt.data(), pt.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "material table upload");
+    } else {
+        std::vector<float> mf(mt.begin(), mt.end()), pf(pt.begin(), pt.end());
+        if (hipMemcpy(ctx->mtab, mf.data(), mf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ctx->ptab, pf.data(), pf.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "material table upload");
+    }
+    return WP_OK;
+}
+
+int wp_alloc_level(wp_ctx *ctx, Level &lv)
+{
+    const long long cells = (long long)lv.nx * lv.ny;
+    for (int b = 0; b < 2; ++b) {
+        lv.q[b] = wp_dalloc(ctx, state_bytes(ctx, cells));
+        if (!lv.q[b]) return wp_fail(ctx, WP_ENOMEM, "state canvas (%lld cells)", cells);
+        if (hipMemsetAsync(lv.q[b], 0, state_bytes(ctx, cells), ctx->stream) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "state clear");
+    }
+    lv.flags = (uint8_t *)wp_dalloc(ctx, (size_t)cells);
+    if (!lv.flags) return wp_fail(ctx, WP_ENOMEM, "flag canvas");
+    if (hipMemsetAsync(lv.flags, 0, (size_t)cells, ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "flag clear");
+    if (ctx->is_acoustics) {
+        // material of each level cell: that of the level-0 cell containing it
+        lv.mat = (uint8_t *)wp_dalloc(ctx, (size_t)cells);
+        if (!lv.mat) return wp_fail(ctx, WP_ENOMEM, "material canvas");
+        std::vector<uint8_t> m((size_t)cells);
+        const int r = lv.nx / ctx->grid.nx0;
+        const int ry = ctx->kind2d ? lv.ny / ctx->grid.ny0 : 1;
+        for (int j = 0; j < lv.ny; ++j)
+            for (int i = 0; i < lv.nx; ++i) m[(size_t)j * lv.nx + i] = ctx->mat0[(size_t)(j / ry) * ctx->grid.nx0 + i / r];
+        if (hipMemcpy(lv.mat, m.data(), m.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "material upload");
+    }
+    return WP_OK;
+}
+
+extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef, const wp_grid *grid,
+                         const wp_allocator *alloc, void *stream, wp_ctx **out)
+{
+    if (!out) return WP_EINVAL;
+    *out = nullptr;
+    if (!problem || !coef || !grid) return WP_EINVAL;
+    wp_ctx *ctx = new wp_ctx();
+    ctx->prob = *problem;
+    ctx->grid = *grid;
+    ctx->stream = (hipStream_t)stream;
+    if (alloc && alloc->alloc && alloc->free) {
+        ctx->alloc = *alloc;
+        ctx->has_alloc = true;
+    }
+    const wp_problem &P = ctx->prob;
+    int rc = WP_OK;
+    auto bail = [&](int code) {
+        *out = ctx;   // hand back for wp_last_error, caller destroys
+        return code;
+    };
+    if (P.kind != WP_ACOUSTICS_1D && P.kind != WP_ACOUSTICS_2D && P.kind != WP_SWE_2D)
+        return bail(wp_fail(ctx, WP_EINVAL, "unknown kind %d", P.kind));
+    ctx->kind2d = P.kind != WP_ACOUSTICS_1D;
+    ctx->is_acoustics = P.kind != WP_SWE_2D;
+    ctx->m = P.kind == WP_ACOUSTICS_1D ? 2 : 3;
+    if (P.precision == WP_FP64) ctx->esz = 8;
+    else if (P.precision == WP_FP32 && ctx->is_acoustics) ctx->esz = 4;
+    else if (P.precision == WP_MIXED && !ctx->is_acoustics) ctx->esz = 4;
+    else if (P.precision == WP_FP32 && !ctx->is_acoustics) ctx->esz = 4;
+    else return bail(wp_fail(ctx, WP_EINVAL, "precision %d not available for kind %d", P.precision, P.kind));
+    if (P.order < 1 || P.order > 2 || P.limiter < 0 || P.limiter > 1 || P.transverse < 0 || P.transverse > 1)
+        return bail(wp_fail(ctx, WP_EINVAL, "order must be 1|2, limiter 0|1, transverse 0|1"));
+    for (int k = 0; k < 4; ++k)
+        if (P.bc[k] < 0 || P.bc[k] > 2) return bail(wp_fail(ctx, WP_EINVAL, "bad boundary type"));
+    if ((P.bc[0] == WP_BC_PERIODIC) != (P.bc[1] == WP_BC_PERIODIC) ||
+        (ctx->kind2d && (P.bc[2] == WP_BC_PERIODIC) != (P.bc[3] == WP_BC_PERIODIC)))
+        return bail(wp_fail(ctx, WP_EINVAL, "periodic boundaries must be paired"));
+    if (!(P.cfl_max > 0.0)) return bail(wp_fail(ctx, WP_EINVAL, "cfl_max must be positive"));
+    const wp_grid &G = ctx->grid;
+    if (G.nx0 < 4 || (ctx->kind2d && G.ny0 < 4)) return bail(wp_fail(ctx, WP_EINVAL, "grid must be at least 4 cells per side"));
+    if (!(G.xhi > G.xlo) || (ctx->kind2d && !(G.yhi > G.ylo))) return bail(wp_fail(ctx, WP_EINVAL, "empty domain"));
+    if (G.num_levels < 1 || G.num_levels > WP_MAX_LEVELS) return bail(wp_fail(ctx, WP_EINVAL, "num_levels out of range"));
+    if (G.num_levels > 1 && P.kind != WP_ACOUSTICS_2D)
+        return bail(wp_fail(ctx, WP_EINVAL, "refinement levels are supported for 2D acoustics"));
+    for (int l = 0; l + 1 < G.num_levels; ++l)
+        if (G.ratio[l] < 2 || G.ratio[l] > 8 || (G.ratio[l] & (G.ratio[l] - 1)))
+            return bail(wp_fail(ctx, WP_EINVAL, "refinement ratios must be 2, 4 or 8"));
+    if (ctx->is_acoustics) {
+        if (!coef->rho || !coef->K) return bail(wp_fail(ctx, WP_EINVAL, "acoustics needs rho and K"));
+        if ((rc = build_materials(ctx, coef)) != WP_OK) return bail(rc);
+    } else {
+        if (!coef->B) return bail(wp_fail(ctx, WP_EINVAL, "shallow water needs B"));
+        if (!(P.g > 0.0)) return bail(wp_fail(ctx, WP_EINVAL, "g must be positive"));
+    }
+    // status words and reduction scratch
+    ctx->status = (int *)wp_dalloc(ctx, 256);
+    ctx->count = (unsigned long long *)wp_dalloc(ctx, 256);
+    ctx->partials = (double *)wp_dalloc(ctx, sizeof(double) * 2 * RED_BLOCKS);
+    ctx->red_out = (double *)wp_dalloc(ctx, 256);
+    ctx->cflbits = (unsigned *)wp_dalloc(ctx, 256);
+    if (!ctx->status || !ctx->count || !ctx->partials || !ctx->red_out || !ctx->cflbits)
+        return bail(wp_fail(ctx, WP_ENOMEM, "scratch"));
+    if (hipMemsetAsync(ctx->status, 0, 256, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->cflbits, 0, 256, ctx->stream) != hipSuccess)
+        return bail(wp_fail(ctx, WP_EDEVICE, "status clear"));
+    // levels
+    int nxl = G.nx0, nyl = ctx->kind2d ? G.ny0 : 1;
+    for (int l = 0; l < G.num_levels; ++l) {
+        Level lv;
+        lv.nx = nxl;
+        lv.ny = nyl;
+        lv.dx = (G.xhi - G.xlo) / nxl;
+        lv.dy = ctx->kind2d ? (G.yhi - G.ylo) / nyl : 1.0;
+        lv.ratio = l == 0 ? 1 : G.ratio[l - 1];
+        ctx->L.push_back(lv);
+        if (l + 1 < G.num_levels) {
+            nxl *= G.ratio[l];
+            nyl *= G.ratio[l];
+        }
+    }
+    for (int l = 0; l < G.num_levels; ++l)
+        if ((rc = wp_alloc_level(ctx, ctx->L[l])) != WP_OK) return bail(rc);
+    ctx->L[0].patches.push_back(wp_patch{0, 0, ctx->L[0].nx, ctx->L[0].ny});
+    if ((rc = wp_upload_tiles(ctx, ctx->L[0])) != WP_OK) return bail(rc);
+    if (!ctx->is_acoustics && (rc = wp_swe_init(ctx, coef)) != WP_OK) return bail(rc);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(wp_fail(ctx, WP_EDEVICE, "create sync"));
+    *out = ctx;
+    return WP_OK;
+}
+
+extern "C" void wp_destroy(wp_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    std::vector<void *> all = ctx->owned;
+    for (void *p : all) wp_dfree(ctx, p);
+    delete ctx;
+}
+
+extern "C" const char *wp_last_error(const wp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null handle"; }
+
+extern "C" const char *wp_status_string(int s)
+{
+    switch (s) {
+    case WP_OK: return "ok";
+    case WP_EINVAL: return "invalid argument";
+    case WP_ENOMEM: return "out of device memory";
+    case WP_EDEVICE: return "HIP runtime error";
+    case WP_ECFL: return "Courant number above the limit";
+    case WP_ENONFINITE: return "non-finite value";
+    case WP_ERANGE: return "outside the stored adjoint snapshots";
+    case WP_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int wp_set_stream(wp_ctx *ctx, void *stream)
+{
+    if (!ctx) return WP_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->stream = (hipStream_t)stream;
+    return WP_OK;
+}
+
+extern "C" int wp_level_info(const wp_ctx *ctx, int level, int *nx, int *ny, int *npatches)
+{
+    if (!ctx || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
+    if (nx) *nx = ctx->L[level].nx;
+    if (ny) *ny = ctx->L[level].ny;
+    if (npatches) *npatches = (int)ctx->L[level].patches.size();
+    return WP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state transfer
+// ---------------------------------------------------------------------------
+// Copy between a caller buffer [m][h][w] and box (i0, j0, w, h) of a level
+// canvas.  Component k of the canvas sits at k * cells elements of size esz
+// (mixed precision: eta doubles, then hu, hv floats).
+static int copy_box(wp_ctx *ctx, Level &lv, int i0, int j0, int w, int h, void *user, int on_device, bool to_canvas)
+{
+    const long long cells = (long long)lv.nx * lv.ny;
+    char *canvas = (char *)lv.q[lv.cur];
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice
+                                         : (to_canvas ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+    size_t uoff = 0;
+    size_t coff = 0;
+    for (int k = 0; k < ctx->m; ++k) {
+        const size_t es = ctx->prob.precision == WP_MIXED ? (k == 0 ? 8 : 4) : (size_t)ctx->esz;
+        char *cbase = canvas + coff + ((size_t)j0 * lv.nx + i0) * es;
+        char *ubase = (char *)user + uoff;
+        hipError_t e;
+        if (to_canvas)
+            e = hipMemcpy2DAsync(cbase, (size_t)lv.nx * es, ubase, (size_t)w * es, (size_t)w * es, h, kind, ctx->stream);
+        else
+            e = hipMemcpy2DAsync(ubase, (size_t)w * es, cbase, (size_t)lv.nx * es, (size_t)w * es, h, kind, ctx->stream);
+        if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "state copy: %s", hipGetErrorString(e));
+        uoff += (size_t)w * h * es;
+        coff += (size_t)cells * es;
+    }
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "state copy sync");
+    return WP_OK;
+}
+
+static int box_of(wp_ctx *ctx, int level, int patch, int &i0, int &j0, int &w, int &h)
+{
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level %d out of range", level);
+    Level &lv = ctx->L[level];
+    if (patch < 0) {
+        i0 = j0 = 0;
+        w = lv.nx;
+        h = lv.ny;
+        return WP_OK;
+    }
+    if (patch >= (int)lv.patches.size()) return wp_fail(ctx, WP_EINVAL, "patch %d out of range", patch);
+    const wp_patch &p = lv.patches[patch];
+    i0 = p.ilo;
+    j0 = p.jlo;
+    w = p.nx;
+    h = p.ny;
+    return WP_OK;
+}
+
+extern "C" int wp_set_state(wp_ctx *ctx, int level, int patch, const void *src, int on_device)
+{
+    if (!ctx || !src) return ctx ? wp_fail(ctx, WP_EINVAL, "null source") : WP_EINVAL;
+    int i0, j0, w, h, rc;
+    if ((rc = box_of(ctx, level, patch, i0, j0, w, h)) != WP_OK) return rc;
+    return copy_box(ctx, ctx->L[level], i0, j0, w, h, const_cast<void *>(src), on_device, true);
+}
+
+extern "C" int wp_get_state(wp_ctx *ctx, int level, int patch, void *dst, int on_device)
+{
+    if (!ctx || !dst) return ctx ? wp_fail(ctx, WP_EINVAL, "null destination") : WP_EINVAL;
+    int i0, j0, w, h, rc;
+    if ((rc = box_of(ctx, level, patch, i0, j0, w, h)) != WP_OK) return rc;
+    if ((rc = copy_box(ctx, ctx->L[level], i0, j0, w, h, dst, on_device, false)) != WP_OK) return rc;
+    return wp_check_status(ctx);
+}
+
+int wp_check_status(wp_ctx *ctx)
+{
+    int st = 0;
+    if (hipMemcpyAsync(&st, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "status read: %s", hipGetErrorString(hipGetLastError()));
+    if (st) {
+        (void)hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
+        if (st & ST_NONFINITE) return wp_fail(ctx, WP_ENONFINITE, "a step produced a non-finite value");
+        if (st & ST_CFL) return wp_fail(ctx, WP_ECFL, "a step exceeded the Courant limit %g", ctx->prob.cfl_max);
+    }
+    return WP_OK;
+}
+
+extern "C" int wp_sync(wp_ctx *ctx)
+{
+    if (!ctx) return WP_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "sync: %s", hipGetErrorString(hipGetLastError()));
+    return wp_check_status(ctx);
+}
+
+extern "C" int wp_get_time(const wp_ctx *ctx, int level, double *t)
+{
+    if (!ctx || !t || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
+    *t = ctx->L[level].t;
+    return WP_OK;
+}
+
+extern "C" int wp_set_time(wp_ctx *ctx, int level, double t)
+{
+    if (!ctx || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
+    ctx->L[level].t = t;
+    return WP_OK;
+}
+
+extern "C" int wp_set_tile_rows(wp_ctx *ctx, int rows)
+{
+    if (!ctx || rows < 0 || rows > 4096) return WP_EINVAL;
+    ctx->tile_rows = rows;
+    int rc;
+    for (auto &lv : ctx->L)
+        if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
+    if (ctx->adj.q[0] && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
+    return WP_OK;
+}
+
+extern "C" int wp_get_tile_rows(const wp_ctx *ctx, int *rows)
+{
+    if (!ctx || !rows) return WP_EINVAL;
+    *rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, ctx->L[0]);
+    return WP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// acoustics stepping
+// ---------------------------------------------------------------------------
+template <typename T>
+static int ensure_acou_inst(wp_ctx *ctx, Level &lv, double dt)
+{
+    if (lv.inst && lv.inst_dt == dt) return WP_OK;
+    AcouInst<T> I;
+    memset(&I, 0, sizeof I);
+    I.q[0] = (T *)lv.q[0];
+    I.q[1] = (T *)lv.q[1];
+    I.mat = lv.mat;
+    I.cs = (long long)lv.nx * lv.ny;
+    I.nx = lv.nx;
+    I.ny = lv.ny;
+    for (int k = 0; k < 4; ++k) I.bc[k] = ctx->prob.bc[k];
+    I.nux = (T)(dt / lv.dx);
+    I.nuy = (T)(ctx->kind2d ? dt / lv.dy : 0.0);
+    I.mtab = (const T *)ctx->mtab;
+    I.ptab = (const T *)ctx->ptab;
+    I.nmat = ctx->nmat;
+    I.order = ctx->prob.order;
+    I.limiter = ctx->prob.limiter;
+    I.transverse = ctx->kind2d ? ctx->prob.transverse : 0;
+    if (!lv.inst) lv.inst = wp_dalloc(ctx, sizeof(AcouInst<T>));
+    if (!lv.inst) return wp_fail(ctx, WP_ENOMEM, "instance");
+    if (hipMemcpyAsync(lv.inst, &I, sizeof I, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "instance upload");
+    lv.inst_dt = dt;
+    memcpy(lv.inst_host, &I, sizeof I);
+    return WP_OK;
+}
+
+template <typename T>
+static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint)
+{
+    int rc;
+    if ((rc = ensure_acou_inst<T>(ctx, lv, dt)) != WP_OK) return rc;
+    if (ctx->kind2d)
+        launch_acou2d<T>((const AcouInst<T> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, ctx->status,
+                         ctx->stream);
+    else
+        launch_acou1d<T>((const AcouInst<T> *)lv.inst, *(const AcouInst<T> *)lv.inst_host, lv.cur, adjoint, ctx->status,
+                         ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    lv.cur ^= 1;
+    return WP_OK;
+}
+
+int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return wp_fail(ctx, WP_EINVAL, "dt must be positive");
+    if (ctx->is_acoustics) {
+        const double nu = ctx->cmax * dt / (ctx->kind2d ? std::min(lv.dx, lv.dy) : lv.dx);
+        if (nu > ctx->prob.cfl_max * (1.0 + 1e-12))
+            return wp_fail(ctx, WP_ECFL, "Courant number %.6g above %.6g", nu, ctx->prob.cfl_max);
+    }
+    return WP_OK;
+}
+
+int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint)
+{
+    if (ctx->is_acoustics) {
+        if (ctx->esz == 8) return acou_step<double>(ctx, lv, dt, adjoint);
+        return acou_step<float>(ctx, lv, dt, adjoint);
+    }
+    return wp_swe_step(ctx, lv, dt, adjoint);
+}
+
+extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
+{
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level %d out of range", level);
+    Level &lv = ctx->L[level];
+    int rc;
+    if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
+    if (lv.patches.empty()) {
+        lv.t += dt;
+        return WP_OK;
+    }
+    if (level > 0 && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK) return rc;
+    if ((rc = wp_step_level(ctx, lv, dt, 0)) != WP_OK) return rc;
+    lv.t += dt;
+    return WP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint run and snapshot store
+// ---------------------------------------------------------------------------
+static bool in_target(const wp_functional *J, double x, double y, bool is2d)
+{
+    switch (J->kind) {
+    case WP_FUNC_INTERVAL: return x >= J->x0 && x <= J->x1;
+    case WP_FUNC_BOX: return x >= J->x0 && x <= J->x1 && (!is2d || (y >= J->y0 && y <= J->y1));
+    case WP_FUNC_DISC: {
+        const double dx = x - J->cx, dy = y - J->cy;
+        return dx * dx + dy * dy <= J->r * J->r;
+    }
+    }
+    return false;
+}
+
+// indicator of the target region at level-0 cell centres (closed set)
+int wp_build_indicator(wp_ctx *ctx, const wp_functional *J, std::vector<uint8_t> &ind)
+{
+    if (!J || J->kind < 0 || J->kind > 2 || J->component < 0 || J->component >= ctx->m)
+        return wp_fail(ctx, WP_EINVAL, "bad functional");
+    const Level &l0 = ctx->L[0];
+    ind.assign((size_t)l0.nx * l0.ny, 0);
+    for (int j = 0; j < l0.ny; ++j)
+        for (int i = 0; i < l0.nx; ++i) {
+            const double x = ctx->grid.xlo + (i + 0.5) * l0.dx;
+            const double y = ctx->kind2d ? ctx->grid.ylo + (j + 0.5) * l0.dy : 0.0;
+            ind[(size_t)j * l0.nx + i] = in_target(J, x, y, ctx->kind2d) ? 1 : 0;
+        }
+    return WP_OK;
+}
+
+int wp_ensure_adjoint_level(wp_ctx *ctx)
+{
+    Level &a = ctx->adj;
+    if (a.q[0]) return WP_OK;
+    const Level &l0 = ctx->L[0];
+    a.nx = l0.nx;
+    a.ny = l0.ny;
+    a.dx = l0.dx;
+    a.dy = l0.dy;
+    a.ratio = 1;
+    int rc;
+    if ((rc = wp_alloc_level(ctx, a)) != WP_OK) return rc;
+    a.patches.push_back(wp_patch{0, 0, a.nx, a.ny});
+    if (!ctx->is_acoustics && (rc = wp_swe_adj_init(ctx)) != WP_OK) return rc;
+    return wp_upload_tiles(ctx, a);
+}
+
+extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *sp)
+{
+    if (!ctx) return WP_EINVAL;
+    if (!sp || sp->nsteps < 0 || sp->snap_every < 1 || sp->nsteps % sp->snap_every != 0)
+        return wp_fail(ctx, WP_EINVAL, "snapshot spec: nsteps must be a non-negative multiple of snap_every >= 1");
+    int rc;
+    std::vector<uint8_t> ind;
+    if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
+    if ((rc = wp_ensure_adjoint_level(ctx)) != WP_OK) return rc;
+    Level &a = ctx->adj;
+    if ((rc = wp_courant_check(ctx, a, sp->dt)) != WP_OK) return rc;
+    const long long cells = (long long)a.nx * a.ny;
+    const int nsnap = sp->nsteps / sp->snap_every + 1;
+    const size_t snap_bytes = (size_t)cells * ctx->m * ctx->snap_esz();
+    if (ctx->snaps_cap < (size_t)nsnap * snap_bytes) {
+        if (ctx->snaps) wp_dfree(ctx, ctx->snaps);
+        ctx->snaps = wp_dalloc(ctx, (size_t)nsnap * snap_bytes);
+        if (!ctx->snaps) {
+            ctx->snaps_cap = 0;
+            ctx->nsnap = 0;
+            return wp_fail(ctx, WP_ENOMEM, "snapshot store (%d x %zu bytes)", nsnap, snap_bytes);
+        }
+        ctx->snaps_cap = (size_t)nsnap * snap_bytes;
+    }
+    // qtilde(x, 0) = phi = I(x) e_component
+    {
+        const size_t es = ctx->snap_esz();
+        std::vector<char> host((size_t)cells * ctx->m * es, 0);
+        for (long long k = 0; k < cells; ++k)
+            if (ind[k]) {
+                char *dst = host.data() + ((size_t)J->component * cells + k) * es;
+                if (es == 8) { double one = 1.0; memcpy(dst, &one, 8); }
+                else { float one = 1.0f; memcpy(dst, &one, 4); }
+            }
+        a.cur = 0;
+        if (hipMemcpy(a.q[0], host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "adjoint initial data upload");
+    }
+    ctx->nsnap = 0;
+    auto snap = [&](int n) -> int {
+        if (hipMemcpyAsync((char *)ctx->snaps + (size_t)n * snap_bytes, a.q[a.cur], snap_bytes,
+                           hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "snapshot copy");
+        return WP_OK;
+    };
+    if ((rc = snap(0)) != WP_OK) return rc;
+    for (int s = 1; s <= sp->nsteps; ++s) {
+        if ((rc = wp_step_level(ctx, a, sp->dt, 1)) != WP_OK) return rc;
+        if (s % sp->snap_every == 0 && (rc = snap(s / sp->snap_every)) != WP_OK) return rc;
+    }
+    ctx->nsnap = nsnap;
+    ctx->snap_ds = sp->dt * sp->snap_every;
+    ctx->adj_tf = sp->dt * sp->nsteps;
+    ctx->snap_bytes = snap_bytes;
+    a.t = ctx->adj_tf;
+    return wp_sync(ctx);
+}
+
+extern "C" int wp_num_snapshots(const wp_ctx *ctx) { return ctx ? ctx->nsnap : 0; }
+
+extern "C" int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device)
+{
+    if (!ctx) return WP_EINVAL;
+    if (n < 0 || n >= ctx->nsnap) return wp_fail(ctx, WP_ERANGE, "snapshot %d of %d", n, ctx->nsnap);
+    if (!dst) return wp_fail(ctx, WP_EINVAL, "null destination");
+    if (hipMemcpyAsync(dst, (char *)ctx->snaps + (size_t)n * ctx->snap_bytes, ctx->snap_bytes,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "snapshot read");
+    return WP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// flagging
+// ---------------------------------------------------------------------------
+int wp_window(wp_ctx *ctx, double t, double t_s, double t_f, int &n_lo, int &n_hi)
+{
+    if (ctx->nsnap <= 0) return wp_fail(ctx, WP_ESTATE, "no adjoint snapshots (run wp_adjoint_run first)");
+    if (!(t_s <= t_f)) return wp_fail(ctx, WP_EINVAL, "t_s must not exceed t_f");
+    const double ds = ctx->snap_ds, slack = 1e-9;
+    const double T = std::min(t + t_f - t_s, t_f);
+    long long hi = (long long)std::ceil((t_f - t) / ds - slack);
+    long long lo = (long long)std::floor((t_f - T) / ds + slack);
+    lo = std::max(lo, 0LL);
+    hi = std::max(hi, lo);
+    if (hi > ctx->nsnap - 1)
+        return wp_fail(ctx, WP_ERANGE, "window at t=%g reaches snapshot %lld of %d", t, hi, ctx->nsnap);
+    n_lo = (int)lo;
+    n_hi = (int)hi;
+    return WP_OK;
+}
+
+extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, double t_f, uint8_t *flags,
+                               int on_device, int64_t *nflagged)
+{
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level out of range");
+    int n_lo, n_hi, rc;
+    if ((rc = wp_window(ctx, t, t_s, t_f, n_lo, n_hi)) != WP_OK) return rc;
+    Level &lv = ctx->L[level];
+    const long long cells = (long long)lv.nx * lv.ny;
+    int ratio = 1;
+    for (int l = 1; l <= level; ++l) ratio *= ctx->L[l].ratio;
+    launch_fill_u8(lv.flags, cells, 0, ctx->stream);
+    if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    const Level &a0 = ctx->adj;
+    const long long hcs = (long long)a0.nx * a0.ny;
+    const long long sstride = hcs * ctx->m;
+    if (ctx->prob.precision == WP_MIXED) {
+        launch_flag_mixed((const double *)lv.q[lv.cur], (const float *)((char *)lv.q[lv.cur] + cells * 8),
+                          (const float *)((char *)lv.q[lv.cur] + cells * 12), cells, lv.nx, lv.ny,
+                          (const float *)ctx->snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
+                          lv.flags, ctx->count, ctx->stream);
+    } else if (ctx->esz == 8) {
+        launch_flag<double, double>((const double *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m,
+                                    (const double *)ctx->snaps, sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol,
+                                    lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count, ctx->stream);
+    } else {
+        launch_flag<float, float>((const float *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m, (const float *)ctx->snaps,
+                                  sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
+                                  lv.flags, ctx->count, ctx->stream);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag launch: %s", hipGetErrorString(e));
+    if (flags && hipMemcpyAsync(flags, lv.flags, (size_t)cells, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "flag copy");
+    if (nflagged) {
+        unsigned long long c = 0;
+        if (hipMemcpyAsync(&c, ctx->count, sizeof c, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "count read");
+        *nflagged = (int64_t)c;
+    } else if (flags && !on_device) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag sync");
+    }
+    lv.flags_valid = true;
+    return WP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// functionals
+// ---------------------------------------------------------------------------
+extern "C" int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int which, int snapshot, double *out)
+{
+    if (!ctx || !out) return ctx ? wp_fail(ctx, WP_EINVAL, "null output") : WP_EINVAL;
+    Level &l0 = ctx->L[0];
+    const long long cells = (long long)l0.nx * l0.ny;
+    const double dA = l0.dx * (ctx->kind2d ? l0.dy : 1.0);
+    const int nb = (int)std::min<long long>(RED_BLOCKS, (cells + 255) / 256);
+    const void *q = l0.q[l0.cur];
+    int rc;
+    if (which == 0) {
+        std::vector<uint8_t> ind;
+        if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
+        if (!ctx->ind_dev) ctx->ind_dev = (uint8_t *)wp_dalloc(ctx, (size_t)cells);
+        if (!ctx->ind_dev) return wp_fail(ctx, WP_ENOMEM, "indicator");
+        if (hipMemcpy(ctx->ind_dev, ind.data(), (size_t)cells, hipMemcpyHostToDevice) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "indicator upload");
+        if (ctx->prob.precision == WP_MIXED) {
+            if (J->component == 0)
+                launch_sum_indicator<double>((const double *)q, cells, cells, 0, ctx->ind_dev, ctx->partials, nb,
+                                             ctx->red_out, ctx->stream);
+            else
+                launch_sum_indicator<float>((const float *)((char *)q + cells * 8), cells, cells, J->component - 1,
+                                            ctx->ind_dev, ctx->partials, nb, ctx->red_out, ctx->stream);
+        } else if (ctx->esz == 8) {
+            launch_sum_indicator<double>((const double *)q, cells, cells, J->component, ctx->ind_dev, ctx->partials,
+                                         nb, ctx->red_out, ctx->stream);
+        } else {
+            launch_sum_indicator<float>((const float *)q, cells, cells, J->component, ctx->ind_dev, ctx->partials, nb,
+                                        ctx->red_out, ctx->stream);
+        }
+    } else if (which == 1) {
+        if (snapshot < 0 || snapshot >= ctx->nsnap)
+            return wp_fail(ctx, WP_ERANGE, "snapshot %d of %d", snapshot, ctx->nsnap);
+        const void *s = (const char *)ctx->snaps + (size_t)snapshot * ctx->snap_bytes;
+        if (ctx->prob.precision == WP_MIXED)
+            launch_sum_dot_mixed((const double *)q, (const float *)((char *)q + cells * 8),
+                                 (const float *)((char *)q + cells * 12), cells, (const float *)s, cells, cells,
+                                 ctx->partials, nb, ctx->red_out, ctx->stream);
+        else if (ctx->esz == 8)
+            launch_sum_dot<double, double>((const double *)q, cells, (const double *)s, cells, cells, ctx->m,
+                                           ctx->partials, nb, ctx->red_out, ctx->stream);
+        else
+            launch_sum_dot<float, float>((const float *)q, cells, (const float *)s, cells, cells, ctx->m, ctx->partials,
+                                         nb, ctx->red_out, ctx->stream);
+    } else {
+        return wp_fail(ctx, WP_EINVAL, "which must be 0 (J) or 1 (inner product)");
+    }
+    double v = 0.0;
+    if (hipMemcpyAsync(&v, ctx->red_out, sizeof v, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "reduction read");
+    *out = v * dA;
+    return wp_check_status(ctx);
+}

@@ -1,0 +1,100 @@
+// Internal declarations shared by the host code and the HIP kernels of the
+// wave-propagation library.  Not part of the public C ABI (include/wp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wp.h"
+
+namespace wp {
+
+constexpr int MAXMAT = 16;     // distinct (rho, K) pairs per acoustics instance
+constexpr int WAVE = 64;       // CDNA wavefront
+constexpr int STRIP = WAVE - 4; // output columns per wave in the 2D kernels
+
+// One unit of work of a patch-update launch: output cells
+// [i0, i0 + ni) x [j0, j0 + nj) of instance `inst`.
+struct Tile {
+    int inst, i0, j0, ni, nj;
+};
+
+// Per-instance description of a 2D (or 1D) acoustics level canvas.  The
+// canvas covers the whole domain at the level's resolution with no ghost
+// border: ghost cells are resolved by the loaders from the boundary rules
+// (or read from the canvas itself when they lie inside the domain).
+template <typename T>
+struct AcouInst {
+    T *q[2];                  // double-buffered state, component stride cs
+    const uint8_t *mat;       // material index per cell
+    long long cs;             // component stride (elements)
+    int nx, ny;
+    int bc[4];
+    T nux, nuy;               // dt/dx, dt/dy
+    const T *mtab;            // [nmat][4]: Z, c, K = Z c, 1/rho = c / Z
+    const T *ptab;            // [nmat][nmat][3]: 1/(Z_a+Z_b), kappa1, kappa2
+    int nmat;
+    int order, limiter, transverse;
+};
+
+// Shallow-water instance (single level).  ETA is the storage type of eta
+// (double in the FP64 and mixed paths), T of hu, hv and the bulk arithmetic.
+template <typename ETA, typename T>
+struct SweInst {
+    ETA *eta[2];
+    T *hu[2];
+    T *hv[2];
+    const double *B;          // bathymetry (FP64)
+    const T *cbar;            // sqrt(g hbar), hbar = -B, for the adjoint
+    long long cs;
+    int nx, ny;
+    int bc[4];
+    double nux, nuy;
+    double g;
+    int order, limiter, transverse;
+};
+
+// status word bits latched by kernels
+constexpr int ST_NONFINITE = 1;
+constexpr int ST_CFL = 2;
+
+template <typename T>
+void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
+                   int nmat_max, int *status, hipStream_t s);
+template <typename T>
+void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, int parity, int adjoint,
+                   int *status, hipStream_t s);
+
+template <typename ETA, typename T>
+void launch_swe2d(const SweInst<ETA, T> *inst, const SweInst<ETA, T> &h, const Tile *tiles, int ntiles,
+                  int parity, int *status, unsigned *cflbits, hipStream_t s);
+template <typename ETA, typename T>
+void launch_lswe_adj2d(const SweInst<ETA, T> *inst, const SweInst<ETA, T> &h, const Tile *tiles, int ntiles,
+                       int parity, int *status, hipStream_t s);
+
+// Flag: m(x) = max_n |qhat_n(x) . q(x)| over snapshots n_lo..n_hi, bilinear
+// from the adjoint grid (refinement `ratio` relative to it).
+template <typename TQ, typename TH>
+void launch_flag(const TQ *q, long long cs, int nx, int ny, int m, const TH *snaps, long long snap_stride,
+                 long long hcs, int NX, int NY, int ratio, int n_lo, int n_hi, double tol, const Tile *tiles,
+                 int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
+void launch_flag_mixed(const double *eta, const float *hu, const float *hv, long long cs, int nx, int ny,
+                       const float *snaps, long long snap_stride, long long hcs, int n_lo, int n_hi, double tol,
+                       const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
+
+// Compensated FP64 reductions: out[0] = sum_k sum_cells w(cell) a_k b_k where
+// a is m component arrays (type TA) and b either an indicator (uint8, times
+// unit vector `comp`) or m arrays of type TB.
+template <typename TA>
+void launch_sum_indicator(const TA *a, long long cs, long long n, int comp, const uint8_t *ind, double *partials,
+                          int nblocks, double *out, hipStream_t s);
+template <typename TA, typename TB>
+void launch_sum_dot(const TA *a, long long acs, const TB *b, long long bcs, long long n, int m, double *partials,
+                    int nblocks, double *out, hipStream_t s);
+void launch_sum_dot_mixed(const double *eta, const float *hu, const float *hv, long long cs, const float *b,
+                          long long bcs, long long n, double *partials, int nblocks, double *out, hipStream_t s);
+
+void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s);
+
+}  // namespace wp

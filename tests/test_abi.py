@@ -1,0 +1,42 @@
+"""The C ABI library loads and exports every symbol include/wp.h declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1511_03645_amd as wp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "wp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for name in ("wp_create", "wp_step_patches", "wp_adjoint_run", "wp_flag_adjoint", "wp_regrid"):
+        assert name in syms
+
+
+@pytest.mark.skipif(not os.path.exists(wp.LIB_PATH), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(wp.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert sorted(wp._SIGS) == declared_symbols()
+
+
+@pytest.mark.skipif(not os.path.exists(wp.LIB_PATH), reason="library not built")
+def test_status_strings_without_device():
+    L = wp.lib()
+    assert L.wp_status_string(wp.WP_ECFL).decode().startswith("Courant")
+    assert L.wp_last_error(None).decode() == "null handle"
+    assert L.wp_step_patches(None, 0, 0.1) == wp.WP_EINVAL
