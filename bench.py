@@ -1,0 +1,219 @@
+"""Benchmark of the adjoint-guided wave-propagation hot path on one MI355X.
+
+One "step" is one whole job of the 2D acoustics workload (1024 x 1024 cells,
+two materials split at x = 0, seeded Gaussian pulse and disc target,
+first-arrival final time, CFL 0.9):
+  1. the time-reversed adjoint run from phi with a snapshot every 10 steps,
+  2. the forward run from the seeded pulse, flagged against the snapshot
+     window every 10 steps,
+  3. the target functional J.
+The metric is forward plus adjoint cell updates per second over the whole
+job, inputs resident in device memory.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X published peaks used for the roofline fields
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per 2D acoustics cell update: state read once and written
+# once (3 components) plus the one-byte material index
+ALG_BYTES = {64: 3 * 8 * 2 + 1, 32: 3 * 4 * 2 + 1}
+COUNTERS = os.path.join(ROOT, "profiles", "acou2d_fp64_1024_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1511_03645_amd", "csrc", "acoustics.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024, help="cells per side (workload default 1024)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter calibration)")
+    return ap.parse_args()
+
+
+def source_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_counters(cells):
+    """HBM bytes per forward-kernel launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
+    None if the kernel source changed since the counters were taken."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    if c.get("source_sha") != source_sha() or c.get("cells") != cells:
+        return None
+    fetch = c["fetch_kib"] * 1024.0 / c["copy_fetch_factor"]
+    write = c["write_kib"] * 1024.0 / c["copy_write_factor"]
+    return fetch + write
+
+
+def calibrate_copy():
+    import torch
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
+class Job:
+    """The whole hot path on one workload instance."""
+
+    def __init__(self, cfg, precision):
+        import torch
+        import paper_1511_03645_amd as wp
+        self.wp = wp
+        self.cfg = cfg
+        self.w = wp.from_config(cfg, precision=precision)
+        self.precision = precision
+        # forward initial state resident on the device in the library's layout
+        dt_np = np.float64 if precision == wp.FP64 else np.float32
+        packed = np.concatenate([cfg["q0"][k].astype(dt_np).ravel().view(np.uint8) for k in range(3)])
+        self.q0_dev = torch.from_numpy(packed).cuda()
+        self.cells = cfg["nx"] * cfg["ny"]
+        self.kernel_ms = []
+        # tile height chosen by the autotuner (outside any timed region)
+        from paper_1511_03645_amd.autotune import tune
+        self.w.set_state(cfg["q0"])
+        self.rows, self.tune_us = tune(self.w, cfg["dt"], use_cache=False)
+
+    def run(self, time_kernels=False):
+        import torch
+        cfg, w = self.cfg, self.w
+        N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+        w.adjoint_run(cfg["functional"], dt, N, every)
+        w.set_state(self.q0_dev)
+        t = 0.0
+        ev = []
+        for k in range(N // every):
+            w.flag_adjoint(0, cfg["tol"], t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+            # the `every` steps between flag evaluations replay one captured graph
+            if time_kernels:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                w.run_graph(every, dt, 1)
+                e1.record()
+                ev.append((e0, e1))
+            else:
+                w.run_graph(every, dt, 1)
+            t += every * dt
+        J = w.functional_value(cfg["functional"], which=0)
+        if time_kernels:
+            torch.cuda.synchronize()
+            # per-launch duration: each bracket holds `every` back-to-back
+            # step kernels (graph launch overhead included, so this is an
+            # upper bound on the kernel's own duration)
+            self.kernel_ms += [a.elapsed_time(b) / every for a, b in ev]
+        return J
+
+    def updates(self):
+        return 2 * self.cfg["nsteps"] * self.cells
+
+
+def timed(job, steps, warmup, time_kernels):
+    import torch
+    for _ in range(warmup):
+        job.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = None
+    for _ in range(steps):
+        J = job.run(time_kernels=time_kernels)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, J
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on the host cores: a bounded sample of the same
+    workload (full grid, a fixed number of forward and adjoint steps)."""
+    import oracle
+    cores = os.cpu_count() or 1
+    oracle.set_threads(cores)
+    nsamp = 120
+    oracle.run(cfg, "acoustics_fwd", cfg["q0"], 1)     # warm the workspace
+    t0 = time.perf_counter()
+    oracle.run(cfg, "acoustics_fwd", cfg["q0"], nsamp)
+    oracle.adjoint_run(cfg, nsteps=nsamp, snap_every=nsamp)
+    el = time.perf_counter() - t0
+    ups = 2 * nsamp * cfg["nx"] * cfg["ny"]
+    return {"value": ups / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cfg['nx']}x{cfg['ny']} grid, {nsamp} forward + {nsamp} adjoint steps "
+                      f"({el:.1f} s on {cores} threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
+              f"described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import acoustics2d
+    torch.cuda.set_device(0)
+    cfg = acoustics2d(n=args.n, seed=1)
+    print(f"[bench] workload {cfg['nx']}x{cfg['ny']}, {cfg['nsteps']} forward + {cfg['nsteps']} adjoint steps "
+          f"per job, flags every {cfg['flag_every']}", file=sys.stderr, flush=True)
+
+    job = Job(cfg, wp.FP64)
+    sec, J64 = timed(job, args.steps, args.warmup, time_kernels=True)
+    value = job.updates() / sec
+    kern_ms = float(np.mean(job.kernel_ms))
+    alg = ALG_BYTES[64] * job.cells
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    print(f"[bench] fp64: {sec * 1e3:.2f} ms/job, {value / 1e9:.2f} Gcell-updates/s, forward kernel "
+          f"{kern_ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+    out = {
+        "metric": "cell-updates/sec (fwd+adjoint) + % HBM roofline; FP32-batched vs FP64 at stated J error",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"acoustics2d two-material {cfg['nx']}x{cfg['ny']}, adjoint run + forward run "
+                               f"flagged every {cfg['flag_every']} steps + J",
+                   "cells": job.cells, "steps_per_solve": cfg["nsteps"], "snapshots": cfg["nsteps"] // 10 + 1},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(job.cells),
+                     "kernel": "acou2d_kernel<double, forward>", "kernel_us": kern_ms * 1e3,
+                     "alg_bytes_per_launch": alg, "tile_rows": job.rows},
+        "J": J64,
+    }
+    if not args.no_fp32:
+        job32 = Job(cfg, wp.FP32)
+        sec32, J32 = timed(job32, args.steps, args.warmup, time_kernels=True)
+        k32 = float(np.mean(job32.kernel_ms))
+        out["fp32"] = {"value": job32.updates() / sec32, "ms_per_step": sec32 * 1e3, "tile_rows": job32.rows,
+                       "speedup_vs_fp64": sec / sec32, "J_rel_err_vs_fp64": abs(J32 - J64) / abs(J64),
+                       "kernel_us": k32 * 1e3,
+                       "achieved_GBs": ALG_BYTES[32] * job.cells / (k32 * 1e-3) / 1e9}
+        print(f"[bench] fp32: {sec32 * 1e3:.2f} ms/job, J rel err {out['fp32']['J_rel_err_vs_fp64']:.2e}",
+              file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -318,13 +318,16 @@ class WavePatch:
         self._check(lib().wp_get_snapshot(self.h, n, p, dev))
         return buf.view(np.float64 if es == 8 else np.float32).reshape(self.m, ny, nx).astype(np.float64)
 
-    def flag_adjoint(self, level, tol, t, t_s, t_f, want_flags=True):
+    def flag_adjoint(self, level, tol, t, t_s, t_f, want_flags=True, want_count=True):
+        """wp_flag_adjoint; with want_flags and want_count False nothing is
+        copied back and the call does not synchronise."""
         nx, ny, _ = self.level_info(level)
         flags = np.zeros((ny, nx), dtype=np.uint8) if want_flags else None
         n = ctypes.c_int64()
         p = ctypes.c_void_p(flags.ctypes.data) if want_flags else ctypes.c_void_p()
-        self._check(lib().wp_flag_adjoint(self.h, level, tol, t, t_s, t_f, p, 0, ctypes.byref(n)))
-        return flags, n.value
+        self._check(lib().wp_flag_adjoint(self.h, level, tol, t, t_s, t_f, p, 0,
+                                          ctypes.byref(n) if want_count else None))
+        return flags, (n.value if want_count else None)
 
     def regrid(self, level, patches=None, buffer=0):
         if patches is None:

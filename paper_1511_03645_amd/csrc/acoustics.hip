@@ -47,6 +47,16 @@ __device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp
 __device__ __forceinline__ int from_left(int v) { return dpp_from_left(v); }
 __device__ __forceinline__ int from_right(int v) { return dpp_from_right(v); }
 
+__device__ __forceinline__ double uniform(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Ghost index resolution for one direction; i is first clamped to the
 // two-cell ghost band.  flip: the normal velocity changes sign (wall).
 __device__ __forceinline__ int resolve(int i, int n, int bclo, int bchi, bool &flip)
@@ -130,104 +140,158 @@ __device__ __forceinline__ void solve(T pl, T nl, T pr, T nr, const MCon<T> &L, 
     }
 }
 
-template <typename T, bool ADJ>
-__global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
-                                                      const Tile *__restrict__ tiles, int parity,
-                                                      int *__restrict__ status)
+// Raw buffer access with 32-bit byte offsets (out-of-range reads return 0,
+// out-of-range writes are dropped).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int BUF_FLAGS = 0x00020000;   // gfx9-family buffer resource word 3
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, unsigned bytes)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tl = tiles[blockIdx.x];
-    const AcouInst<T> I = insts[tl.inst];
-    const int lane = threadIdx.x;
-    MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);
-    T *pt = reinterpret_cast<T *>(smem + sizeof(MCon<T>) * MAXMAT);
-    build_tables(I, mc, pt, lane);
-    __syncthreads();
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, BUF_FLAGS);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, double, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned off, float, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, 0);
+}
 
-    const T *__restrict__ qp = I.q[parity];
-    T *__restrict__ qo = I.q[parity ^ 1];
-    const long long cs = I.cs;
-    const int nmat = I.nmat;
-    const T nux = I.nux, nuy = I.nuy;
-    const bool second = I.order >= 2;
-    const bool trans = I.transverse != 0;
-    const int lim = I.limiter;
+template <typename T>
+struct Row {
+    T p, u, v;
+    int m;
+};
 
-    const int col = tl.i0 - 2 + lane;
-    bool fx;
-    const int cx = resolve(col, I.nx, I.bc[0], I.bc[1], fx);
-    const T sx = fx ? T(-1) : T(1);
-    const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
+template <typename T, bool UNI>
+struct Media;
 
-    auto load = [&](int j, T &p, T &u, T &v, int &m) {
-        bool fy;
-        const int jy = resolve(j, I.ny, I.bc[2], I.bc[3], fy);
-        const long long idx = (long long)jy * I.nx + cx;
-        p = qp[idx];
-        u = sx * qp[idx + cs];
-        v = (fy ? T(-1) : T(1)) * qp[idx + 2 * cs];
-        m = I.mat[idx];
-    };
-    auto pair = [&](int a, int b) -> const T * { return pt + (a * nmat + b) * 3; };
-
-    const int j0 = tl.j0;
-    // rows j0-2 .. j0: prologue for the first (discarded) iteration j = j0-1
-    T pA, uA, vA, p0, u0, v0, p1, u1, v1;
-    int mA, m0, m1;
-    load(j0 - 2, pA, uA, vA, mA);
-    load(j0 - 1, p0, u0, v0, m0);
-    load(j0, p1, u1, v1, m1);
-
-    // y-edge (j0-3/2): strengths (only a2 is used later)
-    T b1m, b2m, b1p, b2p;
+template <typename T>
+struct Media<T, false> {
+    const MCon<T> *mc;
+    const T *pt;
+    int nmat;
+    __device__ __forceinline__ const MCon<T> &operator()(int m) const { return mc[m]; }
+    __device__ __forceinline__ void pair(int a, int b, T &inv, T &k1, T &k2) const
     {
-        const T *pp = pair(mA, m0);
-        solve<T, ADJ>(pA, vA, p0, v0, mc[mA], mc[m0], pp[0], b1m, b2m);
-        const T *pq = pair(m0, m1);
-        solve<T, ADJ>(p0, v0, p1, v1, mc[m0], mc[m1], pq[0], b1p, b2p);
+        const T *p = pt + (a * nmat + b) * 3;
+        inv = p[0];
+        k1 = p[1];
+        k2 = p[2];
     }
-    // x-edge (col-1/2) on row j0-1
-    T a1x0, a2x0;
-    int mL0 = from_left(m0);
+    static constexpr bool uniform = false;
+};
+
+template <typename T>
+struct Media<T, true> {
+    MCon<T> m;
+    T inv;
+    __device__ __forceinline__ const MCon<T> &operator()(int) const { return m; }
+    __device__ __forceinline__ void pair(int, int, T &i, T &k1, T &k2) const
     {
-        const T pl = from_left(p0), ul = from_left(u0);
-        const T *pp = pair(mL0, m0);
-        solve<T, ADJ>(pl, ul, p0, u0, mc[mL0], mc[m0], pp[0], a1x0, a2x0);
+        i = inv;
+        k1 = T(1);
+        k2 = T(1);
+    }
+    static constexpr bool uniform = true;
+};
+
+struct Opts {
+    bool second, trans;
+    int lim;
+};
+
+template <typename T, bool ADJ, bool UNI, bool FULL, int RT>
+__device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt, const Tile &tl, int lane, int nx,
+                                      int ny, int bc2, int bc3, int cx, T sx, unsigned csb, T nux, T nuy,
+                                      __amdgpu_buffer_rsrc_t qr, __amdgpu_buffer_rsrc_t qw,
+                                      __amdgpu_buffer_rsrc_t mr, int &bad)
+{
+    // FULL: second order, MC limiter and transverse terms fixed at compile time
+    const bool second = FULL ? true : op_rt.second;
+    const bool trans = FULL ? true : op_rt.trans;
+    const int lim = FULL ? 1 : op_rt.lim;
+    const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
+    const unsigned out_off0 = (unsigned)(tl.i0 - 2 + lane) * (unsigned)sizeof(T);
+    auto ld = [=](Row<T> &r, int j) {
+        bool fy;
+        const int jy = resolve(j, ny, bc2, bc3, fy);
+        const unsigned idx = (unsigned)(jy * nx + cx);
+        const unsigned off = idx * (unsigned)sizeof(T);
+        r.p = bload(qr, off, T(0), 0u);
+        r.u = sx * bload(qr, off, T(0), csb);
+        const T v = bload(qr, off, T(0), 2u * csb);
+        r.v = fy ? -v : v;
+        r.m = UNI ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
+    };
+    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    Row<T> RA, R0, R1, X0, X1, X2;
+    ld(RA, j0 - 2);
+    ld(R0, j0 - 1);
+    ld(R1, j0);
+    ld(X0, j0 + 1);
+    ld(X1, j0 + 2);
+    T inv, k1, k2;
+    T b1p, b2p, b2m;
+    {
+        T b1a;
+        md.pair(RA.m, R0.m, inv, k1, k2);
+        solve<T, ADJ>(RA.p, RA.v, R0.p, R0.v, md(RA.m), md(R0.m), inv, b1a, b2m);
+        md.pair(R0.m, R1.m, inv, k1, k2);
+        solve<T, ADJ>(R0.p, R0.v, R1.p, R1.v, md(R0.m), md(R1.m), inv, b1p, b2p);
+    }
+    T a1x0, a2x0;
+    int mL0 = UNI ? 0 : from_left(R0.m);
+    {
+        const T pl = from_left(R0.p), ul = from_left(R0.u);
+        md.pair(mL0, R0.m, inv, k1, k2);
+        solve<T, ADJ>(pl, ul, R0.p, R0.u, md(mL0), md(R0.m), inv, a1x0, a2x0);
     }
     T Gp_prev = T(0), Gv_prev = T(0);
-    int bad = 0;
 
-    for (int j = j0 - 1; j < j0 + tl.nj; ++j) {
-        // 1. new row j+2
-        T p2, u2, v2;
-        int m2;
-        load(j + 2, p2, u2, v2, m2);
-        // 2. y-edge (j+3/2) between rows j+1 and j+2
-        T b1n, b2n;
+    // RT > 0: the tile height is a compile-time constant and the march is
+    // fully unrolled.  A loop back-edge would make the compiler drain every
+    // outstanding memory operation (prefetched rows and stores) once per row;
+    // unrolled, prefetches stay in flight and the register rotations below
+    // become renaming.  RT = 0: runtime height.
+    constexpr int NIT = RT > 0 ? RT + 1 : 1 << 30;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int j = j0 - 1 + it;
+        if (RT == 0 && j >= j1) break;
+        ld(X2, j + 4);   // prefetch; row j+2 (X0) was issued two iterations ago
+        const Row<T> R2 = X0;
+        T b1n, b2n;      // y-edge (col, j+3/2)
+        md.pair(R1.m, R2.m, inv, k1, k2);
+        solve<T, ADJ>(R1.p, R1.v, R2.p, R2.v, md(R1.m), md(R2.m), inv, b1n, b2n);
+        T a1n, a2n;      // x-edge (col-1/2, j+1)
+        const int mL1 = UNI ? 0 : from_left(R1.m);
         {
-            const T *pp = pair(m1, m2);
-            solve<T, ADJ>(p1, v1, p2, v2, mc[m1], mc[m2], pp[0], b1n, b2n);
+            const T pl = from_left(R1.p), ul = from_left(R1.u);
+            md.pair(mL1, R1.m, inv, k1, k2);
+            solve<T, ADJ>(pl, ul, R1.p, R1.u, md(mL1), md(R1.m), inv, a1n, a2n);
         }
-        // 3. x-edge (col-1/2) on row j+1
-        T a1n, a2n;
-        const int mL1 = from_left(m1);
-        {
-            const T pl = from_left(p1), ul = from_left(u1);
-            const T *pp = pair(mL1, m1);
-            solve<T, ADJ>(pl, ul, p1, u1, mc[mL1], mc[m1], pp[0], a1n, a2n);
-        }
-        // 4a. flux correction F at x-edge (col-1/2, j): L = (col-1, j), R = (col, j)
-        const T a1r = from_right(a1x0);   // a1 at edge col+1/2 (upwind of wave 1)
-        const T a2l = from_left(a2x0);    // a2 at edge col-3/2 (upwind of wave 2)
-        const MCon<T> &L = mc[mL0];
-        const MCon<T> &C = mc[m0];
+        // F at x-edge (col-1/2, j): L = (col-1, j), C = (col, j)
+        const T a1r = from_right(a1x0);
+        const T a2l = from_left(a2x0);
+        const MCon<T> &L = md(mL0);
+        const MCon<T> &C = md(R0.m);
         T Fp = T(0), Fu = T(0);
         {
-            const T *pp = pair(mL0, m0);
-            const T invx = pp[0];
+            T invx;
+            md.pair(mL0, R0.m, invx, k1, k2);
             if (second) {
-                const T t1 = limited(a1x0, pp[1] * a1r, lim);
-                const T t2 = limited(a2x0, pp[2] * a2l, lim);
+                const T t1 = limited(a1x0, k1 * a1r, lim);
+                const T t2 = limited(a2x0, k2 * a2l, lim);
                 if (!ADJ) {
                     Fp = C.hZx * t2 - L.hZx * t1;
                     Fu = L.hx * t1 + C.hx * t2;
@@ -237,8 +301,8 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
                 }
             }
             if (trans) {
-                // transverse: y-edge fluctuations of cells (col, j) and (col-1, j),
-                // split at this x-edge (up-going from below plus down-going from above)
+                // y-edge fluctuations of cells (col, j) and (col-1, j) split at
+                // this x-edge: up-going from below plus down-going from above
                 const T S = b2m + b1p;
                 const T SL = from_left(S);
                 if (!ADJ) {
@@ -252,15 +316,15 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
                 }
             }
         }
-        // 4b. flux correction G at y-edge (col, j+1/2): B = (col, j), A = (col, j+1)
-        const MCon<T> &A = mc[m1];
+        // G at y-edge (col, j+1/2): C = (col, j), A = (col, j+1)
+        const MCon<T> &A = md(R1.m);
         T Gp = T(0), Gv = T(0);
         {
-            const T *pp = pair(m0, m1);
-            const T invy = pp[0];
+            T invy;
+            md.pair(R0.m, R1.m, invy, k1, k2);
             if (second) {
-                const T s1 = limited(b1p, pp[1] * b1n, lim);
-                const T s2 = limited(b2p, pp[2] * b2m, lim);
+                const T s1 = limited(b1p, k1 * b1n, lim);
+                const T s2 = limited(b2p, k2 * b2m, lim);
                 if (!ADJ) {
                     Gp = A.hZy * s2 - C.hZy * s1;
                     Gv = C.hy * s1 + A.hy * s2;
@@ -271,46 +335,97 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
             }
             if (trans) {
                 const T a1rn = from_right(a1n);
-                const T R0 = a2x0 + a1r, R1 = a2n + a1rn;
+                const T R0s = a2x0 + a1r, R1s = a2n + a1rn;
                 if (!ADJ) {
-                    const T UB = C.Khx * invy * R0, UA = A.Khx * invy * R1;
+                    const T UB = C.Khx * invy * R0s, UA = A.Khx * invy * R1s;
                     Gp -= A.K * UB - C.K * UA;
                     Gv -= A.c * UB + C.c * UA;
                 } else {
-                    const T UB = C.Zhx * invy * R0, UA = A.Zhx * invy * R1;
+                    const T UB = C.Zhx * invy * R0s, UA = A.Zhx * invy * R1s;
                     Gp += C.c * UA - A.c * UB;
                     Gv += A.K * UB + C.K * UA;
                 }
             }
         }
-        // 4c. update cell (col, j)
+        // update cell (col, j)
         const T Fpr = from_right(Fp), Fur = from_right(Fu);
         T pn, un, vn;
         if (!ADJ) {
-            pn = p0 - nux * (C.K * (a2x0 + a1r)) - nuy * (C.K * (b2m + b1p)) - nux * (Fpr - Fp) - nuy * (Gp - Gp_prev);
-            un = u0 - nux * (C.c * (a2x0 - a1r)) - nux * (Fur - Fu);
-            vn = v0 - nuy * (C.c * (b2m - b1p)) - nuy * (Gv - Gv_prev);
+            pn = R0.p - nux * (C.K * (a2x0 + a1r)) - nuy * (C.K * (b2m + b1p)) - nux * (Fpr - Fp) - nuy * (Gp - Gp_prev);
+            un = R0.u - nux * (C.c * (a2x0 - a1r)) - nux * (Fur - Fu);
+            vn = R0.v - nuy * (C.c * (b2m - b1p)) - nuy * (Gv - Gv_prev);
         } else {
-            pn = p0 - nux * (a2x0 + a1r) - nuy * (b2m + b1p) - nux * (Fpr - Fp) - nuy * (Gp - Gp_prev);
-            un = u0 - nux * (C.Z * (a1r - a2x0)) - nux * (Fur - Fu);
-            vn = v0 - nuy * (C.Z * (b1p - b2m)) - nuy * (Gv - Gv_prev);
+            pn = R0.p - nux * (a2x0 + a1r) - nuy * (b2m + b1p) - nux * (Fpr - Fp) - nuy * (Gp - Gp_prev);
+            un = R0.u - nux * (C.Z * (a1r - a2x0)) - nux * (Fur - Fu);
+            vn = R0.v - nuy * (C.Z * (b1p - b2m)) - nuy * (Gv - Gv_prev);
         }
-        if (j >= j0 && out_lane) {
-            const long long idx = (long long)j * I.nx + col;
-            qo[idx] = pn;
-            qo[idx + cs] = un;
-            qo[idx + 2 * cs] = vn;
+        if (j >= j0 && j < j1 && out_lane) {
+            const unsigned off = (unsigned)j * (unsigned)nx * (unsigned)sizeof(T) + out_off0;
+            bstore(qw, off, 0u, pn);
+            bstore(qw, off, csb, un);
+            bstore(qw, off, 2u * csb, vn);
             bad |= !(isfinite(pn) && isfinite(un) && isfinite(vn));
         }
-        // 5. rotate
-        p0 = p1; u0 = u1; v0 = v1; m0 = m1;
-        p1 = p2; u1 = u2; v1 = v2; m1 = m2;
+        R0 = R1;
+        R1 = R2;
+        X0 = X1;
+        X1 = X2;
         mL0 = mL1;
-        a1x0 = a1n; a2x0 = a2n;
+        a1x0 = a1n;
+        a2x0 = a2n;
         b2m = b2p;
-        b1p = b1n; b2p = b2n;
-        Gp_prev = Gp; Gv_prev = Gv;
-        (void)b1m;
+        b1p = b1n;
+        b2p = b2n;
+        Gp_prev = Gp;
+        Gv_prev = Gv;
+    }
+}
+
+// KIND 0: each tile takes the single-material or the mixed path as flagged;
+// KIND 1: every tile is single-material (the lean march alone sets the
+// register count and so the occupancy); KIND 2: every tile is mixed.
+template <typename T, bool ADJ, bool FULL, int RT, int KIND>
+__global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
+                                                      const Tile *__restrict__ tiles, int parity,
+                                                      int *__restrict__ status)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile tl = tiles[blockIdx.x];
+    const AcouInst<T> *__restrict__ Ip = insts + tl.inst;
+    const int lane = threadIdx.x;
+    MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);
+    T *pt = reinterpret_cast<T *>(smem + sizeof(MCon<T>) * MAXMAT);
+    build_tables(*Ip, mc, pt, lane);
+    __syncthreads();
+
+    const int nx = Ip->nx, ny = Ip->ny;
+    const int bc0 = Ip->bc[0], bc1 = Ip->bc[1], bc2 = Ip->bc[2], bc3 = Ip->bc[3];
+    const unsigned cells = (unsigned)nx * (unsigned)ny;
+    const unsigned csb = cells * (unsigned)sizeof(T);
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(Ip->q[parity], 3u * csb);
+    const __amdgpu_buffer_rsrc_t qw = make_rsrc(Ip->q[parity ^ 1], 3u * csb);
+    const __amdgpu_buffer_rsrc_t mr = make_rsrc(Ip->mat, cells);
+    const Opts op{Ip->order >= 2, Ip->transverse != 0, Ip->limiter};
+    const T nux = Ip->nux, nuy = Ip->nuy;
+    const int col = tl.i0 - 2 + lane;
+    bool fx;
+    const int cx = resolve(col, nx, bc0, bc1, fx);
+    const T sx = fx ? T(-1) : T(1);
+    int bad = 0;
+    if (KIND == 1 || (KIND == 0 && tl.mat >= 0)) {
+        // one material: its constants are wave-uniform, kept in SGPRs
+        Media<T, true> md;
+        const MCon<T> &src = mc[tl.mat];
+        md.m.Z = uniform(src.Z); md.m.c = uniform(src.c); md.m.K = uniform(src.K); md.m.ir = uniform(src.ir);
+        md.m.hx = uniform(src.hx); md.m.hZx = uniform(src.hZx); md.m.hy = uniform(src.hy); md.m.hZy = uniform(src.hZy);
+        md.m.gx = uniform(src.gx); md.m.gZx = uniform(src.gZx); md.m.gy = uniform(src.gy); md.m.gZy = uniform(src.gZy);
+        md.m.Khx = uniform(src.Khx); md.m.Khy = uniform(src.Khy); md.m.Zhx = uniform(src.Zhx); md.m.Zhy = uniform(src.Zhy);
+        const T *pp = pt + (tl.mat * Ip->nmat + tl.mat) * 3;
+        md.inv = uniform(pp[0]);
+        march<T, ADJ, true, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, bad);
+    } else if (KIND != 1) {
+        Media<T, false> md{mc, pt, Ip->nmat};
+        march<T, ADJ, false, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, bad);
     }
     if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
 }
@@ -321,7 +436,7 @@ __global__ __launch_bounds__(256) void acou1d_kernel(const AcouInst<T> *__restri
                                                      int *__restrict__ status)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const AcouInst<T> I = insts[0];
+    const AcouInst<T> &I = *insts;
     MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);
     T *pt = reinterpret_cast<T *>(smem + sizeof(MCon<T>) * MAXMAT);
     if (threadIdx.x < WAVE) build_tables(I, mc, pt, threadIdx.x);
@@ -332,6 +447,7 @@ __global__ __launch_bounds__(256) void acou1d_kernel(const AcouInst<T> *__restri
     T *qo = I.q[parity ^ 1];
     T p[5], u[5];
     int m[5];
+#pragma unroll
     for (int k = 0; k < 5; ++k) {
         bool f;
         const int ii = resolve(i - 2 + k, I.nx, I.bc[0], I.bc[1], f);
@@ -341,12 +457,14 @@ __global__ __launch_bounds__(256) void acou1d_kernel(const AcouInst<T> *__restri
     }
     // edges e = 0..3 between cells (e, e+1) of the stencil: i-3/2 .. i+3/2
     T a1[4], a2[4];
+#pragma unroll
     for (int e = 0; e < 4; ++e) {
         const T *pp = pt + (m[e] * I.nmat + m[e + 1]) * 3;
         solve<T, ADJ>(p[e], u[e], p[e + 1], u[e + 1], mc[m[e]], mc[m[e + 1]], pp[0], a1[e], a2[e]);
     }
     T Fp[2] = {T(0), T(0)}, Fu[2] = {T(0), T(0)};
     if (I.order >= 2) {
+#pragma unroll
         for (int h = 0; h < 2; ++h) {   // h = 0: edge i-1/2 (e = 1), h = 1: edge i+1/2 (e = 2)
             const int e = 1 + h;
             const MCon<T> &L = mc[m[e]], &R = mc[m[e + 1]];
@@ -387,14 +505,33 @@ static size_t acou_smem(int nmat)
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint, int nmat_max,
-                   int *status, hipStream_t s)
+                   bool full, int rows, int kind, int *status, hipStream_t s)
 {
     if (ntiles <= 0) return;
     const size_t sm = acou_smem<T>(nmat_max);
-    if (adjoint)
-        hipLaunchKernelGGL((acou2d_kernel<T, true>), dim3(ntiles), dim3(WAVE), sm, s, insts, tiles, parity, status);
-    else
-        hipLaunchKernelGGL((acou2d_kernel<T, false>), dim3(ntiles), dim3(WAVE), sm, s, insts, tiles, parity, status);
+    const dim3 g(ntiles), b(WAVE);
+#define WP_LAUNCH(ADJ, FULL, RT, KIND) \
+    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, status)
+#define WP_BY_RT(ADJ, KIND)                              \
+    switch (full ? rows : 0) {                           \
+    case 4: WP_LAUNCH(ADJ, true, 4, KIND); break;        \
+    case 6: WP_LAUNCH(ADJ, true, 6, KIND); break;        \
+    case 8: WP_LAUNCH(ADJ, true, 8, KIND); break;        \
+    case 12: WP_LAUNCH(ADJ, true, 12, KIND); break;      \
+    case 16: WP_LAUNCH(ADJ, true, 16, KIND); break;      \
+    default:                                             \
+        if (full) WP_LAUNCH(ADJ, true, 0, 0);            \
+        else WP_LAUNCH(ADJ, false, 0, 0);                \
+    }
+    if (kind == 1) {
+        if (adjoint) { WP_BY_RT(true, 1) } else { WP_BY_RT(false, 1) }
+    } else if (kind == 2) {
+        if (adjoint) { WP_BY_RT(true, 2) } else { WP_BY_RT(false, 2) }
+    } else {
+        if (adjoint) { WP_BY_RT(true, 0) } else { WP_BY_RT(false, 0) }
+    }
+#undef WP_BY_RT
+#undef WP_LAUNCH
 }
 
 template <typename T>
@@ -409,8 +546,10 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &h, int parity
         hipLaunchKernelGGL((acou1d_kernel<T, false>), dim3(nb), dim3(256), sm, s, inst_dev, parity, status);
 }
 
-template void launch_acou2d<double>(const AcouInst<double> *, const Tile *, int, int, int, int, int *, hipStream_t);
-template void launch_acou2d<float>(const AcouInst<float> *, const Tile *, int, int, int, int, int *, hipStream_t);
+template void launch_acou2d<double>(const AcouInst<double> *, const Tile *, int, int, int, int, bool, int, int,
+                                    int *, hipStream_t);
+template void launch_acou2d<float>(const AcouInst<float> *, const Tile *, int, int, int, int, bool, int, int,
+                                   int *, hipStream_t);
 template void launch_acou1d<double>(const AcouInst<double> *, const AcouInst<double> &, int, int, int *,
                                     hipStream_t);
 template void launch_acou1d<float>(const AcouInst<float> *, const AcouInst<float> &, int, int, int *, hipStream_t);

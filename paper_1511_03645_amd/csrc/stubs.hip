@@ -3,7 +3,8 @@
 
 int wp_swe_init(wp_ctx *ctx, const wp_coefficients *) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
 int wp_swe_adj_init(wp_ctx *ctx) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
-int wp_swe_step(wp_ctx *ctx, Level &, double, int) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
+int wp_swe_step(wp_ctx *ctx, Level &, double, int, hipStream_t) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
+int wp_swe_prepare(wp_ctx *ctx, Level &, double) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
 int wp_fill_coarse_ghosts(wp_ctx *ctx, int, double) { return wp_fail(ctx, WP_EINVAL, "refinement not built"); }
 extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
 {
@@ -29,4 +30,3 @@ extern "C" void wp_batch_destroy(wp_batch *) {}
 extern "C" int wp_batch_step(wp_batch *, int, int) { return WP_EINVAL; }
 extern "C" int wp_batch_adjoint_run(wp_batch *, const wp_functional *, int, int) { return WP_EINVAL; }
 extern "C" const char *wp_batch_last_error(const wp_batch *) { return "batches not built"; }
-extern "C" int wp_run_graph(wp_ctx *ctx, int, double, int) { return wp_fail(ctx, WP_EINVAL, "graphs not built"); }

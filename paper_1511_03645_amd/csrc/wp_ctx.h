@@ -24,6 +24,8 @@ struct Level {
     std::vector<wp::Tile> tiles_host;
     wp::Tile *tiles_dev = nullptr;
     int ntiles = 0;
+    int tile_rows = 0;                   // rows of the step tiles (compile-time march height if supported)
+    int nuni = 0;                        // number of single-material tiles (they follow the mixed ones)
     wp::Tile *ftiles_dev = nullptr;      // flag / reduction tiles
     int nftiles = 0;
     double t = 0.0;
@@ -71,13 +73,25 @@ struct wp_ctx {
     unsigned long long *count = nullptr;
     double *partials = nullptr, *red_out = nullptr;
     unsigned *cflbits = nullptr;
-    uint8_t *ind_dev = nullptr;
+    uint8_t *ind_dev = nullptr;          // indicator of the cached functional
+    wp_functional ind_key{};
+    bool ind_valid = false;
+    void *phi_dev = nullptr;             // adjoint initial data of the cached functional
+    wp_functional phi_key{};
+    bool phi_valid = false;
     std::string err;
     int tile_rows = 0;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_steps = 0;
+    // captured launch sequences, replayed on an internal stream joined to
+    // `stream` with events
+    hipStream_t cap_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipGraphExec_t graph_exec = nullptr;     // forward steps of level 0
+    int graph_steps = 0, graph_parity = -1;
     double graph_dt = 0.0;
-    int graph_parity = -1;
+    hipGraphExec_t adj_exec = nullptr;       // adjoint run with snapshot copies
+    int adj_steps = 0, adj_every = 0;
+    double adj_dt = 0.0;
+    const void *adj_snaps = nullptr;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };
 
@@ -87,16 +101,23 @@ void wp_dfree(wp_ctx *ctx, void *p);
 std::vector<wp::Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, int rows, int width, bool xcd_order);
 int wp_upload_tiles(wp_ctx *ctx, Level &lv);
 int wp_default_rows(const wp_ctx *ctx, const Level &lv);
+uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j);
+void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles);
 int wp_alloc_level(wp_ctx *ctx, Level &lv);
 int wp_check_status(wp_ctx *ctx);
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt);
-int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint);
+int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s);
+int wp_prepare_level(wp_ctx *ctx, Level &lv, double dt);
 int wp_build_indicator(wp_ctx *ctx, const wp_functional *J, std::vector<uint8_t> &ind);
 int wp_ensure_adjoint_level(wp_ctx *ctx);
 int wp_window(wp_ctx *ctx, double t, double t_s, double t_f, int &n_lo, int &n_hi);
 // shallow water (swe_host.hip)
 int wp_swe_init(wp_ctx *ctx, const wp_coefficients *coef);
 int wp_swe_adj_init(wp_ctx *ctx);
-int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint);
+int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s);
+int wp_swe_prepare(wp_ctx *ctx, Level &lv, double dt);
+int wp_graph_begin(wp_ctx *ctx, hipStream_t &s);
+int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec);
+int wp_graph_launch(wp_ctx *ctx, hipGraphExec_t exec);
 // refinement (amr_host.hip)
 int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t);

@@ -76,7 +76,7 @@ std::vector<Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, 
     for (const auto &p : patches)
         for (int i = 0; i < p.nx; i += width)
             for (int j = 0; j < p.ny; j += rows)
-                t.push_back(Tile{inst, p.ilo + i, p.jlo + j, std::min(width, p.nx - i), std::min(rows, p.ny - j)});
+                t.push_back(Tile{inst, p.ilo + i, p.jlo + j, std::min(width, p.nx - i), std::min(rows, p.ny - j), -1});
     if (!xcd_order || t.size() < 16) return t;
     const size_t n = t.size(), nx = 8;
     std::vector<Tile> o(n);
@@ -91,11 +91,55 @@ std::vector<Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, 
     return o;
 }
 
+static int host_resolve(int i, int n, int lo, int hi)
+{
+    i = std::min(std::max(i, -2), n + 1);
+    if (i < 0) return lo == WP_BC_PERIODIC ? i + n : (lo == WP_BC_WALL ? -1 - i : 0);
+    if (i >= n) return hi == WP_BC_PERIODIC ? i - n : (hi == WP_BC_WALL ? 2 * n - 1 - i : n - 1);
+    return i;
+}
+
+// Material of a level cell: that of the level-0 cell containing it.
+uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j)
+{
+    const int r = lv.nx / ctx->grid.nx0;
+    const int ry = ctx->kind2d ? lv.ny / ctx->grid.ny0 : 1;
+    return ctx->mat0[(size_t)(j / ry) * ctx->grid.nx0 + i / r];
+}
+
+// Mark tiles whose whole read footprint (two-cell halo, ghost cells
+// resolved by the boundary rules) holds one material.
+void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &tiles)
+{
+    if (!ctx->is_acoustics || !ctx->kind2d) return;
+    const int *bc = ctx->prob.bc;
+    for (auto &t : tiles) {
+        int m0 = -1;
+        bool uni = true;
+        for (int j = t.j0 - 2; j <= t.j0 + t.nj + 1 && uni; ++j) {
+            const int jj = host_resolve(j, lv.ny, bc[2], bc[3]);
+            for (int i = t.i0 - 2; i <= t.i0 + t.ni + 1; ++i) {
+                const int m = wp_level_mat(ctx, lv, host_resolve(i, lv.nx, bc[0], bc[1]), jj);
+                if (m0 < 0) m0 = m;
+                else if (m != m0) { uni = false; break; }
+            }
+        }
+        t.mat = uni ? m0 : -1;
+    }
+}
+
 int wp_upload_tiles(wp_ctx *ctx, Level &lv)
 {
     const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
     const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, lv);
     lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, true);
+    lv.tile_rows = rows;
+    wp_classify_tiles(ctx, lv, lv.tiles_host);
+    // mixed-material tiles (the slower march) first, so they are dispatched
+    // at the start rather than forming the tail; each group keeps its
+    // XCD-aware order
+    std::stable_partition(lv.tiles_host.begin(), lv.tiles_host.end(), [](const Tile &t) { return t.mat < 0; });
+    lv.nuni = (int)std::count_if(lv.tiles_host.begin(), lv.tiles_host.end(), [](const Tile &t) { return t.mat >= 0; });
     // flag / reduction tiles: larger blocks of whole patches
     std::vector<Tile> ft = wp_make_tiles(lv.patches, 0, 16, 64, false);
     if (lv.tiles_dev) wp_dfree(ctx, lv.tiles_dev);
@@ -118,9 +162,9 @@ int wp_default_rows(const wp_ctx *ctx, const Level &lv)
     // enough strips to give every SIMD several waves on small grids, long
     // marches (little halo re-read) on large ones
     const long long cells = (long long)lv.nx * lv.ny;
-    if (cells <= (1LL << 18)) return 8;
-    if (cells <= (1LL << 21)) return 16;
-    return 32;
+    if (cells <= (1LL << 18)) return 4;
+    if (cells <= (1LL << 21)) return 8;
+    return 16;
 }
 
 // ---------------------------------------------------------------------------
@@ -311,6 +355,10 @@ extern "C" void wp_destroy(wp_ctx *ctx)
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->adj_exec) (void)hipGraphExecDestroy(ctx->adj_exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     std::vector<void *> all = ctx->owned;
     for (void *p : all) wp_dfree(ctx, p);
     delete ctx;
@@ -507,16 +555,22 @@ static int ensure_acou_inst(wp_ctx *ctx, Level &lv, double dt)
 }
 
 template <typename T>
-static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint)
+static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t stream)
 {
     int rc;
     if ((rc = ensure_acou_inst<T>(ctx, lv, dt)) != WP_OK) return rc;
-    if (ctx->kind2d)
-        launch_acou2d<T>((const AcouInst<T> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, ctx->status,
-                         ctx->stream);
+    if (stream != ctx->stream && lv.inst_dt != dt) return wp_fail(ctx, WP_ESTATE, "descriptor not prepared before capture");
+    if (ctx->kind2d) {
+        const bool full = ctx->prob.order == 2 && ctx->prob.limiter == 1 && ctx->prob.transverse == 1;
+        const AcouInst<T> *I = (const AcouInst<T> *)lv.inst;
+        // one launch: a single-material level runs the lean kernel, any other
+        // the kernel that picks the path per tile
+        launch_acou2d<T>(I, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, full, lv.tile_rows,
+                         lv.nuni == lv.ntiles ? 1 : 0, ctx->status, stream);
+    }
     else
         launch_acou1d<T>((const AcouInst<T> *)lv.inst, *(const AcouInst<T> *)lv.inst_host, lv.cur, adjoint, ctx->status,
-                         ctx->stream);
+                         stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "step launch: %s", hipGetErrorString(e));
     lv.cur ^= 1;
@@ -534,13 +588,106 @@ int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt)
     return WP_OK;
 }
 
-int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint)
+// Make the level's instance descriptor current for step size dt (an upload
+// when dt changed), so that a following capture records launches only.
+int wp_prepare_level(wp_ctx *ctx, Level &lv, double dt)
+{
+    if (ctx->is_acoustics) return ctx->esz == 8 ? ensure_acou_inst<double>(ctx, lv, dt) : ensure_acou_inst<float>(ctx, lv, dt);
+    return wp_swe_prepare(ctx, lv, dt);
+}
+
+int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s)
 {
     if (ctx->is_acoustics) {
-        if (ctx->esz == 8) return acou_step<double>(ctx, lv, dt, adjoint);
-        return acou_step<float>(ctx, lv, dt, adjoint);
+        if (ctx->esz == 8) return acou_step<double>(ctx, lv, dt, adjoint, s);
+        return acou_step<float>(ctx, lv, dt, adjoint, s);
     }
-    return wp_swe_step(ctx, lv, dt, adjoint);
+    return wp_swe_step(ctx, lv, dt, adjoint, s);
+}
+
+// ---------------------------------------------------------------------------
+// graphs: capture on an internal stream, joined to the caller's stream
+// ---------------------------------------------------------------------------
+int wp_graph_begin(wp_ctx *ctx, hipStream_t &s)
+{
+    if (!ctx->cap_stream) {
+        if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "capture stream creation failed");
+    }
+    s = ctx->cap_stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "stream capture begin: %s", hipGetErrorString(hipGetLastError()));
+    return WP_OK;
+}
+
+int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess || !g)
+        return wp_fail(ctx, WP_EDEVICE, "stream capture end: %s", hipGetErrorString(hipGetLastError()));
+    if (exec) {
+        (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+    hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        exec = nullptr;
+        return wp_fail(ctx, WP_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    return WP_OK;
+}
+
+int wp_graph_launch(wp_ctx *ctx, hipGraphExec_t exec)
+{
+    if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
+        hipStreamWaitEvent(ctx->cap_stream, ctx->ev_fork, 0) != hipSuccess ||
+        hipGraphLaunch(exec, ctx->cap_stream) != hipSuccess ||
+        hipEventRecord(ctx->ev_join, ctx->cap_stream) != hipSuccess ||
+        hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "graph launch: %s", hipGetErrorString(hipGetLastError()));
+    return WP_OK;
+}
+
+extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
+{
+    if (!ctx) return WP_EINVAL;
+    if (nsteps < 1 || replays < 0) return wp_fail(ctx, WP_EINVAL, "nsteps must be >= 1 and replays >= 0");
+    if (ctx->L.size() != 1) return wp_fail(ctx, WP_EINVAL, "graph replay is for single-level instances (use wp_advance)");
+    Level &lv = ctx->L[0];
+    int rc;
+    if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
+    if (!ctx->graph_exec || ctx->graph_steps != nsteps || ctx->graph_dt != dt || ctx->graph_parity != lv.cur) {
+        if ((rc = wp_prepare_level(ctx, lv, dt)) != WP_OK) return rc;
+        hipStream_t s;
+        if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
+        int par = lv.cur;
+        for (int k = 0; k < nsteps && rc == WP_OK; ++k) {
+            rc = wp_step_level(ctx, lv, dt, 0, s);
+        }
+        lv.cur = par;
+        int rc2 = wp_graph_end(ctx, s, ctx->graph_exec);
+        if (rc != WP_OK) return rc;
+        if (rc2 != WP_OK) return rc2;
+        ctx->graph_steps = nsteps;
+        ctx->graph_dt = dt;
+        ctx->graph_parity = lv.cur;
+    }
+    for (int r = 0; r < replays; ++r) {
+        if ((rc = wp_graph_launch(ctx, ctx->graph_exec)) != WP_OK) return rc;
+        if (nsteps & 1) {
+            // an odd sequence ends on the other buffer: later replays need the
+            // graph captured for that parity
+            lv.cur ^= 1;
+            lv.t += nsteps * dt;
+            if (r + 1 < replays) return wp_run_graph(ctx, nsteps, dt, replays - r - 1);
+            return WP_OK;
+        }
+        lv.t += nsteps * dt;
+    }
+    return WP_OK;
 }
 
 extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
@@ -555,7 +702,7 @@ extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
         return WP_OK;
     }
     if (level > 0 && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK) return rc;
-    if ((rc = wp_step_level(ctx, lv, dt, 0)) != WP_OK) return rc;
+    if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream)) != WP_OK) return rc;
     lv.t += dt;
     return WP_OK;
 }
@@ -615,8 +762,8 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
     if (!sp || sp->nsteps < 0 || sp->snap_every < 1 || sp->nsteps % sp->snap_every != 0)
         return wp_fail(ctx, WP_EINVAL, "snapshot spec: nsteps must be a non-negative multiple of snap_every >= 1");
     int rc;
-    std::vector<uint8_t> ind;
-    if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
+    if (!J || J->kind < 0 || J->kind > 2 || J->component < 0 || J->component >= ctx->m)
+        return wp_fail(ctx, WP_EINVAL, "bad functional");
     if ((rc = wp_ensure_adjoint_level(ctx)) != WP_OK) return rc;
     Level &a = ctx->adj;
     if ((rc = wp_courant_check(ctx, a, sp->dt)) != WP_OK) return rc;
@@ -633,32 +780,59 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
         }
         ctx->snaps_cap = (size_t)nsnap * snap_bytes;
     }
-    // qtilde(x, 0) = phi = I(x) e_component
-    {
+    // qtilde(x, 0) = phi = I(x) e_component, kept on the device per functional
+    const size_t phi_bytes = (size_t)cells * ctx->m * ctx->snap_esz();
+    if (!ctx->phi_valid || memcmp(&ctx->phi_key, J, sizeof *J) != 0) {
+        std::vector<uint8_t> ind;
+        if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
         const size_t es = ctx->snap_esz();
-        std::vector<char> host((size_t)cells * ctx->m * es, 0);
+        std::vector<char> host(phi_bytes, 0);
         for (long long k = 0; k < cells; ++k)
             if (ind[k]) {
                 char *dst = host.data() + ((size_t)J->component * cells + k) * es;
                 if (es == 8) { double one = 1.0; memcpy(dst, &one, 8); }
                 else { float one = 1.0f; memcpy(dst, &one, 4); }
             }
-        a.cur = 0;
-        if (hipMemcpy(a.q[0], host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+        if (!ctx->phi_dev) ctx->phi_dev = wp_dalloc(ctx, phi_bytes);
+        if (!ctx->phi_dev) return wp_fail(ctx, WP_ENOMEM, "adjoint initial data");
+        if (hipMemcpy(ctx->phi_dev, host.data(), phi_bytes, hipMemcpyHostToDevice) != hipSuccess)
             return wp_fail(ctx, WP_EDEVICE, "adjoint initial data upload");
+        ctx->phi_key = *J;
+        ctx->phi_valid = true;
     }
     ctx->nsnap = 0;
-    auto snap = [&](int n) -> int {
-        if (hipMemcpyAsync((char *)ctx->snaps + (size_t)n * snap_bytes, a.q[a.cur], snap_bytes,
-                           hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
-            return wp_fail(ctx, WP_EDEVICE, "snapshot copy");
-        return WP_OK;
-    };
-    if ((rc = snap(0)) != WP_OK) return rc;
-    for (int s = 1; s <= sp->nsteps; ++s) {
-        if ((rc = wp_step_level(ctx, a, sp->dt, 1)) != WP_OK) return rc;
-        if (s % sp->snap_every == 0 && (rc = snap(s / sp->snap_every)) != WP_OK) return rc;
+    // the whole run (steps and snapshot copies) is one captured graph,
+    // re-captured only when the step count, interval, dt or store change
+    if ((rc = wp_prepare_level(ctx, a, sp->dt)) != WP_OK) return rc;
+    a.cur = 0;
+    if (hipMemcpyAsync(a.q[0], ctx->phi_dev, phi_bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "adjoint initial data copy");
+    if (!ctx->adj_exec || ctx->adj_steps != sp->nsteps || ctx->adj_every != sp->snap_every || ctx->adj_dt != sp->dt ||
+        ctx->adj_snaps != ctx->snaps) {
+        hipStream_t cs;
+        if ((rc = wp_graph_begin(ctx, cs)) != WP_OK) return rc;
+        auto snap = [&](int n) -> int {
+            if (hipMemcpyAsync((char *)ctx->snaps + (size_t)n * snap_bytes, a.q[a.cur], snap_bytes,
+                               hipMemcpyDeviceToDevice, cs) != hipSuccess)
+                return wp_fail(ctx, WP_EDEVICE, "snapshot copy");
+            return WP_OK;
+        };
+        rc = snap(0);
+        for (int s = 1; s <= sp->nsteps && rc == WP_OK; ++s) {
+            rc = wp_step_level(ctx, a, sp->dt, 1, cs);
+            if (rc == WP_OK && s % sp->snap_every == 0) rc = snap(s / sp->snap_every);
+        }
+        int rc2 = wp_graph_end(ctx, cs, ctx->adj_exec);
+        if (rc != WP_OK) return rc;
+        if (rc2 != WP_OK) return rc2;
+        ctx->adj_steps = sp->nsteps;
+        ctx->adj_every = sp->snap_every;
+        ctx->adj_dt = sp->dt;
+        ctx->adj_snaps = ctx->snaps;
+    } else {
+        a.cur = sp->nsteps & 1;
     }
+    if ((rc = wp_graph_launch(ctx, ctx->adj_exec)) != WP_OK) return rc;
     ctx->nsnap = nsnap;
     ctx->snap_ds = sp->dt * sp->snap_every;
     ctx->adj_tf = sp->dt * sp->nsteps;
@@ -763,12 +937,16 @@ extern "C" int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int whic
     const void *q = l0.q[l0.cur];
     int rc;
     if (which == 0) {
-        std::vector<uint8_t> ind;
-        if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
-        if (!ctx->ind_dev) ctx->ind_dev = (uint8_t *)wp_dalloc(ctx, (size_t)cells);
-        if (!ctx->ind_dev) return wp_fail(ctx, WP_ENOMEM, "indicator");
-        if (hipMemcpy(ctx->ind_dev, ind.data(), (size_t)cells, hipMemcpyHostToDevice) != hipSuccess)
-            return wp_fail(ctx, WP_EDEVICE, "indicator upload");
+        if (!ctx->ind_valid || memcmp(&ctx->ind_key, J, sizeof *J) != 0) {
+            std::vector<uint8_t> ind;
+            if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
+            if (!ctx->ind_dev) ctx->ind_dev = (uint8_t *)wp_dalloc(ctx, (size_t)cells);
+            if (!ctx->ind_dev) return wp_fail(ctx, WP_ENOMEM, "indicator");
+            if (hipMemcpy(ctx->ind_dev, ind.data(), (size_t)cells, hipMemcpyHostToDevice) != hipSuccess)
+                return wp_fail(ctx, WP_EDEVICE, "indicator upload");
+            ctx->ind_key = *J;
+            ctx->ind_valid = true;
+        }
         if (ctx->prob.precision == WP_MIXED) {
             if (J->component == 0)
                 launch_sum_indicator<double>((const double *)q, cells, cells, 0, ctx->ind_dev, ctx->partials, nb,

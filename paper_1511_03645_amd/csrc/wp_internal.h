@@ -18,6 +18,7 @@ constexpr int STRIP = WAVE - 4; // output columns per wave in the 2D kernels
 // [i0, i0 + ni) x [j0, j0 + nj) of instance `inst`.
 struct Tile {
     int inst, i0, j0, ni, nj;
+    int mat;   // material of every cell the tile reads (halo included), -1 if mixed
 };
 
 // Per-instance description of a 2D (or 1D) acoustics level canvas.  The
@@ -61,7 +62,7 @@ constexpr int ST_CFL = 2;
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
-                   int nmat_max, int *status, hipStream_t s);
+                   int nmat_max, bool full, int rows, int kind, int *status, hipStream_t s);
 template <typename T>
 void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, int parity, int adjoint,
                    int *status, hipStream_t s);

@@ -206,3 +206,40 @@ def test_flag_window_out_of_range():
     with pytest.raises(wp.WPError) as e:
         w.flag_adjoint(0, 1e-3, 0.0, cfg["t_f"], cfg["t_f"])
     assert e.value.code == wp.WP_ERANGE
+
+
+@pytest.mark.parametrize("nsteps", [4, 3])
+def test_graph_replay_matches_eager(nsteps):
+    """Captured step sequences replayed several times, with eager steps and
+    synchronisations in between, equal the same steps launched eagerly,
+    bit for bit, after every replay."""
+    cfg = small_cfg(100, 77, (0, 1, 0, 0))
+    q0 = random_state(3, 77, 100, seed=17)
+    dt = 0.8 * cfg["dx"] / float(np.sqrt(cfg["K"] / cfg["rho"]).max())
+    eager = wp.from_config(cfg)
+    graph = wp.from_config(cfg)
+    eager.set_state(q0)
+    graph.set_state(q0)
+    for rep in range(3):
+        for _ in range(nsteps):
+            eager.step_patches(0, dt)
+        graph.run_graph(nsteps, dt, 1)
+        assert np.array_equal(graph.get_state(), eager.get_state()), f"replay {rep}"
+        eager.step_patches(0, dt)
+        graph.step_patches(0, dt)
+    for _ in range(2 * nsteps):
+        eager.step_patches(0, dt)
+    graph.run_graph(nsteps, dt, 2)
+    assert np.array_equal(graph.get_state(), eager.get_state())
+    assert abs(graph.get_time() - eager.get_time()) < 1e-12
+
+
+def test_adjoint_run_replay_is_identical():
+    cfg = acoustics2d(n=96, seed=1)
+    w = wp.from_config(cfg)
+    w.adjoint_run(cfg["functional"], cfg["dt"], 40, 10)
+    first = [w.get_snapshot(k) for k in range(w.num_snapshots())]
+    w.step_patches(0, cfg["dt"])       # unrelated eager work in between
+    w.adjoint_run(cfg["functional"], cfg["dt"], 40, 10)
+    for k in range(w.num_snapshots()):
+        assert np.array_equal(w.get_snapshot(k), first[k])
