@@ -15,6 +15,7 @@ job, inputs resident in device memory.  Prints one JSON line.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -41,6 +42,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="cells per side (workload default 1024)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -142,6 +144,76 @@ def timed(job, steps, warmup, time_kernels):
     return (time.perf_counter() - t0) / steps, J
 
 
+def batch_compare(steps, warmup, count=64):
+    """64 independent 2D acoustics instances (seeded sizes 128^2..1024^2 and
+    piecewise-constant media), each run forward + adjoint for 256 steps at its
+    own CFL-0.9 dt: FP32 batched (one launch per step for all instances)
+    against a loop of plain single-instance FP64 solves."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import acoustics2d_batch
+    cfgs = acoustics2d_batch(count=count, seed=4)
+    S, every = cfgs[0]["nsteps"], cfgs[0]["snap_every"]
+    cells = sum(c["nx"] * c["ny"] for c in cfgs)
+
+    def make(prec):
+        ws, q0 = [], []
+        dtp = np.float64 if prec == wp.FP64 else np.float32
+        for c in cfgs:
+            w = wp.from_config(c, precision=prec)
+            ws.append(w)
+            q0.append(torch.from_numpy(np.concatenate([c["q0"][k].astype(dtp).ravel().view(np.uint8)
+                                                       for k in range(3)])).cuda())
+        return ws, q0
+
+    w64, q64 = make(wp.FP64)
+
+    def loop64():
+        Js = []
+        for w, c, q in zip(w64, cfgs, q64):
+            w.adjoint_run(c["functional"], c["dt"], S, every)
+            w.set_state(q)
+            w.run_graph(S, c["dt"], 1)
+            Js.append(w.functional_value(c["functional"], 0))
+        return Js
+
+    w32, q32 = make(wp.FP32)
+    b = wp.Batch(w32, [c["dt"] for c in cfgs])
+    funcs = [c["functional"] for c in cfgs]
+
+    def batched32():
+        b.adjoint_run(funcs, S, every)
+        for w, q in zip(w32, q32):
+            w.set_state(q)
+        b.step(S)
+        return [w.functional_value(c["functional"], 0) for w, c in zip(w32, cfgs)]
+
+    def clock(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            J = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, J
+
+    t64, J64 = clock(loop64)
+    t32, J32 = clock(batched32)
+    ups = 2 * S * cells
+    rel = [abs(a - r) / abs(r) for a, r in zip(J32, J64) if r != 0.0]
+    # the same error on the functional's own scale: |dJ| / (area of the target x max|q0|)
+    scl = [math.pi * c["functional"]["r"] ** 2 * float(np.abs(c["q0"]).max()) for c in cfgs]
+    nrm = [abs(a - r) / sc for a, r, sc in zip(J32, J64, scl)]
+    worst = int(np.argmax([abs(a - r) / abs(r) if r else 0.0 for a, r in zip(J32, J64)]))
+    return {"workload": f"{count} acoustics2d instances, {cells} cells in total, {S} forward + {S} adjoint steps each",
+            "fp64_loop_value": ups / t64, "fp32_batched_value": ups / t32, "speedup": t64 / t32,
+            "unit": "cell-updates/s", "J_rel_err_max": max(rel), "J_rel_err_median": float(np.median(rel)),
+            "J_err_over_scale_max": max(nrm), "worst_instance": {"index": worst, "J_fp64": J64[worst],
+                                                                   "J_scale": scl[worst]},
+            "ms_fp64_loop": t64 * 1e3, "ms_fp32_batched": t32 * 1e3}
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: a bounded sample of the same
     workload (full grid, a fixed number of forward and adjoint steps)."""
@@ -209,6 +281,11 @@ def main():
                        "achieved_GBs": ALG_BYTES[32] * job.cells / (k32 * 1e-3) / 1e9}
         print(f"[bench] fp32: {sec32 * 1e3:.2f} ms/job, J rel err {out['fp32']['J_rel_err_vs_fp64']:.2e}",
               file=sys.stderr, flush=True)
+    if not args.no_batch:
+        print("[bench] batch of 64 instances: FP32 batched vs FP64 loop", file=sys.stderr, flush=True)
+        out["batch"] = batch_compare(max(1, min(args.steps, 3)), 1)
+        print(f"[bench] batch speedup {out['batch']['speedup']:.2f}x, J rel err max "
+              f"{out['batch']['J_rel_err_max']:.2e}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

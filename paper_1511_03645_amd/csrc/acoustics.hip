@@ -214,7 +214,7 @@ template <typename T, bool ADJ, bool UNI, bool FULL, int RT>
 __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt, const Tile &tl, int lane, int nx,
                                       int ny, int bc2, int bc3, int cx, T sx, unsigned csb, T nux, T nuy,
                                       __amdgpu_buffer_rsrc_t qr, __amdgpu_buffer_rsrc_t qw,
-                                      __amdgpu_buffer_rsrc_t mr, int &bad)
+                                      __amdgpu_buffer_rsrc_t mr, __amdgpu_buffer_rsrc_t sw, bool snap, int &bad)
 {
     // FULL: second order, MC limiter and transverse terms fixed at compile time
     const bool second = FULL ? true : op_rt.second;
@@ -364,6 +364,11 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
             bstore(qw, off, 0u, pn);
             bstore(qw, off, csb, un);
             bstore(qw, off, 2u * csb, vn);
+            if (snap) {
+                bstore(sw, off, 0u, pn);
+                bstore(sw, off, csb, un);
+                bstore(sw, off, 2u * csb, vn);
+            }
             bad |= !(isfinite(pn) && isfinite(un) && isfinite(vn));
         }
         R0 = R1;
@@ -387,7 +392,7 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
 template <typename T, bool ADJ, bool FULL, int RT, int KIND>
 __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int parity,
-                                                      int *__restrict__ status)
+                                                      int snap_index, int *__restrict__ status)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile tl = tiles[blockIdx.x];
@@ -405,6 +410,9 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
     const __amdgpu_buffer_rsrc_t qr = make_rsrc(Ip->q[parity], 3u * csb);
     const __amdgpu_buffer_rsrc_t qw = make_rsrc(Ip->q[parity ^ 1], 3u * csb);
     const __amdgpu_buffer_rsrc_t mr = make_rsrc(Ip->mat, cells);
+    const bool snap = snap_index >= 0;
+    const __amdgpu_buffer_rsrc_t sw = make_rsrc(snap ? Ip->snap + (long long)snap_index * Ip->snap_stride : Ip->q[0],
+                                                snap ? 3u * csb : 0u);
     const Opts op{Ip->order >= 2, Ip->transverse != 0, Ip->limiter};
     const T nux = Ip->nux, nuy = Ip->nuy;
     const int col = tl.i0 - 2 + lane;
@@ -422,10 +430,12 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
         md.m.Khx = uniform(src.Khx); md.m.Khy = uniform(src.Khy); md.m.Zhx = uniform(src.Zhx); md.m.Zhy = uniform(src.Zhy);
         const T *pp = pt + (tl.mat * Ip->nmat + tl.mat) * 3;
         md.inv = uniform(pp[0]);
-        march<T, ADJ, true, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, bad);
+        march<T, ADJ, true, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw, snap,
+                                      bad);
     } else if (KIND != 1) {
         Media<T, false> md{mc, pt, Ip->nmat};
-        march<T, ADJ, false, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, bad);
+        march<T, ADJ, false, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw, snap,
+                                       bad);
     }
     if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
 }
@@ -433,7 +443,7 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
 // 1D: one thread per cell, the five-cell stencil read straight from memory.
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) void acou1d_kernel(const AcouInst<T> *__restrict__ insts, int parity,
-                                                     int *__restrict__ status)
+                                                     int snap_index, int *__restrict__ status)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const AcouInst<T> &I = *insts;
@@ -492,6 +502,11 @@ __global__ __launch_bounds__(256) void acou1d_kernel(const AcouInst<T> *__restri
     }
     qo[i] = pn;
     qo[i + I.cs] = un;
+    if (snap_index >= 0) {
+        T *sn = I.snap + (long long)snap_index * I.snap_stride;
+        sn[i] = pn;
+        sn[i + I.cs] = un;
+    }
     if (!(isfinite(pn) && isfinite(un))) atomicOr(status, ST_NONFINITE);
 }
 
@@ -505,13 +520,13 @@ static size_t acou_smem(int nmat)
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint, int nmat_max,
-                   bool full, int rows, int kind, int *status, hipStream_t s)
+                   bool full, int rows, int kind, int snap_index, int *status, hipStream_t s)
 {
     if (ntiles <= 0) return;
     const size_t sm = acou_smem<T>(nmat_max);
     const dim3 g(ntiles), b(WAVE);
 #define WP_LAUNCH(ADJ, FULL, RT, KIND) \
-    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, status)
+    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap_index, status)
 #define WP_BY_RT(ADJ, KIND)                              \
     switch (full ? rows : 0) {                           \
     case 4: WP_LAUNCH(ADJ, true, 4, KIND); break;        \
@@ -535,23 +550,24 @@ void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int 
 }
 
 template <typename T>
-void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &h, int parity, int adjoint, int *status,
-                   hipStream_t s)
+void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &h, int parity, int adjoint, int snap_index,
+                   int *status, hipStream_t s)
 {
     const size_t sm = acou_smem<T>(h.nmat);
     const int nb = (h.nx + 255) / 256;
     if (adjoint)
-        hipLaunchKernelGGL((acou1d_kernel<T, true>), dim3(nb), dim3(256), sm, s, inst_dev, parity, status);
+        hipLaunchKernelGGL((acou1d_kernel<T, true>), dim3(nb), dim3(256), sm, s, inst_dev, parity, snap_index, status);
     else
-        hipLaunchKernelGGL((acou1d_kernel<T, false>), dim3(nb), dim3(256), sm, s, inst_dev, parity, status);
+        hipLaunchKernelGGL((acou1d_kernel<T, false>), dim3(nb), dim3(256), sm, s, inst_dev, parity, snap_index, status);
 }
 
 template void launch_acou2d<double>(const AcouInst<double> *, const Tile *, int, int, int, int, bool, int, int,
-                                    int *, hipStream_t);
+                                    int, int *, hipStream_t);
 template void launch_acou2d<float>(const AcouInst<float> *, const Tile *, int, int, int, int, bool, int, int,
-                                   int *, hipStream_t);
-template void launch_acou1d<double>(const AcouInst<double> *, const AcouInst<double> &, int, int, int *,
+                                   int, int *, hipStream_t);
+template void launch_acou1d<double>(const AcouInst<double> *, const AcouInst<double> &, int, int, int, int *,
                                     hipStream_t);
-template void launch_acou1d<float>(const AcouInst<float> *, const AcouInst<float> &, int, int, int *, hipStream_t);
+template void launch_acou1d<float>(const AcouInst<float> *, const AcouInst<float> &, int, int, int, int *,
+                                   hipStream_t);
 
 }  // namespace wp

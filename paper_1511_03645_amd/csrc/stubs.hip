@@ -3,7 +3,7 @@
 
 int wp_swe_init(wp_ctx *ctx, const wp_coefficients *) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
 int wp_swe_adj_init(wp_ctx *ctx) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
-int wp_swe_step(wp_ctx *ctx, Level &, double, int, hipStream_t) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
+int wp_swe_step(wp_ctx *ctx, Level &, double, int, hipStream_t, int) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
 int wp_swe_prepare(wp_ctx *ctx, Level &, double) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
 int wp_fill_coarse_ghosts(wp_ctx *ctx, int, double) { return wp_fail(ctx, WP_EINVAL, "refinement not built"); }
 extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
@@ -25,8 +25,3 @@ extern "C" int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int c
     for (int k = 0; k < (int)p.size() && k < cap; ++k) out[k] = p[k];
     return WP_OK;
 }
-extern "C" int wp_batch_create(wp_ctx *const *, int, const double *, wp_batch **out) { if (out) *out = nullptr; return WP_EINVAL; }
-extern "C" void wp_batch_destroy(wp_batch *) {}
-extern "C" int wp_batch_step(wp_batch *, int, int) { return WP_EINVAL; }
-extern "C" int wp_batch_adjoint_run(wp_batch *, const wp_functional *, int, int) { return WP_EINVAL; }
-extern "C" const char *wp_batch_last_error(const wp_batch *) { return "batches not built"; }

@@ -31,6 +31,8 @@ struct Level {
     double t = 0.0;
     void *inst = nullptr;                // device instance descriptor
     double inst_dt = -1.0;
+    void *snap_base = nullptr;           // snapshot store written by this level's steps (adjoint)
+    void *inst_snap = nullptr;
     alignas(16) unsigned char inst_host[256];
     // AMR: cells of the ghost ring (inside the domain, outside every patch,
     // within two cells of one) filled from the level below before each step
@@ -106,15 +108,18 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile>
 int wp_alloc_level(wp_ctx *ctx, Level &lv);
 int wp_check_status(wp_ctx *ctx);
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt);
-int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s);
+int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap_index);
 int wp_prepare_level(wp_ctx *ctx, Level &lv, double dt);
 int wp_build_indicator(wp_ctx *ctx, const wp_functional *J, std::vector<uint8_t> &ind);
 int wp_ensure_adjoint_level(wp_ctx *ctx);
+int wp_adjoint_setup(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *sp);
+void wp_adjoint_finish(wp_ctx *ctx, const wp_snapshot_spec *sp);
+void wp_xcd_order(std::vector<wp::Tile> &t);
 int wp_window(wp_ctx *ctx, double t, double t_s, double t_f, int &n_lo, int &n_hi);
 // shallow water (swe_host.hip)
 int wp_swe_init(wp_ctx *ctx, const wp_coefficients *coef);
 int wp_swe_adj_init(wp_ctx *ctx);
-int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s);
+int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap_index);
 int wp_swe_prepare(wp_ctx *ctx, Level &lv, double dt);
 int wp_graph_begin(wp_ctx *ctx, hipStream_t &s);
 int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec);

@@ -77,7 +77,15 @@ std::vector<Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, 
         for (int i = 0; i < p.nx; i += width)
             for (int j = 0; j < p.ny; j += rows)
                 t.push_back(Tile{inst, p.ilo + i, p.jlo + j, std::min(width, p.nx - i), std::min(rows, p.ny - j), -1});
-    if (!xcd_order || t.size() < 16) return t;
+    if (xcd_order) wp_xcd_order(t);
+    return t;
+}
+
+// Reorder a spatially ordered tile list so that workgroups k, k+8, k+16, ...
+// (the ones the hardware places on one XCD) take one contiguous run of it.
+void wp_xcd_order(std::vector<Tile> &t)
+{
+    if (t.size() < 16) return;
     const size_t n = t.size(), nx = 8;
     std::vector<Tile> o(n);
     const size_t chunk = (n + nx - 1) / nx;
@@ -88,7 +96,7 @@ std::vector<Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, 
             if (src < n) o[k++] = t[src];
         }
     o.resize(k);
-    return o;
+    t.swap(o);
 }
 
 static int host_resolve(int i, int n, int lo, int hi)
@@ -526,7 +534,7 @@ extern "C" int wp_get_tile_rows(const wp_ctx *ctx, int *rows)
 template <typename T>
 static int ensure_acou_inst(wp_ctx *ctx, Level &lv, double dt)
 {
-    if (lv.inst && lv.inst_dt == dt) return WP_OK;
+    if (lv.inst && lv.inst_dt == dt && lv.inst_snap == lv.snap_base) return WP_OK;
     AcouInst<T> I;
     memset(&I, 0, sizeof I);
     I.q[0] = (T *)lv.q[0];
@@ -544,18 +552,21 @@ static int ensure_acou_inst(wp_ctx *ctx, Level &lv, double dt)
     I.order = ctx->prob.order;
     I.limiter = ctx->prob.limiter;
     I.transverse = ctx->kind2d ? ctx->prob.transverse : 0;
+    I.snap = (T *)lv.snap_base;
+    I.snap_stride = (long long)lv.nx * lv.ny * ctx->m;
     if (!lv.inst) lv.inst = wp_dalloc(ctx, sizeof(AcouInst<T>));
     if (!lv.inst) return wp_fail(ctx, WP_ENOMEM, "instance");
     if (hipMemcpyAsync(lv.inst, &I, sizeof I, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "instance upload");
     lv.inst_dt = dt;
+    lv.inst_snap = lv.snap_base;
     memcpy(lv.inst_host, &I, sizeof I);
     return WP_OK;
 }
 
 template <typename T>
-static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t stream)
+static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t stream, int snap_index)
 {
     int rc;
     if ((rc = ensure_acou_inst<T>(ctx, lv, dt)) != WP_OK) return rc;
@@ -566,11 +577,11 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
         // one launch: a single-material level runs the lean kernel, any other
         // the kernel that picks the path per tile
         launch_acou2d<T>(I, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, full, lv.tile_rows,
-                         lv.nuni == lv.ntiles ? 1 : 0, ctx->status, stream);
+                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream);
     }
     else
-        launch_acou1d<T>((const AcouInst<T> *)lv.inst, *(const AcouInst<T> *)lv.inst_host, lv.cur, adjoint, ctx->status,
-                         stream);
+        launch_acou1d<T>((const AcouInst<T> *)lv.inst, *(const AcouInst<T> *)lv.inst_host, lv.cur, adjoint, snap_index,
+                         ctx->status, stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "step launch: %s", hipGetErrorString(e));
     lv.cur ^= 1;
@@ -596,13 +607,13 @@ int wp_prepare_level(wp_ctx *ctx, Level &lv, double dt)
     return wp_swe_prepare(ctx, lv, dt);
 }
 
-int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s)
+int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap_index)
 {
     if (ctx->is_acoustics) {
-        if (ctx->esz == 8) return acou_step<double>(ctx, lv, dt, adjoint, s);
-        return acou_step<float>(ctx, lv, dt, adjoint, s);
+        if (ctx->esz == 8) return acou_step<double>(ctx, lv, dt, adjoint, s, snap_index);
+        return acou_step<float>(ctx, lv, dt, adjoint, s, snap_index);
     }
-    return wp_swe_step(ctx, lv, dt, adjoint, s);
+    return wp_swe_step(ctx, lv, dt, adjoint, s, snap_index);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,7 +676,7 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
         if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
         int par = lv.cur;
         for (int k = 0; k < nsteps && rc == WP_OK; ++k) {
-            rc = wp_step_level(ctx, lv, dt, 0, s);
+            rc = wp_step_level(ctx, lv, dt, 0, s, -1);
         }
         lv.cur = par;
         int rc2 = wp_graph_end(ctx, s, ctx->graph_exec);
@@ -702,7 +713,7 @@ extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
         return WP_OK;
     }
     if (level > 0 && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK) return rc;
-    if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream)) != WP_OK) return rc;
+    if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream, -1)) != WP_OK) return rc;
     lv.t += dt;
     return WP_OK;
 }
@@ -756,9 +767,12 @@ int wp_ensure_adjoint_level(wp_ctx *ctx)
     return wp_upload_tiles(ctx, a);
 }
 
-extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *sp)
+// Everything of an adjoint run but the stepping: snapshot store, phi on the
+// device, qtilde(x, 0) = phi in the adjoint canvas and in snapshot 0, and a
+// descriptor whose steps write the store.  Shared by wp_adjoint_run and the
+// batched adjoint run.
+int wp_adjoint_setup(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *sp)
 {
-    if (!ctx) return WP_EINVAL;
     if (!sp || sp->nsteps < 0 || sp->snap_every < 1 || sp->nsteps % sp->snap_every != 0)
         return wp_fail(ctx, WP_EINVAL, "snapshot spec: nsteps must be a non-negative multiple of snap_every >= 1");
     int rc;
@@ -781,47 +795,58 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
         ctx->snaps_cap = (size_t)nsnap * snap_bytes;
     }
     // qtilde(x, 0) = phi = I(x) e_component, kept on the device per functional
-    const size_t phi_bytes = (size_t)cells * ctx->m * ctx->snap_esz();
     if (!ctx->phi_valid || memcmp(&ctx->phi_key, J, sizeof *J) != 0) {
         std::vector<uint8_t> ind;
         if ((rc = wp_build_indicator(ctx, J, ind)) != WP_OK) return rc;
         const size_t es = ctx->snap_esz();
-        std::vector<char> host(phi_bytes, 0);
+        std::vector<char> host(snap_bytes, 0);
         for (long long k = 0; k < cells; ++k)
             if (ind[k]) {
                 char *dst = host.data() + ((size_t)J->component * cells + k) * es;
                 if (es == 8) { double one = 1.0; memcpy(dst, &one, 8); }
                 else { float one = 1.0f; memcpy(dst, &one, 4); }
             }
-        if (!ctx->phi_dev) ctx->phi_dev = wp_dalloc(ctx, phi_bytes);
+        if (!ctx->phi_dev) ctx->phi_dev = wp_dalloc(ctx, snap_bytes);
         if (!ctx->phi_dev) return wp_fail(ctx, WP_ENOMEM, "adjoint initial data");
-        if (hipMemcpy(ctx->phi_dev, host.data(), phi_bytes, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(ctx->phi_dev, host.data(), snap_bytes, hipMemcpyHostToDevice) != hipSuccess)
             return wp_fail(ctx, WP_EDEVICE, "adjoint initial data upload");
         ctx->phi_key = *J;
         ctx->phi_valid = true;
     }
     ctx->nsnap = 0;
-    // the whole run (steps and snapshot copies) is one captured graph,
-    // re-captured only when the step count, interval, dt or store change
+    a.snap_base = ctx->snaps;
     if ((rc = wp_prepare_level(ctx, a, sp->dt)) != WP_OK) return rc;
     a.cur = 0;
-    if (hipMemcpyAsync(a.q[0], ctx->phi_dev, phi_bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+    if (hipMemcpyAsync(a.q[0], ctx->phi_dev, snap_bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ctx->snaps, ctx->phi_dev, snap_bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "adjoint initial data copy");
+    ctx->snap_bytes = snap_bytes;
+    return WP_OK;
+}
+
+void wp_adjoint_finish(wp_ctx *ctx, const wp_snapshot_spec *sp)
+{
+    ctx->nsnap = sp->nsteps / sp->snap_every + 1;
+    ctx->snap_ds = sp->dt * sp->snap_every;
+    ctx->adj_tf = sp->dt * sp->nsteps;
+    ctx->adj.t = ctx->adj_tf;
+}
+
+extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *sp)
+{
+    if (!ctx) return WP_EINVAL;
+    int rc;
+    if ((rc = wp_adjoint_setup(ctx, J, sp)) != WP_OK) return rc;
+    Level &a = ctx->adj;
+    // the whole run is one captured graph, re-captured only when the step
+    // count, interval, dt or store change; the stencil writes each snapshot
+    // itself on its snapshot steps
     if (!ctx->adj_exec || ctx->adj_steps != sp->nsteps || ctx->adj_every != sp->snap_every || ctx->adj_dt != sp->dt ||
         ctx->adj_snaps != ctx->snaps) {
         hipStream_t cs;
         if ((rc = wp_graph_begin(ctx, cs)) != WP_OK) return rc;
-        auto snap = [&](int n) -> int {
-            if (hipMemcpyAsync((char *)ctx->snaps + (size_t)n * snap_bytes, a.q[a.cur], snap_bytes,
-                               hipMemcpyDeviceToDevice, cs) != hipSuccess)
-                return wp_fail(ctx, WP_EDEVICE, "snapshot copy");
-            return WP_OK;
-        };
-        rc = snap(0);
-        for (int s = 1; s <= sp->nsteps && rc == WP_OK; ++s) {
-            rc = wp_step_level(ctx, a, sp->dt, 1, cs);
-            if (rc == WP_OK && s % sp->snap_every == 0) rc = snap(s / sp->snap_every);
-        }
+        for (int s = 1; s <= sp->nsteps && rc == WP_OK; ++s)
+            rc = wp_step_level(ctx, a, sp->dt, 1, cs, s % sp->snap_every == 0 ? s / sp->snap_every : -1);
         int rc2 = wp_graph_end(ctx, cs, ctx->adj_exec);
         if (rc != WP_OK) return rc;
         if (rc2 != WP_OK) return rc2;
@@ -833,11 +858,7 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
         a.cur = sp->nsteps & 1;
     }
     if ((rc = wp_graph_launch(ctx, ctx->adj_exec)) != WP_OK) return rc;
-    ctx->nsnap = nsnap;
-    ctx->snap_ds = sp->dt * sp->snap_every;
-    ctx->adj_tf = sp->dt * sp->nsteps;
-    ctx->snap_bytes = snap_bytes;
-    a.t = ctx->adj_tf;
+    wp_adjoint_finish(ctx, sp);
     return wp_sync(ctx);
 }
 

@@ -37,6 +37,8 @@ struct AcouInst {
     const T *ptab;            // [nmat][nmat][3]: 1/(Z_a+Z_b), kappa1, kappa2
     int nmat;
     int order, limiter, transverse;
+    T *snap;                  // snapshot store: on a snapshot step the new state is also written to
+    long long snap_stride;    //   snap + snap_index * snap_stride (elements)
 };
 
 // Shallow-water instance (single level).  ETA is the storage type of eta
@@ -62,10 +64,10 @@ constexpr int ST_CFL = 2;
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
-                   int nmat_max, bool full, int rows, int kind, int *status, hipStream_t s);
+                   int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s);
 template <typename T>
 void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, int parity, int adjoint,
-                   int *status, hipStream_t s);
+                   int snap_index, int *status, hipStream_t s);
 
 template <typename ETA, typename T>
 void launch_swe2d(const SweInst<ETA, T> *inst, const SweInst<ETA, T> &h, const Tile *tiles, int ntiles,
