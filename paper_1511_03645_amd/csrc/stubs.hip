@@ -1,10 +1,6 @@
 // Entry points whose implementation is pending in this build.
 #include "wp_ctx.h"
 
-int wp_swe_init(wp_ctx *ctx, const wp_coefficients *) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
-int wp_swe_adj_init(wp_ctx *ctx) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
-int wp_swe_step(wp_ctx *ctx, Level &, double, int, hipStream_t, int) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
-int wp_swe_prepare(wp_ctx *ctx, Level &, double) { return wp_fail(ctx, WP_EINVAL, "shallow water not built"); }
 int wp_fill_coarse_ghosts(wp_ctx *ctx, int, double) { return wp_fail(ctx, WP_EINVAL, "refinement not built"); }
 extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
 {

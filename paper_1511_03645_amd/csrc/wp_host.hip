@@ -140,7 +140,10 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
 {
     const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
     const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, lv);
-    lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, true);
+    if (ctx->is_acoustics)
+        lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, true);
+    else
+        lv.tiles_host = wp_make_tiles(lv.patches, 0, SWE_TY, SWE_TX, true);
     lv.tile_rows = rows;
     wp_classify_tiles(ctx, lv, lv.tiles_host);
     // mixed-material tiles (the slower march) first, so they are dispatched
@@ -591,7 +594,7 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt)
 {
     if (!(dt > 0.0) || !std::isfinite(dt)) return wp_fail(ctx, WP_EINVAL, "dt must be positive");
-    if (ctx->is_acoustics) {
+    if (ctx->is_acoustics || &lv == &ctx->adj) {
         const double nu = ctx->cmax * dt / (ctx->kind2d ? std::min(lv.dx, lv.dy) : lv.dx);
         if (nu > ctx->prob.cfl_max * (1.0 + 1e-12))
             return wp_fail(ctx, WP_ECFL, "Courant number %.6g above %.6g", nu, ctx->prob.cfl_max);

@@ -41,21 +41,37 @@ struct AcouInst {
     long long snap_stride;    //   snap + snap_index * snap_stride (elements)
 };
 
-// Shallow-water instance (single level).  ETA is the storage type of eta
-// (double in the FP64 and mixed paths), T of hu, hv and the bulk arithmetic.
+// Shallow-water instance (single level).  ETA is the storage and arithmetic
+// type of the surface elevation eta = h + B and of the well-balanced term
+// g hbar d(eta) (double in the FP64 and mixed paths); T is the type of hu,
+// hv and of the bulk arithmetic (double for FP64, float for mixed).
 template <typename ETA, typename T>
 struct SweInst {
     ETA *eta[2];
     T *hu[2];
     T *hv[2];
-    const double *B;          // bathymetry (FP64)
-    const T *cbar;            // sqrt(g hbar), hbar = -B, for the adjoint
-    long long cs;
+    const double *B;          // bathymetry cell averages (FP64)
     int nx, ny;
     int bc[4];
-    double nux, nuy;
+    double nux, nuy;          // dt/dx, dt/dy
     double g;
+    double cfl_max;
     int order, limiter, transverse;
+};
+
+// Linearised shallow-water adjoint (time reversed), state (eta, mu, gamma)
+// of type T; cbar = sqrt(g hbar) per cell with hbar = -B.
+template <typename T>
+struct LsweInst {
+    T *q[2];                  // double-buffered, component stride nx*ny
+    const T *cbar;
+    int nx, ny;
+    int bc[4];
+    T nux, nuy;
+    T g;
+    int order, limiter, transverse;
+    T *snap;                  // snapshot store (see AcouInst)
+    long long snap_stride;
 };
 
 // status word bits latched by kernels
@@ -70,11 +86,13 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, in
                    int snap_index, int *status, hipStream_t s);
 
 template <typename ETA, typename T>
-void launch_swe2d(const SweInst<ETA, T> *inst, const SweInst<ETA, T> &h, const Tile *tiles, int ntiles,
-                  int parity, int *status, unsigned *cflbits, hipStream_t s);
-template <typename ETA, typename T>
-void launch_lswe_adj2d(const SweInst<ETA, T> *inst, const SweInst<ETA, T> &h, const Tile *tiles, int ntiles,
-                       int parity, int *status, hipStream_t s);
+void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int parity, int *status,
+                  unsigned *cflbits, hipStream_t s);
+template <typename T>
+void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, int parity, int snap_index,
+                       int *status, hipStream_t s);
+constexpr int SWE_TX = 16;     // output columns of a shallow-water tile
+constexpr int SWE_TY = 8;      // output rows of a shallow-water tile
 
 // Flag: m(x) = max_n |qhat_n(x) . q(x)| over snapshots n_lo..n_hi, bilinear
 // from the adjoint grid (refinement `ratio` relative to it).
