@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-swe", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -214,6 +215,49 @@ def batch_compare(steps, warmup, count=64):
             "ms_fp64_loop": t64 * 1e3, "ms_fp32_batched": t32 * 1e3}
 
 
+def swe_compare(steps, warmup, n=2048):
+    """The shallow-water workload (n x n 1 km cells, abyssal plain rising to
+    a shelf, Gaussian hump, coastal gauge box, 3 h): adjoint run with snapshots
+    + forward run flagged every 10 steps + J, in FP64 and in mixed precision."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import swe2d
+    cfg = swe2d(n=n, seed=3)
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    res = {}
+    for name, prec in (("fp64", wp.FP64), ("mixed", wp.MIXED)):
+        w = wp.from_config(cfg, precision=prec)
+        eta = cfg["q0"][0].astype(np.float64).ravel().view(np.uint8)
+        dtp = np.float64 if prec == wp.FP64 else np.float32
+        rest = [cfg["q0"][k].astype(dtp).ravel().view(np.uint8) for k in (1, 2)]
+        q0 = torch.from_numpy(np.concatenate([eta] + rest)).cuda()
+
+        def job():
+            w.adjoint_run(cfg["functional"], dt, N, every)
+            w.set_state(q0)
+            t = 0.0
+            for _ in range(N // every):
+                w.flag_adjoint(0, cfg["tol"], t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+                w.run_graph(every, dt, 1)
+                t += every * dt
+            return w.functional_value(cfg["functional"], 0)
+        for _ in range(warmup):
+            job()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            J = job()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        res[name] = {"value": 2 * N * n * n / sec, "ms_per_job": sec * 1e3, "J": J}
+        del w
+    res["workload"] = f"swe2d {n}x{n}, {N} forward + {N} adjoint steps, flags every {every}"
+    res["unit"] = "cell-updates/s"
+    res["mixed_speedup"] = res["mixed"]["value"] / res["fp64"]["value"]
+    res["J_rel_err_mixed"] = abs(res["mixed"]["J"] - res["fp64"]["J"]) / abs(res["fp64"]["J"])
+    return res
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: a bounded sample of the same
     workload (full grid, a fixed number of forward and adjoint steps)."""
@@ -286,6 +330,12 @@ def main():
         out["batch"] = batch_compare(max(1, min(args.steps, 3)), 1)
         print(f"[bench] batch speedup {out['batch']['speedup']:.2f}x, J rel err max "
               f"{out['batch']['J_rel_err_max']:.2e}", file=sys.stderr, flush=True)
+    if not args.no_swe:
+        print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
+        out["swe"] = swe_compare(1, 1)
+        print(f"[bench] swe fp64 {out['swe']['fp64']['value'] / 1e9:.2f}, mixed "
+              f"{out['swe']['mixed']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['swe']['J_rel_err_mixed']:.2e}",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)
