@@ -204,16 +204,41 @@ int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, do
                     uint8_t *flags, int on_device, int64_t *nflagged);
 
 /* Replace the patches of level+1 (Sec. 3 regridding).  patches != NULL: the
- * given boxes (level+1 index space; must be disjoint and properly nested in
- * level's patches shrunk by one level cell, except along the physical
- * boundary).  patches == NULL: Berger-Rigoutsos clustering of the current
- * flags of `level` (from the last wp_flag_adjoint on it), after dilating them
- * by `buffer` cells, with efficiency cutoff 0.7 and sides of at most 64
- * level+1 cells.  New fine cells take the old level+1 data where an old patch
- * covered them, else space interpolation from level.  Sets level+1's time to
- * level's. */
+ * npatches given boxes (level+1 index space; corners and sides multiples of
+ * ratio[level]; disjoint; properly nested: every covered level cell lies in
+ * level's patches with all eight neighbours inside the domain also in them,
+ * i.e. level's patches shrunk by one cell except along the physical
+ * boundary).  patches == NULL: the flags of `level` from the last
+ * wp_flag_adjoint on it, restricted to that nesting region, dilated by
+ * `buffer` cells and restricted again, clustered by wp_cluster with
+ * efficiency 0.7, sides of at most max(1, 64 / ratio) and at least
+ * max(1, 8 / ratio) level cells, then refined by the ratio.  Cells of the new
+ * patches keep the old level+1 data where an old patch covered them and are
+ * otherwise interpolated in space from level (minmod-limited linear, Sec. 3).
+ * Sets level+1's time to level's and empties the levels above level+1 (they
+ * are regridded from level+1 next).  WP_EINVAL for a box that breaks the
+ * rules above, WP_ESTATE if patches == NULL and `level` has no flags. */
 int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int npatches, int buffer);
+/* The patches of a level: *npatches receives their number, out (cap
+ * entries, caller-owned) the first min(cap, number) of them. */
 int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int cap, int *npatches);
+
+/* Berger-Rigoutsos clustering (Sec. 3, after Berger & Rigoutsos 1991) of
+ * the flagged cells of an nx x ny image (host memory, [ny][nx] uint8, nonzero
+ * = flagged) into boxes, on the host.  allowed (optional, same layout):
+ * cells a box may hold; flags outside it are ignored.  Rules, fixed so that
+ * the result is unique: shrink a box to the bounding box of its flags (drop
+ * it if none); accept it if the flagged fraction is at least `efficiency`,
+ * both sides are at most maxside and every cell is allowed; else cut it at
+ * the interior zero of the column/row flag counts nearest the centre, else
+ * at the largest sign change of their second difference, else in halves of
+ * the longer side, each part keeping at least minside cells (1 when the box
+ * holds cells that are not allowed), and recurse on the lower/left part
+ * first; a box with no admissible cut is accepted.  *npatches receives the
+ * number of boxes, out (cap entries, caller-owned) the first min(cap, number).
+ * Needs no handle and no device. */
+int wp_cluster(const uint8_t *flags, const uint8_t *allowed, int nx, int ny, double efficiency, int maxside,
+               int minside, wp_patch *out, int cap, int *npatches);
 
 /* J = sum over level-0 cells of phi^T q dx dy (which = 0), or the inner
  * product integral sum qhat_n^T q dx dy with snapshot n (which = 1; eq. J,

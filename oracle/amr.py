@@ -211,6 +211,30 @@ class Hierarchy:
         self.q[l] = new
         self.t[l] += dt
 
+    def regrid(self, l, boxes):
+        """New patches `boxes` for level l+1 (Sec. 3 regridding): cells an old
+        level-(l+1) patch covered keep their values, the others take the space
+        interpolation of level l at its current time; level l+1 takes level
+        l's time and the levels above it are emptied."""
+        f = l + 1
+        nxf, nyf = self.n[f]
+        old = np.zeros((nyf, nxf), dtype=bool)
+        for (i0, j0, w, h) in self.patches[f]:
+            old[j0:j0 + h, i0:i0 + w] = True
+        cells = []
+        for (i0, j0, w, h) in boxes:
+            for J in range(j0, j0 + h):
+                for I in range(i0, i0 + w):
+                    if not old[J, I]:
+                        cells.append((I, J))
+        vals = coarse_to_fine(self.q[l], self.q[l], 0.0, self.ratios[l], cells, self.bc)
+        for (I, J), v in zip(cells, vals):
+            self.q[f][:, J, I] = v
+        self.patches[f] = [tuple(b) for b in boxes]
+        self.t[f] = self.t[l]
+        for g in range(f + 1, self.L):
+            self.patches[g] = []
+
     def advance(self, l, dt):
         """Berger-Oliger recursion from level l (Sec. 3)."""
         self.step_level(l, dt)

@@ -95,6 +95,7 @@ _SIGS = {
     "wp_flag_adjoint": (_I, [_P, _I, _D, _D, _D, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
     "wp_regrid": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, _I]),
     "wp_get_patches": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
+    "wp_cluster": (_I, [_P, _P, _I, _I, _D, _I, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
     "wp_functional_value": (_I, [_P, ctypes.POINTER(wp_functional), _I, _I, ctypes.POINTER(_D)]),
     "wp_get_time": (_I, [_P, _I, ctypes.POINTER(_D)]),
     "wp_set_time": (_I, [_P, _I, _D]),
@@ -164,6 +165,26 @@ def functional_struct(f):
     kinds = {"interval": FUNC_INTERVAL, "box": FUNC_BOX, "disc": FUNC_DISC}
     return wp_functional(kinds[f["kind"]], int(f.get("component", 0)), f.get("x0", 0.0), f.get("x1", 0.0),
                          f.get("y0", 0.0), f.get("y1", 0.0), f.get("cx", 0.0), f.get("cy", 0.0), f.get("r", 0.0))
+
+
+def cluster(flags, allowed=None, efficiency=0.7, maxside=16, minside=2):
+    """Berger-Rigoutsos boxes (ilo, jlo, nx, ny) of a [ny][nx] flag image
+    (``wp_cluster``; host only)."""
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    ny, nx = f.shape
+    a = None if allowed is None else np.ascontiguousarray(allowed, dtype=np.uint8)
+    if a is not None and a.shape != f.shape:
+        raise ValueError("allowed must match flags")
+    n = ctypes.c_int()
+    args = (f.ctypes.data, None if a is None else a.ctypes.data, nx, ny, float(efficiency), int(maxside), int(minside))
+    rc = lib().wp_cluster(*args, None, 0, ctypes.byref(n))
+    if rc != WP_OK:
+        raise WPError(rc, "wp_cluster: invalid arguments")
+    arr = (wp_patch * max(1, n.value))()
+    rc = lib().wp_cluster(*args, arr, n.value, ctypes.byref(n))
+    if rc != WP_OK:
+        raise WPError(rc, "wp_cluster: invalid arguments")
+    return [(p.ilo, p.jlo, p.nx, p.ny) for p in arr[:n.value]]
 
 
 def _ptr(a):

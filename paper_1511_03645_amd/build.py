@@ -5,6 +5,7 @@
 Every HIP source under csrc/ is compiled with hipcc into one shared library
 next to this file.  Packed FP32 instructions are disabled for all device code.
 """
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -20,22 +21,29 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
 
 
-def build(verbose=False):
+def _compile(hipcc, src, verbose):
+    obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+           *lang, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    return obj, cmd, r.returncode, err
+
+
+def build(verbose=False, jobs=None):
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-    objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in sources():
-        obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-               *lang, "-c", src, "-o", obj]
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda s: _compile(hipcc, s, verbose), sources()))
+    objs = []
+    for src, (obj, cmd, rc, err) in zip(sources(), results):
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
-        if r.returncode != 0:
+        if rc != 0:
             sys.stderr.write(err + "\n")
             raise RuntimeError(f"hipcc failed on {src}")
         if err.strip() and verbose:

@@ -1,0 +1,134 @@
+// Coarse/fine transfer kernels of the block-structured refinement (Davis &
+// LeVeque Sec. 3): ghost cells of a fine level filled from the level below,
+// interpolated in space (minmod-limited linear slopes per direction, the
+// physical boundary by the boundary rule) and in time (linear between the two
+// coarse times), and fine-to-coarse averaging of covered coarse cells.
+#include "wp_internal.h"
+
+namespace wp {
+namespace {
+
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ int resolve1(int i, int n, int bclo, int bchi, bool &flip)
+{
+    i = min(max(i, -2), n + 1);
+    flip = false;
+    if (i < 0) {
+        if (bclo == WP_BC_PERIODIC) return i + n;
+        if (bclo == WP_BC_WALL) { flip = true; return -1 - i; }
+        return 0;
+    }
+    if (i >= n) {
+        if (bchi == WP_BC_PERIODIC) return i - n;
+        if (bchi == WP_BC_WALL) { flip = true; return 2 * n - 1 - i; }
+        return n - 1;
+    }
+    return i;
+}
+
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b)
+{
+    if (a * b <= T(0)) return T(0);
+    return copysign(fmin(fabs(a), fabs(b)), a);
+}
+
+template <typename T>
+__device__ __forceinline__ T cval(const T *C, int k, int i, int j, int NX, int NY, const int *bc, long long cs)
+{
+    bool fi, fj;
+    const int ri = resolve1(i, NX, bc[0], bc[1], fi);
+    const int rj = resolve1(j, NY, bc[2], bc[3], fj);
+    T v = C[k * cs + (long long)rj * NX + ri];
+    if ((fi && k == 1) || (fj && k == 2)) v = -v;
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T space(const T *C, int k, int ic, int jc, T xi, T eta, int NX, int NY, const int *bc,
+                                   long long cs)
+{
+    const T c0 = C[k * cs + (long long)jc * NX + ic];
+    const T sx = minmod(cval(C, k, ic + 1, jc, NX, NY, bc, cs) - c0, c0 - cval(C, k, ic - 1, jc, NX, NY, bc, cs));
+    const T sy = minmod(cval(C, k, ic, jc + 1, NX, NY, bc, cs) - c0, c0 - cval(C, k, ic, jc - 1, NX, NY, bc, cs));
+    return (c0 + xi * sx) + eta * sy;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ring_fill_kernel(const int *__restrict__ cells, long long ncells,
+                                                        T *__restrict__ fine, int nxf, const T *__restrict__ cold,
+                                                        const T *__restrict__ cnew, int NX, int NY, int r, T alpha,
+                                                        int bc0, int bc1, int bc2, int bc3)
+{
+    const int bc[4] = {bc0, bc1, bc2, bc3};
+    const long long csf = (long long)nxf * (NY * r);
+    const long long csc = (long long)NX * NY;
+    for (long long n = blockIdx.x * 256LL + threadIdx.x; n < ncells; n += (long long)gridDim.x * 256) {
+        const int lin = cells[n];
+        const int I = lin % nxf, J = lin / nxf;
+        const int ic = I / r, jc = J / r;
+        const T xi = (T((I % r)) + T(0.5)) / T(r) - T(0.5);
+        const T eta = (T((J % r)) + T(0.5)) / T(r) - T(0.5);
+        for (int k = 0; k < 3; ++k) {
+            const T a = space(cold, k, ic, jc, xi, eta, NX, NY, bc, csc);
+            const T b = space(cnew, k, ic, jc, xi, eta, NX, NY, bc, csc);
+            fine[k * csf + lin] = (T(1) - alpha) * a + alpha * b;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ cells, long long ncells,
+                                                      const T *__restrict__ fine, int nxf, long long csf,
+                                                      T *__restrict__ coarse, int NX, long long csc, int r)
+{
+    const T inv = T(1) / T(r * r);   // exact for the power-of-two ratios
+    for (long long n = blockIdx.x * 256LL + threadIdx.x; n < ncells; n += (long long)gridDim.x * 256) {
+        const int lin = cells[n];
+        const int ic = lin % NX, jc = lin / NX;
+        for (int k = 0; k < 3; ++k) {
+            T s = T(0);
+            for (int jj = 0; jj < r; ++jj)
+                for (int ii = 0; ii < r; ++ii) s += fine[k * csf + (long long)(r * jc + jj) * nxf + (r * ic + ii)];
+            coarse[k * csc + lin] = s * inv;
+        }
+    }
+}
+
+unsigned grid_for(long long n)
+{
+    long long b = (n + 255) / 256;
+    return (unsigned)std::min<long long>(std::max<long long>(b, 1), 8192);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, const T *cold, const T *cnew, int NX,
+                      int NY, int r, double alpha, const int *bc, hipStream_t s)
+{
+    if (ncells <= 0) return;
+    hipLaunchKernelGGL((ring_fill_kernel<T>), dim3(grid_for(ncells)), dim3(256), 0, s, cells, ncells, fine, nxf, cold,
+                       cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3]);
+}
+
+template <typename T>
+void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
+                    long long csc, int r, hipStream_t s)
+{
+    if (ncells <= 0) return;
+    hipLaunchKernelGGL((average_kernel<T>), dim3(grid_for(ncells)), dim3(256), 0, s, cells, ncells, fine, nxf, csf,
+                       coarse, NX, csc, r);
+}
+
+template void launch_ring_fill<double>(const int *, long long, double *, int, const double *, const double *, int,
+                                       int, int, double, const int *, hipStream_t);
+template void launch_ring_fill<float>(const int *, long long, float *, int, const float *, const float *, int, int,
+                                      int, double, const int *, hipStream_t);
+template void launch_average<double>(const int *, long long, const double *, int, long long, double *, int,
+                                     long long, int, hipStream_t);
+template void launch_average<float>(const int *, long long, const float *, int, long long, float *, int, long long,
+                                    int, hipStream_t);
+
+}  // namespace wp

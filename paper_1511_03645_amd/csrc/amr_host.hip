@@ -1,0 +1,265 @@
+// Refinement hierarchy on the host side (Davis & LeVeque Sec. 3): regridding
+// of a level's children (given boxes or Berger-Rigoutsos clusters of its
+// flags), the ghost ring of a fine level from the level below with space-time
+// interpolation, the Berger-Oliger recursion and the fine-to-coarse average.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "wp_ctx.h"
+
+using namespace wp;
+
+namespace {
+
+// Cells inside the level's domain, within two cells (box halo) of a patch and
+// inside none, as linear indices j * nx + i in increasing order.
+std::vector<int> ring_list(const std::vector<wp_patch> &P, int nx, int ny)
+{
+    std::vector<uint8_t> m((size_t)nx * ny, 0);   // 1 inside a patch, 2 ring
+    for (const wp_patch &p : P)
+        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&m[(size_t)j * nx + p.ilo], p.nx, (uint8_t)1);
+    for (const wp_patch &p : P)
+        for (int j = std::max(p.jlo - 2, 0); j < std::min(p.jlo + p.ny + 2, ny); ++j)
+            for (int i = std::max(p.ilo - 2, 0); i < std::min(p.ilo + p.nx + 2, nx); ++i)
+                if (m[(size_t)j * nx + i] == 0) m[(size_t)j * nx + i] = 2;
+    std::vector<int> out;
+    for (const wp_patch &p : P)   // gather from the halos only, then order
+        for (int j = std::max(p.jlo - 2, 0); j < std::min(p.jlo + p.ny + 2, ny); ++j)
+            for (int i = std::max(p.ilo - 2, 0); i < std::min(p.ilo + p.nx + 2, nx); ++i)
+                if (m[(size_t)j * nx + i] == 2) {
+                    m[(size_t)j * nx + i] = 3;
+                    out.push_back(j * nx + i);
+                }
+    std::sort(out.begin(), out.end());
+    return out;
+}
+
+// Coarse cells (linear indices on a canvas NX wide) covered by ratio-aligned
+// fine patches.
+std::vector<int> cover_list(const std::vector<wp_patch> &P, int r, int NX)
+{
+    std::vector<int> out;
+    for (const wp_patch &p : P)
+        for (int jc = p.jlo / r; jc < (p.jlo + p.ny) / r; ++jc)
+            for (int ic = p.ilo / r; ic < (p.ilo + p.nx) / r; ++ic) out.push_back(jc * NX + ic);
+    std::sort(out.begin(), out.end());
+    return out;
+}
+
+int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n, const char *what)
+{
+    if (dev) wp_dfree(ctx, dev);
+    dev = nullptr;
+    n = (long long)v.size();
+    if (v.empty()) return WP_OK;
+    dev = (int *)wp_dalloc(ctx, v.size() * sizeof(int));
+    if (!dev) return wp_fail(ctx, WP_ENOMEM, "%s list", what);
+    if (hipMemcpy(dev, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "%s upload", what);
+    return WP_OK;
+}
+
+// Fine cells `cells` of level l from level l-1 at time weight alpha between
+// the canvas before its last step (cold) and its current one (cnew).
+int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double alpha, bool use_old)
+{
+    Level &F = ctx->L[l], &C = ctx->L[l - 1];
+    const void *cnew = C.q[C.cur];
+    const void *cold = use_old ? C.q[C.cur ^ 1] : cnew;
+    if (ctx->esz == 8)
+        launch_ring_fill<double>(cells, n, (double *)F.q[F.cur], F.nx, (const double *)cold, (const double *)cnew,
+                                 C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, ctx->stream);
+    else
+        launch_ring_fill<float>(cells, n, (float *)F.q[F.cur], F.nx, (const float *)cold, (const float *)cnew, C.nx,
+                                C.ny, F.ratio, alpha, ctx->prob.bc, ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "coarse-to-fine launch: %s", hipGetErrorString(e));
+    return WP_OK;
+}
+
+int fill_ring(wp_ctx *ctx, int l, double alpha)
+{
+    Level &F = ctx->L[l];
+    if (F.nring == 0) return WP_OK;
+    return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, ctx->L[l - 1].prev_valid);
+}
+
+int average_down(wp_ctx *ctx, int l)
+{
+    Level &F = ctx->L[l], &C = ctx->L[l - 1];
+    if (F.ncover == 0) return WP_OK;
+    const long long csf = (long long)F.nx * F.ny, csc = (long long)C.nx * C.ny;
+    if (ctx->esz == 8)
+        launch_average<double>(F.cover_dev, F.ncover, (const double *)F.q[F.cur], F.nx, csf, (double *)C.q[C.cur],
+                               C.nx, csc, F.ratio, ctx->stream);
+    else
+        launch_average<float>(F.cover_dev, F.ncover, (const float *)F.q[F.cur], F.nx, csf, (float *)C.q[C.cur], C.nx,
+                              csc, F.ratio, ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "average launch: %s", hipGetErrorString(e));
+    return WP_OK;
+}
+
+// One Berger-Oliger step of level l and, recursively, its finer levels.
+// sub: index of this step among the ratio steps of level l within one step
+// of level l-1 (time weight sub / ratio for the ghost ring).
+int bo_advance(wp_ctx *ctx, int l, double dt, int sub)
+{
+    Level &lv = ctx->L[l];
+    int rc;
+    if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
+    if (lv.patches.empty()) {
+        lv.t += dt;
+        return WP_OK;
+    }
+    if (l > 0 && (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio)) != WP_OK) return rc;
+    if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream, -1)) != WP_OK) return rc;
+    lv.t_prev = lv.t;
+    lv.prev_valid = true;
+    lv.t += dt;
+    if (l + 1 < (int)ctx->L.size() && !ctx->L[l + 1].patches.empty()) {
+        const int r = ctx->L[l + 1].ratio;
+        // this level's ring at its new time, read by the finer level's
+        // interpolation next to the ring
+        if (l > 0 && (rc = fill_ring(ctx, l, (double)(sub + 1) / (double)lv.ratio)) != WP_OK) return rc;
+        for (int k = 0; k < r; ++k)
+            if ((rc = bo_advance(ctx, l + 1, dt / r, k)) != WP_OK) return rc;
+        if ((rc = average_down(ctx, l + 1)) != WP_OK) return rc;
+    }
+    return WP_OK;
+}
+
+// Replace the patches of level f (> 0) with `boxes` (validated).
+int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
+{
+    Level &F = ctx->L[f], &C = ctx->L[f - 1];
+    int rc;
+    // new cells outside every old patch: space interpolation from the level
+    // below at its current time
+    std::vector<uint8_t> old((size_t)F.nx * F.ny, 0);
+    for (const wp_patch &p : F.patches)
+        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&old[(size_t)j * F.nx + p.ilo], p.nx, (uint8_t)1);
+    std::vector<int> fresh;
+    for (const wp_patch &p : boxes)
+        for (int j = p.jlo; j < p.jlo + p.ny; ++j)
+            for (int i = p.ilo; i < p.ilo + p.nx; ++i)
+                if (!old[(size_t)j * F.nx + i]) fresh.push_back(j * F.nx + i);
+    if (!fresh.empty()) {
+        int *dev = nullptr;
+        long long n = 0;
+        if ((rc = upload_ints(ctx, fresh, dev, n, "new cell")) != WP_OK) return rc;
+        rc = fill_from_coarse(ctx, f, dev, n, 0.0, false);
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == WP_OK)
+            rc = wp_fail(ctx, WP_EDEVICE, "regrid sync");
+        wp_dfree(ctx, dev);
+        if (rc != WP_OK) return rc;
+    }
+    F.patches = boxes;
+    if ((rc = wp_upload_tiles(ctx, F)) != WP_OK) return rc;
+    if ((rc = upload_ints(ctx, ring_list(F.patches, F.nx, F.ny), F.ring_dev, F.nring, "ring")) != WP_OK) return rc;
+    if ((rc = upload_ints(ctx, cover_list(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, "cover")) != WP_OK)
+        return rc;
+    F.t = C.t;
+    F.prev_valid = false;
+    F.flags_valid = false;
+    // finer levels are emptied: they are regridded from this one next
+    for (size_t l = f + 1; l < ctx->L.size(); ++l) {
+        Level &G = ctx->L[l];
+        if (G.patches.empty()) continue;
+        G.patches.clear();
+        if ((rc = wp_upload_tiles(ctx, G)) != WP_OK) return rc;
+        if ((rc = upload_ints(ctx, {}, G.ring_dev, G.nring, "ring")) != WP_OK) return rc;
+        if ((rc = upload_ints(ctx, {}, G.cover_dev, G.ncover, "cover")) != WP_OK) return rc;
+        G.prev_valid = false;
+        G.flags_valid = false;
+    }
+    return WP_OK;
+}
+
+}  // namespace
+
+// Ghost ring of `level` from the level below at time t: linear time weight
+// between the times of the two canvases of the level below (its current one
+// alone when it has not stepped since its state was set).
+int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t)
+{
+    const Level &C = ctx->L[level - 1];
+    double alpha = 1.0;
+    if (C.prev_valid && C.t > C.t_prev) alpha = std::min(std::max((t - C.t_prev) / (C.t - C.t_prev), 0.0), 1.0);
+    return fill_ring(ctx, level, alpha);
+}
+
+extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
+{
+    if (!ctx) return WP_EINVAL;
+    if (nsteps < 0) return wp_fail(ctx, WP_EINVAL, "nsteps must be non-negative");
+    int rc;
+    if ((rc = wp_courant_check(ctx, ctx->L[0], dt0)) != WP_OK) return rc;
+    for (int s = 0; s < nsteps; ++s)
+        if ((rc = bo_advance(ctx, 0, dt0, 0)) != WP_OK) return rc;
+    return WP_OK;
+}
+
+extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int npatches, int buffer)
+{
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level + 1 >= (int)ctx->L.size())
+        return wp_fail(ctx, WP_EINVAL, "level %d has no finer level", level);
+    Level &C = ctx->L[level], &F = ctx->L[level + 1];
+    const int r = F.ratio;
+    std::vector<uint8_t> allowed;
+    wp_nesting_mask(C.patches, C.nx, C.ny, allowed);
+    std::vector<wp_patch> boxes;
+    if (patches) {
+        if (npatches < 0) return wp_fail(ctx, WP_EINVAL, "npatches must be non-negative");
+        std::vector<uint8_t> used((size_t)C.nx * C.ny, 0);
+        for (int k = 0; k < npatches; ++k) {
+            const wp_patch p = patches[k];
+            if (p.nx < 1 || p.ny < 1 || p.ilo < 0 || p.jlo < 0 || p.ilo + p.nx > F.nx || p.jlo + p.ny > F.ny)
+                return wp_fail(ctx, WP_EINVAL, "patch %d outside level %d", k, level + 1);
+            if (p.ilo % r || p.jlo % r || p.nx % r || p.ny % r)
+                return wp_fail(ctx, WP_EINVAL, "patch %d not aligned to the refinement ratio %d", k, r);
+            for (int jc = p.jlo / r; jc < (p.jlo + p.ny) / r; ++jc)
+                for (int ic = p.ilo / r; ic < (p.ilo + p.nx) / r; ++ic) {
+                    uint8_t &u = used[(size_t)jc * C.nx + ic];
+                    if (u) return wp_fail(ctx, WP_EINVAL, "patch %d overlaps another", k);
+                    if (!allowed[(size_t)jc * C.nx + ic])
+                        return wp_fail(ctx, WP_EINVAL, "patch %d not properly nested in level %d", k, level);
+                    u = 1;
+                }
+            boxes.push_back(p);
+        }
+    } else {
+        if (buffer < 0) return wp_fail(ctx, WP_EINVAL, "buffer must be non-negative");
+        if (!C.flags_valid) return wp_fail(ctx, WP_ESTATE, "level %d has no flags (flag it first)", level);
+        std::vector<uint8_t> fl((size_t)C.nx * C.ny);
+        if (hipMemcpyAsync(fl.data(), C.flags, fl.size(), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "flag read");
+        for (size_t k = 0; k < fl.size(); ++k) fl[k] = (fl[k] && allowed[k]) ? 1 : 0;
+        std::vector<uint8_t> dil;
+        wp_dilate(fl, C.nx, C.ny, buffer, dil);
+        for (size_t k = 0; k < dil.size(); ++k) dil[k] = (dil[k] && allowed[k]) ? 1 : 0;
+        // first pass sizes the output
+        int n = 0;
+        int rc = wp_cluster(dil.data(), allowed.data(), C.nx, C.ny, 0.7, std::max(1, 64 / r), std::max(1, 8 / r),
+                            nullptr, 0, &n);
+        if (rc != WP_OK) return wp_fail(ctx, rc, "clustering failed");
+        boxes.resize(n);
+        rc = wp_cluster(dil.data(), allowed.data(), C.nx, C.ny, 0.7, std::max(1, 64 / r), std::max(1, 8 / r),
+                        boxes.data(), n, &n);
+        if (rc != WP_OK) return wp_fail(ctx, rc, "clustering failed");
+        for (wp_patch &p : boxes) p = wp_patch{p.ilo * r, p.jlo * r, p.nx * r, p.ny * r};
+    }
+    return install(ctx, level + 1, boxes);
+}
+
+extern "C" int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int cap, int *np)
+{
+    if (!ctx || level < 0 || level >= (int)ctx->L.size() || (cap > 0 && !out)) return WP_EINVAL;
+    const auto &p = ctx->L[level].patches;
+    if (np) *np = (int)p.size();
+    for (int k = 0; k < (int)p.size() && k < cap; ++k) out[k] = p[k];
+    return WP_OK;
+}

@@ -34,12 +34,17 @@ struct Level {
     void *snap_base = nullptr;           // snapshot store written by this level's steps (adjoint)
     void *inst_snap = nullptr;
     alignas(16) unsigned char inst_host[256];
-    // AMR: cells of the ghost ring (inside the domain, outside every patch,
-    // within two cells of one) filled from the level below before each step
+    // the other canvas holds the state at t_prev after a step
+    double t_prev = 0.0;
+    bool prev_valid = false;
+    // refinement: cells of the ghost ring (inside the domain, outside every
+    // patch, within two cells of one), filled from the level below before
+    // each step; coarse cells covered by the patches (linear indices on the
+    // level below), overwritten by the average of their children
     int *ring_dev = nullptr;
     long long nring = 0;
-    void *coarse_old = nullptr;          // level below at the start of its step
-    double t_coarse_old = 0.0, t_coarse_new = 0.0;
+    int *cover_dev = nullptr;
+    long long ncover = 0;
 };
 
 struct wp_ctx {
@@ -124,5 +129,7 @@ int wp_swe_prepare(wp_ctx *ctx, Level &lv, double dt);
 int wp_graph_begin(wp_ctx *ctx, hipStream_t &s);
 int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec);
 int wp_graph_launch(wp_ctx *ctx, hipGraphExec_t exec);
-// refinement (amr_host.hip)
+// refinement (amr_host.hip, cluster.cpp)
 int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t);
+void wp_nesting_mask(const std::vector<wp_patch> &patches, int nx, int ny, std::vector<uint8_t> &mask);
+void wp_dilate(const std::vector<uint8_t> &f, int nx, int ny, int k, std::vector<uint8_t> &out);

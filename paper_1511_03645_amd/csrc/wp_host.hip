@@ -172,7 +172,8 @@ int wp_default_rows(const wp_ctx *ctx, const Level &lv)
     (void)ctx;
     // enough strips to give every SIMD several waves on small grids, long
     // marches (little halo re-read) on large ones
-    const long long cells = (long long)lv.nx * lv.ny;
+    long long cells = 0;   // cells the level's patches hold
+    for (const wp_patch &p : lv.patches) cells += (long long)p.nx * p.ny;
     if (cells <= (1LL << 18)) return 4;
     if (cells <= (1LL << 21)) return 8;
     return 16;
@@ -315,9 +316,17 @@ extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef,
     if (G.num_levels < 1 || G.num_levels > WP_MAX_LEVELS) return bail(wp_fail(ctx, WP_EINVAL, "num_levels out of range"));
     if (G.num_levels > 1 && P.kind != WP_ACOUSTICS_2D)
         return bail(wp_fail(ctx, WP_EINVAL, "refinement levels are supported for 2D acoustics"));
-    for (int l = 0; l + 1 < G.num_levels; ++l)
+    long long cells_l = (long long)G.nx0 * (ctx->kind2d ? G.ny0 : 1);
+    for (int l = 0; l + 1 < G.num_levels; ++l) {
         if (G.ratio[l] < 2 || G.ratio[l] > 8 || (G.ratio[l] & (G.ratio[l] - 1)))
             return bail(wp_fail(ctx, WP_EINVAL, "refinement ratios must be 2, 4 or 8"));
+        cells_l *= (long long)G.ratio[l] * G.ratio[l];
+    }
+    if (cells_l >= (1LL << 31)) return bail(wp_fail(ctx, WP_EINVAL, "finest level canvas above 2^31 cells"));
+    if (G.num_levels > 1)
+        for (int k = 0; k < 4; ++k)
+            if (P.bc[k] == WP_BC_PERIODIC)
+                return bail(wp_fail(ctx, WP_EINVAL, "refinement levels need extrapolation or wall boundaries"));
     if (ctx->is_acoustics) {
         if (!coef->rho || !coef->K) return bail(wp_fail(ctx, WP_EINVAL, "acoustics needs rho and K"));
         if ((rc = build_materials(ctx, coef)) != WP_OK) return bail(rc);
@@ -464,6 +473,7 @@ extern "C" int wp_set_state(wp_ctx *ctx, int level, int patch, const void *src, 
     if (!ctx || !src) return ctx ? wp_fail(ctx, WP_EINVAL, "null source") : WP_EINVAL;
     int i0, j0, w, h, rc;
     if ((rc = box_of(ctx, level, patch, i0, j0, w, h)) != WP_OK) return rc;
+    ctx->L[level].prev_valid = false;   // the other canvas no longer precedes this state
     return copy_box(ctx, ctx->L[level], i0, j0, w, h, const_cast<void *>(src), on_device, true);
 }
 
@@ -510,6 +520,7 @@ extern "C" int wp_set_time(wp_ctx *ctx, int level, double t)
 {
     if (!ctx || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
     ctx->L[level].t = t;
+    ctx->L[level].prev_valid = false;
     return WP_OK;
 }
 
@@ -696,10 +707,14 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
             // graph captured for that parity
             lv.cur ^= 1;
             lv.t += nsteps * dt;
+            lv.t_prev = lv.t - dt;
+            lv.prev_valid = true;
             if (r + 1 < replays) return wp_run_graph(ctx, nsteps, dt, replays - r - 1);
             return WP_OK;
         }
         lv.t += nsteps * dt;
+        lv.t_prev = lv.t - dt;
+        lv.prev_valid = true;
     }
     return WP_OK;
 }
@@ -717,6 +732,8 @@ extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
     }
     if (level > 0 && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK) return rc;
     if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream, -1)) != WP_OK) return rc;
+    lv.t_prev = lv.t;
+    lv.prev_valid = true;
     lv.t += dt;
     return WP_OK;
 }

@@ -118,4 +118,14 @@ void launch_sum_dot_mixed(const double *eta, const float *hu, const float *hv, l
 
 void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s);
 
+// Refinement transfers: fill fine cells (linear indices into the fine canvas)
+// from the coarse level at two times (time weight alpha), and average fine
+// children onto covered coarse cells (linear coarse indices).
+template <typename T>
+void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, const T *cold, const T *cnew, int NX,
+                      int NY, int r, double alpha, const int *bc, hipStream_t s);
+template <typename T>
+void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
+                    long long csc, int r, hipStream_t s);
+
 }  // namespace wp

@@ -54,6 +54,32 @@ def test_average_down_inverts_prolongation():
     assert np.all(o2 == 1.75)
 
 
+def test_regrid_keeps_old_fine_data_and_interpolates_new_cells():
+    """Regridding: cells an old patch covered keep their data; new cells take
+    the coarse field's linear reconstruction (exact for a linear field away
+    from the boundary); levels above are emptied."""
+    n, r = 10, 2
+    cfg = _cfg(n, seed=1)
+    H = amr.Hierarchy(cfg, [r, r], [[(4, 4, 6, 6)], [(10, 10, 2, 2)]])
+    X, Y = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5)
+    H.set_level(0, np.stack([1.0 + 0.5 * X - 0.25 * Y, 2.0 * Y, X + Y]))
+    marker = np.full((3, n * r, n * r), 7.0)
+    H.set_level(1, marker)
+    H.t[0] = 0.375
+    H.regrid(0, [(4, 4, 4, 4), (8, 4, 6, 8)])
+    assert H.patches[1] == [(4, 4, 4, 4), (8, 4, 6, 8)] and H.patches[2] == [] and H.t[1] == 0.375
+    for J in range(4, 12):
+        for I in range(4, 14):
+            inside_new = (I < 8 and J < 8) or (8 <= I < 14)
+            if not inside_new:
+                continue
+            if 4 <= I < 10 and 4 <= J < 10:
+                assert np.all(H.q[1][:, J, I] == 7.0)
+            else:
+                x, y = (I + 0.5) / r, (J + 0.5) / r
+                assert np.allclose(H.q[1][:, J, I], [1.0 + 0.5 * x - 0.25 * y, 2.0 * y, x + y], atol=1e-14)
+
+
 def _cfg(n, seed=0):
     from wp_synth import random_media
     rho, K = random_media(n, n, seed=seed)

@@ -151,11 +151,11 @@ def _split_length(L, rng, lo=8, hi=64):
     return out
 
 
-def _jittered_boxes(i0, j0, Lx, Ly, rng):
+def _jittered_boxes(i0, j0, Lx, Ly, rng, lo=8, hi=64):
     boxes, y = [], j0
-    for h in _split_length(Ly, rng):
+    for h in _split_length(Ly, rng, lo, hi):
         x = i0
-        for w in _split_length(Lx, rng):
+        for w in _split_length(Lx, rng, lo, hi):
             boxes.append((x, y, w, h))
             x += w
         y += h
@@ -163,23 +163,26 @@ def _jittered_boxes(i0, j0, Lx, Ly, rng):
 
 
 def amr_hierarchy(n0=256, ratios=(4, 4), n_l2=400, n_l3=1600, seed=2):
-    """Properly nested synthetic patch layout: level 1 is one n0 x n0 patch;
-    level 2 holds `n_l2` disjoint boxes of seeded sides 8..64 (in level-2
-    cells); level 3 holds up to `n_l3` disjoint boxes of sides 8..64, each inside
+    """Properly nested, ratio-aligned synthetic patch layout: level 1 is one
+    n0 x n0 patch; level 2 holds `n_l2` disjoint boxes of seeded sides 8..64
+    level-2 cells (multiples of ratios[0]); level 3 holds up to `n_l3` disjoint
+    boxes of sides 8..64 level-3 cells (multiples of ratios[1]), each inside
     one level-2 box shrunk by one level-2 cell.  Boxes are (ilo, jlo, nx, ny)
-    in their own level's index space."""
+    in their own level's index space.  The boxes are drawn on the level below
+    (in its cells) and refined, so every corner and side is a multiple of the
+    ratio."""
     rng = np.random.default_rng(seed)
     r1, r2 = ratios
-    n1 = n0 * r1
-    cand = _jittered_boxes(0, 0, n1, n1, rng)
+    cand = [(i * r1, j * r1, w * r1, h * r1)
+            for (i, j, w, h) in _jittered_boxes(0, 0, n0, n0, rng, max(1, 8 // r1), 64 // r1)]
     keep = rng.permutation(len(cand))[:n_l2]
     l2 = [cand[k] for k in sorted(keep)]
+    lo3 = max(1, 8 // r2)
     l3_cand = []
     for (i, j, w, h) in l2:
-        lo_i, lo_j = (i + 1) * r2, (j + 1) * r2
-        Lx, Ly = (w - 2) * r2, (h - 2) * r2
-        if Lx >= 8 and Ly >= 8:
-            l3_cand += _jittered_boxes(lo_i, lo_j, Lx, Ly, rng)
+        if w - 2 >= lo3 and h - 2 >= lo3:
+            l3_cand += [(a * r2, b * r2, c * r2, d * r2)
+                        for (a, b, c, d) in _jittered_boxes(i + 1, j + 1, w - 2, h - 2, rng, lo3, 64 // r2)]
     keep3 = rng.permutation(len(l3_cand))[:n_l3]
     l3 = [l3_cand[k] for k in sorted(keep3)]
     return dict(levels=[[(0, 0, n0, n0)], l2, l3], ratios=list(ratios), n0=n0)
