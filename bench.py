@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-swe", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -258,6 +259,65 @@ def swe_compare(steps, warmup, n=2048):
     return res
 
 
+def amr_compare(steps, warmup):
+    """The 3-level AMR workload (coarse grid 256^2, refinement ratios 4, 4,
+    seeded ratio-aligned patches of sides 8..64: 400 on level 1, 1600 on
+    level 2): adjoint run on the coarse grid with snapshots, then the forward
+    run in Berger-Oliger steps (each pair of coarse steps one captured graph,
+    every patch of a level in one launch per substep) with adjoint flags on
+    every level every 10 coarse steps, then J; FP64 and FP32.  Cell updates
+    count every level's patch cells once per substep."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import acoustics2d_amr
+    cfg = acoustics2d_amr(n0=256, seed=2)
+    h = cfg["hierarchy"]
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    ratios = h["ratios"]
+    cells = [sum(b[2] * b[3] for b in lv) for lv in h["levels"]]
+    per_coarse = cells[0] + ratios[0] * cells[1] + ratios[0] * ratios[1] * cells[2]
+    res = {"workload": f"acoustics2d 3 levels, coarse {cfg['nx']}x{cfg['ny']}, ratios {ratios[0]},{ratios[1]}, "
+                       f"{len(h['levels'][1])} + {len(h['levels'][2])} patches ({cells[1]} + {cells[2]} cells), "
+                       f"{N} coarse steps, flags every {every}, tol {cfg['tol']}",
+           "unit": "cell-updates/s", "patches": [len(lv) for lv in h["levels"]], "cells": cells}
+    for name, prec in (("fp64", wp.FP64), ("fp32", wp.FP32)):
+        w = wp.from_config(cfg, precision=prec, num_levels=3, ratios=tuple(ratios))
+        w.set_state(cfg["q0"])
+        w.regrid(0, h["levels"][1])
+        w.regrid(1, h["levels"][2])
+        init = [w.get_state(level=l) for l in range(3)]
+        dtp = np.float64 if prec == wp.FP64 else np.float32
+        dev = [torch.from_numpy(np.concatenate([q[k].astype(dtp).ravel().view(np.uint8) for k in range(3)])).cuda()
+               for q in init]
+
+        def job():
+            w.adjoint_run(cfg["functional"], dt, N, every)
+            for l in range(3):
+                w.set_state(dev[l], level=l)
+                w.set_time(0.0, level=l)
+            t = 0.0
+            for _ in range(N // every):
+                for l in range(3):
+                    w.flag_adjoint(l, cfg["tol"], t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+                w.advance(every, dt)
+                t += every * dt
+            return w.functional_value(cfg["functional"], 0)
+        for _ in range(warmup):
+            job()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            J = job()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        ups = N * (per_coarse + cells[0])     # forward hierarchy + adjoint on the coarse grid
+        res[name] = {"value": ups / sec, "ms_per_job": sec * 1e3, "J": J}
+        del w
+    res["fp32_speedup"] = res["fp32"]["value"] / res["fp64"]["value"]
+    res["J_rel_err_fp32"] = abs(res["fp32"]["J"] - res["fp64"]["J"]) / abs(res["fp64"]["J"])
+    return res
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: a bounded sample of the same
     workload (full grid, a fixed number of forward and adjoint steps)."""
@@ -330,6 +390,12 @@ def main():
         out["batch"] = batch_compare(max(1, min(args.steps, 3)), 1)
         print(f"[bench] batch speedup {out['batch']['speedup']:.2f}x, J rel err max "
               f"{out['batch']['J_rel_err_max']:.2e}", file=sys.stderr, flush=True)
+    if not args.no_amr:
+        print("[bench] 3-level AMR: FP64 and FP32", file=sys.stderr, flush=True)
+        out["amr"] = amr_compare(max(1, min(args.steps, 3)), 1)
+        print(f"[bench] amr fp64 {out['amr']['fp64']['value'] / 1e9:.2f}, fp32 "
+              f"{out['amr']['fp32']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['amr']['J_rel_err_fp32']:.2e}",
+              file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
         out["swe"] = swe_compare(1, 1)

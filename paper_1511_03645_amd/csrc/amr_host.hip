@@ -62,49 +62,51 @@ int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n,
 
 // Fine cells `cells` of level l from level l-1 at time weight alpha between
 // the canvas before its last step (cold) and its current one (cnew).
-int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double alpha, bool use_old)
+int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double alpha, bool use_old, hipStream_t s)
 {
     Level &F = ctx->L[l], &C = ctx->L[l - 1];
     const void *cnew = C.q[C.cur];
     const void *cold = use_old ? C.q[C.cur ^ 1] : cnew;
     if (ctx->esz == 8)
         launch_ring_fill<double>(cells, n, (double *)F.q[F.cur], F.nx, (const double *)cold, (const double *)cnew,
-                                 C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, ctx->stream);
+                                 C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
     else
         launch_ring_fill<float>(cells, n, (float *)F.q[F.cur], F.nx, (const float *)cold, (const float *)cnew, C.nx,
-                                C.ny, F.ratio, alpha, ctx->prob.bc, ctx->stream);
+                                C.ny, F.ratio, alpha, ctx->prob.bc, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "coarse-to-fine launch: %s", hipGetErrorString(e));
     return WP_OK;
 }
 
-int fill_ring(wp_ctx *ctx, int l, double alpha)
+int fill_ring(wp_ctx *ctx, int l, double alpha, hipStream_t s)
 {
     Level &F = ctx->L[l];
     if (F.nring == 0) return WP_OK;
-    return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, ctx->L[l - 1].prev_valid);
+    return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, ctx->L[l - 1].prev_valid, s);
 }
 
-int average_down(wp_ctx *ctx, int l)
+int average_down(wp_ctx *ctx, int l, hipStream_t s)
 {
     Level &F = ctx->L[l], &C = ctx->L[l - 1];
     if (F.ncover == 0) return WP_OK;
     const long long csf = (long long)F.nx * F.ny, csc = (long long)C.nx * C.ny;
     if (ctx->esz == 8)
         launch_average<double>(F.cover_dev, F.ncover, (const double *)F.q[F.cur], F.nx, csf, (double *)C.q[C.cur],
-                               C.nx, csc, F.ratio, ctx->stream);
+                               C.nx, csc, F.ratio, s);
     else
         launch_average<float>(F.cover_dev, F.ncover, (const float *)F.q[F.cur], F.nx, csf, (float *)C.q[C.cur], C.nx,
-                              csc, F.ratio, ctx->stream);
+                              csc, F.ratio, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "average launch: %s", hipGetErrorString(e));
     return WP_OK;
 }
 
-// One Berger-Oliger step of level l and, recursively, its finer levels.
-// sub: index of this step among the ratio steps of level l within one step
-// of level l-1 (time weight sub / ratio for the ghost ring).
-int bo_advance(wp_ctx *ctx, int l, double dt, int sub)
+// One Berger-Oliger step of level l and, recursively, its finer levels, on
+// stream s.  sub: index of this step among the ratio steps of level l within
+// one step of level l-1 (time weight sub / ratio for the ghost ring).  With
+// launch = false only the host bookkeeping (canvas parity, times) is done:
+// the replay of a captured sequence.
+int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launch)
 {
     Level &lv = ctx->L[l];
     int rc;
@@ -113,8 +115,12 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub)
         lv.t += dt;
         return WP_OK;
     }
-    if (l > 0 && (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio)) != WP_OK) return rc;
-    if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream, -1)) != WP_OK) return rc;
+    if (launch && l > 0 && (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio, s)) != WP_OK) return rc;
+    if (launch) {
+        if ((rc = wp_step_level(ctx, lv, dt, 0, s, -1)) != WP_OK) return rc;
+    } else {
+        lv.cur ^= 1;
+    }
     lv.t_prev = lv.t;
     lv.prev_valid = true;
     lv.t += dt;
@@ -122,12 +128,32 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub)
         const int r = ctx->L[l + 1].ratio;
         // this level's ring at its new time, read by the finer level's
         // interpolation next to the ring
-        if (l > 0 && (rc = fill_ring(ctx, l, (double)(sub + 1) / (double)lv.ratio)) != WP_OK) return rc;
+        if (launch && l > 0 && (rc = fill_ring(ctx, l, (double)(sub + 1) / (double)lv.ratio, s)) != WP_OK) return rc;
         for (int k = 0; k < r; ++k)
-            if ((rc = bo_advance(ctx, l + 1, dt / r, k)) != WP_OK) return rc;
-        if ((rc = average_down(ctx, l + 1)) != WP_OK) return rc;
+            if ((rc = bo_advance(ctx, l + 1, dt / r, k, s, launch)) != WP_OK) return rc;
+        if (launch && (rc = average_down(ctx, l + 1, s)) != WP_OK) return rc;
     }
     return WP_OK;
+}
+
+// Descriptors of every level for the step sizes of a coarse step dt0, so
+// that a capture records launches only.
+int prepare_levels(wp_ctx *ctx, double dt0)
+{
+    double dt = dt0;
+    int rc;
+    for (size_t l = 0; l < ctx->L.size(); ++l) {
+        if (l > 0) dt = dt / ctx->L[l].ratio;
+        if (!ctx->L[l].patches.empty() && (rc = wp_prepare_level(ctx, ctx->L[l], dt)) != WP_OK) return rc;
+    }
+    return WP_OK;
+}
+
+std::vector<int> parities(const wp_ctx *ctx)
+{
+    std::vector<int> p;
+    for (const Level &lv : ctx->L) p.push_back(lv.cur);
+    return p;
 }
 
 // Replace the patches of level f (> 0) with `boxes` (validated).
@@ -149,7 +175,7 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
         int *dev = nullptr;
         long long n = 0;
         if ((rc = upload_ints(ctx, fresh, dev, n, "new cell")) != WP_OK) return rc;
-        rc = fill_from_coarse(ctx, f, dev, n, 0.0, false);
+        rc = fill_from_coarse(ctx, f, dev, n, 0.0, false, ctx->stream);
         if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == WP_OK)
             rc = wp_fail(ctx, WP_EDEVICE, "regrid sync");
         wp_dfree(ctx, dev);
@@ -187,17 +213,47 @@ int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t)
     const Level &C = ctx->L[level - 1];
     double alpha = 1.0;
     if (C.prev_valid && C.t > C.t_prev) alpha = std::min(std::max((t - C.t_prev) / (C.t - C.t_prev), 0.0), 1.0);
-    return fill_ring(ctx, level, alpha);
+    return fill_ring(ctx, level, alpha, ctx->stream);
 }
 
+// Two coarse steps return every canvas to its parity, so their launch
+// sequence is captured once as a graph and replayed for each pair of steps
+// (re-captured when dt0, the tile tables or the parities change).
 extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
 {
     if (!ctx) return WP_EINVAL;
     if (nsteps < 0) return wp_fail(ctx, WP_EINVAL, "nsteps must be non-negative");
     int rc;
     if ((rc = wp_courant_check(ctx, ctx->L[0], dt0)) != WP_OK) return rc;
-    for (int s = 0; s < nsteps; ++s)
-        if ((rc = bo_advance(ctx, 0, dt0, 0)) != WP_OK) return rc;
+    const int pairs = nsteps / 2;
+    if (pairs > 0) {
+        const std::vector<int> par = parities(ctx);
+        if (!ctx->bo_exec || ctx->bo_dt != dt0 || ctx->bo_gen != ctx->topo_gen || ctx->bo_par != par) {
+            if ((rc = prepare_levels(ctx, dt0)) != WP_OK) return rc;
+            std::vector<Level> saved = ctx->L;   // host bookkeeping is replayed below
+            hipStream_t s;
+            if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
+            for (int k = 0; k < 2 && rc == WP_OK; ++k) rc = bo_advance(ctx, 0, dt0, 0, s, true);
+            const int rc2 = wp_graph_end(ctx, s, ctx->bo_exec);
+            for (size_t l = 0; l < ctx->L.size(); ++l) {
+                ctx->L[l].cur = saved[l].cur;
+                ctx->L[l].t = saved[l].t;
+                ctx->L[l].t_prev = saved[l].t_prev;
+                ctx->L[l].prev_valid = saved[l].prev_valid;
+            }
+            if (rc != WP_OK) return rc;
+            if (rc2 != WP_OK) return rc2;
+            ctx->bo_dt = dt0;
+            ctx->bo_gen = ctx->topo_gen;
+            ctx->bo_par = par;
+        }
+        for (int p = 0; p < pairs; ++p) {
+            if ((rc = wp_graph_launch(ctx, ctx->bo_exec)) != WP_OK) return rc;
+            for (int k = 0; k < 2; ++k)
+                if ((rc = bo_advance(ctx, 0, dt0, 0, ctx->stream, false)) != WP_OK) return rc;
+        }
+    }
+    if (nsteps & 1) return bo_advance(ctx, 0, dt0, 0, ctx->stream, true);
     return WP_OK;
 }
 

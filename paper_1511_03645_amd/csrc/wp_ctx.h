@@ -95,6 +95,11 @@ struct wp_ctx {
     hipGraphExec_t graph_exec = nullptr;     // forward steps of level 0
     int graph_steps = 0, graph_parity = -1;
     double graph_dt = 0.0;
+    hipGraphExec_t bo_exec = nullptr;        // two Berger-Oliger coarse steps of every level
+    double bo_dt = 0.0;
+    unsigned long long bo_gen = 0;
+    std::vector<int> bo_par;
+    unsigned long long topo_gen = 1;         // bumped whenever a tile table changes
     hipGraphExec_t adj_exec = nullptr;       // adjoint run with snapshot copies
     int adj_steps = 0, adj_every = 0;
     double adj_dt = 0.0;

@@ -158,6 +158,7 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
     lv.tiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, lv.tiles_host.size()));
     lv.ftiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, ft.size()));
     if (!lv.tiles_dev || !lv.ftiles_dev) return wp_fail(ctx, WP_ENOMEM, "tile table allocation failed");
+    ++ctx->topo_gen;   // captured sequences hold the old table pointers
     lv.ntiles = (int)lv.tiles_host.size();
     lv.nftiles = (int)ft.size();
     if (lv.ntiles && hipMemcpy(lv.tiles_dev, lv.tiles_host.data(), sizeof(Tile) * lv.ntiles, hipMemcpyHostToDevice) != hipSuccess)
@@ -376,6 +377,7 @@ extern "C" void wp_destroy(wp_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->adj_exec) (void)hipGraphExecDestroy(ctx->adj_exec);
+    if (ctx->bo_exec) (void)hipGraphExecDestroy(ctx->bo_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);

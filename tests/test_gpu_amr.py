@@ -196,3 +196,37 @@ def test_adjoint_guided_regrid_pipeline():
         t += every * dt
         compare(w, H, f"after cycle {cycle}")
     assert regrids > 0
+
+
+def test_advance_graph_replays_match_eager():
+    """Pairs of coarse steps run as one captured graph: every replay, with
+    eager steps and synchronisations in between, equals eager stepping bit
+    for bit, and the result still matches the oracle."""
+    n, ratios = 16, [2, 4]
+    boxes = [[(4, 4, 20, 16)], [(24, 24, 40, 32), (64, 24, 8, 8)]]
+    cfg, H, a = build(n, ratios, boxes, (0, 0, 0, 0), seed=7)
+    _, _, b = build(n, ratios, boxes, (0, 0, 0, 0), seed=7)
+    dt = dt_of(cfg)
+
+    def same(what):
+        for l in range(3):
+            for k in range(len(H.patches[l]) if l else 1):
+                pa = a.get_state(level=l, patch=k if l else -1)
+                pb = b.get_state(level=l, patch=k if l else -1)
+                assert np.array_equal(pa, pb), f"{what}: level {l} patch {k}"
+
+    for rep in range(3):
+        a.advance(2, dt)
+        b.advance(1, dt)
+        b.advance(1, dt)
+        a.sync()
+        same(f"replay {rep}")
+    a.advance(3, dt)
+    for _ in range(3):
+        b.advance(1, dt)
+    same("pair plus odd step")
+    for _ in range(9):
+        H.advance(0, dt)
+    compare(a, H, "graph path")
+    for l in range(3):
+        assert a.get_time(l) == b.get_time(l)
