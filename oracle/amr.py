@@ -60,6 +60,34 @@ def minmod(a, b):
     return math.copysign(min(abs(a), abs(b)), a)
 
 
+def resolve_many(idx, n, lo, hi):
+    """`resolve` applied to every entry of an integer array."""
+    i = np.clip(np.asarray(idx), -2, n + 1)
+    out = i.copy()
+    flip = np.zeros(i.shape, dtype=bool)
+    low, high = i < 0, i >= n
+    if lo == BC_PERIODIC:
+        out[low] = i[low] + n
+    elif lo == BC_WALL:
+        out[low] = -1 - i[low]
+        flip[low] = True
+    else:
+        out[low] = 0
+    if hi == BC_PERIODIC:
+        out[high] = i[high] - n
+    elif hi == BC_WALL:
+        out[high] = 2 * n - 1 - i[high]
+        flip[high] = True
+    else:
+        out[high] = n - 1
+    return out, flip
+
+
+def minmod_many(a, b):
+    """`minmod` entry by entry."""
+    return np.where(a * b <= 0.0, 0.0, np.copysign(np.minimum(np.abs(a), np.abs(b)), a))
+
+
 def ring_cells(patches, nx, ny):
     """Sorted list of (i, j) ghost-ring cells of a level."""
     inside = np.zeros((ny, nx), dtype=bool)
@@ -73,19 +101,20 @@ def ring_cells(patches, nx, ny):
 
 def interp_space(C, k, ic, jc, xi, eta, bc, ucomp=1, vcomp=2):
     """Minmod-limited linear value of component k of coarse array C at the
-    offset (xi, eta) (in coarse cell widths) from the centre of (ic, jc)."""
+    offset (xi, eta) (in coarse cell widths) from the centre of (ic, jc).
+    Scalars or equally shaped arrays for ic, jc, xi, eta."""
     _, NY, NX = C.shape
+    ic, jc = np.asarray(ic), np.asarray(jc)
 
     def val(i, j):
-        ri, fi = resolve(i, NX, bc[0], bc[1])
-        rj, fj = resolve(j, NY, bc[2], bc[3])
+        ri, fi = resolve_many(i, NX, bc[0], bc[1])
+        rj, fj = resolve_many(j, NY, bc[2], bc[3])
         v = C[k, rj, ri]
-        if (fi and k == ucomp) or (fj and k == vcomp):
-            v = -v
-        return v
+        flip = (fi if k == ucomp else False) | (fj if k == vcomp else False)
+        return np.where(flip, -v, v)
     c0 = C[k, jc, ic]
-    sx = minmod(val(ic + 1, jc) - c0, c0 - val(ic - 1, jc))
-    sy = minmod(val(ic, jc + 1) - c0, c0 - val(ic, jc - 1))
+    sx = minmod_many(val(ic + 1, jc) - c0, c0 - val(ic - 1, jc))
+    sy = minmod_many(val(ic, jc + 1) - c0, c0 - val(ic, jc - 1))
     return (c0 + xi * sx) + eta * sy
 
 
@@ -93,30 +122,32 @@ def coarse_to_fine(Cold, Cnew, alpha, r, cells, bc):
     """Values [len(cells)][m] at fine cells (I, J) from the coarse level at
     the two times, time weight alpha."""
     m = Cold.shape[0]
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, 2)
     out = np.zeros((len(cells), m))
-    for n, (I, J) in enumerate(cells):
-        ic, jc = I // r, J // r
-        xi = ((I % r) + 0.5) / r - 0.5
-        eta = ((J % r) + 0.5) / r - 0.5
-        for k in range(m):
-            a = interp_space(Cold, k, ic, jc, xi, eta, bc)
-            b = interp_space(Cnew, k, ic, jc, xi, eta, bc)
-            out[n, k] = (1.0 - alpha) * a + alpha * b
+    if len(cells) == 0:
+        return out
+    I, J = cells[:, 0], cells[:, 1]
+    ic, jc = I // r, J // r
+    xi = ((I % r) + 0.5) / r - 0.5
+    eta = ((J % r) + 0.5) / r - 0.5
+    for k in range(m):
+        a = interp_space(Cold, k, ic, jc, xi, eta, bc)
+        b = interp_space(Cnew, k, ic, jc, xi, eta, bc)
+        out[:, k] = (1.0 - alpha) * a + alpha * b
     return out
 
 
 def average_down(fine, coarse, r, patches):
     """coarse cell = mean of its r x r children, for every coarse cell that
-    the (r-aligned) fine patches cover."""
+    the (r-aligned) fine patches cover: the children summed row by row from
+    zero, then divided by r^2."""
     for (i0, j0, w, h) in patches:
-        for jc in range(j0 // r, (j0 + h) // r):
-            for ic in range(i0 // r, (i0 + w) // r):
-                for k in range(fine.shape[0]):
-                    s = 0.0
-                    for jj in range(r):
-                        for ii in range(r):
-                            s += fine[k, r * jc + jj, r * ic + ii]
-                    coarse[k, jc, ic] = s / (r * r)
+        ic0, ic1, jc0, jc1 = i0 // r, (i0 + w) // r, j0 // r, (j0 + h) // r
+        s = np.zeros((fine.shape[0], jc1 - jc0, ic1 - ic0))
+        for jj in range(r):
+            for ii in range(r):
+                s = s + fine[:, r * jc0 + jj:r * jc1:r, r * ic0 + ii:r * ic1:r]
+        coarse[:, jc0:jc1, ic0:ic1] = s / (r * r)
 
 
 # ---------------------------------------------------------------------------
@@ -167,24 +198,19 @@ class Hierarchy:
     def _patch_step(self, l, p, which, dt):
         i0, j0, w, h = p
         nxl, nyl = self.n[l]
-        G = np.zeros((3, h + 4, w + 4))
-        rho = np.zeros((h + 4, w + 4))
-        K = np.zeros((h + 4, w + 4))
-        for gj in range(-2, h + 2):
-            rj, fj = resolve(j0 + gj, nyl, self.bc[2], self.bc[3])
-            for gi in range(-2, w + 2):
-                ri, fi = resolve(i0 + gi, nxl, self.bc[0], self.bc[1])
-                v = self.q[l][:, rj, ri].copy()
-                if fi:
-                    v[1] = -v[1]
-                if fj:
-                    v[2] = -v[2]
-                G[:, gj + 2, gi + 2] = v
-                rho[gj + 2, gi + 2] = self.rho[l][rj, ri]
-                K[gj + 2, gi + 2] = self.K[l][rj, ri]
+        # the patch with two ghost layers read from the level's array, ghost
+        # indices outside the domain resolved by the boundary rule
+        ri, fi = resolve_many(np.arange(i0 - 2, i0 + w + 2), nxl, self.bc[0], self.bc[1])
+        rj, fj = resolve_many(np.arange(j0 - 2, j0 + h + 2), nyl, self.bc[2], self.bc[3])
+        G = self.q[l][:, rj[:, None], ri[None, :]]
+        G[1] = np.where(fi[None, :], -G[1], G[1])
+        G[2] = np.where(fj[:, None], -G[2], G[2])
+        G = np.ascontiguousarray(G)
+        rho = np.ascontiguousarray(self.rho[l][rj[:, None], ri[None, :]])
+        K = np.ascontiguousarray(self.K[l][rj[:, None], ri[None, :]])
         aux = np.zeros((4, h + 4, w + 4))
         L = lib()
-        L.or_make_aux(0, w, h, _dp(np.ascontiguousarray(rho)), _dp(np.ascontiguousarray(K)), 9.81, _dp(aux))
+        L.or_make_aux(0, w, h, _dp(rho), _dp(K), 9.81, _dp(aux))
         Gn = np.zeros_like(G)
         dx, dy = self.dx[l]
         L.or_patch_step(which, w, h, dt / dx, dt / dy, 9.81, _dp(aux), _dp(G), _dp(Gn),
@@ -194,10 +220,9 @@ class Hierarchy:
     def fill_ring(self, l, alpha):
         if l == 0 or not self.patches[l]:
             return
-        cells = ring_cells(self.patches[l], *self.n[l])
+        cells = np.asarray(ring_cells(self.patches[l], *self.n[l]), dtype=np.int64).reshape(-1, 2)
         vals = coarse_to_fine(self.q_old[l - 1], self.q[l - 1], alpha, self.ratios[l - 1], cells, self.bc)
-        for (I, J), v in zip(cells, vals):
-            self.q[l][:, J, I] = v
+        self.q[l][:, cells[:, 1], cells[:, 0]] = vals.T
 
     def step_level(self, l, dt, alpha=None):
         """One step of every patch of level l (ghost ring filled first)."""
@@ -221,15 +246,13 @@ class Hierarchy:
         old = np.zeros((nyf, nxf), dtype=bool)
         for (i0, j0, w, h) in self.patches[f]:
             old[j0:j0 + h, i0:i0 + w] = True
-        cells = []
+        new = np.zeros((nyf, nxf), dtype=bool)
         for (i0, j0, w, h) in boxes:
-            for J in range(j0, j0 + h):
-                for I in range(i0, i0 + w):
-                    if not old[J, I]:
-                        cells.append((I, J))
+            new[j0:j0 + h, i0:i0 + w] = True
+        jj, ii = np.nonzero(new & ~old)
+        cells = np.stack([ii, jj], axis=1)
         vals = coarse_to_fine(self.q[l], self.q[l], 0.0, self.ratios[l], cells, self.bc)
-        for (I, J), v in zip(cells, vals):
-            self.q[f][:, J, I] = v
+        self.q[f][:, jj, ii] = vals.T
         self.patches[f] = [tuple(b) for b in boxes]
         self.t[f] = self.t[l]
         for g in range(f + 1, self.L):

@@ -230,3 +230,41 @@ def test_advance_graph_replays_match_eager():
     compare(a, H, "graph path")
     for l in range(3):
         assert a.get_time(l) == b.get_time(l)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_three_level_workload():
+    """The 3-level workload at full size (coarse 256 x 256, ratios 4, 4, 400
+    + 1600 seeded patches) in the benchmark's launch configuration (pairs of
+    coarse steps replayed as one graph): two coarse steps from seeded data on
+    every level, every owned cell of every level against the oracle."""
+    from wp_synth import acoustics2d_amr
+    cfg = acoustics2d_amr(n0=256, seed=2)
+    h = cfg["hierarchy"]
+    ratios = h["ratios"]
+    print(f"case amr full size: patches {[len(b) for b in h['levels']]}", flush=True)
+    H = amr.Hierarchy(cfg, ratios, [])
+    w = wp.from_config(cfg, num_levels=3, ratios=tuple(ratios))
+    q0 = random_state(3, 256, 256, seed=11)
+    H.set_level(0, q0)
+    w.set_state(q0, level=0)
+    for l in (0, 1):
+        H.regrid(l, h["levels"][l + 1])
+        w.regrid(l, h["levels"][l + 1])
+    for l in (1, 2):
+        nl = H.n[l][0]
+        ql = 0.5 * random_state(3, nl, nl, seed=20 + l)
+        H.set_level(l, ql)
+        w.set_state(ql, level=l)
+    w.advance(2, cfg["dt"])
+    for _ in range(2):
+        H.advance(0, cfg["dt"])
+    for l in range(3):
+        got = w.get_state(level=l)
+        nl = H.n[l][0]
+        own = np.zeros((nl, nl), dtype=bool)
+        for (i0, j0, a, b) in H.patches[l]:
+            own[j0:j0 + b, i0:i0 + a] = True
+        ref = H.q[l][:, own]
+        err = np.abs(got[:, own] - ref).max()
+        assert err <= TOL64 * np.abs(ref).max(), f"level {l}: max err {err:.3e}"
