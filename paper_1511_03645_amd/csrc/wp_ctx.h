@@ -88,10 +88,9 @@ struct wp_ctx {
     bool phi_valid = false;
     std::string err;
     int tile_rows = 0;
-    // captured launch sequences, replayed on an internal stream joined to
-    // `stream` with events
+    // captured launch sequences (recorded on an internal stream, replayed on
+    // `stream`)
     hipStream_t cap_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t graph_exec = nullptr;     // forward steps of level 0
     int graph_steps = 0, graph_parity = -1;
     double graph_dt = 0.0;

@@ -379,8 +379,6 @@ extern "C" void wp_destroy(wp_ctx *ctx)
     if (ctx->adj_exec) (void)hipGraphExecDestroy(ctx->adj_exec);
     if (ctx->bo_exec) (void)hipGraphExecDestroy(ctx->bo_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     std::vector<void *> all = ctx->owned;
     for (void *p : all) wp_dfree(ctx, p);
     delete ctx;
@@ -633,14 +631,12 @@ int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s,
 }
 
 // ---------------------------------------------------------------------------
-// graphs: capture on an internal stream, joined to the caller's stream
+// graphs: captured on an internal stream, replayed on the handle stream
 // ---------------------------------------------------------------------------
 int wp_graph_begin(wp_ctx *ctx, hipStream_t &s)
 {
     if (!ctx->cap_stream) {
-        if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess)
+        if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return wp_fail(ctx, WP_EDEVICE, "capture stream creation failed");
     }
     s = ctx->cap_stream;
@@ -667,13 +663,11 @@ int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec)
     return WP_OK;
 }
 
+// A captured sequence runs on the handle's stream, ordered with the rest of
+// its work like any launch.
 int wp_graph_launch(wp_ctx *ctx, hipGraphExec_t exec)
 {
-    if (hipEventRecord(ctx->ev_fork, ctx->stream) != hipSuccess ||
-        hipStreamWaitEvent(ctx->cap_stream, ctx->ev_fork, 0) != hipSuccess ||
-        hipGraphLaunch(exec, ctx->cap_stream) != hipSuccess ||
-        hipEventRecord(ctx->ev_join, ctx->cap_stream) != hipSuccess ||
-        hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0) != hipSuccess)
+    if (hipGraphLaunch(exec, ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "graph launch: %s", hipGetErrorString(hipGetLastError()));
     return WP_OK;
 }
