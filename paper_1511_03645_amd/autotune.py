@@ -1,8 +1,8 @@
 """Tile-shape autotuner for the patch-update kernels.
 
 The 2D kernels march one wavefront up a 60-column strip; the number of rows
-per tile trades halo re-computation and per-tile start-up latency against
-the number of wavefronts in flight.  ``tune`` times the candidate heights on
+per tile trades halo reads and re-computation against the number of
+wavefronts in flight.  ``tune`` times the candidate heights on
 the live instance (the state is restored afterwards) and caches the winner
 in ``tune_cache.json`` next to this file, keyed by device, equation,
 precision and level size, so a later process starts from the measured
@@ -14,6 +14,7 @@ import json
 import os
 
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+# tile heights with a compile-time march
 CANDIDATES = (4, 6, 8, 12, 16)
 
 

@@ -26,13 +26,17 @@
 namespace wp {
 namespace {
 
+// Lane shifts by one across the whole wave.  The lane without a source (0
+// for a shift from the left, 63 from the right) reads 0; those are halo
+// columns whose results are never stored, and no stored column depends on
+// them.
 __device__ __forceinline__ int dpp_from_left(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);   // wave_shr:1
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);   // wave_shr:1
 }
 __device__ __forceinline__ int dpp_from_right(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);   // wave_shl:1
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);   // wave_shl:1
 }
 __device__ __forceinline__ double from_left(double v)
 {
@@ -57,8 +61,32 @@ __device__ __forceinline__ float uniform(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Ghost index resolution for one direction; i is first clamped to the
-// two-cell ghost band.  flip: the normal velocity changes sign (wall).
+// The same resolution as an affine map per side, i -> a i + b below 0 and
+// above n - 1 (periodic: a = 1; wall: a = -1; extrapolation: a = 0), so that
+// a wave-uniform index resolves with selects instead of branches.
+struct Resolver {
+    int n, alo, blo, ahi, bhi;
+    bool flo, fhi;
+    __device__ __forceinline__ Resolver(int n_, int bclo, int bchi) : n(n_)
+    {
+        alo = bclo == WP_BC_PERIODIC ? 1 : (bclo == WP_BC_WALL ? -1 : 0);
+        blo = bclo == WP_BC_PERIODIC ? n : (bclo == WP_BC_WALL ? -1 : 0);
+        ahi = bchi == WP_BC_PERIODIC ? 1 : (bchi == WP_BC_WALL ? -1 : 0);
+        bhi = bchi == WP_BC_PERIODIC ? -n : (bchi == WP_BC_WALL ? 2 * n - 1 : n - 1);
+        flo = bclo == WP_BC_WALL;
+        fhi = bchi == WP_BC_WALL;
+    }
+    __device__ __forceinline__ int operator()(int i, bool &flip) const
+    {
+        i = min(max(i, -2), n + 1);
+        const bool below = i < 0, above = i >= n;
+        flip = (below & flo) | (above & fhi);
+        const int a = below ? alo : (above ? ahi : 1);
+        const int b = below ? blo : (above ? bhi : 0);
+        return a * i + b;
+    }
+};
+
 __device__ __forceinline__ int resolve(int i, int n, int bclo, int bchi, bool &flip)
 {
     i = min(max(i, -2), n + 1);
@@ -210,21 +238,213 @@ struct Opts {
     int lim;
 };
 
+// Edge quantities carried from one row of the march to the next.
+template <typename T>
+struct Carry {
+    T a1x0, a2x0;        // x-edge (col-1/2, j) wave strengths
+    T b2m;               // y-edge (col, j-1/2) wave 2
+    T b1p, b2p;          // y-edge (col, j+1/2) waves 1, 2
+    T Gp_prev, Gv_prev;  // correction flux at y-edge (col, j-1/2)
+    int mL0;             // material of (col-1, j)
+};
+
+// Solves of the edges below and left of row j (R0) that start the march.
+template <typename T, bool ADJ, bool UNI>
+__device__ __forceinline__ void march_start(const Media<T, UNI> &md, const Row<T> &RA, const Row<T> &R0,
+                                            const Row<T> &R1, Carry<T> &c)
+{
+    T inv, k1, k2, b1a;
+    md.pair(RA.m, R0.m, inv, k1, k2);
+    solve<T, ADJ>(RA.p, RA.v, R0.p, R0.v, md(RA.m), md(R0.m), inv, b1a, c.b2m);
+    md.pair(R0.m, R1.m, inv, k1, k2);
+    solve<T, ADJ>(R0.p, R0.v, R1.p, R1.v, md(R0.m), md(R1.m), inv, c.b1p, c.b2p);
+    c.mL0 = UNI ? 0 : from_left(R0.m);
+    const T pl = from_left(R0.p), ul = from_left(R0.u);
+    md.pair(c.mL0, R0.m, inv, k1, k2);
+    solve<T, ADJ>(pl, ul, R0.p, R0.u, md(c.mL0), md(R0.m), inv, c.a1x0, c.a2x0);
+    c.Gp_prev = T(0);
+    c.Gv_prev = T(0);
+}
+
+// New state of cell (col, j) from rows j (R0), j+1 (R1), j+2 (R2) and the
+// carried edge quantities, which advance to row j+1.  Per cell: the y-edge
+// j+3/2 and x-edge (col-1/2, j+1) Riemann solves (each solved once, the
+// neighbours' through DPP lane shifts), limited correction fluxes at the
+// x-edge col-1/2 and y-edge j+1/2 with the transverse terms, and the
+// fluctuation-form update.
+template <typename T, bool ADJ, bool UNI>
+__device__ __forceinline__ void row_step(const Media<T, UNI> &md, bool second, bool trans, int lim, T nux, T nuy,
+                                         const Row<T> &R0, const Row<T> &R1, const Row<T> &R2, Carry<T> &c, T &pn,
+                                         T &un, T &vn)
+{
+    T inv, k1, k2;
+    T b1n, b2n;      // y-edge (col, j+3/2)
+    md.pair(R1.m, R2.m, inv, k1, k2);
+    solve<T, ADJ>(R1.p, R1.v, R2.p, R2.v, md(R1.m), md(R2.m), inv, b1n, b2n);
+    T a1n, a2n;      // x-edge (col-1/2, j+1)
+    const int mL1 = UNI ? 0 : from_left(R1.m);
+    {
+        const T pl = from_left(R1.p), ul = from_left(R1.u);
+        md.pair(mL1, R1.m, inv, k1, k2);
+        solve<T, ADJ>(pl, ul, R1.p, R1.u, md(mL1), md(R1.m), inv, a1n, a2n);
+    }
+    // F at x-edge (col-1/2, j): L = (col-1, j), C = (col, j)
+    const T a1r = from_right(c.a1x0);
+    const T a2l = from_left(c.a2x0);
+    const MCon<T> &L = md(c.mL0);
+    const MCon<T> &C = md(R0.m);
+    T Fp = T(0), Fu = T(0);
+    {
+        T invx;
+        md.pair(c.mL0, R0.m, invx, k1, k2);
+        if (second) {
+            const T t1 = limited(c.a1x0, k1 * a1r, lim);
+            const T t2 = limited(c.a2x0, k2 * a2l, lim);
+            if (!ADJ) {
+                Fp = C.hZx * t2 - L.hZx * t1;
+                Fu = L.hx * t1 + C.hx * t2;
+            } else {
+                Fp = C.gx * t2 - L.gx * t1;
+                Fu = -(L.gZx * t1 + C.gZx * t2);
+            }
+        }
+        if (trans) {
+            // y-edge fluctuations of cells (col, j) and (col-1, j) split at
+            // this x-edge: up-going from below plus down-going from above
+            const T S = c.b2m + c.b1p;
+            const T SL = from_left(S);
+            if (!ADJ) {
+                const T TR = C.Khy * invx * S, TL = L.Khy * invx * SL;
+                Fp += L.K * TR - C.K * TL;
+                Fu -= L.c * TR + C.c * TL;
+            } else {
+                const T TR = C.Zhy * invx * S, TL = L.Zhy * invx * SL;
+                Fp += L.c * TR - C.c * TL;
+                Fu += L.K * TR + C.K * TL;
+            }
+        }
+    }
+    // G at y-edge (col, j+1/2): C = (col, j), A = (col, j+1)
+    const MCon<T> &A = md(R1.m);
+    T Gp = T(0), Gv = T(0);
+    {
+        T invy;
+        md.pair(R0.m, R1.m, invy, k1, k2);
+        if (second) {
+            const T s1 = limited(c.b1p, k1 * b1n, lim);
+            const T s2 = limited(c.b2p, k2 * c.b2m, lim);
+            if (!ADJ) {
+                Gp = A.hZy * s2 - C.hZy * s1;
+                Gv = C.hy * s1 + A.hy * s2;
+            } else {
+                Gp = A.gy * s2 - C.gy * s1;
+                Gv = -(C.gZy * s1 + A.gZy * s2);
+            }
+        }
+        if (trans) {
+            const T a1rn = from_right(a1n);
+            const T R0s = c.a2x0 + a1r, R1s = a2n + a1rn;
+            if (!ADJ) {
+                const T UB = C.Khx * invy * R0s, UA = A.Khx * invy * R1s;
+                Gp -= A.K * UB - C.K * UA;
+                Gv -= A.c * UB + C.c * UA;
+            } else {
+                const T UB = C.Zhx * invy * R0s, UA = A.Zhx * invy * R1s;
+                Gp += C.c * UA - A.c * UB;
+                Gv += A.K * UB + C.K * UA;
+            }
+        }
+    }
+    // update cell (col, j)
+    const T Fpr = from_right(Fp), Fur = from_right(Fu);
+    if (!ADJ) {
+        pn = R0.p - nux * (C.K * (c.a2x0 + a1r)) - nuy * (C.K * (c.b2m + c.b1p)) - nux * (Fpr - Fp) -
+             nuy * (Gp - c.Gp_prev);
+        un = R0.u - nux * (C.c * (c.a2x0 - a1r)) - nux * (Fur - Fu);
+        vn = R0.v - nuy * (C.c * (c.b2m - c.b1p)) - nuy * (Gv - c.Gv_prev);
+    } else {
+        pn = R0.p - nux * (c.a2x0 + a1r) - nuy * (c.b2m + c.b1p) - nux * (Fpr - Fp) - nuy * (Gp - c.Gp_prev);
+        un = R0.u - nux * (C.Z * (a1r - c.a2x0)) - nux * (Fur - Fu);
+        vn = R0.v - nuy * (C.Z * (c.b1p - c.b2m)) - nuy * (Gv - c.Gv_prev);
+    }
+    c.mL0 = mL1;
+    c.a1x0 = a1n;
+    c.a2x0 = a2n;
+    c.b2m = c.b2p;
+    c.b1p = b1n;
+    c.b2p = b2n;
+    c.Gp_prev = Gp;
+    c.Gv_prev = Gv;
+}
+
+// Rows requested ahead of their first use in the compile-time march.
+constexpr int PREFETCH = 3;
+// sched_barrier mask: ALU instructions and memory writes may be moved across,
+// memory reads may not.
+constexpr int SCHED_KEEP_LOADS = 0x0001 | 0x0040;
+
+// Compile-time march of one wave over a tile of RT rows: iteration `it`
+// updates row j0 - 1 + it.  The tile reads RT + 4 rows (two-row halo above
+// and below); row r (counted from j0 - 2) is first needed at iteration
+// max(0, r - 3) and requested PREFETCH iterations before that, so a few rows
+// are always in flight while arithmetic proceeds.  The unrolled march is one
+// branch-free block.
+template <typename T, bool ADJ, bool UNI, int RT, typename LD>
+__device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &tl, int nx, T nux, T nuy,
+                                           unsigned csb, unsigned out_off0, bool out_lane,
+                                           __amdgpu_buffer_rsrc_t qw, __amdgpu_buffer_rsrc_t sw, const LD &ld, int &bad)
+{
+    constexpr int NR = RT + 4;
+    constexpr int FIRST = 3 + PREFETCH < NR ? 3 + PREFETCH : NR;   // rows requested before the march
+    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    Row<T> rw[NR];
+#pragma unroll
+    for (int r = 0; r < FIRST; ++r) ld(rw[r], j0 - 2 + r);
+    __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+    Carry<T> c;
+    march_start<T, ADJ, UNI>(md, rw[0], rw[1], rw[2], c);
+    // stores of halo lanes and of rows past a short tile go to this offset,
+    // beyond the buffer's range (3 components), where they are dropped; the
+    // snapshot store has an empty range when no snapshot is taken
+    const unsigned nowhere = 3u * csb;
+#pragma unroll
+    for (int it = 0; it <= RT; ++it) {
+        if (FIRST + it < NR) {
+            ld(rw[FIRST + it], j0 - 2 + FIRST + it);
+            __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+        }
+        T pn, un, vn;
+        row_step<T, ADJ, UNI>(md, true, true, 1, nux, nuy, rw[it + 1], rw[it + 2], rw[it + 3], c, pn, un, vn);
+        if (it == 0) continue;   // row j0-1 only starts the y-edge fluxes
+        const int j = j0 - 1 + it;
+        const bool keep = j < j1 && out_lane;
+        const unsigned off = keep ? (unsigned)j * (unsigned)nx * (unsigned)sizeof(T) + out_off0 : nowhere;
+        bstore(qw, off, 0u, pn);
+        bstore(qw, off, csb, un);
+        bstore(qw, off, 2u * csb, vn);
+        bstore(sw, off, 0u, pn);
+        bstore(sw, off, csb, un);
+        bstore(sw, off, 2u * csb, vn);
+        bad |= keep & !(isfinite(pn) & isfinite(un) & isfinite(vn));
+    }
+}
+
+// One wave marches its tile up the rows.  RT > 0: the compile-time march
+// above (full method: second order, MC limiter, transverse terms).  RT = 0
+// (runtime height, any options): a rolling window of rows prefetched two
+// rows ahead.
 template <typename T, bool ADJ, bool UNI, bool FULL, int RT>
 __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt, const Tile &tl, int lane, int nx,
                                       int ny, int bc2, int bc3, int cx, T sx, unsigned csb, T nux, T nuy,
                                       __amdgpu_buffer_rsrc_t qr, __amdgpu_buffer_rsrc_t qw,
                                       __amdgpu_buffer_rsrc_t mr, __amdgpu_buffer_rsrc_t sw, bool snap, int &bad)
 {
-    // FULL: second order, MC limiter and transverse terms fixed at compile time
-    const bool second = FULL ? true : op_rt.second;
-    const bool trans = FULL ? true : op_rt.trans;
-    const int lim = FULL ? 1 : op_rt.lim;
     const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
     const unsigned out_off0 = (unsigned)(tl.i0 - 2 + lane) * (unsigned)sizeof(T);
+    const Resolver rowres(ny, bc2, bc3);
     auto ld = [=](Row<T> &r, int j) {
         bool fy;
-        const int jy = resolve(j, ny, bc2, bc3, fy);
+        const int jy = rowres(j, fy);
         const unsigned idx = (unsigned)(jy * nx + cx);
         const unsigned off = idx * (unsigned)sizeof(T);
         r.p = bload(qr, off, T(0), 0u);
@@ -233,162 +453,49 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
         r.v = fy ? -v : v;
         r.m = UNI ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
     };
-    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
-    Row<T> RA, R0, R1, X0, X1, X2;
-    ld(RA, j0 - 2);
-    ld(R0, j0 - 1);
-    ld(R1, j0);
-    ld(X0, j0 + 1);
-    ld(X1, j0 + 2);
-    T inv, k1, k2;
-    T b1p, b2p, b2m;
-    {
-        T b1a;
-        md.pair(RA.m, R0.m, inv, k1, k2);
-        solve<T, ADJ>(RA.p, RA.v, R0.p, R0.v, md(RA.m), md(R0.m), inv, b1a, b2m);
-        md.pair(R0.m, R1.m, inv, k1, k2);
-        solve<T, ADJ>(R0.p, R0.v, R1.p, R1.v, md(R0.m), md(R1.m), inv, b1p, b2p);
-    }
-    T a1x0, a2x0;
-    int mL0 = UNI ? 0 : from_left(R0.m);
-    {
-        const T pl = from_left(R0.p), ul = from_left(R0.u);
-        md.pair(mL0, R0.m, inv, k1, k2);
-        solve<T, ADJ>(pl, ul, R0.p, R0.u, md(mL0), md(R0.m), inv, a1x0, a2x0);
-    }
-    T Gp_prev = T(0), Gv_prev = T(0);
-
-    // RT > 0: the tile height is a compile-time constant and the march is
-    // fully unrolled.  A loop back-edge would make the compiler drain every
-    // outstanding memory operation (prefetched rows and stores) once per row;
-    // unrolled, prefetches stay in flight and the register rotations below
-    // become renaming.  RT = 0: runtime height.
-    constexpr int NIT = RT > 0 ? RT + 1 : 1 << 30;
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int j = j0 - 1 + it;
-        if (RT == 0 && j >= j1) break;
-        ld(X2, j + 4);   // prefetch; row j+2 (X0) was issued two iterations ago
-        const Row<T> R2 = X0;
-        T b1n, b2n;      // y-edge (col, j+3/2)
-        md.pair(R1.m, R2.m, inv, k1, k2);
-        solve<T, ADJ>(R1.p, R1.v, R2.p, R2.v, md(R1.m), md(R2.m), inv, b1n, b2n);
-        T a1n, a2n;      // x-edge (col-1/2, j+1)
-        const int mL1 = UNI ? 0 : from_left(R1.m);
-        {
-            const T pl = from_left(R1.p), ul = from_left(R1.u);
-            md.pair(mL1, R1.m, inv, k1, k2);
-            solve<T, ADJ>(pl, ul, R1.p, R1.u, md(mL1), md(R1.m), inv, a1n, a2n);
-        }
-        // F at x-edge (col-1/2, j): L = (col-1, j), C = (col, j)
-        const T a1r = from_right(a1x0);
-        const T a2l = from_left(a2x0);
-        const MCon<T> &L = md(mL0);
-        const MCon<T> &C = md(R0.m);
-        T Fp = T(0), Fu = T(0);
-        {
-            T invx;
-            md.pair(mL0, R0.m, invx, k1, k2);
-            if (second) {
-                const T t1 = limited(a1x0, k1 * a1r, lim);
-                const T t2 = limited(a2x0, k2 * a2l, lim);
-                if (!ADJ) {
-                    Fp = C.hZx * t2 - L.hZx * t1;
-                    Fu = L.hx * t1 + C.hx * t2;
-                } else {
-                    Fp = C.gx * t2 - L.gx * t1;
-                    Fu = -(L.gZx * t1 + C.gZx * t2);
+    if constexpr (RT > 0) {
+        march_tile<T, ADJ, UNI, RT>(md, tl, nx, nux, nuy, csb, out_off0, out_lane, qw, sw, ld, bad);
+    } else {
+        // FULL: second order, MC limiter and transverse terms fixed at compile time
+        const bool second = FULL ? true : op_rt.second;
+        const bool trans = FULL ? true : op_rt.trans;
+        const int lim = FULL ? 1 : op_rt.lim;
+        const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+        Carry<T> c;
+        Row<T> RA, R0, R1, X0, X1, X2;
+        ld(RA, j0 - 2);
+        ld(R0, j0 - 1);
+        ld(R1, j0);
+        ld(X0, j0 + 1);
+        ld(X1, j0 + 2);
+        march_start<T, ADJ, UNI>(md, RA, R0, R1, c);
+        for (int j = j0 - 1; j < j1; ++j) {
+            ld(X2, j + 4);   // prefetch; row j+2 (X0) was issued two iterations ago
+            T pn, un, vn;
+            row_step<T, ADJ, UNI>(md, second, trans, lim, nux, nuy, R0, R1, X0, c, pn, un, vn);
+            if (j >= j0 && out_lane) {
+                const unsigned off = (unsigned)j * (unsigned)nx * (unsigned)sizeof(T) + out_off0;
+                bstore(qw, off, 0u, pn);
+                bstore(qw, off, csb, un);
+                bstore(qw, off, 2u * csb, vn);
+                if (snap) {
+                    bstore(sw, off, 0u, pn);
+                    bstore(sw, off, csb, un);
+                    bstore(sw, off, 2u * csb, vn);
                 }
+                bad |= !(isfinite(pn) && isfinite(un) && isfinite(vn));
             }
-            if (trans) {
-                // y-edge fluctuations of cells (col, j) and (col-1, j) split at
-                // this x-edge: up-going from below plus down-going from above
-                const T S = b2m + b1p;
-                const T SL = from_left(S);
-                if (!ADJ) {
-                    const T TR = C.Khy * invx * S, TL = L.Khy * invx * SL;
-                    Fp += L.K * TR - C.K * TL;
-                    Fu -= L.c * TR + C.c * TL;
-                } else {
-                    const T TR = C.Zhy * invx * S, TL = L.Zhy * invx * SL;
-                    Fp += L.c * TR - C.c * TL;
-                    Fu += L.K * TR + C.K * TL;
-                }
-            }
+            R0 = R1;
+            R1 = X0;
+            X0 = X1;
+            X1 = X2;
         }
-        // G at y-edge (col, j+1/2): C = (col, j), A = (col, j+1)
-        const MCon<T> &A = md(R1.m);
-        T Gp = T(0), Gv = T(0);
-        {
-            T invy;
-            md.pair(R0.m, R1.m, invy, k1, k2);
-            if (second) {
-                const T s1 = limited(b1p, k1 * b1n, lim);
-                const T s2 = limited(b2p, k2 * b2m, lim);
-                if (!ADJ) {
-                    Gp = A.hZy * s2 - C.hZy * s1;
-                    Gv = C.hy * s1 + A.hy * s2;
-                } else {
-                    Gp = A.gy * s2 - C.gy * s1;
-                    Gv = -(C.gZy * s1 + A.gZy * s2);
-                }
-            }
-            if (trans) {
-                const T a1rn = from_right(a1n);
-                const T R0s = a2x0 + a1r, R1s = a2n + a1rn;
-                if (!ADJ) {
-                    const T UB = C.Khx * invy * R0s, UA = A.Khx * invy * R1s;
-                    Gp -= A.K * UB - C.K * UA;
-                    Gv -= A.c * UB + C.c * UA;
-                } else {
-                    const T UB = C.Zhx * invy * R0s, UA = A.Zhx * invy * R1s;
-                    Gp += C.c * UA - A.c * UB;
-                    Gv += A.K * UB + C.K * UA;
-                }
-            }
-        }
-        // update cell (col, j)
-        const T Fpr = from_right(Fp), Fur = from_right(Fu);
-        T pn, un, vn;
-        if (!ADJ) {
-            pn = R0.p - nux * (C.K * (a2x0 + a1r)) - nuy * (C.K * (b2m + b1p)) - nux * (Fpr - Fp) - nuy * (Gp - Gp_prev);
-            un = R0.u - nux * (C.c * (a2x0 - a1r)) - nux * (Fur - Fu);
-            vn = R0.v - nuy * (C.c * (b2m - b1p)) - nuy * (Gv - Gv_prev);
-        } else {
-            pn = R0.p - nux * (a2x0 + a1r) - nuy * (b2m + b1p) - nux * (Fpr - Fp) - nuy * (Gp - Gp_prev);
-            un = R0.u - nux * (C.Z * (a1r - a2x0)) - nux * (Fur - Fu);
-            vn = R0.v - nuy * (C.Z * (b1p - b2m)) - nuy * (Gv - Gv_prev);
-        }
-        if (j >= j0 && j < j1 && out_lane) {
-            const unsigned off = (unsigned)j * (unsigned)nx * (unsigned)sizeof(T) + out_off0;
-            bstore(qw, off, 0u, pn);
-            bstore(qw, off, csb, un);
-            bstore(qw, off, 2u * csb, vn);
-            if (snap) {
-                bstore(sw, off, 0u, pn);
-                bstore(sw, off, csb, un);
-                bstore(sw, off, 2u * csb, vn);
-            }
-            bad |= !(isfinite(pn) && isfinite(un) && isfinite(vn));
-        }
-        R0 = R1;
-        R1 = R2;
-        X0 = X1;
-        X1 = X2;
-        mL0 = mL1;
-        a1x0 = a1n;
-        a2x0 = a2n;
-        b2m = b2p;
-        b1p = b1n;
-        b2p = b2n;
-        Gp_prev = Gp;
-        Gv_prev = Gv;
     }
 }
 
 // KIND 0: each tile takes the single-material or the mixed path as flagged;
 // KIND 1: every tile is single-material (the lean march alone sets the
-// register count and so the occupancy); KIND 2: every tile is mixed.
+// register count and so the occupancy).
 template <typename T, bool ADJ, bool FULL, int RT, int KIND>
 __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int parity,
@@ -527,6 +634,8 @@ void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int 
     const dim3 g(ntiles), b(WAVE);
 #define WP_LAUNCH(ADJ, FULL, RT, KIND) \
     hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap_index, status)
+    // tile heights 4, 6, 8, 12 and 16 have a compile-time march; any other
+    // height takes the runtime march
 #define WP_BY_RT(ADJ, KIND)                              \
     switch (full ? rows : 0) {                           \
     case 4: WP_LAUNCH(ADJ, true, 4, KIND); break;        \
@@ -540,8 +649,6 @@ void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int 
     }
     if (kind == 1) {
         if (adjoint) { WP_BY_RT(true, 1) } else { WP_BY_RT(false, 1) }
-    } else if (kind == 2) {
-        if (adjoint) { WP_BY_RT(true, 2) } else { WP_BY_RT(false, 2) }
     } else {
         if (adjoint) { WP_BY_RT(true, 0) } else { WP_BY_RT(false, 0) }
     }

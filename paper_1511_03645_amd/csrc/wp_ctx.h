@@ -91,9 +91,12 @@ struct wp_ctx {
     // captured launch sequences (recorded on an internal stream, replayed on
     // `stream`)
     hipStream_t cap_stream = nullptr;
+    // every cached sequence records the tile-table generation it was
+    // captured with and is re-captured when a table has been rebuilt since
     hipGraphExec_t graph_exec = nullptr;     // forward steps of level 0
     int graph_steps = 0, graph_parity = -1;
     double graph_dt = 0.0;
+    unsigned long long graph_gen = 0;
     hipGraphExec_t bo_exec = nullptr;        // two Berger-Oliger coarse steps of every level
     double bo_dt = 0.0;
     unsigned long long bo_gen = 0;
@@ -102,6 +105,7 @@ struct wp_ctx {
     hipGraphExec_t adj_exec = nullptr;       // adjoint run with snapshot copies
     int adj_steps = 0, adj_every = 0;
     double adj_dt = 0.0;
+    unsigned long long adj_gen = 0;
     const void *adj_snaps = nullptr;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };

@@ -50,6 +50,9 @@ void wp_dfree(wp_ctx *ctx, void *p)
     if (!p) return;
     auto it = std::find(ctx->owned.begin(), ctx->owned.end(), p);
     if (it != ctx->owned.end()) ctx->owned.erase(it);
+    // work already queued may still read the block; a caller's allocator may
+    // hand it out again at once
+    (void)hipStreamSynchronize(ctx->stream);
     if (ctx->has_alloc)
         ctx->alloc.free(p, ctx->alloc.user);
     else
@@ -177,7 +180,7 @@ int wp_default_rows(const wp_ctx *ctx, const Level &lv)
     for (const wp_patch &p : lv.patches) cells += (long long)p.nx * p.ny;
     if (cells <= (1LL << 18)) return 4;
     if (cells <= (1LL << 21)) return 8;
-    return 16;
+    return 12;
 }
 
 // ---------------------------------------------------------------------------
@@ -323,7 +326,12 @@ extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef,
             return bail(wp_fail(ctx, WP_EINVAL, "refinement ratios must be 2, 4 or 8"));
         cells_l *= (long long)G.ratio[l] * G.ratio[l];
     }
-    if (cells_l >= (1LL << 31)) return bail(wp_fail(ctx, WP_EINVAL, "finest level canvas above 2^31 cells"));
+    // kernels address a canvas with 32-bit byte offsets; a dropped store
+    // goes just past the three components, plus a component offset
+    const long long esz_max = P.precision == WP_FP32 ? 4 : 8;
+    if (cells_l * 5 * esz_max >= (1LL << 32))
+        return bail(wp_fail(ctx, WP_EINVAL, "finest level canvas of %lld cells is above the %lld-cell limit", cells_l,
+                            ((1LL << 32) - 1) / (5 * esz_max)));
     if (G.num_levels > 1)
         for (int k = 0; k < 4; ++k)
             if (P.bc[k] == WP_BC_PERIODIC)
@@ -680,7 +688,8 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
     Level &lv = ctx->L[0];
     int rc;
     if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
-    if (!ctx->graph_exec || ctx->graph_steps != nsteps || ctx->graph_dt != dt || ctx->graph_parity != lv.cur) {
+    if (!ctx->graph_exec || ctx->graph_steps != nsteps || ctx->graph_dt != dt || ctx->graph_parity != lv.cur ||
+        ctx->graph_gen != ctx->topo_gen) {
         if ((rc = wp_prepare_level(ctx, lv, dt)) != WP_OK) return rc;
         hipStream_t s;
         if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
@@ -693,6 +702,7 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
         if (rc != WP_OK) return rc;
         if (rc2 != WP_OK) return rc2;
         ctx->graph_steps = nsteps;
+        ctx->graph_gen = ctx->topo_gen;
         ctx->graph_dt = dt;
         ctx->graph_parity = lv.cur;
     }
@@ -858,7 +868,7 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
     // count, interval, dt or store change; the stencil writes each snapshot
     // itself on its snapshot steps
     if (!ctx->adj_exec || ctx->adj_steps != sp->nsteps || ctx->adj_every != sp->snap_every || ctx->adj_dt != sp->dt ||
-        ctx->adj_snaps != ctx->snaps) {
+        ctx->adj_snaps != ctx->snaps || ctx->adj_gen != ctx->topo_gen) {
         hipStream_t cs;
         if ((rc = wp_graph_begin(ctx, cs)) != WP_OK) return rc;
         for (int s = 1; s <= sp->nsteps && rc == WP_OK; ++s)
@@ -867,6 +877,7 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
         if (rc != WP_OK) return rc;
         if (rc2 != WP_OK) return rc2;
         ctx->adj_steps = sp->nsteps;
+        ctx->adj_gen = ctx->topo_gen;
         ctx->adj_every = sp->snap_every;
         ctx->adj_dt = sp->dt;
         ctx->adj_snaps = ctx->snaps;

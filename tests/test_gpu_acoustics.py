@@ -234,6 +234,31 @@ def test_graph_replay_matches_eager(nsteps):
     assert abs(graph.get_time() - eager.get_time()) < 1e-12
 
 
+def test_graphs_recaptured_after_tile_change():
+    """Changing the tile height rebuilds the tile table: cached forward and
+    adjoint sequences are captured again (a stale sequence would read the
+    released table), and every height gives the oracle's result."""
+    cfg = small_cfg(100, 77, (0, 0, 1, 1), seed=3)
+    q0 = random_state(3, 77, 100, seed=23)
+    dt = 0.8 * cfg["dx"] / float(np.sqrt(cfg["K"] / cfg["rho"]).max())
+    w = wp.from_config(cfg)
+    w.set_state(q0)
+    q = q0
+    for rows in (8, 12, 16, 5, 24, 32):
+        w.set_tile_rows(rows)
+        w.run_graph(6, dt, 1)
+        q, _, _ = oracle.run(cfg, "acoustics_fwd", q, 6, dt=dt)
+        close64(w.get_state(), q, f"after rows {rows}")
+    cfg2 = acoustics2d(n=64, seed=1)
+    snaps_ref, _ = oracle.adjoint_run(cfg2, nsteps=20, snap_every=10)
+    w2 = wp.from_config(cfg2)
+    for rows in (8, 16):
+        w2.set_tile_rows(rows)
+        w2.adjoint_run(cfg2["functional"], cfg2["dt"], 20, 10)
+        for k in range(len(snaps_ref)):
+            close64(w2.get_snapshot(k), snaps_ref[k], f"snapshot {k} with rows {rows}")
+
+
 def test_adjoint_run_replay_is_identical():
     cfg = acoustics2d(n=96, seed=1)
     w = wp.from_config(cfg)
