@@ -117,3 +117,22 @@ def test_swe_courant_violation_is_latched():
     with pytest.raises(wp.WPError) as e:
         w.sync()
     assert e.value.code == wp.WP_ECFL
+
+
+@pytest.mark.timeout(600)
+def test_swe_full_size_workload_steps():
+    """The 2048 x 2048 shelf workload in the benchmark's launch configuration:
+    forward steps of a perturbed state and adjoint steps from the gauge box,
+    element by element against the oracle (FP64)."""
+    cfg = swe2d(n=2048, seed=3)
+    print("case swe full size 2048^2", flush=True)
+    q0 = perturbed(cfg, seed=7)
+    oracle.set_threads(16)
+    ref, _, _ = oracle.run(cfg, "swe", q0, 3)
+    w = wp.from_config(cfg, precision=wp.FP64)
+    w.set_state(q0)
+    w.run_graph(3, cfg["dt"], 1)
+    per_component_close(w.get_state(), ref, 1e-12, "swe full size")
+    snaps_ref, _ = oracle.adjoint_run(cfg, nsteps=10, snap_every=10)
+    w.adjoint_run(cfg["functional"], cfg["dt"], 10, 10)
+    per_component_close(w.get_snapshot(1), snaps_ref[1], 1e-12, "lswe adjoint full size")

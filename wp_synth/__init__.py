@@ -268,8 +268,9 @@ def acoustics2d_batch(count=64, nmin=128, nmax=1024, steps=256, snap_every=8,
     seeded side N in [nmin, nmax], background rho = K = 1 plus 4 seeded
     axis-aligned rectangles (snapped to cell edges) with rho in U[0.5,2] and
     K in U[0.5,4], a width-0.1 Gaussian pulse and a radius-0.2 disc target
-    placed a seeded fraction of the travel distance away.  Each runs `steps`
-    steps at its own CFL-0.9 dt."""
+    at a seeded bearing, 0.9..1.0 of the background travel distance c T away
+    (c = 1), so that the front is crossing the target at the final time and J
+    is not a tail value.  Each runs `steps` steps at its own CFL-0.9 dt."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
@@ -291,7 +292,7 @@ def acoustics2d_batch(count=64, nmin=128, nmax=1024, steps=256, snap_every=8,
         T = steps * dt
         px, py = rng.uniform(-2.0, 2.0, 2)
         ang = rng.uniform(0.0, 2.0 * math.pi)
-        d = rng.uniform(0.5, 0.9) * T
+        d = rng.uniform(0.9, 1.0) * T
         tx = float(np.clip(px + d * math.cos(ang), -3.5, 3.5))
         ty = float(np.clip(py + d * math.sin(ang), -3.5, 3.5))
         q0 = np.zeros((3, n, n))
