@@ -540,9 +540,10 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
         march<T, ADJ, true, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw, snap,
                                       bad);
     } else if (KIND != 1) {
+        // mixed tiles are acou_mixed_rows(RT) high
         Media<T, false> md{mc, pt, Ip->nmat};
-        march<T, ADJ, false, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw, snap,
-                                       bad);
+        march<T, ADJ, false, FULL, acou_mixed_rows(RT)>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr,
+                                                        qw, mr, sw, snap, bad);
     }
     if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
 }

@@ -54,7 +54,7 @@ static int build_side(wp_batch *b, int adjoint)
         if ((rc = wp_prepare_level(c, lv, b->dts[k])) != WP_OK) return bfail(b, rc, c->err.c_str());
         memcpy(host.data() + k * dsz, lv.inst_host, dsz);
         std::vector<Tile> t = wp_make_tiles(lv.patches, (int)k, b->rows, STRIP, false);
-        wp_classify_tiles(c, lv, t);
+        wp_classify_tiles(c, lv, t, b->rows);
         for (const Tile &x : t) (x.mat < 0 ? mixed : uni).push_back(x);
     }
     wp_xcd_order(mixed);

@@ -117,7 +117,7 @@ std::vector<wp::Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int in
 int wp_upload_tiles(wp_ctx *ctx, Level &lv);
 int wp_default_rows(const wp_ctx *ctx, const Level &lv);
 uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j);
-void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles);
+void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles, int rows);
 int wp_alloc_level(wp_ctx *ctx, Level &lv);
 int wp_check_status(wp_ctx *ctx);
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt);

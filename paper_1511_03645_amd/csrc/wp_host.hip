@@ -119,10 +119,13 @@ uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j)
 }
 
 // Mark tiles whose whole read footprint (two-cell halo, ghost cells
-// resolved by the boundary rules) holds one material.
-void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &tiles)
+// resolved by the boundary rules) holds one material, and cut the others
+// (mixed) into pieces acou_mixed_rows(rows) high.
+void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &tiles, int rows)
 {
     if (!ctx->is_acoustics || !ctx->kind2d) return;
+    std::vector<Tile> out;
+    out.reserve(tiles.size());
     const int *bc = ctx->prob.bc;
     for (auto &t : tiles) {
         int m0 = -1;
@@ -136,7 +139,14 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
             }
         }
         t.mat = uni ? m0 : -1;
+        if (uni) {
+            out.push_back(t);
+            continue;
+        }
+        const int hm = acou_mixed_rows(rows);
+        for (int j = 0; j < t.nj; j += hm) out.push_back(Tile{t.inst, t.i0, t.j0 + j, t.ni, std::min(hm, t.nj - j), -1});
     }
+    tiles.swap(out);
 }
 
 int wp_upload_tiles(wp_ctx *ctx, Level &lv)
@@ -144,16 +154,21 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
     const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
     const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, lv);
     if (ctx->is_acoustics)
-        lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, true);
+        lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, false);
     else
-        lv.tiles_host = wp_make_tiles(lv.patches, 0, SWE_TY, SWE_TX, true);
+        lv.tiles_host = wp_make_tiles(lv.patches, 0, SWE_TY, SWE_TX, false);
     lv.tile_rows = rows;
-    wp_classify_tiles(ctx, lv, lv.tiles_host);
+    wp_classify_tiles(ctx, lv, lv.tiles_host, rows);
     // mixed-material tiles (the slower march) first, so they are dispatched
-    // at the start rather than forming the tail; each group keeps its
-    // XCD-aware order
-    std::stable_partition(lv.tiles_host.begin(), lv.tiles_host.end(), [](const Tile &t) { return t.mat < 0; });
-    lv.nuni = (int)std::count_if(lv.tiles_host.begin(), lv.tiles_host.end(), [](const Tile &t) { return t.mat >= 0; });
+    // at the start rather than forming the tail; each group in XCD-aware
+    // order
+    std::vector<Tile> mixed, uni;
+    for (const Tile &t : lv.tiles_host) (t.mat < 0 ? mixed : uni).push_back(t);
+    wp_xcd_order(mixed);
+    wp_xcd_order(uni);
+    lv.nuni = (int)uni.size();
+    lv.tiles_host = mixed;
+    lv.tiles_host.insert(lv.tiles_host.end(), uni.begin(), uni.end());
     // flag / reduction tiles: larger blocks of whole patches
     std::vector<Tile> ft = wp_make_tiles(lv.patches, 0, 16, 64, false);
     if (lv.tiles_dev) wp_dfree(ctx, lv.tiles_dev);

@@ -14,6 +14,11 @@ constexpr int MAXMAT = 16;     // distinct (rho, K) pairs per acoustics instance
 constexpr int WAVE = 64;       // CDNA wavefront
 constexpr int STRIP = WAVE - 4; // output columns per wave in the 2D kernels
 
+// Height of the mixed-material tiles of a 2D acoustics launch whose
+// single-material tiles are `rows` high: their per-cell table lookups make a
+// row slower, so they are cut shorter to finish with the rest of the launch.
+__host__ __device__ constexpr int acou_mixed_rows(int rows) { return rows >= 8 ? rows / 2 : rows; }
+
 // One unit of work of a patch-update launch: output cells
 // [i0, i0 + ni) x [j0, j0 + nj) of instance `inst`.
 struct Tile {
