@@ -219,19 +219,104 @@ struct Media<T, false> {
     static constexpr bool uniform = false;
 };
 
+// A single-material tile.  Every product of material constants, of the
+// Riemann normalisation inv = 1/(2Z) and of the step ratios that the update
+// applies to a wave strength is folded into one wave-uniform constant, and the
+// march carries strengths scaled by 1/inv (A = a / inv); the MC limiter is
+// scale-invariant, and its factor 1/2 sits in the constants as well.  With
+// (S, S_L) the y-edge fluctuation sums of this and the left column, R the
+// x-edge sums of this and the next row, and L_p, M_p the doubled limited
+// x- and y-edge strengths:
+//   F_p = fp (L_2 - L_1) + tp (S - S_L)      F_u = fu (L_1 + L_2) + tu (S + S_L)
+//   G_p = gp (M_2 - M_1) + up (R_1 - R_0)    G_v = gv (M_1 + M_2) + uv (R_0 + R_1)
+//   p' = p - p1 (A_2 + A_1r) - p2 (B_2 + B_1) - nux dF_p - nuy dG_p
+//   u' = u - u1 (A_2 - A_1r) - nux dF_u,     v' = v - v1 (B_2 - B_1) - nuy dG_v
+template <typename T>
+struct UniCon {
+    T Z, c, K;                   // Riemann solves
+    T fp, fu, tp, tu;            // x-edge correction and transverse terms
+    T gp, gv, up, uv;            // y-edge correction and transverse terms
+    T p1, p2, u1, v1;            // update
+};
+
+template <typename T, bool ADJ>
+__device__ __forceinline__ UniCon<T> make_unicon(const MCon<T> &m, T inv, T nux, T nuy)
+{
+    UniCon<T> u;
+    const T half = T(0.5), inv2 = inv * inv;
+    u.Z = m.Z;
+    u.c = m.c;
+    u.K = m.K;
+    if (!ADJ) {
+        u.fp = m.hZx * inv * half;
+        u.fu = m.hx * inv * half;
+        u.tp = m.K * m.Khy * inv2;
+        u.tu = -(m.c * m.Khy * inv2);
+        u.gp = m.hZy * inv * half;
+        u.gv = m.hy * inv * half;
+        u.up = m.K * m.Khx * inv2;
+        u.uv = -(m.c * m.Khx * inv2);
+        u.p1 = nux * m.K * inv;
+        u.p2 = nuy * m.K * inv;
+        u.u1 = nux * m.c * inv;
+        u.v1 = nuy * m.c * inv;
+    } else {
+        u.fp = m.gx * inv * half;
+        u.fu = -(m.gZx * inv * half);
+        u.tp = m.c * m.Zhy * inv2;
+        u.tu = m.K * m.Zhy * inv2;
+        u.gp = m.gy * inv * half;
+        u.gv = -(m.gZy * inv * half);
+        u.up = m.c * m.Zhx * inv2;
+        u.uv = m.K * m.Zhx * inv2;
+        u.p1 = nux * inv;
+        u.p2 = nuy * inv;
+        u.u1 = -(nux * m.Z * inv);
+        u.v1 = -(nuy * m.Z * inv);
+    }
+    // wave-uniform: keep them in scalar registers
+    u.Z = uniform(u.Z); u.c = uniform(u.c); u.K = uniform(u.K);
+    u.fp = uniform(u.fp); u.fu = uniform(u.fu); u.tp = uniform(u.tp); u.tu = uniform(u.tu);
+    u.gp = uniform(u.gp); u.gv = uniform(u.gv); u.up = uniform(u.up); u.uv = uniform(u.uv);
+    u.p1 = uniform(u.p1); u.p2 = uniform(u.p2); u.u1 = uniform(u.u1); u.v1 = uniform(u.v1);
+    return u;
+}
+
 template <typename T>
 struct Media<T, true> {
-    MCon<T> m;
-    T inv;
-    __device__ __forceinline__ const MCon<T> &operator()(int) const { return m; }
-    __device__ __forceinline__ void pair(int, int, T &i, T &k1, T &k2) const
-    {
-        i = inv;
-        k1 = T(1);
-        k2 = T(1);
-    }
+    UniCon<T> u;
     static constexpr bool uniform = true;
 };
+
+// Twice the MC-limited strength, 2 a phi(b / a) = sign(a) max(0, min(|a| + b',
+// 4 min(|a|, b'))) with b' = b sign(a) (b' <= 0, opposite signs, gives 0).
+// limiter 0: no limiting (2a).
+template <typename T>
+__device__ __forceinline__ T lim2(T a, T b, int limiter)
+{
+    if (limiter == 0) return a + a;
+    const T aa = fabs(a);
+    const T bs = copysign(T(1), a) * b;
+    const T r = fmax(fmin(aa + bs, T(4) * fmin(aa, bs)), T(0));
+    return copysign(r, a);
+}
+
+// Scaled strengths of one edge of a single-material tile (see UniCon):
+// forward A1 = Z dn - dp, A2 = Z dn + dp; adjoint A1 = -(c dn + K dp),
+// A2 = K dp - c dn, with dp = p_R - p_L, dn = n_R - n_L.
+template <typename T, bool ADJ>
+__device__ __forceinline__ void solve_uni(T pl, T nl, T pr, T nr, const UniCon<T> &u, T &a1, T &a2)
+{
+    const T dp = pr - pl, dn = nr - nl;
+    if (!ADJ) {
+        a1 = u.Z * dn - dp;
+        a2 = u.Z * dn + dp;
+    } else {
+        const T kdp = u.K * dp;
+        a1 = -(u.c * dn + kdp);
+        a2 = kdp - u.c * dn;
+    }
+}
 
 struct Opts {
     bool second, trans;
@@ -253,6 +338,16 @@ template <typename T, bool ADJ, bool UNI>
 __device__ __forceinline__ void march_start(const Media<T, UNI> &md, const Row<T> &RA, const Row<T> &R0,
                                             const Row<T> &R1, Carry<T> &c)
 {
+    if constexpr (UNI) {
+        T b1a;
+        solve_uni<T, ADJ>(RA.p, RA.v, R0.p, R0.v, md.u, b1a, c.b2m);
+        solve_uni<T, ADJ>(R0.p, R0.v, R1.p, R1.v, md.u, c.b1p, c.b2p);
+        c.mL0 = 0;
+        solve_uni<T, ADJ>(from_left(R0.p), from_left(R0.u), R0.p, R0.u, md.u, c.a1x0, c.a2x0);
+        c.Gp_prev = T(0);
+        c.Gv_prev = T(0);
+        return;
+    } else {
     T inv, k1, k2, b1a;
     md.pair(RA.m, R0.m, inv, k1, k2);
     solve<T, ADJ>(RA.p, RA.v, R0.p, R0.v, md(RA.m), md(R0.m), inv, b1a, c.b2m);
@@ -264,6 +359,7 @@ __device__ __forceinline__ void march_start(const Media<T, UNI> &md, const Row<T
     solve<T, ADJ>(pl, ul, R0.p, R0.u, md(c.mL0), md(R0.m), inv, c.a1x0, c.a2x0);
     c.Gp_prev = T(0);
     c.Gv_prev = T(0);
+    }
 }
 
 // New state of cell (col, j) from rows j (R0), j+1 (R1), j+2 (R2) and the
@@ -277,6 +373,45 @@ __device__ __forceinline__ void row_step(const Media<T, UNI> &md, bool second, b
                                          const Row<T> &R0, const Row<T> &R1, const Row<T> &R2, Carry<T> &c, T &pn,
                                          T &un, T &vn)
 {
+    if constexpr (UNI) {
+        const UniCon<T> &u = md.u;
+        T b1n, b2n;      // y-edge (col, j+3/2)
+        solve_uni<T, ADJ>(R1.p, R1.v, R2.p, R2.v, u, b1n, b2n);
+        T a1n, a2n;      // x-edge (col-1/2, j+1)
+        solve_uni<T, ADJ>(from_left(R1.p), from_left(R1.u), R1.p, R1.u, u, a1n, a2n);
+        const T a1r = from_right(c.a1x0);
+        const T a2l = from_left(c.a2x0);
+        T Fp = T(0), Fu = T(0), Gp = T(0), Gv = T(0);
+        if (second) {
+            const T t1 = lim2(c.a1x0, a1r, lim), t2 = lim2(c.a2x0, a2l, lim);
+            Fp = u.fp * (t2 - t1);
+            Fu = u.fu * (t1 + t2);
+            const T s1 = lim2(c.b1p, b1n, lim), s2 = lim2(c.b2p, c.b2m, lim);
+            Gp = u.gp * (s2 - s1);
+            Gv = u.gv * (s1 + s2);
+        }
+        if (trans) {
+            const T S = c.b2m + c.b1p;
+            const T SL = from_left(S);
+            Fp += u.tp * (S - SL);
+            Fu += u.tu * (S + SL);
+            const T R0s = c.a2x0 + a1r, R1s = a2n + from_right(a1n);
+            Gp += u.up * (R1s - R0s);
+            Gv += u.uv * (R0s + R1s);
+        }
+        const T Fpr = from_right(Fp), Fur = from_right(Fu);
+        pn = R0.p - u.p1 * (c.a2x0 + a1r) - u.p2 * (c.b2m + c.b1p) - nux * (Fpr - Fp) - nuy * (Gp - c.Gp_prev);
+        un = R0.u - u.u1 * (c.a2x0 - a1r) - nux * (Fur - Fu);
+        vn = R0.v - u.v1 * (c.b2m - c.b1p) - nuy * (Gv - c.Gv_prev);
+        c.a1x0 = a1n;
+        c.a2x0 = a2n;
+        c.b2m = c.b2p;
+        c.b1p = b1n;
+        c.b2p = b2n;
+        c.Gp_prev = Gp;
+        c.Gv_prev = Gv;
+        return;
+    } else {
     T inv, k1, k2;
     T b1n, b2n;      // y-edge (col, j+3/2)
     md.pair(R1.m, R2.m, inv, k1, k2);
@@ -375,6 +510,7 @@ __device__ __forceinline__ void row_step(const Media<T, UNI> &md, bool second, b
     c.b2p = b2n;
     c.Gp_prev = Gp;
     c.Gv_prev = Gv;
+    }
 }
 
 // Rows requested ahead of their first use in the compile-time march.
@@ -389,6 +525,10 @@ constexpr int SCHED_KEEP_LOADS = 0x0001 | 0x0040;
 // max(0, r - 3) and requested PREFETCH iterations before that, so a few rows
 // are always in flight while arithmetic proceeds.  The unrolled march is one
 // branch-free block.
+//
+// A tile flagged `down` is marched from its top row downwards: that is the
+// upward march of the problem reflected in y (rows taken in reverse order, v
+// negated on load and on store), which the method treats identically.
 template <typename T, bool ADJ, bool UNI, int RT, typename LD>
 __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &tl, int nx, T nux, T nuy,
                                            unsigned csb, unsigned out_off0, bool out_lane,
@@ -397,9 +537,12 @@ __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &
     constexpr int NR = RT + 4;
     constexpr int FIRST = 3 + PREFETCH < NR ? 3 + PREFETCH : NR;   // rows requested before the march
     const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    const bool down = tl.down != 0;
+    const int jb = down ? j0 + RT + 1 : j0 - 2;   // row of rw[0]
+    const int js = down ? -1 : 1;                 // row step of the march
     Row<T> rw[NR];
 #pragma unroll
-    for (int r = 0; r < FIRST; ++r) ld(rw[r], j0 - 2 + r);
+    for (int r = 0; r < FIRST; ++r) ld(rw[r], jb + js * r, down);
     __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
     Carry<T> c;
     march_start<T, ADJ, UNI>(md, rw[0], rw[1], rw[2], c);
@@ -410,13 +553,14 @@ __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &
 #pragma unroll
     for (int it = 0; it <= RT; ++it) {
         if (FIRST + it < NR) {
-            ld(rw[FIRST + it], j0 - 2 + FIRST + it);
+            ld(rw[FIRST + it], jb + js * (FIRST + it), down);
             __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
         }
         T pn, un, vn;
         row_step<T, ADJ, UNI>(md, true, true, 1, nux, nuy, rw[it + 1], rw[it + 2], rw[it + 3], c, pn, un, vn);
-        if (it == 0) continue;   // row j0-1 only starts the y-edge fluxes
-        const int j = j0 - 1 + it;
+        if (it == 0) continue;   // the first row only starts the y-edge fluxes
+        const int j = jb + js * (it + 1);
+        if (down) vn = -vn;
         const bool keep = j < j1 && out_lane;
         const unsigned off = keep ? (unsigned)j * (unsigned)nx * (unsigned)sizeof(T) + out_off0 : nowhere;
         bstore(qw, off, 0u, pn);
@@ -442,7 +586,9 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
     const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
     const unsigned out_off0 = (unsigned)(tl.i0 - 2 + lane) * (unsigned)sizeof(T);
     const Resolver rowres(ny, bc2, bc3);
-    auto ld = [=](Row<T> &r, int j) {
+    // row j into r; `flip` also negates v (the reflected frame of a
+    // downward march)
+    auto ld = [=](Row<T> &r, int j, bool flip) {
         bool fy;
         const int jy = rowres(j, fy);
         const unsigned idx = (unsigned)(jy * nx + cx);
@@ -450,7 +596,7 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
         r.p = bload(qr, off, T(0), 0u);
         r.u = sx * bload(qr, off, T(0), csb);
         const T v = bload(qr, off, T(0), 2u * csb);
-        r.v = fy ? -v : v;
+        r.v = fy != flip ? -v : v;
         r.m = UNI ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
     };
     if constexpr (RT > 0) {
@@ -463,14 +609,14 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
         const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
         Carry<T> c;
         Row<T> RA, R0, R1, X0, X1, X2;
-        ld(RA, j0 - 2);
-        ld(R0, j0 - 1);
-        ld(R1, j0);
-        ld(X0, j0 + 1);
-        ld(X1, j0 + 2);
+        ld(RA, j0 - 2, false);
+        ld(R0, j0 - 1, false);
+        ld(R1, j0, false);
+        ld(X0, j0 + 1, false);
+        ld(X1, j0 + 2, false);
         march_start<T, ADJ, UNI>(md, RA, R0, R1, c);
         for (int j = j0 - 1; j < j1; ++j) {
-            ld(X2, j + 4);   // prefetch; row j+2 (X0) was issued two iterations ago
+            ld(X2, j + 4, false);   // prefetch; row j+2 (X0) was issued two iterations ago
             T pn, un, vn;
             row_step<T, ADJ, UNI>(md, second, trans, lim, nux, nuy, R0, R1, X0, c, pn, un, vn);
             if (j >= j0 && out_lane) {
@@ -528,15 +674,9 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
     const T sx = fx ? T(-1) : T(1);
     int bad = 0;
     if (KIND == 1 || (KIND == 0 && tl.mat >= 0)) {
-        // one material: its constants are wave-uniform, kept in SGPRs
+        // one material: folded constants, wave-uniform, kept in SGPRs
         Media<T, true> md;
-        const MCon<T> &src = mc[tl.mat];
-        md.m.Z = uniform(src.Z); md.m.c = uniform(src.c); md.m.K = uniform(src.K); md.m.ir = uniform(src.ir);
-        md.m.hx = uniform(src.hx); md.m.hZx = uniform(src.hZx); md.m.hy = uniform(src.hy); md.m.hZy = uniform(src.hZy);
-        md.m.gx = uniform(src.gx); md.m.gZx = uniform(src.gZx); md.m.gy = uniform(src.gy); md.m.gZy = uniform(src.gZy);
-        md.m.Khx = uniform(src.Khx); md.m.Khy = uniform(src.Khy); md.m.Zhx = uniform(src.Zhx); md.m.Zhy = uniform(src.Zhy);
-        const T *pp = pt + (tl.mat * Ip->nmat + tl.mat) * 3;
-        md.inv = uniform(pp[0]);
+        md.u = make_unicon<T, ADJ>(mc[tl.mat], pt[(tl.mat * Ip->nmat + tl.mat) * 3], nux, nuy);
         march<T, ADJ, true, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw, snap,
                                       bad);
     } else if (KIND != 1) {

@@ -41,7 +41,10 @@ __device__ __forceinline__ double interp(const TH *s, int NX, int NY, int ratio,
     return a + b;
 }
 
-template <typename TQ, typename TH>
+// One workgroup of 4 waves per flag tile (at most 64 columns x 16 rows):
+// lane x takes column i0 + x, wave y rows j0 + y, j0 + y + 4, ...  SAME: the
+// level is the adjoint grid itself (no interpolation).
+template <typename TQ, typename TH, bool SAME>
 __global__ __launch_bounds__(256) void flag_kernel(const TQ *__restrict__ q, long long cs, int nx, int m,
                                                    const TH *__restrict__ snaps, long long sstride, long long hcs,
                                                    int NX, int NY, int ratio, int n_lo, int n_hi, double tol,
@@ -49,27 +52,36 @@ __global__ __launch_bounds__(256) void flag_kernel(const TQ *__restrict__ q, lon
                                                    unsigned long long *__restrict__ count)
 {
     const Tile tl = tiles[blockIdx.x];
-    const int ncell = tl.ni * tl.nj;
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
     unsigned long long local = 0;
-    for (int k = threadIdx.x; k < ncell; k += blockDim.x) {
-        const int i = tl.i0 + k % tl.ni, j = tl.j0 + k / tl.ni;
-        const long long idx = (long long)j * nx + i;
-        int i0, j0;
-        double wx, wy;
-        bracket(i, ratio, NX, i0, wx);
-        bracket(j, ratio, NY, j0, wy);
-        double qv[3];
-        for (int c = 0; c < m; ++c) qv[c] = (double)q[idx + c * cs];
-        double best = 0.0;
-        for (int n = n_lo; n <= n_hi; ++n) {
-            const TH *sn = snaps + (long long)n * sstride;
-            double ip = interp(sn, NX, NY, ratio, i0, wx, j0, wy) * qv[0];
-            for (int c = 1; c < m; ++c) ip = ip + interp(sn + c * hcs, NX, NY, ratio, i0, wx, j0, wy) * qv[c];
-            best = fmax(best, fabs(ip));
+    if (x < tl.ni) {
+        const int i = tl.i0 + x;
+        int i0 = i;
+        double wx = 0.0;
+        if (!SAME) bracket(i, ratio, NX, i0, wx);
+        for (int j = tl.j0 + y; j < tl.j0 + tl.nj; j += 4) {
+            const long long idx = (long long)j * nx + i;
+            int j0 = j;
+            double wy = 0.0;
+            if (!SAME) bracket(j, ratio, NY, j0, wy);
+            double qv[3];
+            for (int c = 0; c < m; ++c) qv[c] = (double)q[idx + c * cs];
+            double best = 0.0;
+            for (int n = n_lo; n <= n_hi; ++n) {
+                const TH *sn = snaps + (long long)n * sstride;
+                double ip, h;
+                h = SAME ? (double)sn[idx] : interp(sn, NX, NY, ratio, i0, wx, j0, wy);
+                ip = h * qv[0];
+                for (int c = 1; c < m; ++c) {
+                    h = SAME ? (double)sn[idx + c * hcs] : interp(sn + c * hcs, NX, NY, ratio, i0, wx, j0, wy);
+                    ip = ip + h * qv[c];
+                }
+                best = fmax(best, fabs(ip));
+            }
+            const uint8_t f = best > tol ? 1 : 0;
+            flags[idx] = f;
+            local += f;
         }
-        const uint8_t f = best > tol ? 1 : 0;
-        flags[idx] = f;
-        local += f;
     }
     // wave-level sum then one atomic per wave
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
@@ -222,8 +234,12 @@ void launch_flag(const TQ *q, long long cs, int nx, int ny, int m, const TH *sna
 {
     (void)ny;
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL((flag_kernel<TQ, TH>), dim3(ntiles), dim3(256), 0, s, q, cs, nx, m, snaps, snap_stride, hcs,
-                       NX, NY, ratio, n_lo, n_hi, tol, tiles, flags, count);
+    if (ratio == 1)
+        hipLaunchKernelGGL((flag_kernel<TQ, TH, true>), dim3(ntiles), dim3(256), 0, s, q, cs, nx, m, snaps,
+                           snap_stride, hcs, NX, NY, ratio, n_lo, n_hi, tol, tiles, flags, count);
+    else
+        hipLaunchKernelGGL((flag_kernel<TQ, TH, false>), dim3(ntiles), dim3(256), 0, s, q, cs, nx, m, snaps,
+                           snap_stride, hcs, NX, NY, ratio, n_lo, n_hi, tol, tiles, flags, count);
 }
 
 void launch_flag_mixed(const double *eta, const float *hu, const float *hv, long long cs, int nx, int ny,

@@ -79,7 +79,8 @@ std::vector<Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, 
     for (const auto &p : patches)
         for (int i = 0; i < p.nx; i += width)
             for (int j = 0; j < p.ny; j += rows)
-                t.push_back(Tile{inst, p.ilo + i, p.jlo + j, std::min(width, p.nx - i), std::min(rows, p.ny - j), -1});
+                t.push_back(Tile{inst, p.ilo + i, p.jlo + j, std::min(width, p.nx - i), std::min(rows, p.ny - j), -1,
+                                 (j / rows) & 1});
     if (xcd_order) wp_xcd_order(t);
     return t;
 }
@@ -144,7 +145,8 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
             continue;
         }
         const int hm = acou_mixed_rows(rows);
-        for (int j = 0; j < t.nj; j += hm) out.push_back(Tile{t.inst, t.i0, t.j0 + j, t.ni, std::min(hm, t.nj - j), -1});
+        for (int j = 0; j < t.nj; j += hm)
+            out.push_back(Tile{t.inst, t.i0, t.j0 + j, t.ni, std::min(hm, t.nj - j), -1, ((t.j0 + j) / hm) & 1});
     }
     tiles.swap(out);
 }
@@ -949,7 +951,9 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     const long long cells = (long long)lv.nx * lv.ny;
     int ratio = 1;
     for (int l = 1; l <= level; ++l) ratio *= ctx->L[l].ratio;
-    launch_fill_u8(lv.flags, cells, 0, ctx->stream);
+    // cells outside the patches read 0 (a level covered by one patch has none)
+    const bool full = lv.patches.size() == 1 && lv.patches[0].nx == lv.nx && lv.patches[0].ny == lv.ny;
+    if (!full) launch_fill_u8(lv.flags, cells, 0, ctx->stream);
     if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "count clear");
     const Level &a0 = ctx->adj;

@@ -24,6 +24,9 @@ __host__ __device__ constexpr int acou_mixed_rows(int rows) { return rows >= 8 ?
 struct Tile {
     int inst, i0, j0, ni, nj;
     int mat;   // material of every cell the tile reads (halo included), -1 if mixed
+    int down;  // 2D acoustics: march the rows downwards (alternates between
+               // vertically adjacent tiles, so the halo rows they share are
+               // read by both at about the same time)
 };
 
 // Per-instance description of a 2D (or 1D) acoustics level canvas.  The
