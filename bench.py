@@ -5,7 +5,7 @@ two materials split at x = 0, seeded Gaussian pulse and disc target,
 first-arrival final time, CFL 0.9):
   1. the time-reversed adjoint run from phi with a snapshot every 10 steps,
   2. the forward run from the seeded pulse, flagged against the snapshot
-     window every 10 steps,
+     window every 10 steps (one captured sequence),
   3. the target functional J.
 The metric is forward plus adjoint cell updates per second over the whole
 job, inputs resident in device memory.  Prints one JSON line.
@@ -107,32 +107,20 @@ class Job:
             self.rows, self.tune_us = tune(self.w, cfg["dt"], use_cache=False)
 
     def run(self, time_kernels=False):
-        import torch
         cfg, w = self.cfg, self.w
         N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
         w.adjoint_run(cfg["functional"], dt, N, every)
         w.set_state(self.q0_dev)
-        t = 0.0
-        ev = []
-        for k in range(N // every):
-            w.flag_adjoint(0, cfg["tol"], t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
-            # the `every` steps between flag evaluations replay one captured graph
-            if time_kernels:
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                w.run_graph(every, dt, 1)
-                e1.record()
-                ev.append((e0, e1))
-            else:
-                w.run_graph(every, dt, 1)
-            t += every * dt
+        w.set_time(0.0)
+        # the forward run flagged every `every` steps, one captured sequence;
+        # the first step launch of each block records its own duration on the
+        # device clock (events recorded inside a captured sequence are not
+        # timed by the runtime)
+        _, step_ms = w.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"], want_counts=False,
+                                       want_times=time_kernels)
         J = w.functional_value(cfg["functional"], which=0)
         if time_kernels:
-            torch.cuda.synchronize()
-            # per-launch duration: each bracket holds `every` back-to-back
-            # step kernels (graph launch overhead included, so this is an
-            # upper bound on the kernel's own duration)
-            self.kernel_ms += [a.elapsed_time(b) / every for a, b in ev]
+            self.kernel_ms += step_ms
         return J
 
     def updates(self):
@@ -242,11 +230,8 @@ def swe_compare(steps, warmup, n=2048):
         def job():
             w.adjoint_run(cfg["functional"], dt, N, every)
             w.set_state(q0)
-            t = 0.0
-            for _ in range(N // every):
-                w.flag_adjoint(0, cfg["tol"], t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
-                w.run_graph(every, dt, 1)
-                t += every * dt
+            w.set_time(0.0)
+            w.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"], want_counts=False)
             return w.functional_value(cfg["functional"], 0)
         for _ in range(warmup):
             job()

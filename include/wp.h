@@ -203,6 +203,23 @@ int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device);
 int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, double t_f,
                     uint8_t *flags, int on_device, int64_t *nflagged);
 
+/* The forward run with adjoint-guided flagging (Sec. 4; Sec. 5.1.2) on a
+ * single-level instance: nsteps steps of size dt from the current state and
+ * time t0, with the flag of wp_flag_adjoint(0, tol, t, t_s, t_f) evaluated at
+ * t = t0 + k flag_every dt before each block of flag_every steps
+ * (k = 0 .. nsteps/flag_every - 1), all enqueued as one captured sequence.
+ * counts (optional, host, nsteps/flag_every entries) receives the number of
+ * flagged cells of each event; step_ms (optional, host, same length; 2D
+ * acoustics) the duration of the first step launch of each block on the
+ * device's constant-rate clock: from its earliest workgroup start to that of
+ * the second step (dispatch and completion included), or to its own latest
+ * workgroup end when flag_every is 1.  The flag canvas keeps the last event's flags.
+ * Either output synchronises the stream.  WP_EINVAL if nsteps is not a multiple of
+ * flag_every or the instance has refinement levels; WP_ERANGE if a window
+ * reaches before the first snapshot (nothing is enqueued then). */
+int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_every, double tol, double t_s, double t_f,
+                       int64_t *counts, float *step_ms);
+
 /* Replace the patches of level+1 (Sec. 3 regridding).  patches != NULL: the
  * npatches given boxes (level+1 index space; corners and sides multiples of
  * ratio[level]; disjoint; properly nested: every covered level cell lies in

@@ -95,6 +95,8 @@ _SIGS = {
     "wp_flag_adjoint": (_I, [_P, _I, _D, _D, _D, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
     "wp_regrid": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, _I]),
     "wp_get_patches": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
+    "wp_forward_flagged": (_I, [_P, _D, _I, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_float)]),
     "wp_cluster": (_I, [_P, _P, _I, _I, _D, _I, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
     "wp_functional_value": (_I, [_P, ctypes.POINTER(wp_functional), _I, _I, ctypes.POINTER(_D)]),
     "wp_get_time": (_I, [_P, _I, ctypes.POINTER(_D)]),
@@ -349,6 +351,15 @@ class WavePatch:
         self._check(lib().wp_flag_adjoint(self.h, level, tol, t, t_s, t_f, p, 0,
                                           ctypes.byref(n) if want_count else None))
         return flags, (n.value if want_count else None)
+
+    def forward_flagged(self, dt, nsteps, flag_every, tol, t_s, t_f, want_counts=True, want_times=False):
+        """wp_forward_flagged: (flagged cells per flag event or None,
+        duration in ms of the first step launch of each block or None)."""
+        nev = nsteps // flag_every if flag_every > 0 else 0
+        counts = (ctypes.c_int64 * max(1, nev))() if want_counts else None
+        times = (ctypes.c_float * max(1, nev))() if want_times else None
+        self._check(lib().wp_forward_flagged(self.h, dt, nsteps, flag_every, tol, t_s, t_f, counts, times))
+        return (list(counts[:nev]) if want_counts else None), (list(times[:nev]) if want_times else None)
 
     def regrid(self, level, patches=None, buffer=0):
         if patches is None:

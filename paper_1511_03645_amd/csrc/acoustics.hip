@@ -642,11 +642,16 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
 // KIND 0: each tile takes the single-material or the mixed path as flagged;
 // KIND 1: every tile is single-material (the lean march alone sets the
 // register count and so the occupancy).
+// stamp (optional): workgroup b writes its start and end on the device's
+// constant-rate clock to stamp[2b] and stamp[2b + 1] (one slot each, no
+// contention), from which the launch's own duration is read back.
 template <typename T, bool ADJ, bool FULL, int RT, int KIND>
 __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int parity,
-                                                      int snap_index, int *__restrict__ status)
+                                                      int snap_index, int *__restrict__ status,
+                                                      unsigned long long *__restrict__ stamp)
 {
+    if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x] = (unsigned long long)wall_clock64();
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile tl = tiles[blockIdx.x];
     const AcouInst<T> *__restrict__ Ip = insts + tl.inst;
@@ -686,6 +691,7 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
                                                         qw, mr, sw, snap, bad);
     }
     if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
+    if (stamp && lane == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
 }
 
 // 1D: one thread per cell, the five-cell stencil read straight from memory.
@@ -768,13 +774,14 @@ static size_t acou_smem(int nmat)
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint, int nmat_max,
-                   bool full, int rows, int kind, int snap_index, int *status, hipStream_t s)
+                   bool full, int rows, int kind, int snap_index, int *status, hipStream_t s, unsigned long long *stamp)
 {
     if (ntiles <= 0) return;
     const size_t sm = acou_smem<T>(nmat_max);
     const dim3 g(ntiles), b(WAVE);
-#define WP_LAUNCH(ADJ, FULL, RT, KIND) \
-    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap_index, status)
+#define WP_LAUNCH(ADJ, FULL, RT, KIND)                                                                       \
+    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap_index, status, \
+                       stamp)
     // tile heights 4, 6, 8, 12 and 16 have a compile-time march; any other
     // height takes the runtime march
 #define WP_BY_RT(ADJ, KIND)                              \
@@ -810,9 +817,9 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &h, int parity
 }
 
 template void launch_acou2d<double>(const AcouInst<double> *, const Tile *, int, int, int, int, bool, int, int,
-                                    int, int *, hipStream_t);
+                                    int, int *, hipStream_t, unsigned long long *);
 template void launch_acou2d<float>(const AcouInst<float> *, const Tile *, int, int, int, int, bool, int, int,
-                                   int, int *, hipStream_t);
+                                   int, int *, hipStream_t, unsigned long long *);
 template void launch_acou1d<double>(const AcouInst<double> *, const AcouInst<double> &, int, int, int, int *,
                                     hipStream_t);
 template void launch_acou1d<float>(const AcouInst<float> *, const AcouInst<float> &, int, int, int, int *,

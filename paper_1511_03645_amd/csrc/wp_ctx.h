@@ -102,6 +102,16 @@ struct wp_ctx {
     unsigned long long bo_gen = 0;
     std::vector<int> bo_par;
     unsigned long long topo_gen = 1;         // bumped whenever a tile table changes
+    hipGraphExec_t ff_exec = nullptr;        // flagged forward run
+    double ff_key[6] = {0, 0, 0, 0, 0, 0}, ff_t0 = 0.0;
+    int ff_parity = -1;
+    unsigned long long ff_gen = 0;
+    const void *ff_snaps = nullptr;
+    unsigned long long *ev_counts = nullptr;   // flagged cells per flag event
+    size_t ev_counts_cap = 0;
+    unsigned long long *stamps = nullptr;      // workgroup clocks of the timed steps
+    size_t stamps_cap = 0;
+    unsigned long long *stamp_next = nullptr;  // clock slot for the next 2D acoustics launch
     hipGraphExec_t adj_exec = nullptr;       // adjoint run with snapshot copies
     int adj_steps = 0, adj_every = 0;
     double adj_dt = 0.0;

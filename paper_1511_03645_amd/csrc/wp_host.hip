@@ -403,6 +403,7 @@ extern "C" void wp_destroy(wp_ctx *ctx)
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->adj_exec) (void)hipGraphExecDestroy(ctx->adj_exec);
     if (ctx->bo_exec) (void)hipGraphExecDestroy(ctx->bo_exec);
+    if (ctx->ff_exec) (void)hipGraphExecDestroy(ctx->ff_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     std::vector<void *> all = ctx->owned;
     for (void *p : all) wp_dfree(ctx, p);
@@ -616,7 +617,8 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
         // one launch: a single-material level runs the lean kernel, any other
         // the kernel that picks the path per tile
         launch_acou2d<T>(I, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, full, lv.tile_rows,
-                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream);
+                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream, ctx->stamp_next);
+        ctx->stamp_next = nullptr;   // consumed by this launch only
     }
     else
         launch_acou1d<T>((const AcouInst<T> *)lv.inst, *(const AcouInst<T> *)lv.inst_host, lv.cur, adjoint, snap_index,
@@ -940,6 +942,41 @@ int wp_window(wp_ctx *ctx, double t, double t_s, double t_f, int &n_lo, int &n_h
     return WP_OK;
 }
 
+// Enqueue the flag of `level` for snapshot window [n_lo, n_hi] on stream s,
+// adding the number of flagged cells to *count (which the caller clears).
+static int flag_launch(wp_ctx *ctx, int level, double tol, int n_lo, int n_hi, unsigned long long *count,
+                       hipStream_t s)
+{
+    Level &lv = ctx->L[level];
+    const long long cells = (long long)lv.nx * lv.ny;
+    int ratio = 1;
+    for (int l = 1; l <= level; ++l) ratio *= ctx->L[l].ratio;
+    // cells outside the patches read 0 (a level covered by one patch has none)
+    const bool full = lv.patches.size() == 1 && lv.patches[0].nx == lv.nx && lv.patches[0].ny == lv.ny;
+    if (!full) launch_fill_u8(lv.flags, cells, 0, s);
+    const Level &a0 = ctx->adj;
+    const long long hcs = (long long)a0.nx * a0.ny;
+    const long long sstride = hcs * ctx->m;
+    if (ctx->prob.precision == WP_MIXED) {
+        launch_flag_mixed((const double *)lv.q[lv.cur], (const float *)((char *)lv.q[lv.cur] + cells * 8),
+                          (const float *)((char *)lv.q[lv.cur] + cells * 12), cells, lv.nx, lv.ny,
+                          (const float *)ctx->snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
+                          lv.flags, count, s);
+    } else if (ctx->esz == 8) {
+        launch_flag<double, double>((const double *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m,
+                                    (const double *)ctx->snaps, sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol,
+                                    lv.ftiles_dev, lv.nftiles, lv.flags, count, s);
+    } else {
+        launch_flag<float, float>((const float *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m, (const float *)ctx->snaps,
+                                  sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
+                                  lv.flags, count, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag launch: %s", hipGetErrorString(e));
+    lv.flags_valid = true;
+    return WP_OK;
+}
+
 extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, double t_f, uint8_t *flags,
                                int on_device, int64_t *nflagged)
 {
@@ -949,32 +986,9 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     if ((rc = wp_window(ctx, t, t_s, t_f, n_lo, n_hi)) != WP_OK) return rc;
     Level &lv = ctx->L[level];
     const long long cells = (long long)lv.nx * lv.ny;
-    int ratio = 1;
-    for (int l = 1; l <= level; ++l) ratio *= ctx->L[l].ratio;
-    // cells outside the patches read 0 (a level covered by one patch has none)
-    const bool full = lv.patches.size() == 1 && lv.patches[0].nx == lv.nx && lv.patches[0].ny == lv.ny;
-    if (!full) launch_fill_u8(lv.flags, cells, 0, ctx->stream);
     if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "count clear");
-    const Level &a0 = ctx->adj;
-    const long long hcs = (long long)a0.nx * a0.ny;
-    const long long sstride = hcs * ctx->m;
-    if (ctx->prob.precision == WP_MIXED) {
-        launch_flag_mixed((const double *)lv.q[lv.cur], (const float *)((char *)lv.q[lv.cur] + cells * 8),
-                          (const float *)((char *)lv.q[lv.cur] + cells * 12), cells, lv.nx, lv.ny,
-                          (const float *)ctx->snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
-                          lv.flags, ctx->count, ctx->stream);
-    } else if (ctx->esz == 8) {
-        launch_flag<double, double>((const double *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m,
-                                    (const double *)ctx->snaps, sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol,
-                                    lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count, ctx->stream);
-    } else {
-        launch_flag<float, float>((const float *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m, (const float *)ctx->snaps,
-                                  sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
-                                  lv.flags, ctx->count, ctx->stream);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag launch: %s", hipGetErrorString(e));
+    if ((rc = flag_launch(ctx, level, tol, n_lo, n_hi, ctx->count, ctx->stream)) != WP_OK) return rc;
     if (flags && hipMemcpyAsync(flags, lv.flags, (size_t)cells, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                 ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "flag copy");
@@ -987,8 +1001,129 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     } else if (flags && !on_device) {
         if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag sync");
     }
-    lv.flags_valid = true;
     return WP_OK;
+}
+
+// The flagged forward run as one captured sequence: a clear of the event
+// counters, then per event the flag at the block's start time and the
+// block's steps, the first two of which record their workgroups' start and
+// end times on the device clock.  Re-captured when any parameter,
+// the start time, the canvas parity or a tile table changes.
+extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_every, double tol, double t_s,
+                                  double t_f, int64_t *counts, float *step_ms)
+{
+    if (!ctx) return WP_EINVAL;
+    if (ctx->L.size() != 1) return wp_fail(ctx, WP_EINVAL, "flagged forward runs are for single-level instances");
+    if (flag_every < 1 || nsteps < 0 || nsteps % flag_every != 0)
+        return wp_fail(ctx, WP_EINVAL, "nsteps must be a non-negative multiple of flag_every >= 1");
+    Level &lv = ctx->L[0];
+    int rc;
+    if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
+    const int nev = nsteps / flag_every;
+    if (nev == 0) return WP_OK;
+    // every window is checked before anything is enqueued
+    std::vector<int> lo(nev), hi(nev);
+    for (int k = 0; k < nev; ++k)
+        if ((rc = wp_window(ctx, lv.t + (double)k * flag_every * dt, t_s, t_f, lo[k], hi[k])) != WP_OK) return rc;
+    if ((int)ctx->ev_counts_cap < nev) {
+        if (ctx->ev_counts) wp_dfree(ctx, ctx->ev_counts);
+        ctx->ev_counts = (unsigned long long *)wp_dalloc(ctx, sizeof(unsigned long long) * nev);
+        if (!ctx->ev_counts) {
+            ctx->ev_counts_cap = 0;
+            return wp_fail(ctx, WP_ENOMEM, "flag counters");
+        }
+        ctx->ev_counts_cap = nev;
+        ctx->ff_gen = 0;   // pointer changed
+    }
+    // launch clocks: one (start, end) slot per workgroup of the first two
+    // steps of every block
+    const size_t nslot = 2 * (size_t)std::max(lv.ntiles, 1);
+    const int ntimed = flag_every >= 2 ? 2 : 1;
+    if (ctx->stamps_cap < (size_t)nev * ntimed * nslot) {
+        if (ctx->stamps) wp_dfree(ctx, ctx->stamps);
+        ctx->stamps = (unsigned long long *)wp_dalloc(ctx, sizeof(unsigned long long) * nslot * ntimed * nev);
+        if (!ctx->stamps) {
+            ctx->stamps_cap = 0;
+            return wp_fail(ctx, WP_ENOMEM, "launch clocks");
+        }
+        ctx->stamps_cap = (size_t)nev * ntimed * nslot;
+        ctx->ff_gen = 0;   // pointer changed
+    }
+    const double key[6] = {dt, (double)nsteps, (double)flag_every, tol, t_s, t_f};
+    if (!ctx->ff_exec || memcmp(key, ctx->ff_key, sizeof key) != 0 || ctx->ff_t0 != lv.t ||
+        ctx->ff_parity != lv.cur || ctx->ff_gen != ctx->topo_gen || ctx->ff_snaps != ctx->snaps) {
+        if ((rc = wp_prepare_level(ctx, lv, dt)) != WP_OK) return rc;
+        hipStream_t s;
+        if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
+        const int par = lv.cur;
+        launch_fill_u8((uint8_t *)ctx->ev_counts, (long long)sizeof(unsigned long long) * nev, 0, s);
+        for (int k = 0; k < nev && rc == WP_OK; ++k) {
+            rc = flag_launch(ctx, 0, tol, lo[k], hi[k], ctx->ev_counts + k, s);
+            for (int st = 0; st < flag_every && rc == WP_OK; ++st) {
+                if (st < ntimed && ctx->is_acoustics && ctx->kind2d)
+                    ctx->stamp_next = ctx->stamps + nslot * ((size_t)ntimed * k + st);
+                rc = wp_step_level(ctx, lv, dt, 0, s, -1);
+            }
+        }
+        ctx->stamp_next = nullptr;
+        lv.cur = par;
+        const int rc2 = wp_graph_end(ctx, s, ctx->ff_exec);
+        if (rc != WP_OK) return rc;
+        if (rc2 != WP_OK) return rc2;
+        memcpy(ctx->ff_key, key, sizeof key);
+        ctx->ff_t0 = lv.t;
+        ctx->ff_parity = par;
+        ctx->ff_gen = ctx->topo_gen;
+        ctx->ff_snaps = ctx->snaps;
+    }
+    if ((rc = wp_graph_launch(ctx, ctx->ff_exec)) != WP_OK) return rc;
+    lv.cur = (lv.cur + nsteps) & 1;
+    lv.t_prev = lv.t + (double)(nsteps - 1) * dt;
+    lv.prev_valid = true;
+    lv.t += (double)nsteps * dt;
+    if (counts || step_ms) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flagged run sync");
+        if (counts) {
+            std::vector<unsigned long long> c(nev);
+            if (hipMemcpy(c.data(), ctx->ev_counts, sizeof(unsigned long long) * nev, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return wp_fail(ctx, WP_EDEVICE, "count read");
+            for (int k = 0; k < nev; ++k) counts[k] = (int64_t)c[k];
+        }
+        if (step_ms) {
+            if (!(ctx->is_acoustics && ctx->kind2d)) return wp_fail(ctx, WP_EINVAL, "launch times are for 2D acoustics");
+            std::vector<unsigned long long> st(nslot * ntimed * nev);
+            int khz = 0, dev = 0;
+            if (hipMemcpy(st.data(), ctx->stamps, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost) !=
+                    hipSuccess ||
+                hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+                return wp_fail(ctx, WP_EDEVICE, "launch clock read");
+            // earliest workgroup start and latest end of timed launch i
+            auto window = [&](size_t i, unsigned long long &t0, unsigned long long &t1) {
+                t0 = ~0ULL;
+                t1 = 0;
+                for (size_t b = 0; b < nslot / 2; ++b) {
+                    t0 = std::min(t0, st[nslot * i + 2 * b]);
+                    t1 = std::max(t1, st[nslot * i + 2 * b + 1]);
+                }
+            };
+            for (int k = 0; k < nev; ++k) {
+                unsigned long long a0, a1, b0, b1;
+                window((size_t)ntimed * k, a0, a1);
+                // launch duration: from its first workgroup start to that of
+                // the next launch (dispatch and completion included); the
+                // workgroup window alone when a block has one step
+                unsigned long long d = a1 - a0;
+                if (ntimed == 2) {
+                    window((size_t)ntimed * k + 1, b0, b1);
+                    d = b0 - a0;
+                }
+                step_ms[k] = (float)((double)d / (double)khz);
+            }
+        }
+    }
+    return wp_check_status(ctx);
 }
 
 // ---------------------------------------------------------------------------

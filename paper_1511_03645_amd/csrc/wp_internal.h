@@ -88,7 +88,8 @@ constexpr int ST_CFL = 2;
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
-                   int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s);
+                   int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s,
+                   unsigned long long *stamp = nullptr);
 template <typename T>
 void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, int parity, int adjoint,
                    int snap_index, int *status, hipStream_t s);

@@ -259,6 +259,38 @@ def test_graphs_recaptured_after_tile_change():
             close64(w2.get_snapshot(k), snaps_ref[k], f"snapshot {k} with rows {rows}")
 
 
+def test_forward_flagged_equals_flag_and_step_loop():
+    """The flagged forward run as one captured sequence gives the per-event
+    counts, the final flags and the final state of the loop of
+    wp_flag_adjoint and eager steps (itself checked against the oracle),
+    bit for bit, on repeated runs, with timing events that add up."""
+    cfg = acoustics2d(n=128, seed=1)
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    loop, fused = wp.from_config(cfg), wp.from_config(cfg)
+    for w in (loop, fused):
+        w.adjoint_run(cfg["functional"], dt, N, every)
+    for rep in range(2):
+        for w in (loop, fused):
+            w.set_state(cfg["q0"])
+            w.set_time(0.0)
+        counts = []
+        t = 0.0
+        for _ in range(N // every):
+            fl, n = loop.flag_adjoint(0, cfg["tol"], t, cfg["t_s"], cfg["t_f"])
+            counts.append(n)
+            for _ in range(every):
+                loop.step_patches(0, dt)
+            t += every * dt
+        got, ms = fused.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"], want_times=True)
+        assert got == counts, f"run {rep}"
+        assert sum(counts) > 0
+        assert all(x > 0.0 for x in ms)
+        assert np.array_equal(fused.get_state(), loop.get_state()), f"run {rep}"
+        assert abs(fused.get_time() - loop.get_time()) < 1e-12
+    with pytest.raises(wp.WPError):
+        fused.forward_flagged(dt, N + 3, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+
+
 def test_adjoint_run_replay_is_identical():
     cfg = acoustics2d(n=96, seed=1)
     w = wp.from_config(cfg)
