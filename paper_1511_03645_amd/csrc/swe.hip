@@ -3,51 +3,31 @@
 // shallow-water adjoint (Sec. 5.3 linearised system, Sec. 2/4 adjoint and
 // time reversal), for gfx950.
 //
-// Layout: one 128-thread workgroup per 16 x 8 output tile.  Phase A loads
-// the tile and its two-cell halo into LDS (ghosts resolved by the boundary
-// rules); phase B solves every x- and y-edge Riemann problem the tile needs
-// once, keeping f-waves, speeds and Roe states in LDS; phase C forms the
-// limited correction fluxes with the transverse terms, one thread per edge;
-// phase D updates one cell per thread.
+// Layout (the strip march of the acoustics kernels): one 64-lane wave owns a
+// strip of 64 columns (60 outputs and a two-column halo on each side) and
+// marches up the rows of its tile.  Every x- and y-edge Riemann problem is
+// solved once; quantities of neighbouring columns' edges (upwind waves for
+// the limiter, transverse splits, fluctuations, correction fluxes) move
+// across lanes by DPP shifts, and those of the y-edges below are carried in
+// registers.  Ghost cells are resolved in the loader.
 //
 // Mixed precision (ETA = double, T = float): eta = h + B is stored and
 // updated in FP64 and the well-balanced term g hbar d(eta) is formed in FP64,
 // so a lake at rest stays exactly at rest and metre-scale waves are not lost
 // against 4000 m of depth; the waves, limiter and transverse terms run in
 // FP32.
-#include "wp_internal.h"
+#include "march_common.h"
 
 namespace wp {
 namespace {
 
-constexpr int TX = SWE_TX, TY = SWE_TY;
-constexpr int SX = TX + 4, SY = TY + 4;          // state region with halo
-constexpr int NS = SX * SY;
-constexpr int EXW = TX + 3, EXH = TY + 2;        // x-edges li in [-1, TX+1], lj in [-1, TY]
-constexpr int EYW = TX + 2, EYH = TY + 3;        // y-edges li in [-1, TX],   lj in [-1, TY+1]
-constexpr int NEX = EXW * EXH, NEY = EYW * EYH;
-constexpr int NT = 128;
+using namespace march;
 
-__device__ __forceinline__ int sidx(int li, int lj) { return (li + 2) + (lj + 2) * SX; }
-__device__ __forceinline__ int exid(int li, int lj) { return (li + 1) + (lj + 1) * EXW; }
-__device__ __forceinline__ int eyid(int li, int lj) { return (li + 1) + (lj + 1) * EYW; }
-
-__device__ __forceinline__ int resolve(int i, int n, int bclo, int bchi, bool &flip)
-{
-    i = min(max(i, -2), n + 1);
-    flip = false;
-    if (i < 0) {
-        if (bclo == WP_BC_PERIODIC) return i + n;
-        if (bclo == WP_BC_WALL) { flip = true; return -1 - i; }
-        return 0;
-    }
-    if (i >= n) {
-        if (bchi == WP_BC_PERIODIC) return i - n;
-        if (bchi == WP_BC_WALL) { flip = true; return 2 * n - 1 - i; }
-        return n - 1;
-    }
-    return i;
-}
+// Rows requested ahead of their first use in the compile-time march.
+constexpr int PREFETCH = 3;
+// sched_barrier mask: ALU instructions and memory writes may be moved across,
+// memory reads may not.
+constexpr int SCHED_KEEP_LOADS = 0x0001 | 0x0040;
 
 template <typename T>
 __device__ __forceinline__ T mc_phi(T theta)
@@ -64,16 +44,143 @@ __device__ __forceinline__ T lim_factor(const T *w, const T *wu, int limiter)
     if (limiter == 0) return T(1);
     const T a = wu[0] * w[0] + wu[1] * w[1] + wu[2] * w[2];
     const T b = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-    if (b == T(0)) return T(0);
-    return mc_phi(a / b);
+    return b == T(0) ? T(0) : mc_phi(a / b);
 }
 
 template <typename T>
 __device__ __forceinline__ T sgn(T s) { return s > T(0) ? T(1) : (s < T(0) ? T(-1) : T(0)); }
 
-// Transverse split (constant Roe state) of d along direction tdir with the
-// eigen-structure of that direction at Roe state (uh, vh, c): returns the
-// part with negative speeds (neg = true) or positive speeds.
+// Second-order correction flux of an edge with NW waves w[3 p + k] at speeds
+// s[p]: per family the upwind wave is that of the lower/left neighbour edge
+// (wlo) for s > 0, else of the upper/right one (whi); nu = dt/dx of the
+// edge's direction.
+template <int NW, typename T>
+__device__ __forceinline__ void corr_flux(const T *w, const T *s, const T *wlo, const T *whi, T nu, int lim, T F[3])
+{
+#pragma unroll
+    for (int p = 0; p < NW; ++p) {
+        T wu[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) wu[k] = s[p] > T(0) ? wlo[3 * p + k] : whi[3 * p + k];
+        const T phi = lim_factor(&w[3 * p], wu, lim);
+        const T coef = T(0.5) * sgn(s[p]) * (T(1) - nu * fabs(s[p]));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) F[k] += coef * (phi * w[3 * p + k]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void sub_scaled(T F[3], T a, const T o[3])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] -= a * o[k];
+}
+
+// ---------------------------------------------------------------------------
+// nonlinear shallow water
+// ---------------------------------------------------------------------------
+
+// A cell as loaded (momenta already reflected for wall ghosts) ...
+template <typename ETA, typename T>
+struct SRaw {
+    ETA eta;
+    double B;
+    T hu, hv;
+};
+
+// ... and with the quantities derived from it once.
+template <typename ETA, typename T>
+struct SRow {
+    ETA eta, he;   // surface elevation and depth h = eta - B, in the eta precision
+    T h, hu, hv, u, v, sq;
+};
+
+template <typename ETA, typename T>
+__device__ __forceinline__ SRow<ETA, T> derive(const SRaw<ETA, T> &a, int &bad)
+{
+    SRow<ETA, T> r;
+    r.eta = a.eta;
+    r.he = a.eta - (ETA)a.B;
+    r.h = (T)r.he;
+    r.hu = a.hu;
+    r.hv = a.hv;
+    r.u = r.hu / r.h;
+    r.v = r.hv / r.h;
+    r.sq = sqrt(r.h);
+    bad |= !(r.h > T(0));
+    return r;
+}
+
+template <typename ETA, typename T>
+__device__ __forceinline__ SRow<ETA, T> shift_left(const SRow<ETA, T> &r)
+{
+    return SRow<ETA, T>{from_left(r.eta), from_left(r.he), from_left(r.h), from_left(r.hu),
+                        from_left(r.hv), from_left(r.u), from_left(r.v), from_left(r.sq)};
+}
+
+// An edge: f-waves w[3 p + k] at speeds s[p], and the Roe state (u, v, c)
+// that splits fluctuations transversally.
+template <typename T>
+struct SEdge {
+    T w[9];
+    T s[3];
+    T ru, rv, c;
+};
+
+// Roe f-wave solve at the edge between L and R in direction DIR (0: x,
+// 1: y).  The flux difference uses 1/2 g (h_R^2 - h_L^2) + g hbar dB =
+// g hbar d(eta), formed in the eta precision, so a lake at rest gives zero
+// waves exactly.
+template <int DIR, typename ETA, typename T>
+__device__ __forceinline__ SEdge<T> roe_edge(const SRow<ETA, T> &L, const SRow<ETA, T> &R, double g)
+{
+    constexpr int n = DIR == 0 ? 1 : 2, t = DIR == 0 ? 2 : 1;
+    const T unl = DIR == 0 ? L.u : L.v, unr = DIR == 0 ? R.u : R.v;
+    const T utl = DIR == 0 ? L.v : L.u, utr = DIR == 0 ? R.v : R.u;
+    const T qnl = DIR == 0 ? L.hu : L.hv, qnr = DIR == 0 ? R.hu : R.hv;
+    const T hbar = T(0.5) * (L.h + R.h);
+    const T un = (L.sq * unl + R.sq * unr) / (L.sq + R.sq);
+    const T ut = (L.sq * utl + R.sq * utr) / (L.sq + R.sq);
+    const T c = sqrt(T(g) * hbar);
+    const ETA hbe = ETA(0.5) * (L.he + R.he);
+    const T wb = (T)(ETA(g) * hbe * (R.eta - L.eta));
+    const T d1 = qnr - qnl;
+    const T d2 = (qnr * unr - qnl * unl) + wb;
+    const T d3 = qnr * utr - qnl * utl;
+    const T s1 = un - c, s3 = un + c;
+    const T inv2c = T(0.5) / c;
+    const T b1 = ((un + c) * d1 - d2) * inv2c;
+    const T b3 = (d2 - (un - c) * d1) * inv2c;
+    const T b2 = d3 - ut * d1;
+    SEdge<T> e;
+    e.w[0] = b1; e.w[n] = b1 * s1; e.w[t] = b1 * ut;
+    e.w[3] = T(0); e.w[3 + n] = T(0); e.w[3 + t] = b2;
+    e.w[6] = b3; e.w[6 + n] = b3 * s3; e.w[6 + t] = b3 * ut;
+    e.s[0] = s1; e.s[1] = un; e.s[2] = s3;
+    e.ru = DIR == 0 ? un : ut;
+    e.rv = DIR == 0 ? ut : un;
+    e.c = c;
+    return e;
+}
+
+// fluctuation of an edge: waves with negative speed (neg) or positive speed,
+// zero-speed waves split evenly
+template <typename T>
+__device__ __forceinline__ void fluct(const SEdge<T> &E, bool neg, T out[3])
+{
+    out[0] = out[1] = out[2] = T(0);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const T s = E.s[p];
+        const T f = s < T(0) ? (neg ? T(1) : T(0)) : (s > T(0) ? (neg ? T(0) : T(1)) : T(0.5));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[k] += f * E.w[p * 3 + k];
+    }
+}
+
+// Transverse split of d along direction tdir with the eigen-structure of
+// that direction at the Roe state (uh, vh, c) of the edge d came from: the
+// part carried by negative speeds (neg) or by non-negative speeds.
 template <typename T>
 __device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T c, bool neg, T out[3])
 {
@@ -85,283 +192,339 @@ __device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T
     const T g2 = d[ko] - vo * d[0];
     const T l1 = vt - c, l2 = vt, l3 = vt + c;
     T o[3] = {T(0), T(0), T(0)};
-    if ((l1 < T(0)) == neg && (neg || l1 >= T(0))) {
+    if ((l1 < T(0)) == neg) {
         o[0] += l1 * g1; o[kt] += l1 * g1 * (vt - c); o[ko] += l1 * g1 * vo;
     }
-    if ((l2 < T(0)) == neg && (neg || l2 >= T(0))) {
+    if ((l2 < T(0)) == neg) {
         o[ko] += l2 * g2;
     }
-    if ((l3 < T(0)) == neg && (neg || l3 >= T(0))) {
+    if ((l3 < T(0)) == neg) {
         o[0] += l3 * g3; o[kt] += l3 * g3 * (vt + c); o[ko] += l3 * g3 * vo;
     }
     out[0] = o[0]; out[1] = o[1]; out[2] = o[2];
 }
 
-template <typename ETA, typename T>
-struct SweSmem {
-    // the tile state is dead once the edges are solved, so the correction
-    // fluxes reuse its space
-    union {
-        struct {
-            ETA eta[NS];
-            ETA he[NS];      // h = eta - B in the eta precision
-            T h[NS], hu[NS], hv[NS], u[NS], v[NS], sq[NS];
-        };
-        struct {
-            T F[3][(TX + 1) * TY];
-            T G[3][TX * (TY + 1)];
-        };
-    };
-    T ex[15][NEX];   // x-edges: waves [9], speeds [3], Roe state (u, v, c) [3]
-    T ey[15][NEY];
+// An x-edge with its fluctuations A+dQ (ap) and A-dQ (am) and their splits
+// along y: down-going parts (apd, amd) and up-going parts (apu, amu).
+template <typename T>
+struct XEdge {
+    SEdge<T> e;
+    T ap[3], am[3];
+    T apd[3], amd[3], apu[3], amu[3];
 };
 
 template <typename ETA, typename T>
-__device__ __forceinline__ void edge_solve(SweSmem<ETA, T> &S, int dir, int il, int ir, double g, T *dst, int e,
-                                           int nedge)
+__device__ __forceinline__ XEdge<T> x_edge(const SRow<ETA, T> &R, double g, bool trans)
 {
-    const int n = dir == 0 ? 1 : 2, t = dir == 0 ? 2 : 1;
-    const T hl = S.h[il], hr = S.h[ir];
-    const T sl = S.sq[il], sr = S.sq[ir];
-    const T unl = dir == 0 ? S.u[il] : S.v[il], unr = dir == 0 ? S.u[ir] : S.v[ir];
-    const T utl = dir == 0 ? S.v[il] : S.u[il], utr = dir == 0 ? S.v[ir] : S.u[ir];
-    const T qnl = dir == 0 ? S.hu[il] : S.hv[il], qnr = dir == 0 ? S.hu[ir] : S.hv[ir];
-    const T hbar = T(0.5) * (hl + hr);
-    const T un = (sl * unl + sr * unr) / (sl + sr);
-    const T ut = (sl * utl + sr * utr) / (sl + sr);
-    const T c = sqrt(T(g) * hbar);
-    // well-balanced term g hbar d(eta) in the eta precision
-    const ETA hbe = ETA(0.5) * (S.he[il] + S.he[ir]);
-    const T wb = (T)(ETA(g) * hbe * (S.eta[ir] - S.eta[il]));
-    const T d1 = qnr - qnl;
-    const T d2 = (qnr * unr - qnl * unl) + wb;
-    const T d3 = qnr * utr - qnl * utl;
-    const T s1 = un - c, s3 = un + c;
-    const T inv2c = T(0.5) / c;
-    const T b1 = ((un + c) * d1 - d2) * inv2c;
-    const T b3 = (d2 - (un - c) * d1) * inv2c;
-    const T b2 = d3 - ut * d1;
-    T w[9];
-    w[0] = b1; w[n] = b1 * s1; w[t] = b1 * ut;
-    w[3] = T(0); w[3 + n] = T(0); w[3 + t] = b2;
-    w[6] = b3; w[6 + n] = b3 * s3; w[6 + t] = b3 * ut;
-    for (int k = 0; k < 9; ++k) dst[k * nedge + e] = w[k];
-    dst[9 * nedge + e] = s1;
-    dst[10 * nedge + e] = un;
-    dst[11 * nedge + e] = s3;
-    dst[12 * nedge + e] = dir == 0 ? un : ut;   // Roe u
-    dst[13 * nedge + e] = dir == 0 ? ut : un;   // Roe v
-    dst[14 * nedge + e] = c;
+    XEdge<T> x;
+    x.e = roe_edge<0>(shift_left(R), R, g);
+    fluct(x.e, false, x.ap);
+    fluct(x.e, true, x.am);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x.apd[k] = x.amd[k] = x.apu[k] = x.amu[k] = T(0);
+    if (trans) {
+        swe_tsplit(1, x.ap, x.e.ru, x.e.rv, x.e.c, true, x.apd);
+        swe_tsplit(1, x.am, x.e.ru, x.e.rv, x.e.c, true, x.amd);
+        swe_tsplit(1, x.ap, x.e.ru, x.e.rv, x.e.c, false, x.apu);
+        swe_tsplit(1, x.am, x.e.ru, x.e.rv, x.e.c, false, x.amu);
+    }
+    return x;
 }
 
-// fluctuations of an edge: waves with negative speed (neg) or positive speed,
-// zero-speed waves split evenly
+// The y-edge below a row as the row's update needs it: B+dQ (bp) and its
+// splits along x, left-going (lft) and right-going (rgt).
 template <typename T>
-__device__ __forceinline__ void fluct(const T *E, int e, int nedge, bool neg, T out[3])
+struct YUp {
+    T w[9];
+    T bp[3], lft[3], rgt[3];
+};
+
+template <typename T>
+__device__ __forceinline__ YUp<T> y_up(const SEdge<T> &E, bool trans)
 {
-    out[0] = out[1] = out[2] = T(0);
-    for (int p = 0; p < 3; ++p) {
-        const T s = E[(9 + p) * nedge + e];
-        const T f = s < T(0) ? (neg ? T(1) : T(0)) : (s > T(0) ? (neg ? T(0) : T(1)) : T(0.5));
-        for (int k = 0; k < 3; ++k) out[k] += f * E[(p * 3 + k) * nedge + e];
+    YUp<T> y;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) y.w[k] = E.w[k];
+    fluct(E, false, y.bp);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y.lft[k] = y.rgt[k] = T(0);
+    if (trans) {
+        swe_tsplit(0, y.bp, E.ru, E.rv, E.c, true, y.lft);
+        swe_tsplit(0, y.bp, E.ru, E.rv, E.c, false, y.rgt);
     }
+    return y;
 }
+
+template <typename T>
+__device__ __forceinline__ T edge_cfl(const T s[3], T nu)
+{
+    return fmax(fmax(fabs(s[0]) * nu, fabs(s[1]) * nu), fabs(s[2]) * nu);
+}
+
+// What one row's update hands to the next.
+template <typename T>
+struct SCarry {
+    YUp<T> ym;      // y-edge j - 1/2
+    SEdge<T> yp;    // y-edge j + 1/2
+    XEdge<T> xe;    // x-edge (col - 1/2, j)
+    T Gp[3];        // correction flux at y-edge j - 1/2
+};
+
+struct SOpts {
+    bool second, trans;
+    int lim;
+};
 
 template <typename ETA, typename T>
-__global__ __launch_bounds__(NT) void swe2d_kernel(const SweInst<ETA, T> *__restrict__ inst,
-                                                   const Tile *__restrict__ tiles, int parity,
-                                                   int *__restrict__ status, unsigned *__restrict__ cflbits)
+__device__ __forceinline__ void swe_start(const SRow<ETA, T> &Ra, const SRow<ETA, T> &R0, const SRow<ETA, T> &R1,
+                                          double g, const SOpts &op, SCarry<T> &c)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    SweSmem<ETA, T> &S = *reinterpret_cast<SweSmem<ETA, T> *>(smem_raw);
+    c.ym = y_up(roe_edge<1>(Ra, R0, g), op.trans);
+    c.yp = roe_edge<1>(R0, R1, g);
+    c.xe = x_edge(R0, g, op.trans);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.Gp[k] = T(0);
+}
+
+// Update of row j (R0) from rows j, j+1 (R1) and j+2 (R2) and the carry;
+// cx_in / cy_in: whether this row's x-edges / the y-edge j + 1/2 count
+// toward the Courant number.
+template <typename ETA, typename T>
+__device__ __forceinline__ void swe_row(const SRow<ETA, T> &R0, const SRow<ETA, T> &R1, const SRow<ETA, T> &R2,
+                                        double g, T nux, T nuy, const SOpts &op, bool cx_in, bool cy_in,
+                                        SCarry<T> &c, T &cfl, ETA &en, T &qun, T &qvn)
+{
+    const SEdge<T> yn = roe_edge<1>(R1, R2, g);   // y-edge j + 3/2
+    const XEdge<T> xn = x_edge(R1, g, op.trans);  // x-edge (col - 1/2, j + 1)
+    const T hx = T(0.5) * nux, hy = T(0.5) * nuy;
+    // correction flux F at the x-edge (col - 1/2, j)
+    T F[3] = {T(0), T(0), T(0)};
+    if (cx_in) cfl = fmax(cfl, edge_cfl(c.xe.e.s, nux));
+    if (op.second) {
+        T wl[9], wr[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            wl[k] = from_left(c.xe.e.w[k]);
+            wr[k] = from_right(c.xe.e.w[k]);
+        }
+        corr_flux<3>(c.xe.e.w, c.xe.e.s, wl, wr, nux, op.lim, F);
+    }
+    // B-dQ of the y-edge j + 1/2 into this cell and its splits along x
+    T bm[3], bml[3] = {T(0), T(0), T(0)}, bmr[3] = {T(0), T(0), T(0)};
+    fluct(c.yp, true, bm);
+    if (op.trans) {
+        swe_tsplit(0, bm, c.yp.ru, c.yp.rv, c.yp.c, true, bml);
+        swe_tsplit(0, bm, c.yp.ru, c.yp.rv, c.yp.c, false, bmr);
+        // the y-fluctuations of this cell going left, then those of the
+        // left neighbour going right
+        sub_scaled(F, hy, c.ym.lft);
+        sub_scaled(F, hy, bml);
+        T d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_left(c.ym.rgt[k]);
+        sub_scaled(F, hy, d);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_left(bmr[k]);
+        sub_scaled(F, hy, d);
+    }
+    // correction flux G at the y-edge (col, j + 1/2)
+    T G[3] = {T(0), T(0), T(0)};
+    if (cy_in) cfl = fmax(cfl, edge_cfl(c.yp.s, nuy));
+    if (op.second) corr_flux<3>(c.yp.w, c.yp.s, c.ym.w, yn.w, nuy, op.lim, G);
+    if (op.trans) {
+        // the x-fluctuations of (col, j + 1) going down, then those of
+        // (col, j) going up; those of the right edges come from the next lane
+        T d[3];
+        sub_scaled(G, hx, xn.apd);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_right(xn.amd[k]);
+        sub_scaled(G, hx, d);
+        sub_scaled(G, hx, c.xe.apu);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_right(c.xe.amu[k]);
+        sub_scaled(G, hx, d);
+    }
+    T inc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T am = from_right(c.xe.am[k]), Fr = from_right(F[k]);
+        inc[k] = nux * (c.xe.ap[k] + am) + nuy * (c.ym.bp[k] + bm[k]) + nux * (Fr - F[k]) + nuy * (G[k] - c.Gp[k]);
+    }
+    en = R0.eta - (ETA)inc[0];
+    qun = R0.hu - inc[1];
+    qvn = R0.hv - inc[2];
+    c.ym = y_up(c.yp, op.trans);
+    c.yp = yn;
+    c.xe = xn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.Gp[k] = G[k];
+}
+
+// RT > 0: tiles of at most RT rows, the march fully unrolled with rows
+// requested PREFETCH iterations ahead; RT = 0: any height, a rolling window
+// of rows prefetched two rows ahead.
+template <typename ETA, typename T, int RT>
+__global__ __launch_bounds__(WAVE) void swe2d_kernel(const SweInst<ETA, T> *__restrict__ inst,
+                                                     const Tile *__restrict__ tiles, int parity,
+                                                     int *__restrict__ status, unsigned *__restrict__ cflbits)
+{
     const Tile tl = tiles[blockIdx.x];
     const SweInst<ETA, T> &I = *inst;
-    const ETA *__restrict__ eta = I.eta[parity];
-    const T *__restrict__ hu = I.hu[parity];
-    const T *__restrict__ hv = I.hv[parity];
+    const int lane = threadIdx.x;
     const int nx = I.nx, ny = I.ny;
-    const int tid = threadIdx.x;
-    int bad = 0;
-    // phase A: state with halo
-    for (int k = tid; k < NS; k += NT) {
-        const int li = k % SX - 2, lj = k / SX - 2;
-        bool fx, fy;
-        const int gi = resolve(tl.i0 + li, nx, I.bc[0], I.bc[1], fx);
-        const int gj = resolve(tl.j0 + lj, ny, I.bc[2], I.bc[3], fy);
-        const long long g = (long long)gj * nx + gi;
-        const ETA e = eta[g];
-        const ETA he = e - (ETA)I.B[g];
-        const T h = (T)he;
-        const T qu = fx ? -hu[g] : hu[g];
-        const T qv = fy ? -hv[g] : hv[g];
-        S.eta[k] = e;
-        S.he[k] = he;
-        S.h[k] = h;
-        S.hu[k] = qu;
-        S.hv[k] = qv;
-        S.u[k] = qu / h;
-        S.v[k] = qv / h;
-        S.sq[k] = sqrt(h);
-        bad |= !(h > T(0));
-    }
-    __syncthreads();
-    // the state of this thread's own output cell, kept for the update
-    const int own_li = tid % TX, own_lj = tid / TX;
-    const ETA own_eta = S.eta[sidx(own_li, own_lj)];
-    const T own_hu = S.hu[sidx(own_li, own_lj)], own_hv = S.hv[sidx(own_li, own_lj)];
-    // phase B: edge Riemann problems
-    for (int e = tid; e < NEX; e += NT) {
-        const int li = e % EXW - 1, lj = e / EXW - 1;
-        edge_solve(S, 0, sidx(li - 1, lj), sidx(li, lj), I.g, &S.ex[0][0], e, NEX);
-    }
-    for (int e = tid; e < NEY; e += NT) {
-        const int li = e % EYW - 1, lj = e / EYW - 1;
-        edge_solve(S, 1, sidx(li, lj - 1), sidx(li, lj), I.g, &S.ey[0][0], e, NEY);
-    }
-    __syncthreads();   // state no longer read: the fluxes below overwrite it
-    // phase C: correction fluxes
+    const unsigned cells = (unsigned)nx * (unsigned)ny;
+    constexpr unsigned SE = sizeof(ETA), ST = sizeof(T);
+    const __amdgpu_buffer_rsrc_t re = make_rsrc(I.eta[parity], cells * SE);
+    const __amdgpu_buffer_rsrc_t ru = make_rsrc(I.hu[parity], cells * ST);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc(I.hv[parity], cells * ST);
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(I.B, cells * 8u);
+    const __amdgpu_buffer_rsrc_t we = make_rsrc(I.eta[parity ^ 1], cells * SE);
+    const __amdgpu_buffer_rsrc_t wu = make_rsrc(I.hu[parity ^ 1], cells * ST);
+    const __amdgpu_buffer_rsrc_t wv = make_rsrc(I.hv[parity ^ 1], cells * ST);
+    const double g = I.g;
     const T nux = (T)I.nux, nuy = (T)I.nuy;
-    const bool second = I.order >= 2, trans = I.transverse != 0;
+    const SOpts op{I.order >= 2, I.transverse != 0, I.limiter};
+    const int col = tl.i0 - 2 + lane;
+    bool fx;
+    const int cx = resolve(col, nx, I.bc[0], I.bc[1], fx);
+    const T sx = fx ? T(-1) : T(1);
+    const Resolver rowres(ny, I.bc[2], I.bc[3]);
+    const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
+    const bool xedge_lane = lane >= 2 && lane <= 2 + tl.ni;   // x-edges i0 - 1/2 .. i0 + ni - 1/2
+    int bad = 0;
     T cfl = T(0);
-    for (int f = tid; f < (TX + 1) * TY; f += NT) {
-        const int li = f % (TX + 1), lj = f / (TX + 1);
-        const int e = exid(li, lj);
-        const T *E = &S.ex[0][0];
-        T F[3] = {T(0), T(0), T(0)};
-        for (int p = 0; p < 3; ++p) {
-            const T s = E[(9 + p) * NEX + e];
-            if (li <= tl.ni && lj < tl.nj) cfl = fmax(cfl, fabs(s) * nux);
-            if (!second) continue;
-            const int eu = s > T(0) ? exid(li - 1, lj) : exid(li + 1, lj);
-            T w[3], wu[3];
-            for (int k = 0; k < 3; ++k) { w[k] = E[(p * 3 + k) * NEX + e]; wu[k] = E[(p * 3 + k) * NEX + eu]; }
-            const T phi = lim_factor(w, wu, I.limiter);
-            const T coef = T(0.5) * sgn(s) * (T(1) - nux * fabs(s));
-            for (int k = 0; k < 3; ++k) F[k] += coef * (phi * w[k]);
-        }
-        if (trans) {
-            const T *Y = &S.ey[0][0];
-            // y-edge fluctuations of cells (li, lj) and (li-1, lj), split along x
-            // with each y-edge's Roe state: A- parts from column li, A+ parts from li-1
-            const int ys[4] = {eyid(li, lj), eyid(li, lj + 1), eyid(li - 1, lj), eyid(li - 1, lj + 1)};
-            const bool up[4] = {true, false, true, false};    // B+dQ at the lower, B-dQ at the upper y-edge
-            const bool neg[4] = {true, true, false, false};
-            for (int q = 0; q < 4; ++q) {
-                T d[3], o[3];
-                fluct(Y, ys[q], NEY, !up[q], d);
-                swe_tsplit(0, d, Y[12 * NEY + ys[q]], Y[13 * NEY + ys[q]], Y[14 * NEY + ys[q]], neg[q], o);
-                for (int k = 0; k < 3; ++k) F[k] -= T(0.5) * nuy * o[k];
+    auto ld = [&](SRaw<ETA, T> &r, int j) {
+        bool fy;
+        const int jy = rowres(j, fy);
+        const unsigned idx = (unsigned)(jy * nx + cx);
+        r.eta = bload(re, idx * SE, ETA(0), 0u);
+        r.B = bload(rb, idx * 8u, 0.0, 0u);
+        r.hu = sx * bload(ru, idx * ST, T(0), 0u);
+        const T qv = bload(rv, idx * ST, T(0), 0u);
+        r.hv = fy ? -qv : qv;
+    };
+    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    // stores of halo lanes and of rows past a short tile go beyond the
+    // buffers' range, where they are dropped
+    const unsigned nowE = cells * SE, nowT = cells * ST;
+    auto put = [&](int j, bool valid, ETA en, T qun, T qvn) {
+        const bool keep = valid && j < j1 && out_lane;
+        const unsigned idx = (unsigned)(j * nx + col);
+        bstore(we, keep ? idx * SE : nowE, 0u, en);
+        bstore(wu, keep ? idx * ST : nowT, 0u, qun);
+        bstore(wv, keep ? idx * ST : nowT, 0u, qvn);
+        bad |= keep & !(isfinite((double)en) & isfinite((double)qun) & isfinite((double)qvn));
+    };
+    SCarry<T> c;
+    if constexpr (RT > 0) {
+        constexpr int NR = RT + 4;
+        constexpr int FIRST = 3 + PREFETCH < NR ? 3 + PREFETCH : NR;
+        SRaw<ETA, T> raw[NR];
+#pragma unroll
+        for (int r = 0; r < FIRST; ++r) ld(raw[r], j0 - 2 + r);
+        __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+        const SRow<ETA, T> Ra = derive(raw[0], bad);
+        SRow<ETA, T> R0 = derive(raw[1], bad), R1 = derive(raw[2], bad);
+        swe_start(Ra, R0, R1, g, op, c);
+#pragma unroll
+        for (int it = 0; it <= RT; ++it) {
+            if (FIRST + it < NR) {
+                ld(raw[FIRST + it], j0 - 2 + FIRST + it);
+                __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
             }
+            const int j = j0 - 1 + it;
+            const SRow<ETA, T> R2 = derive(raw[it + 3], bad);
+            ETA en;
+            T qun, qvn;
+            swe_row(R0, R1, R2, g, nux, nuy, op, xedge_lane && it > 0 && j < j1, out_lane && j + 1 <= j1, c, cfl,
+                    en, qun, qvn);
+            if (it > 0) put(j, true, en, qun, qvn);
+            R0 = R1;
+            R1 = R2;
         }
-        for (int k = 0; k < 3; ++k) S.F[k][f] = F[k];
-    }
-    for (int f = tid; f < TX * (TY + 1); f += NT) {
-        const int li = f % TX, lj = f / TX;
-        const int e = eyid(li, lj);
-        const T *E = &S.ey[0][0];
-        T G[3] = {T(0), T(0), T(0)};
-        for (int p = 0; p < 3; ++p) {
-            const T s = E[(9 + p) * NEY + e];
-            if (li < tl.ni && lj <= tl.nj) cfl = fmax(cfl, fabs(s) * nuy);
-            if (!second) continue;
-            const int eu = s > T(0) ? eyid(li, lj - 1) : eyid(li, lj + 1);
-            T w[3], wu[3];
-            for (int k = 0; k < 3; ++k) { w[k] = E[(p * 3 + k) * NEY + e]; wu[k] = E[(p * 3 + k) * NEY + eu]; }
-            const T phi = lim_factor(w, wu, I.limiter);
-            const T coef = T(0.5) * sgn(s) * (T(1) - nuy * fabs(s));
-            for (int k = 0; k < 3; ++k) G[k] += coef * (phi * w[k]);
-        }
-        if (trans) {
-            const T *X = &S.ex[0][0];
-            // x-edge fluctuations of cells (li, lj) and (li, lj-1), split along y
-            const int xs[4] = {exid(li, lj), exid(li + 1, lj), exid(li, lj - 1), exid(li + 1, lj - 1)};
-            const bool plus[4] = {true, false, true, false};   // A+dQ at the left, A-dQ at the right x-edge
-            const bool neg[4] = {true, true, false, false};
-            for (int q = 0; q < 4; ++q) {
-                T d[3], o[3];
-                fluct(X, xs[q], NEX, !plus[q], d);
-                swe_tsplit(1, d, X[12 * NEX + xs[q]], X[13 * NEX + xs[q]], X[14 * NEX + xs[q]], neg[q], o);
-                for (int k = 0; k < 3; ++k) G[k] -= T(0.5) * nux * o[k];
-            }
-        }
-        for (int k = 0; k < 3; ++k) S.G[k][f] = G[k];
-    }
-    __syncthreads();
-    // phase D: update
-    ETA *__restrict__ eta_o = I.eta[parity ^ 1];
-    T *__restrict__ hu_o = I.hu[parity ^ 1];
-    T *__restrict__ hv_o = I.hv[parity ^ 1];
-    static_assert(TX * TY == NT, "one output cell per thread");
-    {
-        const int li = own_li, lj = own_lj;
-        T ap[3], am[3], bp[3], bm[3];
-        fluct(&S.ex[0][0], exid(li, lj), NEX, false, ap);
-        fluct(&S.ex[0][0], exid(li + 1, lj), NEX, true, am);
-        fluct(&S.ey[0][0], eyid(li, lj), NEY, false, bp);
-        fluct(&S.ey[0][0], eyid(li, lj + 1), NEY, true, bm);
-        const int fl = li + lj * (TX + 1), fr = fl + 1;
-        const int gb = li + lj * TX, gt = gb + TX;
-        T inc[3];
-        for (int k = 0; k < 3; ++k)
-            inc[k] = nux * (ap[k] + am[k]) + nuy * (bp[k] + bm[k]) + nux * (S.F[k][fr] - S.F[k][fl]) +
-                     nuy * (S.G[k][gt] - S.G[k][gb]);
-        if (li < tl.ni && lj < tl.nj) {
-            const long long g = (long long)(tl.j0 + lj) * nx + (tl.i0 + li);
-            const ETA en = own_eta - (ETA)inc[0];
-            const T qun = own_hu - inc[1], qvn = own_hv - inc[2];
-            eta_o[g] = en;
-            hu_o[g] = qun;
-            hv_o[g] = qvn;
-            bad |= !(isfinite((double)en) && isfinite((double)qun) && isfinite((double)qvn));
+    } else {
+        SRaw<ETA, T> X0, X1, X2;
+        SRaw<ETA, T> a;
+        ld(a, j0 - 2);
+        const SRow<ETA, T> Ra = derive(a, bad);
+        ld(a, j0 - 1);
+        SRow<ETA, T> R0 = derive(a, bad);
+        ld(a, j0);
+        SRow<ETA, T> R1 = derive(a, bad);
+        ld(X0, j0 + 1);
+        ld(X1, j0 + 2);
+        swe_start(Ra, R0, R1, g, op, c);
+        for (int j = j0 - 1; j < j1; ++j) {
+            ld(X2, j + 4);   // row j + 2 (X0) was requested two iterations ago
+            const SRow<ETA, T> R2 = derive(X0, bad);
+            ETA en;
+            T qun, qvn;
+            swe_row(R0, R1, R2, g, nux, nuy, op, xedge_lane && j >= j0, out_lane, c, cfl, en, qun, qvn);
+            put(j, j >= j0, en, qun, qvn);
+            R0 = R1;
+            R1 = R2;
+            X0 = X1;
+            X1 = X2;
         }
     }
-    // reductions: Courant number and failures, one atomic per wave
+    // Courant number and failures: one atomic per wave, skipped when the
+    // running maximum is already as large
     for (int off = 32; off > 0; off >>= 1) cfl = fmax(cfl, __shfl_down(cfl, off));
-    if ((tid & 63) == 0) {
-        const float cf = (float)cfl;
-        atomicMax(cflbits, __float_as_uint(cf));
+    if (lane == 0) {
+        const unsigned cb = __float_as_uint((float)cfl);
+        if (cb > __hip_atomic_load(cflbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(cflbits, cb);
         if ((double)cfl > I.cfl_max) atomicOr(status, ST_CFL);
     }
-    if (__any(bad) && (tid & 63) == 0) atomicOr(status, ST_NONFINITE);
+    if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
 }
 
 // ---------------------------------------------------------------------------
 // linearised shallow-water adjoint, time reversed, f-wave form
 // ---------------------------------------------------------------------------
+
 template <typename T>
-struct LswSmem {
-    T q[3][NS];
-    T c[NS];
-    T ex[8][NEX];    // waves [6], speeds [2]
-    T ey[8][NEY];
-    T F[3][(TX + 1) * TY];
-    T G[3][TX * (TY + 1)];
+struct LRow {
+    T q[3];   // (eta, mu, gamma) of the time-reversed adjoint
+    T c;      // sqrt(g hbar) of the linearisation
 };
 
-// reversed flux -A^T q = (-g hbar mu_n, -eta, 0) split into f-waves
-// b1 (c_l, 1) at speed -c_l and b2 (-c_r, 1) at speed +c_r (n: normal momentum)
 template <typename T>
-__device__ __forceinline__ void lsw_edge(LswSmem<T> &S, int dir, int il, int ir, T g, T *dst, int e, int nedge)
+__device__ __forceinline__ LRow<T> shift_left(const LRow<T> &r)
 {
-    const int n = dir == 0 ? 1 : 2, t = dir == 0 ? 2 : 1;
-    const T cl = S.c[il], cr = S.c[ir];
-    const T f1l = -(cl * cl) * S.q[n][il], f1r = -(cr * cr) * S.q[n][ir];
-    const T f2l = -S.q[0][il], f2r = -S.q[0][ir];
+    return LRow<T>{{from_left(r.q[0]), from_left(r.q[1]), from_left(r.q[2])}, from_left(r.c)};
+}
+
+// f-waves of the reversed flux -A^T q = (-c^2 mu_n, -eta, 0): w[0..2] =
+// b1 (c_L, 1) at speed -c_L, w[3..5] = b2 (-c_R, 1) at speed +c_R (index n:
+// normal momentum).  Wave 1 is the fluctuation into the lower/left cell,
+// wave 2 that into the upper/right cell.
+template <typename T>
+struct LEdge {
+    T w[6];
+    T s[2];
+};
+
+template <int DIR, typename T>
+__device__ __forceinline__ LEdge<T> lsw_edge(const LRow<T> &L, const LRow<T> &R)
+{
+    constexpr int n = DIR == 0 ? 1 : 2, t = DIR == 0 ? 2 : 1;
+    const T cl = L.c, cr = R.c;
+    const T f1l = -(cl * cl) * L.q[n], f1r = -(cr * cr) * R.q[n];
+    const T f2l = -L.q[0], f2r = -R.q[0];
     const T df1 = f1r - f1l, df2 = f2r - f2l;
     const T inv = T(1) / (cl + cr);
     const T b1 = (df1 + cr * df2) * inv;
     const T b2 = (cl * df2 - df1) * inv;
-    T w[6];
-    w[0] = b1 * cl; w[n] = b1; w[t] = T(0);
-    w[3] = -b2 * cr; w[3 + n] = b2; w[3 + t] = T(0);
-    for (int k = 0; k < 6; ++k) dst[k * nedge + e] = w[k];
-    dst[6 * nedge + e] = -cl;
-    dst[7 * nedge + e] = cr;
-    (void)g;
+    LEdge<T> e;
+    e.w[0] = b1 * cl; e.w[n] = b1; e.w[t] = T(0);
+    e.w[3] = -b2 * cr; e.w[3 + n] = b2; e.w[3 + t] = T(0);
+    e.s[0] = -cl;
+    e.s[1] = cr;
+    return e;
 }
 
-// transverse split of d living in cell `own` along tdir (n = normal momentum of
-// tdir): part into the lo neighbour (neg) or into the hi neighbour
+// transverse split along tdir of d living in a cell with sound speed cown:
+// the part into the lo neighbour (neg) or into the hi neighbour
 template <typename T>
 __device__ __forceinline__ void lsw_tsplit(int tdir, const T d[3], T clo, T cown, T chi, bool neg, T o[3])
 {
@@ -376,175 +539,225 @@ __device__ __forceinline__ void lsw_tsplit(int tdir, const T d[3], T clo, T cown
 }
 
 template <typename T>
-__device__ __forceinline__ void lfluct(const T *E, int e, int nedge, bool neg, T out[3])
-{
-    const int p = neg ? 0 : 1;
-    for (int k = 0; k < 3; ++k) out[k] = E[(p * 3 + k) * nedge + e];
-}
+struct LCarry {
+    LEdge<T> ym, yp, xe;   // y-edges j -+ 1/2, x-edge (col - 1/2, j)
+    T Gp[3];
+};
 
 template <typename T>
-__global__ __launch_bounds__(NT) void lswe_adj_kernel(const LsweInst<T> *__restrict__ inst,
-                                                      const Tile *__restrict__ tiles, int parity, int snap_index,
-                                                      int *__restrict__ status)
+__device__ __forceinline__ void lswe_row(const LRow<T> &R0, const LRow<T> &R1, const LRow<T> &R2, T nux, T nuy,
+                                         const SOpts &op, LCarry<T> &c, T qn[3])
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    LswSmem<T> &S = *reinterpret_cast<LswSmem<T> *>(smem_raw);
+    const LEdge<T> yn = lsw_edge<1>(R1, R2);                  // y-edge j + 3/2
+    const LEdge<T> xn = lsw_edge<0>(shift_left(R1), R1);      // x-edge (col - 1/2, j + 1)
+    const T hx = T(0.5) * nux, hy = T(0.5) * nuy;
+    T am[3];   // wave 1 of the x-edge (col + 1/2, j): A-dQ of this cell
+#pragma unroll
+    for (int k = 0; k < 3; ++k) am[k] = from_right(c.xe.w[k]);
+    // F at the x-edge (col - 1/2, j)
+    T F[3] = {T(0), T(0), T(0)};
+    if (op.second) {
+        T wl[6], wr[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            wl[k] = from_left(c.xe.w[k]);
+            wr[k] = from_right(c.xe.w[k]);
+        }
+        corr_flux<2>(c.xe.w, c.xe.s, wl, wr, nux, op.lim, F);
+    }
+    if (op.trans) {
+        const T cL = from_left(R0.c), cR = R0.c;
+        T d[3], o[3];
+        // the y-fluctuations of this cell going left ...
+        lsw_tsplit(0, &c.ym.w[3], cL, cR, T(0), true, o);
+        sub_scaled(F, hy, o);
+        lsw_tsplit(0, &c.yp.w[0], cL, cR, T(0), true, o);
+        sub_scaled(F, hy, o);
+        // ... and those of the left neighbour going right
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_left(c.ym.w[3 + k]);
+        lsw_tsplit(0, d, T(0), cL, cR, false, o);
+        sub_scaled(F, hy, o);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_left(c.yp.w[k]);
+        lsw_tsplit(0, d, T(0), cL, cR, false, o);
+        sub_scaled(F, hy, o);
+    }
+    // G at the y-edge (col, j + 1/2)
+    T G[3] = {T(0), T(0), T(0)};
+    if (op.second) corr_flux<2>(c.yp.w, c.yp.s, c.ym.w, yn.w, nuy, op.lim, G);
+    if (op.trans) {
+        const T cB = R0.c, cA = R1.c;
+        T d[3], o[3];
+        // the x-fluctuations of (col, j + 1) going down ...
+        lsw_tsplit(1, &xn.w[3], cB, cA, T(0), true, o);
+        sub_scaled(G, hx, o);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_right(xn.w[k]);
+        lsw_tsplit(1, d, cB, cA, T(0), true, o);
+        sub_scaled(G, hx, o);
+        // ... and those of (col, j) going up
+        lsw_tsplit(1, &c.xe.w[3], T(0), cB, cA, false, o);
+        sub_scaled(G, hx, o);
+        lsw_tsplit(1, am, T(0), cB, cA, false, o);
+        sub_scaled(G, hx, o);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T Fr = from_right(F[k]);
+        T v = R0.q[k];
+        v = v - nux * (c.xe.w[3 + k] + am[k]);
+        v = v - nuy * (c.ym.w[3 + k] + c.yp.w[k]);
+        v = v - nux * (Fr - F[k]);
+        v = v - nuy * (G[k] - c.Gp[k]);
+        qn[k] = v;
+    }
+    c.ym = c.yp;
+    c.yp = yn;
+    c.xe = xn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.Gp[k] = G[k];
+}
+
+template <typename T, int RT>
+__global__ __launch_bounds__(WAVE) void lswe_adj_kernel(const LsweInst<T> *__restrict__ inst,
+                                                        const Tile *__restrict__ tiles, int parity, int snap_index,
+                                                        int *__restrict__ status)
+{
     const Tile tl = tiles[blockIdx.x];
     const LsweInst<T> &I = *inst;
-    const T *__restrict__ q = I.q[parity];
+    const int lane = threadIdx.x;
     const int nx = I.nx, ny = I.ny;
-    const long long cs = (long long)nx * ny;
-    const int tid = threadIdx.x;
-    for (int k = tid; k < NS; k += NT) {
-        const int li = k % SX - 2, lj = k / SX - 2;
-        bool fx, fy;
-        const int gi = resolve(tl.i0 + li, nx, I.bc[0], I.bc[1], fx);
-        const int gj = resolve(tl.j0 + lj, ny, I.bc[2], I.bc[3], fy);
-        const long long g = (long long)gj * nx + gi;
-        S.q[0][k] = q[g];
-        S.q[1][k] = fx ? -q[g + cs] : q[g + cs];
-        S.q[2][k] = fy ? -q[g + 2 * cs] : q[g + 2 * cs];
-        S.c[k] = I.cbar[g];
-    }
-    __syncthreads();
-    for (int e = tid; e < NEX; e += NT) {
-        const int li = e % EXW - 1, lj = e / EXW - 1;
-        lsw_edge(S, 0, sidx(li - 1, lj), sidx(li, lj), I.g, &S.ex[0][0], e, NEX);
-    }
-    for (int e = tid; e < NEY; e += NT) {
-        const int li = e % EYW - 1, lj = e / EYW - 1;
-        lsw_edge(S, 1, sidx(li, lj - 1), sidx(li, lj), I.g, &S.ey[0][0], e, NEY);
-    }
-    __syncthreads();
+    const unsigned cells = (unsigned)nx * (unsigned)ny;
+    const unsigned csb = cells * (unsigned)sizeof(T);
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(I.q[parity], 3u * csb);
+    const __amdgpu_buffer_rsrc_t cr = make_rsrc(I.cbar, csb);
+    const __amdgpu_buffer_rsrc_t qw = make_rsrc(I.q[parity ^ 1], 3u * csb);
+    // the snapshot store has an empty range when no snapshot is taken
+    const bool snap = snap_index >= 0;
+    const __amdgpu_buffer_rsrc_t sw =
+        make_rsrc(snap ? (const void *)(I.snap + (long long)snap_index * I.snap_stride) : (const void *)I.q[0],
+                  snap ? 3u * csb : 0u);
     const T nux = I.nux, nuy = I.nuy;
-    const bool second = I.order >= 2, trans = I.transverse != 0;
-    for (int f = tid; f < (TX + 1) * TY; f += NT) {
-        const int li = f % (TX + 1), lj = f / (TX + 1);
-        const int e = exid(li, lj);
-        const T *E = &S.ex[0][0];
-        T F[3] = {T(0), T(0), T(0)};
-        if (second)
-            for (int p = 0; p < 2; ++p) {
-                const T s = E[(6 + p) * NEX + e];
-                const int eu = s > T(0) ? exid(li - 1, lj) : exid(li + 1, lj);
-                T w[3], wu[3];
-                for (int k = 0; k < 3; ++k) { w[k] = E[(p * 3 + k) * NEX + e]; wu[k] = E[(p * 3 + k) * NEX + eu]; }
-                const T phi = lim_factor(w, wu, I.limiter);
-                const T coef = T(0.5) * sgn(s) * (T(1) - nux * fabs(s));
-                for (int k = 0; k < 3; ++k) F[k] += coef * (phi * w[k]);
-            }
-        if (trans) {
-            const T *Y = &S.ey[0][0];
-            const T cL = S.c[sidx(li - 1, lj)], cR = S.c[sidx(li, lj)];
-            T d[3], o[3];
-            // A- parts of the y-fluctuations living in (li, lj)
-            lfluct(Y, eyid(li, lj), NEY, false, d);
-            lsw_tsplit(0, d, cL, cR, T(0), true, o);
-            for (int k = 0; k < 3; ++k) F[k] -= T(0.5) * nuy * o[k];
-            lfluct(Y, eyid(li, lj + 1), NEY, true, d);
-            lsw_tsplit(0, d, cL, cR, T(0), true, o);
-            for (int k = 0; k < 3; ++k) F[k] -= T(0.5) * nuy * o[k];
-            // A+ parts of those living in (li-1, lj)
-            lfluct(Y, eyid(li - 1, lj), NEY, false, d);
-            lsw_tsplit(0, d, T(0), cL, cR, false, o);
-            for (int k = 0; k < 3; ++k) F[k] -= T(0.5) * nuy * o[k];
-            lfluct(Y, eyid(li - 1, lj + 1), NEY, true, d);
-            lsw_tsplit(0, d, T(0), cL, cR, false, o);
-            for (int k = 0; k < 3; ++k) F[k] -= T(0.5) * nuy * o[k];
-        }
-        for (int k = 0; k < 3; ++k) S.F[k][f] = F[k];
-    }
-    for (int f = tid; f < TX * (TY + 1); f += NT) {
-        const int li = f % TX, lj = f / TX;
-        const int e = eyid(li, lj);
-        const T *E = &S.ey[0][0];
-        T G[3] = {T(0), T(0), T(0)};
-        if (second)
-            for (int p = 0; p < 2; ++p) {
-                const T s = E[(6 + p) * NEY + e];
-                const int eu = s > T(0) ? eyid(li, lj - 1) : eyid(li, lj + 1);
-                T w[3], wu[3];
-                for (int k = 0; k < 3; ++k) { w[k] = E[(p * 3 + k) * NEY + e]; wu[k] = E[(p * 3 + k) * NEY + eu]; }
-                const T phi = lim_factor(w, wu, I.limiter);
-                const T coef = T(0.5) * sgn(s) * (T(1) - nuy * fabs(s));
-                for (int k = 0; k < 3; ++k) G[k] += coef * (phi * w[k]);
-            }
-        if (trans) {
-            const T *X = &S.ex[0][0];
-            const T cB = S.c[sidx(li, lj - 1)], cA = S.c[sidx(li, lj)];
-            T d[3], o[3];
-            // B- parts of the x-fluctuations living in (li, lj)
-            lfluct(X, exid(li, lj), NEX, false, d);
-            lsw_tsplit(1, d, cB, cA, T(0), true, o);
-            for (int k = 0; k < 3; ++k) G[k] -= T(0.5) * nux * o[k];
-            lfluct(X, exid(li + 1, lj), NEX, true, d);
-            lsw_tsplit(1, d, cB, cA, T(0), true, o);
-            for (int k = 0; k < 3; ++k) G[k] -= T(0.5) * nux * o[k];
-            // B+ parts of those living in (li, lj-1)
-            lfluct(X, exid(li, lj - 1), NEX, false, d);
-            lsw_tsplit(1, d, T(0), cB, cA, false, o);
-            for (int k = 0; k < 3; ++k) G[k] -= T(0.5) * nux * o[k];
-            lfluct(X, exid(li + 1, lj - 1), NEX, true, d);
-            lsw_tsplit(1, d, T(0), cB, cA, false, o);
-            for (int k = 0; k < 3; ++k) G[k] -= T(0.5) * nux * o[k];
-        }
-        for (int k = 0; k < 3; ++k) S.G[k][f] = G[k];
-    }
-    __syncthreads();
-    T *__restrict__ qo = I.q[parity ^ 1];
-    T *__restrict__ sn = snap_index >= 0 ? I.snap + (long long)snap_index * I.snap_stride : nullptr;
+    const SOpts op{I.order >= 2, I.transverse != 0, I.limiter};
+    const int col = tl.i0 - 2 + lane;
+    bool fx;
+    const int cx = resolve(col, nx, I.bc[0], I.bc[1], fx);
+    const T sx = fx ? T(-1) : T(1);
+    const Resolver rowres(ny, I.bc[2], I.bc[3]);
+    const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
+    auto ld = [&](LRow<T> &r, int j) {
+        bool fy;
+        const int jy = rowres(j, fy);
+        const unsigned off = (unsigned)(jy * nx + cx) * (unsigned)sizeof(T);
+        r.q[0] = bload(qr, off, T(0), 0u);
+        r.q[1] = sx * bload(qr, off, T(0), csb);
+        const T gm = bload(qr, off, T(0), 2u * csb);
+        r.q[2] = fy ? -gm : gm;
+        r.c = bload(cr, off, T(0), 0u);
+    };
+    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    const unsigned nowhere = 3u * csb;
     int bad = 0;
-    for (int c = tid; c < TX * TY; c += NT) {
-        const int li = c % TX, lj = c / TX;
-        if (li >= tl.ni || lj >= tl.nj) continue;
-        T ap[3], am[3], bp[3], bm[3];
-        lfluct(&S.ex[0][0], exid(li, lj), NEX, false, ap);
-        lfluct(&S.ex[0][0], exid(li + 1, lj), NEX, true, am);
-        lfluct(&S.ey[0][0], eyid(li, lj), NEY, false, bp);
-        lfluct(&S.ey[0][0], eyid(li, lj + 1), NEY, true, bm);
-        const int fl = li + lj * (TX + 1), fr = fl + 1;
-        const int gb = li + lj * TX, gt = gb + TX;
-        const int si = sidx(li, lj);
-        const long long g = (long long)(tl.j0 + lj) * nx + (tl.i0 + li);
+    auto put = [&](int j, bool valid, const T qn[3]) {
+        const bool keep = valid && j < j1 && out_lane;
+        const unsigned off = keep ? (unsigned)(j * nx + col) * (unsigned)sizeof(T) : nowhere;
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
-            T v = S.q[k][si];
-            v = v - nux * (ap[k] + am[k]);
-            v = v - nuy * (bp[k] + bm[k]);
-            v = v - nux * (S.F[k][fr] - S.F[k][fl]);
-            v = v - nuy * (S.G[k][gt] - S.G[k][gb]);
-            qo[g + k * cs] = v;
-            if (sn) sn[g + k * cs] = v;
-            bad |= !isfinite((double)v);
+            bstore(qw, off, (unsigned)k * csb, qn[k]);
+            bstore(sw, off, (unsigned)k * csb, qn[k]);
+        }
+        bad |= keep & !(isfinite((double)qn[0]) & isfinite((double)qn[1]) & isfinite((double)qn[2]));
+    };
+    LCarry<T> c;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.Gp[k] = T(0);
+    if constexpr (RT > 0) {
+        constexpr int NR = RT + 4;
+        constexpr int FIRST = 3 + PREFETCH < NR ? 3 + PREFETCH : NR;
+        LRow<T> rw[NR];
+#pragma unroll
+        for (int r = 0; r < FIRST; ++r) ld(rw[r], j0 - 2 + r);
+        __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+        c.ym = lsw_edge<1>(rw[0], rw[1]);
+        c.yp = lsw_edge<1>(rw[1], rw[2]);
+        c.xe = lsw_edge<0>(shift_left(rw[1]), rw[1]);
+#pragma unroll
+        for (int it = 0; it <= RT; ++it) {
+            if (FIRST + it < NR) {
+                ld(rw[FIRST + it], j0 - 2 + FIRST + it);
+                __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+            }
+            T qn[3];
+            lswe_row(rw[it + 1], rw[it + 2], rw[it + 3], nux, nuy, op, c, qn);
+            if (it > 0) put(j0 - 1 + it, true, qn);
+        }
+    } else {
+        LRow<T> R0, R1, X0, X1, X2, a;
+        ld(a, j0 - 2);
+        ld(R0, j0 - 1);
+        ld(R1, j0);
+        ld(X0, j0 + 1);
+        ld(X1, j0 + 2);
+        c.ym = lsw_edge<1>(a, R0);
+        c.yp = lsw_edge<1>(R0, R1);
+        c.xe = lsw_edge<0>(shift_left(R0), R0);
+        for (int j = j0 - 1; j < j1; ++j) {
+            ld(X2, j + 4);
+            T qn[3];
+            lswe_row(R0, R1, X0, nux, nuy, op, c, qn);
+            put(j, j >= j0, qn);
+            R0 = R1;
+            R1 = X0;
+            X0 = X1;
+            X1 = X2;
         }
     }
-    if (__any(bad) && (tid & 63) == 0) atomicOr(status, ST_NONFINITE);
+    if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
 }
 
 }  // namespace
 
+// compile-time tile heights; others take the runtime march
+#define WP_SWE_BY_RT(F) \
+    switch (rows) {     \
+    case 4: F(4); break; \
+    case 8: F(8); break; \
+    case 12: F(12); break; \
+    default: F(0); break; \
+    }
+
 template <typename ETA, typename T>
-void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int parity, int *status,
+void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int *status,
                   unsigned *cflbits, hipStream_t s)
 {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL((swe2d_kernel<ETA, T>), dim3(ntiles), dim3(NT), sizeof(SweSmem<ETA, T>), s, inst, tiles,
-                       parity, status, cflbits);
+#define WP_L(R)                                                                                                   \
+    hipLaunchKernelGGL((swe2d_kernel<ETA, T, R>), dim3(ntiles), dim3(WAVE), 0, s, inst, tiles, parity, status, \
+                       cflbits)
+    WP_SWE_BY_RT(WP_L)
+#undef WP_L
 }
 
 template <typename T>
-void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, int parity, int snap_index,
+void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int snap_index,
                        int *status, hipStream_t s)
 {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL((lswe_adj_kernel<T>), dim3(ntiles), dim3(NT), sizeof(LswSmem<T>), s, inst, tiles, parity,
-                       snap_index, status);
+#define WP_L(R)                                                                                                   \
+    hipLaunchKernelGGL((lswe_adj_kernel<T, R>), dim3(ntiles), dim3(WAVE), 0, s, inst, tiles, parity, snap_index, \
+                       status)
+    WP_SWE_BY_RT(WP_L)
+#undef WP_L
 }
 
-template void launch_swe2d<double, double>(const SweInst<double, double> *, const Tile *, int, int, int *,
+template void launch_swe2d<double, double>(const SweInst<double, double> *, const Tile *, int, int, int, int *,
                                            unsigned *, hipStream_t);
-template void launch_swe2d<double, float>(const SweInst<double, float> *, const Tile *, int, int, int *, unsigned *,
-                                          hipStream_t);
-template void launch_lswe_adj2d<double>(const LsweInst<double> *, const Tile *, int, int, int, int *, hipStream_t);
-template void launch_lswe_adj2d<float>(const LsweInst<float> *, const Tile *, int, int, int, int *, hipStream_t);
+template void launch_swe2d<double, float>(const SweInst<double, float> *, const Tile *, int, int, int, int *,
+                                          unsigned *, hipStream_t);
+template void launch_lswe_adj2d<double>(const LsweInst<double> *, const Tile *, int, int, int, int, int *,
+                                        hipStream_t);
+template void launch_lswe_adj2d<float>(const LsweInst<float> *, const Tile *, int, int, int, int, int *,
+                                       hipStream_t);
 
 }  // namespace wp

@@ -125,17 +125,17 @@ int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, i
     const bool f64 = ctx->prob.precision == WP_FP64;
     if (adjoint) {
         if (f64)
-            launch_lswe_adj2d<double>((const LsweInst<double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.cur, snap_index,
+            launch_lswe_adj2d<double>((const LsweInst<double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur, snap_index,
                                       ctx->status, s);
         else
-            launch_lswe_adj2d<float>((const LsweInst<float> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.cur, snap_index,
+            launch_lswe_adj2d<float>((const LsweInst<float> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur, snap_index,
                                      ctx->status, s);
     } else {
         if (f64)
-            launch_swe2d<double, double>((const SweInst<double, double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.cur,
+            launch_swe2d<double, double>((const SweInst<double, double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur,
                                          ctx->status, ctx->cflbits, s);
         else
-            launch_swe2d<double, float>((const SweInst<double, float> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.cur,
+            launch_swe2d<double, float>((const SweInst<double, float> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur,
                                         ctx->status, ctx->cflbits, s);
     }
     hipError_t e = hipGetLastError();

@@ -155,10 +155,7 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
 {
     const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
     const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, lv);
-    if (ctx->is_acoustics)
-        lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, false);
-    else
-        lv.tiles_host = wp_make_tiles(lv.patches, 0, SWE_TY, SWE_TX, false);
+    lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, false);
     lv.tile_rows = rows;
     wp_classify_tiles(ctx, lv, lv.tiles_host, rows);
     // mixed-material tiles (the slower march) first, so they are dispatched

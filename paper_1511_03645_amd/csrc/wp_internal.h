@@ -95,13 +95,11 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, in
                    int snap_index, int *status, hipStream_t s);
 
 template <typename ETA, typename T>
-void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int parity, int *status,
+void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int *status,
                   unsigned *cflbits, hipStream_t s);
 template <typename T>
-void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, int parity, int snap_index,
+void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int snap_index,
                        int *status, hipStream_t s);
-constexpr int SWE_TX = 16;     // output columns of a shallow-water tile
-constexpr int SWE_TY = 8;      // output rows of a shallow-water tile
 
 // Flag: m(x) = max_n |qhat_n(x) . q(x)| over snapshots n_lo..n_hi, bilinear
 // from the adjoint grid (refinement `ratio` relative to it).
