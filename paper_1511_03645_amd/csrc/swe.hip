@@ -104,8 +104,9 @@ __device__ __forceinline__ SRow<ETA, T> derive(const SRaw<ETA, T> &a, int &bad)
     r.h = (T)r.he;
     r.hu = a.hu;
     r.hv = a.hv;
-    r.u = r.hu / r.h;
-    r.v = r.hv / r.h;
+    const T rh = T(1) / r.h;
+    r.u = r.hu * rh;
+    r.v = r.hv * rh;
     r.sq = sqrt(r.h);
     bad |= !(r.h > T(0));
     return r;
@@ -139,8 +140,9 @@ __device__ __forceinline__ SEdge<T> roe_edge(const SRow<ETA, T> &L, const SRow<E
     const T utl = DIR == 0 ? L.v : L.u, utr = DIR == 0 ? R.v : R.u;
     const T qnl = DIR == 0 ? L.hu : L.hv, qnr = DIR == 0 ? R.hu : R.hv;
     const T hbar = T(0.5) * (L.h + R.h);
-    const T un = (L.sq * unl + R.sq * unr) / (L.sq + R.sq);
-    const T ut = (L.sq * utl + R.sq * utr) / (L.sq + R.sq);
+    const T rs = T(1) / (L.sq + R.sq);
+    const T un = (L.sq * unl + R.sq * unr) * rs;
+    const T ut = (L.sq * utl + R.sq * utr) * rs;
     const T c = sqrt(T(g) * hbar);
     const ETA hbe = ETA(0.5) * (L.he + R.he);
     const T wb = (T)(ETA(g) * hbe * (R.eta - L.eta));
@@ -163,26 +165,28 @@ __device__ __forceinline__ SEdge<T> roe_edge(const SRow<ETA, T> &L, const SRow<E
     return e;
 }
 
-// fluctuation of an edge: waves with negative speed (neg) or positive speed,
-// zero-speed waves split evenly
+// Fluctuations of an edge: A-dQ (am, waves with negative speed) and A+dQ
+// (ap, positive speed); a zero-speed wave is split evenly.
 template <typename T>
-__device__ __forceinline__ void fluct(const SEdge<T> &E, bool neg, T out[3])
+__device__ __forceinline__ void flucts(const SEdge<T> &E, T am[3], T ap[3])
 {
-    out[0] = out[1] = out[2] = T(0);
+    T fn[3];
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        const T s = E.s[p];
-        const T f = s < T(0) ? (neg ? T(1) : T(0)) : (s > T(0) ? (neg ? T(0) : T(1)) : T(0.5));
+    for (int p = 0; p < 3; ++p) fn[p] = E.s[p] < T(0) ? T(1) : (E.s[p] > T(0) ? T(0) : T(0.5));
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out[k] += f * E.w[p * 3 + k];
+    for (int k = 0; k < 3; ++k) {
+        am[k] = fn[0] * E.w[k] + fn[1] * E.w[3 + k] + fn[2] * E.w[6 + k];
+        ap[k] = (T(1) - fn[0]) * E.w[k] + (T(1) - fn[1]) * E.w[3 + k] + (T(1) - fn[2]) * E.w[6 + k];
     }
 }
 
 // Transverse split of d along direction tdir with the eigen-structure of
-// that direction at the Roe state (uh, vh, c) of the edge d came from: the
-// part carried by negative speeds (neg) or by non-negative speeds.
+// that direction at the Roe state (uh, vh, c) of the edge d came from: neg
+// gets the part carried by negative speeds, pos the part carried by
+// non-negative speeds.  The eigenvalues vt - c < vt < vt + c enter through
+// 0/1 masks.
 template <typename T>
-__device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T c, bool neg, T out[3])
+__device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T c, T neg[3], T pos[3])
 {
     const int kt = tdir == 0 ? 1 : 2, ko = tdir == 0 ? 2 : 1;
     const T vt = tdir == 0 ? uh : vh, vo = tdir == 0 ? vh : uh;
@@ -191,68 +195,37 @@ __device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T
     const T g3 = (d[kt] - (vt - c) * d[0]) * inv2c;
     const T g2 = d[ko] - vo * d[0];
     const T l1 = vt - c, l2 = vt, l3 = vt + c;
-    T o[3] = {T(0), T(0), T(0)};
-    if ((l1 < T(0)) == neg) {
-        o[0] += l1 * g1; o[kt] += l1 * g1 * (vt - c); o[ko] += l1 * g1 * vo;
-    }
-    if ((l2 < T(0)) == neg) {
-        o[ko] += l2 * g2;
-    }
-    if ((l3 < T(0)) == neg) {
-        o[0] += l3 * g3; o[kt] += l3 * g3 * (vt + c); o[ko] += l3 * g3 * vo;
-    }
-    out[0] = o[0]; out[1] = o[1]; out[2] = o[2];
+    const T a1 = l1 * g1, a2 = l2 * g2, a3 = l3 * g3;
+    const T c1[3] = {a1, a1 * (vt - c), a1 * vo};   // (mass, tangential-direction, other) parts
+    const T c3[3] = {a3, a3 * (vt + c), a3 * vo};
+    const T m1 = l1 < T(0) ? T(1) : T(0), m2 = l2 < T(0) ? T(1) : T(0), m3 = l3 < T(0) ? T(1) : T(0);
+    neg[0] = m1 * c1[0] + m3 * c3[0];
+    neg[kt] = m1 * c1[1] + m3 * c3[1];
+    neg[ko] = m1 * c1[2] + m2 * a2 + m3 * c3[2];
+    pos[0] = (T(1) - m1) * c1[0] + (T(1) - m3) * c3[0];
+    pos[kt] = (T(1) - m1) * c1[1] + (T(1) - m3) * c3[1];
+    pos[ko] = (T(1) - m1) * c1[2] + (T(1) - m2) * a2 + (T(1) - m3) * c3[2];
 }
 
-// An x-edge with its fluctuations A+dQ (ap) and A-dQ (am) and their splits
-// along y: down-going parts (apd, amd) and up-going parts (apu, amu).
 template <typename T>
-struct XEdge {
-    SEdge<T> e;
-    T ap[3], am[3];
-    T apd[3], amd[3], apu[3], amu[3];
-};
-
-template <typename ETA, typename T>
-__device__ __forceinline__ XEdge<T> x_edge(const SRow<ETA, T> &R, double g, bool trans)
+__device__ __forceinline__ T dot3(const T *a, const T *b)
 {
-    XEdge<T> x;
-    x.e = roe_edge<0>(shift_left(R), R, g);
-    fluct(x.e, false, x.ap);
-    fluct(x.e, true, x.am);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) x.apd[k] = x.amd[k] = x.apu[k] = x.amu[k] = T(0);
-    if (trans) {
-        swe_tsplit(1, x.ap, x.e.ru, x.e.rv, x.e.c, true, x.apd);
-        swe_tsplit(1, x.am, x.e.ru, x.e.rv, x.e.c, true, x.amd);
-        swe_tsplit(1, x.ap, x.e.ru, x.e.rv, x.e.c, false, x.apu);
-        swe_tsplit(1, x.am, x.e.ru, x.e.rv, x.e.c, false, x.amu);
-    }
-    return x;
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// The y-edge below a row as the row's update needs it: B+dQ (bp) and its
-// splits along x, left-going (lft) and right-going (rgt).
+// Limited correction-flux contribution of wave family p: a = upwind wave .
+// own wave, w = own wave, s its speed, nu = dt/dx of the edge's direction.
 template <typename T>
-struct YUp {
-    T w[9];
-    T bp[3], lft[3], rgt[3];
-};
-
-template <typename T>
-__device__ __forceinline__ YUp<T> y_up(const SEdge<T> &E, bool trans)
+__device__ __forceinline__ void corr_add(const T *w, T s, T a, T nu, int lim, T F[3])
 {
-    YUp<T> y;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) y.w[k] = E.w[k];
-    fluct(E, false, y.bp);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) y.lft[k] = y.rgt[k] = T(0);
-    if (trans) {
-        swe_tsplit(0, y.bp, E.ru, E.rv, E.c, true, y.lft);
-        swe_tsplit(0, y.bp, E.ru, E.rv, E.c, false, y.rgt);
+    T phi = T(1);
+    if (lim != 0) {
+        const T b = dot3(w, w);
+        phi = b == T(0) ? T(0) : mc_phi(a / b);
     }
-    return y;
+    const T coef = T(0.5) * sgn(s) * (T(1) - nu * fabs(s));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] += coef * (phi * w[k]);
 }
 
 template <typename T>
@@ -261,13 +234,18 @@ __device__ __forceinline__ T edge_cfl(const T s[3], T nu)
     return fmax(fmax(fabs(s[0]) * nu, fabs(s[1]) * nu), fabs(s[2]) * nu);
 }
 
-// What one row's update hands to the next.
+// What the iteration for row j hands to that for row j + 1.  Every edge is
+// reduced to what later rows need as soon as it is solved, and everything
+// of row j + 1's increment except its G difference is summed ahead.
 template <typename T>
 struct SCarry {
-    YUp<T> ym;      // y-edge j - 1/2
-    SEdge<T> yp;    // y-edge j + 1/2
-    XEdge<T> xe;    // x-edge (col - 1/2, j)
-    T Gp[3];        // correction flux at y-edge j - 1/2
+    T yw[9], ys[3];        // waves and speeds of the y-edge j + 1/2
+    T dlo[3];              // per family: waves of y-edges j - 1/2 and j + 1/2 dotted
+    T bpP[3];              // B+dQ of the y-edge j + 1/2 (into row j + 1) ...
+    T bpl[3], bpr[3];      // ... and its left- and right-going parts
+    T apu[3], amu[3];      // up-going parts of the x-fluctuations of row j
+    T P[3];                // increment of row j without nuy (G(j + 1/2) - G(j - 1/2))
+    T Gp[3];               // correction flux at the y-edge j - 1/2
 };
 
 struct SOpts {
@@ -275,95 +253,156 @@ struct SOpts {
     int lim;
 };
 
+// Carry for the first iteration (the update of row j0 - 1 is not formed):
+// rows Ra = j0 - 2, R0 = j0 - 1, R1 = j0.
 template <typename ETA, typename T>
 __device__ __forceinline__ void swe_start(const SRow<ETA, T> &Ra, const SRow<ETA, T> &R0, const SRow<ETA, T> &R1,
                                           double g, const SOpts &op, SCarry<T> &c)
 {
-    c.ym = y_up(roe_edge<1>(Ra, R0, g), op.trans);
-    c.yp = roe_edge<1>(R0, R1, g);
-    c.xe = x_edge(R0, g, op.trans);
+    const SEdge<T> ym = roe_edge<1>(Ra, R0, g);
+    const SEdge<T> yp = roe_edge<1>(R0, R1, g);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) c.Gp[k] = T(0);
+    for (int p = 0; p < 3; ++p) c.dlo[p] = dot3(&ym.w[3 * p], &yp.w[3 * p]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.yw[k] = yp.w[k];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) c.ys[p] = yp.s[p];
+    T bm[3];
+    flucts(yp, bm, c.bpP);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.bpl[k] = c.bpr[k] = T(0);
+    if (op.trans) swe_tsplit(0, c.bpP, yp.ru, yp.rv, yp.c, c.bpl, c.bpr);
+    const SEdge<T> xe = roe_edge<0>(shift_left(R0), R0, g);
+    T am[3], ap[3], dn[3];
+    flucts(xe, am, ap);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.apu[k] = c.amu[k] = T(0);
+    if (op.trans) {
+        swe_tsplit(1, ap, xe.ru, xe.rv, xe.c, dn, c.apu);
+        swe_tsplit(1, am, xe.ru, xe.rv, xe.c, dn, c.amu);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.P[k] = c.Gp[k] = T(0);
 }
 
-// Update of row j (R0) from rows j, j+1 (R1) and j+2 (R2) and the carry;
-// cx_in / cy_in: whether this row's x-edges / the y-edge j + 1/2 count
+// Iteration for row j: solves the y-edge j + 3/2 and the x-edge of row
+// j + 1, forms the correction fluxes G at the y-edge j + 1/2 and F at the
+// x-edge of row j + 1, and (upd) the update of row j (R0) into en, qun, qvn.
+// cy_in / cx_in: whether the y-edge j + 1/2 / the x-edge of row j + 1 count
 // toward the Courant number.
 template <typename ETA, typename T>
 __device__ __forceinline__ void swe_row(const SRow<ETA, T> &R0, const SRow<ETA, T> &R1, const SRow<ETA, T> &R2,
-                                        double g, T nux, T nuy, const SOpts &op, bool cx_in, bool cy_in,
+                                        double g, T nux, T nuy, const SOpts &op, bool upd, bool cy_in, bool cx_in,
                                         SCarry<T> &c, T &cfl, ETA &en, T &qun, T &qvn)
 {
-    const SEdge<T> yn = roe_edge<1>(R1, R2, g);   // y-edge j + 3/2
-    const XEdge<T> xn = x_edge(R1, g, op.trans);  // x-edge (col - 1/2, j + 1)
     const T hx = T(0.5) * nux, hy = T(0.5) * nuy;
-    // correction flux F at the x-edge (col - 1/2, j)
-    T F[3] = {T(0), T(0), T(0)};
-    if (cx_in) cfl = fmax(cfl, edge_cfl(c.xe.e.s, nux));
-    if (op.second) {
-        T wl[9], wr[9];
+    // y-edge j + 3/2: fluctuations and their splits along x
+    const SEdge<T> yn = roe_edge<1>(R1, R2, g);
+    T bmN[3], bpN[3], bml[3], bmr[3], bpl[3], bpr[3];
+    flucts(yn, bmN, bpN);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            wl[k] = from_left(c.xe.e.w[k]);
-            wr[k] = from_right(c.xe.e.w[k]);
-        }
-        corr_flux<3>(c.xe.e.w, c.xe.e.s, wl, wr, nux, op.lim, F);
-    }
-    // B-dQ of the y-edge j + 1/2 into this cell and its splits along x
-    T bm[3], bml[3] = {T(0), T(0), T(0)}, bmr[3] = {T(0), T(0), T(0)};
-    fluct(c.yp, true, bm);
+    for (int k = 0; k < 3; ++k) bml[k] = bmr[k] = bpl[k] = bpr[k] = T(0);
     if (op.trans) {
-        swe_tsplit(0, bm, c.yp.ru, c.yp.rv, c.yp.c, true, bml);
-        swe_tsplit(0, bm, c.yp.ru, c.yp.rv, c.yp.c, false, bmr);
-        // the y-fluctuations of this cell going left, then those of the
-        // left neighbour going right
-        sub_scaled(F, hy, c.ym.lft);
-        sub_scaled(F, hy, bml);
-        T d[3];
+        swe_tsplit(0, bmN, yn.ru, yn.rv, yn.c, bml, bmr);
+        swe_tsplit(0, bpN, yn.ru, yn.rv, yn.c, bpl, bpr);
+    }
+    T dhi[3];   // per family: waves of y-edges j + 1/2 and j + 3/2 dotted
 #pragma unroll
-        for (int k = 0; k < 3; ++k) d[k] = from_left(c.ym.rgt[k]);
+    for (int p = 0; p < 3; ++p) dhi[p] = dot3(&yn.w[3 * p], &c.yw[3 * p]);
+    // G at the y-edge (col, j + 1/2): limited waves
+    T G[3] = {T(0), T(0), T(0)};
+    if (cy_in) cfl = fmax(cfl, edge_cfl(c.ys, nuy));
+    if (op.second) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) corr_add(&c.yw[3 * p], c.ys[p], c.ys[p] > T(0) ? c.dlo[p] : dhi[p], nuy, op.lim, G);
+    }
+    // x-edge (col - 1/2, j + 1): fluctuations and their splits along y
+    const SEdge<T> xn = roe_edge<0>(shift_left(R1), R1, g);
+    T am[3], ap[3], amd[3], amu[3], apd[3], apu[3];
+    flucts(xn, am, ap);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) amd[k] = amu[k] = apd[k] = apu[k] = T(0);
+    if (op.trans) {
+        swe_tsplit(1, ap, xn.ru, xn.rv, xn.c, apd, apu);
+        swe_tsplit(1, am, xn.ru, xn.rv, xn.c, amd, amu);
+        // G: the x-fluctuations of (col, j + 1) going down, then those of
+        // (col, j) going up; those of the right edges come from the next lane
+        T d[3];
+        sub_scaled(G, hx, apd);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_right(amd[k]);
+        sub_scaled(G, hx, d);
+        sub_scaled(G, hx, c.apu);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_right(c.amu[k]);
+        sub_scaled(G, hx, d);
+    }
+    if (upd) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T inc = c.P[k] + nuy * (G[k] - c.Gp[k]);
+            if (k == 0) en = R0.eta - (ETA)inc;
+            if (k == 1) qun = R0.hu - inc;
+            if (k == 2) qvn = R0.hv - inc;
+        }
+    }
+    // F at the x-edge (col - 1/2, j + 1); the upwind wave's dot product with
+    // the left neighbour edge is the left lane's with its right neighbour
+    T F[3] = {T(0), T(0), T(0)};
+    if (cx_in) cfl = fmax(cfl, edge_cfl(xn.s, nux));
+    if (op.second) {
+        T dR[3], dL[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            T wr[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) wr[k] = from_right(xn.w[3 * p + k]);
+            dR[p] = dot3(wr, &xn.w[3 * p]);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) dL[p] = from_left(dR[p]);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) corr_add(&xn.w[3 * p], xn.s[p], xn.s[p] > T(0) ? dL[p] : dR[p], nux, op.lim, F);
+    }
+    if (op.trans) {
+        // the y-fluctuations of row j + 1 going left, then those of the
+        // left neighbour going right
+        T d[3];
+        sub_scaled(F, hy, c.bpl);
+        sub_scaled(F, hy, bml);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[k] = from_left(c.bpr[k]);
         sub_scaled(F, hy, d);
 #pragma unroll
         for (int k = 0; k < 3; ++k) d[k] = from_left(bmr[k]);
         sub_scaled(F, hy, d);
     }
-    // correction flux G at the y-edge (col, j + 1/2)
-    T G[3] = {T(0), T(0), T(0)};
-    if (cy_in) cfl = fmax(cfl, edge_cfl(c.yp.s, nuy));
-    if (op.second) corr_flux<3>(c.yp.w, c.yp.s, c.ym.w, yn.w, nuy, op.lim, G);
-    if (op.trans) {
-        // the x-fluctuations of (col, j + 1) going down, then those of
-        // (col, j) going up; those of the right edges come from the next lane
-        T d[3];
-        sub_scaled(G, hx, xn.apd);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d[k] = from_right(xn.amd[k]);
-        sub_scaled(G, hx, d);
-        sub_scaled(G, hx, c.xe.apu);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) d[k] = from_right(c.xe.amu[k]);
-        sub_scaled(G, hx, d);
-    }
-    T inc[3];
+    // row j + 1's increment so far: A+dQ + A-dQ, B+dQ + B-dQ, F difference
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const T am = from_right(c.xe.am[k]), Fr = from_right(F[k]);
-        inc[k] = nux * (c.xe.ap[k] + am) + nuy * (c.ym.bp[k] + bm[k]) + nux * (Fr - F[k]) + nuy * (G[k] - c.Gp[k]);
+        const T amr = from_right(am[k]), Fr = from_right(F[k]);
+        c.P[k] = nux * (ap[k] + amr) + nuy * (c.bpP[k] + bmN[k]) + nux * (Fr - F[k]);
     }
-    en = R0.eta - (ETA)inc[0];
-    qun = R0.hu - inc[1];
-    qvn = R0.hv - inc[2];
-    c.ym = y_up(c.yp, op.trans);
-    c.yp = yn;
-    c.xe = xn;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) c.Gp[k] = G[k];
+    for (int k = 0; k < 9; ++k) c.yw[k] = yn.w[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        c.ys[k] = yn.s[k];
+        c.dlo[k] = dhi[k];
+        c.bpP[k] = bpN[k];
+        c.bpl[k] = bpl[k];
+        c.bpr[k] = bpr[k];
+        c.apu[k] = apu[k];
+        c.amu[k] = amu[k];
+        c.Gp[k] = G[k];
+    }
 }
 
 // RT > 0: tiles of at most RT rows, the march fully unrolled with rows
 // requested PREFETCH iterations ahead; RT = 0: any height, a rolling window
-// of rows prefetched two rows ahead.
-template <typename ETA, typename T, int RT>
+// of rows prefetched two rows ahead.  FULL: second order, MC limiter and
+// transverse terms fixed at compile time, else as the instance says.
+template <typename ETA, typename T, int RT, bool FULL>
 __global__ __launch_bounds__(WAVE) void swe2d_kernel(const SweInst<ETA, T> *__restrict__ inst,
                                                      const Tile *__restrict__ tiles, int parity,
                                                      int *__restrict__ status, unsigned *__restrict__ cflbits)
@@ -383,7 +422,7 @@ __global__ __launch_bounds__(WAVE) void swe2d_kernel(const SweInst<ETA, T> *__re
     const __amdgpu_buffer_rsrc_t wv = make_rsrc(I.hv[parity ^ 1], cells * ST);
     const double g = I.g;
     const T nux = (T)I.nux, nuy = (T)I.nuy;
-    const SOpts op{I.order >= 2, I.transverse != 0, I.limiter};
+    const SOpts op = FULL ? SOpts{true, true, 1} : SOpts{I.order >= 2, I.transverse != 0, I.limiter};
     const int col = tl.i0 - 2 + lane;
     bool fx;
     const int cx = resolve(col, nx, I.bc[0], I.bc[1], fx);
@@ -434,10 +473,10 @@ __global__ __launch_bounds__(WAVE) void swe2d_kernel(const SweInst<ETA, T> *__re
             }
             const int j = j0 - 1 + it;
             const SRow<ETA, T> R2 = derive(raw[it + 3], bad);
-            ETA en;
-            T qun, qvn;
-            swe_row(R0, R1, R2, g, nux, nuy, op, xedge_lane && it > 0 && j < j1, out_lane && j + 1 <= j1, c, cfl,
-                    en, qun, qvn);
+            ETA en = ETA(0);
+            T qun = T(0), qvn = T(0);
+            swe_row(R0, R1, R2, g, nux, nuy, op, it > 0, out_lane && j + 1 <= j1, xedge_lane && j + 1 < j1, c,
+                    cfl, en, qun, qvn);
             if (it > 0) put(j, true, en, qun, qvn);
             R0 = R1;
             R1 = R2;
@@ -457,9 +496,9 @@ __global__ __launch_bounds__(WAVE) void swe2d_kernel(const SweInst<ETA, T> *__re
         for (int j = j0 - 1; j < j1; ++j) {
             ld(X2, j + 4);   // row j + 2 (X0) was requested two iterations ago
             const SRow<ETA, T> R2 = derive(X0, bad);
-            ETA en;
-            T qun, qvn;
-            swe_row(R0, R1, R2, g, nux, nuy, op, xedge_lane && j >= j0, out_lane, c, cfl, en, qun, qvn);
+            ETA en = ETA(0);
+            T qun = T(0), qvn = T(0);
+            swe_row(R0, R1, R2, g, nux, nuy, op, true, out_lane, xedge_lane && j + 1 < j1, c, cfl, en, qun, qvn);
             put(j, j >= j0, en, qun, qvn);
             R0 = R1;
             R1 = R2;
@@ -502,6 +541,7 @@ template <typename T>
 struct LEdge {
     T w[6];
     T s[2];
+    T inv;   // 1 / (c_L + c_R)
 };
 
 template <int DIR, typename T>
@@ -520,21 +560,24 @@ __device__ __forceinline__ LEdge<T> lsw_edge(const LRow<T> &L, const LRow<T> &R)
     e.w[3] = -b2 * cr; e.w[3 + n] = b2; e.w[3 + t] = T(0);
     e.s[0] = -cl;
     e.s[1] = cr;
+    e.inv = inv;
     return e;
 }
 
 // transverse split along tdir of d living in a cell with sound speed cown:
-// the part into the lo neighbour (neg) or into the hi neighbour
+// the part into the lo neighbour (neg, cn = c_lo) or into the hi neighbour
+// (cn = c_hi); inv = 1 / (c_lo + cown) or 1 / (cown + c_hi), the edge's own
+// reciprocal sum
 template <typename T>
-__device__ __forceinline__ void lsw_tsplit(int tdir, const T d[3], T clo, T cown, T chi, bool neg, T o[3])
+__device__ __forceinline__ void lsw_tsplit(int tdir, const T d[3], T cn, T cown, T inv, bool neg, T o[3])
 {
     const int n = tdir == 0 ? 1 : 2, t = tdir == 0 ? 2 : 1;
     if (neg) {
-        const T gm = (d[0] + cown * d[n]) / (clo + cown);
-        o[0] = -clo * gm * clo; o[n] = -clo * gm; o[t] = T(0);
+        const T gm = (d[0] + cown * d[n]) * inv;
+        o[0] = -cn * gm * cn; o[n] = -cn * gm; o[t] = T(0);
     } else {
-        const T gp = (cown * d[n] - d[0]) / (cown + chi);
-        o[0] = -chi * gp * chi; o[n] = chi * gp; o[t] = T(0);
+        const T gp = (cown * d[n] - d[0]) * inv;
+        o[0] = -cn * gp * cn; o[n] = cn * gp; o[t] = T(0);
     }
 }
 
@@ -566,40 +609,40 @@ __device__ __forceinline__ void lswe_row(const LRow<T> &R0, const LRow<T> &R1, c
         corr_flux<2>(c.xe.w, c.xe.s, wl, wr, nux, op.lim, F);
     }
     if (op.trans) {
-        const T cL = from_left(R0.c), cR = R0.c;
+        const T cL = from_left(R0.c), cR = R0.c, inv = c.xe.inv;
         T d[3], o[3];
         // the y-fluctuations of this cell going left ...
-        lsw_tsplit(0, &c.ym.w[3], cL, cR, T(0), true, o);
+        lsw_tsplit(0, &c.ym.w[3], cL, cR, inv, true, o);
         sub_scaled(F, hy, o);
-        lsw_tsplit(0, &c.yp.w[0], cL, cR, T(0), true, o);
+        lsw_tsplit(0, &c.yp.w[0], cL, cR, inv, true, o);
         sub_scaled(F, hy, o);
         // ... and those of the left neighbour going right
 #pragma unroll
         for (int k = 0; k < 3; ++k) d[k] = from_left(c.ym.w[3 + k]);
-        lsw_tsplit(0, d, T(0), cL, cR, false, o);
+        lsw_tsplit(0, d, cR, cL, inv, false, o);
         sub_scaled(F, hy, o);
 #pragma unroll
         for (int k = 0; k < 3; ++k) d[k] = from_left(c.yp.w[k]);
-        lsw_tsplit(0, d, T(0), cL, cR, false, o);
+        lsw_tsplit(0, d, cR, cL, inv, false, o);
         sub_scaled(F, hy, o);
     }
     // G at the y-edge (col, j + 1/2)
     T G[3] = {T(0), T(0), T(0)};
     if (op.second) corr_flux<2>(c.yp.w, c.yp.s, c.ym.w, yn.w, nuy, op.lim, G);
     if (op.trans) {
-        const T cB = R0.c, cA = R1.c;
+        const T cB = R0.c, cA = R1.c, inv = c.yp.inv;
         T d[3], o[3];
         // the x-fluctuations of (col, j + 1) going down ...
-        lsw_tsplit(1, &xn.w[3], cB, cA, T(0), true, o);
+        lsw_tsplit(1, &xn.w[3], cB, cA, inv, true, o);
         sub_scaled(G, hx, o);
 #pragma unroll
         for (int k = 0; k < 3; ++k) d[k] = from_right(xn.w[k]);
-        lsw_tsplit(1, d, cB, cA, T(0), true, o);
+        lsw_tsplit(1, d, cB, cA, inv, true, o);
         sub_scaled(G, hx, o);
         // ... and those of (col, j) going up
-        lsw_tsplit(1, &c.xe.w[3], T(0), cB, cA, false, o);
+        lsw_tsplit(1, &c.xe.w[3], cA, cB, inv, false, o);
         sub_scaled(G, hx, o);
-        lsw_tsplit(1, am, T(0), cB, cA, false, o);
+        lsw_tsplit(1, am, cA, cB, inv, false, o);
         sub_scaled(G, hx, o);
     }
 #pragma unroll
@@ -728,15 +771,27 @@ __global__ __launch_bounds__(WAVE) void lswe_adj_kernel(const LsweInst<T> *__res
     }
 
 template <typename ETA, typename T>
-void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int *status,
-                  unsigned *cflbits, hipStream_t s)
+void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int rows, bool full, int parity,
+                  int *status, unsigned *cflbits, hipStream_t s)
 {
     if (ntiles <= 0) return;
-#define WP_L(R)                                                                                                   \
-    hipLaunchKernelGGL((swe2d_kernel<ETA, T, R>), dim3(ntiles), dim3(WAVE), 0, s, inst, tiles, parity, status, \
-                       cflbits)
-    WP_SWE_BY_RT(WP_L)
+    if constexpr (sizeof(T) == 8) {
+        // FP64: the rolling march (about 250 registers, two waves per SIMD)
+        // beats the unrolled one (one wave per SIMD)
+        if (full)
+            hipLaunchKernelGGL((swe2d_kernel<ETA, T, 0, true>), dim3(ntiles), dim3(WAVE), 0, s, inst, tiles, parity,
+                               status, cflbits);
+        else
+            hipLaunchKernelGGL((swe2d_kernel<ETA, T, 0, false>), dim3(ntiles), dim3(WAVE), 0, s, inst, tiles, parity,
+                               status, cflbits);
+    } else {
+        if (!full) rows = 0;
+#define WP_L(R)                                                                                                  \
+    hipLaunchKernelGGL((swe2d_kernel<ETA, T, R, (R > 0)>), dim3(ntiles), dim3(WAVE), 0, s, inst, tiles, parity, \
+                       status, cflbits)
+        WP_SWE_BY_RT(WP_L)
 #undef WP_L
+    }
 }
 
 template <typename T>
@@ -751,9 +806,9 @@ void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, i
 #undef WP_L
 }
 
-template void launch_swe2d<double, double>(const SweInst<double, double> *, const Tile *, int, int, int, int *,
-                                           unsigned *, hipStream_t);
-template void launch_swe2d<double, float>(const SweInst<double, float> *, const Tile *, int, int, int, int *,
+template void launch_swe2d<double, double>(const SweInst<double, double> *, const Tile *, int, int, bool, int,
+                                           int *, unsigned *, hipStream_t);
+template void launch_swe2d<double, float>(const SweInst<double, float> *, const Tile *, int, int, bool, int, int *,
                                           unsigned *, hipStream_t);
 template void launch_lswe_adj2d<double>(const LsweInst<double> *, const Tile *, int, int, int, int, int *,
                                         hipStream_t);

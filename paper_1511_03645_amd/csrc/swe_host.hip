@@ -123,6 +123,8 @@ int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, i
     int rc;
     if ((rc = wp_swe_prepare(ctx, lv, dt)) != WP_OK) return rc;
     const bool f64 = ctx->prob.precision == WP_FP64;
+    // second order, MC limiter and transverse terms: the compile-time march
+    const bool full = ctx->prob.order == 2 && ctx->prob.limiter == 1 && ctx->prob.transverse == 1;
     if (adjoint) {
         if (f64)
             launch_lswe_adj2d<double>((const LsweInst<double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur, snap_index,
@@ -132,11 +134,11 @@ int wp_swe_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, i
                                      ctx->status, s);
     } else {
         if (f64)
-            launch_swe2d<double, double>((const SweInst<double, double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur,
-                                         ctx->status, ctx->cflbits, s);
+            launch_swe2d<double, double>((const SweInst<double, double> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, full,
+                                         lv.cur, ctx->status, ctx->cflbits, s);
         else
-            launch_swe2d<double, float>((const SweInst<double, float> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, lv.cur,
-                                        ctx->status, ctx->cflbits, s);
+            launch_swe2d<double, float>((const SweInst<double, float> *)lv.inst, lv.tiles_dev, lv.ntiles, lv.tile_rows, full,
+                                        lv.cur, ctx->status, ctx->cflbits, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "shallow-water launch: %s", hipGetErrorString(e));

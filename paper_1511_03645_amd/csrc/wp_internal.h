@@ -95,8 +95,8 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, in
                    int snap_index, int *status, hipStream_t s);
 
 template <typename ETA, typename T>
-void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int *status,
-                  unsigned *cflbits, hipStream_t s);
+void launch_swe2d(const SweInst<ETA, T> *inst, const Tile *tiles, int ntiles, int rows, bool full, int parity,
+                  int *status, unsigned *cflbits, hipStream_t s);
 template <typename T>
 void launch_lswe_adj2d(const LsweInst<T> *inst, const Tile *tiles, int ntiles, int rows, int parity, int snap_index,
                        int *status, hipStream_t s);
