@@ -46,7 +46,10 @@ def parse():
     ap.add_argument("--no-swe", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
     ap.add_argument("--rows", type=int, default=0,
-                    help="tile height of the 2D acoustics kernels (default: chosen by the autotuner)")
+                    help="tile height of the one-step 2D acoustics kernel (default: chosen by the autotuner)")
+    ap.add_argument("--pair-rows", type=int, default=-1,
+                    help="tile height of the two-step kernel: 8, 12 or 16, 0 for one step per launch "
+                         "(default: chosen by the autotuner)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -84,7 +87,7 @@ def calibrate_copy():
 class Job:
     """The whole hot path on one workload instance."""
 
-    def __init__(self, cfg, precision, rows=0):
+    def __init__(self, cfg, precision, rows=0, pair_rows=-1):
         import torch
         import paper_1511_03645_amd as wp
         self.wp = wp
@@ -105,6 +108,14 @@ class Job:
             self.rows, self.tune_us = rows, {}
         else:
             self.rows, self.tune_us = tune(self.w, cfg["dt"], use_cache=False)
+        # two steps per launch in the graph-captured runs: tile height tuned
+        # the same way (-1), given, or off (0)
+        from paper_1511_03645_amd.autotune import tune_pairs
+        if pair_rows == -1:
+            self.pair_rows, self.pair_tune_us = tune_pairs(self.w, cfg["dt"])
+        else:
+            self.w.set_step_pairs(pair_rows)
+            self.pair_rows, self.pair_tune_us = self.w.get_step_pairs(), {}
 
     def run(self, time_kernels=False):
         cfg, w = self.cfg, self.w
@@ -344,14 +355,20 @@ def main():
     print(f"[bench] workload {cfg['nx']}x{cfg['ny']}, {cfg['nsteps']} forward + {cfg['nsteps']} adjoint steps "
           f"per job, flags every {cfg['flag_every']}", file=sys.stderr, flush=True)
 
-    job = Job(cfg, wp.FP64, args.rows)
+    job = Job(cfg, wp.FP64, args.rows, args.pair_rows)
     sec, J64 = timed(job, args.steps, args.warmup, time_kernels=True)
     value = job.updates() / sec
-    kern_ms = float(np.mean(job.kernel_ms))
+    # the forward run's step launches: kernel_ms holds the device time per
+    # step; a two-step launch reads and writes the state once
+    spl = 2 if job.pair_rows else 1
+    step_ms = float(np.mean(job.kernel_ms))
+    launch_ms = spl * step_ms
     alg = ALG_BYTES[64] * job.cells
-    achieved = alg / (kern_ms * 1e-3) / 1e9
-    print(f"[bench] fp64: {sec * 1e3:.2f} ms/job, {value / 1e9:.2f} Gcell-updates/s, forward kernel "
-          f"{kern_ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+    achieved = alg / (launch_ms * 1e-3) / 1e9
+    kname = "acou2d_pair_kernel<double, forward>" if spl == 2 else "acou2d_kernel<double, forward>"
+    print(f"[bench] fp64: {sec * 1e3:.2f} ms/job, {value / 1e9:.2f} Gcell-updates/s, forward launch "
+          f"{launch_ms * 1e3:.1f} us for {spl} step(s) ({kname}, rows {job.pair_rows or job.rows})",
+          file=sys.stderr, flush=True)
     out = {
         "metric": "cell-updates/sec (fwd+adjoint) + % HBM roofline; FP32-batched vs FP64 at stated J error",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -362,15 +379,17 @@ def main():
                    "cells": job.cells, "steps_per_solve": cfg["nsteps"], "snapshots": cfg["nsteps"] // 10 + 1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(job.cells),
-                     "kernel": "acou2d_kernel<double, forward>", "kernel_us": kern_ms * 1e3,
-                     "alg_bytes_per_launch": alg, "tile_rows": job.rows},
+                     "kernel": kname, "kernel_us": launch_ms * 1e3, "steps_per_launch": spl,
+                     "alg_bytes_per_launch": alg, "tile_rows": job.pair_rows or job.rows},
         "J": J64,
     }
     if not args.no_fp32:
         job32 = Job(cfg, wp.FP32)
         sec32, J32 = timed(job32, args.steps, args.warmup, time_kernels=True)
-        k32 = float(np.mean(job32.kernel_ms))
-        out["fp32"] = {"value": job32.updates() / sec32, "ms_per_step": sec32 * 1e3, "tile_rows": job32.rows,
+        spl32 = 2 if job32.pair_rows else 1
+        k32 = spl32 * float(np.mean(job32.kernel_ms))
+        out["fp32"] = {"value": job32.updates() / sec32, "ms_per_step": sec32 * 1e3,
+                       "tile_rows": job32.pair_rows or job32.rows, "steps_per_launch": spl32,
                        "speedup_vs_fp64": sec / sec32, "J_rel_err_vs_fp64": abs(J32 - J64) / abs(J64),
                        "kernel_us": k32 * 1e3,
                        "achieved_GBs": ALG_BYTES[32] * job.cells / (k32 * 1e-3) / 1e9}

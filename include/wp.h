@@ -293,9 +293,22 @@ const char *wp_batch_last_error(const wp_batch *b);
 int wp_set_tile_rows(wp_ctx *ctx, int rows);
 int wp_get_tile_rows(const wp_ctx *ctx, int *rows);
 
+/* Two steps per launch (the wave-propagation update of Sec. 3 applied
+ * twice, the intermediate state kept in registers, its ghost cells set by
+ * the boundary rules): used by wp_run_graph, wp_adjoint_run and
+ * wp_forward_flagged on a single-level 2D acoustics instance with the full
+ * method (order 2, MC limiter, transverse terms) and no periodic boundary.
+ * rows: -1 the built-in tile height, 0 off (one step per launch), or 8,
+ * 10, 12 or 16 rows per tile.  The results equal those of one step per launch up
+ * to rounding (bit for bit where both use the same per-cell path).
+ * WP_EINVAL for any other rows.  wp_get_step_pairs reports the tile height
+ * of level 0 in use, 0 when its steps go one per launch. */
+int wp_set_step_pairs(wp_ctx *ctx, int rows);
+int wp_get_step_pairs(const wp_ctx *ctx, int *rows);
+
 /* Capture `nsteps` single-level steps of size dt into a HIP graph and replay
- * it `replays` times (the launch sequence is identical to nsteps calls of
- * wp_step_patches on level 0). */
+ * it `replays` times (the steps of nsteps calls of wp_step_patches on level
+ * 0, two per launch where wp_set_step_pairs allows it). */
 int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays);
 
 #ifdef __cplusplus

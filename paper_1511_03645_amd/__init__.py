@@ -108,6 +108,8 @@ _SIGS = {
     "wp_batch_adjoint_run": (_I, [_P, ctypes.POINTER(wp_functional), _I, _I]),
     "wp_batch_last_error": (ctypes.c_char_p, [_P]),
     "wp_set_tile_rows": (_I, [_P, _I]),
+    "wp_set_step_pairs": (_I, [_P, _I]),
+    "wp_get_step_pairs": (_I, [_P, ctypes.POINTER(_I)]),
     "wp_get_tile_rows": (_I, [_P, ctypes.POINTER(_I)]),
     "wp_run_graph": (_I, [_P, _I, _D, _I]),
 }
@@ -398,6 +400,16 @@ class WavePatch:
     def get_tile_rows(self):
         r = ctypes.c_int()
         self._check(lib().wp_get_tile_rows(self.h, ctypes.byref(r)))
+        return r.value
+
+    def set_step_pairs(self, rows):
+        """Two steps per launch in graph, adjoint and flagged runs: rows -1
+        (built-in tile height), 0 (off), 8, 10, 12 or 16."""
+        self._check(lib().wp_set_step_pairs(self.h, rows))
+
+    def get_step_pairs(self):
+        r = ctypes.c_int()
+        self._check(lib().wp_get_step_pairs(self.h, ctypes.byref(r)))
         return r.value
 
     def run_graph(self, nsteps, dt, replays):

@@ -69,3 +69,37 @@ def tune(w, dt, level=0, steps=20, candidates=CANDIDATES, use_cache=True, verbos
     except OSError:
         pass
     return best, times
+
+
+# tile heights of the two-step kernel
+PAIR_CANDIDATES = (8, 10, 12)
+
+
+def tune_pairs(w, dt, steps=20, candidates=PAIR_CANDIDATES, verbose=False):
+    """Pick the two-step tile height for `w` by timing captured runs of
+    `steps` steps at each candidate (the state and time are restored);
+    returns (rows, {rows: microseconds per step}), or (0, {}) when the
+    instance cannot take two steps per launch."""
+    import torch
+    if w.get_step_pairs() == 0:
+        return 0, {}
+    saved = w.get_state(0)
+    t_saved = w.get_time(0)
+    times = {}
+    for rows in candidates:
+        w.set_step_pairs(rows)
+        w.run_graph(steps, dt, 1)     # capture and warm up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        w.run_graph(steps, dt, 2)
+        e1.record()
+        torch.cuda.synchronize()
+        times[rows] = e0.elapsed_time(e1) * 1e3 / (2 * steps)
+        if verbose:
+            print(f"[autotune] two-step rows {rows}: {times[rows]:.2f} us/step", flush=True)
+    best = min(times, key=times.get)
+    w.set_step_pairs(best)
+    w.set_state(saved, 0)
+    w.set_time(t_saved, 0)
+    return best, times

@@ -1,0 +1,261 @@
+// Two acoustics time steps per launch on a single-level 2D canvas (Davis &
+// LeVeque Sec. 3 wave propagation; Sec. 2/4 for the time-reversed adjoint),
+// for gfx950.
+//
+// One 64-lane wave owns a strip of 64 columns: 56 outputs and a four-column
+// halo on each side.  A first march takes the rows j0-4 .. j1+3 of q^n and
+// produces q^{n+1} on rows j0-2 .. j1+1 (lanes 2..61 exact); a second march
+// follows it four rows behind and turns those rows, straight from
+// registers, into q^{n+2} on rows j0 .. j1-1 (lanes 4..59).  q^{n+1} never
+// goes to memory unless it is a snapshot step, so a pair of steps reads the
+// state once and writes it once.
+//
+// The second march needs the ghost cells of q^{n+1}.  They follow the
+// boundary rule from the first march's interior results: ghost columns by a
+// cross-lane permute from the mirrored (wall, u negated) or nearest
+// (extrapolation) column, ghost rows by a copy of the mirrored or nearest
+// row (wall: v negated), taken as soon as that row exists.  Periodic
+// boundaries would need another strip's results and keep the one-step
+// kernel.  Every cell of both steps goes through the same row update as the
+// one-step kernel.
+#include "acou_stencil.h"
+
+namespace wp {
+namespace {
+
+using namespace march;
+
+__device__ __forceinline__ double bperm(double v, int addr)
+{
+    return __hiloint2double(__builtin_amdgcn_ds_bpermute(addr, __double2hiint(v)),
+                            __builtin_amdgcn_ds_bpermute(addr, __double2loint(v)));
+}
+__device__ __forceinline__ float bperm(float v, int addr)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
+// Ghost columns of a first-step row: lane `addr / 4` holds the cell whose
+// value the ghost takes; flip: negate u (wall).
+struct XFix {
+    bool on;     // some lane the second step reads is a ghost column
+    int addr;
+    bool flip;
+};
+
+template <typename T>
+__device__ __forceinline__ void fix_columns(Row<T> &r, const XFix &xf)
+{
+    if (!xf.on) return;
+    r.p = bperm(r.p, xf.addr);
+    const T u = bperm(r.u, xf.addr);
+    r.u = xf.flip ? -u : u;
+    r.v = bperm(r.v, xf.addr);
+}
+
+template <typename T>
+__device__ __forceinline__ Row<T> pick(bool c, const Row<T> &a, const Row<T> &b)
+{
+    return Row<T>{c ? a.p : b.p, c ? a.u : b.u, c ? a.v : b.v, c ? a.m : b.m};
+}
+
+template <typename T>
+__device__ __forceinline__ Row<T> reflect_y(const Row<T> &a, bool wall)
+{
+    return Row<T>{a.p, a.u, wall ? -a.v : a.v, a.m};
+}
+
+// The two marches of one tile (RT rows at most; j0 is 0 or at least 4).
+// First-step iteration i updates row j0-3+i from input rows A[i+1..i+3]
+// (A[r] is row j0-4+r) into S[i-1] (S[s] is row j0-2+s); second-step
+// iteration k = i-4 updates row j0-1+k from S[k+1..k+3].
+template <typename T, bool ADJ, bool UNI, int RT, typename LD>
+__device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &tl, int nx, int ny, bool wall_lo,
+                                           bool wall_hi, T nux, T nuy, unsigned csb, unsigned out_off0,
+                                           bool out_lane, const XFix &xf, __amdgpu_buffer_rsrc_t qw,
+                                           __amdgpu_buffer_rsrc_t s1w, __amdgpu_buffer_rsrc_t s2w, const LD &ld,
+                                           int &bad)
+{
+    constexpr int NA = RT + 8;
+    constexpr int NS = RT + 4;
+    constexpr int FIRST = 3 + PREFETCH < NA ? 3 + PREFETCH : NA;
+    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    Row<T> A[NA];
+    Row<T> S[NS];
+#pragma unroll
+    for (int r = 0; r < FIRST; ++r) ld(A[r], j0 - 4 + r);
+    __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+    Carry<T> ca, cb;
+    march_start<T, ADJ, UNI>(md, A[0], A[1], A[2], ca);
+    // stores of halo lanes and of rows outside the tile go to this offset,
+    // beyond the buffer's range (3 components), where they are dropped; a
+    // snapshot store has an empty range when that step takes no snapshot
+    const unsigned nowhere = 3u * csb;
+    const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);
+#pragma unroll
+    for (int i = 0; i <= RT + 4; ++i) {
+        if (FIRST + i < NA) {
+            ld(A[FIRST + i], j0 - 4 + FIRST + i);
+            __builtin_amdgcn_sched_barrier(SCHED_KEEP_LOADS);
+        }
+        T pn, un, vn;
+        row_step<T, ADJ, UNI>(md, true, true, 1, nux, nuy, A[i + 1], A[i + 2], A[i + 3], ca, pn, un, vn);
+        if (i == 0) continue;   // the first row only starts the y-edge fluxes
+        const int s = i - 1;
+        const int r = j0 - 2 + s;
+        {
+            const bool keep = r >= j0 && r < j1 && out_lane;
+            const unsigned off = keep ? (unsigned)r * rowb + out_off0 : nowhere;
+            bstore(s1w, off, 0u, pn);
+            bstore(s1w, off, csb, un);
+            bstore(s1w, off, 2u * csb, vn);
+            bad |= keep & !(isfinite(pn) & isfinite(un) & isfinite(vn));
+        }
+        Row<T> o{pn, un, vn, A[s + 2].m};
+        fix_columns(o, xf);
+        // ghost rows above the domain (the rows they copy come first)
+        if (s >= 3) {
+            const Row<T> g0 = reflect_y(S[s - 1], wall_hi);              // row ny
+            const Row<T> g1 = wall_hi ? reflect_y(S[s - 3], true) : S[s - 2];   // row ny + 1
+            o = pick(r == ny, g0, pick(r == ny + 1, g1, o));
+        }
+        S[s] = o;
+        if (s == 3) {
+            // ghost rows below the domain, once rows 0 and 1 exist
+            const bool bot = j0 == 0;
+            const Row<T> g1 = reflect_y(S[2], wall_lo);                  // row -1
+            const Row<T> g2 = wall_lo ? reflect_y(S[3], true) : S[2];    // row -2
+            S[1] = pick(bot, g1, S[1]);
+            S[0] = pick(bot, g2, S[0]);
+        }
+        if (i >= 4) {
+            const int k = i - 4;
+            if (k == 0) march_start<T, ADJ, UNI>(md, S[0], S[1], S[2], cb);
+            T qp, qu, qv;
+            row_step<T, ADJ, UNI>(md, true, true, 1, nux, nuy, S[k + 1], S[k + 2], S[k + 3], cb, qp, qu, qv);
+            if (k == 0) continue;
+            const int j = j0 - 1 + k;
+            const bool keep = j < j1 && out_lane;
+            const unsigned off = keep ? (unsigned)j * rowb + out_off0 : nowhere;
+            bstore(qw, off, 0u, qp);
+            bstore(qw, off, csb, qu);
+            bstore(qw, off, 2u * csb, qv);
+            bstore(s2w, off, 0u, qp);
+            bstore(s2w, off, csb, qu);
+            bstore(s2w, off, 2u * csb, qv);
+            bad |= keep & !(isfinite(qp) & isfinite(qu) & isfinite(qv));
+        }
+    }
+}
+
+// KIND 0: each tile takes the single-material or the mixed path as flagged;
+// KIND 1: every tile is single-material.  stamp: as for the one-step kernel.
+// At most 256 registers, so that two waves share a SIMD (the unconstrained
+// FP64 march takes a few more and would run one).
+template <typename T, bool ADJ, int RT, int KIND>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void acou2d_pair_kernel(const AcouInst<T> *__restrict__ insts,
+                                                           const Tile *__restrict__ tiles, int parity, int snap1,
+                                                           int snap2, int *__restrict__ status,
+                                                           unsigned long long *__restrict__ stamp)
+{
+    if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x] = (unsigned long long)wall_clock64();
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile tl = tiles[blockIdx.x];
+    const AcouInst<T> *__restrict__ Ip = insts + tl.inst;
+    const int lane = threadIdx.x;
+    MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);
+    T *pt = reinterpret_cast<T *>(smem + sizeof(MCon<T>) * MAXMAT);
+    build_tables(*Ip, mc, pt, lane);
+    __syncthreads();
+
+    const int nx = Ip->nx, ny = Ip->ny;
+    const int bc0 = Ip->bc[0], bc1 = Ip->bc[1], bc2 = Ip->bc[2], bc3 = Ip->bc[3];
+    const unsigned cells = (unsigned)nx * (unsigned)ny;
+    const unsigned csb = cells * (unsigned)sizeof(T);
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(Ip->q[parity], 3u * csb);
+    const __amdgpu_buffer_rsrc_t qw = make_rsrc(Ip->q[parity ^ 1], 3u * csb);
+    const __amdgpu_buffer_rsrc_t mr = make_rsrc(Ip->mat, cells);
+    const __amdgpu_buffer_rsrc_t s1w = make_rsrc(snap1 >= 0 ? Ip->snap + (long long)snap1 * Ip->snap_stride : Ip->q[0],
+                                                 snap1 >= 0 ? 3u * csb : 0u);
+    const __amdgpu_buffer_rsrc_t s2w = make_rsrc(snap2 >= 0 ? Ip->snap + (long long)snap2 * Ip->snap_stride : Ip->q[0],
+                                                 snap2 >= 0 ? 3u * csb : 0u);
+    const T nux = Ip->nux, nuy = Ip->nuy;
+    const int col = tl.i0 - 4 + lane;
+    bool fx;
+    const int cx = resolve(col, nx, bc0, bc1, fx);
+    const T sx = fx ? T(-1) : T(1);
+    // ghost columns among the lanes 2..61 that the second step reads
+    XFix xf;
+    xf.on = tl.i0 < 2 || tl.i0 + 57 >= nx;
+    {
+        const bool ghost = col < 0 || col >= nx;
+        const int src = min(max(ghost ? cx - (tl.i0 - 4) : lane, 0), WAVE - 1);
+        xf.addr = 4 * src;
+        xf.flip = ghost && fx;
+    }
+    const bool out_lane = lane >= 4 && lane < 4 + tl.ni;
+    const unsigned out_off0 = (unsigned)col * (unsigned)sizeof(T);
+    const Resolver rowres(ny, bc2, bc3);
+    auto ld = [=](Row<T> &r, int j) {
+        bool fy;
+        const int jy = rowres(j, fy);
+        const unsigned idx = (unsigned)(jy * nx + cx);
+        const unsigned off = idx * (unsigned)sizeof(T);
+        r.p = bload(qr, off, T(0), 0u);
+        r.u = sx * bload(qr, off, T(0), csb);
+        const T v = bload(qr, off, T(0), 2u * csb);
+        r.v = fy ? -v : v;
+        r.m = KIND == 1 ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
+    };
+    const bool wall_lo = bc2 == WP_BC_WALL, wall_hi = bc3 == WP_BC_WALL;
+    int bad = 0;
+    if (KIND == 1 || tl.mat >= 0) {
+        Media<T, true> md;
+        md.u = make_unicon<T, ADJ>(mc[tl.mat], pt[(tl.mat * Ip->nmat + tl.mat) * 3], nux, nuy);
+        march_pair<T, ADJ, true, RT>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0, out_lane, xf, qw, s1w,
+                                     s2w, ld, bad);
+    } else if (KIND != 1) {
+        // mixed tiles are acou_mixed_rows(RT) high
+        Media<T, false> md{mc, pt, Ip->nmat};
+        march_pair<T, ADJ, false, acou_mixed_rows(RT)>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0,
+                                                       out_lane, xf, qw, s1w, s2w, ld, bad);
+    }
+    if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
+    if (stamp && lane == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+}
+
+}  // namespace
+
+template <typename T>
+void launch_acou2d_pair(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
+                        int nmat_max, int rows, int kind, int snap1, int snap2, int *status, hipStream_t s,
+                        unsigned long long *stamp)
+{
+    if (ntiles <= 0) return;
+    const size_t sm = sizeof(MCon<T>) * MAXMAT + sizeof(T) * 3 * (size_t)nmat_max * nmat_max;
+    const dim3 g(ntiles), b(WAVE);
+#define WP_LAUNCH(ADJ, RT, KIND)                                                                                 \
+    hipLaunchKernelGGL((acou2d_pair_kernel<T, ADJ, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap1, snap2, \
+                       status, stamp)
+#define WP_BY_RT(ADJ, KIND)                  \
+    switch (rows) {                          \
+    case 8: WP_LAUNCH(ADJ, 8, KIND); break;  \
+    case 10: WP_LAUNCH(ADJ, 10, KIND); break; \
+    case 12: WP_LAUNCH(ADJ, 12, KIND); break; \
+    default: WP_LAUNCH(ADJ, 16, KIND); break; \
+    }
+    if (kind == 1) {
+        if (adjoint) { WP_BY_RT(true, 1) } else { WP_BY_RT(false, 1) }
+    } else {
+        if (adjoint) { WP_BY_RT(true, 0) } else { WP_BY_RT(false, 0) }
+    }
+#undef WP_BY_RT
+#undef WP_LAUNCH
+}
+
+template void launch_acou2d_pair<double>(const AcouInst<double> *, const Tile *, int, int, int, int, int, int, int,
+                                         int, int *, hipStream_t, unsigned long long *);
+template void launch_acou2d_pair<float>(const AcouInst<float> *, const Tile *, int, int, int, int, int, int, int,
+                                        int, int *, hipStream_t, unsigned long long *);
+
+}  // namespace wp

@@ -26,6 +26,10 @@ struct Level {
     int ntiles = 0;
     int tile_rows = 0;                   // rows of the step tiles (compile-time march height if supported)
     int nuni = 0;                        // number of single-material tiles (they follow the mixed ones)
+    // two-step tiles (single-level 2D acoustics; see launch_acou2d_pair):
+    // none when the level cannot take two steps per launch
+    wp::Tile *ptiles_dev = nullptr;
+    int nptiles = 0, npuni = 0, pair_rows = 0;
     wp::Tile *ftiles_dev = nullptr;      // flag / reduction tiles
     int nftiles = 0;
     double t = 0.0;
@@ -88,13 +92,14 @@ struct wp_ctx {
     bool phi_valid = false;
     std::string err;
     int tile_rows = 0;
+    int pair_rows = -1;                  // two-step tile height: -1 built-in choice, 0 off
     // captured launch sequences (recorded on an internal stream, replayed on
     // `stream`)
     hipStream_t cap_stream = nullptr;
     // every cached sequence records the tile-table generation it was
     // captured with and is re-captured when a table has been rebuilt since
     hipGraphExec_t graph_exec = nullptr;     // forward steps of level 0
-    int graph_steps = 0, graph_parity = -1;
+    int graph_steps = 0, graph_parity = -1, graph_flip = 0;   // flip: canvas parity change of one replay
     double graph_dt = 0.0;
     unsigned long long graph_gen = 0;
     hipGraphExec_t bo_exec = nullptr;        // two Berger-Oliger coarse steps of every level
@@ -104,7 +109,7 @@ struct wp_ctx {
     unsigned long long topo_gen = 1;         // bumped whenever a tile table changes
     hipGraphExec_t ff_exec = nullptr;        // flagged forward run
     double ff_key[6] = {0, 0, 0, 0, 0, 0}, ff_t0 = 0.0;
-    int ff_parity = -1;
+    int ff_parity = -1, ff_flip = 0;         // flip: canvas parity change of the run
     unsigned long long ff_gen = 0;
     const void *ff_snaps = nullptr;
     unsigned long long *ev_counts = nullptr;   // flagged cells per flag event
@@ -113,7 +118,7 @@ struct wp_ctx {
     size_t stamps_cap = 0;
     unsigned long long *stamp_next = nullptr;  // clock slot for the next 2D acoustics launch
     hipGraphExec_t adj_exec = nullptr;       // adjoint run with snapshot copies
-    int adj_steps = 0, adj_every = 0;
+    int adj_steps = 0, adj_every = 0, adj_end = 0;   // adj_end: canvas parity after the run
     double adj_dt = 0.0;
     unsigned long long adj_gen = 0;
     const void *adj_snaps = nullptr;
@@ -127,7 +132,9 @@ std::vector<wp::Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int in
 int wp_upload_tiles(wp_ctx *ctx, Level &lv);
 int wp_default_rows(const wp_ctx *ctx, const Level &lv);
 uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j);
-void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles, int rows);
+void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles, int rows, int halo = 2);
+bool wp_pair_ready(const wp_ctx *ctx, const Level &lv);
+int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2);
 int wp_alloc_level(wp_ctx *ctx, Level &lv);
 int wp_check_status(wp_ctx *ctx);
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt);

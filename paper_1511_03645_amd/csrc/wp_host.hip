@@ -119,10 +119,11 @@ uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j)
     return ctx->mat0[(size_t)(j / ry) * ctx->grid.nx0 + i / r];
 }
 
-// Mark tiles whose whole read footprint (two-cell halo, ghost cells
-// resolved by the boundary rules) holds one material, and cut the others
-// (mixed) into pieces acou_mixed_rows(rows) high.
-void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &tiles, int rows)
+// Mark tiles whose whole read footprint (`halo` cells around the tile, ghost
+// cells resolved by the boundary rules as the loaders do) holds one
+// material, and cut the others (mixed) into pieces acou_mixed_rows(rows)
+// high.
+void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &tiles, int rows, int halo)
 {
     if (!ctx->is_acoustics || !ctx->kind2d) return;
     std::vector<Tile> out;
@@ -131,9 +132,9 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
     for (auto &t : tiles) {
         int m0 = -1;
         bool uni = true;
-        for (int j = t.j0 - 2; j <= t.j0 + t.nj + 1 && uni; ++j) {
+        for (int j = t.j0 - halo; j <= t.j0 + t.nj + halo - 1 && uni; ++j) {
             const int jj = host_resolve(j, lv.ny, bc[2], bc[3]);
-            for (int i = t.i0 - 2; i <= t.i0 + t.ni + 1; ++i) {
+            for (int i = t.i0 - halo; i <= t.i0 + t.ni + halo - 1; ++i) {
                 const int m = wp_level_mat(ctx, lv, host_resolve(i, lv.nx, bc[0], bc[1]), jj);
                 if (m0 < 0) m0 = m;
                 else if (m != m0) { uni = false; break; }
@@ -151,8 +152,61 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
     tiles.swap(out);
 }
 
+// Whether a level can take two steps per launch: a 2D acoustics canvas
+// covered by one patch, the full method (second order, MC limiter,
+// transverse terms), no periodic boundary.
+static bool pair_capable(const wp_ctx *ctx, const Level &lv)
+{
+    if (!ctx->is_acoustics || !ctx->kind2d || ctx->pair_rows == 0) return false;
+    if (!(ctx->prob.order == 2 && ctx->prob.limiter == 1 && ctx->prob.transverse == 1)) return false;
+    for (int k = 0; k < 4; ++k)
+        if (ctx->prob.bc[k] == WP_BC_PERIODIC) return false;
+    if (lv.nx < 8 || lv.ny < 8 || lv.patches.size() != 1) return false;
+    const wp_patch &p = lv.patches[0];
+    return p.ilo == 0 && p.jlo == 0 && p.nx == lv.nx && p.ny == lv.ny;
+}
+
+// Two-step tiles: PAIR_STRIP columns by pair_rows rows (8, 10, 12 or 16;
+// mixed tiles cut to acou_mixed_rows of that, so every tile starts on row 0
+// or at least 4 rows above it), classified with the four-cell footprint;
+// mixed ones first, each group in XCD order.
+static int upload_pair_tiles(wp_ctx *ctx, Level &lv)
+{
+    if (lv.ptiles_dev) wp_dfree(ctx, lv.ptiles_dev);
+    lv.ptiles_dev = nullptr;
+    lv.nptiles = lv.npuni = lv.pair_rows = 0;
+    if (!pair_capable(ctx, lv)) return WP_OK;
+    const long long cells = (long long)lv.nx * lv.ny;
+    const int rows = ctx->pair_rows > 0 ? ctx->pair_rows : (cells <= (1LL << 19) ? 8 : 12);
+    std::vector<Tile> t = wp_make_tiles(lv.patches, 0, rows, PAIR_STRIP, false);
+    wp_classify_tiles(ctx, lv, t, rows, 4);
+    std::vector<Tile> mixed, uni;
+    for (Tile &x : t) {
+        x.down = 0;
+        (x.mat < 0 ? mixed : uni).push_back(x);
+    }
+    wp_xcd_order(mixed);
+    wp_xcd_order(uni);
+    t = mixed;
+    t.insert(t.end(), uni.begin(), uni.end());
+    lv.ptiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, t.size()));
+    if (!lv.ptiles_dev) return wp_fail(ctx, WP_ENOMEM, "tile table allocation failed");
+    if (!t.empty() && hipMemcpy(lv.ptiles_dev, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "tile upload failed");
+    lv.nptiles = (int)t.size();
+    lv.npuni = (int)uni.size();
+    lv.pair_rows = rows;
+    return WP_OK;
+}
+
+bool wp_pair_ready(const wp_ctx *ctx, const Level &lv)
+{
+    return ctx->pair_rows != 0 && lv.ptiles_dev && lv.nptiles > 0;
+}
+
 int wp_upload_tiles(wp_ctx *ctx, Level &lv)
 {
+    int rc;
     const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
     const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, lv);
     lv.tiles_host = wp_make_tiles(lv.patches, 0, is_1d ? 1 : rows, STRIP, false);
@@ -168,6 +222,7 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
     lv.nuni = (int)uni.size();
     lv.tiles_host = mixed;
     lv.tiles_host.insert(lv.tiles_host.end(), uni.begin(), uni.end());
+    if ((rc = upload_pair_tiles(ctx, lv)) != WP_OK) return rc;
     // flag / reduction tiles: larger blocks of whole patches
     std::vector<Tile> ft = wp_make_tiles(lv.patches, 0, 16, 64, false);
     if (lv.tiles_dev) wp_dfree(ctx, lv.tiles_dev);
@@ -626,6 +681,49 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
     return WP_OK;
 }
 
+// Two steps of a level in one launch; snap1 / snap2: snapshot slots of the
+// first / second step (-1: none).  The result lands in the other canvas.
+template <typename T>
+static int acou_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t stream, int snap1, int snap2)
+{
+    int rc;
+    if ((rc = ensure_acou_inst<T>(ctx, lv, dt)) != WP_OK) return rc;
+    if (stream != ctx->stream && lv.inst_dt != dt) return wp_fail(ctx, WP_ESTATE, "descriptor not prepared before capture");
+    launch_acou2d_pair<T>((const AcouInst<T> *)lv.inst, lv.ptiles_dev, lv.nptiles, lv.cur, adjoint, ctx->nmat,
+                          lv.pair_rows, lv.npuni == lv.nptiles ? 1 : 0, snap1, snap2, ctx->status, stream,
+                          ctx->stamp_next);
+    ctx->stamp_next = nullptr;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    lv.cur ^= 1;
+    return WP_OK;
+}
+
+int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2)
+{
+    if (!wp_pair_ready(ctx, lv)) return wp_fail(ctx, WP_ESTATE, "level cannot take two steps per launch");
+    if (ctx->esz == 8) return acou_pair<double>(ctx, lv, dt, adjoint, s, snap1, snap2);
+    return acou_pair<float>(ctx, lv, dt, adjoint, s, snap1, snap2);
+}
+
+extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
+{
+    if (!ctx || !(rows == -1 || rows == 0 || rows == 8 || rows == 10 || rows == 12 || rows == 16)) return WP_EINVAL;
+    ctx->pair_rows = rows;
+    int rc;
+    for (auto &lv : ctx->L)
+        if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
+    if (ctx->adj.q[0] && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
+    return WP_OK;
+}
+
+extern "C" int wp_get_step_pairs(const wp_ctx *ctx, int *rows)
+{
+    if (!ctx || !rows) return WP_EINVAL;
+    *rows = ctx->L.empty() ? 0 : ctx->L[0].pair_rows;
+    return WP_OK;
+}
+
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt)
 {
     if (!(dt > 0.0) || !std::isfinite(dt)) return wp_fail(ctx, WP_EINVAL, "dt must be positive");
@@ -710,9 +808,18 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
         hipStream_t s;
         if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
         int par = lv.cur;
-        for (int k = 0; k < nsteps && rc == WP_OK; ++k) {
-            rc = wp_step_level(ctx, lv, dt, 0, s, -1);
+        // two steps per launch where the level allows it
+        const bool pairs = wp_pair_ready(ctx, lv);
+        for (int k = 0; k < nsteps && rc == WP_OK;) {
+            if (pairs && k + 1 < nsteps) {
+                rc = wp_step_pair(ctx, lv, dt, 0, s, -1, -1);
+                k += 2;
+            } else {
+                rc = wp_step_level(ctx, lv, dt, 0, s, -1);
+                k += 1;
+            }
         }
+        ctx->graph_flip = lv.cur ^ par;
         lv.cur = par;
         int rc2 = wp_graph_end(ctx, s, ctx->graph_exec);
         if (rc != WP_OK) return rc;
@@ -722,20 +829,22 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
         ctx->graph_dt = dt;
         ctx->graph_parity = lv.cur;
     }
+    // the other canvas ends two steps back when the last launch took two
+    const double back = wp_pair_ready(ctx, lv) && nsteps % 2 == 0 ? 2.0 * dt : dt;
     for (int r = 0; r < replays; ++r) {
         if ((rc = wp_graph_launch(ctx, ctx->graph_exec)) != WP_OK) return rc;
-        if (nsteps & 1) {
-            // an odd sequence ends on the other buffer: later replays need the
+        if (ctx->graph_flip) {
+            // a sequence that ends on the other buffer: later replays need the
             // graph captured for that parity
             lv.cur ^= 1;
             lv.t += nsteps * dt;
-            lv.t_prev = lv.t - dt;
+            lv.t_prev = lv.t - back;
             lv.prev_valid = true;
             if (r + 1 < replays) return wp_run_graph(ctx, nsteps, dt, replays - r - 1);
             return WP_OK;
         }
         lv.t += nsteps * dt;
-        lv.t_prev = lv.t - dt;
+        lv.t_prev = lv.t - back;
         lv.prev_valid = true;
     }
     return WP_OK;
@@ -887,18 +996,28 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
         ctx->adj_snaps != ctx->snaps || ctx->adj_gen != ctx->topo_gen) {
         hipStream_t cs;
         if ((rc = wp_graph_begin(ctx, cs)) != WP_OK) return rc;
-        for (int s = 1; s <= sp->nsteps && rc == WP_OK; ++s)
-            rc = wp_step_level(ctx, a, sp->dt, 1, cs, s % sp->snap_every == 0 ? s / sp->snap_every : -1);
+        auto snap_of = [&](int s) { return s % sp->snap_every == 0 ? s / sp->snap_every : -1; };
+        const bool pairs = wp_pair_ready(ctx, a);
+        for (int s = 1; s <= sp->nsteps && rc == WP_OK;) {
+            if (pairs && s + 1 <= sp->nsteps) {
+                rc = wp_step_pair(ctx, a, sp->dt, 1, cs, snap_of(s), snap_of(s + 1));
+                s += 2;
+            } else {
+                rc = wp_step_level(ctx, a, sp->dt, 1, cs, snap_of(s));
+                s += 1;
+            }
+        }
         int rc2 = wp_graph_end(ctx, cs, ctx->adj_exec);
         if (rc != WP_OK) return rc;
         if (rc2 != WP_OK) return rc2;
+        ctx->adj_end = a.cur;
         ctx->adj_steps = sp->nsteps;
         ctx->adj_gen = ctx->topo_gen;
         ctx->adj_every = sp->snap_every;
         ctx->adj_dt = sp->dt;
         ctx->adj_snaps = ctx->snaps;
     } else {
-        a.cur = sp->nsteps & 1;
+        a.cur = ctx->adj_end;
     }
     if ((rc = wp_graph_launch(ctx, ctx->adj_exec)) != WP_OK) return rc;
     wp_adjoint_finish(ctx, sp);
@@ -1033,9 +1152,15 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         ctx->ff_gen = 0;   // pointer changed
     }
     // launch clocks: one (start, end) slot per workgroup of the first two
-    // steps of every block
-    const size_t nslot = 2 * (size_t)std::max(lv.ntiles, 1);
-    const int ntimed = flag_every >= 2 ? 2 : 1;
+    // launches of every block (a launch takes two steps where the level
+    // allows it)
+    const bool pairs = wp_pair_ready(ctx, lv);
+    const int nlaunch = pairs ? flag_every / 2 + (flag_every & 1) : flag_every;
+    const int ntimed = std::min(nlaunch, 2);
+    const int nblk[2] = {pairs && flag_every >= 2 ? lv.nptiles : lv.ntiles,
+                         pairs && flag_every >= 4 ? lv.nptiles : lv.ntiles};
+    const int first_steps = pairs && flag_every >= 2 ? 2 : 1;
+    const size_t nslot = 2 * (size_t)std::max(std::max(lv.ntiles, lv.nptiles), 1);
     if (ctx->stamps_cap < (size_t)nev * ntimed * nslot) {
         if (ctx->stamps) wp_dfree(ctx, ctx->stamps);
         ctx->stamps = (unsigned long long *)wp_dalloc(ctx, sizeof(unsigned long long) * nslot * ntimed * nev);
@@ -1056,13 +1181,21 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         launch_fill_u8((uint8_t *)ctx->ev_counts, (long long)sizeof(unsigned long long) * nev, 0, s);
         for (int k = 0; k < nev && rc == WP_OK; ++k) {
             rc = flag_launch(ctx, 0, tol, lo[k], hi[k], ctx->ev_counts + k, s);
-            for (int st = 0; st < flag_every && rc == WP_OK; ++st) {
-                if (st < ntimed && ctx->is_acoustics && ctx->kind2d)
-                    ctx->stamp_next = ctx->stamps + nslot * ((size_t)ntimed * k + st);
-                rc = wp_step_level(ctx, lv, dt, 0, s, -1);
+            // the block's steps, two per launch where the level allows it
+            for (int st = 0, launch = 0; st < flag_every && rc == WP_OK; ++launch) {
+                if (launch < ntimed && ctx->is_acoustics && ctx->kind2d)
+                    ctx->stamp_next = ctx->stamps + nslot * ((size_t)ntimed * k + launch);
+                if (pairs && st + 1 < flag_every) {
+                    rc = wp_step_pair(ctx, lv, dt, 0, s, -1, -1);
+                    st += 2;
+                } else {
+                    rc = wp_step_level(ctx, lv, dt, 0, s, -1);
+                    st += 1;
+                }
             }
         }
         ctx->stamp_next = nullptr;
+        ctx->ff_flip = lv.cur ^ par;
         lv.cur = par;
         const int rc2 = wp_graph_end(ctx, s, ctx->ff_exec);
         if (rc != WP_OK) return rc;
@@ -1074,8 +1207,8 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         ctx->ff_snaps = ctx->snaps;
     }
     if ((rc = wp_graph_launch(ctx, ctx->ff_exec)) != WP_OK) return rc;
-    lv.cur = (lv.cur + nsteps) & 1;
-    lv.t_prev = lv.t + (double)(nsteps - 1) * dt;
+    lv.cur ^= ctx->ff_flip;
+    lv.t_prev = lv.t + (double)(nsteps - (pairs && flag_every % 2 == 0 ? 2 : 1)) * dt;
     lv.prev_valid = true;
     lv.t += (double)nsteps * dt;
     if (counts || step_ms) {
@@ -1096,27 +1229,29 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
                 hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
                 return wp_fail(ctx, WP_EDEVICE, "launch clock read");
-            // earliest workgroup start and latest end of timed launch i
-            auto window = [&](size_t i, unsigned long long &t0, unsigned long long &t1) {
+            // earliest workgroup start and latest end of timed launch i (the
+            // l-th of its block)
+            auto window = [&](size_t i, int l, unsigned long long &t0, unsigned long long &t1) {
                 t0 = ~0ULL;
                 t1 = 0;
-                for (size_t b = 0; b < nslot / 2; ++b) {
+                for (size_t b = 0; b < (size_t)nblk[l]; ++b) {
                     t0 = std::min(t0, st[nslot * i + 2 * b]);
                     t1 = std::max(t1, st[nslot * i + 2 * b + 1]);
                 }
             };
             for (int k = 0; k < nev; ++k) {
                 unsigned long long a0, a1, b0, b1;
-                window((size_t)ntimed * k, a0, a1);
+                window((size_t)ntimed * k, 0, a0, a1);
                 // launch duration: from its first workgroup start to that of
                 // the next launch (dispatch and completion included); the
-                // workgroup window alone when a block has one step
+                // workgroup window alone when a block has one launch; per
+                // step of that launch
                 unsigned long long d = a1 - a0;
                 if (ntimed == 2) {
-                    window((size_t)ntimed * k + 1, b0, b1);
+                    window((size_t)ntimed * k + 1, 1, b0, b1);
                     d = b0 - a0;
                 }
-                step_ms[k] = (float)((double)d / (double)khz);
+                step_ms[k] = (float)((double)d / (double)khz / first_steps);
             }
         }
     }

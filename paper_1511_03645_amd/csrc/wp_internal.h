@@ -13,6 +13,7 @@ namespace wp {
 constexpr int MAXMAT = 16;     // distinct (rho, K) pairs per acoustics instance
 constexpr int WAVE = 64;       // CDNA wavefront
 constexpr int STRIP = WAVE - 4; // output columns per wave in the 2D kernels
+constexpr int PAIR_STRIP = WAVE - 8;   // output columns per wave of the two-step kernel
 
 // Height of the mixed-material tiles of a 2D acoustics launch whose
 // single-material tiles are `rows` high: their per-cell table lookups make a
@@ -90,6 +91,14 @@ template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
                    int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s,
                    unsigned long long *stamp = nullptr);
+// Two steps per launch on a single-level canvas (tiles PAIR_STRIP wide,
+// rows 8, 10, 12 or 16 high; no periodic boundary); q^{n+2} lands in
+// q[parity ^ 1], and snapshots snap1 / snap2 (-1: none) take q^{n+1} /
+// q^{n+2}.
+template <typename T>
+void launch_acou2d_pair(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
+                        int nmat_max, int rows, int kind, int snap1, int snap2, int *status, hipStream_t s,
+                        unsigned long long *stamp = nullptr);
 template <typename T>
 void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, int parity, int adjoint,
                    int snap_index, int *status, hipStream_t s);

@@ -218,6 +218,7 @@ def test_graph_replay_matches_eager(nsteps):
     dt = 0.8 * cfg["dx"] / float(np.sqrt(cfg["K"] / cfg["rho"]).max())
     eager = wp.from_config(cfg)
     graph = wp.from_config(cfg)
+    graph.set_step_pairs(0)   # one step per launch: the same kernels as eager steps
     eager.set_state(q0)
     graph.set_state(q0)
     for rep in range(3):
@@ -244,8 +245,9 @@ def test_graphs_recaptured_after_tile_change():
     w = wp.from_config(cfg)
     w.set_state(q0)
     q = q0
-    for rows in (8, 12, 16, 5, 24, 32):
+    for rows, pair_rows in ((8, 8), (12, 0), (16, 16), (5, 12), (24, 0), (32, -1)):
         w.set_tile_rows(rows)
+        w.set_step_pairs(pair_rows)
         w.run_graph(6, dt, 1)
         q, _, _ = oracle.run(cfg, "acoustics_fwd", q, 6, dt=dt)
         close64(w.get_state(), q, f"after rows {rows}")
@@ -267,6 +269,7 @@ def test_forward_flagged_equals_flag_and_step_loop():
     cfg = acoustics2d(n=128, seed=1)
     N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
     loop, fused = wp.from_config(cfg), wp.from_config(cfg)
+    fused.set_step_pairs(0)   # one step per launch: the same kernels as eager steps
     for w in (loop, fused):
         w.adjoint_run(cfg["functional"], dt, N, every)
     for rep in range(2):

@@ -17,6 +17,7 @@ def _instances(cfgs, precision, rows=8):
     for c in cfgs:
         w = wp.from_config(c, precision=precision)
         w.set_tile_rows(rows)
+        w.set_step_pairs(0)   # one step per launch, as the batched kernel takes
         w.set_state(c["q0"])
         ws.append(w)
     return ws
