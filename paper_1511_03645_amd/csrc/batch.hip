@@ -25,10 +25,18 @@ struct wp_batch {
     Tile *tiles[2] = {nullptr, nullptr};
     int ntiles[2] = {0, 0};
     int kind[2] = {0, 0};
+    // two steps per launch (every instance able to take them): tile tables
+    // of the two-step kernel
+    int prows = 0;
+    Tile *ptiles[2] = {nullptr, nullptr};
+    int nptiles[2] = {0, 0};
+    int pkind[2] = {0, 0};
     int *status = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int exec_steps[2] = {0, 0};
+    int exec_every[2] = {0, 0};
     int exec_parity[2] = {-1, -1};
+    int exec_end[2] = {0, 0};             // canvas parity after the captured sequence
 };
 
 static int bfail(wp_batch *b, int code, const char *msg)
@@ -39,38 +47,63 @@ static int bfail(wp_batch *b, int code, const char *msg)
 
 static Level &batch_level(wp_ctx *c, int adjoint) { return adjoint ? c->adj : c->L[0]; }
 
-// Descriptors and the combined tile table for the forward levels (adjoint =
-// 0) or the adjoint levels (adjoint = 1) of every instance.
+// Descriptors and the combined tile tables for the forward levels (adjoint =
+// 0) or the adjoint levels (adjoint = 1) of every instance.  The tables
+// depend on the instances' grids and media only, so they are built once per
+// side; the descriptors (step size, snapshot store) are uploaded every time.
 static int build_side(wp_batch *b, int adjoint)
 {
+    const bool tables = !b->tiles[adjoint];
     wp_ctx *c0 = b->inst[0];
     const size_t dsz = b->esz == 8 ? sizeof(AcouInst<double>) : sizeof(AcouInst<float>);
     std::vector<unsigned char> host(dsz * b->inst.size());
-    std::vector<Tile> mixed, uni;
+    std::vector<Tile> mixed, uni, pmixed, puni;
     for (size_t k = 0; k < b->inst.size(); ++k) {
         wp_ctx *c = b->inst[k];
         Level &lv = batch_level(c, adjoint);
         int rc;
         if ((rc = wp_prepare_level(c, lv, b->dts[k])) != WP_OK) return bfail(b, rc, c->err.c_str());
         memcpy(host.data() + k * dsz, lv.inst_host, dsz);
+        if (!tables) continue;
         std::vector<Tile> t = wp_make_tiles(lv.patches, (int)k, b->rows, STRIP, false);
         wp_classify_tiles(c, lv, t, b->rows);
         for (const Tile &x : t) (x.mat < 0 ? mixed : uni).push_back(x);
+        if (b->prows) {
+            std::vector<Tile> pt = wp_make_tiles(lv.patches, (int)k, b->prows, PAIR_STRIP, false);
+            wp_classify_tiles(c, lv, pt, b->prows, 4);
+            for (Tile x : pt) {
+                x.down = 0;
+                (x.mat < 0 ? pmixed : puni).push_back(x);
+            }
+        }
     }
-    wp_xcd_order(mixed);
-    wp_xcd_order(uni);
-    std::vector<Tile> all = mixed;   // slower mixed-material tiles dispatched first
-    all.insert(all.end(), uni.begin(), uni.end());
+    // slower mixed-material tiles dispatched first, each group in XCD order
+    auto table = [&](std::vector<Tile> &mx, std::vector<Tile> &un, Tile *&dev, int &n, int &kind) {
+        wp_xcd_order(mx);
+        wp_xcd_order(un);
+        std::vector<Tile> all = mx;
+        all.insert(all.end(), un.begin(), un.end());
+        if (dev) wp_dfree(c0, dev);
+        dev = (Tile *)wp_dalloc(c0, sizeof(Tile) * std::max<size_t>(1, all.size()));
+        if (!dev) return bfail(b, WP_ENOMEM, "batch tables");
+        if (!all.empty() && hipMemcpy(dev, all.data(), sizeof(Tile) * all.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(b, WP_EDEVICE, "batch table upload");
+        n = (int)all.size();
+        kind = mx.empty() ? 1 : 0;
+        return (int)WP_OK;
+    };
+    int rc;
+    if (tables) {
+        if ((rc = table(mixed, uni, b->tiles[adjoint], b->ntiles[adjoint], b->kind[adjoint])) != WP_OK) return rc;
+        if (b->prows &&
+            (rc = table(pmixed, puni, b->ptiles[adjoint], b->nptiles[adjoint], b->pkind[adjoint])) != WP_OK)
+            return rc;
+    }
     if (!b->desc[adjoint]) b->desc[adjoint] = wp_dalloc(c0, host.size());
-    if (b->tiles[adjoint]) wp_dfree(c0, b->tiles[adjoint]);
-    b->tiles[adjoint] = (Tile *)wp_dalloc(c0, sizeof(Tile) * std::max<size_t>(1, all.size()));
-    if (!b->desc[adjoint] || !b->tiles[adjoint]) return bfail(b, WP_ENOMEM, "batch tables");
-    if (hipMemcpy(b->desc[adjoint], host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->tiles[adjoint], all.data(), sizeof(Tile) * all.size(), hipMemcpyHostToDevice) != hipSuccess)
+    if (!b->desc[adjoint]) return bfail(b, WP_ENOMEM, "batch tables");
+    if (hipMemcpy(b->desc[adjoint], host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
         return bfail(b, WP_EDEVICE, "batch table upload");
-    b->ntiles[adjoint] = (int)all.size();
-    b->kind[adjoint] = mixed.empty() ? 1 : 0;
-    if (b->exec[adjoint]) {
+    if (tables && b->exec[adjoint]) {
         (void)hipGraphExecDestroy(b->exec[adjoint]);
         b->exec[adjoint] = nullptr;
     }
@@ -87,6 +120,18 @@ static void launch_side(wp_batch *b, int adjoint, int parity, int snap_index, hi
         launch_acou2d<float>((const AcouInst<float> *)b->desc[adjoint], b->tiles[adjoint], b->ntiles[adjoint],
                              parity, adjoint, b->nmat_max, b->full, b->rows, b->kind[adjoint], snap_index, b->status,
                              s);
+}
+
+static void launch_side_pair(wp_batch *b, int adjoint, int parity, int snap1, int snap2, hipStream_t s)
+{
+    if (b->esz == 8)
+        launch_acou2d_pair<double>((const AcouInst<double> *)b->desc[adjoint], b->ptiles[adjoint],
+                                   b->nptiles[adjoint], parity, adjoint, b->nmat_max, b->prows, b->pkind[adjoint],
+                                   snap1, snap2, b->status, s);
+    else
+        launch_acou2d_pair<float>((const AcouInst<float> *)b->desc[adjoint], b->ptiles[adjoint],
+                                  b->nptiles[adjoint], parity, adjoint, b->nmat_max, b->prows, b->pkind[adjoint],
+                                  snap1, snap2, b->status, s);
 }
 
 static int common_parity(wp_batch *b, int adjoint)
@@ -145,6 +190,11 @@ extern "C" int wp_batch_create(wp_ctx *const *instances, int n, const double *dt
         cells += (long long)c->L[0].nx * c->L[0].ny;
     }
     b->rows = c0->tile_rows > 0 ? c0->tile_rows : (cells <= (1LL << 22) ? 8 : 12);
+    // two steps per launch when every instance can take them (the first
+    // instance's setting decides the tile height, 0: off)
+    bool pairs = c0->pair_rows != 0;
+    for (wp_ctx *c : b->inst) pairs = pairs && wp_pair_capable(c, c->L[0]);
+    b->prows = !pairs ? 0 : (c0->pair_rows > 0 ? c0->pair_rows : (cells <= (1LL << 19) ? 8 : 12));
     b->status = (int *)wp_dalloc(c0, 256);
     if (!b->status) return bfail(b, WP_ENOMEM, "batch status");
     if (hipMemsetAsync(b->status, 0, 256, b->stream) != hipSuccess) return bfail(b, WP_EDEVICE, "status clear");
@@ -165,6 +215,7 @@ extern "C" void wp_batch_destroy(wp_batch *b)
         for (int s = 0; s < 2; ++s) {
             wp_dfree(c0, b->desc[s]);
             wp_dfree(c0, b->tiles[s]);
+            wp_dfree(c0, b->ptiles[s]);
         }
         wp_dfree(c0, b->status);
     }
@@ -181,22 +232,36 @@ static int run_side(wp_batch *b, int adjoint, int nsteps, int snap_every)
     if (par < 0) return bfail(b, WP_ESTATE, "instances are on different buffers (step them through the batch)");
     wp_ctx *c0 = b->inst[0];
     int rc;
-    if (snap_every > 0 || !b->exec[adjoint] || b->exec_steps[adjoint] != nsteps || b->exec_parity[adjoint] != par) {
+    // the launches read the descriptors (snapshot store included) at run
+    // time, so a sequence is reused while steps, interval and parity match
+    if (!b->exec[adjoint] || b->exec_steps[adjoint] != nsteps || b->exec_every[adjoint] != snap_every ||
+        b->exec_parity[adjoint] != par) {
         hipStream_t cs;
         if ((rc = wp_graph_begin(c0, cs)) != WP_OK) return bfail(b, rc, c0->err.c_str());
         int p = par;
-        for (int s = 1; s <= nsteps; ++s) {
-            launch_side(b, adjoint, p, snap_every > 0 && s % snap_every == 0 ? s / snap_every : -1, cs);
+        auto snap_of = [&](int s) { return snap_every > 0 && s % snap_every == 0 ? s / snap_every : -1; };
+        for (int s = 1; s <= nsteps;) {
+            // two steps per launch where possible; either way the result
+            // lands in the other canvas
+            if (b->prows && s + 1 <= nsteps) {
+                launch_side_pair(b, adjoint, p, snap_of(s), snap_of(s + 1), cs);
+                s += 2;
+            } else {
+                launch_side(b, adjoint, p, snap_of(s), cs);
+                s += 1;
+            }
             p ^= 1;
         }
         if ((rc = wp_graph_end(c0, cs, b->exec[adjoint])) != WP_OK) return bfail(b, rc, c0->err.c_str());
-        b->exec_steps[adjoint] = snap_every > 0 ? -1 : nsteps;   // snapshot sequences are not reused
+        b->exec_steps[adjoint] = nsteps;
+        b->exec_every[adjoint] = snap_every;
         b->exec_parity[adjoint] = par;
+        b->exec_end[adjoint] = p;
     }
     if ((rc = wp_graph_launch(c0, b->exec[adjoint])) != WP_OK) return bfail(b, rc, c0->err.c_str());
     for (size_t k = 0; k < b->inst.size(); ++k) {
         Level &lv = batch_level(b->inst[k], adjoint);
-        lv.cur = (par + nsteps) & 1;
+        lv.cur = b->exec_end[adjoint];
         lv.t += nsteps * b->dts[k];
     }
     return WP_OK;

@@ -133,6 +133,7 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv);
 int wp_default_rows(const wp_ctx *ctx, const Level &lv);
 uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j);
 void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles, int rows, int halo = 2);
+bool wp_pair_capable(const wp_ctx *ctx, const Level &lv);
 bool wp_pair_ready(const wp_ctx *ctx, const Level &lv);
 int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2);
 int wp_alloc_level(wp_ctx *ctx, Level &lv);

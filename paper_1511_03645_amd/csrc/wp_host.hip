@@ -155,7 +155,7 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
 // Whether a level can take two steps per launch: a 2D acoustics canvas
 // covered by one patch, the full method (second order, MC limiter,
 // transverse terms), no periodic boundary.
-static bool pair_capable(const wp_ctx *ctx, const Level &lv)
+bool wp_pair_capable(const wp_ctx *ctx, const Level &lv)
 {
     if (!ctx->is_acoustics || !ctx->kind2d || ctx->pair_rows == 0) return false;
     if (!(ctx->prob.order == 2 && ctx->prob.limiter == 1 && ctx->prob.transverse == 1)) return false;
@@ -175,7 +175,7 @@ static int upload_pair_tiles(wp_ctx *ctx, Level &lv)
     if (lv.ptiles_dev) wp_dfree(ctx, lv.ptiles_dev);
     lv.ptiles_dev = nullptr;
     lv.nptiles = lv.npuni = lv.pair_rows = 0;
-    if (!pair_capable(ctx, lv)) return WP_OK;
+    if (!wp_pair_capable(ctx, lv)) return WP_OK;
     const long long cells = (long long)lv.nx * lv.ny;
     const int rows = ctx->pair_rows > 0 ? ctx->pair_rows : (cells <= (1LL << 19) ? 8 : 12);
     std::vector<Tile> t = wp_make_tiles(lv.patches, 0, rows, PAIR_STRIP, false);

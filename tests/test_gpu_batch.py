@@ -76,3 +76,36 @@ def test_batch_rejects_mismatched_instances():
         wp.Batch([a, c], [cfgs[0]["dt"], cfgs[1]["dt"]])
     with pytest.raises(wp.WPError):
         wp.Batch([a, a], [cfgs[0]["dt"]] * 2)
+
+
+def test_batch_two_step_launches_equal_single_instances():
+    """Batches take two steps per launch when every instance can: with the
+    same two-step tile height, each instance's forward steps and adjoint
+    snapshots equal its own two-step graph and adjoint runs bit for bit."""
+    cfgs = acoustics2d_batch(count=5, nmin=40, nmax=140, steps=24, snap_every=6, seed=4)
+    print("case batch two-step of", [c["nx"] for c in cfgs], flush=True)
+    singles = _instances(cfgs, wp.FP64)
+    batched = _instances(cfgs, wp.FP64)
+    for w in singles + batched:
+        w.set_step_pairs(8)
+    for w, c in zip(singles, cfgs):
+        w.run_graph(c["nsteps"], c["dt"], 1)
+    b = wp.Batch(batched, [c["dt"] for c in cfgs])
+    b.step(cfgs[0]["nsteps"])
+    for k, (ws, wb) in enumerate(zip(singles, batched)):
+        assert np.array_equal(ws.get_state(), wb.get_state()), f"instance {k}"
+    ref, _, _ = oracle.run(cfgs[1], "acoustics_fwd", cfgs[1]["q0"], cfgs[1]["nsteps"])
+    assert np.abs(batched[1].get_state() - ref).max() <= 1e-12 * np.abs(ref).max()
+    # odd step count: pairs and a final single step
+    for w, c in zip(singles, cfgs):
+        w.run_graph(5, c["dt"], 1)
+    b.step(5)
+    for k, (ws, wb) in enumerate(zip(singles, batched)):
+        assert np.array_equal(ws.get_state(), wb.get_state()), f"instance {k} after 5 more"
+    for w, c in zip(singles, cfgs):
+        w.adjoint_run(c["functional"], c["dt"], 30, 6)
+    b.adjoint_run([c["functional"] for c in cfgs], 30, 6)
+    for k, (ws, wb) in enumerate(zip(singles, batched)):
+        assert ws.num_snapshots() == wb.num_snapshots() == 6
+        for n in range(6):
+            assert np.array_equal(ws.get_snapshot(n), wb.get_snapshot(n)), f"instance {k} snapshot {n}"
