@@ -30,8 +30,10 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per 2D acoustics cell update: state read once and written
 # once (3 components) plus the one-byte material index
 ALG_BYTES = {64: 3 * 8 * 2 + 1, 32: 3 * 4 * 2 + 1}
-COUNTERS = os.path.join(ROOT, "profiles", "acou2d_fp64_1024_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1511_03645_amd", "csrc", "acoustics.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "acou2d_pair_fp64_1024_counters.json")
+# sources of the dominant (two-step) kernel: the counters are void once any changes
+KERNEL_SRC = [os.path.join(ROOT, "paper_1511_03645_amd", "csrc", f)
+              for f in ("acoustics_pair.hip", "acou_stencil.h", "march_common.h", "wp_internal.h")]
 
 
 def parse():
@@ -56,17 +58,21 @@ def parse():
 
 
 def source_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def traffic_from_counters(cells):
+def traffic_from_counters(cells, rows):
     """HBM bytes per forward-kernel launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
-    None if the kernel source changed since the counters were taken."""
+    None if the kernel source, the grid or the tile height differ from those
+    the counters were taken with."""
     if not os.path.exists(COUNTERS):
         return None
     c = json.load(open(COUNTERS))
-    if c.get("source_sha") != source_sha() or c.get("cells") != cells:
+    if c.get("source_sha") != source_sha() or c.get("cells") != cells or c.get("tile_rows") != rows:
         return None
     fetch = c["fetch_kib"] * 1024.0 / c["copy_fetch_factor"]
     write = c["write_kib"] * 1024.0 / c["copy_write_factor"]
@@ -378,7 +384,7 @@ def main():
                                f"flagged every {cfg['flag_every']} steps + J",
                    "cells": job.cells, "steps_per_solve": cfg["nsteps"], "snapshots": cfg["nsteps"] // 10 + 1},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(job.cells),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(job.cells, job.pair_rows or job.rows) if spl == 2 else None,
                      "kernel": kname, "kernel_us": launch_ms * 1e3, "steps_per_launch": spl,
                      "alg_bytes_per_launch": alg, "tile_rows": job.pair_rows or job.rows},
         "J": J64,
