@@ -148,15 +148,49 @@ __device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &
     }
 }
 
+// The adjoint flag of q^n on the tile's cells (Sec. 4): the measure
+// max_n |qhat_n . q| over the window's snapshots, in FP64 with every product
+// and sum rounded as written, so that it decides exactly as the flag kernel.
+template <typename T>
+__device__ void flag_tile(const Tile &tl, int nx, unsigned cells, int col, bool out_lane,
+                          __amdgpu_buffer_rsrc_t qr, const PairFlag &fl)
+{
+#pragma clang fp contract(off)
+    const unsigned csb = cells * (unsigned)sizeof(T);
+    const __amdgpu_buffer_rsrc_t fw = make_rsrc(fl.flags, cells);
+    unsigned local = 0;
+    for (int j = tl.j0; j < tl.j0 + tl.nj; ++j) {
+        const unsigned idx = (unsigned)(j * nx + col);
+        const unsigned off = idx * (unsigned)sizeof(T);
+        const double q0 = (double)bload(qr, off, T(0), 0u);
+        const double q1 = (double)bload(qr, off, T(0), csb);
+        const double q2 = (double)bload(qr, off, T(0), 2u * csb);
+        double best = 0.0;
+        for (int n = fl.n_lo; n <= fl.n_hi; ++n) {
+            const __amdgpu_buffer_rsrc_t sr =
+                make_rsrc((const T *)fl.snaps + (long long)n * fl.sstride, 3u * csb);
+            double ip = (double)bload(sr, off, T(0), 0u) * q0;
+            ip = ip + (double)bload(sr, off, T(0), csb) * q1;
+            ip = ip + (double)bload(sr, off, T(0), 2u * csb) * q2;
+            best = fmax(best, fabs(ip));
+        }
+        const unsigned f = best > fl.tol ? 1u : 0u;
+        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)f, fw, out_lane ? idx : cells, 0, 0);
+        local += out_lane ? f : 0u;
+    }
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
+    if (threadIdx.x == 0 && local) atomicAdd(fl.count, (unsigned long long)local);
+}
+
 // KIND 0: each tile takes the single-material or the mixed path as flagged;
 // KIND 1: every tile is single-material.  stamp: as for the one-step kernel.
 // At most 256 registers, so that two waves share a SIMD (the unconstrained
 // FP64 march takes a few more and would run one).
-template <typename T, bool ADJ, int RT, int KIND>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void acou2d_pair_kernel(const AcouInst<T> *__restrict__ insts,
-                                                           const Tile *__restrict__ tiles, int parity, int snap1,
-                                                           int snap2, int *__restrict__ status,
-                                                           unsigned long long *__restrict__ stamp)
+// FLAG: take the adjoint flag of q^n on the tile's cells first.
+template <typename T, bool ADJ, int RT, int KIND, bool FLAG>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void acou2d_pair_kernel(
+    const AcouInst<T> *__restrict__ insts, const Tile *__restrict__ tiles, int parity, int snap1, int snap2,
+    int *__restrict__ status, unsigned long long *__restrict__ stamp, PairFlag fl)
 {
     if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x] = (unsigned long long)wall_clock64();
     extern __shared__ __align__(16) unsigned char smem[];
@@ -208,6 +242,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void 
         r.m = KIND == 1 ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
     };
     const bool wall_lo = bc2 == WP_BC_WALL, wall_hi = bc3 == WP_BC_WALL;
+    if constexpr (FLAG) flag_tile<T>(tl, nx, cells, col, out_lane, qr, fl);
     int bad = 0;
     if (KIND == 1 || tl.mat >= 0) {
         Media<T, true> md;
@@ -229,33 +264,36 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void 
 template <typename T>
 void launch_acou2d_pair(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
                         int nmat_max, int rows, int kind, int snap1, int snap2, int *status, hipStream_t s,
-                        unsigned long long *stamp)
+                        unsigned long long *stamp, const PairFlag *flag)
 {
     if (ntiles <= 0) return;
     const size_t sm = sizeof(MCon<T>) * MAXMAT + sizeof(T) * 3 * (size_t)nmat_max * nmat_max;
     const dim3 g(ntiles), b(WAVE);
-#define WP_LAUNCH(ADJ, RT, KIND)                                                                                 \
-    hipLaunchKernelGGL((acou2d_pair_kernel<T, ADJ, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap1, snap2, \
-                       status, stamp)
-#define WP_BY_RT(ADJ, KIND)                  \
-    switch (rows) {                          \
-    case 8: WP_LAUNCH(ADJ, 8, KIND); break;  \
-    case 10: WP_LAUNCH(ADJ, 10, KIND); break; \
-    case 12: WP_LAUNCH(ADJ, 12, KIND); break; \
-    default: WP_LAUNCH(ADJ, 16, KIND); break; \
+    const PairFlag fl = flag ? *flag : PairFlag{nullptr, 0, 0, -1, 0.0, nullptr, nullptr};
+#define WP_LAUNCH(ADJ, RT, KIND, FLAG)                                                                   \
+    hipLaunchKernelGGL((acou2d_pair_kernel<T, ADJ, RT, KIND, FLAG>), g, b, sm, s, insts, tiles, parity, \
+                       snap1, snap2, status, stamp, fl)
+#define WP_BY_RT(ADJ, KIND, FLAG)                   \
+    switch (rows) {                                 \
+    case 8: WP_LAUNCH(ADJ, 8, KIND, FLAG); break;   \
+    case 10: WP_LAUNCH(ADJ, 10, KIND, FLAG); break; \
+    case 12: WP_LAUNCH(ADJ, 12, KIND, FLAG); break; \
+    default: WP_LAUNCH(ADJ, 16, KIND, FLAG); break; \
     }
-    if (kind == 1) {
-        if (adjoint) { WP_BY_RT(true, 1) } else { WP_BY_RT(false, 1) }
+    if (flag && !adjoint) {
+        if (kind == 1) { WP_BY_RT(false, 1, true) } else { WP_BY_RT(false, 0, true) }
+    } else if (kind == 1) {
+        if (adjoint) { WP_BY_RT(true, 1, false) } else { WP_BY_RT(false, 1, false) }
     } else {
-        if (adjoint) { WP_BY_RT(true, 0) } else { WP_BY_RT(false, 0) }
+        if (adjoint) { WP_BY_RT(true, 0, false) } else { WP_BY_RT(false, 0, false) }
     }
 #undef WP_BY_RT
 #undef WP_LAUNCH
 }
 
 template void launch_acou2d_pair<double>(const AcouInst<double> *, const Tile *, int, int, int, int, int, int, int,
-                                         int, int *, hipStream_t, unsigned long long *);
+                                         int, int *, hipStream_t, unsigned long long *, const PairFlag *);
 template void launch_acou2d_pair<float>(const AcouInst<float> *, const Tile *, int, int, int, int, int, int, int,
-                                        int, int *, hipStream_t, unsigned long long *);
+                                        int, int *, hipStream_t, unsigned long long *, const PairFlag *);
 
 }  // namespace wp

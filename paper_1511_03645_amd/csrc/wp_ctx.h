@@ -135,7 +135,8 @@ uint8_t wp_level_mat(const wp_ctx *ctx, const Level &lv, int i, int j);
 void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<wp::Tile> &tiles, int rows, int halo = 2);
 bool wp_pair_capable(const wp_ctx *ctx, const Level &lv);
 bool wp_pair_ready(const wp_ctx *ctx, const Level &lv);
-int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2);
+int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2,
+                 const wp::PairFlag *flag = nullptr);
 int wp_alloc_level(wp_ctx *ctx, Level &lv);
 int wp_check_status(wp_ctx *ctx);
 int wp_courant_check(wp_ctx *ctx, const Level &lv, double dt);

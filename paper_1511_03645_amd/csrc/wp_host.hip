@@ -684,14 +684,15 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
 // Two steps of a level in one launch; snap1 / snap2: snapshot slots of the
 // first / second step (-1: none).  The result lands in the other canvas.
 template <typename T>
-static int acou_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t stream, int snap1, int snap2)
+static int acou_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t stream, int snap1, int snap2,
+                     const PairFlag *flag)
 {
     int rc;
     if ((rc = ensure_acou_inst<T>(ctx, lv, dt)) != WP_OK) return rc;
     if (stream != ctx->stream && lv.inst_dt != dt) return wp_fail(ctx, WP_ESTATE, "descriptor not prepared before capture");
     launch_acou2d_pair<T>((const AcouInst<T> *)lv.inst, lv.ptiles_dev, lv.nptiles, lv.cur, adjoint, ctx->nmat,
                           lv.pair_rows, lv.npuni == lv.nptiles ? 1 : 0, snap1, snap2, ctx->status, stream,
-                          ctx->stamp_next);
+                          ctx->stamp_next, flag);
     ctx->stamp_next = nullptr;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "step launch: %s", hipGetErrorString(e));
@@ -699,11 +700,12 @@ static int acou_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
     return WP_OK;
 }
 
-int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2)
+int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2,
+                 const PairFlag *flag)
 {
     if (!wp_pair_ready(ctx, lv)) return wp_fail(ctx, WP_ESTATE, "level cannot take two steps per launch");
-    if (ctx->esz == 8) return acou_pair<double>(ctx, lv, dt, adjoint, s, snap1, snap2);
-    return acou_pair<float>(ctx, lv, dt, adjoint, s, snap1, snap2);
+    if (ctx->esz == 8) return acou_pair<double>(ctx, lv, dt, adjoint, s, snap1, snap2, flag);
+    return acou_pair<float>(ctx, lv, dt, adjoint, s, snap1, snap2, flag);
 }
 
 extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
@@ -1154,12 +1156,17 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
     // launch clocks: one (start, end) slot per workgroup of the first two
     // launches of every block (a launch takes two steps where the level
     // allows it)
+    // A block's first launch takes the block's flag as well when it takes two
+    // steps (acoustics, level 0 on the adjoint grid); the timed launches are
+    // then the two after it where the block has them.
     const bool pairs = wp_pair_ready(ctx, lv);
+    const bool fuse = pairs && flag_every >= 2;
     const int nlaunch = pairs ? flag_every / 2 + (flag_every & 1) : flag_every;
-    const int ntimed = std::min(nlaunch, 2);
-    const int nblk[2] = {pairs && flag_every >= 2 ? lv.nptiles : lv.ntiles,
-                         pairs && flag_every >= 4 ? lv.nptiles : lv.ntiles};
-    const int first_steps = pairs && flag_every >= 2 ? 2 : 1;
+    const int tfirst = fuse && nlaunch >= 3 ? 1 : 0;
+    const int ntimed = std::min(nlaunch - tfirst, 2);
+    auto is_pair = [&](int l) { return pairs && 2 * l + 1 < flag_every; };
+    const int nblk[2] = {is_pair(tfirst) ? lv.nptiles : lv.ntiles, is_pair(tfirst + 1) ? lv.nptiles : lv.ntiles};
+    const int first_steps = is_pair(tfirst) ? 2 : 1;
     const size_t nslot = 2 * (size_t)std::max(std::max(lv.ntiles, lv.nptiles), 1);
     if (ctx->stamps_cap < (size_t)nev * ntimed * nslot) {
         if (ctx->stamps) wp_dfree(ctx, ctx->stamps);
@@ -1179,14 +1186,17 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
         const int par = lv.cur;
         launch_fill_u8((uint8_t *)ctx->ev_counts, (long long)sizeof(unsigned long long) * nev, 0, s);
+        const Level &a0 = ctx->adj;
         for (int k = 0; k < nev && rc == WP_OK; ++k) {
-            rc = flag_launch(ctx, 0, tol, lo[k], hi[k], ctx->ev_counts + k, s);
+            if (!fuse) rc = flag_launch(ctx, 0, tol, lo[k], hi[k], ctx->ev_counts + k, s);
             // the block's steps, two per launch where the level allows it
             for (int st = 0, launch = 0; st < flag_every && rc == WP_OK; ++launch) {
-                if (launch < ntimed && ctx->is_acoustics && ctx->kind2d)
-                    ctx->stamp_next = ctx->stamps + nslot * ((size_t)ntimed * k + launch);
+                if (launch >= tfirst && launch < tfirst + ntimed && ctx->is_acoustics && ctx->kind2d)
+                    ctx->stamp_next = ctx->stamps + nslot * ((size_t)ntimed * k + (launch - tfirst));
                 if (pairs && st + 1 < flag_every) {
-                    rc = wp_step_pair(ctx, lv, dt, 0, s, -1, -1);
+                    const PairFlag fl{ctx->snaps, (long long)a0.nx * a0.ny * ctx->m, lo[k], hi[k], tol, lv.flags,
+                                      ctx->ev_counts + k};
+                    rc = wp_step_pair(ctx, lv, dt, 0, s, -1, -1, fuse && launch == 0 ? &fl : nullptr);
                     st += 2;
                 } else {
                     rc = wp_step_level(ctx, lv, dt, 0, s, -1);
@@ -1194,6 +1204,7 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
                 }
             }
         }
+        lv.flags_valid = true;
         ctx->stamp_next = nullptr;
         ctx->ff_flip = lv.cur ^ par;
         lv.cur = par;

@@ -95,10 +95,24 @@ void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int 
 // rows 8, 10, 12 or 16 high; no periodic boundary); q^{n+2} lands in
 // q[parity ^ 1], and snapshots snap1 / snap2 (-1: none) take q^{n+1} /
 // q^{n+2}.
+//
+// With `flag` (forward only, a single instance whose level is the adjoint
+// grid), the launch first takes the adjoint flag of q^n on its tiles'
+// cells, as launch_flag does for ratio 1: flags[cell] = max over snapshots
+// n_lo..n_hi of |qhat_n . q^n| > tol, and the number flagged added to
+// *count.
+struct PairFlag {
+    const void *snaps;            // snapshot store [n][3][ny][nx], state precision
+    long long sstride;            // elements per snapshot
+    int n_lo, n_hi;
+    double tol;
+    uint8_t *flags;               // the level's flag canvas
+    unsigned long long *count;
+};
 template <typename T>
 void launch_acou2d_pair(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
                         int nmat_max, int rows, int kind, int snap1, int snap2, int *status, hipStream_t s,
-                        unsigned long long *stamp = nullptr);
+                        unsigned long long *stamp = nullptr, const PairFlag *flag = nullptr);
 template <typename T>
 void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &inst_host, int parity, int adjoint,
                    int snap_index, int *status, hipStream_t s);

@@ -52,10 +52,14 @@ def test_batch_forward_and_adjoint_equal_single_instances():
         assert np.abs(s - snaps_ref[n]).max() <= 1e-12 * max(np.abs(snaps_ref[n]).max(), 1e-300)
 
 
-def test_batch_fp32_error_against_fp64():
+@pytest.mark.parametrize("pair_rows", [0, 12])
+def test_batch_fp32_error_against_fp64(pair_rows):
+    """FP32 batches, one or two steps per launch, against FP64 single
+    instances: the error is stated per instance and bounded."""
     cfgs = acoustics2d_batch(count=4, nmin=64, nmax=160, steps=40, snap_every=8, seed=11)
     w64 = _instances(cfgs, wp.FP64)
     w32 = _instances(cfgs, wp.FP32)
+    w32[0].set_step_pairs(pair_rows)   # the first instance's setting governs the batch
     b = wp.Batch(w32, [c["dt"] for c in cfgs])
     b.step(40)
     for w, c in zip(w64, cfgs):
@@ -64,7 +68,8 @@ def test_batch_fp32_error_against_fp64():
     for k in range(len(cfgs)):
         a, r = w32[k].get_state(), w64[k].get_state()
         rel = np.abs(a - r).max() / np.abs(r).max()
-        print(f"instance {k} ({cfgs[k]['nx']}^2): FP32 batched max-abs err / max|q| = {rel:.2e}")
+        print(f"instance {k} ({cfgs[k]['nx']}^2), pair rows {pair_rows}: FP32 batched max-abs err / max|q| = "
+              f"{rel:.2e}")
         assert rel < 1e-5
 
 

@@ -163,3 +163,25 @@ def test_step_pairs_rejects_other_heights():
             w.set_step_pairs(rows)
     periodic = wp.from_config(cfg2d(64, 64, (2, 2, 2, 2)))
     assert periodic.get_step_pairs() == 0
+
+
+def test_pair_fp32_error_stated():
+    """FP32 two-step launches against the FP64 oracle: forward state and
+    adjoint snapshots, the error stated per output and bounded by 1e-5
+    relative to max |q| (the one-step FP32 bound)."""
+    cfg = acoustics2d(n=256, seed=1)
+    nsteps = 100
+    ref, _, _ = oracle.run(cfg, "acoustics_fwd", cfg["q0"], nsteps)
+    w = wp.from_config(cfg, precision=wp.FP32)
+    assert w.get_step_pairs() > 0
+    w.set_state(cfg["q0"])
+    w.run_graph(nsteps, cfg["dt"], 1)
+    rel = np.abs(w.get_state() - ref).max() / np.abs(ref).max()
+    print(f"FP32 two-step forward 256^2, {nsteps} steps: max-abs error / max|q| = {rel:.3e}")
+    assert rel < 1e-5
+    snaps_ref, _ = oracle.adjoint_run(cfg, nsteps=40, snap_every=10)
+    w.adjoint_run(cfg["functional"], cfg["dt"], 40, 10)
+    for k in range(len(snaps_ref)):
+        rel = np.abs(w.get_snapshot(k) - snaps_ref[k]).max() / np.abs(snaps_ref[k]).max()
+        print(f"FP32 two-step adjoint snapshot {k}: max-abs error / max|q| = {rel:.3e}")
+        assert rel < 1e-5
