@@ -78,6 +78,51 @@ __global__ __launch_bounds__(256) void ring_fill_kernel(const int *__restrict__ 
     }
 }
 
+// The same fill organised by coarse parent: entry e is (linear index of a
+// coarse cell, 64-bit mask of its r x r children in the ring, child (ii, jj)
+// at bit ii + r jj).  The parent's slopes at both times are formed once and
+// every ring child is written from them, with the arithmetic of
+// ring_fill_kernel.
+template <typename T>
+__global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__ blocks, long long nblocks,
+                                                         T *__restrict__ fine, int nxf, const T *__restrict__ cold,
+                                                         const T *__restrict__ cnew, int NX, int NY, int r, T alpha,
+                                                         int bc0, int bc1, int bc2, int bc3)
+{
+    const int bc[4] = {bc0, bc1, bc2, bc3};
+    const long long csf = (long long)nxf * (NY * r);
+    const long long csc = (long long)NX * NY;
+    // one thread per (parent, component)
+    for (long long w = blockIdx.x * 256LL + threadIdx.x; w < 3 * nblocks; w += (long long)gridDim.x * 256) {
+        const long long n = w / 3;
+        const int k = (int)(w - 3 * n);
+        const int lin = blocks[3 * n];
+        const unsigned long long mask =
+            (unsigned long long)(unsigned)blocks[3 * n + 1] | ((unsigned long long)(unsigned)blocks[3 * n + 2] << 32);
+        const int ic = lin % NX, jc = lin / NX;
+        {
+            T c0[2], sx[2], sy[2];
+            for (int t = 0; t < 2; ++t) {
+                const T *C = t == 0 ? cold : cnew;
+                c0[t] = C[k * csc + (long long)jc * NX + ic];
+                sx[t] = minmod(cval(C, k, ic + 1, jc, NX, NY, bc, csc) - c0[t],
+                               c0[t] - cval(C, k, ic - 1, jc, NX, NY, bc, csc));
+                sy[t] = minmod(cval(C, k, ic, jc + 1, NX, NY, bc, csc) - c0[t],
+                               c0[t] - cval(C, k, ic, jc - 1, NX, NY, bc, csc));
+            }
+            for (unsigned long long m = mask; m; m &= m - 1) {
+                const int b = __builtin_ctzll(m);
+                const int ii = b % r, jj = b / r;
+                const T xi = (T(ii) + T(0.5)) / T(r) - T(0.5);
+                const T eta = (T(jj) + T(0.5)) / T(r) - T(0.5);
+                const T a = (c0[0] + xi * sx[0]) + eta * sy[0];
+                const T v = (c0[1] + xi * sx[1]) + eta * sy[1];
+                fine[k * csf + (long long)(jc * r + jj) * nxf + (ic * r + ii)] = (T(1) - alpha) * a + alpha * v;
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ cells, long long ncells,
                                                       const T *__restrict__ fine, int nxf, long long csf,
@@ -114,6 +159,15 @@ void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, cons
 }
 
 template <typename T>
+void launch_ring_fill_blocks(const int *blocks, long long nblocks, T *fine, int nxf, const T *cold, const T *cnew,
+                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s)
+{
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL((ring_block_kernel<T>), dim3(grid_for(3 * nblocks)), dim3(256), 0, s, blocks, nblocks, fine, nxf,
+                       cold, cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3]);
+}
+
+template <typename T>
 void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
                     long long csc, int r, hipStream_t s)
 {
@@ -126,6 +180,10 @@ template void launch_ring_fill<double>(const int *, long long, double *, int, co
                                        int, int, double, const int *, hipStream_t);
 template void launch_ring_fill<float>(const int *, long long, float *, int, const float *, const float *, int, int,
                                       int, double, const int *, hipStream_t);
+template void launch_ring_fill_blocks<double>(const int *, long long, double *, int, const double *, const double *,
+                                              int, int, int, double, const int *, hipStream_t);
+template void launch_ring_fill_blocks<float>(const int *, long long, float *, int, const float *, const float *, int,
+                                             int, int, double, const int *, hipStream_t);
 template void launch_average<double>(const int *, long long, const double *, int, long long, double *, int,
                                      long long, int, hipStream_t);
 template void launch_average<float>(const int *, long long, const float *, int, long long, float *, int, long long,

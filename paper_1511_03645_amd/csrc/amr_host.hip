@@ -35,6 +35,32 @@ std::vector<int> ring_list(const std::vector<wp_patch> &P, int nx, int ny)
     return out;
 }
 
+// The ring grouped by coarse parent (r <= 8): per parent its linear index
+// on the level below (NX wide) and the 64-bit mask of its children in the
+// ring, as three ints, parents in increasing order.
+std::vector<int> ring_blocks(const std::vector<int> &ring, int nx, int r, int NX)
+{
+    std::vector<std::pair<int, unsigned long long>> par;
+    for (int lin : ring) {
+        const int I = lin % nx, J = lin / nx;
+        const int pc = (J / r) * NX + I / r;
+        const unsigned long long bit = 1ULL << ((I % r) + r * (J % r));
+        par.emplace_back(pc, bit);
+    }
+    std::sort(par.begin(), par.end());
+    std::vector<int> out;
+    for (size_t k = 0; k < par.size();) {
+        unsigned long long m = 0;
+        size_t e = k;
+        for (; e < par.size() && par[e].first == par[k].first; ++e) m |= par[e].second;
+        out.push_back(par[k].first);
+        out.push_back((int)(unsigned)(m & 0xffffffffULL));
+        out.push_back((int)(unsigned)(m >> 32));
+        k = e;
+    }
+    return out;
+}
+
 // Coarse cells (linear indices on a canvas NX wide) covered by ratio-aligned
 // fine patches.
 std::vector<int> cover_list(const std::vector<wp_patch> &P, int r, int NX)
@@ -80,9 +106,21 @@ int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double a
 
 int fill_ring(wp_ctx *ctx, int l, double alpha, hipStream_t s)
 {
-    Level &F = ctx->L[l];
+    Level &F = ctx->L[l], &C = ctx->L[l - 1];
     if (F.nring == 0) return WP_OK;
-    return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, ctx->L[l - 1].prev_valid, s);
+    if (!F.ringb_dev) return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, C.prev_valid, s);
+    // by coarse parent: each parent's slopes formed once for all its ring children
+    const void *cnew = C.q[C.cur];
+    const void *cold = C.prev_valid ? C.q[C.cur ^ 1] : cnew;
+    if (ctx->esz == 8)
+        launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)F.q[F.cur], F.nx, (const double *)cold,
+                                        (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
+    else
+        launch_ring_fill_blocks<float>(F.ringb_dev, F.nringb, (float *)F.q[F.cur], F.nx, (const float *)cold,
+                                       (const float *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "coarse-to-fine launch: %s", hipGetErrorString(e));
+    return WP_OK;
 }
 
 int average_down(wp_ctx *ctx, int l, hipStream_t s)
@@ -183,7 +221,14 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     }
     F.patches = boxes;
     if ((rc = wp_upload_tiles(ctx, F)) != WP_OK) return rc;
-    if ((rc = upload_ints(ctx, ring_list(F.patches, F.nx, F.ny), F.ring_dev, F.nring, "ring")) != WP_OK) return rc;
+    {
+        const std::vector<int> ring = ring_list(F.patches, F.nx, F.ny);
+        if ((rc = upload_ints(ctx, ring, F.ring_dev, F.nring, "ring")) != WP_OK) return rc;
+        std::vector<int> blocks;
+        if (F.ratio <= 8) blocks = ring_blocks(ring, F.nx, F.ratio, C.nx);
+        if ((rc = upload_ints(ctx, blocks, F.ringb_dev, F.nringb, "ring block")) != WP_OK) return rc;
+        F.nringb /= 3;
+    }
     if ((rc = upload_ints(ctx, cover_list(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, "cover")) != WP_OK)
         return rc;
     F.t = C.t;
@@ -196,6 +241,7 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
         G.patches.clear();
         if ((rc = wp_upload_tiles(ctx, G)) != WP_OK) return rc;
         if ((rc = upload_ints(ctx, {}, G.ring_dev, G.nring, "ring")) != WP_OK) return rc;
+        if ((rc = upload_ints(ctx, {}, G.ringb_dev, G.nringb, "ring block")) != WP_OK) return rc;
         if ((rc = upload_ints(ctx, {}, G.cover_dev, G.ncover, "cover")) != WP_OK) return rc;
         G.prev_valid = false;
         G.flags_valid = false;

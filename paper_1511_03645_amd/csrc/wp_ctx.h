@@ -47,6 +47,8 @@ struct Level {
     // level below), overwritten by the average of their children
     int *ring_dev = nullptr;
     long long nring = 0;
+    int *ringb_dev = nullptr;            // the ring by coarse parent (see launch_ring_fill_blocks)
+    long long nringb = 0;
     int *cover_dev = nullptr;
     long long ncover = 0;
 };
