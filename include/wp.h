@@ -298,8 +298,8 @@ int wp_get_tile_rows(const wp_ctx *ctx, int *rows);
  * the boundary rules): used by wp_run_graph, wp_adjoint_run and
  * wp_forward_flagged on a single-level 2D acoustics instance with the full
  * method (order 2, MC limiter, transverse terms) and no periodic boundary.
- * rows: -1 the built-in tile height, 0 off (one step per launch), or 8,
- * 10, 12 or 16 rows per tile.  The results equal those of one step per launch up
+ * rows: -1 the built-in tile height, 0 off (one step per launch), or 4 to
+ * 64 rows per tile.  The results equal those of one step per launch up
  * to rounding (bit for bit where both use the same per-cell path).
  * WP_EINVAL for any other rows.  wp_get_step_pairs reports the tile height
  * of level 0 in use, 0 when its steps go one per launch. */

@@ -404,7 +404,7 @@ class WavePatch:
 
     def set_step_pairs(self, rows):
         """Two steps per launch in graph, adjoint and flagged runs: rows -1
-        (built-in tile height), 0 (off), 8, 10, 12 or 16."""
+        (built-in tile height), 0 (off), or 4 to 64 rows per tile."""
         self._check(lib().wp_set_step_pairs(self.h, rows))
 
     def get_step_pairs(self):

@@ -65,7 +65,8 @@ __device__ __forceinline__ Row<T> reflect_y(const Row<T> &a, bool wall)
     return Row<T>{a.p, a.u, wall ? -a.v : a.v, a.m};
 }
 
-// The two marches of one tile (RT rows at most; j0 is 0 or at least 4).
+// The two marches of one tile, unrolled (RT rows at most; j0 is 0 or at
+// least 4).
 // First-step iteration i updates row j0-3+i from input rows A[i+1..i+3]
 // (A[r] is row j0-4+r) into S[i-1] (S[s] is row j0-2+s); second-step
 // iteration k = i-4 updates row j0-1+k from S[k+1..k+3].
@@ -182,8 +183,92 @@ __device__ void flag_tile(const Tile &tl, int nx, unsigned cells, int col, bool 
     if (threadIdx.x == 0 && local) atomicAdd(fl.count, (unsigned long long)local);
 }
 
+// The same two marches as a rolled loop over the tile's own height (any nj):
+// input rows in a rolling window prefetched three rows ahead, the last four
+// first-step rows in registers.  Registers are what the window and the two
+// carries need, not what an unrolled schedule hoists.
+template <typename T, bool ADJ, bool UNI, typename LD>
+__device__ __forceinline__ void march_pair_rolled(const Media<T, UNI> &md, const Tile &tl, int nx, int ny,
+                                                  bool wall_lo, bool wall_hi, T nux, T nuy, unsigned csb,
+                                                  unsigned out_off0, bool out_lane, const XFix &xf,
+                                                  __amdgpu_buffer_rsrc_t qw, __amdgpu_buffer_rsrc_t s1w,
+                                                  __amdgpu_buffer_rsrc_t s2w, const LD &ld, int &bad)
+{
+    const int j0 = tl.j0, j1 = tl.j0 + tl.nj;
+    Row<T> RA, R0, R1, R2, P0, P1, P2;
+    ld(RA, j0 - 4);
+    ld(R0, j0 - 3);
+    ld(R1, j0 - 2);
+    ld(R2, j0 - 1);
+    ld(P0, j0);
+    ld(P1, j0 + 1);
+    Carry<T> ca, cb;
+    march_start<T, ADJ, UNI>(md, RA, R0, R1, ca);
+    const unsigned nowhere = 3u * csb;
+    const unsigned rowb = (unsigned)nx * (unsigned)sizeof(T);
+    Row<T> Sm3, Sm2, Sm1;   // first-step rows s-3, s-2, s-1
+    for (int i = 0; i <= tl.nj + 4; ++i) {
+        ld(P2, j0 + 2 + i);   // input row i + 6, three iterations before its use
+        T pn, un, vn;
+        row_step<T, ADJ, UNI>(md, true, true, 1, nux, nuy, R0, R1, R2, ca, pn, un, vn);
+        const int m0 = R0.m;   // material of the updated row
+        R0 = R1;
+        R1 = R2;
+        R2 = P0;
+        P0 = P1;
+        P1 = P2;
+        if (i == 0) continue;
+        const int s = i - 1;
+        const int r = j0 - 2 + s;
+        {
+            const bool keep = r >= j0 && r < j1 && out_lane;
+            const unsigned off = keep ? (unsigned)r * rowb + out_off0 : nowhere;
+            bstore(s1w, off, 0u, pn);
+            bstore(s1w, off, csb, un);
+            bstore(s1w, off, 2u * csb, vn);
+            bad |= keep & !(isfinite(pn) & isfinite(un) & isfinite(vn));
+        }
+        Row<T> o{pn, un, vn, m0};
+        fix_columns(o, xf);
+        if (s >= 3) {
+            const Row<T> g0 = reflect_y(Sm1, wall_hi);                    // row ny
+            const Row<T> g1 = wall_hi ? reflect_y(Sm3, true) : Sm2;       // row ny + 1
+            o = pick(r == ny, g0, pick(r == ny + 1, g1, o));
+        }
+        if (s == 3 && j0 == 0) {
+            // ghost rows below the domain, once rows 0 (Sm1) and 1 (o) exist
+            const Row<T> g1 = reflect_y(Sm1, wall_lo);                    // row -1
+            const Row<T> g2 = wall_lo ? reflect_y(o, true) : Sm1;         // row -2
+            Sm2 = g1;
+            Sm3 = g2;
+        }
+        if (s >= 3) {
+            const int k = s - 3;
+            if (k == 0) march_start<T, ADJ, UNI>(md, Sm3, Sm2, Sm1, cb);
+            T qp, qu, qv;
+            row_step<T, ADJ, UNI>(md, true, true, 1, nux, nuy, Sm2, Sm1, o, cb, qp, qu, qv);
+            if (k > 0) {
+                const int j = j0 - 1 + k;
+                const bool keep = j < j1 && out_lane;
+                const unsigned off = keep ? (unsigned)j * rowb + out_off0 : nowhere;
+                bstore(qw, off, 0u, qp);
+                bstore(qw, off, csb, qu);
+                bstore(qw, off, 2u * csb, qv);
+                bstore(s2w, off, 0u, qp);
+                bstore(s2w, off, csb, qu);
+                bstore(s2w, off, 2u * csb, qv);
+                bad |= keep & !(isfinite(qp) & isfinite(qu) & isfinite(qv));
+            }
+        }
+        Sm3 = Sm2;
+        Sm2 = Sm1;
+        Sm1 = o;
+    }
+}
+
 // KIND 0: each tile takes the single-material or the mixed path as flagged;
-// KIND 1: every tile is single-material.  stamp: as for the one-step kernel.
+// KIND 1: every tile is single-material.  RT 0: the rolled march (tiles of
+// any height).  stamp: as for the one-step kernel.
 // At most 256 registers, so that two waves share a SIMD (the unconstrained
 // FP64 march takes a few more and would run one).
 // FLAG: take the adjoint flag of q^n on the tile's cells first.
@@ -247,13 +332,21 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void 
     if (KIND == 1 || tl.mat >= 0) {
         Media<T, true> md;
         md.u = make_unicon<T, ADJ>(mc[tl.mat], pt[(tl.mat * Ip->nmat + tl.mat) * 3], nux, nuy);
-        march_pair<T, ADJ, true, RT>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0, out_lane, xf, qw, s1w,
-                                     s2w, ld, bad);
+        if constexpr (RT == 0)
+            march_pair_rolled<T, ADJ, true>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0, out_lane, xf,
+                                            qw, s1w, s2w, ld, bad);
+        else
+            march_pair<T, ADJ, true, RT>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0, out_lane, xf, qw,
+                                         s1w, s2w, ld, bad);
     } else if (KIND != 1) {
         // mixed tiles are acou_mixed_rows(RT) high
         Media<T, false> md{mc, pt, Ip->nmat};
-        march_pair<T, ADJ, false, acou_mixed_rows(RT)>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0,
-                                                       out_lane, xf, qw, s1w, s2w, ld, bad);
+        if constexpr (RT == 0)
+            march_pair_rolled<T, ADJ, false>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0, out_lane, xf,
+                                             qw, s1w, s2w, ld, bad);
+        else
+            march_pair<T, ADJ, false, acou_mixed_rows(RT)>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0,
+                                                           out_lane, xf, qw, s1w, s2w, ld, bad);
     }
     if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
     if (stamp && lane == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
@@ -273,12 +366,13 @@ void launch_acou2d_pair(const AcouInst<T> *insts, const Tile *tiles, int ntiles,
 #define WP_LAUNCH(ADJ, RT, KIND, FLAG)                                                                   \
     hipLaunchKernelGGL((acou2d_pair_kernel<T, ADJ, RT, KIND, FLAG>), g, b, sm, s, insts, tiles, parity, \
                        snap1, snap2, status, stamp, fl)
+    // heights 8, 10 and 12 have an unrolled march; any other the rolled one
 #define WP_BY_RT(ADJ, KIND, FLAG)                   \
     switch (rows) {                                 \
     case 8: WP_LAUNCH(ADJ, 8, KIND, FLAG); break;   \
     case 10: WP_LAUNCH(ADJ, 10, KIND, FLAG); break; \
     case 12: WP_LAUNCH(ADJ, 12, KIND, FLAG); break; \
-    default: WP_LAUNCH(ADJ, 16, KIND, FLAG); break; \
+    default: WP_LAUNCH(ADJ, 0, KIND, FLAG); break;  \
     }
     if (flag && !adjoint) {
         if (kind == 1) { WP_BY_RT(false, 1, true) } else { WP_BY_RT(false, 0, true) }

@@ -166,10 +166,10 @@ bool wp_pair_capable(const wp_ctx *ctx, const Level &lv)
     return p.ilo == 0 && p.jlo == 0 && p.nx == lv.nx && p.ny == lv.ny;
 }
 
-// Two-step tiles: PAIR_STRIP columns by pair_rows rows (8, 10, 12 or 16;
-// mixed tiles cut to acou_mixed_rows of that, so every tile starts on row 0
-// or at least 4 rows above it), classified with the four-cell footprint;
-// mixed ones first, each group in XCD order.
+// Two-step tiles: PAIR_STRIP columns by pair_rows rows (4..64; mixed tiles
+// cut to acou_mixed_rows of that, so every tile starts on row 0 or at least
+// 4 rows above it), classified with the four-cell footprint; mixed ones
+// first, each group in XCD order.
 static int upload_pair_tiles(wp_ctx *ctx, Level &lv)
 {
     if (lv.ptiles_dev) wp_dfree(ctx, lv.ptiles_dev);
@@ -710,7 +710,7 @@ int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, 
 
 extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
 {
-    if (!ctx || !(rows == -1 || rows == 0 || rows == 8 || rows == 10 || rows == 12 || rows == 16)) return WP_EINVAL;
+    if (!ctx || !(rows == -1 || rows == 0 || (rows >= 4 && rows <= 64))) return WP_EINVAL;
     ctx->pair_rows = rows;
     int rc;
     for (auto &lv : ctx->L)

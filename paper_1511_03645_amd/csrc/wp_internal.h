@@ -92,7 +92,8 @@ void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int 
                    int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s,
                    unsigned long long *stamp = nullptr);
 // Two steps per launch on a single-level canvas (tiles PAIR_STRIP wide,
-// rows 8, 10, 12 or 16 high; no periodic boundary); q^{n+2} lands in
+// 4..64 rows high: 8, 10 and 12 unrolled, others rolled; no periodic
+// boundary); q^{n+2} lands in
 // q[parity ^ 1], and snapshots snap1 / snap2 (-1: none) take q^{n+1} /
 // q^{n+2}.
 //

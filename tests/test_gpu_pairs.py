@@ -44,6 +44,11 @@ CASES = [
     (56, 56, (WALL, WALL, EXTRAP, EXTRAP), 12),
     (230, 64, (EXTRAP, EXTRAP, WALL, WALL), 16),
     (150, 95, (WALL, EXTRAP, EXTRAP, WALL), 10),
+    # rolled march: any height
+    (100, 77, (WALL, EXTRAP, WALL, EXTRAP), 5),
+    (121, 140, (EXTRAP, WALL, EXTRAP, WALL), 24),
+    (64, 200, (WALL,) * 4, 32),
+    (90, 40, (EXTRAP,) * 4, 64),
     (57, 9, (WALL,) * 4, 8),
 ]
 
@@ -97,13 +102,14 @@ def test_pairs_agree_with_single_steps_across_replays(nx, ny, bc):
     assert abs(two.get_time() - one.get_time()) < 1e-12
 
 
-@pytest.mark.parametrize("every,nsteps", [(10, 80), (5, 45), (3, 30)])
-def test_pair_adjoint_snapshots_match_oracle(every, nsteps):
+@pytest.mark.parametrize("every,nsteps,rows", [(10, 80, -1), (5, 45, 12), (3, 30, 20)])
+def test_pair_adjoint_snapshots_match_oracle(every, nsteps, rows):
     """Snapshots taken by the first or the second step of a launch."""
-    print(f"case pairs adjoint every={every} steps={nsteps}", flush=True)
+    print(f"case pairs adjoint every={every} steps={nsteps} rows={rows}", flush=True)
     cfg = acoustics2d(n=128, seed=1)
     snaps_ref, _ = oracle.adjoint_run(cfg, nsteps=nsteps, snap_every=every)
     w = wp.from_config(cfg)
+    w.set_step_pairs(rows)
     assert w.get_step_pairs() > 0
     w.adjoint_run(cfg["functional"], cfg["dt"], nsteps, every)
     assert w.num_snapshots() == len(snaps_ref)
@@ -158,7 +164,7 @@ def test_pair_full_size_graph_run():
 def test_step_pairs_rejects_other_heights():
     cfg = cfg2d(64, 64, (WALL,) * 4)
     w = wp.from_config(cfg)
-    for rows in (4, 6, 7, 24, -2):
+    for rows in (1, 3, 65, 1000, -2):
         with pytest.raises(wp.WPError):
             w.set_step_pairs(rows)
     periodic = wp.from_config(cfg2d(64, 64, (2, 2, 2, 2)))
