@@ -336,9 +336,8 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
         if (buffer < 0) return wp_fail(ctx, WP_EINVAL, "buffer must be non-negative");
         if (!C.flags_valid) return wp_fail(ctx, WP_ESTATE, "level %d has no flags (flag it first)", level);
         std::vector<uint8_t> fl((size_t)C.nx * C.ny);
-        if (hipMemcpyAsync(fl.data(), C.flags, fl.size(), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-            hipStreamSynchronize(ctx->stream) != hipSuccess)
-            return wp_fail(ctx, WP_EDEVICE, "flag read");
+        int rcf;
+        if ((rcf = wp_host_copy(ctx, fl.data(), C.flags, fl.size(), false)) != WP_OK) return rcf;
         for (size_t k = 0; k < fl.size(); ++k) fl[k] = (fl[k] && allowed[k]) ? 1 : 0;
         std::vector<uint8_t> dil;
         wp_dilate(fl, C.nx, C.ny, buffer, dil);

@@ -145,8 +145,7 @@ static int common_parity(wp_batch *b, int adjoint)
 static int check_status(wp_batch *b)
 {
     int st = 0;
-    if (hipMemcpyAsync(&st, b->status, sizeof st, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
-        hipStreamSynchronize(b->stream) != hipSuccess)
+    if (wp_host_copy(b->inst[0], &st, b->status, sizeof st, false) != WP_OK)
         return bfail(b, WP_EDEVICE, "batch status read");
     if (st) {
         (void)hipMemsetAsync(b->status, 0, sizeof st, b->stream);

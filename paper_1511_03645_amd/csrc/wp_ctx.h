@@ -124,10 +124,21 @@ struct wp_ctx {
     double adj_dt = 0.0;
     unsigned long long adj_gen = 0;
     const void *adj_snaps = nullptr;
+    // pinned host staging for every transfer between device memory and the
+    // caller's (pageable) host memory; allocated on first use, grown up to
+    // WP_PIN_CAP, released by wp_destroy
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };
 
 int wp_fail(wp_ctx *ctx, int code, const char *fmt, ...);
+// Copies between device memory and host memory through the pinned staging
+// buffer, on the handle's stream, complete when they return: `rows` rows of
+// `width` bytes, `dpitch` / `spitch` bytes apart on the destination / source.
+int wp_host_copy2d(wp_ctx *ctx, void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t rows,
+                   bool to_device);
+int wp_host_copy(wp_ctx *ctx, void *dst, const void *src, size_t bytes, bool to_device);
 void *wp_dalloc(wp_ctx *ctx, size_t bytes);
 void wp_dfree(wp_ctx *ctx, void *p);
 std::vector<wp::Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, int rows, int width, bool xcd_order);

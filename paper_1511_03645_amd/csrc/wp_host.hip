@@ -457,6 +457,7 @@ extern "C" void wp_destroy(wp_ctx *ctx)
     if (ctx->bo_exec) (void)hipGraphExecDestroy(ctx->bo_exec);
     if (ctx->ff_exec) (void)hipGraphExecDestroy(ctx->ff_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
     std::vector<void *> all = ctx->owned;
     for (void *p : all) wp_dfree(ctx, p);
     delete ctx;
@@ -502,6 +503,76 @@ extern "C" int wp_level_info(const wp_ctx *ctx, int level, int *nx, int *ny, int
 // Copy between a caller buffer [m][h][w] and box (i0, j0, w, h) of a level
 // canvas.  Component k of the canvas sits at k * cells elements of size esz
 // (mixed precision: eta doubles, then hu, hv floats).
+constexpr size_t WP_PIN_CAP = 32u << 20;
+
+// Pinned staging for host transfers: asynchronous copies to or from pageable
+// memory are not reliably complete at the stream's synchronisation (seen
+// under a profiler's interception), copies to or from pinned memory are.
+static int ensure_pin(wp_ctx *ctx, size_t want)
+{
+    want = std::min(std::max(want, (size_t)4096), WP_PIN_CAP);
+    if (ctx->pin_bytes >= want) return WP_OK;
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    ctx->pin = nullptr;
+    ctx->pin_bytes = 0;
+    if (hipHostMalloc(&ctx->pin, want, hipHostMallocDefault) != hipSuccess || !ctx->pin)
+        return wp_fail(ctx, WP_ENOMEM, "pinned staging buffer (%zu bytes)", want);
+    ctx->pin_bytes = want;
+    return WP_OK;
+}
+
+int wp_host_copy2d(wp_ctx *ctx, void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t rows,
+                   bool to_device)
+{
+    if (rows == 0 || width == 0) return WP_OK;
+    int rc;
+    if ((rc = ensure_pin(ctx, width * rows)) != WP_OK) return rc;
+    if (width > ctx->pin_bytes) {
+        // rows wider than the staging buffer: one row at a time, in pieces
+        for (size_t r = 0; r < rows; ++r)
+            for (size_t o = 0; o < width; o += ctx->pin_bytes) {
+                const size_t n = std::min(ctx->pin_bytes, width - o);
+                if ((rc = wp_host_copy2d(ctx, (char *)dst + r * dpitch + o, n, (const char *)src + r * spitch + o, n,
+                                         n, 1, to_device)) != WP_OK)
+                    return rc;
+            }
+        return WP_OK;
+    }
+    const size_t chunk = ctx->pin_bytes / width;
+    char *pin = (char *)ctx->pin;
+    for (size_t r0 = 0; r0 < rows; r0 += chunk) {
+        const size_t n = std::min(chunk, rows - r0);
+        hipError_t e;
+        if (to_device) {
+            for (size_t r = 0; r < n; ++r) memcpy(pin + r * width, (const char *)src + (r0 + r) * spitch, width);
+            e = hipMemcpy2DAsync((char *)dst + r0 * dpitch, dpitch, pin, width, width, n, hipMemcpyHostToDevice,
+                                 ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        } else {
+            e = hipMemcpy2DAsync(pin, width, (const char *)src + r0 * spitch, spitch, width, n, hipMemcpyDeviceToHost,
+                                 ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            if (e == hipSuccess)
+                for (size_t r = 0; r < n; ++r) memcpy((char *)dst + (r0 + r) * dpitch, pin + r * width, width);
+        }
+        if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "host transfer: %s", hipGetErrorString(e));
+    }
+    return WP_OK;
+}
+
+int wp_host_copy(wp_ctx *ctx, void *dst, const void *src, size_t bytes, bool to_device)
+{
+    if (bytes == 0) return WP_OK;
+    // as rows of at most 1 MiB
+    const size_t width = std::min(bytes, (size_t)1 << 20);
+    const size_t rows = bytes / width, tail = bytes - rows * width;
+    int rc = wp_host_copy2d(ctx, dst, width, src, width, width, rows, to_device);
+    if (rc == WP_OK && tail)
+        rc = wp_host_copy2d(ctx, (char *)dst + rows * width, tail, (const char *)src + rows * width, tail, tail, 1,
+                            to_device);
+    return rc;
+}
+
 static int copy_box(wp_ctx *ctx, Level &lv, int i0, int j0, int w, int h, void *user, int on_device, bool to_canvas)
 {
     const long long cells = (long long)lv.nx * lv.ny;
@@ -514,6 +585,17 @@ static int copy_box(wp_ctx *ctx, Level &lv, int i0, int j0, int w, int h, void *
         const size_t es = ctx->prob.precision == WP_MIXED ? (k == 0 ? 8 : 4) : (size_t)ctx->esz;
         char *cbase = canvas + coff + ((size_t)j0 * lv.nx + i0) * es;
         char *ubase = (char *)user + uoff;
+        if (!on_device) {
+            // host memory: through the pinned staging buffer
+            const int rc = to_canvas ? wp_host_copy2d(ctx, cbase, (size_t)lv.nx * es, ubase, (size_t)w * es,
+                                                      (size_t)w * es, h, true)
+                                     : wp_host_copy2d(ctx, ubase, (size_t)w * es, cbase, (size_t)lv.nx * es,
+                                                      (size_t)w * es, h, false);
+            if (rc != WP_OK) return rc;
+            uoff += (size_t)w * h * es;
+            coff += (size_t)cells * es;
+            continue;
+        }
         hipError_t e;
         if (to_canvas)
             e = hipMemcpy2DAsync(cbase, (size_t)lv.nx * es, ubase, (size_t)w * es, (size_t)w * es, h, kind, ctx->stream);
@@ -566,10 +648,8 @@ extern "C" int wp_get_state(wp_ctx *ctx, int level, int patch, void *dst, int on
 
 int wp_check_status(wp_ctx *ctx)
 {
-    int st = 0;
-    if (hipMemcpyAsync(&st, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "status read: %s", hipGetErrorString(hipGetLastError()));
+    int st = 0, rc;
+    if ((rc = wp_host_copy(ctx, &st, ctx->status, sizeof(int), false)) != WP_OK) return rc;
     if (st) {
         (void)hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->stream);
         (void)hipStreamSynchronize(ctx->stream);
@@ -1033,8 +1113,9 @@ extern "C" int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device)
     if (!ctx) return WP_EINVAL;
     if (n < 0 || n >= ctx->nsnap) return wp_fail(ctx, WP_ERANGE, "snapshot %d of %d", n, ctx->nsnap);
     if (!dst) return wp_fail(ctx, WP_EINVAL, "null destination");
-    if (hipMemcpyAsync(dst, (char *)ctx->snaps + (size_t)n * ctx->snap_bytes, ctx->snap_bytes,
-                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+    const char *src = (const char *)ctx->snaps + (size_t)n * ctx->snap_bytes;
+    if (!on_device) return wp_host_copy(ctx, dst, src, ctx->snap_bytes, false);
+    if (hipMemcpyAsync(dst, src, ctx->snap_bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "snapshot read");
     return WP_OK;
@@ -1107,17 +1188,14 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "count clear");
     if ((rc = flag_launch(ctx, level, tol, n_lo, n_hi, ctx->count, ctx->stream)) != WP_OK) return rc;
-    if (flags && hipMemcpyAsync(flags, lv.flags, (size_t)cells, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                ctx->stream) != hipSuccess)
+    if (flags && on_device &&
+        hipMemcpyAsync(flags, lv.flags, (size_t)cells, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "flag copy");
+    if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cells, false)) != WP_OK) return rc;
     if (nflagged) {
         unsigned long long c = 0;
-        if (hipMemcpyAsync(&c, ctx->count, sizeof c, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-            hipStreamSynchronize(ctx->stream) != hipSuccess)
-            return wp_fail(ctx, WP_EDEVICE, "count read");
+        if ((rc = wp_host_copy(ctx, &c, ctx->count, sizeof c, false)) != WP_OK) return rc;
         *nflagged = (int64_t)c;
-    } else if (flags && !on_device) {
-        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag sync");
     }
     return WP_OK;
 }
@@ -1226,18 +1304,18 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flagged run sync");
         if (counts) {
             std::vector<unsigned long long> c(nev);
-            if (hipMemcpy(c.data(), ctx->ev_counts, sizeof(unsigned long long) * nev, hipMemcpyDeviceToHost) !=
-                hipSuccess)
-                return wp_fail(ctx, WP_EDEVICE, "count read");
+            if ((rc = wp_host_copy(ctx, c.data(), ctx->ev_counts, sizeof(unsigned long long) * nev, false)) != WP_OK)
+                return rc;
             for (int k = 0; k < nev; ++k) counts[k] = (int64_t)c[k];
         }
         if (step_ms) {
             if (!(ctx->is_acoustics && ctx->kind2d)) return wp_fail(ctx, WP_EINVAL, "launch times are for 2D acoustics");
             std::vector<unsigned long long> st(nslot * ntimed * nev);
             int khz = 0, dev = 0;
-            if (hipMemcpy(st.data(), ctx->stamps, sizeof(unsigned long long) * st.size(), hipMemcpyDeviceToHost) !=
-                    hipSuccess ||
-                hipGetDevice(&dev) != hipSuccess ||
+            if ((rc = wp_host_copy(ctx, st.data(), ctx->stamps, sizeof(unsigned long long) * st.size(), false)) !=
+                WP_OK)
+                return rc;
+            if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
                 return wp_fail(ctx, WP_EDEVICE, "launch clock read");
             // earliest workgroup start and latest end of timed launch i (the
@@ -1324,9 +1402,8 @@ extern "C" int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int whic
         return wp_fail(ctx, WP_EINVAL, "which must be 0 (J) or 1 (inner product)");
     }
     double v = 0.0;
-    if (hipMemcpyAsync(&v, ctx->red_out, sizeof v, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "reduction read");
+    int rc2;
+    if ((rc2 = wp_host_copy(ctx, &v, ctx->red_out, sizeof v, false)) != WP_OK) return rc2;
     *out = v * dA;
     return wp_check_status(ctx);
 }
