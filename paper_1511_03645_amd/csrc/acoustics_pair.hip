@@ -114,8 +114,9 @@ __device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &
         }
         Row<T> o{pn, un, vn, A[s + 2].m};
         fix_columns(o, xf);
-        // ghost rows above the domain (the rows they copy come first)
-        if (s >= 3) {
+        // ghost rows above the domain (the rows they copy come first); r is
+        // wave-uniform, so rows below the top skip this on a scalar branch
+        if (s >= 3 && r >= ny) {
             const Row<T> g0 = reflect_y(S[s - 1], wall_hi);              // row ny
             const Row<T> g1 = wall_hi ? reflect_y(S[s - 3], true) : S[s - 2];   // row ny + 1
             o = pick(r == ny, g0, pick(r == ny + 1, g1, o));
