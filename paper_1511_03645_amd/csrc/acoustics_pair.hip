@@ -74,8 +74,8 @@ template <typename T, bool ADJ, bool UNI, int RT, typename LD>
 __device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &tl, int nx, int ny, bool wall_lo,
                                            bool wall_hi, T nux, T nuy, unsigned csb, unsigned out_off0,
                                            bool out_lane, const XFix &xf, __amdgpu_buffer_rsrc_t qw,
-                                           __amdgpu_buffer_rsrc_t s1w, __amdgpu_buffer_rsrc_t s2w, const LD &ld,
-                                           int &bad)
+                                           __amdgpu_buffer_rsrc_t s1w, __amdgpu_buffer_rsrc_t s2w, bool snap1,
+                                           bool snap2, const LD &ld, int &bad)
 {
     constexpr int NA = RT + 8;
     constexpr int NS = RT + 4;
@@ -104,13 +104,14 @@ __device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &
         if (i == 0) continue;   // the first row only starts the y-edge fluxes
         const int s = i - 1;
         const int r = j0 - 2 + s;
-        {
+        if (snap1) {
+            // q^{n+1} is a snapshot (a non-finite value in it reaches the
+            // second step's checked outputs in any case)
             const bool keep = r >= j0 && r < j1 && out_lane;
             const unsigned off = keep ? (unsigned)r * rowb + out_off0 : nowhere;
             bstore(s1w, off, 0u, pn);
             bstore(s1w, off, csb, un);
             bstore(s1w, off, 2u * csb, vn);
-            bad |= keep & !(isfinite(pn) & isfinite(un) & isfinite(vn));
         }
         Row<T> o{pn, un, vn, A[s + 2].m};
         fix_columns(o, xf);
@@ -142,9 +143,11 @@ __device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &
             bstore(qw, off, 0u, qp);
             bstore(qw, off, csb, qu);
             bstore(qw, off, 2u * csb, qv);
-            bstore(s2w, off, 0u, qp);
-            bstore(s2w, off, csb, qu);
-            bstore(s2w, off, 2u * csb, qv);
+            if (snap2) {
+                bstore(s2w, off, 0u, qp);
+                bstore(s2w, off, csb, qu);
+                bstore(s2w, off, 2u * csb, qv);
+            }
             bad |= keep & !(isfinite(qp) & isfinite(qu) & isfinite(qv));
         }
     }
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void 
                                             qw, s1w, s2w, ld, bad);
         else
             march_pair<T, ADJ, true, RT>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0, out_lane, xf, qw,
-                                         s1w, s2w, ld, bad);
+                                         s1w, s2w, snap1 >= 0, snap2 >= 0, ld, bad);
     } else if (KIND != 1) {
         // mixed tiles are acou_mixed_rows(RT) high
         Media<T, false> md{mc, pt, Ip->nmat};
@@ -347,7 +350,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2))) void 
                                              qw, s1w, s2w, ld, bad);
         else
             march_pair<T, ADJ, false, acou_mixed_rows(RT)>(md, tl, nx, ny, wall_lo, wall_hi, nux, nuy, csb, out_off0,
-                                                           out_lane, xf, qw, s1w, s2w, ld, bad);
+                                                           out_lane, xf, qw, s1w, s2w, snap1 >= 0, snap2 >= 0, ld,
+                                                           bad);
     }
     if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
     if (stamp && lane == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
