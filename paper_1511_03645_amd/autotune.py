@@ -72,7 +72,7 @@ def tune(w, dt, level=0, steps=20, candidates=CANDIDATES, use_cache=True, verbos
 
 
 # tile heights of the two-step kernel
-PAIR_CANDIDATES = (8, 10, 12)
+PAIR_CANDIDATES = (8, 10, 12, 16)
 
 
 def tune_pairs(w, dt, steps=20, candidates=PAIR_CANDIDATES, verbose=False):

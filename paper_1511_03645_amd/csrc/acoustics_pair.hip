@@ -123,13 +123,10 @@ __device__ __forceinline__ void march_pair(const Media<T, UNI> &md, const Tile &
             o = pick(r == ny, g0, pick(r == ny + 1, g1, o));
         }
         S[s] = o;
-        if (s == 3) {
+        if (s == 3 && j0 == 0) {
             // ghost rows below the domain, once rows 0 and 1 exist
-            const bool bot = j0 == 0;
-            const Row<T> g1 = reflect_y(S[2], wall_lo);                  // row -1
-            const Row<T> g2 = wall_lo ? reflect_y(S[3], true) : S[2];    // row -2
-            S[1] = pick(bot, g1, S[1]);
-            S[0] = pick(bot, g2, S[0]);
+            S[1] = reflect_y(S[2], wall_lo);                             // row -1
+            S[0] = wall_lo ? reflect_y(S[3], true) : S[2];               // row -2
         }
         if (i >= 4) {
             const int k = i - 4;
@@ -371,12 +368,13 @@ void launch_acou2d_pair(const AcouInst<T> *insts, const Tile *tiles, int ntiles,
 #define WP_LAUNCH(ADJ, RT, KIND, FLAG)                                                                   \
     hipLaunchKernelGGL((acou2d_pair_kernel<T, ADJ, RT, KIND, FLAG>), g, b, sm, s, insts, tiles, parity, \
                        snap1, snap2, status, stamp, fl)
-    // heights 8, 10 and 12 have an unrolled march; any other the rolled one
+    // heights 8, 10, 12 and 16 have an unrolled march; any other the rolled one
 #define WP_BY_RT(ADJ, KIND, FLAG)                   \
     switch (rows) {                                 \
     case 8: WP_LAUNCH(ADJ, 8, KIND, FLAG); break;   \
     case 10: WP_LAUNCH(ADJ, 10, KIND, FLAG); break; \
     case 12: WP_LAUNCH(ADJ, 12, KIND, FLAG); break; \
+    case 16: WP_LAUNCH(ADJ, 16, KIND, FLAG); break; \
     default: WP_LAUNCH(ADJ, 0, KIND, FLAG); break;  \
     }
     if (flag && !adjoint) {
