@@ -32,7 +32,8 @@ using namespace march;
 template <typename T, bool ADJ, bool UNI, int RT, typename LD>
 __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &tl, int nx, T nux, T nuy,
                                            unsigned csb, unsigned out_off0, bool out_lane,
-                                           __amdgpu_buffer_rsrc_t qw, __amdgpu_buffer_rsrc_t sw, const LD &ld, int &bad)
+                                           __amdgpu_buffer_rsrc_t qw, __amdgpu_buffer_rsrc_t sw, bool snap,
+                                           const LD &ld, int &bad)
 {
     constexpr int NR = RT + 4;
     constexpr int FIRST = 3 + PREFETCH < NR ? 3 + PREFETCH : NR;   // rows requested before the march
@@ -66,9 +67,11 @@ __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &
         bstore(qw, off, 0u, pn);
         bstore(qw, off, csb, un);
         bstore(qw, off, 2u * csb, vn);
-        bstore(sw, off, 0u, pn);
-        bstore(sw, off, csb, un);
-        bstore(sw, off, 2u * csb, vn);
+        if (snap) {   // wave-uniform
+            bstore(sw, off, 0u, pn);
+            bstore(sw, off, csb, un);
+            bstore(sw, off, 2u * csb, vn);
+        }
         bad |= keep & !(isfinite(pn) & isfinite(un) & isfinite(vn));
     }
 }
@@ -100,7 +103,7 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
         r.m = UNI ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
     };
     if constexpr (RT > 0) {
-        march_tile<T, ADJ, UNI, RT>(md, tl, nx, nux, nuy, csb, out_off0, out_lane, qw, sw, ld, bad);
+        march_tile<T, ADJ, UNI, RT>(md, tl, nx, nux, nuy, csb, out_off0, out_lane, qw, sw, snap, ld, bad);
     } else {
         // FULL: second order, MC limiter and transverse terms fixed at compile time
         const bool second = FULL ? true : op_rt.second;
