@@ -92,6 +92,8 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
     const int bc[4] = {bc0, bc1, bc2, bc3};
     const long long csf = (long long)nxf * (NY * r);
     const long long csc = (long long)NX * NY;
+    const bool pow2 = (r & (r - 1)) == 0;
+    const T inv_r = T(1) / T(r);
     // one thread per (parent, component)
     for (long long w = blockIdx.x * 256LL + threadIdx.x; w < 3 * nblocks; w += (long long)gridDim.x * 256) {
         const long long n = w / 3;
@@ -113,8 +115,9 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
             for (unsigned long long m = mask; m; m &= m - 1) {
                 const int b = __builtin_ctzll(m);
                 const int ii = b % r, jj = b / r;
-                const T xi = (T(ii) + T(0.5)) / T(r) - T(0.5);
-                const T eta = (T(jj) + T(0.5)) / T(r) - T(0.5);
+                // a power-of-two ratio divides exactly as its reciprocal multiplies
+                const T xi = (pow2 ? (T(ii) + T(0.5)) * inv_r : (T(ii) + T(0.5)) / T(r)) - T(0.5);
+                const T eta = (pow2 ? (T(jj) + T(0.5)) * inv_r : (T(jj) + T(0.5)) / T(r)) - T(0.5);
                 const T a = (c0[0] + xi * sx[0]) + eta * sy[0];
                 const T v = (c0[1] + xi * sx[1]) + eta * sy[1];
                 fine[k * csf + (long long)(jc * r + jj) * nxf + (ic * r + ii)] = (T(1) - alpha) * a + alpha * v;

@@ -706,9 +706,10 @@ __global__ __launch_bounds__(WAVE) void lswe_adj_kernel(const LsweInst<T> *__res
         const bool keep = valid && j < j1 && out_lane;
         const unsigned off = keep ? (unsigned)(j * nx + col) * (unsigned)sizeof(T) : nowhere;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            bstore(qw, off, (unsigned)k * csb, qn[k]);
-            bstore(sw, off, (unsigned)k * csb, qn[k]);
+        for (int k = 0; k < 3; ++k) bstore(qw, off, (unsigned)k * csb, qn[k]);
+        if (snap) {   // wave-uniform
+#pragma unroll
+            for (int k = 0; k < 3; ++k) bstore(sw, off, (unsigned)k * csb, qn[k]);
         }
         bad |= keep & !(isfinite((double)qn[0]) & isfinite((double)qn[1]) & isfinite((double)qn[2]));
     };
