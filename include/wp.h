@@ -277,7 +277,11 @@ typedef struct wp_batch wp_batch;
 
 /* Build a batch over n instances (each created with one level and already
  * holding its state).  dts[k]: the fixed step of instance k.  The
- * instances stay owned by the caller and must outlive the batch. */
+ * instances stay owned by the caller and must outlive the batch.  Steps go
+ * two per launch (see wp_set_step_pairs) when every instance can take
+ * them, at the tile height set on the first instance (0 there: one step
+ * per launch); the tile tables are built once, from the instances' grids
+ * and media at creation. */
 int wp_batch_create(wp_ctx *const *instances, int n, const double *dts, wp_batch **out);
 void wp_batch_destroy(wp_batch *b);
 /* nsteps steps of every instance, forward (adjoint = 0) or of the adjoint
