@@ -23,6 +23,22 @@ namespace {
 
 using namespace march;
 
+// 1/b from the hardware reciprocal refined by Newton steps (within an ulp
+// or two of the quotient; for the limiter ratio, whose b = 0 is excluded)
+__device__ __forceinline__ double recip(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float b)
+{
+    const float r = __builtin_amdgcn_rcpf(b);
+    return fmaf(r, fmaf(-b, r, 1.0f), r);
+}
+
 // Rows requested ahead of their first use in the compile-time march.
 constexpr int PREFETCH = 3;
 // sched_barrier mask: ALU instructions and memory writes may be moved across,
@@ -44,11 +60,12 @@ __device__ __forceinline__ T lim_factor(const T *w, const T *wu, int limiter)
     if (limiter == 0) return T(1);
     const T a = wu[0] * w[0] + wu[1] * w[1] + wu[2] * w[2];
     const T b = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-    return b == T(0) ? T(0) : mc_phi(a / b);
+    return b == T(0) ? T(0) : mc_phi(a * recip(b));
 }
 
 template <typename T>
 __device__ __forceinline__ T sgn(T s) { return s > T(0) ? T(1) : (s < T(0) ? T(-1) : T(0)); }
+
 
 // Second-order correction flux of an edge with NW waves w[3 p + k] at speeds
 // s[p]: per family the upwind wave is that of the lower/left neighbour edge
@@ -125,7 +142,7 @@ template <typename T>
 struct SEdge {
     T w[9];
     T s[3];
-    T ru, rv, c;
+    T ru, rv, c, hic;   // hic = 1 / (2 c)
 };
 
 // Roe f-wave solve at the edge between L and R in direction DIR (0: x,
@@ -143,14 +160,17 @@ __device__ __forceinline__ SEdge<T> roe_edge(const SRow<ETA, T> &L, const SRow<E
     const T rs = T(1) / (L.sq + R.sq);
     const T un = (L.sq * unl + R.sq * unr) * rs;
     const T ut = (L.sq * utl + R.sq * utr) * rs;
-    const T c = sqrt(T(g) * hbar);
+    // c = sqrt(g hbar) and 1/(2c) from one reciprocal square root
+    const T gh = T(g) * hbar;
+    const T rq = rsqrt(gh);
+    const T c = gh * rq;
     const ETA hbe = ETA(0.5) * (L.he + R.he);
     const T wb = (T)(ETA(g) * hbe * (R.eta - L.eta));
     const T d1 = qnr - qnl;
     const T d2 = (qnr * unr - qnl * unl) + wb;
     const T d3 = qnr * utr - qnl * utl;
     const T s1 = un - c, s3 = un + c;
-    const T inv2c = T(0.5) / c;
+    const T inv2c = T(0.5) * rq;
     const T b1 = ((un + c) * d1 - d2) * inv2c;
     const T b3 = (d2 - (un - c) * d1) * inv2c;
     const T b2 = d3 - ut * d1;
@@ -162,6 +182,7 @@ __device__ __forceinline__ SEdge<T> roe_edge(const SRow<ETA, T> &L, const SRow<E
     e.ru = DIR == 0 ? un : ut;
     e.rv = DIR == 0 ? ut : un;
     e.c = c;
+    e.hic = inv2c;
     return e;
 }
 
@@ -181,16 +202,17 @@ __device__ __forceinline__ void flucts(const SEdge<T> &E, T am[3], T ap[3])
 }
 
 // Transverse split of d along direction tdir with the eigen-structure of
-// that direction at the Roe state (uh, vh, c) of the edge d came from: neg
+// that direction at the Roe state (uh, vh, c; hic = 1/(2c)) of the edge d
+// came from: neg
 // gets the part carried by negative speeds, pos the part carried by
 // non-negative speeds.  The eigenvalues vt - c < vt < vt + c enter through
 // 0/1 masks.
 template <typename T>
-__device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T c, T neg[3], T pos[3])
+__device__ __forceinline__ void swe_tsplit(int tdir, const T d[3], T uh, T vh, T c, T hic, T neg[3], T pos[3])
 {
     const int kt = tdir == 0 ? 1 : 2, ko = tdir == 0 ? 2 : 1;
     const T vt = tdir == 0 ? uh : vh, vo = tdir == 0 ? vh : uh;
-    const T inv2c = T(0.5) / c;
+    const T inv2c = hic;
     const T g1 = ((vt + c) * d[0] - d[kt]) * inv2c;
     const T g3 = (d[kt] - (vt - c) * d[0]) * inv2c;
     const T g2 = d[ko] - vo * d[0];
@@ -221,7 +243,7 @@ __device__ __forceinline__ void corr_add(const T *w, T s, T a, T nu, int lim, T 
     T phi = T(1);
     if (lim != 0) {
         const T b = dot3(w, w);
-        phi = b == T(0) ? T(0) : mc_phi(a / b);
+        phi = b == T(0) ? T(0) : mc_phi(a * recip(b));
     }
     const T coef = T(0.5) * sgn(s) * (T(1) - nu * fabs(s));
 #pragma unroll
@@ -271,15 +293,15 @@ __device__ __forceinline__ void swe_start(const SRow<ETA, T> &Ra, const SRow<ETA
     flucts(yp, bm, c.bpP);
 #pragma unroll
     for (int k = 0; k < 3; ++k) c.bpl[k] = c.bpr[k] = T(0);
-    if (op.trans) swe_tsplit(0, c.bpP, yp.ru, yp.rv, yp.c, c.bpl, c.bpr);
+    if (op.trans) swe_tsplit(0, c.bpP, yp.ru, yp.rv, yp.c, yp.hic, c.bpl, c.bpr);
     const SEdge<T> xe = roe_edge<0>(shift_left(R0), R0, g);
     T am[3], ap[3], dn[3];
     flucts(xe, am, ap);
 #pragma unroll
     for (int k = 0; k < 3; ++k) c.apu[k] = c.amu[k] = T(0);
     if (op.trans) {
-        swe_tsplit(1, ap, xe.ru, xe.rv, xe.c, dn, c.apu);
-        swe_tsplit(1, am, xe.ru, xe.rv, xe.c, dn, c.amu);
+        swe_tsplit(1, ap, xe.ru, xe.rv, xe.c, xe.hic, dn, c.apu);
+        swe_tsplit(1, am, xe.ru, xe.rv, xe.c, xe.hic, dn, c.amu);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) c.P[k] = c.Gp[k] = T(0);
@@ -303,8 +325,8 @@ __device__ __forceinline__ void swe_row(const SRow<ETA, T> &R0, const SRow<ETA, 
 #pragma unroll
     for (int k = 0; k < 3; ++k) bml[k] = bmr[k] = bpl[k] = bpr[k] = T(0);
     if (op.trans) {
-        swe_tsplit(0, bmN, yn.ru, yn.rv, yn.c, bml, bmr);
-        swe_tsplit(0, bpN, yn.ru, yn.rv, yn.c, bpl, bpr);
+        swe_tsplit(0, bmN, yn.ru, yn.rv, yn.c, yn.hic, bml, bmr);
+        swe_tsplit(0, bpN, yn.ru, yn.rv, yn.c, yn.hic, bpl, bpr);
     }
     T dhi[3];   // per family: waves of y-edges j + 1/2 and j + 3/2 dotted
 #pragma unroll
@@ -323,8 +345,8 @@ __device__ __forceinline__ void swe_row(const SRow<ETA, T> &R0, const SRow<ETA, 
 #pragma unroll
     for (int k = 0; k < 3; ++k) amd[k] = amu[k] = apd[k] = apu[k] = T(0);
     if (op.trans) {
-        swe_tsplit(1, ap, xn.ru, xn.rv, xn.c, apd, apu);
-        swe_tsplit(1, am, xn.ru, xn.rv, xn.c, amd, amu);
+        swe_tsplit(1, ap, xn.ru, xn.rv, xn.c, xn.hic, apd, apu);
+        swe_tsplit(1, am, xn.ru, xn.rv, xn.c, xn.hic, amd, amu);
         // G: the x-fluctuations of (col, j + 1) going down, then those of
         // (col, j) going up; those of the right edges come from the next lane
         T d[3];
