@@ -23,8 +23,9 @@ namespace {
 
 using namespace march;
 
-// 1/b from the hardware reciprocal refined by Newton steps (within an ulp
-// or two of the quotient; for the limiter ratio, whose b = 0 is excluded)
+// 1/b from the hardware reciprocal refined by Newton steps, within an ulp
+// or two of the quotient (b nonzero and not subnormal: depths, sums of
+// square roots and sound speeds, and the limiter's b = 0 is excluded)
 __device__ __forceinline__ double recip(double b)
 {
     double r = __builtin_amdgcn_rcp(b);
@@ -121,7 +122,7 @@ __device__ __forceinline__ SRow<ETA, T> derive(const SRaw<ETA, T> &a, int &bad)
     r.h = (T)r.he;
     r.hu = a.hu;
     r.hv = a.hv;
-    const T rh = T(1) / r.h;
+    const T rh = recip(r.h);
     r.u = r.hu * rh;
     r.v = r.hv * rh;
     r.sq = sqrt(r.h);
@@ -157,7 +158,7 @@ __device__ __forceinline__ SEdge<T> roe_edge(const SRow<ETA, T> &L, const SRow<E
     const T utl = DIR == 0 ? L.v : L.u, utr = DIR == 0 ? R.v : R.u;
     const T qnl = DIR == 0 ? L.hu : L.hv, qnr = DIR == 0 ? R.hu : R.hv;
     const T hbar = T(0.5) * (L.h + R.h);
-    const T rs = T(1) / (L.sq + R.sq);
+    const T rs = recip(L.sq + R.sq);
     const T un = (L.sq * unl + R.sq * unr) * rs;
     const T ut = (L.sq * utl + R.sq * utr) * rs;
     // c = sqrt(g hbar) and 1/(2c) from one reciprocal square root
@@ -574,7 +575,7 @@ __device__ __forceinline__ LEdge<T> lsw_edge(const LRow<T> &L, const LRow<T> &R)
     const T f1l = -(cl * cl) * L.q[n], f1r = -(cr * cr) * R.q[n];
     const T f2l = -L.q[0], f2r = -R.q[0];
     const T df1 = f1r - f1l, df2 = f2r - f2l;
-    const T inv = T(1) / (cl + cr);
+    const T inv = recip(cl + cr);
     const T b1 = (df1 + cr * df2) * inv;
     const T b2 = (cl * df2 - df1) * inv;
     LEdge<T> e;
