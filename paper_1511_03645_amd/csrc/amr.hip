@@ -93,11 +93,14 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
     const long long csf = (long long)nxf * (NY * r);
     const long long csc = (long long)NX * NY;
     const bool pow2 = (r & (r - 1)) == 0;
+    const int lr = __builtin_ctz((unsigned)r);
     const T inv_r = T(1) / T(r);
-    // one thread per (parent, component)
+    // one thread per (component, parent), component-major: neighbouring
+    // lanes take neighbouring parents of one component plane, so their
+    // children's stores fall close together
     for (long long w = blockIdx.x * 256LL + threadIdx.x; w < 3 * nblocks; w += (long long)gridDim.x * 256) {
-        const long long n = w / 3;
-        const int k = (int)(w - 3 * n);
+        const int k = (int)(w / nblocks);
+        const long long n = w - (long long)k * nblocks;
         const int lin = blocks[3 * n];
         const unsigned long long mask =
             (unsigned long long)(unsigned)blocks[3 * n + 1] | ((unsigned long long)(unsigned)blocks[3 * n + 2] << 32);
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
             }
             for (unsigned long long m = mask; m; m &= m - 1) {
                 const int b = __builtin_ctzll(m);
-                const int ii = b % r, jj = b / r;
+                const int ii = pow2 ? (b & (r - 1)) : b % r, jj = pow2 ? (b >> lr) : b / r;
                 // a power-of-two ratio divides exactly as its reciprocal multiplies
                 const T xi = (pow2 ? (T(ii) + T(0.5)) * inv_r : (T(ii) + T(0.5)) / T(r)) - T(0.5);
                 const T eta = (pow2 ? (T(jj) + T(0.5)) * inv_r : (T(jj) + T(0.5)) / T(r)) - T(0.5);
