@@ -20,6 +20,11 @@ Pieces and the passages of Davis & LeVeque (arXiv:1511.03645) they follow:
                        |qhat^T q|, against a tolerance (Sec. 4; Sec. 5.1.2 time
                        range), with bilinear interpolation from the adjoint
                        grid (Sec. 4).
+* ``difference_flag``/``surface_flag`` – the two comparison criteria the
+                       adjoint flag replaces: undivided differences of every
+                       component to the face neighbours (Sec. 5.2.4, "pressure
+                       flagging") and the sea-surface departure from sea level
+                       (Sec. 5.3, "surface flagging").
 * ``amr``            – coarse/fine transfer, Berger-Oliger stepping and
                        Berger-Rigoutsos clustering (Sec. 3), in ``oracle.amr``.
 """
@@ -308,3 +313,61 @@ def flag(q, snaps, t, t_s, t_f, ds, tol, ratio=1, region=None):
     n_lo, n_hi = snapshot_window(t, t_s, t_f, ds, len(snaps))
     mval = flag_measure(q, snaps, n_lo, n_hi, ratio, region)
     return (mval > tol).astype(np.uint8), mval
+
+
+def _face_neighbours(c, axis, bc_lo, bc_hi, negate):
+    """The values of c at the lower and upper face neighbours along `axis`
+    (1: x, columns; 0: y, rows).  Outside the domain the boundary rule gives
+    the neighbour: extrapolation the boundary cell itself, a wall that same
+    cell (its mirror) with the sign changed when the component is normal to
+    the wall (`negate`), periodic the cell at the other end."""
+    c = np.asarray(c, dtype=np.float64)
+    lo = np.roll(c, 1, axis=axis)
+    hi = np.roll(c, -1, axis=axis)
+    first = [slice(None)] * 2
+    last = [slice(None)] * 2
+    first[axis] = 0
+    last[axis] = -1
+    first, last = tuple(first), tuple(last)
+    wall_sign = -1.0 if negate else 1.0
+    if bc_lo == 0:
+        lo[first] = c[first]
+    elif bc_lo == 1:
+        lo[first] = wall_sign * c[first]
+    if bc_hi == 0:
+        hi[last] = c[last]
+    elif bc_hi == 1:
+        hi[last] = wall_sign * c[last]
+    # periodic (2): np.roll already wrapped
+    return lo, hi
+
+
+def difference_measure(q, bc):
+    """Undivided-difference measure (Sec. 5.2.4): per cell, the largest
+    |q_k(nb) - q_k(x)| over the components k of q (m, ny, nx) and the face
+    neighbours nb (none along y when ny == 1).  Component 1 is normal to the
+    x-walls, component 2 to the y-walls.  bc = (x-low, x-high, y-low, y-high)
+    as 0 extrapolation, 1 wall, 2 periodic."""
+    q = np.asarray(q, dtype=np.float64)
+    m, ny, nx = q.shape
+    d = np.zeros((ny, nx))
+    for k in range(m):
+        lo, hi = _face_neighbours(q[k], 1, bc[0], bc[1], k == 1)
+        d = np.maximum(d, np.maximum(np.abs(lo - q[k]), np.abs(hi - q[k])))
+        if ny > 1:
+            lo, hi = _face_neighbours(q[k], 0, bc[2], bc[3], k == 2)
+            d = np.maximum(d, np.maximum(np.abs(lo - q[k]), np.abs(hi - q[k])))
+    return d
+
+
+def difference_flag(q, bc, tol):
+    """Flags (uint8, flagged iff the measure exceeds tol) and the measure."""
+    d = difference_measure(q, bc)
+    return (d > tol).astype(np.uint8), d
+
+
+def surface_flag(eta, tol):
+    """Sea-surface criterion (Sec. 5.3): flagged iff |eta - 0| > tol, with
+    eta = h + B the surface elevation and sea level at 0."""
+    d = np.abs(np.asarray(eta, dtype=np.float64))
+    return (d > tol).astype(np.uint8), d

@@ -182,3 +182,97 @@ def test_sec51_inner_product_selects_waves_reaching_target():
     assert flagged.size > 0
     assert flagged.min() > -1.6 and flagged.max() < -0.4
     assert not np.any(fl[0][(x > -3.5) & (x < -2.5)])
+
+
+# ---- the comparison criteria (Sec. 5.2.4 undivided differences, Sec. 5.3 surface) ----
+
+def _brute_difference(q, bc):
+    """Explicit enumeration: every cell, every component, the four face
+    neighbours resolved one by one by the boundary rule."""
+    m, ny, nx = q.shape
+    d = np.zeros((ny, nx))
+    for j in range(ny):
+        for i in range(nx):
+            for k in range(m):
+                steps = [(-1, 0), (1, 0)] + ([(0, -1), (0, 1)] if ny > 1 else [])
+                for di, dj in steps:
+                    ii, jj, sign = i + di, j + dj, 1.0
+                    n, side = (nx, (bc[0] if ii < 0 else bc[1])) if di else (ny, (bc[2] if jj < 0 else bc[3]))
+                    idx = ii if di else jj
+                    if idx < 0 or idx >= n:
+                        if side == 2:
+                            idx %= n
+                        else:
+                            idx = min(max(idx, 0), n - 1)
+                            if side == 1 and ((di and k == 1) or (dj and k == 2)):
+                                sign = -1.0
+                        if di:
+                            ii = idx
+                        else:
+                            jj = idx
+                    d[j, i] = max(d[j, i], abs(sign * q[k, jj, ii] - q[k, j, i]))
+    return d
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1), (2, 2, 2, 2), (1, 0, 2, 1), (0, 2, 1, 0)])
+def test_difference_measure_matches_brute_force(bc):
+    rng = np.random.default_rng(11)
+    q = rng.standard_normal((3, 5, 7))
+    assert np.array_equal(oracle.difference_measure(q, bc), _brute_difference(q, bc))
+    q1 = rng.standard_normal((2, 1, 9))       # 1D acoustics: x-neighbours only
+    assert np.array_equal(oracle.difference_measure(q1, bc), _brute_difference(q1, bc))
+
+
+def test_difference_measure_of_a_linear_field():
+    """q_k = a_k x + b_k y (dyadic values, exact arithmetic): the undivided
+    differences are |a_k| dx and |b_k| dy in every interior cell, and with
+    extrapolation the boundary cells keep their one inner neighbour, so the
+    measure is max_k max(|a_k| dx, |b_k| dy) everywhere."""
+    nx, ny, dx, dy = 8, 6, 0.25, 0.5
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    X, Y = np.meshgrid(x, y)
+    a, b = (1.0, -3.0, 0.5), (2.0, 0.25, -1.0)
+    q = np.stack([a[k] * X + b[k] * Y for k in range(3)])
+    d = oracle.difference_measure(q, (0, 0, 0, 0))
+    assert np.all(d == max(max(abs(a[k]) * dx, abs(b[k]) * dy) for k in range(3)))
+
+
+def test_difference_measure_walls_negate_the_normal_component_only():
+    """Constant p, u, v: every difference vanishes except across a wall for
+    the component normal to it, where the mirror cell differs by 2|q_k|."""
+    ny, nx = 4, 5
+    q = np.stack([np.full((ny, nx), 1.5), np.full((ny, nx), 0.25), np.full((ny, nx), -0.125)])
+    d = oracle.difference_measure(q, (1, 0, 0, 0))            # wall at x-low only
+    want = np.zeros((ny, nx))
+    want[:, 0] = 0.5                                          # |(-u) - u|
+    assert np.array_equal(d, want)
+    d = oracle.difference_measure(q, (0, 0, 0, 1))            # wall at y-high only
+    want = np.zeros((ny, nx))
+    want[-1, :] = 0.25                                        # |(-v) - v|
+    assert np.array_equal(d, want)
+    assert np.array_equal(oracle.difference_measure(q, (2, 2, 2, 2)), np.zeros((ny, nx)))
+
+
+def test_difference_flag_of_a_step_is_the_two_cells_beside_it():
+    """A jump of 0.75 in p between columns 3 and 4: exactly those two columns
+    exceed a tolerance below 0.75, and none reaches it at 0.75 (strict)."""
+    q = np.zeros((3, 5, 8))
+    q[0, :, 4:] = 0.75
+    f, d = oracle.difference_flag(q, (0, 0, 0, 0), 0.5)
+    want = np.zeros((5, 8), dtype=np.uint8)
+    want[:, 3:5] = 1
+    assert np.array_equal(f, want)
+    f, _ = oracle.difference_flag(q, (0, 0, 0, 0), 0.75)
+    assert not f.any()
+    # periodic in x: the seam between the last and the first column is a jump too
+    f, _ = oracle.difference_flag(q, (2, 2, 0, 0), 0.5)
+    want[:, 0] = want[:, 7] = 1
+    assert np.array_equal(f, want)
+
+
+def test_surface_flag_is_strict_on_the_departure_from_sea_level():
+    eta = np.array([[0.1, -0.1, 0.1000001, -0.1000001, 0.0]])
+    f, d = oracle.surface_flag(eta, 0.1)
+    assert f.tolist() == [[0, 0, 1, 1, 0]]
+    assert np.array_equal(d, np.abs(eta))
