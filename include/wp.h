@@ -203,6 +203,25 @@ int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device);
 int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, double t_f,
                     uint8_t *flags, int on_device, int64_t *nflagged);
 
+/* The comparison flags that the adjoint-guided flag replaces, on every patch
+ * of `level` at its current time, each cell flagged iff its measure exceeds
+ * tol (tol >= 0); flags and *nflagged as for wp_flag_adjoint, and wp_regrid
+ * with patches == NULL clusters these flags the same way.
+ * wp_flag_difference (Sec. 5.2.4, "pressure flagging"): the measure is the
+ * largest undivided difference |q_k(nb) - q_k(x)| over the components k and
+ * the four face neighbours nb of the cell (two along x for 1D acoustics),
+ * compared in FP64 from the stored values.  A neighbour across the domain
+ * edge follows the boundary rule: extrapolation gives the cell itself, a
+ * wall its mirror with the normal component (1 along x, 2 along y) negated,
+ * periodic the wrapped cell.  On a refined level the ghost ring is first
+ * filled from the level below at the level's time, so patch-edge cells see
+ * interpolated neighbours.  Any kind.
+ * wp_flag_surface (Sec. 5.3, "surface flagging"): the measure is the
+ * departure |eta| of the sea surface eta = h + B from sea level 0 (every cell
+ * is wet).  Shallow water only, WP_EINVAL otherwise. */
+int wp_flag_difference(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged);
+int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged);
+
 /* The forward run with adjoint-guided flagging (Sec. 4; Sec. 5.1.2) on a
  * single-level instance: nsteps steps of size dt from the current state and
  * time t0, with the flag of wp_flag_adjoint(0, tol, t, t_s, t_f) evaluated at
@@ -226,8 +245,9 @@ int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_every, doubl
  * level's patches with all eight neighbours inside the domain also in them,
  * i.e. level's patches shrunk by one cell except along the physical
  * boundary).  patches == NULL: the flags of `level` from the last
- * wp_flag_adjoint on it, restricted to that nesting region, dilated by
- * `buffer` cells and restricted again, clustered by wp_cluster with
+ * wp_flag_adjoint, wp_flag_difference or wp_flag_surface on it,
+ * restricted to that nesting region, dilated by `buffer` cells and
+ * restricted again, clustered by wp_cluster with
  * efficiency 0.7, sides of at most max(1, 64 / ratio) and at least
  * max(1, 8 / ratio) level cells, then refined by the ratio.  Cells of the new
  * patches keep the old level+1 data where an old patch covered them and are

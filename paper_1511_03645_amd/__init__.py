@@ -93,6 +93,8 @@ _SIGS = {
     "wp_num_snapshots": (_I, [_P]),
     "wp_get_snapshot": (_I, [_P, _I, _P, _I]),
     "wp_flag_adjoint": (_I, [_P, _I, _D, _D, _D, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
+    "wp_flag_difference": (_I, [_P, _I, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
+    "wp_flag_surface": (_I, [_P, _I, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
     "wp_regrid": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, _I]),
     "wp_get_patches": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
     "wp_forward_flagged": (_I, [_P, _D, _I, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int64),
@@ -353,6 +355,22 @@ class WavePatch:
         self._check(lib().wp_flag_adjoint(self.h, level, tol, t, t_s, t_f, p, 0,
                                           ctypes.byref(n) if want_count else None))
         return flags, (n.value if want_count else None)
+
+    def _flag_standard(self, fn, level, tol, want_flags, want_count):
+        nx, ny, _ = self.level_info(level)
+        flags = np.zeros((ny, nx), dtype=np.uint8) if want_flags else None
+        n = ctypes.c_int64()
+        p = ctypes.c_void_p(flags.ctypes.data) if want_flags else ctypes.c_void_p()
+        self._check(fn(self.h, level, tol, p, 0, ctypes.byref(n) if want_count else None))
+        return flags, (n.value if want_count else None)
+
+    def flag_difference(self, level, tol, want_flags=True, want_count=True):
+        """wp_flag_difference (undivided differences of every component)."""
+        return self._flag_standard(lib().wp_flag_difference, level, tol, want_flags, want_count)
+
+    def flag_surface(self, level, tol, want_flags=True, want_count=True):
+        """wp_flag_surface (shallow water: |eta| above sea level 0)."""
+        return self._flag_standard(lib().wp_flag_surface, level, tol, want_flags, want_count)
 
     def forward_flagged(self, dt, nsteps, flag_every, tol, t_s, t_f, want_counts=True, want_times=False):
         """wp_forward_flagged: (flagged cells per flag event or None,

@@ -358,7 +358,9 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
 
 extern "C" int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int cap, int *np)
 {
-    if (!ctx || level < 0 || level >= (int)ctx->L.size() || (cap > 0 && !out)) return WP_EINVAL;
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail_get(ctx, WP_EINVAL, "level out of range");
+    if (cap > 0 && !out) return wp_fail_get(ctx, WP_EINVAL, "null output with a positive capacity");
     const auto &p = ctx->L[level].patches;
     if (np) *np = (int)p.size();
     for (int k = 0; k < (int)p.size() && k < cap; ++k) out[k] = p[k];

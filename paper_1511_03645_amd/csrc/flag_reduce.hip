@@ -1,7 +1,8 @@
-// Adjoint inner-product flag kernel (Davis & LeVeque Sec. 4 and Sec. 5.1.2)
-// and compensated FP64 reductions for the functional J (eq. J_general) and
-// the inner-product integral (eq. q_equality / eq. J).
-#include "wp_internal.h"
+// Adjoint inner-product flag kernel (Davis & LeVeque Sec. 4 and Sec. 5.1.2),
+// the two comparison flags of Sec. 5.2.4 and 5.3 (undivided differences,
+// sea-surface departure), and compensated FP64 reductions for the functional
+// J (eq. J_general) and the inner-product integral (eq. q_equality / eq. J).
+#include "march_common.h"
 
 namespace wp {
 namespace {
@@ -113,6 +114,97 @@ __global__ __launch_bounds__(256) void flag_mixed_kernel(const double *__restric
         const uint8_t f = best > tol ? 1 : 0;
         flags[idx] = f;
         local += f;
+    }
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+}
+
+// Undivided-difference flag, the comparison criterion of Sec. 5.2.4 ("pressure
+// flagging"): d(x) = max over the components k and the four face neighbours
+// nb of |q_k(nb) - q_k(x)|; a neighbour across the physical boundary is the
+// cell the boundary rule maps it to (extrapolation: the cell itself; wall:
+// its mirror with the normal component, 1 along x and 2 along y, negated;
+// periodic: the wrapped cell).  Flagged iff d > tol.  Component 0 is of type
+// TE, components 1 and 2 of type TU (c2 null for 1D acoustics, which has no
+// y-neighbours).  Tiles and threads as flag_kernel.
+template <typename TE, typename TU>
+__global__ __launch_bounds__(256) void diff_flag_kernel(const TE *__restrict__ c0, const TU *__restrict__ c1,
+                                                        const TU *__restrict__ c2, int nx, int ny, int bc0, int bc1,
+                                                        int bc2, int bc3, double tol, const Tile *__restrict__ tiles,
+                                                        uint8_t *__restrict__ flags,
+                                                        unsigned long long *__restrict__ count)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    unsigned long long local = 0;
+    if (x < tl.ni) {
+        const int i = tl.i0 + x;
+        bool fl, fr;
+        const int il = march::resolve(i - 1, nx, bc0, bc1, fl);
+        const int ir = march::resolve(i + 1, nx, bc0, bc1, fr);
+        for (int j = tl.j0 + y; j < tl.j0 + tl.nj; j += 4) {
+            const long long row = (long long)j * nx, idx = row + i;
+            double d = 0.0;
+            auto diff = [&](double nb, double c) { d = fmax(d, fabs(nb - c)); };
+            {
+                const double c = c0[idx];
+                diff(c0[row + il], c);
+                diff(c0[row + ir], c);
+            }
+            {
+                const double c = c1[idx];
+                const double l = c1[row + il], r = c1[row + ir];
+                diff(fl ? -l : l, c);
+                diff(fr ? -r : r, c);
+            }
+            if (c2) {
+                const double c = c2[idx];
+                diff(c2[row + il], c);
+                diff(c2[row + ir], c);
+            }
+            if (ny > 1) {
+                bool fd, fu;
+                const long long rd = (long long)march::resolve(j - 1, ny, bc2, bc3, fd) * nx + i;
+                const long long ru = (long long)march::resolve(j + 1, ny, bc2, bc3, fu) * nx + i;
+                diff(c0[rd], c0[idx]);
+                diff(c0[ru], c0[idx]);
+                diff(c1[rd], c1[idx]);
+                diff(c1[ru], c1[idx]);
+                if (c2) {
+                    const double c = c2[idx];
+                    const double dn = c2[rd], up = c2[ru];
+                    diff(fd ? -dn : dn, c);
+                    diff(fu ? -up : up, c);
+                }
+            }
+            const uint8_t f = d > tol ? 1 : 0;
+            flags[idx] = f;
+            local += f;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+}
+
+// Surface flag, the comparison criterion of Sec. 5.3 ("surface flagging"):
+// the sea surface eta = h + B departs from sea level (0) by more than tol.
+// Every cell of the path is wet (bathymetry below sea level is required).
+template <typename TE>
+__global__ __launch_bounds__(256) void surface_flag_kernel(const TE *__restrict__ eta, int nx, double tol,
+                                                           const Tile *__restrict__ tiles,
+                                                           uint8_t *__restrict__ flags,
+                                                           unsigned long long *__restrict__ count)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    unsigned long long local = 0;
+    if (x < tl.ni) {
+        for (int j = tl.j0 + y; j < tl.j0 + tl.nj; j += 4) {
+            const long long idx = (long long)j * nx + tl.i0 + x;
+            const uint8_t f = fabs((double)eta[idx]) > tol ? 1 : 0;
+            flags[idx] = f;
+            local += f;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
     if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
@@ -276,6 +368,23 @@ void launch_sum_dot_mixed(const double *eta, const float *hu, const float *hv, l
     hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
 }
 
+template <typename TE, typename TU>
+void launch_flag_difference(const TE *c0, const TU *c1, const TU *c2, int nx, int ny, const int *bc, double tol,
+                            const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((diff_flag_kernel<TE, TU>), dim3(ntiles), dim3(256), 0, s, c0, c1, c2, nx, ny, bc[0], bc[1],
+                       bc[2], bc[3], tol, tiles, flags, count);
+}
+
+template <typename TE>
+void launch_flag_surface(const TE *eta, int nx, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
+                         unsigned long long *count, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((surface_flag_kernel<TE>), dim3(ntiles), dim3(256), 0, s, eta, nx, tol, tiles, flags, count);
+}
+
 void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s)
 {
     if (n <= 0) return;
@@ -297,5 +406,19 @@ template void launch_sum_dot<double, double>(const double *, long long, const do
                                              double *, int, double *, hipStream_t);
 template void launch_sum_dot<float, float>(const float *, long long, const float *, long long, long long, int,
                                            double *, int, double *, hipStream_t);
+
+template void launch_flag_difference<double, double>(const double *, const double *, const double *, int, int,
+                                                     const int *, double, const Tile *, int, uint8_t *,
+                                                     unsigned long long *, hipStream_t);
+template void launch_flag_difference<float, float>(const float *, const float *, const float *, int, int, const int *,
+                                                   double, const Tile *, int, uint8_t *, unsigned long long *,
+                                                   hipStream_t);
+template void launch_flag_difference<double, float>(const double *, const float *, const float *, int, int,
+                                                    const int *, double, const Tile *, int, uint8_t *,
+                                                    unsigned long long *, hipStream_t);
+template void launch_flag_surface<double>(const double *, int, double, const Tile *, int, uint8_t *,
+                                          unsigned long long *, hipStream_t);
+template void launch_flag_surface<float>(const float *, int, double, const Tile *, int, uint8_t *,
+                                         unsigned long long *, hipStream_t);
 
 }  // namespace wp

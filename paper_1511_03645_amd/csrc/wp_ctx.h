@@ -133,6 +133,12 @@ struct wp_ctx {
 };
 
 int wp_fail(wp_ctx *ctx, int code, const char *fmt, ...);
+// The getters take a const handle; their argument errors still leave the
+// handle's last-error message (a per-handle record, not state).
+inline int wp_fail_get(const wp_ctx *ctx, int code, const char *what)
+{
+    return ctx ? wp_fail(const_cast<wp_ctx *>(ctx), code, "%s", what) : code;
+}
 // Copies between device memory and host memory through the pinned staging
 // buffer, on the handle's stream, complete when they return: `rows` rows of
 // `width` bytes, `dpitch` / `spitch` bytes apart on the destination / source.

@@ -490,7 +490,8 @@ extern "C" int wp_set_stream(wp_ctx *ctx, void *stream)
 
 extern "C" int wp_level_info(const wp_ctx *ctx, int level, int *nx, int *ny, int *npatches)
 {
-    if (!ctx || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail_get(ctx, WP_EINVAL, "level out of range");
     if (nx) *nx = ctx->L[level].nx;
     if (ny) *ny = ctx->L[level].ny;
     if (npatches) *npatches = (int)ctx->L[level].patches.size();
@@ -669,7 +670,9 @@ extern "C" int wp_sync(wp_ctx *ctx)
 
 extern "C" int wp_get_time(const wp_ctx *ctx, int level, double *t)
 {
-    if (!ctx || !t || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
+    if (!ctx) return WP_EINVAL;
+    if (!t) return wp_fail_get(ctx, WP_EINVAL, "null output");
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail_get(ctx, WP_EINVAL, "level out of range");
     *t = ctx->L[level].t;
     return WP_OK;
 }
@@ -695,7 +698,8 @@ extern "C" int wp_set_tile_rows(wp_ctx *ctx, int rows)
 
 extern "C" int wp_get_tile_rows(const wp_ctx *ctx, int *rows)
 {
-    if (!ctx || !rows) return WP_EINVAL;
+    if (!ctx) return WP_EINVAL;
+    if (!rows) return wp_fail_get(ctx, WP_EINVAL, "null output");
     *rows = ctx->tile_rows > 0 ? ctx->tile_rows : wp_default_rows(ctx, ctx->L[0]);
     return WP_OK;
 }
@@ -801,7 +805,8 @@ extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
 
 extern "C" int wp_get_step_pairs(const wp_ctx *ctx, int *rows)
 {
-    if (!ctx || !rows) return WP_EINVAL;
+    if (!ctx) return WP_EINVAL;
+    if (!rows) return wp_fail_get(ctx, WP_EINVAL, "null output");
     *rows = ctx->L.empty() ? 0 : ctx->L[0].pair_rows;
     return WP_OK;
 }
@@ -1198,6 +1203,75 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
         *nflagged = (int64_t)c;
     }
     return WP_OK;
+}
+
+// The comparison flags (Sec. 5.2.4, Sec. 5.3) on every patch of a level, with
+// the count and the copy-out of wp_flag_adjoint.  A refined level's ghost
+// ring is filled from the level below at the level's time first, so that the
+// cells along a patch edge see their neighbours.
+static int flag_standard(wp_ctx *ctx, int level, bool surface, double tol, uint8_t *flags, int on_device,
+                         int64_t *nflagged)
+{
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level out of range");
+    if (surface && ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "the surface flag is for shallow water");
+    if (!(tol >= 0.0)) return wp_fail(ctx, WP_EINVAL, "tolerance must be non-negative");
+    Level &lv = ctx->L[level];
+    const long long cells = (long long)lv.nx * lv.ny;
+    hipStream_t s = ctx->stream;
+    int rc;
+    if (!surface && level > 0 && !lv.patches.empty() && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK)
+        return rc;
+    if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), s) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    const bool full = lv.patches.size() == 1 && lv.patches[0].nx == lv.nx && lv.patches[0].ny == lv.ny;
+    if (!full) launch_fill_u8(lv.flags, cells, 0, s);
+    const char *q = (const char *)lv.q[lv.cur];
+    const int m = ctx->m;
+    if (surface) {
+        if (ctx->esz == 8 || ctx->prob.precision == WP_MIXED)
+            launch_flag_surface<double>((const double *)q, lv.nx, tol, lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count,
+                                        s);
+        else
+            launch_flag_surface<float>((const float *)q, lv.nx, tol, lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count,
+                                       s);
+    } else if (ctx->prob.precision == WP_MIXED) {
+        launch_flag_difference<double, float>((const double *)q, (const float *)(q + cells * 8),
+                                              (const float *)(q + cells * 12), lv.nx, lv.ny, ctx->prob.bc, tol,
+                                              lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count, s);
+    } else if (ctx->esz == 8) {
+        const double *c = (const double *)q;
+        launch_flag_difference<double, double>(c, c + cells, m > 2 ? c + 2 * cells : nullptr, lv.nx, lv.ny,
+                                               ctx->prob.bc, tol, lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count, s);
+    } else {
+        const float *c = (const float *)q;
+        launch_flag_difference<float, float>(c, c + cells, m > 2 ? c + 2 * cells : nullptr, lv.nx, lv.ny,
+                                             ctx->prob.bc, tol, lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flag launch: %s", hipGetErrorString(e));
+    lv.flags_valid = true;
+    if (flags && on_device &&
+        hipMemcpyAsync(flags, lv.flags, (size_t)cells, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "flag copy");
+    if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cells, false)) != WP_OK) return rc;
+    if (nflagged) {
+        unsigned long long c = 0;
+        if ((rc = wp_host_copy(ctx, &c, ctx->count, sizeof c, false)) != WP_OK) return rc;
+        *nflagged = (int64_t)c;
+    }
+    return WP_OK;
+}
+
+extern "C" int wp_flag_difference(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device,
+                                  int64_t *nflagged)
+{
+    return flag_standard(ctx, level, false, tol, flags, on_device, nflagged);
+}
+
+extern "C" int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged)
+{
+    return flag_standard(ctx, level, true, tol, flags, on_device, nflagged);
 }
 
 // The flagged forward run as one captured sequence: a clear of the event

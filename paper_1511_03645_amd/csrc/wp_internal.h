@@ -135,6 +135,16 @@ void launch_flag_mixed(const double *eta, const float *hu, const float *hv, long
                        const float *snaps, long long snap_stride, long long hcs, int n_lo, int n_hi, double tol,
                        const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
 
+// Comparison flags: the undivided difference of every component to its four
+// face neighbours (boundary rule across the domain edge, bc[4]), and the
+// sea-surface departure |eta| (shallow water).  c2 null: two components.
+template <typename TE, typename TU>
+void launch_flag_difference(const TE *c0, const TU *c1, const TU *c2, int nx, int ny, const int *bc, double tol,
+                            const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
+template <typename TE>
+void launch_flag_surface(const TE *eta, int nx, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
+                         unsigned long long *count, hipStream_t s);
+
 // Compensated FP64 reductions: out[0] = sum_k sum_cells w(cell) a_k b_k where
 // a is m component arrays (type TA) and b either an indicator (uint8, times
 // unit vector `comp`) or m arrays of type TB.
