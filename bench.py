@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-swe", action="store_true")
     ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-flagging", action="store_true", help="skip the adjoint vs difference flagging comparison")
     ap.add_argument("--rows", type=int, default=0,
                     help="tile height of the one-step 2D acoustics kernel (default: chosen by the autotuner)")
     ap.add_argument("--pair-rows", type=int, default=-1,
@@ -326,6 +327,90 @@ def amr_compare(steps, warmup):
     return res
 
 
+def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
+    """Adjoint-guided flagging against the undivided-difference flag it
+    replaces, on the 2D acoustics problem with three levels (coarse n0^2,
+    refinement ratios 4, 4): every `regrid_every` coarse steps each of levels
+    0 and 1 is flagged, and the level above it rebuilt by Berger-Rigoutsos
+    from the flags (dilated by `buffer` cells); Berger-Oliger steps in
+    between.  The adjoint-flagged run includes its adjoint solve.  Accuracy
+    is the error in J against a uniform run at the finest resolution
+    (n0 * 16)^2, averaged onto the coarse grid.  Times are wall-clock,
+    regridding (host clustering) included."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import acoustics2d
+    cfg = acoustics2d(n=n0, seed=1)
+    N, every, dt, F = cfg["nsteps"], cfg["snap_every"], cfg["dt"], cfg["functional"]
+    r = ratios[0] * ratios[1]
+    # reference: the finest resolution everywhere
+    fine = acoustics2d(n=n0 * r, seed=1)
+    wf = wp.from_config(fine)
+    wf.set_state(fine["q0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wf.run_graph(N * r, dt / r, 1)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    qf = wf.get_state()
+    del wf
+    wc = wp.from_config(cfg)
+    wc.set_state(qf.reshape(3, n0, r, n0, r).mean(axis=(2, 4)))
+    J_ref = wc.functional_value(F, 0)
+    del wc, qf
+    gi = int((F["cx"] - cfg["xlo"]) / cfg["dx"])
+    gj = int((F["cy"] - cfg["ylo"]) / cfg["dy"])
+
+    def run(mode, tol, gauge=False):
+        w = wp.from_config(cfg, num_levels=3, ratios=tuple(ratios))
+        w.set_state(cfg["q0"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "adjoint":
+            w.adjoint_run(F, dt, N, every)
+        t, ups, fine_cells, g = 0.0, 0, [0, 0], []
+        for _ in range(N // regrid_every):
+            for l in (0, 1):
+                if mode == "adjoint":
+                    w.flag_adjoint(l, tol, t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+                else:
+                    w.flag_difference(l, tol, want_flags=False, want_count=False)
+                w.regrid(l, None, buffer=buffer)
+            c1 = sum(p[2] * p[3] for p in w.get_patches(1))
+            c2 = sum(p[2] * p[3] for p in w.get_patches(2))
+            fine_cells[0] += c1
+            fine_cells[1] += c2
+            ups += regrid_every * (n0 * n0 + ratios[0] * c1 + r * c2)
+            w.advance(regrid_every, dt)
+            t += regrid_every * dt
+            if gauge:
+                g.append(float(w.get_state(0)[0, gj, gi]))
+        J = w.functional_value(F, 0)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        cyc = N // regrid_every
+        del w
+        return {"seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref), "cell_updates": ups,
+                "mean_cells_level1": fine_cells[0] / cyc, "mean_cells_level2": fine_cells[1] / cyc}, g
+
+    runs = []
+    for mode, tol in (("adjoint", 1e-3), ("difference", 0.02), ("difference", 0.005), ("difference", 0.002)):
+        run(mode, tol)                      # warm-up (graph capture, allocations)
+        res, _ = run(mode, tol)
+        res.update(flag=mode, tol=tol)
+        runs.append(res)
+    _, ga = run("adjoint", 1e-3, gauge=True)
+    _, gd = run("difference", 0.002, gauge=True)
+    ga, gd = np.array(ga), np.array(gd)
+    return {"workload": f"acoustics2d, 3 levels, coarse {n0}^2, ratios {ratios[0]},{ratios[1]}, {N} coarse steps, "
+                        f"flag + regrid of levels 0 and 1 every {regrid_every} coarse steps, buffer {buffer}",
+            "J_reference": J_ref, "reference": f"uniform {n0 * r}^2, {N * r} steps, {t_ref:.3f} s",
+            "runs": runs,
+            "gauge": {"cell": [gi, gj], "samples": len(ga),
+                      "max_abs_diff_rel": float(np.abs(ga - gd).max() / max(np.abs(gd).max(), 1e-300)),
+                      "between": "adjoint tol 1e-3 and difference tol 0.002, level-0 p every regrid"}}
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: a bounded sample of the same
     workload (full grid, a fixed number of forward and adjoint steps)."""
@@ -412,6 +497,12 @@ def main():
         print(f"[bench] amr fp64 {out['amr']['fp64']['value'] / 1e9:.2f}, fp32 "
               f"{out['amr']['fp32']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['amr']['J_rel_err_fp32']:.2e}",
               file=sys.stderr, flush=True)
+    if not args.no_flagging:
+        print("[bench] adjoint flagging vs undivided-difference flagging, 3-level AMR", file=sys.stderr, flush=True)
+        out["amr_flagging"] = flagging_compare()
+        for r in out["amr_flagging"]["runs"]:
+            print(f"[bench]   {r['flag']:10s} tol {r['tol']:g}: {r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
+                  f"finest-level cells {r['mean_cells_level2']:.0f}", file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
         out["swe"] = swe_compare(1, 1)
