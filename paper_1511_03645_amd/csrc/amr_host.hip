@@ -14,30 +14,49 @@ namespace {
 
 // Cells inside the level's domain, within two cells (box halo) of a patch and
 // inside none, as linear indices j * nx + i in increasing order.
+// The bounding box of the patches grown by `halo` cells, clipped to nx x ny,
+// as (i0, j0, w, h); empty when there are no patches.
+struct Window {
+    int i0 = 0, j0 = 0, w = 0, h = 0;
+    Window(const std::vector<wp_patch> &P, int halo, int nx, int ny)
+    {
+        if (P.empty()) return;
+        int a = nx, b = ny, c = 0, d = 0;
+        for (const wp_patch &p : P) {
+            a = std::min(a, p.ilo);
+            b = std::min(b, p.jlo);
+            c = std::max(c, p.ilo + p.nx);
+            d = std::max(d, p.jlo + p.ny);
+        }
+        i0 = std::max(a - halo, 0);
+        j0 = std::max(b - halo, 0);
+        w = std::min(c + halo, nx) - i0;
+        h = std::min(d + halo, ny) - j0;
+    }
+    size_t at(int i, int j) const { return (size_t)(j - j0) * w + (i - i0); }
+};
+
 std::vector<int> ring_list(const std::vector<wp_patch> &P, int nx, int ny)
 {
-    std::vector<uint8_t> m((size_t)nx * ny, 0);   // 1 inside a patch, 2 ring
+    const Window W(P, 2, nx, ny);
+    std::vector<uint8_t> m((size_t)W.w * W.h, 0);   // 1 inside a patch, 2 ring
     for (const wp_patch &p : P)
-        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&m[(size_t)j * nx + p.ilo], p.nx, (uint8_t)1);
+        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&m[W.at(p.ilo, j)], p.nx, (uint8_t)1);
     for (const wp_patch &p : P)
         for (int j = std::max(p.jlo - 2, 0); j < std::min(p.jlo + p.ny + 2, ny); ++j)
             for (int i = std::max(p.ilo - 2, 0); i < std::min(p.ilo + p.nx + 2, nx); ++i)
-                if (m[(size_t)j * nx + i] == 0) m[(size_t)j * nx + i] = 2;
+                if (m[W.at(i, j)] == 0) m[W.at(i, j)] = 2;
     std::vector<int> out;
     for (const wp_patch &p : P)   // gather from the halos only, then order
         for (int j = std::max(p.jlo - 2, 0); j < std::min(p.jlo + p.ny + 2, ny); ++j)
             for (int i = std::max(p.ilo - 2, 0); i < std::min(p.ilo + p.nx + 2, nx); ++i)
-                if (m[(size_t)j * nx + i] == 2) {
-                    m[(size_t)j * nx + i] = 3;
+                if (m[W.at(i, j)] == 2) {
+                    m[W.at(i, j)] = 3;
                     out.push_back(j * nx + i);
                 }
     std::sort(out.begin(), out.end());
     return out;
 }
-
-// The ring grouped by coarse parent (r <= 8): per parent its linear index
-// on the level below (NX wide) and the 64-bit mask of its children in the
-// ring, as three ints, parents in increasing order.
 std::vector<int> ring_blocks(const std::vector<int> &ring, int nx, int r, int NX)
 {
     std::vector<std::pair<int, unsigned long long>> par;
@@ -73,17 +92,14 @@ std::vector<int> cover_list(const std::vector<wp_patch> &P, int r, int NX)
     return out;
 }
 
-int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n, const char *what)
+int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n, size_t &cap, const char *what)
 {
-    if (dev) wp_dfree(ctx, dev);
-    dev = nullptr;
     n = (long long)v.size();
     if (v.empty()) return WP_OK;
-    dev = (int *)wp_dalloc(ctx, v.size() * sizeof(int));
-    if (!dev) return wp_fail(ctx, WP_ENOMEM, "%s list", what);
-    if (hipMemcpy(dev, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "%s upload", what);
-    return WP_OK;
+    void *d = dev;
+    const int rc = wp_upload(ctx, v.data(), v.size() * sizeof(int), d, cap, what);
+    dev = (int *)d;
+    return rc;
 }
 
 // Fine cells `cells` of level l from level l-1 at time weight alpha between
@@ -108,7 +124,7 @@ int fill_ring(wp_ctx *ctx, int l, double alpha, hipStream_t s)
 {
     Level &F = ctx->L[l], &C = ctx->L[l - 1];
     if (F.nring == 0) return WP_OK;
-    if (!F.ringb_dev) return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, C.prev_valid, s);
+    if (F.nringb == 0) return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, C.prev_valid, s);
     // by coarse parent: each parent's slopes formed once for all its ring children
     const void *cnew = C.q[C.cur];
     const void *cold = C.prev_valid ? C.q[C.cur ^ 1] : cnew;
@@ -201,35 +217,35 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     int rc;
     // new cells outside every old patch: space interpolation from the level
     // below at its current time
-    std::vector<uint8_t> old((size_t)F.nx * F.ny, 0);
-    for (const wp_patch &p : F.patches)
-        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&old[(size_t)j * F.nx + p.ilo], p.nx, (uint8_t)1);
+    const Window W(boxes, 0, F.nx, F.ny);
+    std::vector<uint8_t> old((size_t)W.w * W.h, 0);
+    for (const wp_patch &p : F.patches) {   // the old patches, clipped to the new boxes' window
+        const int a = std::max(p.ilo, W.i0), b = std::min(p.ilo + p.nx, W.i0 + W.w);
+        for (int j = std::max(p.jlo, W.j0); j < std::min(p.jlo + p.ny, W.j0 + W.h) && a < b; ++j)
+            std::fill_n(&old[W.at(a, j)], b - a, (uint8_t)1);
+    }
     std::vector<int> fresh;
     for (const wp_patch &p : boxes)
         for (int j = p.jlo; j < p.jlo + p.ny; ++j)
             for (int i = p.ilo; i < p.ilo + p.nx; ++i)
-                if (!old[(size_t)j * F.nx + i]) fresh.push_back(j * F.nx + i);
+                if (!old[W.at(i, j)]) fresh.push_back(j * F.nx + i);
     if (!fresh.empty()) {
-        int *dev = nullptr;
         long long n = 0;
-        if ((rc = upload_ints(ctx, fresh, dev, n, "new cell")) != WP_OK) return rc;
-        rc = fill_from_coarse(ctx, f, dev, n, 0.0, false, ctx->stream);
-        if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == WP_OK)
-            rc = wp_fail(ctx, WP_EDEVICE, "regrid sync");
-        wp_dfree(ctx, dev);
-        if (rc != WP_OK) return rc;
+        if ((rc = upload_ints(ctx, fresh, ctx->fresh_dev, n, ctx->fresh_cap, "new cell")) != WP_OK) return rc;
+        if ((rc = fill_from_coarse(ctx, f, ctx->fresh_dev, n, 0.0, false, ctx->stream)) != WP_OK) return rc;
     }
     F.patches = boxes;
     if ((rc = wp_upload_tiles(ctx, F)) != WP_OK) return rc;
     {
         const std::vector<int> ring = ring_list(F.patches, F.nx, F.ny);
-        if ((rc = upload_ints(ctx, ring, F.ring_dev, F.nring, "ring")) != WP_OK) return rc;
+        if ((rc = upload_ints(ctx, ring, F.ring_dev, F.nring, F.ring_cap, "ring")) != WP_OK) return rc;
         std::vector<int> blocks;
         if (F.ratio <= 8) blocks = ring_blocks(ring, F.nx, F.ratio, C.nx);
-        if ((rc = upload_ints(ctx, blocks, F.ringb_dev, F.nringb, "ring block")) != WP_OK) return rc;
+        if ((rc = upload_ints(ctx, blocks, F.ringb_dev, F.nringb, F.ringb_cap, "ring block")) != WP_OK) return rc;
         F.nringb /= 3;
     }
-    if ((rc = upload_ints(ctx, cover_list(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, "cover")) != WP_OK)
+    if ((rc = upload_ints(ctx, cover_list(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, F.cover_cap, "cover")) !=
+        WP_OK)
         return rc;
     F.t = C.t;
     F.prev_valid = false;
@@ -240,9 +256,7 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
         if (G.patches.empty()) continue;
         G.patches.clear();
         if ((rc = wp_upload_tiles(ctx, G)) != WP_OK) return rc;
-        if ((rc = upload_ints(ctx, {}, G.ring_dev, G.nring, "ring")) != WP_OK) return rc;
-        if ((rc = upload_ints(ctx, {}, G.ringb_dev, G.nringb, "ring block")) != WP_OK) return rc;
-        if ((rc = upload_ints(ctx, {}, G.cover_dev, G.ncover, "cover")) != WP_OK) return rc;
+        G.nring = G.nringb = G.ncover = 0;
         G.prev_valid = false;
         G.flags_valid = false;
     }
@@ -310,12 +324,24 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
         return wp_fail(ctx, WP_EINVAL, "level %d has no finer level", level);
     Level &C = ctx->L[level], &F = ctx->L[level + 1];
     const int r = F.ratio;
+    // every cell a finer patch may cover lies in the bounding box of this
+    // level's patches: the host images below cover that window only
+    int wi0 = C.nx, wj0 = C.ny, wi1 = 0, wj1 = 0;
+    for (const wp_patch &p : C.patches) {
+        wi0 = std::min(wi0, p.ilo);
+        wj0 = std::min(wj0, p.jlo);
+        wi1 = std::max(wi1, p.ilo + p.nx);
+        wj1 = std::max(wj1, p.jlo + p.ny);
+    }
+    if (C.patches.empty()) wi0 = wj0 = wi1 = wj1 = 0;
+    const int ww = wi1 - wi0, wh = wj1 - wj0;
     std::vector<uint8_t> allowed;
-    wp_nesting_mask(C.patches, C.nx, C.ny, allowed);
+    wp_nesting_mask(C.patches, C.nx, C.ny, wi0, wj0, ww, wh, allowed);
+    auto in_window = [&](int i, int j) { return i >= wi0 && i < wi1 && j >= wj0 && j < wj1; };
     std::vector<wp_patch> boxes;
     if (patches) {
         if (npatches < 0) return wp_fail(ctx, WP_EINVAL, "npatches must be non-negative");
-        std::vector<uint8_t> used((size_t)C.nx * C.ny, 0);
+        std::vector<uint8_t> used((size_t)ww * wh, 0);
         for (int k = 0; k < npatches; ++k) {
             const wp_patch p = patches[k];
             if (p.nx < 1 || p.ny < 1 || p.ilo < 0 || p.jlo < 0 || p.ilo + p.nx > F.nx || p.jlo + p.ny > F.ny)
@@ -324,34 +350,35 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
                 return wp_fail(ctx, WP_EINVAL, "patch %d not aligned to the refinement ratio %d", k, r);
             for (int jc = p.jlo / r; jc < (p.jlo + p.ny) / r; ++jc)
                 for (int ic = p.ilo / r; ic < (p.ilo + p.nx) / r; ++ic) {
-                    uint8_t &u = used[(size_t)jc * C.nx + ic];
-                    if (u) return wp_fail(ctx, WP_EINVAL, "patch %d overlaps another", k);
-                    if (!allowed[(size_t)jc * C.nx + ic])
+                    if (!in_window(ic, jc))
                         return wp_fail(ctx, WP_EINVAL, "patch %d not properly nested in level %d", k, level);
-                    u = 1;
+                    const size_t w = (size_t)(jc - wj0) * ww + (ic - wi0);
+                    if (used[w]) return wp_fail(ctx, WP_EINVAL, "patch %d overlaps another", k);
+                    if (!allowed[w])
+                        return wp_fail(ctx, WP_EINVAL, "patch %d not properly nested in level %d", k, level);
+                    used[w] = 1;
                 }
             boxes.push_back(p);
         }
     } else {
         if (buffer < 0) return wp_fail(ctx, WP_EINVAL, "buffer must be non-negative");
         if (!C.flags_valid) return wp_fail(ctx, WP_ESTATE, "level %d has no flags (flag it first)", level);
-        std::vector<uint8_t> fl((size_t)C.nx * C.ny);
+        // the window's rows in one linear copy, then its columns
+        std::vector<uint8_t> rows((size_t)C.nx * wh), fl((size_t)ww * wh);
         int rcf;
-        if ((rcf = wp_host_copy(ctx, fl.data(), C.flags, fl.size(), false)) != WP_OK) return rcf;
+        if ((rcf = wp_host_copy(ctx, rows.data(), C.flags + (size_t)wj0 * C.nx, rows.size(), false)) != WP_OK)
+            return rcf;
+        for (int j = 0; j < wh; ++j)
+            std::copy_n(&rows[(size_t)j * C.nx + wi0], ww, &fl[(size_t)j * ww]);
         for (size_t k = 0; k < fl.size(); ++k) fl[k] = (fl[k] && allowed[k]) ? 1 : 0;
+        // flags outside the window are outside the nesting region, so the
+        // window's dilation restricted to it is the whole level's
         std::vector<uint8_t> dil;
-        wp_dilate(fl, C.nx, C.ny, buffer, dil);
+        wp_dilate(fl, ww, wh, buffer, dil);
         for (size_t k = 0; k < dil.size(); ++k) dil[k] = (dil[k] && allowed[k]) ? 1 : 0;
-        // first pass sizes the output
-        int n = 0;
-        int rc = wp_cluster(dil.data(), allowed.data(), C.nx, C.ny, 0.7, std::max(1, 64 / r), std::max(1, 8 / r),
-                            nullptr, 0, &n);
-        if (rc != WP_OK) return wp_fail(ctx, rc, "clustering failed");
-        boxes.resize(n);
-        rc = wp_cluster(dil.data(), allowed.data(), C.nx, C.ny, 0.7, std::max(1, 64 / r), std::max(1, 8 / r),
-                        boxes.data(), n, &n);
-        if (rc != WP_OK) return wp_fail(ctx, rc, "clustering failed");
-        for (wp_patch &p : boxes) p = wp_patch{p.ilo * r, p.jlo * r, p.nx * r, p.ny * r};
+        if (ww > 0 && wh > 0)
+            wp_cluster_boxes(dil.data(), allowed.data(), ww, wh, 0.7, std::max(1, 64 / r), std::max(1, 8 / r), boxes);
+        for (wp_patch &p : boxes) p = wp_patch{(p.ilo + wi0) * r, (p.jlo + wj0) * r, p.nx * r, p.ny * r};
     }
     return install(ctx, level + 1, boxes);
 }

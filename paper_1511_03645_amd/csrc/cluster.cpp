@@ -18,12 +18,37 @@
 
 namespace {
 
-struct Img {
+// Summed-area tables of the flag image and of its disallowed cells over a
+// window (i0, j0, nx, ny) of an image of row pitch `pitch`, so that the flag
+// count of any box, and so a box's row and column signatures, cost O(1) per
+// entry instead of a scan of the box.  Coordinates are window-relative.
+struct Sat {
     int nx, ny;
-    const uint8_t *f;    // flagged (already restricted to allowed)
-    const uint8_t *ok;   // allowed
-    bool flag(int i, int j) const { return f[(size_t)j * nx + i] != 0; }
-    bool allowed(int i, int j) const { return ok[(size_t)j * nx + i] != 0; }
+    std::vector<int> F, B;   // (nx + 1) x (ny + 1), entry (i, j) sums cells [0, i) x [0, j)
+    Sat(const uint8_t *f, const uint8_t *ok, size_t pitch, int i0, int j0, int nx_, int ny_) : nx(nx_), ny(ny_)
+    {
+        const size_t W = (size_t)nx + 1;
+        F.assign(W * (ny + 1), 0);
+        B.assign(W * (ny + 1), 0);
+        for (int j = 0; j < ny; ++j) {
+            const uint8_t *fr = f + (size_t)(j0 + j) * pitch + i0;
+            const uint8_t *okr = ok ? ok + (size_t)(j0 + j) * pitch + i0 : nullptr;
+            int rf = 0, rb = 0;
+            for (int i = 0; i < nx; ++i) {
+                const bool a = !okr || okr[i];
+                rf += a && fr[i];
+                rb += !a;
+                F[(j + 1) * W + i + 1] = F[j * W + i + 1] + rf;
+                B[(j + 1) * W + i + 1] = B[j * W + i + 1] + rb;
+            }
+        }
+    }
+    static int box(const std::vector<int> &S, size_t W, int i0, int j0, int i1, int j1)
+    {
+        return S[j1 * W + i1] - S[j0 * W + i1] - S[j1 * W + i0] + S[j0 * W + i0];
+    }
+    int flags(int i0, int j0, int i1, int j1) const { return box(F, (size_t)nx + 1, i0, j0, i1, j1); }
+    int bad(int i0, int j0, int i1, int j1) const { return box(B, (size_t)nx + 1, i0, j0, i1, j1); }
 };
 
 struct Key {
@@ -37,33 +62,24 @@ struct Key {
     }
 };
 
-void cluster_box(const Img &im, int i0, int j0, int w, int h, double eff_min, int maxside, int minside,
+void cluster_box(const Sat &im, int i0, int j0, int w, int h, double eff_min, int maxside, int minside,
                  std::vector<wp_patch> &out)
 {
     // shrink to the bounding box of the flags
-    int imin = i0 + w, imax = i0 - 1, jmin = j0 + h, jmax = j0 - 1;
-    long long nflag = 0;
-    for (int j = j0; j < j0 + h; ++j)
-        for (int i = i0; i < i0 + w; ++i)
-            if (im.flag(i, j)) {
-                imin = std::min(imin, i);
-                imax = std::max(imax, i);
-                jmin = std::min(jmin, j);
-                jmax = std::max(jmax, j);
-                ++nflag;
-            }
+    const long long nflag = im.flags(i0, j0, i0 + w, j0 + h);
     if (nflag == 0) return;
-    i0 = imin;
-    j0 = jmin;
-    w = imax - imin + 1;
-    h = jmax - jmin + 1;
-    bool all_ok = true;
-    for (int j = j0; j < j0 + h && all_ok; ++j)
-        for (int i = i0; i < i0 + w; ++i)
-            if (!im.allowed(i, j)) {
-                all_ok = false;
-                break;
-            }
+    {
+        int a = 0, b = w - 1, c = 0, d = h - 1;
+        while (im.flags(i0 + a, j0, i0 + a + 1, j0 + h) == 0) ++a;
+        while (im.flags(i0 + b, j0, i0 + b + 1, j0 + h) == 0) --b;
+        while (im.flags(i0, j0 + c, i0 + w, j0 + c + 1) == 0) ++c;
+        while (im.flags(i0, j0 + d, i0 + w, j0 + d + 1) == 0) --d;
+        i0 += a;
+        j0 += c;
+        w = b - a + 1;
+        h = d - c + 1;
+    }
+    const bool all_ok = im.bad(i0, j0, i0 + w, j0 + h) == 0;
     const double eff = (double)nflag / ((double)w * h);
     if (eff >= eff_min && w <= maxside && h <= maxside && all_ok) {
         out.push_back(wp_patch{i0, j0, w, h});
@@ -71,14 +87,10 @@ void cluster_box(const Img &im, int i0, int j0, int w, int h, double eff_min, in
     }
     const int ms = all_ok ? minside : 1;
     std::vector<long long> sig[2];
-    sig[0].assign(w, 0);
-    sig[1].assign(h, 0);
-    for (int j = 0; j < h; ++j)
-        for (int i = 0; i < w; ++i)
-            if (im.flag(i0 + i, j0 + j)) {
-                sig[0][i]++;
-                sig[1][j]++;
-            }
+    sig[0].resize(w);
+    sig[1].resize(h);
+    for (int i = 0; i < w; ++i) sig[0][i] = im.flags(i0 + i, j0, i0 + i + 1, j0 + h);
+    for (int j = 0; j < h; ++j) sig[1][j] = im.flags(i0, j0 + j, i0 + w, j0 + j + 1);
     const int len[2] = {w, h};
     bool found = false;
     int cut_ax = 0, cut_at = 0;
@@ -143,42 +155,92 @@ void cluster_box(const Img &im, int i0, int j0, int w, int h, double eff_min, in
 
 }  // namespace
 
-// Proper-nesting region of a level: cells of its patches that have no
-// neighbour (8-neighbourhood, inside the domain) outside every patch.
-void wp_nesting_mask(const std::vector<wp_patch> &patches, int nx, int ny, std::vector<uint8_t> &mask)
+// Proper-nesting region of a level within the window [wi0, wi0 + ww) x
+// [wj0, wj0 + wh), which must hold all of its patches: cells of the patches
+// that have no neighbour (8-neighbourhood, inside the domain nx x ny)
+// outside every patch.  mask is ww x wh.
+void wp_nesting_mask(const std::vector<wp_patch> &patches, int nx, int ny, int wi0, int wj0, int ww, int wh,
+                     std::vector<uint8_t> &mask)
 {
-    std::vector<uint8_t> inside((size_t)nx * ny, 0);
+    // "inside" on the window grown by one cell: outside the domain counts as
+    // inside (no neighbour there), domain cells outside the window are in no
+    // patch; then a 3 x 3 erosion, along rows and then along columns
+    const int pw = ww + 2, ph = wh + 2;
+    std::vector<uint8_t> in((size_t)pw * ph, 0), row((size_t)pw * ph, 0);
+    for (int b = 0; b < ph; ++b)
+        for (int a = 0; a < pw; ++a) {
+            const int i = wi0 - 1 + a, j = wj0 - 1 + b;
+            if (i < 0 || i >= nx || j < 0 || j >= ny) in[(size_t)b * pw + a] = 1;
+        }
     for (const auto &p : patches)
         for (int j = p.jlo; j < p.jlo + p.ny; ++j)
-            for (int i = p.ilo; i < p.ilo + p.nx; ++i) inside[(size_t)j * nx + i] = 1;
-    mask.assign((size_t)nx * ny, 0);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            if (!inside[(size_t)j * nx + i]) continue;
-            bool ok = true;
-            for (int dj = -1; dj <= 1 && ok; ++dj)
-                for (int di = -1; di <= 1; ++di) {
-                    const int a = i + di, b = j + dj;
-                    if (a >= 0 && a < nx && b >= 0 && b < ny && !inside[(size_t)b * nx + a]) {
-                        ok = false;
-                        break;
-                    }
-                }
-            mask[(size_t)j * nx + i] = ok;
+            std::fill_n(&in[(size_t)(j - wj0 + 1) * pw + (p.ilo - wi0 + 1)], p.nx, (uint8_t)1);
+    for (int b = 0; b < ph; ++b)
+        for (int a = 1; a < pw - 1; ++a) {
+            const uint8_t *x = &in[(size_t)b * pw + a];
+            row[(size_t)b * pw + a] = x[-1] & x[0] & x[1];
+        }
+    mask.assign((size_t)ww * wh, 0);
+    for (int b = 1; b < ph - 1; ++b)
+        for (int a = 1; a < pw - 1; ++a) {
+            const size_t k = (size_t)b * pw + a;
+            mask[(size_t)(b - 1) * ww + (a - 1)] = in[k] & row[k - pw] & row[k] & row[k + pw];
         }
 }
 
-// Box dilation by k cells (flag buffering around flagged cells).
+// Box dilation by k cells (flag buffering around flagged cells) of an
+// nx x ny image: a running count along each row, then along each column.
 void wp_dilate(const std::vector<uint8_t> &f, int nx, int ny, int k, std::vector<uint8_t> &out)
 {
     out = f;
     if (k <= 0) return;
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            if (!f[(size_t)j * nx + i]) continue;
-            for (int b = std::max(j - k, 0); b <= std::min(j + k, ny - 1); ++b)
-                for (int a = std::max(i - k, 0); a <= std::min(i + k, nx - 1); ++a) out[(size_t)b * nx + a] = 1;
-        }
+    std::vector<uint8_t> rows((size_t)nx * ny, 0);
+    std::vector<int> pre(std::max(nx, ny) + 1);
+    for (int j = 0; j < ny; ++j) {
+        const uint8_t *r = &f[(size_t)j * nx];
+        pre[0] = 0;
+        for (int i = 0; i < nx; ++i) pre[i + 1] = pre[i] + (r[i] != 0);
+        for (int i = 0; i < nx; ++i)
+            rows[(size_t)j * nx + i] = pre[std::min(i + k + 1, nx)] - pre[std::max(i - k, 0)] > 0;
+    }
+    for (int i = 0; i < nx; ++i) {
+        pre[0] = 0;
+        for (int j = 0; j < ny; ++j) pre[j + 1] = pre[j] + rows[(size_t)j * nx + i];
+        for (int j = 0; j < ny; ++j)
+            out[(size_t)j * nx + i] = pre[std::min(j + k + 1, ny)] - pre[std::max(j - k, 0)] > 0;
+    }
+}
+
+// The boxes of an nx x ny flag image restricted to `allowed` (see wp_cluster).
+// Clustering starts by shrinking the whole image to the bounding box of its
+// (allowed) flags, so the tables cover that box only.
+void wp_cluster_boxes(const uint8_t *flags, const uint8_t *allowed, int nx, int ny, double efficiency, int maxside,
+                      int minside, std::vector<wp_patch> &out)
+{
+    out.clear();
+    int a = nx, b = ny, c = -1, d = -1;
+    for (int j = 0; j < ny; ++j) {
+        const uint8_t *fr = flags + (size_t)j * nx;
+        const uint8_t *okr = allowed ? allowed + (size_t)j * nx : nullptr;
+        int lo = -1, hi = -1;
+        for (int i = 0; i < nx; ++i)
+            if (fr[i] && (!okr || okr[i])) {
+                if (lo < 0) lo = i;
+                hi = i;
+            }
+        if (lo < 0) continue;
+        a = std::min(a, lo);
+        c = std::max(c, hi);
+        b = std::min(b, j);
+        d = j;
+    }
+    if (c < 0) return;
+    const Sat im(flags, allowed, (size_t)nx, a, b, c - a + 1, d - b + 1);
+    cluster_box(im, 0, 0, c - a + 1, d - b + 1, efficiency, maxside, minside, out);
+    for (wp_patch &p : out) {
+        p.ilo += a;
+        p.jlo += b;
+    }
 }
 
 extern "C" int wp_cluster(const uint8_t *flags, const uint8_t *allowed, int nx, int ny, double efficiency,
@@ -186,13 +248,8 @@ extern "C" int wp_cluster(const uint8_t *flags, const uint8_t *allowed, int nx, 
 {
     if (!flags || nx < 1 || ny < 1 || maxside < 1 || minside < 1 || !npatches || (cap > 0 && !out))
         return WP_EINVAL;
-    std::vector<uint8_t> ok(allowed ? allowed : flags, (allowed ? allowed : flags) + (size_t)nx * ny);
-    if (!allowed) std::fill(ok.begin(), ok.end(), 1);
-    std::vector<uint8_t> f((size_t)nx * ny);
-    for (size_t k = 0; k < f.size(); ++k) f[k] = (flags[k] && ok[k]) ? 1 : 0;
-    Img im{nx, ny, f.data(), ok.data()};
     std::vector<wp_patch> boxes;
-    cluster_box(im, 0, 0, nx, ny, efficiency, maxside, minside, boxes);
+    wp_cluster_boxes(flags, allowed, nx, ny, efficiency, maxside, minside, boxes);
     *npatches = (int)boxes.size();
     for (int k = 0; k < (int)boxes.size() && k < cap; ++k) out[k] = boxes[k];
     return WP_OK;

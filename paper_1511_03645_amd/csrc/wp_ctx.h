@@ -51,6 +51,9 @@ struct Level {
     long long nringb = 0;
     int *cover_dev = nullptr;
     long long ncover = 0;
+    // allocated sizes (bytes) of the tables above: a smaller table is written
+    // into the same block
+    size_t tiles_cap = 0, ftiles_cap = 0, ring_cap = 0, ringb_cap = 0, cover_cap = 0;
 };
 
 struct wp_ctx {
@@ -129,6 +132,9 @@ struct wp_ctx {
     // WP_PIN_CAP, released by wp_destroy
     void *pin = nullptr;
     size_t pin_bytes = 0;
+    // new fine cells of a regrid (device list, reused)
+    int *fresh_dev = nullptr;
+    size_t fresh_cap = 0;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };
 
@@ -145,6 +151,9 @@ inline int wp_fail_get(const wp_ctx *ctx, int code, const char *what)
 int wp_host_copy2d(wp_ctx *ctx, void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t rows,
                    bool to_device);
 int wp_host_copy(wp_ctx *ctx, void *dst, const void *src, size_t bytes, bool to_device);
+// Copy a host table to a device block of `cap` bytes, first replacing the
+// block by one half as large again as needed when it is too small.
+int wp_upload(wp_ctx *ctx, const void *src, size_t bytes, void *&dev, size_t &cap, const char *what);
 void *wp_dalloc(wp_ctx *ctx, size_t bytes);
 void wp_dfree(wp_ctx *ctx, void *p);
 std::vector<wp::Tile> wp_make_tiles(const std::vector<wp_patch> &patches, int inst, int rows, int width, bool xcd_order);
@@ -177,5 +186,8 @@ int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec);
 int wp_graph_launch(wp_ctx *ctx, hipGraphExec_t exec);
 // refinement (amr_host.hip, cluster.cpp)
 int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t);
-void wp_nesting_mask(const std::vector<wp_patch> &patches, int nx, int ny, std::vector<uint8_t> &mask);
+void wp_nesting_mask(const std::vector<wp_patch> &patches, int nx, int ny, int wi0, int wj0, int ww, int wh,
+                     std::vector<uint8_t> &mask);
 void wp_dilate(const std::vector<uint8_t> &f, int nx, int ny, int k, std::vector<uint8_t> &out);
+void wp_cluster_boxes(const uint8_t *flags, const uint8_t *allowed, int nx, int ny, double efficiency, int maxside,
+                      int minside, std::vector<wp_patch> &out);

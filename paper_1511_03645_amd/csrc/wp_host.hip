@@ -129,17 +129,28 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
     std::vector<Tile> out;
     out.reserve(tiles.size());
     const int *bc = ctx->prob.bc;
+    // a level cell's material is that of the level-0 cell containing it, so
+    // the footprint's materials are those of the level-0 rows and columns
+    // its resolved rows and columns fall in
+    const int r = lv.nx / ctx->grid.nx0, ry = lv.ny / ctx->grid.ny0;
+    std::vector<int> cols, rws;
     for (auto &t : tiles) {
+        cols.clear();
+        rws.clear();
+        for (int i = t.i0 - halo; i <= t.i0 + t.ni + halo - 1; ++i) cols.push_back(host_resolve(i, lv.nx, bc[0], bc[1]) / r);
+        for (int j = t.j0 - halo; j <= t.j0 + t.nj + halo - 1; ++j) rws.push_back(host_resolve(j, lv.ny, bc[2], bc[3]) / ry);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        std::sort(rws.begin(), rws.end());
+        rws.erase(std::unique(rws.begin(), rws.end()), rws.end());
         int m0 = -1;
         bool uni = true;
-        for (int j = t.j0 - halo; j <= t.j0 + t.nj + halo - 1 && uni; ++j) {
-            const int jj = host_resolve(j, lv.ny, bc[2], bc[3]);
-            for (int i = t.i0 - halo; i <= t.i0 + t.ni + halo - 1; ++i) {
-                const int m = wp_level_mat(ctx, lv, host_resolve(i, lv.nx, bc[0], bc[1]), jj);
+        for (size_t b = 0; b < rws.size() && uni; ++b)
+            for (size_t a = 0; a < cols.size(); ++a) {
+                const int m = ctx->mat0[(size_t)rws[b] * ctx->grid.nx0 + cols[a]];
                 if (m0 < 0) m0 = m;
                 else if (m != m0) { uni = false; break; }
             }
-        }
         t.mat = uni ? m0 : -1;
         if (uni) {
             out.push_back(t);
@@ -225,19 +236,18 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
     if ((rc = upload_pair_tiles(ctx, lv)) != WP_OK) return rc;
     // flag / reduction tiles: larger blocks of whole patches
     std::vector<Tile> ft = wp_make_tiles(lv.patches, 0, 16, 64, false);
-    if (lv.tiles_dev) wp_dfree(ctx, lv.tiles_dev);
-    if (lv.ftiles_dev) wp_dfree(ctx, lv.ftiles_dev);
-    lv.tiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, lv.tiles_host.size()));
-    lv.ftiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, ft.size()));
-    if (!lv.tiles_dev || !lv.ftiles_dev) return wp_fail(ctx, WP_ENOMEM, "tile table allocation failed");
-    ++ctx->topo_gen;   // captured sequences hold the old table pointers
+    // captured sequences hold the old table pointers and sizes (the new
+    // tables may reuse the blocks; the copies follow earlier work on the stream)
+    ++ctx->topo_gen;
     lv.ntiles = (int)lv.tiles_host.size();
     lv.nftiles = (int)ft.size();
-    if (lv.ntiles && hipMemcpy(lv.tiles_dev, lv.tiles_host.data(), sizeof(Tile) * lv.ntiles, hipMemcpyHostToDevice) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "tile upload failed");
-    if (lv.nftiles && hipMemcpy(lv.ftiles_dev, ft.data(), sizeof(Tile) * lv.nftiles, hipMemcpyHostToDevice) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "tile upload failed");
-    return WP_OK;
+    void *t = lv.tiles_dev, *f = lv.ftiles_dev;
+    rc = wp_upload(ctx, lv.tiles_host.data(), sizeof(Tile) * lv.ntiles, t, lv.tiles_cap, "tile table");
+    lv.tiles_dev = (Tile *)t;
+    if (rc != WP_OK) return rc;
+    rc = wp_upload(ctx, ft.data(), sizeof(Tile) * lv.nftiles, f, lv.ftiles_cap, "flag tile table");
+    lv.ftiles_dev = (Tile *)f;
+    return rc;
 }
 
 int wp_default_rows(const wp_ctx *ctx, const Level &lv)
@@ -559,6 +569,18 @@ int wp_host_copy2d(wp_ctx *ctx, void *dst, size_t dpitch, const void *src, size_
         if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "host transfer: %s", hipGetErrorString(e));
     }
     return WP_OK;
+}
+
+int wp_upload(wp_ctx *ctx, const void *src, size_t bytes, void *&dev, size_t &cap, const char *what)
+{
+    if (bytes > cap || !dev) {
+        if (dev) wp_dfree(ctx, dev);
+        const size_t want = std::max(bytes + bytes / 2, (size_t)256);
+        dev = wp_dalloc(ctx, want);
+        cap = dev ? want : 0;
+        if (!dev) return wp_fail(ctx, WP_ENOMEM, "%s allocation failed", what);
+    }
+    return wp_host_copy(ctx, dev, src, bytes, true);
 }
 
 int wp_host_copy(wp_ctx *ctx, void *dst, const void *src, size_t bytes, bool to_device)
