@@ -25,6 +25,10 @@ Pieces and the passages of Davis & LeVeque (arXiv:1511.03645) they follow:
                        component to the face neighbours (Sec. 5.2.4, "pressure
                        flagging") and the sea-surface departure from sea level
                        (Sec. 5.3, "surface flagging").
+* ``richardson_estimate``/``richardson_flag`` – the error estimate the paper
+                       names as the next step (Sec. 1, Future Work): Richardson
+                       extrapolation between the grid and its 2x coarsening,
+                       alone or weighted by the adjoint as the flag is.
 * ``amr``            – coarse/fine transfer, Berger-Oliger stepping and
                        Berger-Rigoutsos clustering (Sec. 3), in ``oracle.amr``.
 """
@@ -371,3 +375,56 @@ def surface_flag(eta, tol):
     eta = h + B the surface elevation and sea level at 0."""
     d = np.abs(np.asarray(eta, dtype=np.float64))
     return (d > tol).astype(np.uint8), d
+
+
+def coarsen2(q):
+    """Mean of each 2 x 2 block of cells of q ([m][ny][nx], even sizes),
+    summed as ((lower-left + lower-right) + (upper-left + upper-right)) / 4."""
+    q = np.asarray(q, dtype=np.float64)
+    return ((q[:, 0::2, 0::2] + q[:, 0::2, 1::2]) + (q[:, 1::2, 0::2] + q[:, 1::2, 1::2])) * 0.25
+
+
+def coarse_config(cfg):
+    """The 2D acoustics problem on the 2x coarser grid: each coarse cell takes
+    the media of its lower-left fine cell."""
+    c = dict(cfg)
+    c["nx"], c["ny"] = cfg["nx"] // 2, cfg["ny"] // 2
+    c["dx"], c["dy"] = 2 * cfg["dx"], 2 * cfg["dy"]
+    c["rho"] = np.asarray(cfg["rho"])[0::2, 0::2]
+    c["K"] = np.asarray(cfg["K"])[0::2, 0::2]
+    return c
+
+
+def richardson_estimate(cfg, q, dt):
+    """Richardson estimate of the local error of one step of size dt, per
+    coarse cell (Sec. 1 names the estimator; the scaling is the standard one):
+    for a method of order p the one-step error is about C dt^(p+1) at a fixed
+    Courant number, so one step of 2 dt on the 2x coarser grid errs by
+    2^(p+1) C dt^(p+1) and two fine steps by 2 C dt^(p+1); their difference
+    over 2^(p+1) - 2 estimates the error of one fine step."""
+    p = cfg["order"]
+    fine, _, _ = run(cfg, "acoustics_fwd", q, 2, dt=dt)
+    coarse, _, _ = run(coarse_config(cfg), "acoustics_fwd", coarsen2(q), 1, dt=2 * dt)
+    return (coarse - coarsen2(fine)) / (2 ** (p + 1) - 2)
+
+
+def richardson_measure(E, snaps=None, n_lo=0, n_hi=-1):
+    """Per fine cell: max_k |E_k| of its 2 x 2 parent (snaps None), or the
+    adjoint weighting max over snapshots n_lo..n_hi of |qhat_n(x)^T E(parent)|
+    (the flag measure of Sec. 4 with the error in place of q)."""
+    Ef = np.repeat(np.repeat(np.asarray(E, dtype=np.float64), 2, axis=1), 2, axis=2)
+    if snaps is None:
+        return np.max(np.abs(Ef), axis=0)
+    return flag_measure(Ef, snaps, n_lo, n_hi)
+
+
+def richardson_flag(cfg, q, dt, tol, snaps=None, t=0.0, t_s=0.0, t_f=0.0, ds=1.0):
+    """Flags (iff the measure exceeds tol), the measure, and the estimate."""
+    E = richardson_estimate(cfg, q, dt)
+    if snaps is None:
+        m = richardson_measure(E)
+    else:
+        n_lo, n_hi = snapshot_window(t, t_s, t_f, ds, len(snaps))
+        m = richardson_measure(E, snaps, n_lo, n_hi)
+    return (m > tol).astype(np.uint8), m, E
+

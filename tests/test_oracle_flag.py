@@ -276,3 +276,74 @@ def test_surface_flag_is_strict_on_the_departure_from_sea_level():
     f, d = oracle.surface_flag(eta, 0.1)
     assert f.tolist() == [[0, 0, 1, 1, 0]]
     assert np.array_equal(d, np.abs(eta))
+
+
+# ---- Richardson error estimate (Sec. 1 and Future Work: the estimator the paper names as next) ----
+
+def _wave_config(n, limiter=0):
+    """y-invariant 2D acoustics in a uniform medium (rho = K = 1, so c = Z = 1)
+    on [-2, 2] x a strip four cells high, extrapolation on every side."""
+    return dict(kind="acoustics2d", nx=n, ny=4, xlo=-2.0, xhi=2.0, ylo=0.0, yhi=16.0 / n, dx=4.0 / n, dy=4.0 / n,
+                rho=np.ones((4, n)), K=np.ones((4, n)), bc=[0, 0, 0, 0], order=2, limiter=limiter, transverse=1,
+                g=9.81)
+
+
+def _wave_averages(n, t, w=0.3, x0=-0.5):
+    """Exact cell averages of the right-going wave p = u = exp(-((x - x0 - t)/w)^2)
+    (closed form through erf), v = 0."""
+    edges = np.array([-2.0 + 4.0 * k / n for k in range(n + 1)]) - x0 - t
+    F = np.array([w * math.sqrt(math.pi) / 2 * math.erf(e / w) for e in edges])
+    a = np.diff(F) / (4.0 / n)
+    q = np.zeros((3, 4, n))
+    q[0] = a
+    q[1] = a
+    return q
+
+
+def test_coarsen2_is_the_block_mean():
+    q = np.arange(3 * 4 * 6, dtype=np.float64).reshape(3, 4, 6) * 0.5
+    c = oracle.coarsen2(q)
+    assert c.shape == (3, 2, 3)
+    assert c[1, 1, 2] == np.mean(q[1, 2:4, 4:6])
+    assert np.array_equal(c, q.reshape(3, 2, 2, 3, 2).mean(axis=(2, 4)))
+
+
+def test_richardson_estimate_vanishes_on_a_constant_state():
+    cfg = _wave_config(32)
+    q = np.stack([np.full((4, 32), 0.75), np.full((4, 32), -0.25), np.zeros((4, 32))])
+    assert not oracle.richardson_estimate(cfg, q, 0.8 * cfg["dx"]).any()
+
+
+def test_richardson_estimate_matches_the_true_one_step_error():
+    """Unlimited second-order scheme on a smooth travelling wave: the estimate
+    equals the actual error of one fine step from exact averages (coarsened),
+    to 6% at 64 cells and 2% at 128, and shrinks about 2^(p+1) = 8 times per
+    halving of h.  A wrong scaling of the coarse/fine difference (any divisor
+    other than 2^(p+1) - 2) misses by a constant factor."""
+    errs, sizes = [], []
+    for n in (64, 128):
+        cfg = _wave_config(n)
+        dt = 0.8 * cfg["dx"]
+        q0 = _wave_averages(n, 0.0)
+        E = oracle.richardson_estimate(cfg, q0, dt)
+        one, _, _ = oracle.run(cfg, "acoustics_fwd", q0, 1, dt=dt)
+        true = oracle.coarsen2(one - _wave_averages(n, dt))
+        errs.append(np.abs(E - true).max() / np.abs(true).max())
+        sizes.append(np.abs(E).max())
+    assert errs[0] < 0.06 and errs[1] < 0.02
+    assert 7.0 < sizes[0] / sizes[1] < 8.5
+
+
+def test_richardson_measure_weights_the_parent_estimate():
+    """Brute force: every fine cell takes its 2 x 2 parent's estimate, and the
+    weighted measure is max over the snapshots of |qhat . E|."""
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((3, 2, 3))
+    snaps = rng.standard_normal((4, 3, 4, 6))
+    m0 = oracle.richardson_measure(E)
+    m1 = oracle.richardson_measure(E, snaps, 1, 2)
+    for j in range(4):
+        for i in range(6):
+            e = E[:, j // 2, i // 2]
+            assert m0[j, i] == max(abs(x) for x in e)
+            assert m1[j, i] == max(abs(float(np.sum(snaps[n, :, j, i] * e))) for n in (1, 2))
