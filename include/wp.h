@@ -222,6 +222,27 @@ int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, do
 int wp_flag_difference(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged);
 int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged);
 
+/* Richardson error estimate (the estimator Sec. 1 describes, and that the
+ * closing Future Work section proposes to weight by the adjoint) on level 0
+ * of a 2D acoustics instance with even nx0, ny0, from its current state:
+ * two steps of dt on the same grid and one step of 2 dt on the 2x coarser
+ * grid (each coarse cell takes the medium of its lower-left fine cell,
+ * the state its 2 x 2 block mean), and per coarse cell and component
+ * E = (coarse result - block mean of the fine result) / (2^(p+1) - 2), p the
+ * problem's order: for a method of order p this estimates the error of one
+ * step of dt.  Every fine cell is measured with its parent's E: weighted = 0
+ * takes max_k |E_k|; weighted = 1 takes max |qhat_n(x)^T E| over the
+ * snapshots of the window of wp_flag_adjoint at time t.  A cell is flagged
+ * iff the measure exceeds tol.  flags and *nflagged as for wp_flag_adjoint
+ * (wp_regrid clusters them); estimate (optional, host, [m][ny0/2][nx0/2]
+ * FP64) receives E.  The state and time of the instance are unchanged (the
+ * steps run on internal copies of the problem, created on the first call).
+ * WP_EINVAL for another level or kind, odd sizes, dt <= 0 or tol < 0;
+ * WP_ECFL as for a step of dt; WP_ERANGE as for wp_flag_adjoint when
+ * weighted. */
+int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
+                       double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate);
+
 /* The forward run with adjoint-guided flagging (Sec. 4; Sec. 5.1.2) on a
  * single-level instance: nsteps steps of size dt from the current state and
  * time t0, with the flag of wp_flag_adjoint(0, tol, t, t_s, t_f) evaluated at
@@ -245,8 +266,8 @@ int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_every, doubl
  * level's patches with all eight neighbours inside the domain also in them,
  * i.e. level's patches shrunk by one cell except along the physical
  * boundary).  patches == NULL: the flags of `level` from the last
- * wp_flag_adjoint, wp_flag_difference or wp_flag_surface on it,
- * restricted to that nesting region, dilated by `buffer` cells and
+ * wp_flag_adjoint, wp_flag_difference, wp_flag_surface or
+ * wp_flag_richardson on it, restricted to that nesting region, dilated by `buffer` cells and
  * restricted again, clustered by wp_cluster with
  * efficiency 0.7, sides of at most max(1, 64 / ratio) and at least
  * max(1, 8 / ratio) level cells, then refined by the ratio.  Cells of the new

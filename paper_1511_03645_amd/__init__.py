@@ -95,6 +95,8 @@ _SIGS = {
     "wp_flag_adjoint": (_I, [_P, _I, _D, _D, _D, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
     "wp_flag_difference": (_I, [_P, _I, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
     "wp_flag_surface": (_I, [_P, _I, _D, _P, _I, ctypes.POINTER(ctypes.c_int64)]),
+    "wp_flag_richardson": (_I, [_P, _I, _D, _I, _D, _D, _D, _D, _P, _I, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(_D)]),
     "wp_regrid": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, _I]),
     "wp_get_patches": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
     "wp_forward_flagged": (_I, [_P, _D, _I, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int64),
@@ -371,6 +373,19 @@ class WavePatch:
     def flag_surface(self, level, tol, want_flags=True, want_count=True):
         """wp_flag_surface (shallow water: |eta| above sea level 0)."""
         return self._flag_standard(lib().wp_flag_surface, level, tol, want_flags, want_count)
+
+    def flag_richardson(self, dt, tol, weighted=False, t=0.0, t_s=0.0, t_f=0.0, level=0, want_flags=True,
+                        want_count=True, want_estimate=False):
+        """wp_flag_richardson: (flags, count, estimate [m][ny/2][nx/2] or None)."""
+        nx, ny, _ = self.level_info(level)
+        flags = np.zeros((ny, nx), dtype=np.uint8) if want_flags else None
+        est = np.zeros((self.m, ny // 2, nx // 2)) if want_estimate else None
+        n = ctypes.c_int64()
+        p = ctypes.c_void_p(flags.ctypes.data) if want_flags else ctypes.c_void_p()
+        e = est.ctypes.data_as(ctypes.POINTER(_D)) if want_estimate else None
+        self._check(lib().wp_flag_richardson(self.h, level, dt, int(weighted), tol, t, t_s, t_f, p, 0,
+                                             ctypes.byref(n) if want_count else None, e))
+        return flags, (n.value if want_count else None), est
 
     def forward_flagged(self, dt, nsteps, flag_every, tol, t_s, t_f, want_counts=True, want_times=False):
         """wp_forward_flagged: (flagged cells per flag event or None,

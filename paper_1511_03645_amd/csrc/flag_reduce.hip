@@ -1,7 +1,10 @@
 // Adjoint inner-product flag kernel (Davis & LeVeque Sec. 4 and Sec. 5.1.2),
 // the two comparison flags of Sec. 5.2.4 and 5.3 (undivided differences,
-// sea-surface departure), and compensated FP64 reductions for the functional
-// J (eq. J_general) and the inner-product integral (eq. q_equality / eq. J).
+// sea-surface departure), the Richardson error estimate and its flag (Sec. 1
+// and Future Work), and compensated FP64 reductions for the functional J
+// (eq. J_general) and the inner-product integral (eq. q_equality / eq. J).
+#include <algorithm>
+
 #include "march_common.h"
 
 namespace wp {
@@ -210,6 +213,86 @@ __global__ __launch_bounds__(256) void surface_flag_kernel(const TE *__restrict_
     if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
 }
 
+// Richardson error estimate (the estimator named in Sec. 1 and in the
+// closing Future Work): the 2 x 2 block mean of a fine canvas, summed as
+// ((lower-left + lower-right) + (upper-left + upper-right)) / 4 in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void coarsen2_kernel(const T *__restrict__ f, long long fcs, int nx,
+                                                       T *__restrict__ c, long long ccs, int NX, int NY, int m)
+{
+    const long long n = (long long)NX * NY;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int I = (int)(k % NX), J = (int)(k / NX);
+        const long long a = (long long)(2 * J) * nx + 2 * I;
+        for (int q = 0; q < m; ++q) {
+            const T *fq = f + q * fcs;
+            const double s = ((double)fq[a] + (double)fq[a + 1]) + ((double)fq[a + nx] + (double)fq[a + nx + 1]);
+            c[q * ccs + k] = (T)(s * 0.25);
+        }
+    }
+}
+
+// E = (coarse step of 2 dt - block mean of two fine steps) / denom, FP64,
+// per coarse cell and component ([m][NY][NX]).
+template <typename T>
+__global__ __launch_bounds__(256) void richardson_estimate_kernel(const T *__restrict__ coarse, long long ccs,
+                                                                  const T *__restrict__ fine, long long fcs, int nx,
+                                                                  int NX, int NY, int m, double denom,
+                                                                  double *__restrict__ E)
+{
+    const long long n = (long long)NX * NY;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int I = (int)(k % NX), J = (int)(k / NX);
+        const long long a = (long long)(2 * J) * nx + 2 * I;
+        for (int q = 0; q < m; ++q) {
+            const T *fq = fine + q * fcs;
+            const double s = ((double)fq[a] + (double)fq[a + 1]) + ((double)fq[a + nx] + (double)fq[a + nx + 1]);
+            E[q * n + k] = ((double)coarse[q * ccs + k] - s * 0.25) / denom;
+        }
+    }
+}
+
+// Flag of a fine cell from its parent's estimate: max_k |E_k| (snaps null),
+// or max over snapshots n_lo..n_hi of |qhat_n(x) . E(parent)| with qhat on
+// the fine grid (the adjoint grid).  Tiles and threads as flag_kernel.
+template <typename TH>
+__global__ __launch_bounds__(256) void richardson_flag_kernel(const double *__restrict__ E, int NX, int NY, int m,
+                                                              int nx, const TH *__restrict__ snaps, long long sstride,
+                                                              long long hcs, int n_lo, int n_hi, double tol,
+                                                              const Tile *__restrict__ tiles,
+                                                              uint8_t *__restrict__ flags,
+                                                              unsigned long long *__restrict__ count)
+{
+    const Tile tl = tiles[blockIdx.x];
+    const int x = threadIdx.x & 63, y = threadIdx.x >> 6;
+    const long long nc = (long long)NX * NY;
+    unsigned long long local = 0;
+    if (x < tl.ni) {
+        const int i = tl.i0 + x;
+        for (int j = tl.j0 + y; j < tl.j0 + tl.nj; j += 4) {
+            const long long idx = (long long)j * nx + i, par = (long long)(j / 2) * NX + i / 2;
+            double e[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < m; ++c) e[c] = E[c * nc + par];
+            double best = 0.0;
+            if (!snaps) {
+                for (int c = 0; c < m; ++c) best = fmax(best, fabs(e[c]));
+            } else {
+                for (int n = n_lo; n <= n_hi; ++n) {
+                    const TH *sn = snaps + (long long)n * sstride;
+                    double ip = (double)sn[idx] * e[0];
+                    for (int c = 1; c < m; ++c) ip = ip + (double)sn[idx + c * hcs] * e[c];
+                    best = fmax(best, fabs(ip));
+                }
+            }
+            const uint8_t f = best > tol ? 1 : 0;
+            flags[idx] = f;
+            local += f;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+}
+
 // ---------------------------------------------------------------------------
 // compensated reductions
 // ---------------------------------------------------------------------------
@@ -385,6 +468,32 @@ void launch_flag_surface(const TE *eta, int nx, double tol, const Tile *tiles, i
     hipLaunchKernelGGL((surface_flag_kernel<TE>), dim3(ntiles), dim3(256), 0, s, eta, nx, tol, tiles, flags, count);
 }
 
+template <typename T>
+void launch_coarsen2(const T *f, long long fcs, int nx, T *c, long long ccs, int NX, int NY, int m, hipStream_t s)
+{
+    const long long n = (long long)NX * NY;
+    if (n <= 0) return;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((coarsen2_kernel<T>), dim3(blocks), dim3(256), 0, s, f, fcs, nx, c, ccs, NX, NY, m);
+}
+
+template <typename T>
+void launch_richardson(const T *coarse, long long ccs, const T *fine, long long fcs, int nx, int NX, int NY, int m,
+                       double denom, double *E, const void *snaps, long long sstride, long long hcs, int n_lo,
+                       int n_hi, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
+                       unsigned long long *count, hipStream_t s)
+{
+    const long long n = (long long)NX * NY;
+    if (n > 0) {
+        const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL((richardson_estimate_kernel<T>), dim3(blocks), dim3(256), 0, s, coarse, ccs, fine, fcs, nx,
+                           NX, NY, m, denom, E);
+    }
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((richardson_flag_kernel<T>), dim3(ntiles), dim3(256), 0, s, E, NX, NY, m, nx,
+                       (const T *)snaps, sstride, hcs, n_lo, n_hi, tol, tiles, flags, count);
+}
+
 void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s)
 {
     if (n <= 0) return;
@@ -420,5 +529,14 @@ template void launch_flag_surface<double>(const double *, int, double, const Til
                                           unsigned long long *, hipStream_t);
 template void launch_flag_surface<float>(const float *, int, double, const Tile *, int, uint8_t *,
                                          unsigned long long *, hipStream_t);
+
+template void launch_coarsen2<double>(const double *, long long, int, double *, long long, int, int, int, hipStream_t);
+template void launch_coarsen2<float>(const float *, long long, int, float *, long long, int, int, int, hipStream_t);
+template void launch_richardson<double>(const double *, long long, const double *, long long, int, int, int, int,
+                                        double, double *, const void *, long long, long long, int, int, double,
+                                        const Tile *, int, uint8_t *, unsigned long long *, hipStream_t);
+template void launch_richardson<float>(const float *, long long, const float *, long long, int, int, int, int, double,
+                                       double *, const void *, long long, long long, int, int, double, const Tile *,
+                                       int, uint8_t *, unsigned long long *, hipStream_t);
 
 }  // namespace wp

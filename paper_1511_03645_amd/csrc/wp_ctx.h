@@ -135,6 +135,11 @@ struct wp_ctx {
     // new fine cells of a regrid (device list, reused)
     int *fresh_dev = nullptr;
     size_t fresh_cap = 0;
+    // Richardson estimate: single-level copies of the problem at this
+    // resolution and at half of it (created on first use), and the estimate
+    wp_ctx *rich[2] = {nullptr, nullptr};
+    double *richE = nullptr;
+    size_t richE_cap = 0;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };
 

@@ -468,6 +468,7 @@ extern "C" void wp_destroy(wp_ctx *ctx)
     if (ctx->ff_exec) (void)hipGraphExecDestroy(ctx->ff_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->pin) (void)hipHostFree(ctx->pin);
+    for (wp_ctx *h : ctx->rich) wp_destroy(h);
     std::vector<void *> all = ctx->owned;
     for (void *p : all) wp_dfree(ctx, p);
     delete ctx;
@@ -1294,6 +1295,102 @@ extern "C" int wp_flag_difference(wp_ctx *ctx, int level, double tol, uint8_t *f
 extern "C" int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged)
 {
     return flag_standard(ctx, level, true, tol, flags, on_device, nflagged);
+}
+
+// Richardson error estimate and flag (the estimator that Sec. 1 describes
+// and the Future Work section proposes to weight by the adjoint).  Two steps
+// of dt from the level-0 state on a copy of the problem at the same
+// resolution, one step of 2 dt from its 2 x 2 block means on a copy at half
+// the resolution (each coarse cell with the medium of its lower-left fine
+// cell); E = (coarse - block mean of fine) / (2^(p+1) - 2).
+static int rich_helper(wp_ctx *ctx, int which, wp_ctx *&out)
+{
+    if (out) return wp_set_stream(out, ctx->stream);
+    const int nx = ctx->grid.nx0, ny = ctx->grid.ny0;
+    const int f = which == 0 ? 1 : 2;
+    const int hx = nx / f, hy = ny / f;
+    std::vector<double> rho((size_t)hx * hy), K((size_t)hx * hy);
+    for (int j = 0; j < hy; ++j)
+        for (int i = 0; i < hx; ++i) {
+            const uint8_t m = ctx->mat0[(size_t)(f * j) * nx + f * i];
+            rho[(size_t)j * hx + i] = ctx->rho[m];
+            K[(size_t)j * hx + i] = ctx->K[m];
+        }
+    wp_grid g = ctx->grid;
+    g.nx0 = hx;
+    g.ny0 = hy;
+    g.num_levels = 1;
+    const wp_coefficients coef{rho.data(), K.data(), nullptr};
+    const int rc = wp_create(&ctx->prob, &coef, &g, ctx->has_alloc ? &ctx->alloc : nullptr, ctx->stream, &out);
+    if (rc != WP_OK) return wp_fail(ctx, rc, "Richardson estimate: helper instance: %s", wp_status_string(rc));
+    return WP_OK;
+}
+
+extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
+                                  double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate)
+{
+    if (!ctx) return WP_EINVAL;
+    if (level != 0) return wp_fail(ctx, WP_EINVAL, "the Richardson estimate is taken on level 0");
+    if (!ctx->is_acoustics || !ctx->kind2d) return wp_fail(ctx, WP_EINVAL, "the Richardson estimate is for 2D acoustics");
+    if (ctx->grid.nx0 % 2 || ctx->grid.ny0 % 2 || ctx->grid.nx0 < 4 || ctx->grid.ny0 < 4)
+        return wp_fail(ctx, WP_EINVAL, "the Richardson estimate needs even grid sizes of at least 4");
+    if (!(dt > 0.0)) return wp_fail(ctx, WP_EINVAL, "dt must be positive");
+    if (!(tol >= 0.0)) return wp_fail(ctx, WP_EINVAL, "tolerance must be non-negative");
+    int rc, n_lo = 0, n_hi = -1;
+    if (weighted && (rc = wp_window(ctx, t, t_s, t_f, n_lo, n_hi)) != WP_OK) return rc;
+    Level &lv = ctx->L[0];
+    if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
+    for (int k = 0; k < 2; ++k)
+        if ((rc = rich_helper(ctx, k, ctx->rich[k])) != WP_OK) return rc;
+    wp_ctx *F = ctx->rich[0], *C = ctx->rich[1];
+    Level &fl = F->L[0], &cl = C->L[0];
+    const int nx = lv.nx, ny = lv.ny, NX = nx / 2, NY = ny / 2, m = ctx->m;
+    const long long cs = (long long)nx * ny, ccs = (long long)NX * NY;
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(fl.q[fl.cur], lv.q[lv.cur], (size_t)cs * m * ctx->esz, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "Richardson estimate: state copy");
+    if (ctx->esz == 8)
+        launch_coarsen2<double>((const double *)lv.q[lv.cur], cs, nx, (double *)cl.q[cl.cur], ccs, NX, NY, m, s);
+    else
+        launch_coarsen2<float>((const float *)lv.q[lv.cur], cs, nx, (float *)cl.q[cl.cur], ccs, NX, NY, m, s);
+    fl.prev_valid = cl.prev_valid = false;
+    for (int k = 0; k < 2 && rc == WP_OK; ++k) rc = wp_step_patches(F, 0, dt);
+    if (rc == WP_OK) rc = wp_step_patches(C, 0, 2.0 * dt);
+    if (rc != WP_OK) return wp_fail(ctx, rc, "Richardson estimate: %s", F->err.empty() ? C->err.c_str() : F->err.c_str());
+    const size_t ebytes = sizeof(double) * (size_t)ccs * m;
+    if (ctx->richE_cap < ebytes) {
+        if (ctx->richE) wp_dfree(ctx, ctx->richE);
+        ctx->richE = (double *)wp_dalloc(ctx, ebytes);
+        ctx->richE_cap = ctx->richE ? ebytes : 0;
+        if (!ctx->richE) return wp_fail(ctx, WP_ENOMEM, "Richardson estimate buffer");
+    }
+    if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), s) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    const double denom = (double)((1 << (ctx->prob.order + 1)) - 2);
+    const long long hcs = cs, sstride = cs * m;
+    const void *snaps = weighted ? ctx->snaps : nullptr;
+    if (ctx->esz == 8)
+        launch_richardson<double>((const double *)cl.q[cl.cur], ccs, (const double *)fl.q[fl.cur], cs, nx, NX, NY, m,
+                                  denom, ctx->richE, snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
+                                  lv.flags, ctx->count, s);
+    else
+        launch_richardson<float>((const float *)cl.q[cl.cur], ccs, (const float *)fl.q[fl.cur], cs, nx, NX, NY, m,
+                                 denom, ctx->richE, snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
+                                 lv.flags, ctx->count, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "Richardson launch: %s", hipGetErrorString(e));
+    lv.flags_valid = true;
+    if (flags && on_device &&
+        hipMemcpyAsync(flags, lv.flags, (size_t)cs, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "flag copy");
+    if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cs, false)) != WP_OK) return rc;
+    if (estimate && (rc = wp_host_copy(ctx, estimate, ctx->richE, ebytes, false)) != WP_OK) return rc;
+    if (nflagged) {
+        unsigned long long c = 0;
+        if ((rc = wp_host_copy(ctx, &c, ctx->count, sizeof c, false)) != WP_OK) return rc;
+        *nflagged = (int64_t)c;
+    }
+    return WP_OK;
 }
 
 // The flagged forward run as one captured sequence: a clear of the event

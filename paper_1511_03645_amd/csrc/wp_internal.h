@@ -145,6 +145,18 @@ template <typename TE>
 void launch_flag_surface(const TE *eta, int nx, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
                          unsigned long long *count, hipStream_t s);
 
+// Richardson estimate: 2 x 2 block means of a canvas, and E = (coarse -
+// block mean of fine) / denom per coarse cell (FP64, [m][NY][NX]) with the
+// flag of every fine cell of the tiles from its parent's E (snaps null:
+// max_k |E_k|; else max over snapshots n_lo..n_hi of |qhat . E|).
+template <typename T>
+void launch_coarsen2(const T *f, long long fcs, int nx, T *c, long long ccs, int NX, int NY, int m, hipStream_t s);
+template <typename T>
+void launch_richardson(const T *coarse, long long ccs, const T *fine, long long fcs, int nx, int NX, int NY, int m,
+                       double denom, double *E, const void *snaps, long long sstride, long long hcs, int n_lo,
+                       int n_hi, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
+                       unsigned long long *count, hipStream_t s);
+
 // Compensated FP64 reductions: out[0] = sum_k sum_cells w(cell) a_k b_k where
 // a is m component arrays (type TA) and b either an indicator (uint8, times
 // unit vector `comp`) or m arrays of type TB.
