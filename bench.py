@@ -411,6 +411,65 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
                       "between": "adjoint tol 1e-3 and difference tol 0.002, level-0 p every regrid"}}
 
 
+def richardson_compare(n0=256, ratio=4, regrid_every=2, buffer=3):
+    """Two levels (coarse n0^2, ratio 4): the level-1 patches rebuilt every
+    `regrid_every` coarse steps from level 0's adjoint flag, the Richardson
+    estimate weighted by the adjoint, the Richardson estimate alone, or the
+    undivided differences.  J error against a uniform (n0 * ratio)^2 run."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import acoustics2d
+    cfg = acoustics2d(n=n0, seed=1)
+    N, every, dt, F = cfg["nsteps"], cfg["snap_every"], cfg["dt"], cfg["functional"]
+    fine = acoustics2d(n=n0 * ratio, seed=1)
+    wf = wp.from_config(fine)
+    wf.set_state(fine["q0"])
+    wf.run_graph(N * ratio, dt / ratio, 1)
+    qf = wf.get_state()
+    del wf
+    wc = wp.from_config(cfg)
+    wc.set_state(qf.reshape(3, n0, ratio, n0, ratio).mean(axis=(2, 4)))
+    J_ref = wc.functional_value(F, 0)
+    del wc, qf
+
+    def run(mode, tol):
+        w = wp.from_config(cfg, num_levels=2, ratios=(ratio,))
+        w.set_state(cfg["q0"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode in ("adjoint", "richardson_adjoint"):
+            w.adjoint_run(F, dt, N, every)
+        t, cells = 0.0, 0
+        for _ in range(N // regrid_every):
+            if mode == "adjoint":
+                w.flag_adjoint(0, tol, t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+            elif mode == "richardson_adjoint":
+                w.flag_richardson(dt, tol, weighted=True, t=t, t_s=cfg["t_s"], t_f=cfg["t_f"], want_flags=False,
+                                  want_count=False)
+            elif mode == "richardson":
+                w.flag_richardson(dt, tol, want_flags=False, want_count=False)
+            else:
+                w.flag_difference(0, tol, want_flags=False, want_count=False)
+            w.regrid(0, None, buffer=buffer)
+            cells += sum(p[2] * p[3] for p in w.get_patches(1))
+            w.advance(regrid_every, dt)
+            t += regrid_every * dt
+        J = w.functional_value(F, 0)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        del w
+        return {"flag": mode, "tol": tol, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
+                "mean_cells_level1": cells / (N // regrid_every)}
+
+    runs = []
+    for mode, tol in (("adjoint", 1e-3), ("richardson_adjoint", 1e-5), ("richardson", 1e-4), ("difference", 0.005)):
+        run(mode, tol)
+        runs.append(run(mode, tol))
+    return {"workload": f"acoustics2d, 2 levels, coarse {n0}^2, ratio {ratio}, {N} coarse steps, flag + regrid of "
+                        f"level 0 every {regrid_every} coarse steps, buffer {buffer}",
+            "J_reference": J_ref, "reference": f"uniform {n0 * ratio}^2", "runs": runs}
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: a bounded sample of the same
     workload (full grid, a fixed number of forward and adjoint steps)."""
@@ -503,6 +562,10 @@ def main():
         for r in out["amr_flagging"]["runs"]:
             print(f"[bench]   {r['flag']:10s} tol {r['tol']:g}: {r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
                   f"finest-level cells {r['mean_cells_level2']:.0f}", file=sys.stderr, flush=True)
+        out["amr_flagging"]["two_level"] = richardson_compare()
+        for r in out["amr_flagging"]["two_level"]["runs"]:
+            print(f"[bench]   2 levels {r['flag']:18s} tol {r['tol']:g}: J rel err {r['J_rel_err']:.2e}, "
+                  f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
         out["swe"] = swe_compare(1, 1)
