@@ -346,6 +346,9 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
     # reference: the finest resolution everywhere
     fine = acoustics2d(n=n0 * r, seed=1)
     wf = wp.from_config(fine)
+    # 16-row two-step tiles: the reference's launches stay apart from the
+    # timed 12-row ones in kernel statistics
+    wf.set_step_pairs(16)
     wf.set_state(fine["q0"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -423,6 +426,7 @@ def richardson_compare(n0=256, ratio=4, regrid_every=2, buffer=3):
     N, every, dt, F = cfg["nsteps"], cfg["snap_every"], cfg["dt"], cfg["functional"]
     fine = acoustics2d(n=n0 * ratio, seed=1)
     wf = wp.from_config(fine)
+    wf.set_step_pairs(16)
     wf.set_state(fine["q0"])
     wf.run_graph(N * ratio, dt / ratio, 1)
     qf = wf.get_state()
