@@ -148,20 +148,34 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
 // stamp (optional): workgroup b writes its start and end on the device's
 // constant-rate clock to stamp[2b] and stamp[2b + 1] (one slot each, no
 // contention), from which the launch's own duration is read back.
-template <typename T, bool ADJ, bool FULL, int RT, int KIND>
+// DUAL (unrolled heights only): a tile may carry a second narrow tile for
+// lanes 32..63.  A cell's update reads two lanes either side, so the two
+// halves, each with its own two halo lanes, never see each other's outputs;
+// rows, columns and the output range become per-lane.
+template <typename T, bool ADJ, bool FULL, int RT, int KIND, bool DUAL>
 __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int parity,
                                                       int snap_index, int *__restrict__ status,
                                                       unsigned long long *__restrict__ stamp)
 {
+    static_assert(!DUAL || RT > 0, "two tiles per wave need the unrolled march");
     if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x] = (unsigned long long)wall_clock64();
     extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tl = tiles[blockIdx.x];
+    Tile tl = tiles[blockIdx.x];
     const AcouInst<T> *__restrict__ Ip = insts + tl.inst;
-    const int lane = threadIdx.x;
+    int lane = threadIdx.x;
+    if constexpr (DUAL) {
+        if (tl.nib > 0 && lane >= WAVE / 2) {
+            tl.i0 = tl.i0b;
+            tl.j0 = tl.j0b;
+            tl.ni = tl.nib;
+            tl.nj = tl.njb;
+            lane -= WAVE / 2;
+        }
+    }
     MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);
     T *pt = reinterpret_cast<T *>(smem + sizeof(MCon<T>) * MAXMAT);
-    build_tables(*Ip, mc, pt, lane);
+    build_tables(*Ip, mc, pt, threadIdx.x);
     __syncthreads();
 
     const int nx = Ip->nx, ny = Ip->ny;
@@ -193,8 +207,8 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
         march<T, ADJ, false, FULL, acou_mixed_rows(RT)>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr,
                                                         qw, mr, sw, snap, bad);
     }
-    if (__any(bad) && lane == 0) atomicOr(status, ST_NONFINITE);
-    if (stamp && lane == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+    if (__any(bad) && threadIdx.x == 0) atomicOr(status, ST_NONFINITE);
+    if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
 }
 
 // 1D: one thread per cell, the five-cell stencil read straight from memory.
@@ -277,14 +291,33 @@ static size_t acou_smem(int nmat)
 
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint, int nmat_max,
-                   bool full, int rows, int kind, int snap_index, int *status, hipStream_t s, unsigned long long *stamp)
+                   bool full, int rows, int kind, int snap_index, int *status, hipStream_t s, unsigned long long *stamp,
+                   bool dual)
 {
     if (ntiles <= 0) return;
     const size_t sm = acou_smem<T>(nmat_max);
     const dim3 g(ntiles), b(WAVE);
+    if (dual) {
+        // forward steps of refined levels with narrow patches, unrolled heights
+#define WP_DUAL(RT, KIND)                                                                                     \
+    hipLaunchKernelGGL((acou2d_kernel<T, false, true, RT, KIND, true>), g, b, sm, s, insts, tiles, parity, \
+                       snap_index, status, stamp)
+#define WP_DUAL_RT(KIND)                      \
+    switch (rows) {                           \
+    case 4: WP_DUAL(4, KIND); break;          \
+    case 6: WP_DUAL(6, KIND); break;          \
+    case 8: WP_DUAL(8, KIND); break;          \
+    case 12: WP_DUAL(12, KIND); break;        \
+    default: WP_DUAL(16, KIND); break;        \
+    }
+        if (kind == 1) { WP_DUAL_RT(1) } else { WP_DUAL_RT(0) }
+#undef WP_DUAL_RT
+#undef WP_DUAL
+        return;
+    }
 #define WP_LAUNCH(ADJ, FULL, RT, KIND)                                                                       \
-    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND>), g, b, sm, s, insts, tiles, parity, snap_index, status, \
-                       stamp)
+    hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND, false>), g, b, sm, s, insts, tiles, parity, snap_index, \
+                       status, stamp)
     // tile heights 4, 6, 8, 12 and 16 have a compile-time march; any other
     // height takes the runtime march
 #define WP_BY_RT(ADJ, KIND)                              \
@@ -320,9 +353,9 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &h, int parity
 }
 
 template void launch_acou2d<double>(const AcouInst<double> *, const Tile *, int, int, int, int, bool, int, int,
-                                    int, int *, hipStream_t, unsigned long long *);
+                                    int, int *, hipStream_t, unsigned long long *, bool);
 template void launch_acou2d<float>(const AcouInst<float> *, const Tile *, int, int, int, int, bool, int, int,
-                                   int, int *, hipStream_t, unsigned long long *);
+                                   int, int *, hipStream_t, unsigned long long *, bool);
 template void launch_acou1d<double>(const AcouInst<double> *, const AcouInst<double> &, int, int, int, int *,
                                     hipStream_t);
 template void launch_acou1d<float>(const AcouInst<float> *, const AcouInst<float> &, int, int, int, int *,

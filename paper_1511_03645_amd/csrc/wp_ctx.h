@@ -26,6 +26,7 @@ struct Level {
     int ntiles = 0;
     int tile_rows = 0;                   // rows of the step tiles (compile-time march height if supported)
     int nuni = 0;                        // number of single-material tiles (they follow the mixed ones)
+    bool dual = false;                   // some tiles carry a second narrow tile (see Tile)
     // two-step tiles (single-level 2D acoustics; see launch_acou2d_pair):
     // none when the level cannot take two steps per launch
     wp::Tile *ptiles_dev = nullptr;

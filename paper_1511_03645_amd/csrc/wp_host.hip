@@ -215,6 +215,38 @@ bool wp_pair_ready(const wp_ctx *ctx, const Level &lv)
     return ctx->pair_rows != 0 && lv.ptiles_dev && lv.nptiles > 0;
 }
 
+// Narrow tiles (at most HALF_STRIP wide) of the same material and march
+// direction share a wave two by two, one in each half; true if any did.
+static bool pair_narrow(std::vector<Tile> &t)
+{
+    std::vector<Tile> out;
+    out.reserve(t.size());
+    std::map<std::pair<int, int>, size_t> open;   // (mat, down) -> narrow tile waiting for a partner
+    bool any = false;
+    for (const Tile &x : t) {
+        if (x.ni > HALF_STRIP) {
+            out.push_back(x);
+            continue;
+        }
+        const auto key = std::make_pair(x.mat, x.down);
+        const auto it = open.find(key);
+        if (it == open.end()) {
+            open[key] = out.size();
+            out.push_back(x);
+            continue;
+        }
+        Tile &a = out[it->second];
+        a.i0b = x.i0;
+        a.j0b = x.j0;
+        a.nib = x.ni;
+        a.njb = x.nj;
+        open.erase(it);
+        any = true;
+    }
+    t.swap(out);
+    return any;
+}
+
 int wp_upload_tiles(wp_ctx *ctx, Level &lv)
 {
     int rc;
@@ -228,6 +260,15 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
     // order
     std::vector<Tile> mixed, uni;
     for (const Tile &t : lv.tiles_host) (t.mat < 0 ? mixed : uni).push_back(t);
+    // levels of several patches (refined levels, forward steps only): two
+    // narrow tiles per wave where the unrolled march runs them
+    lv.dual = false;
+    const bool full = ctx->prob.order == 2 && ctx->prob.limiter == 1 && ctx->prob.transverse == 1;
+    if (ctx->is_acoustics && ctx->kind2d && full && lv.patches.size() > 1 &&
+        (rows == 4 || rows == 6 || rows == 8 || rows == 12 || rows == 16)) {
+        const bool a = pair_narrow(mixed), b = pair_narrow(uni);
+        lv.dual = a || b;
+    }
     wp_xcd_order(mixed);
     wp_xcd_order(uni);
     lv.nuni = (int)uni.size();
@@ -775,8 +816,9 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
         const AcouInst<T> *I = (const AcouInst<T> *)lv.inst;
         // one launch: a single-material level runs the lean kernel, any other
         // the kernel that picks the path per tile
+        if (lv.dual && adjoint) return wp_fail(ctx, WP_ESTATE, "adjoint step on a level with two tiles per wave");
         launch_acou2d<T>(I, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, full, lv.tile_rows,
-                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream, ctx->stamp_next);
+                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream, ctx->stamp_next, lv.dual);
         ctx->stamp_next = nullptr;   // consumed by this launch only
     }
     else

@@ -28,7 +28,13 @@ struct Tile {
     int down;  // 2D acoustics: march the rows downwards (alternates between
                // vertically adjacent tiles, so the halo rows they share are
                // read by both at about the same time)
+    // a second narrow tile (nib > 0) in the upper half of the wave (one-step
+    // 2D acoustics): lanes 32..63 take (i0b, j0b, nib, njb), lanes 0..31 the
+    // first; same instance, material and direction
+    int i0b = 0, j0b = 0, nib = 0, njb = 0;
 };
+// widest tile of a half wave: 32 lanes less a two-column halo on each side
+constexpr int HALF_STRIP = WAVE / 2 - 4;
 
 // Per-instance description of a 2D (or 1D) acoustics level canvas.  The
 // canvas covers the whole domain at the level's resolution with no ghost
@@ -87,10 +93,11 @@ struct LsweInst {
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_CFL = 2;
 
+// dual: some tiles hold a second half-wave tile (forward, unrolled heights)
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
                    int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s,
-                   unsigned long long *stamp = nullptr);
+                   unsigned long long *stamp = nullptr, bool dual = false);
 // Two steps per launch on a single-level canvas (tiles PAIR_STRIP wide,
 // 4..64 rows high: 8, 10 and 12 unrolled, others rolled; no periodic
 // boundary); q^{n+2} lands in
