@@ -169,7 +169,15 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
         lv.t += dt;
         return WP_OK;
     }
-    if (launch && l > 0 && (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio, s)) != WP_OK) return rc;
+    // the ring at this step's start time; after the first step of a level
+    // with children it is already there: the fill after the previous step
+    // wrote it for the finer level, from the same canvases of the level
+    // below (which does not step meanwhile), and the average of the finer
+    // level touches no ring cell (proper nesting)
+    const bool has_children = l + 1 < (int)ctx->L.size() && !ctx->L[l + 1].patches.empty();
+    if (launch && l > 0 && !(sub > 0 && has_children) &&
+        (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio, s)) != WP_OK)
+        return rc;
     if (launch) {
         if ((rc = wp_step_level(ctx, lv, dt, 0, s, -1)) != WP_OK) return rc;
     } else {
@@ -178,7 +186,7 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
     lv.t_prev = lv.t;
     lv.prev_valid = true;
     lv.t += dt;
-    if (l + 1 < (int)ctx->L.size() && !ctx->L[l + 1].patches.empty()) {
+    if (has_children) {
         const int r = ctx->L[l + 1].ratio;
         // this level's ring at its new time, read by the finer level's
         // interpolation next to the ring
