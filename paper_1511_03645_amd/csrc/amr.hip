@@ -115,15 +115,42 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
                 sy[t] = minmod(cval(C, k, ic, jc + 1, NX, NY, bc, csc) - c0[t],
                                c0[t] - cval(C, k, ic, jc - 1, NX, NY, bc, csc));
             }
-            for (unsigned long long m = mask; m; m &= m - 1) {
-                const int b = __builtin_ctzll(m);
-                const int ii = pow2 ? (b & (r - 1)) : b % r, jj = pow2 ? (b >> lr) : b / r;
+            auto child = [&](int ii, int jj) {
                 // a power-of-two ratio divides exactly as its reciprocal multiplies
                 const T xi = (pow2 ? (T(ii) + T(0.5)) * inv_r : (T(ii) + T(0.5)) / T(r)) - T(0.5);
                 const T eta = (pow2 ? (T(jj) + T(0.5)) * inv_r : (T(jj) + T(0.5)) / T(r)) - T(0.5);
                 const T a = (c0[0] + xi * sx[0]) + eta * sy[0];
                 const T v = (c0[1] + xi * sx[1]) + eta * sy[1];
-                fine[k * csf + (long long)(jc * r + jj) * nxf + (ic * r + ii)] = (T(1) - alpha) * a + alpha * v;
+                return (T(1) - alpha) * a + alpha * v;
+            };
+            if (r == 4) {
+                // a full row of four children (along a patch's lower or upper
+                // edge) goes out as one contiguous 4-element store (aligned:
+                // the fine row length and the component stride are multiples
+                // of 4 elements, the canvas 256-byte aligned)
+                for (int jj = 0; jj < 4; ++jj) {
+                    const unsigned rm = (unsigned)(mask >> (4 * jj)) & 0xfu;
+                    if (!rm) continue;
+                    T *dst = fine + k * csf + (long long)(jc * 4 + jj) * nxf + (long long)ic * 4;
+                    if (rm == 0xfu) {
+                        typedef T T4 __attribute__((ext_vector_type(4)));
+                        T4 q;
+                        q.x = child(0, jj);
+                        q.y = child(1, jj);
+                        q.z = child(2, jj);
+                        q.w = child(3, jj);
+                        *reinterpret_cast<T4 *>(dst) = q;
+                    } else {
+                        for (int ii = 0; ii < 4; ++ii)
+                            if (rm >> ii & 1u) dst[ii] = child(ii, jj);
+                    }
+                }
+            } else {
+                for (unsigned long long m = mask; m; m &= m - 1) {
+                    const int b = __builtin_ctzll(m);
+                    const int ii = pow2 ? (b & (r - 1)) : b % r, jj = pow2 ? (b >> lr) : b / r;
+                    fine[k * csf + (long long)(jc * r + jj) * nxf + (ic * r + ii)] = child(ii, jj);
+                }
             }
         }
     }
