@@ -167,8 +167,21 @@ __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ ce
         const int ic = lin % NX, jc = lin / NX;
         for (int k = 0; k < 3; ++k) {
             T s = T(0);
-            for (int jj = 0; jj < r; ++jj)
-                for (int ii = 0; ii < r; ++ii) s += fine[k * csf + (long long)(r * jc + jj) * nxf + (r * ic + ii)];
+            if (r == 4) {
+                // each row of four children in one aligned vector load, summed
+                // in the same order
+                typedef T T4 __attribute__((ext_vector_type(4)));
+                for (int jj = 0; jj < 4; ++jj) {
+                    const T4 q = *reinterpret_cast<const T4 *>(fine + k * csf + (long long)(4 * jc + jj) * nxf + 4 * ic);
+                    s += q.x;
+                    s += q.y;
+                    s += q.z;
+                    s += q.w;
+                }
+            } else {
+                for (int jj = 0; jj < r; ++jj)
+                    for (int ii = 0; ii < r; ++ii) s += fine[k * csf + (long long)(r * jc + jj) * nxf + (r * ic + ii)];
+            }
             coarse[k * csc + lin] = s * inv;
         }
     }
