@@ -161,24 +161,40 @@ __device__ void flag_tile(const Tile &tl, int nx, unsigned cells, int col, bool 
     const unsigned csb = cells * (unsigned)sizeof(T);
     const __amdgpu_buffer_rsrc_t fw = make_rsrc(fl.flags, cells);
     unsigned local = 0;
-    for (int j = tl.j0; j < tl.j0 + tl.nj; ++j) {
-        const unsigned idx = (unsigned)(j * nx + col);
-        const unsigned off = idx * (unsigned)sizeof(T);
-        const double q0 = (double)bload(qr, off, T(0), 0u);
-        const double q1 = (double)bload(qr, off, T(0), csb);
-        const double q2 = (double)bload(qr, off, T(0), 2u * csb);
-        double best = 0.0;
+    // four rows at a time, so that their loads are in flight together (rows
+    // past the tile read and write out of range: loads return 0, stores drop)
+    constexpr int G = 4;
+    for (int j = tl.j0; j < tl.j0 + tl.nj; j += G) {
+        unsigned idx[G], off[G];
+        double q0[G], q1[G], q2[G], best[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const bool in = j + g < tl.j0 + tl.nj;
+            idx[g] = in ? (unsigned)((j + g) * nx + col) : cells;
+            off[g] = idx[g] * (unsigned)sizeof(T);
+            q0[g] = (double)bload(qr, off[g], T(0), 0u);
+            q1[g] = (double)bload(qr, off[g], T(0), csb);
+            q2[g] = (double)bload(qr, off[g], T(0), 2u * csb);
+            best[g] = 0.0;
+        }
         for (int n = fl.n_lo; n <= fl.n_hi; ++n) {
             const __amdgpu_buffer_rsrc_t sr =
                 make_rsrc((const T *)fl.snaps + (long long)n * fl.sstride, 3u * csb);
-            double ip = (double)bload(sr, off, T(0), 0u) * q0;
-            ip = ip + (double)bload(sr, off, T(0), csb) * q1;
-            ip = ip + (double)bload(sr, off, T(0), 2u * csb) * q2;
-            best = fmax(best, fabs(ip));
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double ip = (double)bload(sr, off[g], T(0), 0u) * q0[g];
+                ip = ip + (double)bload(sr, off[g], T(0), csb) * q1[g];
+                ip = ip + (double)bload(sr, off[g], T(0), 2u * csb) * q2[g];
+                best[g] = fmax(best[g], fabs(ip));
+            }
         }
-        const unsigned f = best > fl.tol ? 1u : 0u;
-        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)f, fw, out_lane ? idx : cells, 0, 0);
-        local += out_lane ? f : 0u;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const bool keep = out_lane && idx[g] < cells;
+            const unsigned f = best[g] > fl.tol ? 1u : 0u;
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)f, fw, keep ? idx[g] : cells, 0, 0);
+            local += keep ? f : 0u;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
     if (threadIdx.x == 0 && local) atomicAdd(fl.count, (unsigned long long)local);
