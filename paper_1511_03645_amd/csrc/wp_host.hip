@@ -1347,7 +1347,7 @@ extern "C" int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flag
 // cell); E = (coarse - block mean of fine) / (2^(p+1) - 2).
 static int rich_helper(wp_ctx *ctx, int which, wp_ctx *&out)
 {
-    if (out) return wp_set_stream(out, ctx->stream);
+    if (out) return out->stream == ctx->stream ? WP_OK : wp_set_stream(out, ctx->stream);
     const int nx = ctx->grid.nx0, ny = ctx->grid.ny0;
     const int f = which == 0 ? 1 : 2;
     const int hx = nx / f, hy = ny / f;
