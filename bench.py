@@ -517,7 +517,10 @@ def main():
     spl = 2 if job.pair_rows else 1
     step_ms = float(np.mean(job.kernel_ms))
     launch_ms = spl * step_ms
-    alg = ALG_BYTES[64] * job.cells
+    # algorithmic bytes per cell update (state read and written once, the
+    # material byte) times the cell updates one launch performs: a two-step
+    # launch updates every cell twice while reading and writing it once
+    alg = ALG_BYTES[64] * job.cells * spl
     achieved = alg / (launch_ms * 1e-3) / 1e9
     kname = "acou2d_pair_kernel<double, forward>" if spl == 2 else "acou2d_kernel<double, forward>"
     print(f"[bench] fp64: {sec * 1e3:.2f} ms/job, {value / 1e9:.2f} Gcell-updates/s, forward launch "
@@ -534,7 +537,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(job.cells, job.pair_rows or job.rows) if spl == 2 else None,
                      "kernel": kname, "kernel_us": launch_ms * 1e3, "steps_per_launch": spl,
-                     "alg_bytes_per_launch": alg, "tile_rows": job.pair_rows or job.rows},
+                     "alg_bytes_per_launch": alg, "cell_updates_per_launch": job.cells * spl,
+                     "alg_bytes_per_cell_update": ALG_BYTES[64], "tile_rows": job.pair_rows or job.rows},
         "J": J64,
     }
     if not args.no_fp32:
@@ -546,7 +550,7 @@ def main():
                        "tile_rows": job32.pair_rows or job32.rows, "steps_per_launch": spl32,
                        "speedup_vs_fp64": sec / sec32, "J_rel_err_vs_fp64": abs(J32 - J64) / abs(J64),
                        "kernel_us": k32 * 1e3,
-                       "achieved_GBs": ALG_BYTES[32] * job.cells / (k32 * 1e-3) / 1e9}
+                       "achieved_GBs": ALG_BYTES[32] * job.cells * spl32 / (k32 * 1e-3) / 1e9}
         print(f"[bench] fp32: {sec32 * 1e3:.2f} ms/job, J rel err {out['fp32']['J_rel_err_vs_fp64']:.2e}",
               file=sys.stderr, flush=True)
     if not args.no_batch:
