@@ -495,8 +495,8 @@ def cpu_baseline(cfg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
-              f"described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the decomposition across GPUs is "
+              f"designed but not built.", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
