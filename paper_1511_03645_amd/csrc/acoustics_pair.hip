@@ -197,7 +197,7 @@ __device__ void flag_tile(const Tile &tl, int nx, unsigned cells, int col, bool 
         }
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
-    if (threadIdx.x == 0 && local) atomicAdd(fl.count, (unsigned long long)local);
+    if (threadIdx.x == 0 && local) atomicAdd(count_slot(fl.count), (unsigned long long)local);
 }
 
 // The same two marches as a rolled loop over the tile's own height (any nj):

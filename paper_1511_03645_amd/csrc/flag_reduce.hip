@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void flag_kernel(const TQ *__restrict__ q, lon
     }
     // wave-level sum then one atomic per wave
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
-    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count_slot(count), local);
 }
 
 __global__ __launch_bounds__(256) void flag_mixed_kernel(const double *__restrict__ eta, const float *__restrict__ hu,
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void flag_mixed_kernel(const double *__restric
         local += f;
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
-    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count_slot(count), local);
 }
 
 // Undivided-difference flag, the comparison criterion of Sec. 5.2.4 ("pressure
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void diff_flag_kernel(const TE *__restrict__ c
         }
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
-    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count_slot(count), local);
 }
 
 // Surface flag, the comparison criterion of Sec. 5.3 ("surface flagging"):
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void surface_flag_kernel(const TE *__restrict_
         }
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
-    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count_slot(count), local);
 }
 
 // Richardson error estimate (the estimator named in Sec. 1 and in the
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void richardson_flag_kernel(const double *__re
         }
     }
     for (int off = 32; off > 0; off >>= 1) local += __shfl_down(local, off);
-    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count, local);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(count_slot(count), local);
 }
 
 // ---------------------------------------------------------------------------

@@ -118,7 +118,7 @@ struct wp_ctx {
     int ff_parity = -1, ff_flip = 0;         // flip: canvas parity change of the run
     unsigned long long ff_gen = 0;
     const void *ff_snaps = nullptr;
-    unsigned long long *ev_counts = nullptr;   // flagged cells per flag event
+    unsigned long long *ev_counts = nullptr;   // flagged cells per flag event (COUNT_SPAN entries each)
     size_t ev_counts_cap = 0;
     unsigned long long *stamps = nullptr;      // workgroup clocks of the timed steps
     size_t stamps_cap = 0;
@@ -157,6 +157,9 @@ inline int wp_fail_get(const wp_ctx *ctx, int code, const char *what)
 int wp_host_copy2d(wp_ctx *ctx, void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t rows,
                    bool to_device);
 int wp_host_copy(wp_ctx *ctx, void *dst, const void *src, size_t bytes, bool to_device);
+// flag counters spread over slots (COUNT_SPAN entries each): clear n, read n
+int wp_clear_counts(wp_ctx *ctx, unsigned long long *dev, int n, hipStream_t s);
+int wp_read_counts(wp_ctx *ctx, const unsigned long long *dev, int n, int64_t *out);
 // Copy a host table to a device block of `cap` bytes, first replacing the
 // block by one half as large again as needed when it is too small.
 int wp_upload(wp_ctx *ctx, const void *src, size_t bytes, void *&dev, size_t &cap, const char *what);

@@ -465,7 +465,7 @@ extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef,
     }
     // status words and reduction scratch
     ctx->status = (int *)wp_dalloc(ctx, 256);
-    ctx->count = (unsigned long long *)wp_dalloc(ctx, 256);
+    ctx->count = (unsigned long long *)wp_dalloc(ctx, sizeof(unsigned long long) * COUNT_SPAN);
     ctx->partials = (double *)wp_dalloc(ctx, sizeof(double) * 2 * RED_BLOCKS);
     ctx->red_out = (double *)wp_dalloc(ctx, 256);
     ctx->cflbits = (unsigned *)wp_dalloc(ctx, 256);
@@ -609,6 +609,28 @@ int wp_host_copy2d(wp_ctx *ctx, void *dst, size_t dpitch, const void *src, size_
                 for (size_t r = 0; r < n; ++r) memcpy((char *)dst + (r0 + r) * dpitch, pin + r * width, width);
         }
         if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "host transfer: %s", hipGetErrorString(e));
+    }
+    return WP_OK;
+}
+
+// Counters spread over slots (see COUNT_SLOTS): clear n of them, and read
+// them back as their slot sums.
+int wp_clear_counts(wp_ctx *ctx, unsigned long long *dev, int n, hipStream_t s)
+{
+    if (hipMemsetAsync(dev, 0, sizeof(unsigned long long) * COUNT_SPAN * (size_t)n, s) != hipSuccess)
+        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    return WP_OK;
+}
+
+int wp_read_counts(wp_ctx *ctx, const unsigned long long *dev, int n, int64_t *out)
+{
+    std::vector<unsigned long long> v((size_t)COUNT_SPAN * n);
+    int rc;
+    if ((rc = wp_host_copy(ctx, v.data(), dev, v.size() * sizeof(unsigned long long), false)) != WP_OK) return rc;
+    for (int k = 0; k < n; ++k) {
+        unsigned long long c = 0;
+        for (int q = 0; q < COUNT_SLOTS; ++q) c += v[(size_t)k * COUNT_SPAN + (size_t)q * COUNT_STRIDE];
+        out[k] = (int64_t)c;
     }
     return WP_OK;
 }
@@ -1255,18 +1277,13 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     if ((rc = wp_window(ctx, t, t_s, t_f, n_lo, n_hi)) != WP_OK) return rc;
     Level &lv = ctx->L[level];
     const long long cells = (long long)lv.nx * lv.ny;
-    if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    if ((rc = wp_clear_counts(ctx, ctx->count, 1, ctx->stream)) != WP_OK) return rc;
     if ((rc = flag_launch(ctx, level, tol, n_lo, n_hi, ctx->count, ctx->stream)) != WP_OK) return rc;
     if (flags && on_device &&
         hipMemcpyAsync(flags, lv.flags, (size_t)cells, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "flag copy");
     if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cells, false)) != WP_OK) return rc;
-    if (nflagged) {
-        unsigned long long c = 0;
-        if ((rc = wp_host_copy(ctx, &c, ctx->count, sizeof c, false)) != WP_OK) return rc;
-        *nflagged = (int64_t)c;
-    }
+    if (nflagged && (rc = wp_read_counts(ctx, ctx->count, 1, nflagged)) != WP_OK) return rc;
     return WP_OK;
 }
 
@@ -1287,8 +1304,7 @@ static int flag_standard(wp_ctx *ctx, int level, bool surface, double tol, uint8
     int rc;
     if (!surface && level > 0 && !lv.patches.empty() && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK)
         return rc;
-    if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), s) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    if ((rc = wp_clear_counts(ctx, ctx->count, 1, s)) != WP_OK) return rc;
     const bool full = lv.patches.size() == 1 && lv.patches[0].nx == lv.nx && lv.patches[0].ny == lv.ny;
     if (!full) launch_fill_u8(lv.flags, cells, 0, s);
     const char *q = (const char *)lv.q[lv.cur];
@@ -1320,11 +1336,7 @@ static int flag_standard(wp_ctx *ctx, int level, bool surface, double tol, uint8
         hipMemcpyAsync(flags, lv.flags, (size_t)cells, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "flag copy");
     if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cells, false)) != WP_OK) return rc;
-    if (nflagged) {
-        unsigned long long c = 0;
-        if ((rc = wp_host_copy(ctx, &c, ctx->count, sizeof c, false)) != WP_OK) return rc;
-        *nflagged = (int64_t)c;
-    }
+    if (nflagged && (rc = wp_read_counts(ctx, ctx->count, 1, nflagged)) != WP_OK) return rc;
     return WP_OK;
 }
 
@@ -1406,8 +1418,7 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
         ctx->richE_cap = ctx->richE ? ebytes : 0;
         if (!ctx->richE) return wp_fail(ctx, WP_ENOMEM, "Richardson estimate buffer");
     }
-    if (hipMemsetAsync(ctx->count, 0, sizeof(unsigned long long), s) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "count clear");
+    if ((rc = wp_clear_counts(ctx, ctx->count, 1, s)) != WP_OK) return rc;
     const double denom = (double)((1 << (ctx->prob.order + 1)) - 2);
     const long long hcs = cs, sstride = cs * m;
     const void *snaps = weighted ? ctx->snaps : nullptr;
@@ -1427,11 +1438,7 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
         return wp_fail(ctx, WP_EDEVICE, "flag copy");
     if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cs, false)) != WP_OK) return rc;
     if (estimate && (rc = wp_host_copy(ctx, estimate, ctx->richE, ebytes, false)) != WP_OK) return rc;
-    if (nflagged) {
-        unsigned long long c = 0;
-        if ((rc = wp_host_copy(ctx, &c, ctx->count, sizeof c, false)) != WP_OK) return rc;
-        *nflagged = (int64_t)c;
-    }
+    if (nflagged && (rc = wp_read_counts(ctx, ctx->count, 1, nflagged)) != WP_OK) return rc;
     return WP_OK;
 }
 
@@ -1458,7 +1465,7 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         if ((rc = wp_window(ctx, lv.t + (double)k * flag_every * dt, t_s, t_f, lo[k], hi[k])) != WP_OK) return rc;
     if ((int)ctx->ev_counts_cap < nev) {
         if (ctx->ev_counts) wp_dfree(ctx, ctx->ev_counts);
-        ctx->ev_counts = (unsigned long long *)wp_dalloc(ctx, sizeof(unsigned long long) * nev);
+        ctx->ev_counts = (unsigned long long *)wp_dalloc(ctx, sizeof(unsigned long long) * COUNT_SPAN * nev);
         if (!ctx->ev_counts) {
             ctx->ev_counts_cap = 0;
             return wp_fail(ctx, WP_ENOMEM, "flag counters");
@@ -1498,17 +1505,17 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         hipStream_t s;
         if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
         const int par = lv.cur;
-        launch_fill_u8((uint8_t *)ctx->ev_counts, (long long)sizeof(unsigned long long) * nev, 0, s);
+        launch_fill_u8((uint8_t *)ctx->ev_counts, (long long)sizeof(unsigned long long) * COUNT_SPAN * nev, 0, s);
         const Level &a0 = ctx->adj;
         for (int k = 0; k < nev && rc == WP_OK; ++k) {
-            if (!fuse) rc = flag_launch(ctx, 0, tol, lo[k], hi[k], ctx->ev_counts + k, s);
+            if (!fuse) rc = flag_launch(ctx, 0, tol, lo[k], hi[k], ctx->ev_counts + (size_t)k * COUNT_SPAN, s);
             // the block's steps, two per launch where the level allows it
             for (int st = 0, launch = 0; st < flag_every && rc == WP_OK; ++launch) {
                 if (launch >= tfirst && launch < tfirst + ntimed && ctx->is_acoustics && ctx->kind2d)
                     ctx->stamp_next = ctx->stamps + nslot * ((size_t)ntimed * k + (launch - tfirst));
                 if (pairs && st + 1 < flag_every) {
                     const PairFlag fl{ctx->snaps, (long long)a0.nx * a0.ny * ctx->m, lo[k], hi[k], tol, lv.flags,
-                                      ctx->ev_counts + k};
+                                      ctx->ev_counts + (size_t)k * COUNT_SPAN};
                     rc = wp_step_pair(ctx, lv, dt, 0, s, -1, -1, fuse && launch == 0 ? &fl : nullptr);
                     st += 2;
                 } else {
@@ -1537,12 +1544,7 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
     lv.t += (double)nsteps * dt;
     if (counts || step_ms) {
         if (hipStreamSynchronize(ctx->stream) != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "flagged run sync");
-        if (counts) {
-            std::vector<unsigned long long> c(nev);
-            if ((rc = wp_host_copy(ctx, c.data(), ctx->ev_counts, sizeof(unsigned long long) * nev, false)) != WP_OK)
-                return rc;
-            for (int k = 0; k < nev; ++k) counts[k] = (int64_t)c[k];
-        }
+        if (counts && (rc = wp_read_counts(ctx, ctx->ev_counts, nev, counts)) != WP_OK) return rc;
         if (step_ms) {
             if (!(ctx->is_acoustics && ctx->kind2d)) return wp_fail(ctx, WP_EINVAL, "launch times are for 2D acoustics");
             std::vector<unsigned long long> st(nslot * ntimed * nev);

@@ -89,6 +89,17 @@ struct LsweInst {
     long long snap_stride;
 };
 
+// Flag counters: workgroup b adds its count to slot b % COUNT_SLOTS of a
+// counter, the slots COUNT_STRIDE entries apart (separate cache lines), so
+// that the adds of one launch do not all queue on one address.  A counter
+// spans COUNT_SPAN entries and is the sum of its slots.
+constexpr int COUNT_SLOTS = 16, COUNT_STRIDE = 16;
+constexpr int COUNT_SPAN = COUNT_SLOTS * COUNT_STRIDE;
+__device__ __forceinline__ unsigned long long *count_slot(unsigned long long *c)
+{
+    return c + (blockIdx.x % COUNT_SLOTS) * COUNT_STRIDE;
+}
+
 // status word bits latched by kernels
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_CFL = 2;
