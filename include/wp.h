@@ -152,7 +152,9 @@ typedef struct wp_ctx wp_ctx;
 /* Create a solver instance: validates the arguments, uploads the
  * coefficients, allocates one state canvas pair per level and sets level 0
  * to a single patch covering the domain (finer levels start empty).
- * stream: a hipStream_t (NULL: the null stream).  On failure *out is NULL. */
+ * stream: a hipStream_t (NULL: the null stream).  On failure *out is NULL;
+ * WP_EINVAL among others for a level-0 grid of fewer than 4 cells on a side
+ * (nx0; also ny0 in 2D). */
 int wp_create(const wp_problem *problem, const wp_coefficients *coef, const wp_grid *grid,
               const wp_allocator *alloc, void *stream, wp_ctx **out);
 void wp_destroy(wp_ctx *ctx);
