@@ -355,7 +355,8 @@ int wp_get_step_pairs(const wp_ctx *ctx, int *rows);
 
 /* Capture `nsteps` single-level steps of size dt into a HIP graph and replay
  * it `replays` times (the steps of nsteps calls of wp_step_patches on level
- * 0, two per launch where wp_set_step_pairs allows it). */
+ * 0, two per launch where wp_set_step_pairs allows it).  WP_EINVAL unless
+ * nsteps >= 1 and replays >= 0; zero replays capture and change nothing. */
 int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays);
 
 #ifdef __cplusplus
