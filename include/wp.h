@@ -185,6 +185,20 @@ int wp_step_patches(wp_ctx *ctx, int level, double dt);
  * cells it covers.  With one level this is nsteps calls of wp_step_patches. */
 int wp_advance(wp_ctx *ctx, int nsteps, double dt0);
 
+/* Select the system that the steps of the level hierarchy solve
+ * (wp_step_patches, wp_advance, wp_run_graph): adjoint = 0 the forward
+ * system, 1 the adjoint system (Sec. 2 adjoint equation, flux -A^T q, in the
+ * reversed time), so that the adjoint can itself be solved with refinement
+ * (Sec. 7, the proposed AMR of the adjoint problem).  The states of the levels
+ * are kept; the caller sets the adjoint data (e.g. the functional's phi) with
+ * wp_set_state.  Ghost rings, interpolation, averaging and regridding are the
+ * same for both systems.  2D/1D acoustics only (WP_EINVAL otherwise, and for
+ * an adjoint value other than 0 or 1).  While the adjoint system is selected,
+ * wp_forward_flagged and wp_flag_richardson fail with WP_ESTATE.  Tile tables
+ * are rebuilt on a change, so captured sequences are captured again. */
+int wp_set_equation(wp_ctx *ctx, int adjoint);
+int wp_get_equation(const wp_ctx *ctx, int *adjoint);
+
 /* Time-reversed adjoint (Sec. 2, 4): qtilde(x, 0) = phi from the functional,
  * solved forward in time with flux -A^T qtilde on the level-0 grid, the same
  * boundary types as the forward problem.  Snapshots are kept in device

@@ -160,7 +160,7 @@ class Hierarchy:
     ratios; patches: list per level of (ilo, jlo, nx, ny) boxes (level 0 may be
     omitted: one patch covering the domain)."""
 
-    def __init__(self, cfg, ratios, patches, order=None, limiter=None, transverse=None):
+    def __init__(self, cfg, ratios, patches, order=None, limiter=None, transverse=None, equation="forward"):
         self.cfg = cfg
         self.ratios = list(ratios)
         self.L = len(self.ratios) + 1
@@ -168,6 +168,9 @@ class Hierarchy:
         self.order = cfg["order"] if order is None else order
         self.limiter = cfg["limiter"] if limiter is None else limiter
         self.transverse = cfg["transverse"] if transverse is None else transverse
+        # the system every patch step solves: the forward acoustics or its
+        # adjoint (Sec. 2), the latter refined as Sec. 7 proposes
+        self.which = {"forward": 0, "adjoint": 1}[equation]
         nx0, ny0 = cfg["nx"], cfg["ny"]
         self.n = []
         self.dx = []
@@ -231,7 +234,7 @@ class Hierarchy:
         new = self.q[l].copy()
         for p in self.patches[l]:
             i0, j0, w, h = p
-            new[:, j0:j0 + h, i0:i0 + w] = self._patch_step(l, p, 0, dt)
+            new[:, j0:j0 + h, i0:i0 + w] = self._patch_step(l, p, self.which, dt)
         self.q_old[l] = self.q[l]
         self.q[l] = new
         self.t[l] += dt

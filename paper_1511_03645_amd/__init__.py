@@ -89,6 +89,8 @@ _SIGS = {
     "wp_get_state": (_I, [_P, _I, _I, _P, _I]),
     "wp_step_patches": (_I, [_P, _I, _D]),
     "wp_advance": (_I, [_P, _I, _D]),
+    "wp_set_equation": (_I, [_P, _I]),
+    "wp_get_equation": (_I, [_P, ctypes.POINTER(_I)]),
     "wp_adjoint_run": (_I, [_P, ctypes.POINTER(wp_functional), ctypes.POINTER(wp_snapshot_spec)]),
     "wp_num_snapshots": (_I, [_P]),
     "wp_get_snapshot": (_I, [_P, _I, _P, _I]),
@@ -330,6 +332,16 @@ class WavePatch:
 
     def advance(self, nsteps, dt0):
         self._check(lib().wp_advance(self.h, nsteps, dt0))
+
+    def set_equation(self, adjoint):
+        """Solve the adjoint system (True) or the forward system (False) in
+        the hierarchy's steps."""
+        self._check(lib().wp_set_equation(self.h, 1 if adjoint else 0))
+
+    def get_equation(self):
+        v = ctypes.c_int(0)
+        self._check(lib().wp_get_equation(self.h, ctypes.byref(v)))
+        return bool(v.value)
 
     def adjoint_run(self, functional, dt, nsteps, snap_every):
         f = functional_struct(functional)

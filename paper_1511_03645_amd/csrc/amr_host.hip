@@ -179,7 +179,7 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
         (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio, s)) != WP_OK)
         return rc;
     if (launch) {
-        if ((rc = wp_step_level(ctx, lv, dt, 0, s, -1)) != WP_OK) return rc;
+        if ((rc = wp_step_level(ctx, lv, dt, ctx->equation, s, -1)) != WP_OK) return rc;
     } else {
         lv.cur ^= 1;
     }

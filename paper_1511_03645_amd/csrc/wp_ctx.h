@@ -97,6 +97,7 @@ struct wp_ctx {
     wp_functional phi_key{};
     bool phi_valid = false;
     std::string err;
+    int equation = 0;                    // system the level hierarchy's steps solve: 0 forward, 1 adjoint
     int tile_rows = 0;
     int pair_rows = -1;                  // two-step tile height: -1 built-in choice, 0 off
     // captured launch sequences (recorded on an internal stream, replayed on

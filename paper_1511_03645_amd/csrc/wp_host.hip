@@ -264,7 +264,7 @@ int wp_upload_tiles(wp_ctx *ctx, Level &lv)
     // narrow tiles per wave where the unrolled march runs them
     lv.dual = false;
     const bool full = ctx->prob.order == 2 && ctx->prob.limiter == 1 && ctx->prob.transverse == 1;
-    if (ctx->is_acoustics && ctx->kind2d && full && lv.patches.size() > 1 &&
+    if (ctx->is_acoustics && ctx->kind2d && full && ctx->equation == 0 && lv.patches.size() > 1 &&
         (rows == 4 || rows == 6 || rows == 8 || rows == 12 || rows == 16)) {
         const bool a = pair_narrow(mixed), b = pair_narrow(uni);
         lv.dual = a || b;
@@ -993,10 +993,10 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
         const bool pairs = wp_pair_ready(ctx, lv);
         for (int k = 0; k < nsteps && rc == WP_OK;) {
             if (pairs && k + 1 < nsteps) {
-                rc = wp_step_pair(ctx, lv, dt, 0, s, -1, -1);
+                rc = wp_step_pair(ctx, lv, dt, ctx->equation, s, -1, -1);
                 k += 2;
             } else {
-                rc = wp_step_level(ctx, lv, dt, 0, s, -1);
+                rc = wp_step_level(ctx, lv, dt, ctx->equation, s, -1);
                 k += 1;
             }
         }
@@ -1043,10 +1043,34 @@ extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
         return WP_OK;
     }
     if (level > 0 && (rc = wp_fill_coarse_ghosts(ctx, level, lv.t)) != WP_OK) return rc;
-    if ((rc = wp_step_level(ctx, lv, dt, 0, ctx->stream, -1)) != WP_OK) return rc;
+    if ((rc = wp_step_level(ctx, lv, dt, ctx->equation, ctx->stream, -1)) != WP_OK) return rc;
     lv.t_prev = lv.t;
     lv.prev_valid = true;
     lv.t += dt;
+    return WP_OK;
+}
+
+// The system the level hierarchy steps.  The adjoint acoustics update uses
+// the same tiles except the two-tile waves of the forward kernel, so the
+// tables are rebuilt (which also re-captures every cached sequence).
+extern "C" int wp_set_equation(wp_ctx *ctx, int adjoint)
+{
+    if (!ctx) return WP_EINVAL;
+    if (adjoint != 0 && adjoint != 1) return wp_fail(ctx, WP_EINVAL, "equation must be 0 (forward) or 1 (adjoint)");
+    if (!ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "the adjoint hierarchy is for acoustics");
+    if (ctx->equation == adjoint) return WP_OK;
+    ctx->equation = adjoint;
+    int rc;
+    for (Level &lv : ctx->L)
+        if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
+    return WP_OK;
+}
+
+extern "C" int wp_get_equation(const wp_ctx *ctx, int *adjoint)
+{
+    if (!ctx) return WP_EINVAL;
+    if (!adjoint) return wp_fail_get(ctx, WP_EINVAL, "null output");
+    *adjoint = ctx->equation;
     return WP_OK;
 }
 
@@ -1392,6 +1416,8 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
 {
     if (!ctx) return WP_EINVAL;
     if (level != 0) return wp_fail(ctx, WP_EINVAL, "the Richardson estimate is taken on level 0");
+    if (ctx->equation != 0)
+        return wp_fail(ctx, WP_ESTATE, "the Richardson estimate is for the forward system");
     if (!ctx->is_acoustics || !ctx->kind2d) return wp_fail(ctx, WP_EINVAL, "the Richardson estimate is for 2D acoustics");
     if (ctx->grid.nx0 % 2 || ctx->grid.ny0 % 2 || ctx->grid.nx0 < 4 || ctx->grid.ny0 < 4)
         return wp_fail(ctx, WP_EINVAL, "the Richardson estimate needs even grid sizes of at least 4");
@@ -1459,6 +1485,7 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
 {
     if (!ctx) return WP_EINVAL;
     if (ctx->L.size() != 1) return wp_fail(ctx, WP_EINVAL, "flagged forward runs are for single-level instances");
+    if (ctx->equation != 0) return wp_fail(ctx, WP_ESTATE, "flagged forward run on a hierarchy set to the adjoint system");
     if (flag_every < 1 || nsteps < 0 || nsteps % flag_every != 0)
         return wp_fail(ctx, WP_EINVAL, "nsteps must be a non-negative multiple of flag_every >= 1");
     Level &lv = ctx->L[0];

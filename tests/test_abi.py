@@ -40,3 +40,5 @@ def test_status_strings_without_device():
     assert L.wp_status_string(wp.WP_ECFL).decode().startswith("Courant")
     assert L.wp_last_error(None).decode() == "null handle"
     assert L.wp_step_patches(None, 0, 0.1) == wp.WP_EINVAL
+    assert L.wp_set_equation(None, 1) == wp.WP_EINVAL
+    assert L.wp_get_equation(None, None) == wp.WP_EINVAL

@@ -1,0 +1,77 @@
+"""GPU parity of the hierarchy set to the adjoint system (Sec. 2 adjoint
+equation, solved with refinement as Sec. 7 proposes) against the oracle's
+hierarchy, through the C ABI: ghost rings, subcycling and averaging are
+those of the forward path, the patch steps take the transpose flux.
+
+Bar (FP64): max |gpu - oracle| <= 1e-12 * max |oracle| over the cells every
+level owns."""
+import numpy as np
+import pytest
+
+import paper_1511_03645_amd as wp
+from oracle import amr
+from wp_synth import random_state
+
+from test_gpu_amr import LAYOUTS, cfg_of, compare, dt_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,ratios,boxes,bc", LAYOUTS)
+def test_adjoint_hierarchy_matches_oracle(n, ratios, boxes, bc):
+    print(f"case adjoint amr n={n} ratios={ratios} bc={bc}", flush=True)
+    cfg = cfg_of(n, bc, seed=n + 1)
+    H = amr.Hierarchy(cfg, ratios, [], equation="adjoint")
+    w = wp.from_config(cfg, num_levels=len(ratios) + 1, ratios=tuple(ratios))
+    w.set_equation(True)
+    assert w.get_equation() is True
+    q0 = random_state(3, n, n, seed=n + 7)
+    H.set_level(0, q0)
+    w.set_state(q0, level=0)
+    for l, b in enumerate(boxes):
+        H.regrid(l, b)
+        w.regrid(l, b)
+    for l in range(1, len(ratios) + 1):
+        nl = H.n[l][0]
+        ql = random_state(3, nl, nl, seed=200 + l) * 0.5
+        H.set_level(l, ql)
+        w.set_state(ql, level=l)
+    dt = dt_of(cfg)
+    # two coarse steps (the captured pair), then one eager step
+    for _ in range(2):
+        H.advance(0, dt)
+    w.advance(2, dt)
+    compare(w, H, "adjoint, two coarse steps")
+    H.advance(0, dt)
+    w.advance(1, dt)
+    compare(w, H, "adjoint, three coarse steps")
+
+
+def test_equation_switch_round_trip():
+    """Forward steps after switching back equal a forward-only instance's;
+    the forward-only entry points refuse the adjoint setting."""
+    n, ratios, boxes, bc = LAYOUTS[0]
+    cfg = cfg_of(n, bc, seed=3)
+    q0 = random_state(3, n, n, seed=5)
+    runs = []
+    for switch in (False, True):
+        w = wp.from_config(cfg, num_levels=2, ratios=tuple(ratios))
+        w.set_state(q0, level=0)
+        w.regrid(0, boxes[0])
+        if switch:
+            w.set_equation(True)
+            with pytest.raises(wp.WPError):
+                w.flag_richardson(dt_of(cfg), 1e-3)
+            w.set_equation(False)
+            assert w.get_equation() is False
+        w.advance(3, dt_of(cfg))
+        runs.append([w.get_state(level=0)] + [w.get_state(level=1, patch=k) for k in range(len(boxes[0]))])
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_set_equation_rejects_invalid_values():
+    n = 24
+    w = wp.from_config(cfg_of(n), num_levels=1)
+    with pytest.raises(wp.WPError):
+        w._check(wp.lib().wp_set_equation(w.h, 2))

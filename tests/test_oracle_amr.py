@@ -184,3 +184,54 @@ def test_nesting_mask_shrinks_inside_but_not_at_the_boundary():
     assert m[0, 0] and m[4, 8] and not m[5, 5] and not m[3, 9]
     whole = amr.nesting_mask([(0, 0, 20, 12)], 20, 12)
     assert whole.all()
+
+
+def test_adjoint_hierarchy_full_cover_equals_uniform_fine_adjoint_run():
+    """The hierarchy set to the adjoint system (Sec. 2 adjoint equation,
+    refined as Sec. 7 proposes): with a level-1 patch covering the domain
+    the fine level is the uniform fine-grid adjoint run, and differs from
+    the forward run of the same data (the transpose flux is really taken)."""
+    n, r = 12, 2
+    cfg = _cfg(n, seed=6)
+    q0 = random_state(3, n * r, n * r, seed=9)
+    dt = 0.4 * cfg["dx"] / float(np.sqrt(cfg["K"] / cfg["rho"]).max())
+    fine = dict(cfg, nx=n * r, ny=n * r, dx=cfg["dx"] / r, dy=cfg["dy"] / r,
+                rho=np.repeat(np.repeat(cfg["rho"], r, 0), r, 1), K=np.repeat(np.repeat(cfg["K"], r, 0), r, 1))
+    out = {}
+    for eq, which in (("adjoint", "acoustics_adj"), ("forward", "acoustics_fwd")):
+        H = amr.Hierarchy(cfg, [r], [[(0, 0, n * r, n * r)]], equation=eq)
+        H.set_level(1, q0)
+        H.set_level(0, q0.reshape(3, n, r, n, r).mean(axis=(2, 4)))
+        for _ in range(3):
+            H.advance(0, dt)
+        ref, _, _ = oracle.run(fine, which, q0, 3 * r, dt=dt / r)
+        assert np.array_equal(H.q[1], ref)
+        assert np.allclose(H.q[0], ref.reshape(3, n, r, n, r).mean(axis=(2, 4)), atol=1e-15)
+        out[eq] = H.q[1]
+    assert np.abs(out["adjoint"] - out["forward"]).max() > 1e-3
+
+
+def test_adjoint_hierarchy_keeps_the_duality_pairing():
+    """With constant media and walls on every side the adjoint of the
+    acoustics system is solved by (p, -u, -v) of a forward solution
+    (Sec. 2: the adjoint matrix is the forward one with the velocity signs
+    flipped, up to the coefficient scaling, which is 1 here).  A refined
+    hierarchy stepping the adjoint system must then return the sign-flipped
+    forward hierarchy, patch by patch, to round-off."""
+    n, r = 16, 2
+    cfg = dict(_cfg(n), rho=np.ones((n, n)), K=np.ones((n, n)), bc=[1, 1, 1, 1])
+    q0 = random_state(3, n, n, seed=2)
+    q1 = random_state(3, n * r, n * r, seed=3)
+    flip = np.array([1.0, -1.0, -1.0])[:, None, None]
+    dt = 0.8 * cfg["dx"]
+    Hs = {}
+    for eq, s in (("forward", 1.0), ("adjoint", flip)):
+        H = amr.Hierarchy(cfg, [r], [[(6, 4, 12, 20)]], equation=eq)
+        H.set_level(0, q0 * s)
+        H.set_level(1, q1 * s)
+        for _ in range(3):
+            H.advance(0, dt)
+        Hs[eq] = H
+    for l in range(2):
+        a, f = Hs["adjoint"].q[l], Hs["forward"].q[l]
+        assert np.allclose(a * flip, f, rtol=0, atol=1e-13 * np.abs(f).max())
