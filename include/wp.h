@@ -207,6 +207,19 @@ int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *
 int wp_num_snapshots(const wp_ctx *ctx);
 int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device);
 
+/* Install a snapshot store computed outside wp_adjoint_run, for instance the
+ * level-0 composite (after the fine-to-coarse average) of an adjoint solved on
+ * a refined hierarchy (wp_set_equation; Sec. 7, the adjoint refined too), in
+ * place of the store of the last adjoint run.  src: nsnap snapshots, each
+ * [m][ny0][nx0] at the level-0 resolution, in FP64 for WP_FP64 problems and
+ * FP32 otherwise (the store's own precision); snapshot n holds the adjoint
+ * at adjoint time n * ds, i.e. forward time t_f - n * ds with
+ * t_f = (nsnap - 1) * ds, as after wp_adjoint_run.  The data are copied
+ * (on_device: src is device memory); the caller keeps src.  WP_EINVAL for a
+ * null src, nsnap < 1 or ds <= 0; on any failure no store is left
+ * (wp_num_snapshots returns 0). */
+int wp_set_snapshots(wp_ctx *ctx, const void *src, int nsnap, double ds, int on_device);
+
 /* Adjoint-guided flag (Sec. 4; Sec. 5.1.2) on every patch of `level` at
  * forward time t: m(x) = max over the snapshots bracketing the window
  * [t, min(t + t_f - t_s, t_f)] of |qhat_n(x)^T q(x, t)|, qhat bilinear from the

@@ -90,6 +90,7 @@ _SIGS = {
     "wp_step_patches": (_I, [_P, _I, _D]),
     "wp_advance": (_I, [_P, _I, _D]),
     "wp_set_equation": (_I, [_P, _I]),
+    "wp_set_snapshots": (_I, [_P, _P, _I, _D, _I]),
     "wp_get_equation": (_I, [_P, ctypes.POINTER(_I)]),
     "wp_adjoint_run": (_I, [_P, ctypes.POINTER(wp_functional), ctypes.POINTER(wp_snapshot_spec)]),
     "wp_num_snapshots": (_I, [_P]),
@@ -350,6 +351,18 @@ class WavePatch:
 
     def num_snapshots(self):
         return lib().wp_num_snapshots(self.h)
+
+    def set_snapshots(self, snaps, ds):
+        """Install a snapshot store: snaps [nsnap, m, ny0, nx0] (the store's
+        precision: FP64 for FP64 problems, else FP32), snapshot n at adjoint
+        time n * ds."""
+        nx, ny, _ = self.level_info(0)
+        dt = np.float64 if self.precision == FP64 else np.float32
+        a = np.ascontiguousarray(snaps, dtype=dt)
+        if a.ndim != 4 or a.shape[1:] != (self.m, ny, nx):
+            raise ValueError(f"snapshots must be [nsnap, {self.m}, {ny}, {nx}], got {a.shape}")
+        p, dev = _ptr(a)
+        self._check(lib().wp_set_snapshots(self.h, p, a.shape[0], float(ds), dev))
 
     def get_snapshot(self, n):
         nx, ny, _ = self.level_info(0)

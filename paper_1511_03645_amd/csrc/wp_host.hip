@@ -1244,6 +1244,42 @@ extern "C" int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device)
     return WP_OK;
 }
 
+// A snapshot store computed elsewhere (e.g. the level-0 composite of an
+// adjoint solved with refinement) replaces the store of the last adjoint run.
+extern "C" int wp_set_snapshots(wp_ctx *ctx, const void *src, int nsnap, double ds, int on_device)
+{
+    if (!ctx) return WP_EINVAL;
+    if (!src) return wp_fail(ctx, WP_EINVAL, "null source");
+    if (nsnap < 1) return wp_fail(ctx, WP_EINVAL, "at least one snapshot is needed");
+    if (!(ds > 0.0) || !std::isfinite(ds)) return wp_fail(ctx, WP_EINVAL, "ds must be positive");
+    int rc;
+    if ((rc = wp_ensure_adjoint_level(ctx)) != WP_OK) return rc;
+    const Level &a = ctx->adj;
+    const size_t snap_bytes = (size_t)a.nx * a.ny * ctx->m * ctx->snap_esz();
+    const size_t bytes = (size_t)nsnap * snap_bytes;
+    if (ctx->snaps_cap < bytes) {
+        if (ctx->snaps) wp_dfree(ctx, ctx->snaps);
+        ctx->snaps_cap = 0;
+        ctx->nsnap = 0;
+        ctx->snaps = wp_dalloc(ctx, bytes);
+        if (!ctx->snaps) return wp_fail(ctx, WP_ENOMEM, "snapshot store (%d x %zu bytes)", nsnap, snap_bytes);
+        ctx->snaps_cap = bytes;
+    }
+    ctx->nsnap = 0;   // no store until the copy is complete
+    if (on_device) {
+        if (hipMemcpyAsync(ctx->snaps, src, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "snapshot store copy");
+    } else if ((rc = wp_host_copy(ctx, ctx->snaps, src, bytes, true)) != WP_OK) {
+        return rc;
+    }
+    ctx->snap_bytes = snap_bytes;
+    ctx->nsnap = nsnap;
+    ctx->snap_ds = ds;
+    ctx->adj_tf = ds * (nsnap - 1);
+    return WP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // flagging
 // ---------------------------------------------------------------------------

@@ -42,3 +42,4 @@ def test_status_strings_without_device():
     assert L.wp_step_patches(None, 0, 0.1) == wp.WP_EINVAL
     assert L.wp_set_equation(None, 1) == wp.WP_EINVAL
     assert L.wp_get_equation(None, None) == wp.WP_EINVAL
+    assert L.wp_set_snapshots(None, None, 1, 0.1, 0) == wp.WP_EINVAL

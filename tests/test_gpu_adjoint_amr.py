@@ -75,3 +75,61 @@ def test_set_equation_rejects_invalid_values():
     w = wp.from_config(cfg_of(n), num_levels=1)
     with pytest.raises(wp.WPError):
         w._check(wp.lib().wp_set_equation(w.h, 2))
+
+
+def test_refined_adjoint_snapshots_guide_forward_flags():
+    """The adjoint solved on a refined hierarchy, its level-0 composite kept
+    every coarse step as the snapshot store (wp_set_snapshots), and the
+    forward problem flagged with it (Sec. 4 inner product): snapshots and
+    flags equal the oracle's chain of the same steps."""
+    import oracle
+    n, r = 24, 4
+    cfg = cfg_of(n, (0, 1, 0, 0), seed=11)
+    phi = oracle.phi(dict(cfg, functional=dict(kind="disc", cx=0.3, cy=-0.2, r=0.35, component=0)))
+    H = amr.Hierarchy(cfg, [r], [], equation="adjoint")
+    w = wp.from_config(cfg, num_levels=2, ratios=(r,))
+    w.set_equation(True)
+    H.set_level(0, phi)
+    w.set_state(phi, level=0)
+    boxes = [(36, 28, 40, 36), (8, 8, 16, 16)]
+    H.regrid(0, boxes)
+    w.regrid(0, boxes)
+    dt = dt_of(cfg)
+    snaps_o, snaps_g = [H.q[0].copy()], [w.get_state(level=0)]
+    for _ in range(6):
+        H.advance(0, dt)
+        w.advance(1, dt)
+        snaps_o.append(H.q[0].copy())
+        snaps_g.append(w.get_state(level=0))
+    for k, (a, b) in enumerate(zip(snaps_g, snaps_o)):
+        close = np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+        assert close, f"adjoint composite snapshot {k}"
+    f = wp.from_config(cfg, num_levels=1)
+    f.set_snapshots(np.stack(snaps_g), dt)
+    assert f.num_snapshots() == 7
+    assert np.array_equal(f.get_snapshot(3), snaps_g[3])
+    q = random_state(3, n, n, seed=12)
+    f.set_state(q)
+    t_f = 6 * dt
+    for t, t_s in ((0.0, 0.0), (2.5 * dt, 1.0 * dt), (t_f, 0.0)):
+        _, m = oracle.flag(q, snaps_o, t, t_s, t_f, dt, 0.0)
+        tol = float(np.median(m[m > 0]))
+        fl_ref = m > tol
+        fl, cnt = f.flag_adjoint(0, tol, t, t_s, t_f)
+        band = np.abs(m - tol) <= 1e-12 * 3 * np.abs(q).max() * max(np.abs(x).max() for x in snaps_o)
+        assert np.array_equal(fl.astype(bool)[~band], fl_ref[~band]) and cnt == int(fl.sum()) > 0
+
+
+def test_set_snapshots_rejects_invalid_stores():
+    n = 24
+    f = wp.from_config(cfg_of(n), num_levels=1)
+    with pytest.raises(ValueError):
+        f.set_snapshots(np.zeros((2, 3, n, n + 1)), 0.1)
+    good = np.zeros((2, 3, n, n))
+    import ctypes
+    L = wp.lib()
+    assert L.wp_set_snapshots(f.h, ctypes.c_void_p(good.ctypes.data), 0, 0.1, 0) == wp.WP_EINVAL
+    assert L.wp_set_snapshots(f.h, ctypes.c_void_p(good.ctypes.data), 2, 0.0, 0) == wp.WP_EINVAL
+    assert L.wp_set_snapshots(f.h, None, 2, 0.1, 0) == wp.WP_EINVAL
+    f.set_snapshots(good, 0.1)
+    assert f.num_snapshots() == 2
