@@ -474,6 +474,95 @@ def richardson_compare(n0=256, ratio=4, regrid_every=2, buffer=3):
             "J_reference": J_ref, "reference": f"uniform {n0 * ratio}^2", "runs": runs}
 
 
+def adjoint_refinement_compare(n0=256, ratio=4, regrid_every=2, buffer=3, tols=(1e-3, 1e-4)):
+    """The adjoint solved with refinement, guided by forward checkpoints:
+    the forward run on the coarse grid keeps its state every snapshot
+    interval (the checkpoints); the adjoint hierarchy (coarse n0^2, one level
+    of ratio `ratio`) flags level 0 every `regrid_every` coarse steps with
+    its inner product against the checkpoint at the matching forward time and
+    rebuilds level 1.  J is taken from the adjoint as the integral of
+    qhat(T) . q(0) (fine cells where level 1 covers, coarse cells elsewhere),
+    against J of a uniform (n0 * ratio)^2 forward run averaged onto the
+    coarse grid; the coarse adjoint alone is the baseline.  Times are
+    wall-clock, checkpointing and regridding included."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import acoustics2d
+    cfg = acoustics2d(n=n0, seed=1)
+    N, every, dt, F, T = cfg["nsteps"], cfg["snap_every"], cfg["dt"], cfg["functional"], cfg["t_f"]
+    fine = acoustics2d(n=n0 * ratio, seed=1)
+    wf = wp.from_config(fine)
+    wf.set_step_pairs(16)
+    wf.set_state(fine["q0"])
+    wf.run_graph(N * ratio, dt / ratio, 1)
+    qf = wf.get_state()
+    del wf
+    wc = wp.from_config(cfg)
+    wc.set_state(qf.reshape(3, n0, ratio, n0, ratio).mean(axis=(2, 4)))
+    J_ref = wc.functional_value(F, 0)
+    del wc, qf
+    dA, dAf = cfg["dx"] * cfg["dy"], cfg["dx"] * cfg["dy"] / ratio ** 2
+    q0c, q0f = cfg["q0"], fine["q0"]
+
+    # the coarse adjoint alone
+    wu = wp.from_config(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wu.adjoint_run(F, dt, N, every)
+    torch.cuda.synchronize()
+    sec_u = time.perf_counter() - t0
+    J_u = float(np.sum(wu.get_snapshot(N // every) * q0c) * dA)
+    phi = wu.get_snapshot(0)
+    del wu
+
+    def refined(tol):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # forward checkpoints on the coarse grid
+        w = wp.from_config(cfg)
+        w.set_state(q0c)
+        chk = [w.get_state()]
+        for _ in range(N // every):
+            w.run_graph(every, dt, 1)
+            chk.append(w.get_state())
+        del w
+        a = wp.from_config(cfg, num_levels=2, ratios=(ratio,))
+        a.set_equation(True)
+        a.set_snapshots(np.stack(chk), every * dt)
+        a.set_state(phi, level=0)
+        # level 1 holds the same piecewise-constant phi where it is created
+        a.set_state(np.repeat(np.repeat(phi, ratio, 1), ratio, 2), level=1)
+        tau, cells = 0.0, 0
+        for _ in range(N // regrid_every):
+            a.flag_adjoint(0, tol, tau, T, T, want_flags=False, want_count=False)
+            a.regrid(0, None, buffer=buffer)
+            cells += sum(p[2] * p[3] for p in a.get_patches(1))
+            a.advance(regrid_every, dt)
+            tau += regrid_every * dt
+        qh0 = a.get_state(level=0)
+        covered = np.zeros((n0, n0), dtype=bool)
+        J = 0.0
+        for k, (i0, j0, nx, ny) in enumerate(a.get_patches(1)):
+            qh = a.get_state(level=1, patch=k)
+            J += float(np.sum(qh * q0f[:, j0:j0 + ny, i0:i0 + nx]) * dAf)
+            covered[j0 // ratio:(j0 + ny) // ratio, i0 // ratio:(i0 + nx) // ratio] = True
+        J += float(np.sum((qh0 * q0c)[:, ~covered]) * dA)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        del a
+        return {"tol": tol, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
+                "mean_cells_level1": cells / (N // regrid_every)}
+
+    runs = []
+    for tol in tols:
+        refined(tol)
+        runs.append(refined(tol))
+    return {"workload": f"acoustics2d adjoint, coarse {n0}^2, one level of ratio {ratio} rebuilt every "
+                        f"{regrid_every} coarse steps from forward checkpoints every {every} steps, buffer {buffer}",
+            "J_reference": J_ref, "reference": f"uniform {n0 * ratio}^2 forward",
+            "coarse_adjoint": {"seconds": sec_u, "J_rel_err": abs(J_u - J_ref) / abs(J_ref)}, "refined": runs}
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle on the host cores: a bounded sample of the same
     workload (full grid, a fixed number of forward and adjoint steps)."""
@@ -573,6 +662,11 @@ def main():
         out["amr_flagging"]["two_level"] = richardson_compare()
         for r in out["amr_flagging"]["two_level"]["runs"]:
             print(f"[bench]   2 levels {r['flag']:18s} tol {r['tol']:g}: J rel err {r['J_rel_err']:.2e}, "
+                  f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
+        out["amr_flagging"]["adjoint_refined"] = ar = adjoint_refinement_compare()
+        print(f"[bench]   coarse adjoint: J rel err {ar['coarse_adjoint']['J_rel_err']:.2e}", file=sys.stderr, flush=True)
+        for r in ar["refined"]:
+            print(f"[bench]   refined adjoint tol {r['tol']:g}: {r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
                   f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
