@@ -133,3 +133,23 @@ def test_set_snapshots_rejects_invalid_stores():
     assert L.wp_set_snapshots(f.h, None, 2, 0.1, 0) == wp.WP_EINVAL
     f.set_snapshots(good, 0.1)
     assert f.num_snapshots() == 2
+
+
+@pytest.mark.parametrize("nsteps", [4, 5])
+def test_single_level_adjoint_graph_matches_oracle(nsteps):
+    """wp_run_graph on a single-level instance set to the adjoint system (two
+    steps per launch where the level allows it, the last one alone for an
+    odd count) equals the oracle's adjoint run."""
+    import oracle
+    print(f"case single-level adjoint graph nsteps={nsteps}", flush=True)
+    n = 64
+    cfg = cfg_of(n, (0, 1, 2, 2), seed=4)
+    q0 = random_state(3, n, n, seed=6)
+    w = wp.from_config(cfg, num_levels=1)
+    w.set_equation(True)
+    w.set_state(q0)
+    dt = dt_of(cfg)
+    w.run_graph(nsteps, dt, 2)
+    ref, _, _ = oracle.run(cfg, "acoustics_adj", q0, 2 * nsteps, dt=dt)
+    got = w.get_state()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
