@@ -484,7 +484,10 @@ def adjoint_refinement_compare(n0=256, ratio=4, regrid_every=2, buffer=3, tols=(
     qhat(T) . q(0) (fine cells where level 1 covers, coarse cells elsewhere),
     against J of a uniform (n0 * ratio)^2 forward run averaged onto the
     coarse grid; the coarse adjoint alone is the baseline.  Times are
-    wall-clock, checkpointing and regridding included."""
+    wall-clock, checkpointing and regridding included.  Then the two-level
+    forward run is flagged with the coarse adjoint's snapshots and with the
+    refined adjoint's level-0 composites (first tolerance) and its J error
+    compared."""
     import torch
     import paper_1511_03645_amd as wp
     from wp_synth import acoustics2d
@@ -532,13 +535,15 @@ def adjoint_refinement_compare(n0=256, ratio=4, regrid_every=2, buffer=3, tols=(
         a.set_state(phi, level=0)
         # level 1 holds the same piecewise-constant phi where it is created
         a.set_state(np.repeat(np.repeat(phi, ratio, 1), ratio, 2), level=1)
-        tau, cells = 0.0, 0
-        for _ in range(N // regrid_every):
+        tau, cells, comp = 0.0, 0, [phi]
+        for k in range(N // regrid_every):
             a.flag_adjoint(0, tol, tau, T, T, want_flags=False, want_count=False)
             a.regrid(0, None, buffer=buffer)
             cells += sum(p[2] * p[3] for p in a.get_patches(1))
             a.advance(regrid_every, dt)
             tau += regrid_every * dt
+            if ((k + 1) * regrid_every) % every == 0:
+                comp.append(a.get_state(level=0))
         qh0 = a.get_state(level=0)
         covered = np.zeros((n0, n0), dtype=bool)
         J = 0.0
@@ -551,16 +556,43 @@ def adjoint_refinement_compare(n0=256, ratio=4, regrid_every=2, buffer=3, tols=(
         sec = time.perf_counter() - t0
         del a
         return {"tol": tol, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
-                "mean_cells_level1": cells / (N // regrid_every)}
+                "mean_cells_level1": cells / (N // regrid_every)}, np.stack(comp)
 
-    runs = []
+    def forward(snaps, tol=1e-3):
+        """The two-level forward run flagged by the adjoint every
+        `regrid_every` coarse steps (as in the two-level comparison), with
+        the snapshot store of the coarse adjoint run (snaps None) or the
+        given composites."""
+        w = wp.from_config(cfg, num_levels=2, ratios=(ratio,))
+        w.set_state(q0c)
+        if snaps is None:
+            w.adjoint_run(F, dt, N, every)
+        else:
+            w.set_snapshots(snaps, every * dt)
+        t, cells = 0.0, 0
+        for _ in range(N // regrid_every):
+            w.flag_adjoint(0, tol, t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+            w.regrid(0, None, buffer=buffer)
+            cells += sum(p[2] * p[3] for p in w.get_patches(1))
+            w.advance(regrid_every, dt)
+            t += regrid_every * dt
+        J = w.functional_value(F, 0)
+        del w
+        return {"snapshots": "coarse adjoint" if snaps is None else "refined adjoint composite", "tol": tol,
+                "J_rel_err": abs(J - J_ref) / abs(J_ref), "mean_cells_level1": cells / (N // regrid_every)}
+
+    runs, comp = [], None
     for tol in tols:
         refined(tol)
-        runs.append(refined(tol))
+        r, c = refined(tol)
+        runs.append(r)
+        comp = c if comp is None else comp
+    fwd = [forward(None), forward(comp)]
     return {"workload": f"acoustics2d adjoint, coarse {n0}^2, one level of ratio {ratio} rebuilt every "
                         f"{regrid_every} coarse steps from forward checkpoints every {every} steps, buffer {buffer}",
             "J_reference": J_ref, "reference": f"uniform {n0 * ratio}^2 forward",
-            "coarse_adjoint": {"seconds": sec_u, "J_rel_err": abs(J_u - J_ref) / abs(J_ref)}, "refined": runs}
+            "coarse_adjoint": {"seconds": sec_u, "J_rel_err": abs(J_u - J_ref) / abs(J_ref)}, "refined": runs,
+            "forward_flagged_with": fwd}
 
 
 def cpu_baseline(cfg):
@@ -667,6 +699,9 @@ def main():
         print(f"[bench]   coarse adjoint: J rel err {ar['coarse_adjoint']['J_rel_err']:.2e}", file=sys.stderr, flush=True)
         for r in ar["refined"]:
             print(f"[bench]   refined adjoint tol {r['tol']:g}: {r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
+                  f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
+        for r in ar["forward_flagged_with"]:
+            print(f"[bench]   forward flagged with the {r['snapshots']}: J rel err {r['J_rel_err']:.2e}, "
                   f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
