@@ -153,3 +153,32 @@ def test_single_level_adjoint_graph_matches_oracle(nsteps):
     ref, _, _ = oracle.run(cfg, "acoustics_adj", q0, 2 * nsteps, dt=dt)
     got = w.get_state()
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_fp32_adjoint_hierarchy_error_stated():
+    """The adjoint hierarchy in FP32 (three levels, ratios 2 and 4): error
+    against the FP64 oracle within 1e-5 of the state's scale, as for the
+    forward hierarchy."""
+    n, ratios = 16, [2, 4]
+    boxes = [[(4, 4, 20, 16)], [(24, 24, 40, 32)]]
+    cfg = cfg_of(n, (0, 0, 1, 0), seed=8)
+    print("case fp32 adjoint hierarchy", flush=True)
+    H = amr.Hierarchy(cfg, ratios, [], equation="adjoint")
+    w = wp.from_config(cfg, precision=wp.FP32, num_levels=3, ratios=tuple(ratios))
+    w.set_equation(True)
+    q0 = random_state(3, n, n, seed=9)
+    H.set_level(0, q0)
+    w.set_state(q0.astype(np.float32), level=0)
+    for l, b in enumerate(boxes):
+        H.regrid(l, b)
+        w.regrid(l, b)
+    dt = dt_of(cfg)
+    for _ in range(3):
+        H.advance(0, dt)
+    w.advance(3, dt)
+    scale = np.abs(H.q[0]).max()
+    err0 = np.abs(w.get_state(level=0).astype(np.float64) - H.q[0]).max() / scale
+    i0, j0, nx, ny = H.patches[2][0]
+    err2 = np.abs(w.get_state(level=2, patch=0) - H.q[2][:, j0:j0 + ny, i0:i0 + nx]).max() / scale
+    print(f"FP32 adjoint hierarchy: rel err level 0 {err0:.2e}, level 2 {err2:.2e}")
+    assert err0 < 1e-5 and err2 < 1e-5
