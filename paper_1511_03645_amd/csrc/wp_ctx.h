@@ -119,6 +119,7 @@ struct wp_ctx {
     int ff_parity = -1, ff_flip = 0;         // flip: canvas parity change of the run
     unsigned long long ff_gen = 0;
     const void *ff_snaps = nullptr;
+    double ff_store[2] = {0.0, 0.0};         // snapshot interval and count the window indices came from
     unsigned long long *ev_counts = nullptr;   // flagged cells per flag event (COUNT_SPAN entries each)
     size_t ev_counts_cap = 0;
     unsigned long long *stamps = nullptr;      // workgroup clocks of the timed steps

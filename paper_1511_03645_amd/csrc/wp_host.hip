@@ -1570,7 +1570,8 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
     }
     const double key[6] = {dt, (double)nsteps, (double)flag_every, tol, t_s, t_f};
     if (!ctx->ff_exec || memcmp(key, ctx->ff_key, sizeof key) != 0 || ctx->ff_t0 != lv.t ||
-        ctx->ff_parity != lv.cur || ctx->ff_gen != ctx->topo_gen || ctx->ff_snaps != ctx->snaps) {
+        ctx->ff_parity != lv.cur || ctx->ff_gen != ctx->topo_gen || ctx->ff_snaps != ctx->snaps ||
+        ctx->ff_store[0] != ctx->snap_ds || ctx->ff_store[1] != (double)ctx->nsnap) {
         if ((rc = wp_prepare_level(ctx, lv, dt)) != WP_OK) return rc;
         hipStream_t s;
         if ((rc = wp_graph_begin(ctx, s)) != WP_OK) return rc;
@@ -1606,6 +1607,8 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         ctx->ff_parity = par;
         ctx->ff_gen = ctx->topo_gen;
         ctx->ff_snaps = ctx->snaps;
+        ctx->ff_store[0] = ctx->snap_ds;
+        ctx->ff_store[1] = (double)ctx->nsnap;
     }
     if ((rc = wp_graph_launch(ctx, ctx->ff_exec)) != WP_OK) return rc;
     lv.cur ^= ctx->ff_flip;

@@ -191,3 +191,26 @@ def test_pair_fp32_error_stated():
         rel = np.abs(w.get_snapshot(k) - snaps_ref[k]).max() / np.abs(snaps_ref[k]).max()
         print(f"FP32 two-step adjoint snapshot {k}: max-abs error / max|q| = {rel:.3e}")
         assert rel < 1e-5
+
+
+def test_flagged_run_recaptured_when_the_store_spacing_changes():
+    """The captured flagged run holds the snapshot window of each flag event;
+    a new store in the same device block (an adjoint run with a longer
+    snapshot interval) must give the counts of a fresh instance."""
+    print("case flagged run after a store change", flush=True)
+    cfg = acoustics2d(n=128, seed=2)
+    dt, every = cfg["dt"], cfg["flag_every"]
+    N = cfg["nsteps"] - cfg["nsteps"] % every
+    assert cfg["nsteps"] % (2 * cfg["snap_every"]) == 0
+    a, b = wp.from_config(cfg), wp.from_config(cfg)
+    a.adjoint_run(cfg["functional"], dt, cfg["nsteps"], cfg["snap_every"])
+    a.set_state(cfg["q0"])
+    a.set_time(0.0)
+    a.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+    for w in (a, b):
+        w.adjoint_run(cfg["functional"], dt, cfg["nsteps"], 2 * cfg["snap_every"])
+        w.set_state(cfg["q0"])
+        w.set_time(0.0)
+    got, _ = a.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+    ref, _ = b.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+    assert got == ref and sum(ref) > 0
