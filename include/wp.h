@@ -252,8 +252,8 @@ int wp_flag_difference(wp_ctx *ctx, int level, double tol, uint8_t *flags, int o
 int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged);
 
 /* Richardson error estimate (the estimator Sec. 1 describes, and that the
- * closing Future Work section proposes to weight by the adjoint) on level 0
- * of a 2D acoustics instance with even nx0, ny0, from its current state:
+ * closing Future Work section proposes to weight by the adjoint) on a level
+ * of a 2D acoustics instance with even canvas sizes, from its current state:
  * two steps of dt on the same grid and one step of 2 dt on the 2x coarser
  * grid (each coarse cell takes the medium of its lower-left fine cell,
  * the state its 2 x 2 block mean), and per coarse cell and component
@@ -263,12 +263,20 @@ int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_d
  * takes max_k |E_k|; weighted = 1 takes max |qhat_n(x)^T E| over the
  * snapshots of the window of wp_flag_adjoint at time t.  A cell is flagged
  * iff the measure exceeds tol.  flags and *nflagged as for wp_flag_adjoint
- * (wp_regrid clusters them); estimate (optional, host, [m][ny0/2][nx0/2]
- * FP64) receives E.  The state and time of the instance are unchanged (the
- * steps run on internal copies of the problem, created on the first call).
- * WP_EINVAL for another level or kind, odd sizes, dt <= 0 or tol < 0;
- * WP_ECFL as for a step of dt; WP_ERANGE as for wp_flag_adjoint when
- * weighted. */
+ * (wp_regrid clusters them); estimate (optional, host, [m][ny/2][nx/2] of
+ * the level's canvas, FP64) receives E.  The state and time of the instance are unchanged (the
+ * steps run on internal copies of the problem at the level's resolution,
+ * kept until a call on another level).
+ * On a refined level (level > 0, dt that level's step, sizes those of its
+ * canvas) the whole canvas is stepped, and E is kept only on the coarse cells
+ * whose 2 x 2 block and every fine cell within 4 of it (the reach of the two
+ * fine steps and of the coarse step; clipped to the domain) lie in the
+ * level's patches: elsewhere E is 0 and no cell is flagged.  Cells outside
+ * the patches are never flagged.  Unweighted only there (the snapshots are
+ * at level-0 resolution).
+ * WP_EINVAL for a level out of range or without patches, weighted on a
+ * refined level, another kind, odd sizes, dt <= 0 or tol < 0; WP_ECFL as for
+ * a step of dt; WP_ERANGE as for wp_flag_adjoint when weighted. */
 int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
                        double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate);
 

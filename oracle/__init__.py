@@ -428,3 +428,37 @@ def richardson_flag(cfg, q, dt, tol, snaps=None, t=0.0, t_s=0.0, t_f=0.0, ds=1.0
         m = richardson_measure(E, snaps, n_lo, n_hi)
     return (m > tol).astype(np.uint8), m, E
 
+
+
+def richardson_valid(patches, nx, ny, margin=4):
+    """Coarse cells (half the resolution of a refined level of nx x ny cells)
+    whose estimate reads only cells of the level's patches: every fine cell
+    within `margin` (square neighbourhood, clipped to the domain) of the
+    cell's 2 x 2 block lies in a patch.  The margin is the reach of two fine
+    steps, or of one coarse step, of the 2D update (two cells per step)."""
+    inside = np.zeros((ny, nx), dtype=bool)
+    for (i0, j0, w, h) in patches:
+        inside[j0:j0 + h, i0:i0 + w] = True
+    NX, NY = nx // 2, ny // 2
+    valid = np.zeros((NY, NX), dtype=bool)
+    for J in range(NY):
+        for I in range(NX):
+            j0, j1 = max(2 * J - margin, 0), min(2 * J + 1 + margin, ny - 1)
+            i0, i1 = max(2 * I - margin, 0), min(2 * I + 1 + margin, nx - 1)
+            valid[J, I] = inside[j0:j1 + 1, i0:i1 + 1].all()
+    return valid
+
+
+def richardson_flag_level(cfg_l, q_l, dt, tol, patches):
+    """The unweighted Richardson flag on a refined level: cfg_l is the problem
+    at the level's resolution over the whole domain, q_l its canvas.  The
+    estimate is kept on the coarse cells richardson_valid names (zero
+    elsewhere, where it would read cells outside the patches) and flags are
+    set inside the patches only.  Returns flags, measure, estimate."""
+    E = richardson_estimate(cfg_l, q_l, dt) * richardson_valid(patches, cfg_l["nx"], cfg_l["ny"])[None]
+    m = richardson_measure(E)
+    inside = np.zeros(m.shape, dtype=bool)
+    for (i0, j0, w, h) in patches:
+        inside[j0:j0 + h, i0:i0 + w] = True
+    m = np.where(inside, m, 0.0)
+    return (m > tol).astype(np.uint8), m, E

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "march_common.h"
+#include "richardson_level.h"
 
 namespace wp {
 namespace {
@@ -494,6 +495,30 @@ void launch_richardson(const T *coarse, long long ccs, const T *fine, long long 
                        (const T *)snaps, sstride, hcs, n_lo, n_hi, tol, tiles, flags, count);
 }
 
+__global__ void mask_estimate_kernel(double *__restrict__ E, const uint8_t *__restrict__ valid, long long n, int m)
+{
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x)
+        if (!valid[c])
+            for (int k = 0; k < m; ++k) E[(long long)k * n + c] = 0.0;
+}
+
+template <typename T>
+void launch_richardson_masked(const T *coarse, long long ccs, const T *fine, long long fcs, int nx, int NX, int NY,
+                              int m, double denom, double *E, const uint8_t *valid, double tol, const Tile *tiles,
+                              int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s)
+{
+    const long long n = (long long)NX * NY;
+    if (n > 0) {
+        const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+        hipLaunchKernelGGL((richardson_estimate_kernel<T>), dim3(blocks), dim3(256), 0, s, coarse, ccs, fine, fcs, nx,
+                           NX, NY, m, denom, E);
+        hipLaunchKernelGGL(mask_estimate_kernel, dim3(blocks), dim3(256), 0, s, E, valid, n, m);
+    }
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((richardson_flag_kernel<T>), dim3(ntiles), dim3(256), 0, s, E, NX, NY, m, nx, (const T *)nullptr,
+                       0LL, 0LL, 0, -1, tol, tiles, flags, count);
+}
+
 void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s)
 {
     if (n <= 0) return;
@@ -538,5 +563,12 @@ template void launch_richardson<double>(const double *, long long, const double 
 template void launch_richardson<float>(const float *, long long, const float *, long long, int, int, int, int, double,
                                        double *, const void *, long long, long long, int, int, double, const Tile *,
                                        int, uint8_t *, unsigned long long *, hipStream_t);
+
+template void launch_richardson_masked<double>(const double *, long long, const double *, long long, int, int, int,
+                                               int, double, double *, const uint8_t *, double, const Tile *, int,
+                                               uint8_t *, unsigned long long *, hipStream_t);
+template void launch_richardson_masked<float>(const float *, long long, const float *, long long, int, int, int, int,
+                                              double, double *, const uint8_t *, double, const Tile *, int, uint8_t *,
+                                              unsigned long long *, hipStream_t);
 
 }  // namespace wp

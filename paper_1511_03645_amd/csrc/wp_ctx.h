@@ -143,6 +143,9 @@ struct wp_ctx {
     wp_ctx *rich[2] = {nullptr, nullptr};
     double *richE = nullptr;
     size_t richE_cap = 0;
+    int rich_level = -1;                 // level the helpers were made for
+    uint8_t *rich_valid = nullptr;       // coarse cells kept on a refined level
+    size_t rich_valid_cap = 0;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };
 

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "richardson_level.h"
 #include "wp_ctx.h"
 
 using namespace wp;
@@ -1424,16 +1425,26 @@ extern "C" int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flag
 // resolution, one step of 2 dt from its 2 x 2 block means on a copy at half
 // the resolution (each coarse cell with the medium of its lower-left fine
 // cell); E = (coarse - block mean of fine) / (2^(p+1) - 2).
-static int rich_helper(wp_ctx *ctx, int which, wp_ctx *&out)
+// Single-level copy of the problem at the resolution of `level` (which 0) or
+// half of it (which 1); cell (i, j) takes the medium of the level cell
+// (f i, f j), itself that of the level-0 cell containing it.
+static int rich_helper(wp_ctx *ctx, int which, int level, wp_ctx *&out)
 {
-    if (out) return out->stream == ctx->stream ? WP_OK : wp_set_stream(out, ctx->stream);
-    const int nx = ctx->grid.nx0, ny = ctx->grid.ny0;
+    if (out && ctx->rich_level == level)
+        return out->stream == ctx->stream ? WP_OK : wp_set_stream(out, ctx->stream);
+    if (out) {
+        wp_destroy(out);
+        out = nullptr;
+    }
+    int R = 1;
+    for (int l = 1; l <= level; ++l) R *= ctx->L[l].ratio;
+    const int nx0 = ctx->grid.nx0, nx = ctx->L[level].nx, ny = ctx->L[level].ny;
     const int f = which == 0 ? 1 : 2;
     const int hx = nx / f, hy = ny / f;
     std::vector<double> rho((size_t)hx * hy), K((size_t)hx * hy);
     for (int j = 0; j < hy; ++j)
         for (int i = 0; i < hx; ++i) {
-            const uint8_t m = ctx->mat0[(size_t)(f * j) * nx + f * i];
+            const uint8_t m = ctx->mat0[(size_t)(f * j / R) * nx0 + f * i / R];
             rho[(size_t)j * hx + i] = ctx->rho[m];
             K[(size_t)j * hx + i] = ctx->K[m];
         }
@@ -1447,24 +1458,51 @@ static int rich_helper(wp_ctx *ctx, int which, wp_ctx *&out)
     return WP_OK;
 }
 
+// Coarse cells (half the resolution of a refined level) whose estimate only
+// reads cells of the level's patches: the 2 x 2 block of fine cells and
+// every fine cell within `margin` of it (square neighbourhood, clipped to
+// the domain) lie in the patches.  Two fine steps and one coarse step of the
+// 2D update reach two cells per step, four fine cells in all.
+static void rich_valid(const Level &lv, int margin, std::vector<uint8_t> &valid)
+{
+    const int nx = lv.nx, ny = lv.ny;
+    std::vector<uint8_t> outside((size_t)nx * ny, 1), bad;
+    for (const wp_patch &p : lv.patches)
+        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&outside[(size_t)j * nx + p.ilo], p.nx, (uint8_t)0);
+    wp_dilate(outside, nx, ny, margin, bad);
+    const int NX = nx / 2, NY = ny / 2;
+    valid.assign((size_t)NX * NY, 0);
+    for (int J = 0; J < NY; ++J)
+        for (int I = 0; I < NX; ++I) {
+            bool ok = true;
+            for (int b = 0; b < 2 && ok; ++b)
+                for (int a = 0; a < 2 && ok; ++a) ok = !bad[(size_t)(2 * J + b) * nx + 2 * I + a];
+            valid[(size_t)J * NX + I] = ok;
+        }
+}
+
 extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
                                   double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate)
 {
     if (!ctx) return WP_EINVAL;
-    if (level != 0) return wp_fail(ctx, WP_EINVAL, "the Richardson estimate is taken on level 0");
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level %d out of range", level);
+    if (level > 0 && weighted)
+        return wp_fail(ctx, WP_EINVAL, "the adjoint-weighted estimate is taken on level 0");
+    if (ctx->L[level].patches.empty()) return wp_fail(ctx, WP_EINVAL, "level %d has no patches", level);
     if (ctx->equation != 0)
         return wp_fail(ctx, WP_ESTATE, "the Richardson estimate is for the forward system");
     if (!ctx->is_acoustics || !ctx->kind2d) return wp_fail(ctx, WP_EINVAL, "the Richardson estimate is for 2D acoustics");
-    if (ctx->grid.nx0 % 2 || ctx->grid.ny0 % 2 || ctx->grid.nx0 < 4 || ctx->grid.ny0 < 4)
+    if (ctx->L[level].nx % 2 || ctx->L[level].ny % 2 || ctx->L[level].nx < 4 || ctx->L[level].ny < 4)
         return wp_fail(ctx, WP_EINVAL, "the Richardson estimate needs even grid sizes of at least 4");
     if (!(dt > 0.0)) return wp_fail(ctx, WP_EINVAL, "dt must be positive");
     if (!(tol >= 0.0)) return wp_fail(ctx, WP_EINVAL, "tolerance must be non-negative");
     int rc, n_lo = 0, n_hi = -1;
     if (weighted && (rc = wp_window(ctx, t, t_s, t_f, n_lo, n_hi)) != WP_OK) return rc;
-    Level &lv = ctx->L[0];
+    Level &lv = ctx->L[level];
     if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
     for (int k = 0; k < 2; ++k)
-        if ((rc = rich_helper(ctx, k, ctx->rich[k])) != WP_OK) return rc;
+        if ((rc = rich_helper(ctx, k, level, ctx->rich[k])) != WP_OK) return rc;
+    ctx->rich_level = level;
     wp_ctx *F = ctx->rich[0], *C = ctx->rich[1];
     Level &fl = F->L[0], &cl = C->L[0];
     const int nx = lv.nx, ny = lv.ny, NX = nx / 2, NY = ny / 2, m = ctx->m;
@@ -1491,14 +1529,31 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
     const double denom = (double)((1 << (ctx->prob.order + 1)) - 2);
     const long long hcs = cs, sstride = cs * m;
     const void *snaps = weighted ? ctx->snaps : nullptr;
-    if (ctx->esz == 8)
+    if (level > 0) {
+        std::vector<uint8_t> valid;
+        rich_valid(lv, 4, valid);
+        void *vd = ctx->rich_valid;
+        rc = wp_upload(ctx, valid.data(), valid.size(), vd, ctx->rich_valid_cap, "Richardson mask");
+        ctx->rich_valid = (uint8_t *)vd;
+        if (rc != WP_OK) return rc;
+        launch_fill_u8(lv.flags, cs, 0, s);
+        if (ctx->esz == 8)
+            launch_richardson_masked<double>((const double *)cl.q[cl.cur], ccs, (const double *)fl.q[fl.cur], cs, nx,
+                                             NX, NY, m, denom, ctx->richE, ctx->rich_valid, tol, lv.ftiles_dev,
+                                             lv.nftiles, lv.flags, ctx->count, s);
+        else
+            launch_richardson_masked<float>((const float *)cl.q[cl.cur], ccs, (const float *)fl.q[fl.cur], cs, nx, NX,
+                                            NY, m, denom, ctx->richE, ctx->rich_valid, tol, lv.ftiles_dev, lv.nftiles,
+                                            lv.flags, ctx->count, s);
+    } else if (ctx->esz == 8) {
         launch_richardson<double>((const double *)cl.q[cl.cur], ccs, (const double *)fl.q[fl.cur], cs, nx, NX, NY, m,
                                   denom, ctx->richE, snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
                                   lv.flags, ctx->count, s);
-    else
+    } else {
         launch_richardson<float>((const float *)cl.q[cl.cur], ccs, (const float *)fl.q[fl.cur], cs, nx, NX, NY, m,
                                  denom, ctx->richE, snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
                                  lv.flags, ctx->count, s);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "Richardson launch: %s", hipGetErrorString(e));
     lv.flags_valid = true;

@@ -1,0 +1,64 @@
+"""GPU parity of the Richardson estimate on refined levels (Sec. 1 names the
+estimator; the Future Work section proposes it as a flag criterion) against
+the oracle, through the C ABI: the estimate is kept where it reads only
+patch cells, flags are set inside the patches.
+
+Bar (FP64): the kept estimate within 1e-12 of its scale, zero elsewhere;
+flags bit-exact outside the threshold band."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1511_03645_amd as wp
+from wp_synth import random_state
+
+from test_gpu_amr import LAYOUTS, build, dt_of
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(LAYOUTS[0], 1), (LAYOUTS[1], 1), (LAYOUTS[2], 1), (LAYOUTS[2], 2)]
+
+
+@pytest.mark.parametrize("layout,level", CASES)
+def test_refined_level_richardson_matches_oracle(layout, level):
+    n, ratios, boxes, bc = layout
+    print(f"case richardson level {level} n={n} ratios={ratios} bc={bc}", flush=True)
+    cfg, H, w = build(n, ratios, boxes, bc, seed=n + 3)
+    R = int(np.prod(ratios[:level]))
+    nl = n * R
+    ql = random_state(3, nl, nl, seed=70 + level)
+    H.set_level(level, ql)
+    w.set_state(ql, level=level)
+    cfg_l = dict(cfg, nx=nl, ny=nl, dx=cfg["dx"] / R, dy=cfg["dy"] / R,
+                 rho=np.repeat(np.repeat(cfg["rho"], R, 0), R, 1), K=np.repeat(np.repeat(cfg["K"], R, 0), R, 1))
+    dt = dt_of(cfg) / R
+    patches = H.patches[level]
+    _, m_ref, E_ref = oracle.richardson_flag_level(cfg_l, ql, dt, 0.0, patches)
+    tol = float(np.median(m_ref[m_ref > 0]))
+    fl_ref = m_ref > tol
+    fl, cnt, E = w.flag_richardson(dt, tol, level=level, want_estimate=True)
+    valid = oracle.richardson_valid(patches, nl, nl)
+    scale = np.abs(E_ref).max()
+    assert np.abs(E - E_ref)[:, valid].max() <= 1e-12 * scale
+    assert np.all(E[:, ~valid] == 0.0)
+    band = np.abs(m_ref - tol) <= 1e-12 * scale
+    assert np.array_equal(fl.astype(bool)[~band], fl_ref[~band])
+    assert cnt == int(fl.sum()) > 0
+
+
+def test_refined_level_richardson_rejects_weighting_and_empty_levels():
+    n, ratios, boxes, bc = LAYOUTS[2]
+    cfg, H, w = build(n, ratios, boxes[:1], bc, seed=1)
+    dt = dt_of(cfg) / ratios[0]
+    with pytest.raises(wp.WPError):
+        w.flag_richardson(dt, 1e-3, weighted=True, level=1)
+    with pytest.raises(wp.WPError):
+        w.flag_richardson(dt / ratios[1], 1e-3, level=2)
+    # level 0 after a refined level: the helpers follow the level
+    w.flag_richardson(dt, 1e-3, level=1)
+    _, m0, _ = oracle.richardson_flag(cfg, H.q[0], dt * ratios[0], 0.0)
+    tol = float(np.median(m0[m0 > 0]))
+    fl0, cnt0, _ = w.flag_richardson(dt * ratios[0], tol, level=0)
+    band = np.abs(m0 - tol) <= 1e-12 * np.abs(m0).max()
+    assert np.array_equal(fl0.astype(bool)[~band], (m0 > tol)[~band])
+    assert cnt0 == int(fl0.sum()) > 0

@@ -347,3 +347,37 @@ def test_richardson_measure_weights_the_parent_estimate():
             e = E[:, j // 2, i // 2]
             assert m0[j, i] == max(abs(x) for x in e)
             assert m1[j, i] == max(abs(float(np.sum(snaps[n, :, j, i] * e))) for n in (1, 2))
+
+
+def test_refined_level_estimate_ignores_cells_outside_the_patches():
+    """On a refined level the kept estimate depends on the patches' cells
+    only: rewriting every cell outside the patches leaves it unchanged, so
+    the margin covers the reach of the two fine steps and the coarse step.
+    With even-aligned patches a margin of 3 keeps the same cells; with 2 the
+    kept estimate changes (the margin is needed)."""
+    from wp_synth import random_media, random_state
+    n = 32
+    rho, K = random_media(n, n, seed=3)
+    cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=-1.0, xhi=1.0, ylo=-1.0, yhi=1.0, dx=2.0 / n, dy=2.0 / n,
+               rho=rho, K=K, bc=[0, 1, 0, 0], order=2, limiter=1, transverse=1, g=9.81)
+    patches = [(4, 6, 14, 16), (18, 6, 10, 10), (0, 24, 12, 8)]
+    inside = np.zeros((n, n), dtype=bool)
+    for (i0, j0, w, h) in patches:
+        inside[j0:j0 + h, i0:i0 + w] = True
+    q = random_state(3, n, n, seed=4)
+    q2 = np.where(inside[None], q, random_state(3, n, n, seed=5) * 3.0)
+    dt = 0.8 * cfg["dx"] / float(np.sqrt(K / rho).max())
+    E1 = oracle.richardson_estimate(cfg, q, dt)
+    E2 = oracle.richardson_estimate(cfg, q2, dt)
+    for margin, must_hold in ((4, True), (2, False)):
+        v = oracle.richardson_valid(patches, n, n, margin)
+        assert v.any()
+        same = np.array_equal(E1[:, v], E2[:, v])
+        assert same == must_hold, f"margin {margin}"
+    # a patch over the whole level keeps everything, and the level flag is
+    # then the level-0 flag of that problem
+    v = oracle.richardson_valid([(0, 0, n, n)], n, n)
+    assert v.all()
+    fl, m, E = oracle.richardson_flag_level(cfg, q, dt, 1e-3, [(0, 0, n, n)])
+    fl0, m0, E0 = oracle.richardson_flag(cfg, q, dt, 1e-3)
+    assert np.array_equal(E, E0) and np.array_equal(fl, fl0)
