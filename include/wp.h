@@ -272,11 +272,12 @@ int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_d
  * whose 2 x 2 block and every fine cell within 4 of it (the reach of the two
  * fine steps and of the coarse step; clipped to the domain) lie in the
  * level's patches: elsewhere E is 0 and no cell is flagged.  Cells outside
- * the patches are never flagged.  Unweighted only there (the snapshots are
- * at level-0 resolution).
- * WP_EINVAL for a level out of range or without patches, weighted on a
- * refined level, another kind, odd sizes, dt <= 0 or tol < 0; WP_ECFL as for
- * a step of dt; WP_ERANGE as for wp_flag_adjoint when weighted. */
+ * the patches are never flagged.  Weighted, each cell's parent E meets the
+ * snapshots taken bilinearly at the level's cell centres, as in
+ * wp_flag_adjoint on that level.
+ * WP_EINVAL for a level out of range or without patches, another kind, odd
+ * sizes, dt <= 0 or tol < 0; WP_ECFL as for a step of dt; WP_ESTATE or
+ * WP_ERANGE as for wp_flag_adjoint when weighted. */
 int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
                        double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate);
 

@@ -449,14 +449,22 @@ def richardson_valid(patches, nx, ny, margin=4):
     return valid
 
 
-def richardson_flag_level(cfg_l, q_l, dt, tol, patches):
-    """The unweighted Richardson flag on a refined level: cfg_l is the problem
-    at the level's resolution over the whole domain, q_l its canvas.  The
-    estimate is kept on the coarse cells richardson_valid names (zero
-    elsewhere, where it would read cells outside the patches) and flags are
-    set inside the patches only.  Returns flags, measure, estimate."""
+def richardson_flag_level(cfg_l, q_l, dt, tol, patches, snaps=None, t=0.0, t_s=0.0, t_f=0.0, ds=1.0, ratio=1):
+    """The Richardson flag on a refined level: cfg_l is the problem at the
+    level's resolution over the whole domain, q_l its canvas.  The estimate
+    is kept on the coarse cells richardson_valid names (zero elsewhere,
+    where it would read cells outside the patches) and flags are set inside
+    the patches only.  With snaps (adjoint snapshots at level-0 resolution,
+    `ratio` the level's refinement over level 0) each cell's parent estimate
+    is weighted as in the adjoint flag, the snapshots taken bilinearly at the
+    level's cell centres.  Returns flags, measure, estimate."""
     E = richardson_estimate(cfg_l, q_l, dt) * richardson_valid(patches, cfg_l["nx"], cfg_l["ny"])[None]
-    m = richardson_measure(E)
+    if snaps is None:
+        m = richardson_measure(E)
+    else:
+        n_lo, n_hi = snapshot_window(t, t_s, t_f, ds, len(snaps))
+        Ef = np.repeat(np.repeat(E, 2, axis=1), 2, axis=2)
+        m = flag_measure(Ef, snaps, n_lo, n_hi, ratio=ratio)
     inside = np.zeros(m.shape, dtype=bool)
     for (i0, j0, w, h) in patches:
         inside[j0:j0 + h, i0:i0 + w] = True

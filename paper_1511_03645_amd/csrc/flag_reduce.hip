@@ -519,6 +519,25 @@ void launch_richardson_masked(const T *coarse, long long ccs, const T *fine, lon
                        0LL, 0LL, 0, -1, tol, tiles, flags, count);
 }
 
+__global__ void expand_estimate_kernel(const double *__restrict__ E, int NX, int NY, int m, double *__restrict__ Ef,
+                                       int nx, int ny)
+{
+    const long long n = (long long)nx * ny, nc = (long long)NX * NY;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)(c / nx);
+        const long long par = (long long)(j / 2) * NX + i / 2;
+        for (int k = 0; k < m; ++k) Ef[(long long)k * n + c] = E[(long long)k * nc + par];
+    }
+}
+
+void launch_expand_estimate(const double *E, int NX, int NY, int m, double *Ef, int nx, int ny, hipStream_t s)
+{
+    const long long n = (long long)nx * ny;
+    if (n <= 0) return;
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(expand_estimate_kernel, dim3(blocks), dim3(256), 0, s, E, NX, NY, m, Ef, nx, ny);
+}
+
 void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s)
 {
     if (n <= 0) return;
@@ -570,5 +589,9 @@ template void launch_richardson_masked<double>(const double *, long long, const 
 template void launch_richardson_masked<float>(const float *, long long, const float *, long long, int, int, int, int,
                                               double, double *, const uint8_t *, double, const Tile *, int, uint8_t *,
                                               unsigned long long *, hipStream_t);
+
+template void launch_flag<double, float>(const double *, long long, int, int, int, const float *, long long,
+                                         long long, int, int, int, int, int, double, const Tile *, int, uint8_t *,
+                                         unsigned long long *, hipStream_t);
 
 }  // namespace wp

@@ -14,4 +14,8 @@ void launch_richardson_masked(const T *coarse, long long ccs, const T *fine, lon
                               int m, double denom, double *E, const uint8_t *valid, double tol, const Tile *tiles,
                               int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
 
+// Ef [m][ny][nx] (the level's canvas) = E of each cell's 2 x 2 parent, so
+// that the adjoint flag of launch_flag weights the estimate.
+void launch_expand_estimate(const double *E, int NX, int NY, int m, double *Ef, int nx, int ny, hipStream_t s);
+
 }  // namespace wp

@@ -146,6 +146,8 @@ struct wp_ctx {
     int rich_level = -1;                 // level the helpers were made for
     uint8_t *rich_valid = nullptr;       // coarse cells kept on a refined level
     size_t rich_valid_cap = 0;
+    double *richEf = nullptr;            // the estimate on a refined level's cells (weighted flag)
+    size_t richEf_cap = 0;
     size_t snap_esz() const { return prob.precision == WP_FP64 ? 8 : 4; }
 };
 

@@ -1486,8 +1486,6 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
 {
     if (!ctx) return WP_EINVAL;
     if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level %d out of range", level);
-    if (level > 0 && weighted)
-        return wp_fail(ctx, WP_EINVAL, "the adjoint-weighted estimate is taken on level 0");
     if (ctx->L[level].patches.empty()) return wp_fail(ctx, WP_EINVAL, "level %d has no patches", level);
     if (ctx->equation != 0)
         return wp_fail(ctx, WP_ESTATE, "the Richardson estimate is for the forward system");
@@ -1537,14 +1535,40 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
         ctx->rich_valid = (uint8_t *)vd;
         if (rc != WP_OK) return rc;
         launch_fill_u8(lv.flags, cs, 0, s);
+        // weighted: the estimate alone here, its flag below
+        const int nt = weighted ? 0 : lv.nftiles;
         if (ctx->esz == 8)
             launch_richardson_masked<double>((const double *)cl.q[cl.cur], ccs, (const double *)fl.q[fl.cur], cs, nx,
-                                             NX, NY, m, denom, ctx->richE, ctx->rich_valid, tol, lv.ftiles_dev,
-                                             lv.nftiles, lv.flags, ctx->count, s);
+                                             NX, NY, m, denom, ctx->richE, ctx->rich_valid, tol, lv.ftiles_dev, nt,
+                                             lv.flags, ctx->count, s);
         else
             launch_richardson_masked<float>((const float *)cl.q[cl.cur], ccs, (const float *)fl.q[fl.cur], cs, nx, NX,
-                                            NY, m, denom, ctx->richE, ctx->rich_valid, tol, lv.ftiles_dev, lv.nftiles,
+                                            NY, m, denom, ctx->richE, ctx->rich_valid, tol, lv.ftiles_dev, nt,
                                             lv.flags, ctx->count, s);
+        if (weighted) {
+            // each fine cell carries its parent's E; the adjoint flag then
+            // interpolates the snapshots to the level's cells
+            const size_t fbytes = sizeof(double) * (size_t)cs * m;
+            if (ctx->richEf_cap < fbytes) {
+                if (ctx->richEf) wp_dfree(ctx, ctx->richEf);
+                ctx->richEf = (double *)wp_dalloc(ctx, fbytes);
+                ctx->richEf_cap = ctx->richEf ? fbytes : 0;
+                if (!ctx->richEf) return wp_fail(ctx, WP_ENOMEM, "Richardson estimate on the level's cells");
+            }
+            launch_expand_estimate(ctx->richE, NX, NY, m, ctx->richEf, nx, ny, s);
+            int R = 1;
+            for (int l = 1; l <= level; ++l) R *= ctx->L[l].ratio;
+            const Level &a0 = ctx->adj;
+            const long long acs = (long long)a0.nx * a0.ny;
+            if (ctx->esz == 8)
+                launch_flag<double, double>(ctx->richEf, cs, nx, ny, m, (const double *)ctx->snaps, acs * m, acs, a0.nx,
+                                            a0.ny, R, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count,
+                                            s);
+            else
+                launch_flag<double, float>(ctx->richEf, cs, nx, ny, m, (const float *)ctx->snaps, acs * m, acs, a0.nx,
+                                           a0.ny, R, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles, lv.flags, ctx->count,
+                                           s);
+        }
     } else if (ctx->esz == 8) {
         launch_richardson<double>((const double *)cl.q[cl.cur], ccs, (const double *)fl.q[fl.cur], cs, nx, NX, NY, m,
                                   denom, ctx->richE, snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,

@@ -119,8 +119,6 @@ def test_richardson_errors():
     w.set_state(random_state(3, 32, 32, seed=1))
     with pytest.raises(wp.WPError, match="no patches"):
         w.flag_richardson(dt_of(cfg) / 2, 0.1, level=1)
-    with pytest.raises(wp.WPError, match="level 0"):
-        w.flag_richardson(dt_of(cfg) / 2, 0.1, weighted=True, level=1)
     with pytest.raises(wp.WPError, match="out of range"):
         w.flag_richardson(dt_of(cfg), 0.1, level=2)
     with pytest.raises(wp.WPError, match="positive"):

@@ -46,12 +46,12 @@ def test_refined_level_richardson_matches_oracle(layout, level):
     assert cnt == int(fl.sum()) > 0
 
 
-def test_refined_level_richardson_rejects_weighting_and_empty_levels():
+def test_refined_level_richardson_rejects_missing_snapshots_and_empty_levels():
     n, ratios, boxes, bc = LAYOUTS[2]
     cfg, H, w = build(n, ratios, boxes[:1], bc, seed=1)
     dt = dt_of(cfg) / ratios[0]
     with pytest.raises(wp.WPError):
-        w.flag_richardson(dt, 1e-3, weighted=True, level=1)
+        w.flag_richardson(dt, 1e-3, weighted=True, level=1)   # no adjoint run yet
     with pytest.raises(wp.WPError):
         w.flag_richardson(dt / ratios[1], 1e-3, level=2)
     # level 0 after a refined level: the helpers follow the level
@@ -62,3 +62,36 @@ def test_refined_level_richardson_rejects_weighting_and_empty_levels():
     band = np.abs(m0 - tol) <= 1e-12 * np.abs(m0).max()
     assert np.array_equal(fl0.astype(bool)[~band], (m0 > tol)[~band])
     assert cnt0 == int(fl0.sum()) > 0
+
+
+def test_refined_level_weighted_richardson_matches_oracle():
+    """The adjoint-weighted estimate on level 1 (ratio 2): each cell's parent
+    estimate against the snapshots interpolated to the level's cells."""
+    from wp_synth import acoustics2d
+    cfg = acoustics2d(n=32, seed=1)
+    n, N, every, dt0 = cfg["nx"], cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    r = 2
+    print(f"case richardson weighted level 1 n={n}", flush=True)
+    snaps, _ = oracle.adjoint_run(cfg)
+    w = wp.from_config(cfg, num_levels=2, ratios=(r,))
+    w.adjoint_run(cfg["functional"], dt0, N, every)
+    w.set_state(cfg["q0"])
+    boxes = [(8, 8, 40, 32), (48, 16, 12, 24)]
+    w.regrid(0, boxes)
+    nl = n * r
+    ql = random_state(3, nl, nl, seed=5)
+    w.set_state(ql, level=1)
+    cfg_l = dict(cfg, nx=nl, ny=nl, dx=cfg["dx"] / r, dy=cfg["dy"] / r,
+                 rho=np.repeat(np.repeat(cfg["rho"], r, 0), r, 1), K=np.repeat(np.repeat(cfg["K"], r, 0), r, 1))
+    dt, t = dt0 / r, 0.5 * cfg["t_f"]
+    _, m_ref, E_ref = oracle.richardson_flag_level(cfg_l, ql, dt, 0.0, boxes, snaps=snaps, t=t, t_s=cfg["t_s"],
+                                                   t_f=cfg["t_f"], ds=every * dt0, ratio=r)
+    tol = float(np.median(m_ref[m_ref > 0]))
+    fl, cnt, E = w.flag_richardson(dt, tol, weighted=True, t=t, t_s=cfg["t_s"], t_f=cfg["t_f"], level=1,
+                                   want_estimate=True)
+    scale = np.abs(E_ref).max()
+    assert np.abs(E - E_ref).max() <= 1e-12 * scale
+    S = scale * max(np.abs(s).max() for s in snaps)
+    band = np.abs(m_ref - tol) <= 1e-12 * S
+    assert np.array_equal(fl.astype(bool)[~band], (m_ref > tol)[~band])
+    assert cnt == int(fl.sum()) > 0
