@@ -369,13 +369,16 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
         w.set_state(cfg["q0"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if mode == "adjoint":
+        if mode in ("adjoint", "richardson_adjoint"):
             w.adjoint_run(F, dt, N, every)
         t, ups, fine_cells, g = 0.0, 0, [0, 0], []
         for _ in range(N // regrid_every):
             for l in (0, 1):
                 if mode == "adjoint":
                     w.flag_adjoint(l, tol, t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+                elif mode == "richardson_adjoint":
+                    w.flag_richardson(dt / (ratios[0] if l else 1), tol, weighted=True, t=t, t_s=cfg["t_s"],
+                                      t_f=cfg["t_f"], level=l, want_flags=False, want_count=False)
                 else:
                     w.flag_difference(l, tol, want_flags=False, want_count=False)
                 w.regrid(l, None, buffer=buffer)
@@ -397,7 +400,8 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
                 "mean_cells_level1": fine_cells[0] / cyc, "mean_cells_level2": fine_cells[1] / cyc}, g
 
     runs = []
-    for mode, tol in (("adjoint", 1e-3), ("difference", 0.02), ("difference", 0.005), ("difference", 0.002)):
+    for mode, tol in (("adjoint", 1e-3), ("richardson_adjoint", 1e-5), ("richardson_adjoint", 1e-6),
+                      ("difference", 0.02), ("difference", 0.005), ("difference", 0.002)):
         run(mode, tol)                      # warm-up (graph capture, allocations)
         res, _ = run(mode, tol)
         res.update(flag=mode, tol=tol)

@@ -265,8 +265,9 @@ int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_d
  * iff the measure exceeds tol.  flags and *nflagged as for wp_flag_adjoint
  * (wp_regrid clusters them); estimate (optional, host, [m][ny/2][nx/2] of
  * the level's canvas, FP64) receives E.  The state and time of the instance are unchanged (the
- * steps run on internal copies of the problem at the level's resolution,
- * kept until a call on another level).
+ * steps run on internal copies of the problem at the level's resolution and
+ * at half of it, made on the first call on that level and kept until
+ * wp_destroy).
  * On a refined level (level > 0, dt that level's step, sizes those of its
  * canvas) the whole canvas is stepped, and E is kept only on the coarse cells
  * whose 2 x 2 block and every fine cell within 4 of it (the reach of the two

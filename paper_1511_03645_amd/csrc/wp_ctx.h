@@ -140,10 +140,9 @@ struct wp_ctx {
     size_t fresh_cap = 0;
     // Richardson estimate: single-level copies of the problem at this
     // resolution and at half of it (created on first use), and the estimate
-    wp_ctx *rich[2] = {nullptr, nullptr};
+    std::vector<wp_ctx *> rich;          // per level: the copies at its resolution and at half of it
     double *richE = nullptr;
     size_t richE_cap = 0;
-    int rich_level = -1;                 // level the helpers were made for
     uint8_t *rich_valid = nullptr;       // coarse cells kept on a refined level
     size_t rich_valid_cap = 0;
     double *richEf = nullptr;            // the estimate on a refined level's cells (weighted flag)

@@ -1426,16 +1426,12 @@ extern "C" int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flag
 // the resolution (each coarse cell with the medium of its lower-left fine
 // cell); E = (coarse - block mean of fine) / (2^(p+1) - 2).
 // Single-level copy of the problem at the resolution of `level` (which 0) or
-// half of it (which 1); cell (i, j) takes the medium of the level cell
-// (f i, f j), itself that of the level-0 cell containing it.
+// half of it (which 1), made on first use and kept per level; cell (i, j)
+// takes the medium of the level cell (f i, f j), itself that of the level-0
+// cell containing it.
 static int rich_helper(wp_ctx *ctx, int which, int level, wp_ctx *&out)
 {
-    if (out && ctx->rich_level == level)
-        return out->stream == ctx->stream ? WP_OK : wp_set_stream(out, ctx->stream);
-    if (out) {
-        wp_destroy(out);
-        out = nullptr;
-    }
+    if (out) return out->stream == ctx->stream ? WP_OK : wp_set_stream(out, ctx->stream);
     int R = 1;
     for (int l = 1; l <= level; ++l) R *= ctx->L[l].ratio;
     const int nx0 = ctx->grid.nx0, nx = ctx->L[level].nx, ny = ctx->L[level].ny;
@@ -1498,10 +1494,10 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
     if (weighted && (rc = wp_window(ctx, t, t_s, t_f, n_lo, n_hi)) != WP_OK) return rc;
     Level &lv = ctx->L[level];
     if ((rc = wp_courant_check(ctx, lv, dt)) != WP_OK) return rc;
+    if (ctx->rich.size() < 2 * ctx->L.size()) ctx->rich.resize(2 * ctx->L.size(), nullptr);
     for (int k = 0; k < 2; ++k)
-        if ((rc = rich_helper(ctx, k, level, ctx->rich[k])) != WP_OK) return rc;
-    ctx->rich_level = level;
-    wp_ctx *F = ctx->rich[0], *C = ctx->rich[1];
+        if ((rc = rich_helper(ctx, k, level, ctx->rich[2 * level + k])) != WP_OK) return rc;
+    wp_ctx *F = ctx->rich[2 * level], *C = ctx->rich[2 * level + 1];
     Level &fl = F->L[0], &cl = C->L[0];
     const int nx = lv.nx, ny = lv.ny, NX = nx / 2, NY = ny / 2, m = ctx->m;
     const long long cs = (long long)nx * ny, ccs = (long long)NX * NY;
