@@ -381,3 +381,27 @@ def test_refined_level_estimate_ignores_cells_outside_the_patches():
     fl, m, E = oracle.richardson_flag_level(cfg, q, dt, 1e-3, [(0, 0, n, n)])
     fl0, m0, E0 = oracle.richardson_flag(cfg, q, dt, 1e-3)
     assert np.array_equal(E, E0) and np.array_equal(fl, fl0)
+
+
+def test_weighted_level_flag_reduces_to_level_zero_flag():
+    """With one patch over the whole canvas and ratio 1 the weighted
+    refined-level flag is the level-0 weighted flag; at ratio 2 it weights
+    each cell's parent estimate with the snapshots taken at the cell's
+    centre (a constant snapshot gives the unweighted measure times it)."""
+    from wp_synth import random_media, random_state
+    n = 16
+    rho, K = random_media(n, n, seed=6)
+    cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=-1.0, xhi=1.0, ylo=-1.0, yhi=1.0, dx=2.0 / n, dy=2.0 / n,
+               rho=rho, K=K, bc=[0, 0, 1, 1], order=2, limiter=1, transverse=1, g=9.81)
+    q = random_state(3, n, n, seed=7)
+    dt = 0.8 * cfg["dx"] / float(np.sqrt(K / rho).max())
+    snaps = [random_state(3, n, n, seed=10 + k) for k in range(4)]
+    a = oracle.richardson_flag_level(cfg, q, dt, 1e-3, [(0, 0, n, n)], snaps=snaps, t=0.1, t_s=0.0, t_f=0.3, ds=0.1)
+    b = oracle.richardson_flag(cfg, q, dt, 1e-3, snaps=snaps, t=0.1, t_s=0.0, t_f=0.3, ds=0.1)
+    assert np.array_equal(a[2], b[2]) and np.allclose(a[1], b[1], rtol=0, atol=1e-15) and np.array_equal(a[0], b[0])
+    # ratio 2: snapshots on a grid half as fine, constant per component
+    const = [np.stack([np.full((n // 2, n // 2), c) for c in (2.0, 0.0, 0.0)])]
+    _, m, E = oracle.richardson_flag_level(cfg, q, dt, 0.0, [(0, 0, n, n)], snaps=const, t=0.0, t_s=0.0, t_f=0.0,
+                                           ds=1.0, ratio=2)
+    want = 2.0 * np.abs(np.repeat(np.repeat(E[0], 2, 0), 2, 1))
+    assert np.allclose(m, want, rtol=0, atol=1e-15)
