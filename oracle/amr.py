@@ -7,9 +7,9 @@ What it computes:
 
 * ghost ring of a level: cells inside the domain, within two cells (box
   halo) of one of the level's patches and inside none of them; before every
-  step of a level > 0 they are filled from the level below, interpolated in
-  space and in time (Sec. 3: "interpolating in both time and space from the
-  values in the underlying coarse grid");
+  step of a level > 0 they are filled from the level below, whose values
+  are interpolated to the fine cell centres and to the fine substep's time
+  (Sec. 3);
 * space interpolation: minmod-limited linear slopes per direction on the
   coarse grid (neighbours across the physical boundary by the boundary rule),
   evaluated at the fine cell centre: c + xi sx + eta sy;

@@ -235,3 +235,53 @@ def test_adjoint_hierarchy_keeps_the_duality_pairing():
     for l in range(2):
         a, f = Hs["adjoint"].q[l], Hs["forward"].q[l]
         assert np.allclose(a * flip, f, rtol=0, atol=1e-13 * np.abs(f).max())
+
+
+def test_berger_oliger_time_weights_keep_an_exact_linear_solution():
+    """p = 0.75 x - 0.5 t, u = 0.5 x - 0.75 t, v = 0 solves 2D acoustics with
+    rho = K = 1, and the limited wave-propagation step reproduces it exactly
+    (every jump is the same, so every limiter ratio is 1 and the scheme is
+    Lax-Wendroff, exact on linear data).  The coarse-to-fine ghost values
+    are interpolated in space and time (Sec. 3); limited linear slopes are
+    exact on a linear field, so the refined patches stay on the exact
+    solution only if every ghost fill uses the time of the fine substep it
+    serves: the k-th of the r substeps at (1 - k/r, k/r), and a level's own
+    ring, refilled at the end of its step for the finer level's slopes, at
+    the weight of that level's new time.  Three levels of ratio 2, the
+    level-2 patch against level 1's nesting edge, so the level-2 ring's
+    slopes read level-1 ring cells, on both sides; the coarse domain is wide enough that the
+    outflow boundary (inexact for a linear field) stays away from the
+    patches for the steps taken."""
+    n = 32
+    cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=-2.0, xhi=2.0, ylo=-2.0, yhi=2.0, dx=4.0 / n, dy=4.0 / n,
+               rho=np.ones((n, n)), K=np.ones((n, n)), bc=[0, 0, 0, 0], order=2, limiter=1, transverse=1,
+               g=9.81)
+    r = 2
+    # level 1 covers coarse cells 12..19, so its nesting region is level-1
+    # cells 25..38; level-2 patches touch it on the left (level-2 cell 50)
+    # and on the right (level-2 cell 77).  A ring error can only steepen or
+    # flatten one of the two one-sided slopes that minmod compares; the two
+    # sides see it with opposite sign, so one of them picks it up.
+    p1 = [(24, 24, 16, 16)]
+    p2 = [(50, 50, 12, 12), (62, 56, 10, 8), (72, 64, 6, 10)]
+    H = amr.Hierarchy(cfg, [r, r], [p1, p2])
+
+    def exact(l, t):
+        nl = n * r ** l
+        dxl = 4.0 / nl
+        x = -2.0 + (np.arange(nl) + 0.5) * dxl
+        X = np.broadcast_to(x[None, :], (nl, nl))
+        return np.stack([0.75 * X - 0.5 * t, 0.5 * X - 0.75 * t, np.zeros((nl, nl))])
+    for l in range(3):
+        H.set_level(l, exact(l, 0.0))
+    dt = 0.5 * cfg["dx"]
+    for step in range(1, 4):
+        H.advance(0, dt)
+        t = step * dt
+        for l, pats in ((1, p1), (2, p2)):
+            ref = exact(l, t)
+            for (i0, j0, w, h) in pats:
+                got = H.q[l][:, j0:j0 + h, i0:i0 + w]
+                assert np.abs(got - ref[:, j0:j0 + h, i0:i0 + w]).max() < 1e-13, (step, l, (i0, j0))
+        ref0 = exact(0, t)
+        assert np.abs(H.q[0][:, 8:24, 8:24] - ref0[:, 8:24, 8:24]).max() < 1e-13

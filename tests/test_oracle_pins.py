@@ -488,3 +488,65 @@ def test_lswe_adjoint_fwaves_and_identity():
         assert np.allclose(w[0] + w[1], M(hr) @ qr - M(hl) @ ql, rtol=1e-12, atol=1e-10)
         assert np.allclose(M(hl) @ w[0], s[0] * w[0], rtol=1e-12, atol=1e-9)
         assert np.allclose(M(hr) @ w[1], s[1] * w[1], rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("bc", [(BC_EXTRAP,) * 4, (BC_WALL, BC_EXTRAP, BC_EXTRAP, BC_WALL)])
+def test_lswe_adjoint_on_flat_bottom_is_the_acoustics_adjoint(bc):
+    """On a flat bottom (depth hbar) the linearised shallow-water system of
+    Sec. 5.3 is 2D acoustics with rho = 1, K = g hbar: its reversed adjoint
+    flux is -(g hbar mu, eta, 0) in x and -(g hbar gamma, 0, eta) in y, which
+    is D (-(u, K p, 0)) for (eta, mu, gamma) = D (p, u, v), D = diag(g hbar,
+    1, 1).  The Riemann eigenvectors map by D as well, and with one medium
+    every edge shares them, so the limiter ratios agree: the whole 2D step,
+    transverse terms included, must commute with D.  Dropping or mis-signing
+    the linearised adjoint's transverse split breaks it."""
+    from wp_synth import random_state
+    g, hbar, n = 9.81, 1800.0, 40
+    c = math.sqrt(g * hbar)
+    base = dict(nx=n, ny=n, xlo=0.0, xhi=float(n), ylo=0.0, yhi=float(n), dx=1.0, dy=1.0,
+                bc=list(bc), order=2, limiter=1, transverse=1, g=g)
+    lswe = dict(base, kind="swe2d", B=np.full((n, n), -hbar))
+    acou = dict(base, kind="acoustics2d", rho=np.ones((n, n)), K=np.full((n, n), g * hbar))
+    q = random_state(3, n, n, seed=12)
+    D = np.array([g * hbar, 1.0, 1.0])[:, None, None]
+    dt = 0.8 / c
+    ql, _, _ = oracle.run(lswe, "lswe_adj", D * q, 12, dt=dt)
+    qa, _, _ = oracle.run(acou, "acoustics_adj", q, 12, dt=dt)
+    err = np.abs(ql - D * qa).max(axis=(1, 2)) / np.abs(D * qa).max(axis=(1, 2))
+    assert err.max() < 1e-12, err
+    # the transverse terms matter here: without them the result differs
+    qn, _, _ = oracle.run(lswe, "lswe_adj", D * q, 12, dt=dt, transverse=0)
+    assert np.abs(qn - ql).max() > 1e-3 * np.abs(ql).max()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_swe_transverse_split_is_the_jacobian_split_at_a_moving_state(seed):
+    """At a constant moving state (u, v both nonzero) the Roe average is that
+    state, so the transverse split of eq. swe's fluctuation d along direction
+    t must be B^- d = R min(L,0) R^-1 d and B^+ d = R max(L,0) R^-1 d for the
+    flux Jacobian of direction t, with R and L from a library eigensolver."""
+    rng = np.random.default_rng(40 + seed)
+    g = 9.81
+    B = -rng.uniform(200.0, 4000.0)
+    h = -B + rng.uniform(-1.0, 1.0)
+    c = math.sqrt(g * h)
+    # speeds of either sign along each direction: |u|, |v| below and above c
+    u = rng.choice([-1.0, 1.0]) * rng.uniform(0.2, 1.6) * c
+    v = rng.choice([-1.0, 1.0]) * rng.uniform(0.2, 1.6) * c
+    q = [h + B, h * u, h * v]
+    for tdir in (0, 1):
+        if tdir == 0:
+            Jac = np.array([[0.0, 1.0, 0.0], [g * h - u * u, 2 * u, 0.0], [-u * v, v, u]])
+        else:
+            Jac = np.array([[0.0, 0.0, 1.0], [-u * v, v, u], [g * h - v * v, 0.0, 2 * v]])
+        lam, R = np.linalg.eig(Jac)
+        lam, R = lam.real, R.real
+        Ri = np.linalg.inv(R)
+        Am = R @ np.diag(np.minimum(lam, 0.0)) @ Ri
+        Ap = R @ np.diag(np.maximum(lam, 0.0)) @ Ri
+        for _ in range(4):
+            d = rng.normal(size=3) * np.array([1.0, c, c])
+            bm, bp = oracle.transverse_split("swe", tdir, d, [B], [B], [B], ql=q, qr=q, al=[B], ar=[B], g=g)
+            scale = np.abs(d).max() * (abs(u) + abs(v) + c)
+            assert np.abs(bm - Am @ d).max() < 1e-12 * scale, (tdir, bm, Am @ d)
+            assert np.abs(bp - Ap @ d).max() < 1e-12 * scale, (tdir, bp, Ap @ d)
