@@ -282,6 +282,14 @@ int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_d
 int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
                        double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate);
 
+/* The flag canvas of `level` ([ny_l][nx_l] uint8, 1 = flagged, 0 outside the
+ * level's patches) as the last flag call on that level left it: wp_flag_adjoint,
+ * wp_flag_difference, wp_flag_surface, wp_flag_richardson, or the last flag
+ * event of wp_forward_flagged (Sec. 4; Sec. 5.1.2).  dst is device or host
+ * memory per on_device (a host copy synchronises the stream).  WP_ESTATE if
+ * the level has not been flagged since it was created or regridded. */
+int wp_get_flags(wp_ctx *ctx, int level, uint8_t *dst, int on_device);
+
 /* The forward run with adjoint-guided flagging (Sec. 4; Sec. 5.1.2) on a
  * single-level instance: nsteps steps of size dt from the current state and
  * time t0, with the flag of wp_flag_adjoint(0, tol, t, t_s, t_f) evaluated at

@@ -102,6 +102,7 @@ _SIGS = {
                                 ctypes.POINTER(_D)]),
     "wp_regrid": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, _I]),
     "wp_get_patches": (_I, [_P, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
+    "wp_get_flags": (_I, [_P, _I, _P, _I]),
     "wp_forward_flagged": (_I, [_P, _D, _I, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_float)]),
     "wp_cluster": (_I, [_P, _P, _I, _I, _D, _I, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
@@ -145,6 +146,23 @@ def _torch():
         return torch
     except Exception:          # pragma: no cover
         return None
+
+
+class CallbackAllocator:
+    """wp_allocator from two Python callables: alloc(nbytes) -> device
+    address or None, free(address)."""
+
+    def __init__(self, alloc, free):
+        def _alloc(nbytes, user):
+            p = alloc(int(nbytes))
+            return p if p else None
+
+        def _free(p, user):
+            free(p)
+
+        self._a = _ALLOC_FN(_alloc)
+        self._f = _FREE_FN(_free)
+        self.struct = wp_allocator(self._a, self._f, None)
 
 
 class TorchAllocator:
@@ -215,7 +233,7 @@ class WavePatch:
 
     def __init__(self, kind, nx, ny=1, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, rho=None, K=None, B=None,
                  bc=(BC_EXTRAP,) * 4, order=2, limiter=1, transverse=1, precision=FP64, cfl_max=1.0, g=9.81,
-                 num_levels=1, ratios=(), stream=None, torch_alloc=True):
+                 num_levels=1, ratios=(), stream=None, torch_alloc=True, allocator=None):
         L = lib()
         kinds = {"acoustics1d": ACOUSTICS_1D, "acoustics2d": ACOUSTICS_2D, "swe2d": SWE_2D}
         self.kind = kind
@@ -235,12 +253,12 @@ class WavePatch:
         rat = (ctypes.c_int * MAX_LEVELS)(*(list(ratios) + [1] * (MAX_LEVELS - len(ratios))))
         grid = wp_grid(xlo, xhi, ylo, yhi, nx, ny if self.kind_id != ACOUSTICS_1D else 1, num_levels, rat)
         torch = _torch()
-        self.allocator = None
-        alloc_p = None
+        self.allocator = allocator
+        alloc_p = None if allocator is None else ctypes.byref(allocator.struct)
         if torch is not None and torch.cuda.is_available():
             if stream is None:
                 stream = torch.cuda.current_stream().cuda_stream
-            if torch_alloc:
+            if torch_alloc and allocator is None:
                 self.allocator = TorchAllocator()
                 alloc_p = ctypes.byref(self.allocator.struct)
         self.stream = stream
@@ -411,6 +429,14 @@ class WavePatch:
         self._check(lib().wp_flag_richardson(self.h, level, dt, int(weighted), tol, t, t_s, t_f, p, 0,
                                              ctypes.byref(n) if want_count else None, e))
         return flags, (n.value if want_count else None), est
+
+    def get_flags(self, level=0):
+        """wp_get_flags: the level's flag canvas [ny][nx] (uint8) as the last
+        flag call on it left it."""
+        nx, ny, _ = self.level_info(level)
+        flags = np.zeros((ny, nx), dtype=np.uint8)
+        self._check(lib().wp_get_flags(self.h, level, ctypes.c_void_p(flags.ctypes.data), 0))
+        return flags
 
     def forward_flagged(self, dt, nsteps, flag_every, tol, t_s, t_f, want_counts=True, want_times=False):
         """wp_forward_flagged: (flagged cells per flag event or None,

@@ -387,12 +387,12 @@ __global__ __launch_bounds__(256) void sum_dot_mixed_kernel(const double *__rest
 }
 
 __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ partials, int nb,
-                                                     double *__restrict__ out)
+                                                     double *__restrict__ out, double scale)
 {
     KSum acc{0.0, 0.0};
     for (int i = threadIdx.x; i < nb; i += 256) kmerge(acc, KSum{partials[2 * i], partials[2 * i + 1]});
     KSum r = block_reduce<256>(acc);
-    if (threadIdx.x == 0) out[0] = r.s + r.c;
+    if (threadIdx.x == 0) out[0] = (r.s + r.c) * scale;
 }
 
 __global__ void fill_u8_kernel(uint8_t *p, long long n, uint8_t v)
@@ -434,22 +434,22 @@ void launch_sum_indicator(const TA *a, long long cs, long long n, int comp, cons
                           int nblocks, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL((sum_indicator_kernel<TA>), dim3(nblocks), dim3(256), 0, s, a, cs, n, comp, ind, partials);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out, 1.0);
 }
 
 template <typename TA, typename TB>
 void launch_sum_dot(const TA *a, long long acs, const TB *b, long long bcs, long long n, int m, double *partials,
-                    int nblocks, double *out, hipStream_t s)
+                    int nblocks, double *out, hipStream_t s, double scale)
 {
     hipLaunchKernelGGL((sum_dot_kernel<TA, TB>), dim3(nblocks), dim3(256), 0, s, a, acs, b, bcs, n, m, partials);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out, scale);
 }
 
 void launch_sum_dot_mixed(const double *eta, const float *hu, const float *hv, long long cs, const float *b,
                           long long bcs, long long n, double *partials, int nblocks, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(sum_dot_mixed_kernel, dim3(nblocks), dim3(256), 0, s, eta, hu, hv, cs, b, bcs, n, partials);
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out, 1.0);
 }
 
 template <typename TE, typename TU>
@@ -556,9 +556,9 @@ template void launch_sum_indicator<double>(const double *, long long, long long,
 template void launch_sum_indicator<float>(const float *, long long, long long, int, const uint8_t *, double *, int,
                                           double *, hipStream_t);
 template void launch_sum_dot<double, double>(const double *, long long, const double *, long long, long long, int,
-                                             double *, int, double *, hipStream_t);
+                                             double *, int, double *, hipStream_t, double);
 template void launch_sum_dot<float, float>(const float *, long long, const float *, long long, long long, int,
-                                           double *, int, double *, hipStream_t);
+                                           double *, int, double *, hipStream_t, double);
 
 template void launch_flag_difference<double, double>(const double *, const double *, const double *, int, int,
                                                      const int *, double, const Tile *, int, uint8_t *,

@@ -55,6 +55,9 @@ struct Level {
     // allocated sizes (bytes) of the tables above: a smaller table is written
     // into the same block
     size_t tiles_cap = 0, ftiles_cap = 0, ring_cap = 0, ringb_cap = 0, cover_cap = 0;
+    // false after a tile-table rebuild failed (its tables are empty): steps
+    // and flags of the level fail with WP_ESTATE until a rebuild succeeds
+    bool tables_ok = true;
 };
 
 struct wp_ctx {
@@ -68,6 +71,7 @@ struct wp_ctx {
     std::vector<void *> owned;
     std::vector<Level> L;
     Level adj;                           // adjoint grid (level-0 resolution)
+    bool adj_ready = false;              // adj fully built (wp_ensure_adjoint_level)
     // acoustics media
     int nmat = 0;
     std::vector<double> rho, K;

@@ -248,7 +248,17 @@ static bool pair_narrow(std::vector<Tile> &t)
     return any;
 }
 
+static int upload_tiles(wp_ctx *ctx, Level &lv);
+
 int wp_upload_tiles(wp_ctx *ctx, Level &lv)
+{
+    const int rc = upload_tiles(ctx, lv);
+    lv.tables_ok = rc == WP_OK;
+    if (rc != WP_OK) lv.ntiles = lv.nftiles = lv.nptiles = lv.nuni = lv.npuni = 0;
+    return rc;
+}
+
+static int upload_tiles(wp_ctx *ctx, Level &lv)
 {
     int rc;
     const bool is_1d = ctx->prob.kind == WP_ACOUSTICS_1D;
@@ -786,7 +796,7 @@ extern "C" int wp_set_tile_rows(wp_ctx *ctx, int rows)
     int rc;
     for (auto &lv : ctx->L)
         if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
-    if (ctx->adj.q[0] && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
+    if (ctx->adj_ready && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
     return WP_OK;
 }
 
@@ -882,7 +892,8 @@ static int acou_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
 int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap1, int snap2,
                  const PairFlag *flag)
 {
-    if (!wp_pair_ready(ctx, lv)) return wp_fail(ctx, WP_ESTATE, "level cannot take two steps per launch");
+    if (!lv.tables_ok || !wp_pair_ready(ctx, lv))
+        return wp_fail(ctx, WP_ESTATE, "level cannot take two steps per launch");
     if (ctx->esz == 8) return acou_pair<double>(ctx, lv, dt, adjoint, s, snap1, snap2, flag);
     return acou_pair<float>(ctx, lv, dt, adjoint, s, snap1, snap2, flag);
 }
@@ -894,7 +905,7 @@ extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
     int rc;
     for (auto &lv : ctx->L)
         if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
-    if (ctx->adj.q[0] && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
+    if (ctx->adj_ready && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
     return WP_OK;
 }
 
@@ -927,6 +938,7 @@ int wp_prepare_level(wp_ctx *ctx, Level &lv, double dt)
 
 int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, int snap_index)
 {
+    if (!lv.tables_ok) return wp_fail(ctx, WP_ESTATE, "tile tables missing after a failed rebuild");
     if (ctx->is_acoustics) {
         if (ctx->esz == 8) return acou_step<double>(ctx, lv, dt, adjoint, s, snap_index);
         return acou_step<float>(ctx, lv, dt, adjoint, s, snap_index);
@@ -1107,21 +1119,40 @@ int wp_build_indicator(wp_ctx *ctx, const wp_functional *J, std::vector<uint8_t>
     return WP_OK;
 }
 
+// Release every block a level holds and reset it.
+static void release_level(wp_ctx *ctx, Level &lv)
+{
+    void *blocks[] = {lv.q[0], lv.q[1], lv.mat, lv.flags, lv.tiles_dev, lv.ptiles_dev, lv.ftiles_dev, lv.inst,
+                      lv.ring_dev, lv.ringb_dev, lv.cover_dev};
+    for (void *p : blocks) wp_dfree(ctx, p);
+    lv = Level();
+}
+
+// The adjoint grid, built on first use; a failed build releases what it
+// allocated so that the next call starts again from nothing.
 int wp_ensure_adjoint_level(wp_ctx *ctx)
 {
     Level &a = ctx->adj;
-    if (a.q[0]) return WP_OK;
+    if (ctx->adj_ready) return WP_OK;
+    release_level(ctx, a);
     const Level &l0 = ctx->L[0];
     a.nx = l0.nx;
     a.ny = l0.ny;
     a.dx = l0.dx;
     a.dy = l0.dy;
     a.ratio = 1;
-    int rc;
-    if ((rc = wp_alloc_level(ctx, a)) != WP_OK) return rc;
-    a.patches.push_back(wp_patch{0, 0, a.nx, a.ny});
-    if (!ctx->is_acoustics && (rc = wp_swe_adj_init(ctx)) != WP_OK) return rc;
-    return wp_upload_tiles(ctx, a);
+    int rc = wp_alloc_level(ctx, a);
+    if (rc == WP_OK) {
+        a.patches.push_back(wp_patch{0, 0, a.nx, a.ny});
+        if (!ctx->is_acoustics) rc = wp_swe_adj_init(ctx);
+    }
+    if (rc == WP_OK) rc = wp_upload_tiles(ctx, a);
+    if (rc != WP_OK) {
+        release_level(ctx, a);
+        return rc;
+    }
+    ctx->adj_ready = true;
+    return WP_OK;
 }
 
 // Everything of an adjoint run but the stepping: snapshot store, phi on the
@@ -1307,6 +1338,7 @@ static int flag_launch(wp_ctx *ctx, int level, double tol, int n_lo, int n_hi, u
                        hipStream_t s)
 {
     Level &lv = ctx->L[level];
+    if (!lv.tables_ok) return wp_fail(ctx, WP_ESTATE, "tile tables missing after a failed rebuild");
     const long long cells = (long long)lv.nx * lv.ny;
     int ratio = 1;
     for (int l = 1; l <= level; ++l) ratio *= ctx->L[l].ratio;
@@ -1355,6 +1387,22 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     return WP_OK;
 }
 
+extern "C" int wp_get_flags(wp_ctx *ctx, int level, uint8_t *dst, int on_device)
+{
+    if (!ctx) return WP_EINVAL;
+    if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level out of range");
+    if (!dst) return wp_fail(ctx, WP_EINVAL, "null destination");
+    Level &lv = ctx->L[level];
+    if (!lv.flags_valid) return wp_fail(ctx, WP_ESTATE, "level %d has no flags", level);
+    const size_t cells = (size_t)lv.nx * lv.ny;
+    if (on_device) {
+        if (hipMemcpyAsync(dst, lv.flags, cells, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "flag copy");
+        return WP_OK;
+    }
+    return wp_host_copy(ctx, dst, lv.flags, cells, false);
+}
+
 // The comparison flags (Sec. 5.2.4, Sec. 5.3) on every patch of a level, with
 // the count and the copy-out of wp_flag_adjoint.  A refined level's ghost
 // ring is filled from the level below at the level's time first, so that the
@@ -1367,6 +1415,7 @@ static int flag_standard(wp_ctx *ctx, int level, bool surface, double tol, uint8
     if (surface && ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "the surface flag is for shallow water");
     if (!(tol >= 0.0)) return wp_fail(ctx, WP_EINVAL, "tolerance must be non-negative");
     Level &lv = ctx->L[level];
+    if (!lv.tables_ok) return wp_fail(ctx, WP_ESTATE, "tile tables missing after a failed rebuild");
     const long long cells = (long long)lv.nx * lv.ny;
     hipStream_t s = ctx->stream;
     int rc;

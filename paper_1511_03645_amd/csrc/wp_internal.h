@@ -177,13 +177,14 @@ void launch_richardson(const T *coarse, long long ccs, const T *fine, long long 
 
 // Compensated FP64 reductions: out[0] = sum_k sum_cells w(cell) a_k b_k where
 // a is m component arrays (type TA) and b either an indicator (uint8, times
-// unit vector `comp`) or m arrays of type TB.
+// unit vector `comp`) or m arrays of type TB (the sum times `scale`).
+// partials: 2 * nblocks doubles of scratch.
 template <typename TA>
 void launch_sum_indicator(const TA *a, long long cs, long long n, int comp, const uint8_t *ind, double *partials,
                           int nblocks, double *out, hipStream_t s);
 template <typename TA, typename TB>
 void launch_sum_dot(const TA *a, long long acs, const TB *b, long long bcs, long long n, int m, double *partials,
-                    int nblocks, double *out, hipStream_t s);
+                    int nblocks, double *out, hipStream_t s, double scale = 1.0);
 void launch_sum_dot_mixed(const double *eta, const float *hu, const float *hv, long long cs, const float *b,
                           long long bcs, long long n, double *partials, int nblocks, double *out, hipStream_t s);
 

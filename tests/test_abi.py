@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1511_03645_amd as wp
@@ -43,3 +44,19 @@ def test_status_strings_without_device():
     assert L.wp_set_equation(None, 1) == wp.WP_EINVAL
     assert L.wp_get_equation(None, None) == wp.WP_EINVAL
     assert L.wp_set_snapshots(None, None, 1, 0.1, 0) == wp.WP_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(wp.LIB_PATH), reason="library not built")
+def test_create_reports_enomem_when_the_allocator_fails():
+    """An allocator that returns no memory: wp_create fails with WP_ENOMEM
+    and a message before any device work, and the handle it hands back for
+    the message is destroyed cleanly (Sec. 8(b)-style error convention of
+    the library: status codes, per-handle message)."""
+    calls = []
+    a = wp.CallbackAllocator(lambda n: calls.append(n), lambda p: None)
+    rho = np.ones((8, 8))
+    with pytest.raises(wp.WPError) as e:
+        wp.WavePatch("acoustics2d", 8, 8, rho=rho, K=rho, allocator=a)
+    assert e.value.code == wp.WP_ENOMEM
+    assert "material tables" in str(e.value)
+    assert calls

@@ -1,0 +1,185 @@
+"""The configured workloads at their full size and full horizon, on the path
+the benchmark measures, against the FP64 oracle (Sec. 2, 3, 4, 5.1.2):
+
+* the 1D two-material problem (2000 cells, 4500 adjoint + 4500 forward steps,
+  101 snapshots, flag tolerance 1e-3) with the flag of every snapshot time;
+* the adjoint flag fused into the two-step forward launch, every event's flag
+  canvas cell by cell (at sizes the oracle runs in seconds, several tile
+  heights, a ragged last tile column);
+* one whole 1024 x 1024 job (730 adjoint + 730 forward steps, 73 flag
+  events) against the oracle's stored results (tests/golden/c1_job_oracle.json,
+  written by tests/golden/make_c1_job.py from the oracle alone): every
+  event's flag canvas through its digest, the final state and snapshots at
+  sampled cells, J.
+
+Bars: FP64 values within 1e-12 of the oracle's scale; flags bit-exact outside
+the band |m - tol| <= 1e-12 S, S = max(1, max|q| max|qhat|)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1511_03645_amd as wp
+from wp_synth import acoustics1d, acoustics2d
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_job_oracle.json")
+
+
+def close64(a, b, what, scale=None):
+    scale = max(np.abs(b).max() if scale is None else scale, 1e-300)
+    err = np.abs(np.asarray(a) - np.asarray(b)).max()
+    assert err <= TOL64 * scale, f"{what}: max err {err:.3e} vs scale {scale:.3e}"
+
+
+def assert_flags(got, ref, mval, tol, S, what):
+    band = np.abs(mval - tol) <= TOL64 * S
+    bad = np.flatnonzero((got != ref) & ~band)
+    assert bad.size == 0, f"{what}: {bad.size} cells differ outside the band, first at {bad[:5]}"
+
+
+def test_c0_full_configuration():
+    """1D acoustics as configured: 2000 cells on [-5,5], K 1 | 4, hump at
+    x = -2, T = 10, J over [1, 1.5], snapshots every 0.1, the flag at tol
+    1e-3 at every snapshot time of the forward run."""
+    cfg = acoustics1d()
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    assert (cfg["nx"], N, N // every + 1) == (2000, 4500, 101)
+    print(f"case C0 full: {N} steps, flag every {every}", flush=True)
+    snaps, _ = oracle.adjoint_run(cfg)
+    w = wp.from_config(cfg)
+    w.adjoint_run(cfg["functional"], dt, N, every)
+    assert w.num_snapshots() == len(snaps) == 101
+    S_hat = float(np.abs(snaps).max())
+    for n in range(len(snaps)):
+        close64(w.get_snapshot(n).reshape(snaps[n].shape), snaps[n], f"snapshot {n}", scale=S_hat)
+    q = cfg["q0"].copy()
+    w.set_state(q)
+    w.set_time(0.0)
+    ds = every * dt
+    total = 0
+    for k in range(N // every):
+        t = k * ds
+        ref, mval = oracle.flag(q, snaps, t, cfg["t_s"], cfg["t_f"], ds, cfg["tol"])
+        counts, _ = w.forward_flagged(dt, every, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+        got = w.get_flags(0).reshape(ref.shape)
+        S = max(1.0, float(np.abs(q).max()) * S_hat)
+        assert_flags(got, ref, mval, cfg["tol"], S, f"event {k} (t = {t:.3f})")
+        assert counts[0] == int(got.sum())
+        total += counts[0]
+        q, _, _ = oracle.run(cfg, "acoustics_fwd", q, every)
+    assert total > 0
+    close64(w.get_state().reshape(q.shape), q, "final state")
+    Jg = w.functional_value(cfg["functional"], which=0)
+    Jo = oracle.functional(cfg, q)
+    # J(10) is close to 0 on this problem; the bar is taken on the scale of
+    # phi times the largest state value
+    assert abs(Jg - Jo) <= TOL64 * 0.5 * max(1.0, float(np.abs(cfg["q0"]).max()))
+
+
+@pytest.mark.parametrize("n,rows", [(256, 12), (256, 8), (200, 16), (200, 10)])
+def test_fused_flags_every_event_match_oracle(n, rows):
+    """Forward runs with two steps per launch and the flag fused into the
+    first launch of each block: every event's flag canvas (wp_get_flags)
+    against oracle.flag on the oracle's state, cell by cell."""
+    cfg = acoustics2d(n, seed=1)
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    print(f"case fused flags {n}^2 rows={rows}: {N} steps", flush=True)
+    snaps, _ = oracle.adjoint_run(cfg)
+    w = wp.from_config(cfg)
+    w.set_step_pairs(rows)
+    assert w.get_step_pairs() == rows
+    w.adjoint_run(cfg["functional"], dt, N, every)
+    S_hat = float(np.abs(snaps).max())
+    for k in (0, len(snaps) // 2, len(snaps) - 1):
+        close64(w.get_snapshot(k), snaps[k], f"snapshot {k}", scale=S_hat)
+    q = cfg["q0"].copy()
+    w.set_state(q)
+    w.set_time(0.0)
+    ds = every * dt
+    flagged = 0
+    for k in range(N // every):
+        t = k * ds
+        ref, mval = oracle.flag(q, snaps, t, cfg["t_s"], cfg["t_f"], ds, cfg["tol"])
+        counts, _ = w.forward_flagged(dt, every, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+        got = w.get_flags(0)
+        S = max(1.0, float(np.abs(q).max()) * S_hat)
+        assert_flags(got, ref, mval, cfg["tol"], S, f"event {k}")
+        assert counts[0] == int(got.sum())
+        flagged += counts[0]
+        q, _, _ = oracle.run(cfg, "acoustics_fwd", q, every)
+    assert flagged > 0
+    close64(w.get_state(), q, "final state")
+    # one captured run of the whole horizon takes the same flags: its last
+    # event's canvas and its counts equal those of the event-by-event run
+    last = w.get_flags(0)
+    v = wp.from_config(cfg)
+    v.set_step_pairs(rows)
+    v.adjoint_run(cfg["functional"], dt, N, every)
+    v.set_state(cfg["q0"])
+    v.set_time(0.0)
+    counts, _ = v.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+    assert sum(counts) == flagged
+    assert np.array_equal(v.get_flags(0), last)
+    assert np.array_equal(v.get_state(), w.get_state())
+
+
+def _digest(flags, band):
+    f = flags.copy().ravel()
+    f[np.asarray(band, dtype=np.int64)] = 0
+    return hashlib.sha256(f.tobytes()).hexdigest()
+
+
+def test_c1_full_job_matches_stored_oracle():
+    """One whole job of the 1024 x 1024 workload in the benchmark's launch
+    configuration (two steps per launch, 12-row tiles, the flag fused into
+    the first launch of each block, one captured sequence per run) against
+    the oracle's stored results of the same job."""
+    gold = json.load(open(GOLDEN))
+    cfg = acoustics2d(gold["n"], seed=gold["seed"])
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    assert (N, every, dt, cfg["tol"]) == (gold["nsteps"], gold["every"], gold["dt"], gold["tol"])
+    print(f"case C1 full job: {N} + {N} steps, {N // every} flag events", flush=True)
+    w = wp.from_config(cfg)
+    w.set_step_pairs(12)
+    w.adjoint_run(cfg["functional"], dt, N, every)
+    for s in gold["snapshots"]:
+        got = w.get_snapshot(s["n"])
+        idx = np.asarray(s["cells"])
+        for c in range(3):
+            close64(got[c].ravel()[idx], np.asarray(s["values"][c]), f"snapshot {s['n']} component {c}",
+                    scale=gold["snapshot_scale"])
+    # event by event: each event's canvas against the stored digest
+    w.set_state(cfg["q0"])
+    w.set_time(0.0)
+    for k, ev in enumerate(gold["events"]):
+        counts, _ = w.forward_flagged(dt, every, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+        got = w.get_flags(0)
+        band = ev["band"]
+        ok = _digest(got, band) == ev["sha256"]
+        assert ok, (f"event {k} (t = {ev['t']:.4f}): flag canvas differs from the oracle's outside the band "
+                    f"({counts[0]} flagged, oracle {ev['count']})")
+        assert abs(counts[0] - ev["count"]) <= len(band)
+    q = w.get_state()
+    idx = np.asarray(gold["final"]["cells"])
+    for c in range(3):
+        close64(q[c].ravel()[idx], np.asarray(gold["final"]["values"][c]), f"final state component {c}",
+                scale=gold["final"]["scale"])
+    J = w.functional_value(cfg["functional"], which=0)
+    assert abs(J - gold["J"]) <= TOL64 * abs(gold["J"]), (J, gold["J"])
+    # the benchmark's form: the whole forward run as one captured sequence
+    v = wp.from_config(cfg)
+    v.set_step_pairs(12)
+    v.adjoint_run(cfg["functional"], dt, N, every)
+    v.set_state(cfg["q0"])
+    v.set_time(0.0)
+    counts, _ = v.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+    for k, ev in enumerate(gold["events"]):
+        assert abs(counts[k] - ev["count"]) <= len(ev["band"]), f"event {k}"
+    assert _digest(v.get_flags(0), gold["events"][-1]["band"]) == gold["events"][-1]["sha256"]
+    assert np.array_equal(v.get_state(), q)

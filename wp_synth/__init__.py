@@ -262,15 +262,33 @@ def swe2d(n=2048, seed=3, cfl=0.9, T=10800.0, every=10, g=9.81):
 # ---------------------------------------------------------------------------
 # Batch of independent 2D acoustics instances
 # ---------------------------------------------------------------------------
+def _rect_clear_of_path(rect, px, py, tx, ty, margin):
+    """True if the rectangle (xa, xb, ya, yb) keeps `margin` away from every
+    point of the segment (px, py)-(tx, ty) (sampled every 0.01)."""
+    xa, xb, ya, yb = rect
+    L = math.hypot(tx - px, ty - py)
+    s = np.linspace(0.0, 1.0, max(2, int(L / 0.01) + 2))
+    X = px + s * (tx - px)
+    Y = py + s * (ty - py)
+    ddx = np.maximum(np.maximum(xa - X, X - xb), 0.0)
+    ddy = np.maximum(np.maximum(ya - Y, Y - yb), 0.0)
+    return bool(np.min(np.hypot(ddx, ddy)) > margin)
+
+
 def acoustics2d_batch(count=64, nmin=128, nmax=1024, steps=256, snap_every=8,
-                      seed=4, cfl=0.9):
+                      seed=4, cfl=0.9, t_max=4.0):
     """`count` independent 2D acoustics instances on [-4,4]^2.  Each has a
-    seeded side N in [nmin, nmax], background rho = K = 1 plus 4 seeded
-    axis-aligned rectangles (snapped to cell edges) with rho in U[0.5,2] and
-    K in U[0.5,4], a width-0.1 Gaussian pulse and a radius-0.2 disc target
-    at a seeded bearing, 0.9..1.0 of the background travel distance c T away
-    (c = 1), so that the front is crossing the target at the final time and J
-    is not a tail value.  Each runs `steps` steps at its own CFL-0.9 dt."""
+    seeded side N in [nmin, nmax], background rho = K = 1 (c = 1) plus 4
+    seeded axis-aligned rectangles (snapped to cell edges) with rho in
+    U[0.5,2] and K in U[0.5,4], a width-0.1 Gaussian pulse and a radius-0.2
+    disc target.  Each runs `steps` steps of a uniform dt: Courant number 0.9
+    at the largest speed, or less where that would take the final time T
+    past `t_max` (so that the front is still inside the domain at T).  The
+    target's centre is at distance T - u, u in U[0, 0.05], from the pulse at
+    a seeded bearing, both inside [-3.5,3.5]^2, and every rectangle keeps
+    0.4 away from the straight path between them: the direct front crosses
+    the background medium at c = 1 and sits at the target's centre at T, so
+    J is taken on the arriving front, not on a tail."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
@@ -278,23 +296,31 @@ def acoustics2d_batch(count=64, nmin=128, nmax=1024, steps=256, snap_every=8,
         dx = 8.0 / n
         x = cell_centres(-4.0, dx, n)
         X, Y = np.meshgrid(x, x)
+        # the media's values fix the largest speed, hence dt and T
+        media = [(rng.uniform(0.5, 2.0), rng.uniform(0.5, 4.0)) for _ in range(4)]
+        cmax = max(1.0, max(math.sqrt(Kr / r) for r, Kr in media))
+        T = min(steps * cfl * dx / cmax, t_max)
+        dt = T / steps
+        while True:
+            px, py = rng.uniform(-3.5, 3.5, 2)
+            ang = rng.uniform(0.0, 2.0 * math.pi)
+            d = T - rng.uniform(0.0, 0.05)
+            tx, ty = px + d * math.cos(ang), py + d * math.sin(ang)
+            if max(abs(tx), abs(ty)) <= 3.5:
+                break
         rho = np.ones((n, n))
         K = np.ones((n, n))
-        for _ in range(4):
-            xa, xb = np.sort(rng.uniform(-4.0, 4.0, 2))
-            ya, yb = np.sort(rng.uniform(-4.0, 4.0, 2))
-            ia, ib = int(round((xa + 4.0) / dx)), int(round((xb + 4.0) / dx))
-            ja, jb = int(round((ya + 4.0) / dx)), int(round((yb + 4.0) / dx))
-            rho[ja:jb, ia:ib] = rng.uniform(0.5, 2.0)
-            K[ja:jb, ia:ib] = rng.uniform(0.5, 4.0)
-        cmax = float(np.sqrt(K / rho).max())
-        dt = cfl * dx / cmax
-        T = steps * dt
-        px, py = rng.uniform(-2.0, 2.0, 2)
-        ang = rng.uniform(0.0, 2.0 * math.pi)
-        d = rng.uniform(0.9, 1.0) * T
-        tx = float(np.clip(px + d * math.cos(ang), -3.5, 3.5))
-        ty = float(np.clip(py + d * math.sin(ang), -3.5, 3.5))
+        for r, Kr in media:
+            while True:
+                xa, xb = np.sort(rng.uniform(-4.0, 4.0, 2))
+                ya, yb = np.sort(rng.uniform(-4.0, 4.0, 2))
+                ia, ib = int(round((xa + 4.0) / dx)), int(round((xb + 4.0) / dx))
+                ja, jb = int(round((ya + 4.0) / dx)), int(round((yb + 4.0) / dx))
+                rect = (-4.0 + ia * dx, -4.0 + ib * dx, -4.0 + ja * dx, -4.0 + jb * dx)
+                if ib > ia and jb > ja and _rect_clear_of_path(rect, px, py, tx, ty, 0.4):
+                    break
+            rho[ja:jb, ia:ib] = r
+            K[ja:jb, ia:ib] = Kr
         q0 = np.zeros((3, n, n))
         q0[0] = np.exp(-((X - px) ** 2 + (Y - py) ** 2) / 0.1 ** 2)
         out.append(dict(
@@ -303,6 +329,7 @@ def acoustics2d_batch(count=64, nmin=128, nmax=1024, steps=256, snap_every=8,
             rho=rho, K=K, q0=q0, bc=[BC_EXTRAP] * 4,
             order=2, limiter=1, transverse=1, dt=dt, nsteps=steps,
             snap_every=snap_every, flag_every=10, tol=1e-4, t_f=T, t_s=T,
+            pulse=(px, py),
             functional=dict(kind="disc", x0=0.0, x1=0.0, y0=0.0, y1=0.0,
                             cx=tx, cy=ty, r=0.2, component=0),
         ))
