@@ -79,6 +79,10 @@ def lib():
         L.or_patch_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, dp, dp, dp,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_patch_step_edges.restype = ctypes.c_double
+        L.or_patch_step_edges.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, dp, dp, dp,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.or_fill_ghosts.restype = None
         L.or_fill_ghosts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ip,
                                      ctypes.c_int, ctypes.c_int]

@@ -160,7 +160,8 @@ class Hierarchy:
     ratios; patches: list per level of (ilo, jlo, nx, ny) boxes (level 0 may be
     omitted: one patch covering the domain)."""
 
-    def __init__(self, cfg, ratios, patches, order=None, limiter=None, transverse=None, equation="forward"):
+    def __init__(self, cfg, ratios, patches, order=None, limiter=None, transverse=None, equation="forward",
+                 reflux=False):
         self.cfg = cfg
         self.ratios = list(ratios)
         self.L = len(self.ratios) + 1
@@ -171,6 +172,12 @@ class Hierarchy:
         # the system every patch step solves: the forward acoustics or its
         # adjoint (Sec. 2), the latter refined as Sec. 7 proposes
         self.which = {"forward": 0, "adjoint": 1}[equation]
+        # flux bookkeeping at coarse-fine edges: only the adjoint is in
+        # conservation form (Sec. 3 contrasts it with the forward problem)
+        if reflux and self.which != 1:
+            raise ValueError("refluxing needs the conservative (adjoint, f-wave) form")
+        self.reflux = reflux
+        self.edges = [None] * (len(self.ratios) + 1)
         nx0, ny0 = cfg["nx"], cfg["ny"]
         self.n = []
         self.dx = []
@@ -216,9 +223,11 @@ class Hierarchy:
         L.or_make_aux(0, w, h, _dp(rho), _dp(K), 9.81, _dp(aux))
         Gn = np.zeros_like(G)
         dx, dy = self.dx[l]
-        L.or_patch_step(which, w, h, dt / dx, dt / dy, 9.81, _dp(aux), _dp(G), _dp(Gn),
-                        self.order, self.limiter, self.transverse)
-        return Gn[:, 2:h + 2, 2:w + 2]
+        xe = np.zeros((3, 3, h, w + 1))
+        ye = np.zeros((3, 3, h + 1, w))
+        L.or_patch_step_edges(which, w, h, dt / dx, dt / dy, 9.81, _dp(aux), _dp(G), _dp(Gn),
+                              self.order, self.limiter, self.transverse, _dp(xe), _dp(ye))
+        return Gn[:, 2:h + 2, 2:w + 2], xe, ye
 
     def fill_ring(self, l, alpha):
         if l == 0 or not self.patches[l]:
@@ -232,9 +241,11 @@ class Hierarchy:
         if l > 0:
             self.fill_ring(l, self.sub[l] / self.ratios[l - 1] if alpha is None else alpha)
         new = self.q[l].copy()
+        self.edges[l] = []
         for p in self.patches[l]:
             i0, j0, w, h = p
-            new[:, j0:j0 + h, i0:i0 + w] = self._patch_step(l, p, self.which, dt)
+            new[:, j0:j0 + h, i0:i0 + w], xe, ye = self._patch_step(l, p, self.which, dt)
+            self.edges[l].append((p, xe, ye))
         self.q_old[l] = self.q[l]
         self.q[l] = new
         self.t[l] += dt
@@ -262,7 +273,9 @@ class Hierarchy:
             self.patches[g] = []
 
     def advance(self, l, dt):
-        """Berger-Oliger recursion from level l (Sec. 3)."""
+        """Berger-Oliger recursion from level l (Sec. 3), with the flux
+        correction at coarse-fine edges after the finer level's substeps when
+        refluxing is on."""
         self.step_level(l, dt)
         if l + 1 < self.L and self.patches[l + 1]:
             r = self.ratios[l]
@@ -270,10 +283,101 @@ class Hierarchy:
                 # this level's ring at the new time, for the finer level's
                 # time interpolation
                 self.fill_ring(l, (self.sub[l] + 1) / self.ratios[l - 1])
+            if self.reflux:
+                faces = self.coarse_fine_faces(l + 1)
+                coarse = [self._edge_flux(l, f["coarse"]) for f in faces]
+                fine = [np.zeros(3) for _ in faces]
             for k in range(r):
                 self.sub[l + 1] = k
                 self.advance(l + 1, dt / r)
+                if self.reflux:
+                    for n, f in enumerate(faces):
+                        for e in f["fine"]:
+                            fine[n] = fine[n] + self._edge_flux(l + 1, e)
             average_down(self.q[l + 1], self.q[l], r, self.patches[l + 1])
+            if self.reflux:
+                self.apply_reflux(l, dt, faces, coarse, fine)
+
+    # -- flux bookkeeping at coarse-fine edges (refluxing) ---------------------
+    def _flux(self, l, axis, i, j):
+        """Flux of the time-reversed adjoint through a face normal to `axis`
+        (0: x, 1: y) at cell (i, j) of level l from its state at the start of
+        the level's last step: -A^T q = -(u/rho, K p, 0) in x, -B^T q =
+        -(v/rho, 0, K p) in y (Sec. 2 adjoint equation, in the reversed time)."""
+        q = self.q_old[l][:, j, i]
+        rho, K = self.rho[l][j, i], self.K[l][j, i]
+        if axis == 0:
+            return np.array([-q[1] / rho, -K * q[0], 0.0])
+        return np.array([-q[2] / rho, 0.0, -K * q[0]])
+
+    def _edge_flux(self, l, e):
+        """Numerical flux through an edge of level l in its last step, from
+        the cell on the patch side: the cell's flux plus what the edge gave
+        it, F = f(Q_left) + A-dQ + F~ = f(Q_right) - A+dQ + F~ (f-wave form:
+        A-dQ + A+dQ is the flux difference, so both sides agree)."""
+        pidx, axis, li, lj, cell_side = e
+        (i0, j0, w, h), xe, ye = self.edges[l][pidx]
+        arr = xe if axis == 0 else ye
+        am, ap, F = arr[0][:, lj, li], arr[1][:, lj, li], arr[2][:, lj, li]
+        if cell_side < 0:   # the cell is left of / below the edge
+            ci, cj = (i0 + li - 1, j0 + lj) if axis == 0 else (i0 + li, j0 + lj - 1)
+            return self._flux(l, axis, ci, cj) + am + F
+        ci, cj = i0 + li, j0 + lj
+        return self._flux(l, axis, ci, cj) - ap + F
+
+    def _patch_of(self, l, i, j):
+        for n, (i0, j0, w, h) in enumerate(self.patches[l]):
+            if i0 <= i < i0 + w and j0 <= j < j0 + h:
+                return n
+        raise ValueError(f"cell ({i}, {j}) of level {l} lies in none of its patches")
+
+    def coarse_fine_faces(self, f):
+        """Every coarse edge between a level-f patch and a level f-1 cell that
+        no level-f patch covers: the coarse cell, the axis, the side s of the
+        coarse cell (+1: it lies left of / below the edge), the edge as level
+        f-1's step saw it and the r edges of level f along it."""
+        c = f - 1
+        r = self.ratios[c]
+        NX, NY = self.n[c]
+        covered = np.zeros((NY, NX), dtype=bool)
+        for (i0, j0, w, h) in self.patches[f]:
+            covered[j0 // r:(j0 + h) // r, i0 // r:(i0 + w) // r] = True
+        faces = []
+        for pf, (i0, j0, w, h) in enumerate(self.patches[f]):
+            I0, J0, W, H = i0 // r, j0 // r, w // r, h // r
+            sides = []
+            for J in range(J0, J0 + H):
+                sides.append((0, I0 - 1, J, +1, [(pf, 0, 0, (J - J0) * r + jj, +1) for jj in range(r)]))
+                sides.append((0, I0 + W, J, -1, [(pf, 0, w, (J - J0) * r + jj, -1) for jj in range(r)]))
+            for I in range(I0, I0 + W):
+                sides.append((1, I, J0 - 1, +1, [(pf, 1, (I - I0) * r + ii, 0, +1) for ii in range(r)]))
+                sides.append((1, I, J0 + H, -1, [(pf, 1, (I - I0) * r + ii, h, -1) for ii in range(r)]))
+            for axis, I, J, s, fine in sides:
+                if not (0 <= I < NX and 0 <= J < NY) or covered[J, I]:
+                    continue
+                pc = self._patch_of(c, I, J)
+                ci0, cj0 = self.patches[c][pc][:2]
+                # the coarse edge in the coarse patch's edge arrays; the
+                # coarse cell lies on side -s of it in the convention above
+                if axis == 0:
+                    li, lj = (I - ci0 + 1, J - cj0) if s > 0 else (I - ci0, J - cj0)
+                else:
+                    li, lj = (I - ci0, J - cj0 + 1) if s > 0 else (I - ci0, J - cj0)
+                faces.append(dict(cell=(I, J), axis=axis, s=s, coarse=(pc, axis, li, lj, -s), fine=fine))
+        return faces
+
+    def apply_reflux(self, c, dt, faces, coarse, fine):
+        """Correct each coarse cell next to the finer level by the difference
+        between the coarse flux through the shared edge and the mean of the
+        finer level's fluxes through it over its substeps:
+        Q_C += s dt/dx (F_coarse - sum F_fine / r^2), so that what the coarse
+        cell loses through the edge is what the finer level gained."""
+        r = self.ratios[c]
+        dx, dy = self.dx[c]
+        for f, Fc, Ff in zip(faces, coarse, fine):
+            I, J = f["cell"]
+            h = dx if f["axis"] == 0 else dy
+            self.q[c][:, J, I] += f["s"] * (dt / h) * (Fc - Ff / (r * r))
 
 
 # ---------------------------------------------------------------------------

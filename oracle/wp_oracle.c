@@ -734,6 +734,40 @@ double or_patch_step(int which, int nx, int ny, double dtdx, double dtdy, double
     return or_step2d(which, nx, ny, dtdx, dtdy, g, aux, q, qn, order, limiter, transverse);
 }
 
+/* The same step, also returning the quantities each cell edge contributes to
+ * its two cells, for the flux bookkeeping at coarse-fine edges (refluxing):
+ *   xe [3][m][ny][nx+1]: A-dQ, A+dQ and the correction flux F (transverse
+ *      terms included) at x-edge (i-1/2, j), i = 0..nx, j = 0..ny-1;
+ *   ye [3][m][ny+1][nx]: B-dQ, B+dQ and G at y-edge (i, j-1/2), j = 0..ny.
+ * The cell left of (below) an edge receives -dt/dx (A-dQ + F) (-dt/dy (B-dQ
+ * + G)) from it, the cell right of (above) it -dt/dx (A+dQ - F). */
+double or_patch_step_edges(int which, int nx, int ny, double dtdx, double dtdy, double g, const double *aux,
+                           const double *q, double *qn, int order, int limiter, int transverse, double *xe,
+                           double *ye)
+{
+    double cfl = or_step2d(which, nx, ny, dtdx, dtdy, g, aux, q, qn, order, limiter, transverse);
+    grid_t gr = {nx, ny, nx + 2 * NG, ny + 2 * NG};
+    const int m = SOLVERS[which].m;
+    const long xs = (long)ny * (nx + 1), ys = (long)(ny + 1) * nx;
+    for (int k = 0; k < m; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i <= nx; i++) {
+                long e = gidx(&gr, i, j), o = (long)k * xs + (long)j * (nx + 1) + i;
+                xe[o] = WORK.amx[e * MAXM + k];
+                xe[(long)m * xs + o] = WORK.apx[e * MAXM + k];
+                xe[2L * m * xs + o] = WORK.F[e * MAXM + k];
+            }
+    for (int k = 0; k < m; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i < nx; i++) {
+                long e = gidx(&gr, i, j), o = (long)k * ys + (long)j * nx + i;
+                ye[o] = WORK.amy[e * MAXM + k];
+                ye[(long)m * ys + o] = WORK.apy[e * MAXM + k];
+                ye[2L * m * ys + o] = WORK.G[e * MAXM + k];
+            }
+    return cfl;
+}
+
 /* aux fields of a ghosted patch from interior coefficients: acoustics (rho,K)
  * -> {Z, c, rho, K}; swe B -> {B}; lswe B -> {-B, sqrt(-g B)}. */
 void or_make_aux(int which, int nx, int ny, const double *c1, const double *c2, double g, double *aux)

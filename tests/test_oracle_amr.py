@@ -285,3 +285,84 @@ def test_berger_oliger_time_weights_keep_an_exact_linear_solution():
                 assert np.abs(got - ref[:, j0:j0 + h, i0:i0 + w]).max() < 1e-13, (step, l, (i0, j0))
         ref0 = exact(0, t)
         assert np.abs(H.q[0][:, 8:24, 8:24] - ref0[:, 8:24, 8:24]).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# refluxing: flux bookkeeping at coarse-fine edges of the conservative
+# (adjoint, f-wave) hierarchy (Sec. 3: the adjoint is in conservation form)
+# ---------------------------------------------------------------------------
+def _reflux_hierarchy(reflux, patches, ratios=(2, 2), n=32, seed=21):
+    from wp_synth import random_media
+    rho, K = random_media(n, n, seed=seed)
+    cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=-1.0, xhi=1.0, ylo=-1.0, yhi=1.0, dx=2.0 / n, dy=2.0 / n,
+               rho=rho, K=K, bc=[amr.BC_WALL] * 4, order=2, limiter=1, transverse=1)
+    dt = 0.8 * cfg["dx"] / float(np.sqrt(K / rho).max())
+    H = amr.Hierarchy(cfg, ratios, patches, equation="adjoint", reflux=reflux)
+    q0 = random_state(3, n, n, seed=5)
+    H.set_level(0, q0)
+    for l in range(1, len(ratios) + 1):
+        r = H.n[l][0] // n
+        H.set_level(l, np.repeat(np.repeat(q0, r, axis=1), r, axis=2))
+    return H, dt
+
+
+RF_PATCHES = [[(16, 16, 24, 20), (40, 12, 12, 28)], [(36, 40, 24, 16)]]
+
+
+def test_reflux_conserves_the_composite_sum_on_a_walled_domain():
+    """With walls the reversed adjoint flux of p~, -u~/rho, vanishes at the
+    boundary, so sum p~ dA is conserved on a uniform grid.  On three levels
+    the composite sum (the level-0 canvas after the averages) keeps it to
+    round-off only with the flux correction; without it the coarse and fine
+    fluxes through the coarse-fine edges differ and the sum drifts."""
+    for reflux in (True, False):
+        H, dt = _reflux_hierarchy(reflux, RF_PATCHES)
+        s0 = H.q[0][0].sum()
+        scale = np.abs(H.q[0][0]).sum()
+        drift = 0.0
+        for _ in range(4):
+            H.advance(0, dt)
+            drift = max(drift, abs(H.q[0][0].sum() - s0) / scale)
+        if reflux:
+            assert drift < 1e-14, drift
+        else:
+            assert drift > 1e-5, drift
+
+
+def test_reflux_corrects_only_coarse_cells_next_to_finer_patches():
+    """One coarse step of two levels: the correction touches exactly the
+    level-0 cells that share an edge with a level-1 patch and are covered by
+    none (every other cell of both levels equals the run without refluxing,
+    bit for bit); a patch covering the domain has no such edge and changes
+    nothing."""
+    patches = [[(16, 16, 24, 20), (40, 12, 12, 28), (8, 44, 16, 12)]]
+    A, dt = _reflux_hierarchy(True, patches, ratios=(2,))
+    B, _ = _reflux_hierarchy(False, patches, ratios=(2,))
+    A.advance(0, dt)
+    B.advance(0, dt)
+    assert np.array_equal(A.q[1], B.q[1])
+    touched = np.zeros(A.q[0].shape[1:], dtype=bool)
+    faces = A.coarse_fine_faces(1)
+    for f in faces:
+        touched[f["cell"][1], f["cell"][0]] = True
+    # perimeters 2 (12 + 10) + 2 (6 + 14) + 2 (8 + 6) coarse edges, less the
+    # 10 edges the first two patches share, seen from both
+    assert len(faces) == 112 - 2 * 10
+    diff = np.any(A.q[0] != B.q[0], axis=0)
+    assert not (diff & ~touched).any() and diff[touched].all()
+    full = [[(0, 0, 64, 64)]]
+    C, dt = _reflux_hierarchy(True, full, ratios=(2,))
+    D, _ = _reflux_hierarchy(False, full, ratios=(2,))
+    assert C.coarse_fine_faces(1) == []
+    C.advance(0, dt)
+    D.advance(0, dt)
+    assert all(np.array_equal(C.q[l], D.q[l]) for l in range(2))
+
+
+def test_reflux_needs_the_conservative_form():
+    from wp_synth import random_media
+    rho, K = random_media(16, 16, seed=1)
+    cfg = dict(kind="acoustics2d", nx=16, ny=16, xlo=-1.0, xhi=1.0, ylo=-1.0, yhi=1.0, dx=0.125, dy=0.125,
+               rho=rho, K=K, bc=[amr.BC_WALL] * 4, order=2, limiter=1, transverse=1)
+    with pytest.raises(ValueError):
+        amr.Hierarchy(cfg, (2,), [[(8, 8, 8, 8)]], equation="forward", reflux=True)
