@@ -92,6 +92,8 @@ _SIGS = {
     "wp_set_equation": (_I, [_P, _I]),
     "wp_set_snapshots": (_I, [_P, _P, _I, _D, _I]),
     "wp_get_equation": (_I, [_P, ctypes.POINTER(_I)]),
+    "wp_set_reflux": (_I, [_P, _I]),
+    "wp_get_reflux": (_I, [_P, ctypes.POINTER(_I)]),
     "wp_adjoint_run": (_I, [_P, ctypes.POINTER(wp_functional), ctypes.POINTER(wp_snapshot_spec)]),
     "wp_num_snapshots": (_I, [_P]),
     "wp_get_snapshot": (_I, [_P, _I, _P, _I]),
@@ -131,6 +133,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1511_03645_amd.build`")
+        # PyTorch's HIP runtime is loaded first, so that the library binds to
+        # the runtime that owns the device memory and streams torch hands it
+        _torch()
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
@@ -360,6 +365,15 @@ class WavePatch:
     def get_equation(self):
         v = ctypes.c_int(0)
         self._check(lib().wp_get_equation(self.h, ctypes.byref(v)))
+        return bool(v.value)
+
+    def set_reflux(self, on):
+        """wp_set_reflux: flux correction at coarse-fine edges of the adjoint hierarchy."""
+        self._check(lib().wp_set_reflux(self.h, int(on)))
+
+    def get_reflux(self):
+        v = ctypes.c_int()
+        self._check(lib().wp_get_reflux(self.h, ctypes.byref(v)))
         return bool(v.value)
 
     def adjoint_run(self, functional, dt, nsteps, snap_every):

@@ -3,6 +3,7 @@
 // flags), the ghost ring of a fine level from the level below with space-time
 // interpolation, the Berger-Oliger recursion and the fine-to-coarse average.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <vector>
 
@@ -155,6 +156,101 @@ int average_down(wp_ctx *ctx, int l, hipStream_t s)
     return WP_OK;
 }
 
+// The faces of refluxing between level f's patches and the level f-1 cells
+// that none of them covers (see Level), in the order: patch by patch, for
+// each coarse row of a patch its west then east face, then for each coarse
+// column its south then north face; then sorted by coarse cell (stably).
+int build_faces(wp_ctx *ctx, int f)
+{
+    Level &F = ctx->L[f], &C = ctx->L[f - 1];
+    const int r = F.ratio;
+    F.nfaces = F.nfgroups = 0;
+    if (F.patches.empty()) return WP_OK;
+    std::vector<uint8_t> covered((size_t)C.nx * C.ny, 0);
+    for (const wp_patch &p : F.patches)
+        for (int J = p.jlo / r; J < (p.jlo + p.ny) / r; ++J)
+            std::fill_n(&covered[(size_t)J * C.nx + p.ilo / r], p.nx / r, (uint8_t)1);
+    std::vector<std::array<int, 4>> faces;
+    auto add = [&](int I, int J, int axis, bool before, int fi, int fj) {
+        if (I < 0 || J < 0 || I >= C.nx || J >= C.ny || covered[(size_t)J * C.nx + I]) return;
+        faces.push_back({J * C.nx + I, axis | (before ? 2 : 0), fi, fj});
+    };
+    for (const wp_patch &p : F.patches) {
+        const int I0 = p.ilo / r, J0 = p.jlo / r, W = p.nx / r, H = p.ny / r;
+        for (int J = J0; J < J0 + H; ++J) {
+            add(I0 - 1, J, 0, true, p.ilo, J * r);
+            add(I0 + W, J, 0, false, p.ilo + p.nx - 1, J * r);
+        }
+        for (int I = I0; I < I0 + W; ++I) {
+            add(I, J0 - 1, 1, true, I * r, p.jlo);
+            add(I, J0 + H, 1, false, I * r, p.jlo + p.ny - 1);
+        }
+    }
+    std::stable_sort(faces.begin(), faces.end(),
+                     [](const std::array<int, 4> &a, const std::array<int, 4> &b) { return a[0] < b[0]; });
+    std::vector<int> flat, groups;
+    for (size_t k = 0; k < faces.size(); ++k) {
+        flat.insert(flat.end(), faces[k].begin(), faces[k].end());
+        if (k == 0 || faces[k][0] != faces[k - 1][0]) {
+            groups.push_back((int)k);
+            groups.push_back(0);
+        }
+        ++groups.back();
+    }
+    if (faces.empty()) return WP_OK;
+    int rc;
+    long long n = 0;
+    if ((rc = upload_ints(ctx, flat, F.faces_dev, n, F.faces_cap, "reflux faces")) != WP_OK) return rc;
+    if ((rc = upload_ints(ctx, groups, F.fgroups_dev, n, F.fgroups_cap, "reflux groups")) != WP_OK) return rc;
+    const size_t reg_bytes = sizeof(double) * 3 * faces.size();
+    if (F.freg_cap < reg_bytes || !F.freg_dev) {
+        if (F.freg_dev) wp_dfree(ctx, F.freg_dev);
+        F.freg_dev = (double *)wp_dalloc(ctx, reg_bytes + reg_bytes / 2);
+        F.freg_cap = F.freg_dev ? reg_bytes + reg_bytes / 2 : 0;
+        if (!F.freg_dev) return wp_fail(ctx, WP_ENOMEM, "reflux registers");
+    }
+    F.nfaces = (int)faces.size();
+    F.nfgroups = (int)(groups.size() / 2);
+    return WP_OK;
+}
+
+// Refluxing steps (see launch_reflux_fine): after each substep of level f
+// the fluxes of its faces' fine edges are added to the registers; after the
+// last, the level below is corrected.
+int reflux_fine(wp_ctx *ctx, int f, double dtf, bool first, hipStream_t s)
+{
+    Level &F = ctx->L[f];
+    const wp_problem &P = ctx->prob;
+    if (ctx->esz == 8)
+        launch_reflux_fine<double>(F.faces_dev, F.nfaces, (const double *)F.q[F.cur ^ 1], F.mat, F.nx, F.ny, P.bc,
+                                   ctx->mtab64, F.ratio, dtf / F.dx, dtf / F.dy, P.order, P.limiter, P.transverse,
+                                   first, F.freg_dev, s);
+    else
+        launch_reflux_fine<float>(F.faces_dev, F.nfaces, (const float *)F.q[F.cur ^ 1], F.mat, F.nx, F.ny, P.bc,
+                                  ctx->mtab64, F.ratio, dtf / F.dx, dtf / F.dy, P.order, P.limiter, P.transverse,
+                                  first, F.freg_dev, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "reflux launch: %s", hipGetErrorString(e));
+    return WP_OK;
+}
+
+int reflux_apply(wp_ctx *ctx, int c, double dt, hipStream_t s)
+{
+    Level &C = ctx->L[c], &F = ctx->L[c + 1];
+    const wp_problem &P = ctx->prob;
+    if (ctx->esz == 8)
+        launch_reflux_apply<double>(F.fgroups_dev, F.nfgroups, F.faces_dev, F.freg_dev, (const double *)C.q[C.cur ^ 1],
+                                    (double *)C.q[C.cur], C.mat, C.nx, C.ny, P.bc, ctx->mtab64, F.ratio, dt / C.dx,
+                                    dt / C.dy, P.order, P.limiter, P.transverse, s);
+    else
+        launch_reflux_apply<float>(F.fgroups_dev, F.nfgroups, F.faces_dev, F.freg_dev, (const float *)C.q[C.cur ^ 1],
+                                   (float *)C.q[C.cur], C.mat, C.nx, C.ny, P.bc, ctx->mtab64, F.ratio, dt / C.dx,
+                                   dt / C.dy, P.order, P.limiter, P.transverse, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "reflux launch: %s", hipGetErrorString(e));
+    return WP_OK;
+}
+
 // One Berger-Oliger step of level l and, recursively, its finer levels, on
 // stream s.  sub: index of this step among the ratio steps of level l within
 // one step of level l-1 (time weight sub / ratio for the ghost ring).  With
@@ -191,9 +287,15 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
         // this level's ring at its new time, read by the finer level's
         // interpolation next to the ring
         if (launch && l > 0 && (rc = fill_ring(ctx, l, (double)(sub + 1) / (double)lv.ratio, s)) != WP_OK) return rc;
-        for (int k = 0; k < r; ++k)
+        // refluxing of the adjoint system (conservative form) at the edges
+        // between the finer level's patches and this level
+        const bool rf = ctx->reflux && ctx->equation == 1 && ctx->L[l + 1].nfaces > 0;
+        for (int k = 0; k < r; ++k) {
             if ((rc = bo_advance(ctx, l + 1, dt / r, k, s, launch)) != WP_OK) return rc;
+            if (launch && rf && (rc = reflux_fine(ctx, l + 1, dt / r, k == 0, s)) != WP_OK) return rc;
+        }
         if (launch && (rc = average_down(ctx, l + 1, s)) != WP_OK) return rc;
+        if (launch && rf && (rc = reflux_apply(ctx, l, dt, s)) != WP_OK) return rc;
     }
     return WP_OK;
 }
@@ -255,6 +357,7 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     if ((rc = upload_ints(ctx, cover_list(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, F.cover_cap, "cover")) !=
         WP_OK)
         return rc;
+    if ((rc = build_faces(ctx, f)) != WP_OK) return rc;
     F.t = C.t;
     F.prev_valid = false;
     F.flags_valid = false;
@@ -265,6 +368,7 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
         G.patches.clear();
         if ((rc = wp_upload_tiles(ctx, G)) != WP_OK) return rc;
         G.nring = G.nringb = G.ncover = 0;
+        G.nfaces = G.nfgroups = 0;
         G.prev_valid = false;
         G.flags_valid = false;
     }

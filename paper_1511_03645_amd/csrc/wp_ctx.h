@@ -55,6 +55,15 @@ struct Level {
     // allocated sizes (bytes) of the tables above: a smaller table is written
     // into the same block
     size_t tiles_cap = 0, ftiles_cap = 0, ring_cap = 0, ringb_cap = 0, cover_cap = 0;
+    // refluxing (adjoint hierarchy): the edges between this level's patches
+    // and level-1 cells that no patch of this level covers, as int4
+    // {coarse cell, axis | (coarse cell before the edge) << 1, first fine
+    // cell i, j}, sorted by coarse cell; the groups {first face, count} of
+    // each coarse cell; one FP64 register of 3 per face
+    int *faces_dev = nullptr, *fgroups_dev = nullptr;
+    double *freg_dev = nullptr;
+    int nfaces = 0, nfgroups = 0;
+    size_t faces_cap = 0, fgroups_cap = 0, freg_cap = 0;
     // false after a tile-table rebuild failed (its tables are empty): steps
     // and flags of the level fail with WP_ESTATE until a rebuild succeeds
     bool tables_ok = true;
@@ -78,6 +87,7 @@ struct wp_ctx {
     std::vector<uint8_t> mat0;
     double cmax = 0.0;
     void *mtab = nullptr, *ptab = nullptr;
+    double *mtab64 = nullptr;            // [nmat][4] Z, c, rho, K in FP64 (flux bookkeeping)
     // shallow water
     void *Bdev = nullptr;                // bathymetry (FP64)
     void *cbar = nullptr;                // sqrt(-g B) in the adjoint precision
@@ -102,6 +112,7 @@ struct wp_ctx {
     bool phi_valid = false;
     std::string err;
     int equation = 0;                    // system the level hierarchy's steps solve: 0 forward, 1 adjoint
+    bool reflux = false;                 // flux correction at coarse-fine edges (adjoint system only)
     int tile_rows = 0;
     int pair_rows = -1;                  // two-step tile height: -1 built-in choice, 0 off
     // captured launch sequences (recorded on an internal stream, replayed on

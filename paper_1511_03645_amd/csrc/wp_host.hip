@@ -370,6 +370,19 @@ static int build_materials(wp_ctx *ctx, const wp_coefficients *coef)
             p[1] = (Z[a] * Z[b] + 1.0) / (Z[a] * Z[a] + 1.0);   // wave 1, upwind edge to the right
             p[2] = (Z[a] * Z[b] + 1.0) / (Z[b] * Z[b] + 1.0);   // wave 2, upwind edge to the left
         }
+    {
+        std::vector<double> m64(nm * 4);
+        for (int a = 0; a < nm; ++a) {
+            m64[a * 4 + 0] = Z[a];
+            m64[a * 4 + 1] = c[a];
+            m64[a * 4 + 2] = ctx->rho[a];
+            m64[a * 4 + 3] = ctx->K[a];
+        }
+        ctx->mtab64 = (double *)wp_dalloc(ctx, m64.size() * 8);
+        if (!ctx->mtab64) return wp_fail(ctx, WP_ENOMEM, "material tables");
+        if (hipMemcpy(ctx->mtab64, m64.data(), m64.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return wp_fail(ctx, WP_EDEVICE, "material table upload");
+    }
     ctx->mtab = wp_dalloc(ctx, mt.size() * ctx->esz);
     ctx->ptab = wp_dalloc(ctx, pt.size() * ctx->esz);
     if (!ctx->mtab || !ctx->ptab) return wp_fail(ctx, WP_ENOMEM, "material tables");
@@ -1073,9 +1086,32 @@ extern "C" int wp_set_equation(wp_ctx *ctx, int adjoint)
     if (!ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "the adjoint hierarchy is for acoustics");
     if (ctx->equation == adjoint) return WP_OK;
     ctx->equation = adjoint;
+    if (!adjoint) ctx->reflux = false;
     int rc;
     for (Level &lv : ctx->L)
         if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
+    return WP_OK;
+}
+
+extern "C" int wp_set_reflux(wp_ctx *ctx, int on)
+{
+    if (!ctx) return WP_EINVAL;
+    if (on != 0 && on != 1) return wp_fail(ctx, WP_EINVAL, "on must be 0 or 1");
+    if (on && !(ctx->is_acoustics && ctx->kind2d))
+        return wp_fail(ctx, WP_EINVAL, "refluxing is for the 2D acoustics adjoint hierarchy");
+    if (on && ctx->equation != 1)
+        return wp_fail(ctx, WP_ESTATE, "refluxing needs the adjoint system (the forward one is not conservative)");
+    if (ctx->reflux != (on == 1)) {
+        ctx->reflux = on == 1;
+        ++ctx->topo_gen;   // captured Berger-Oliger sequences gain or lose the correction
+    }
+    return WP_OK;
+}
+
+extern "C" int wp_get_reflux(const wp_ctx *ctx, int *on)
+{
+    if (!ctx || !on) return ctx ? wp_fail_get(ctx, WP_EINVAL, "null output") : WP_EINVAL;
+    *on = ctx->reflux ? 1 : 0;
     return WP_OK;
 }
 

@@ -206,4 +206,19 @@ template <typename T>
 void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
                     long long csc, int r, hipStream_t s);
 
+// Refluxing of the adjoint hierarchy (conservative f-wave form): add the
+// fluxes of the fine edges of every face (r per face, from the canvas the
+// fine step started from) to its register (first: start from zero); then
+// correct every coarse cell by s dt/h (F_coarse - register / r^2), the
+// coarse flux from the canvas the coarse step started from.  faces: int4
+// records, groups: int2 {first face, count} per coarse cell.
+template <typename T>
+void launch_reflux_fine(const int *faces, int nfaces, const T *fine_old, const uint8_t *mat, int nx, int ny,
+                        const int *bc, const double *mtab64, int r, double nux, double nuy, int order, int limiter,
+                        int transverse, bool first, double *reg, hipStream_t s);
+template <typename T>
+void launch_reflux_apply(const int *groups, int ngroups, const int *faces, const double *reg, const T *coarse_old,
+                         T *coarse_cur, const uint8_t *mat, int nx, int ny, const int *bc, const double *mtab64,
+                         int r, double nux, double nuy, int order, int limiter, int transverse, hipStream_t s);
+
 }  // namespace wp

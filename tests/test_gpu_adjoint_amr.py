@@ -182,3 +182,82 @@ def test_fp32_adjoint_hierarchy_error_stated():
     err2 = np.abs(w.get_state(level=2, patch=0) - H.q[2][:, j0:j0 + ny, i0:i0 + nx]).max() / scale
     print(f"FP32 adjoint hierarchy: rel err level 0 {err0:.2e}, level 2 {err2:.2e}")
     assert err0 < 1e-5 and err2 < 1e-5
+
+
+REFLUX_LAYOUTS = [
+    # n0, ratios, boxes per fine level, bc
+    (32, [2, 2], [[(16, 16, 24, 20), (40, 12, 12, 28)], [(36, 40, 24, 16)]], (1, 1, 1, 1)),
+    (24, [4], [[(8, 8, 32, 24), (40, 8, 16, 48)]], (0, 0, 0, 0)),
+    (16, [2, 4], [[(4, 4, 20, 16)], [(24, 24, 40, 32), (64, 24, 8, 8)]], (0, 1, 1, 0)),
+]
+
+
+@pytest.mark.parametrize("n,ratios,boxes,bc", REFLUX_LAYOUTS)
+def test_refluxed_adjoint_hierarchy_matches_oracle(n, ratios, boxes, bc):
+    """The flux correction at coarse-fine edges of the adjoint hierarchy
+    (wp_set_reflux) against the oracle's refluxed hierarchy, every level's
+    patches after captured and eager coarse steps; with walls all round the
+    composite sum of p~ (the level-0 canvas) stays constant to round-off."""
+    print(f"case refluxed adjoint amr n={n} ratios={ratios} bc={bc}", flush=True)
+    cfg = cfg_of(n, bc, seed=n + 3)
+    H = amr.Hierarchy(cfg, ratios, [], equation="adjoint", reflux=True)
+    w = wp.from_config(cfg, num_levels=len(ratios) + 1, ratios=tuple(ratios))
+    with pytest.raises(wp.WPError) as e:
+        w.set_reflux(True)          # the forward system is not conservative
+    assert e.value.code == wp.WP_ESTATE
+    w.set_equation(True)
+    w.set_reflux(True)
+    assert w.get_reflux() is True
+    q0 = random_state(3, n, n, seed=n + 9)
+    H.set_level(0, q0)
+    w.set_state(q0, level=0)
+    for l, b in enumerate(boxes):
+        H.regrid(l, b)
+        w.regrid(l, b)
+    for l in range(1, len(ratios) + 1):
+        nl = H.n[l][0]
+        ql = random_state(3, nl, nl, seed=300 + l) * 0.5
+        H.set_level(l, ql)
+        w.set_state(ql, level=l)
+    dt = dt_of(cfg)
+    for _ in range(2):
+        H.advance(0, dt)
+    w.advance(2, dt)
+    compare(w, H, "refluxed adjoint, two coarse steps")
+    # the fine levels start from data of their own, so the level-0 canvas
+    # is the composite state only once the first average has run
+    s2 = float(w.get_state(level=0)[0].sum())
+    H.advance(0, dt)
+    w.advance(1, dt)
+    compare(w, H, "refluxed adjoint, three coarse steps")
+    if bc == (1, 1, 1, 1):
+        p = w.get_state(level=0)[0]
+        assert abs(float(p.sum()) - s2) <= 1e-13 * float(np.abs(p).sum())
+    # switching back to the forward system turns the correction off
+    w.set_equation(False)
+    assert w.get_reflux() is False
+
+
+def test_reflux_fp32_error_stated():
+    """FP32 hierarchy with refluxing against the FP64 oracle: the state error
+    stays below 1e-5 of max |q| after three coarse steps (the registers and
+    the corrections are taken in FP64, the canvases hold FP32)."""
+    n, ratios, boxes, bc = REFLUX_LAYOUTS[0]
+    cfg = cfg_of(n, bc, seed=n + 3)
+    H = amr.Hierarchy(cfg, ratios, [], equation="adjoint", reflux=True)
+    w = wp.from_config(cfg, precision=wp.FP32, num_levels=len(ratios) + 1, ratios=tuple(ratios))
+    w.set_equation(True)
+    w.set_reflux(True)
+    q0 = random_state(3, n, n, seed=n + 9)
+    H.set_level(0, q0)
+    w.set_state(q0, level=0)
+    for l, b in enumerate(boxes):
+        H.regrid(l, b)
+        w.regrid(l, b)
+    dt = dt_of(cfg)
+    for _ in range(3):
+        H.advance(0, dt)
+    w.advance(3, dt)
+    err = np.abs(w.get_state(level=0) - H.q[0]).max() / np.abs(H.q[0]).max()
+    print(f"FP32 refluxed hierarchy: level-0 relative error {err:.2e}")
+    assert err < 1e-5
