@@ -371,6 +371,27 @@ int wp_cluster(const uint8_t *flags, const uint8_t *allowed, int nx, int ny, dou
  * constant in t), both accumulated in FP64 with compensated summation. */
 int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int which, int snapshot, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * compensated FP64 inner-product reduction of wp_functional_value (which = 1,
+ * and J when b holds phi) on caller-owned device arrays, needing no handle.
+ *   a, b       device arrays [m][cells] (component stride = cells), both
+ *              double (precision WP_FP64) or both float (WP_FP32)
+ *   out        device memory, one double: dA * sum_k sum_i a_k[i] b_k[i]
+ *              (the same block count and summation order as
+ *              wp_functional_value, so the two agree)
+ *   stream     hipStream_t the two kernels are enqueued on (NULL: the null
+ *              stream); nothing is copied to the host and nothing synchronises
+ * The per-block partial sums go to a fixed 16 KiB device array of the library
+ * (one per GPU, held until the process ends), so the call allocates nothing;
+ * calls that overlap on one GPU (two streams, two threads) race on it.
+ * WP_EINVAL for a null pointer, another precision, m outside 1..3, or cells
+ * outside 1..WP_NOALLOC_MAX_CELLS; WP_EDEVICE if the array's device address
+ * cannot be found or a launch fails. */
+#define WP_NOALLOC_MAX_CELLS (1LL << 32)
+int wp_inner_product_noalloc(const void *a, const void *b, int precision, long long cells, int m, double dA,
+                             double *out, void *stream);
+
 /* Current time of a level; largest Courant number of the last step. */
 int wp_get_time(const wp_ctx *ctx, int level, double *t);
 int wp_set_time(wp_ctx *ctx, int level, double t);

@@ -108,6 +108,7 @@ _SIGS = {
     "wp_forward_flagged": (_I, [_P, _D, _I, _I, _D, _D, _D, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_float)]),
     "wp_cluster": (_I, [_P, _P, _I, _I, _D, _I, _I, ctypes.POINTER(wp_patch), _I, ctypes.POINTER(_I)]),
+    "wp_inner_product_noalloc": (_I, [_P, _P, _I, ctypes.c_longlong, _I, _D, _P, _P]),
     "wp_functional_value": (_I, [_P, ctypes.POINTER(wp_functional), _I, _I, ctypes.POINTER(_D)]),
     "wp_get_time": (_I, [_P, _I, ctypes.POINTER(_D)]),
     "wp_set_time": (_I, [_P, _I, _D]),
@@ -219,6 +220,24 @@ def cluster(flags, allowed=None, efficiency=0.7, maxside=16, minside=2):
     if rc != WP_OK:
         raise WPError(rc, "wp_cluster: invalid arguments")
     return [(p.ilo, p.jlo, p.nx, p.ny) for p in arr[:n.value]]
+
+
+def inner_product_noalloc(a, b, cells, m, dA, out, precision=FP64, stream=None):
+    """wp_inner_product_noalloc on torch device tensors: out (one float64 on
+    the device) = dA * sum_k sum_i a_k[i] b_k[i]; a, b [m][cells] contiguous,
+    float64 (FP64) or float32 (FP32).  Enqueued on `stream` (default: torch's
+    current stream); nothing is allocated by the library."""
+    torch = _torch()
+    for t in (a, b, out):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("a, b and out must be contiguous device tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    rc = lib().wp_inner_product_noalloc(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), precision,
+                                        int(cells), int(m), float(dA), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(stream or 0))
+    if rc != WP_OK:
+        raise WPError(rc, "wp_inner_product_noalloc: " + lib().wp_status_string(rc).decode())
 
 
 def _ptr(a):
