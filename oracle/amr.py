@@ -154,14 +154,20 @@ def average_down(fine, coarse, r, patches):
 # Berger-Oliger driver
 # ---------------------------------------------------------------------------
 class Hierarchy:
-    """Dense per-level arrays of a 2D acoustics problem on nested patches.
+    """Dense per-level arrays of a 2D acoustics or shallow-water problem on
+    nested patches.
 
-    cfg: level-0 workload dict (rho, K, bc, dx, ...); ratios: refinement
+    cfg: level-0 workload dict (rho, K or B, bc, dx, ...); ratios: refinement
     ratios; patches: list per level of (ilo, jlo, nx, ny) boxes (level 0 may be
-    omitted: one patch covering the domain)."""
+    omitted: one patch covering the domain).  Shallow water (cfg kind
+    "swe2d", state eta, hu, hv): B_levels gives the bathymetry cell averages
+    of the levels above 0 (default: each fine cell takes the value of the
+    level-0 cell containing it); the ghost ring, the regrid and the average
+    work on eta = h + B itself, so a lake at rest (eta = 0, no velocity) stays
+    exactly at rest on every level (Sec. 5.3)."""
 
     def __init__(self, cfg, ratios, patches, order=None, limiter=None, transverse=None, equation="forward",
-                 reflux=False):
+                 reflux=False, B_levels=None):
         self.cfg = cfg
         self.ratios = list(ratios)
         self.L = len(self.ratios) + 1
@@ -172,6 +178,11 @@ class Hierarchy:
         # the system every patch step solves: the forward acoustics or its
         # adjoint (Sec. 2), the latter refined as Sec. 7 proposes
         self.which = {"forward": 0, "adjoint": 1}[equation]
+        self.swe = cfg["kind"] == "swe2d"
+        if self.swe:
+            if equation != "forward":
+                raise ValueError("the shallow-water hierarchy solves the forward problem")
+            self.which = 2
         # flux bookkeeping at coarse-fine edges: only the adjoint is in
         # conservation form (Sec. 3 contrasts it with the forward problem)
         if reflux and self.which != 1:
@@ -195,12 +206,20 @@ class Hierarchy:
         self.sub = [0] * self.L
         self.t = [0.0] * self.L
         # media of each level: those of the level-0 cell containing the cell
-        self.rho, self.K = [], []
+        # (shallow water: the given bathymetry of the level, by default the
+        # same piecewise-constant extension)
+        self.rho, self.K, self.B = [], [], []
         for l, (nxl, nyl) in enumerate(self.n):
             Rl = nxl // nx0
             jj, ii = np.mgrid[0:nyl, 0:nxl]
-            self.rho.append(np.asarray(cfg["rho"])[jj // Rl, ii // Rl])
-            self.K.append(np.asarray(cfg["K"])[jj // Rl, ii // Rl])
+            if self.swe:
+                if l > 0 and B_levels is not None and B_levels[l - 1] is not None:
+                    self.B.append(np.asarray(B_levels[l - 1], dtype=np.float64).reshape(nyl, nxl))
+                else:
+                    self.B.append(np.asarray(cfg["B"], dtype=np.float64)[jj // Rl, ii // Rl])
+            else:
+                self.rho.append(np.asarray(cfg["rho"])[jj // Rl, ii // Rl])
+                self.K.append(np.asarray(cfg["K"])[jj // Rl, ii // Rl])
 
     def set_level(self, l, q):
         self.q[l] = np.array(q, dtype=np.float64).reshape(self.q[l].shape)
@@ -216,16 +235,21 @@ class Hierarchy:
         G[1] = np.where(fi[None, :], -G[1], G[1])
         G[2] = np.where(fj[:, None], -G[2], G[2])
         G = np.ascontiguousarray(G)
-        rho = np.ascontiguousarray(self.rho[l][rj[:, None], ri[None, :]])
-        K = np.ascontiguousarray(self.K[l][rj[:, None], ri[None, :]])
         aux = np.zeros((4, h + 4, w + 4))
         L = lib()
-        L.or_make_aux(0, w, h, _dp(rho), _dp(K), 9.81, _dp(aux))
+        g = self.cfg.get("g", 9.81)
+        if self.swe:
+            B = np.ascontiguousarray(self.B[l][rj[:, None], ri[None, :]])
+            L.or_make_aux(2, w, h, _dp(B), _dp(B), g, _dp(aux))
+        else:
+            rho = np.ascontiguousarray(self.rho[l][rj[:, None], ri[None, :]])
+            K = np.ascontiguousarray(self.K[l][rj[:, None], ri[None, :]])
+            L.or_make_aux(0, w, h, _dp(rho), _dp(K), g, _dp(aux))
         Gn = np.zeros_like(G)
         dx, dy = self.dx[l]
         xe = np.zeros((3, 3, h, w + 1))
         ye = np.zeros((3, 3, h + 1, w))
-        L.or_patch_step_edges(which, w, h, dt / dx, dt / dy, 9.81, _dp(aux), _dp(G), _dp(Gn),
+        L.or_patch_step_edges(which, w, h, dt / dx, dt / dy, g, _dp(aux), _dp(G), _dp(Gn),
                               self.order, self.limiter, self.transverse, _dp(xe), _dp(ye))
         return Gn[:, 2:h + 2, 2:w + 2], xe, ye
 

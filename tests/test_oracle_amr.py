@@ -366,3 +366,54 @@ def test_reflux_needs_the_conservative_form():
                rho=rho, K=K, bc=[amr.BC_WALL] * 4, order=2, limiter=1, transverse=1)
     with pytest.raises(ValueError):
         amr.Hierarchy(cfg, (2,), [[(8, 8, 8, 8)]], equation="forward", reflux=True)
+
+
+# ---------------------------------------------------------------------------
+# shallow water on a hierarchy (Sec. 5.3 ocean with refinement, eta-based
+# ghost rings and averages)
+# ---------------------------------------------------------------------------
+def _swe_levels(n0=32, ratios=(2, 2)):
+    from wp_synth import swe2d_amr
+    return swe2d_amr(n0=n0, ratios=ratios)
+
+
+def test_swe_hierarchy_keeps_a_lake_at_rest_exactly():
+    """eta = 0, hu = hv = 0 over the shelf on three levels, each with its own
+    cell-integrated bathymetry: the well-balanced steps, the ring filled from
+    eta (not h), the averages of eta and the regrid interpolation of eta keep
+    every level exactly at rest, bit for bit."""
+    cfg = _swe_levels()
+    H = amr.Hierarchy(cfg, cfg["ratios"], [], B_levels=cfg["B_levels"])
+    H.regrid(0, [(40, 8, 20, 32), (8, 8, 16, 16)])
+    H.regrid(1, [(88, 24, 24, 32)])
+    for l in range(3):
+        assert not H.q[l].any()
+    for k in range(3):
+        H.advance(0, cfg["dt"])
+        if k == 1:
+            H.regrid(1, [(84, 20, 28, 40)])
+    for l in range(3):
+        assert not H.q[l].any(), f"level {l} moved"
+    # the same with h interpolated instead of eta would not: eta = 0 and
+    # B differing between a coarse cell and its children give h jumps
+    assert np.abs(H.B[1][:, :].reshape(64, 32, 2).mean(axis=2)[::2] - H.B[0]).max() > 0.0
+
+
+def test_swe_full_cover_fine_level_equals_uniform_fine_run():
+    """A level-1 patch covering the domain steps exactly as a uniform run on
+    the fine grid with the fine bathymetry (its ring is empty, every edge is
+    the fine grid's own), bit for bit."""
+    import oracle
+    cfg = _swe_levels(n0=24, ratios=(2,))
+    r = 2
+    n1 = 48
+    H = amr.Hierarchy(cfg, (r,), [[(0, 0, n1, n1)]], B_levels=cfg["B_levels"])
+    q1 = np.repeat(np.repeat(cfg["q0"], r, axis=1), r, axis=2)
+    H.set_level(0, cfg["q0"])
+    H.set_level(1, q1)
+    fine = dict(cfg, nx=n1, ny=n1, dx=cfg["dx"] / r, dy=cfg["dy"] / r, B=cfg["B_levels"][0])
+    for _ in range(3):
+        H.advance(0, cfg["dt"])
+    ref, _, _ = oracle.run(fine, "swe", q1, 6, dt=cfg["dt"] / r)
+    assert np.array_equal(H.q[1], ref)
+    assert np.abs(ref[0]).max() > 1e-3

@@ -220,6 +220,56 @@ def _logcosh(u):
     return a + np.log1p(np.exp(-2.0 * a)) - math.log(2.0)
 
 
+def shelf_bathymetry(n, width, xs=1850e3 / 2048e3, L=25e3):
+    """Cell averages on an n x n grid of [0, width]^2 of the shelf profile
+    B(x) = -2100 + 1900 tanh((x - x_s)/L) (x_s a fraction of the width),
+    integrated exactly per cell with the log-cosh antiderivative."""
+    dx = width / n
+    xe = np.arange(n + 1, dtype=np.float64) * dx
+    F = -2100.0 * xe + 1900.0 * L * _logcosh((xe - xs * width) / L)
+    return np.tile((F[1:] - F[:-1]) / dx, (n, 1))
+
+
+def swe2d_amr(n0=256, ratios=(4, 2), width=2048e3, seed=3, cfl=0.9, T=10800.0, every=10, g=9.81):
+    """The shallow-water ocean of `swe2d` at the full 2048 km width on a
+    coarse n0 x n0 grid with refinement ratios `ratios`: the level-0
+    workload dict plus `B_levels`, the cell-integrated bathymetry of every
+    finer level (exact cell averages at that level's resolution, so that each
+    coarse cell's value is the mean of its children up to rounding), and a
+    point gauge at the centre of the target box.  dt is the coarse step
+    (Courant number at most `cfl` at the deepest point), a multiple of
+    `every` steps to T."""
+    rng = np.random.default_rng(seed)
+    s = width / 2048e3
+    cx = rng.uniform(400e3, 900e3) * s
+    cy = rng.uniform(600e3, 1448e3) * s
+    yg = rng.uniform(800e3, 1248e3) * s
+    dx = width / n0
+    B = shelf_bathymetry(n0, width)
+    B_levels, R = [], 1
+    for r in ratios:
+        R *= r
+        B_levels.append(shelf_bathymetry(n0 * R, width))
+    xc = cell_centres(0.0, dx, n0)
+    X, Y = np.meshgrid(xc, xc)
+    q0 = np.zeros((3, n0, n0))
+    q0[0] = 0.5 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / 50e3 ** 2)
+    cmax = math.sqrt(g * (float(np.max(-B)) + 0.5))
+    nsteps = _steps_to_hit(T, cfl * dx / cmax, every)
+    hw = 25e3 * s
+    x0 = 1950e3 * s
+    return dict(
+        name="swe2d_amr", kind="swe2d", m=3, nx=n0, ny=n0, g=g,
+        xlo=0.0, xhi=width, ylo=0.0, yhi=width, dx=dx, dy=dx,
+        B=B, B_levels=B_levels, ratios=tuple(ratios), q0=q0, pulse=(cx, cy),
+        bc=[BC_EXTRAP] * 4, order=2, limiter=1, transverse=1,
+        dt=T / nsteps, nsteps=nsteps, snap_every=every, flag_every=every,
+        tol=1e-4, t_f=T, t_s=T, gauge=(x0 + hw, yg),
+        functional=dict(kind="box", x0=x0, x1=x0 + 2 * hw, y0=yg - hw, y1=yg + hw, cx=0.0, cy=0.0, r=0.0,
+                        component=0),
+    )
+
+
 def swe2d(n=2048, seed=3, cfl=0.9, T=10800.0, every=10, g=9.81):
     """Shallow water on [0, n km]^2 with 1 km cells.  Bathymetry cell averages
     of B(x) = -2100 + 1900 tanh((x - x_s)/L), x_s = (1850/2048) of the width,
@@ -235,11 +285,7 @@ def swe2d(n=2048, seed=3, cfl=0.9, T=10800.0, every=10, g=9.81):
     cy = rng.uniform(600e3, 1448e3) * s
     yg = rng.uniform(800e3, 1248e3) * s
     dx = 1000.0
-    xe = np.arange(n + 1, dtype=np.float64) * dx
-    xs, L = 1850e3 * s, 25e3
-    F = -2100.0 * xe + 1900.0 * L * _logcosh((xe - xs) / L)
-    Bx = (F[1:] - F[:-1]) / dx
-    B = np.tile(Bx, (n, 1))
+    B = shelf_bathymetry(n, width)
     xc = cell_centres(0.0, dx, n)
     X, Y = np.meshgrid(xc, xc)
     q0 = np.zeros((3, n, n))
