@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--pair-rows", type=int, default=-1,
                     help="tile height of the two-step kernel: 8, 12 or 16, 0 for one step per launch "
                          "(default: chosen by the autotuner)")
+    ap.add_argument("--max-steps", type=int, default=0,
+                    help="cap the step count of the AMR and shallow-water legs (a multiple of 10; for profiling "
+                         "runs, which take counters per dispatch; 0: the full workloads)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -241,7 +244,20 @@ def batch_compare(steps, warmup, count=64):
             "ms_fp64_loop": t64 * 1e3, "ms_fp64_batched": tb64 * 1e3, "ms_fp32_batched": t32 * 1e3}
 
 
-def swe_compare(steps, warmup, n=2048):
+def rel_err(a, ref):
+    """|a - ref| / |ref|, None when ref is 0 (a horizon cut short of the
+    arrival at the target)."""
+    return abs(a - ref) / abs(ref) if ref != 0.0 else None
+
+
+def capped(N, every, max_steps):
+    """N, or max_steps rounded down to a multiple of `every` when smaller."""
+    if max_steps and max_steps < N:
+        return max(every, (max_steps // every) * every)
+    return N
+
+
+def swe_compare(steps, warmup, n=2048, max_steps=0):
     """The shallow-water workload (n x n 1 km cells, abyssal plain rising to
     a shelf, Gaussian hump, coastal gauge box, 3 h): adjoint run with snapshots
     + forward run flagged every 10 steps + J, in FP64 and in mixed precision."""
@@ -250,6 +266,8 @@ def swe_compare(steps, warmup, n=2048):
     from wp_synth import swe2d
     cfg = swe2d(n=n, seed=3)
     N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    N = capped(N, every, max_steps)
+    cfg = dict(cfg, t_f=N * dt, t_s=N * dt)
     res = {}
     for name, prec in (("fp64", wp.FP64), ("mixed", wp.MIXED)):
         w = wp.from_config(cfg, precision=prec)
@@ -277,11 +295,11 @@ def swe_compare(steps, warmup, n=2048):
     res["workload"] = f"swe2d {n}x{n}, {N} forward + {N} adjoint steps, flags every {every}"
     res["unit"] = "cell-updates/s"
     res["mixed_speedup"] = res["mixed"]["value"] / res["fp64"]["value"]
-    res["J_rel_err_mixed"] = abs(res["mixed"]["J"] - res["fp64"]["J"]) / abs(res["fp64"]["J"])
+    res["J_rel_err_mixed"] = rel_err(res["mixed"]["J"], res["fp64"]["J"])
     return res
 
 
-def amr_compare(steps, warmup):
+def amr_compare(steps, warmup, max_steps=0):
     """The 3-level AMR workload (coarse grid 256^2, refinement ratios 4, 4,
     seeded ratio-aligned patches of sides 8..64: 400 on level 1, 1600 on
     level 2): adjoint run on the coarse grid with snapshots, then the forward
@@ -295,6 +313,8 @@ def amr_compare(steps, warmup):
     cfg = acoustics2d_amr(n0=256, seed=2)
     h = cfg["hierarchy"]
     N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    N = capped(N, every, max_steps)
+    cfg = dict(cfg, t_f=N * dt, t_s=N * dt)
     ratios = h["ratios"]
     cells = [sum(b[2] * b[3] for b in lv) for lv in h["levels"]]
     per_coarse = cells[0] + ratios[0] * cells[1] + ratios[0] * ratios[1] * cells[2]
@@ -336,7 +356,7 @@ def amr_compare(steps, warmup):
         res[name] = {"value": ups / sec, "ms_per_job": sec * 1e3, "J": J}
         del w
     res["fp32_speedup"] = res["fp32"]["value"] / res["fp64"]["value"]
-    res["J_rel_err_fp32"] = abs(res["fp32"]["J"] - res["fp64"]["J"]) / abs(res["fp64"]["J"])
+    res["J_rel_err_fp32"] = rel_err(res["fp32"]["J"], res["fp64"]["J"])
     return res
 
 
@@ -728,9 +748,9 @@ def main():
               f"{out['batch']['J_rel_err_max']:.2e}", file=sys.stderr, flush=True)
     if not args.no_amr:
         print("[bench] 3-level AMR: FP64 and FP32", file=sys.stderr, flush=True)
-        out["amr"] = amr_compare(max(1, min(args.steps, 3)), 1)
+        out["amr"] = amr_compare(max(1, min(args.steps, 3)), 1, args.max_steps)
         print(f"[bench] amr fp64 {out['amr']['fp64']['value'] / 1e9:.2f}, fp32 "
-              f"{out['amr']['fp32']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['amr']['J_rel_err_fp32']:.2e}",
+              f"{out['amr']['fp32']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['amr']['J_rel_err_fp32']}",
               file=sys.stderr, flush=True)
     if not args.no_flagging:
         print("[bench] adjoint flagging vs undivided-difference flagging, 3-level AMR", file=sys.stderr, flush=True)
@@ -753,9 +773,9 @@ def main():
                   f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
-        out["swe"] = swe_compare(1, 1)
+        out["swe"] = swe_compare(1, 1, max_steps=args.max_steps)
         print(f"[bench] swe fp64 {out['swe']['fp64']['value'] / 1e9:.2f}, mixed "
-              f"{out['swe']['mixed']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['swe']['J_rel_err_mixed']:.2e}",
+              f"{out['swe']['mixed']['value'] / 1e9:.2f} Gcell-updates/s, J rel err {out['swe']['J_rel_err_mixed']}",
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)

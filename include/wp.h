@@ -99,7 +99,8 @@ typedef struct {
  * A(x) = [[0, K], [1/rho, 0]]; Sec. 5.3: bathymetry B, depth h = eta - B).
  * Acoustics media are piecewise constant: at most 16 distinct (rho, K)
  * pairs; a cell of a finer level has the medium of the level-0 cell that
- * contains it.  Shallow water uses a single level. */
+ * contains it.  Shallow-water levels above 0 take their bathymetry from
+ * wp_set_bathymetry (by default that of the containing level-0 cell). */
 typedef struct {
     const double *rho;
     const double *K;
@@ -161,6 +162,16 @@ void wp_destroy(wp_ctx *ctx);
 const char *wp_last_error(const wp_ctx *ctx);
 const char *wp_status_string(int status);
 int wp_set_stream(wp_ctx *ctx, void *stream);
+
+/* Bathymetry cell averages of a refined shallow-water level (host array
+ * [ny_l][nx_l], FP64, copied; every value below 0: no dry cells), in place of
+ * the default in which each cell takes the value of the level-0 cell
+ * containing it.  Cell-integrated values at every level (each coarse value the
+ * mean of its children) keep the hierarchy consistent; any values keep a
+ * lake at rest (eta = 0, no velocity) exactly at rest, since ghost rings,
+ * regrids and averages work on eta = h + B (Sec. 5.3).  WP_EINVAL for level 0
+ * (set by wp_create), a level out of range, acoustics or a value >= 0. */
+int wp_set_bathymetry(wp_ctx *ctx, int level, const double *B);
 
 /* Number of cells and patches of a level; level l canvas size. */
 int wp_level_info(const wp_ctx *ctx, int level, int *nx, int *ny, int *npatches);

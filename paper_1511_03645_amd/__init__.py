@@ -84,6 +84,7 @@ _SIGS = {
     "wp_last_error": (ctypes.c_char_p, [_P]),
     "wp_status_string": (ctypes.c_char_p, [_I]),
     "wp_set_stream": (_I, [_P, _P]),
+    "wp_set_bathymetry": (_I, [_P, _I, ctypes.POINTER(_D)]),
     "wp_level_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "wp_set_state": (_I, [_P, _I, _I, _P, _I]),
     "wp_get_state": (_I, [_P, _I, _I, _P, _I]),
@@ -313,6 +314,11 @@ class WavePatch:
             self.close()
         except Exception:
             pass
+
+    def set_bathymetry(self, level, B):
+        """wp_set_bathymetry: cell averages [ny_l][nx_l] of a refined shallow-water level."""
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        self._check(lib().wp_set_bathymetry(self.h, level, B.ctypes.data_as(ctypes.POINTER(_D))))
 
     def level_info(self, level):
         nx, ny, npch = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -34,32 +34,41 @@ __device__ __forceinline__ T minmod(T a, T b)
     return copysign(fmin(fabs(a), fabs(b)), a);
 }
 
+// Value of plane k of a coarse canvas at (i, j), ghost cells outside the
+// domain by the boundary rule; kc is the state component (1 and 2 are the
+// velocities or momenta, negated across x and y walls).
 template <typename T>
-__device__ __forceinline__ T cval(const T *C, int k, int i, int j, int NX, int NY, const int *bc, long long cs)
+__device__ __forceinline__ T cval(const T *C, int k, int kc, int i, int j, int NX, int NY, const int *bc,
+                                  long long cs)
 {
     bool fi, fj;
     const int ri = resolve1(i, NX, bc[0], bc[1], fi);
     const int rj = resolve1(j, NY, bc[2], bc[3], fj);
     T v = C[k * cs + (long long)rj * NX + ri];
-    if ((fi && k == 1) || (fj && k == 2)) v = -v;
+    if ((fi && kc == 1) || (fj && kc == 2)) v = -v;
     return v;
 }
 
 template <typename T>
-__device__ __forceinline__ T space(const T *C, int k, int ic, int jc, T xi, T eta, int NX, int NY, const int *bc,
-                                   long long cs)
+__device__ __forceinline__ T space(const T *C, int k, int kc, int ic, int jc, T xi, T eta, int NX, int NY,
+                                   const int *bc, long long cs)
 {
     const T c0 = C[k * cs + (long long)jc * NX + ic];
-    const T sx = minmod(cval(C, k, ic + 1, jc, NX, NY, bc, cs) - c0, c0 - cval(C, k, ic - 1, jc, NX, NY, bc, cs));
-    const T sy = minmod(cval(C, k, ic, jc + 1, NX, NY, bc, cs) - c0, c0 - cval(C, k, ic, jc - 1, NX, NY, bc, cs));
+    const T sx = minmod(cval(C, k, kc, ic + 1, jc, NX, NY, bc, cs) - c0,
+                        c0 - cval(C, k, kc, ic - 1, jc, NX, NY, bc, cs));
+    const T sy = minmod(cval(C, k, kc, ic, jc + 1, NX, NY, bc, cs) - c0,
+                        c0 - cval(C, k, kc, ic, jc - 1, NX, NY, bc, cs));
     return (c0 + xi * sx) + eta * sy;
 }
 
+// Components k0 .. k0 + nk - 1 of the state (the canvases point at component
+// k0's plane, planes cs apart): all three in one type, or one launch per
+// type where the state mixes them (shallow water with eta in FP64).
 template <typename T>
 __global__ __launch_bounds__(256) void ring_fill_kernel(const int *__restrict__ cells, long long ncells,
                                                         T *__restrict__ fine, int nxf, const T *__restrict__ cold,
                                                         const T *__restrict__ cnew, int NX, int NY, int r, T alpha,
-                                                        int bc0, int bc1, int bc2, int bc3)
+                                                        int bc0, int bc1, int bc2, int bc3, int k0, int nk)
 {
     const int bc[4] = {bc0, bc1, bc2, bc3};
     const long long csf = (long long)nxf * (NY * r);
@@ -70,9 +79,9 @@ __global__ __launch_bounds__(256) void ring_fill_kernel(const int *__restrict__ 
         const int ic = I / r, jc = J / r;
         const T xi = (T((I % r)) + T(0.5)) / T(r) - T(0.5);
         const T eta = (T((J % r)) + T(0.5)) / T(r) - T(0.5);
-        for (int k = 0; k < 3; ++k) {
-            const T a = space(cold, k, ic, jc, xi, eta, NX, NY, bc, csc);
-            const T b = space(cnew, k, ic, jc, xi, eta, NX, NY, bc, csc);
+        for (int k = 0; k < nk; ++k) {
+            const T a = space(cold, k, k0 + k, ic, jc, xi, eta, NX, NY, bc, csc);
+            const T b = space(cnew, k, k0 + k, ic, jc, xi, eta, NX, NY, bc, csc);
             fine[k * csf + lin] = (T(1) - alpha) * a + alpha * b;
         }
     }
@@ -87,7 +96,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__ blocks, long long nblocks,
                                                          T *__restrict__ fine, int nxf, const T *__restrict__ cold,
                                                          const T *__restrict__ cnew, int NX, int NY, int r, T alpha,
-                                                         int bc0, int bc1, int bc2, int bc3)
+                                                         int bc0, int bc1, int bc2, int bc3, int k0, int nk)
 {
     const int bc[4] = {bc0, bc1, bc2, bc3};
     const long long csf = (long long)nxf * (NY * r);
@@ -98,8 +107,8 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
     // one thread per (component, parent), component-major: neighbouring
     // lanes take neighbouring parents of one component plane, so their
     // children's stores fall close together
-    for (long long w = blockIdx.x * 256LL + threadIdx.x; w < 3 * nblocks; w += (long long)gridDim.x * 256) {
-        const int k = (int)(w / nblocks);
+    for (long long w = blockIdx.x * 256LL + threadIdx.x; w < nk * nblocks; w += (long long)gridDim.x * 256) {
+        const int k = (int)(w / nblocks), kc = k0 + k;
         const long long n = w - (long long)k * nblocks;
         const int lin = blocks[3 * n];
         const unsigned long long mask =
@@ -110,10 +119,10 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
             for (int t = 0; t < 2; ++t) {
                 const T *C = t == 0 ? cold : cnew;
                 c0[t] = C[k * csc + (long long)jc * NX + ic];
-                sx[t] = minmod(cval(C, k, ic + 1, jc, NX, NY, bc, csc) - c0[t],
-                               c0[t] - cval(C, k, ic - 1, jc, NX, NY, bc, csc));
-                sy[t] = minmod(cval(C, k, ic, jc + 1, NX, NY, bc, csc) - c0[t],
-                               c0[t] - cval(C, k, ic, jc - 1, NX, NY, bc, csc));
+                sx[t] = minmod(cval(C, k, kc, ic + 1, jc, NX, NY, bc, csc) - c0[t],
+                               c0[t] - cval(C, k, kc, ic - 1, jc, NX, NY, bc, csc));
+                sy[t] = minmod(cval(C, k, kc, ic, jc + 1, NX, NY, bc, csc) - c0[t],
+                               c0[t] - cval(C, k, kc, ic, jc - 1, NX, NY, bc, csc));
             }
             auto child = [&](int ii, int jj) {
                 // a power-of-two ratio divides exactly as its reciprocal multiplies
@@ -159,13 +168,13 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
 template <typename T>
 __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ cells, long long ncells,
                                                       const T *__restrict__ fine, int nxf, long long csf,
-                                                      T *__restrict__ coarse, int NX, long long csc, int r)
+                                                      T *__restrict__ coarse, int NX, long long csc, int r, int nk)
 {
     const T inv = T(1) / T(r * r);   // exact for the power-of-two ratios
     for (long long n = blockIdx.x * 256LL + threadIdx.x; n < ncells; n += (long long)gridDim.x * 256) {
         const int lin = cells[n];
         const int ic = lin % NX, jc = lin / NX;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < nk; ++k) {
             T s = T(0);
             if (r == 4) {
                 // each row of four children in one aligned vector load, summed
@@ -197,42 +206,42 @@ unsigned grid_for(long long n)
 
 template <typename T>
 void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, const T *cold, const T *cnew, int NX,
-                      int NY, int r, double alpha, const int *bc, hipStream_t s)
+                      int NY, int r, double alpha, const int *bc, hipStream_t s, int k0, int nk)
 {
     if (ncells <= 0) return;
     hipLaunchKernelGGL((ring_fill_kernel<T>), dim3(grid_for(ncells)), dim3(256), 0, s, cells, ncells, fine, nxf, cold,
-                       cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3]);
+                       cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3], k0, nk);
 }
 
 template <typename T>
 void launch_ring_fill_blocks(const int *blocks, long long nblocks, T *fine, int nxf, const T *cold, const T *cnew,
-                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s)
+                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s, int k0, int nk)
 {
     if (nblocks <= 0) return;
-    hipLaunchKernelGGL((ring_block_kernel<T>), dim3(grid_for(3 * nblocks)), dim3(256), 0, s, blocks, nblocks, fine, nxf,
-                       cold, cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3]);
+    hipLaunchKernelGGL((ring_block_kernel<T>), dim3(grid_for(nk * nblocks)), dim3(256), 0, s, blocks, nblocks, fine,
+                       nxf, cold, cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3], k0, nk);
 }
 
 template <typename T>
 void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
-                    long long csc, int r, hipStream_t s)
+                    long long csc, int r, hipStream_t s, int nk)
 {
     if (ncells <= 0) return;
     hipLaunchKernelGGL((average_kernel<T>), dim3(grid_for(ncells)), dim3(256), 0, s, cells, ncells, fine, nxf, csf,
-                       coarse, NX, csc, r);
+                       coarse, NX, csc, r, nk);
 }
 
 template void launch_ring_fill<double>(const int *, long long, double *, int, const double *, const double *, int,
-                                       int, int, double, const int *, hipStream_t);
+                                       int, int, double, const int *, hipStream_t, int, int);
 template void launch_ring_fill<float>(const int *, long long, float *, int, const float *, const float *, int, int,
-                                      int, double, const int *, hipStream_t);
+                                      int, double, const int *, hipStream_t, int, int);
 template void launch_ring_fill_blocks<double>(const int *, long long, double *, int, const double *, const double *,
-                                              int, int, int, double, const int *, hipStream_t);
+                                              int, int, int, double, const int *, hipStream_t, int, int);
 template void launch_ring_fill_blocks<float>(const int *, long long, float *, int, const float *, const float *, int,
-                                             int, int, double, const int *, hipStream_t);
+                                             int, int, double, const int *, hipStream_t, int, int);
 template void launch_average<double>(const int *, long long, const double *, int, long long, double *, int,
-                                     long long, int, hipStream_t);
+                                     long long, int, hipStream_t, int);
 template void launch_average<float>(const int *, long long, const float *, int, long long, float *, int, long long,
-                                    int, hipStream_t);
+                                    int, hipStream_t, int);
 
 }  // namespace wp

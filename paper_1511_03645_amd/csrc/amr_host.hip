@@ -105,12 +105,24 @@ int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n,
 
 // Fine cells `cells` of level l from level l-1 at time weight alpha between
 // the canvas before its last step (cold) and its current one (cnew).
+// Byte offset of the float planes (hu, hv) of a mixed-precision canvas of
+// `cells` cells: they follow the FP64 eta plane.
+inline size_t mixed_tail(const Level &lv) { return (size_t)lv.nx * lv.ny * sizeof(double); }
+
 int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double alpha, bool use_old, hipStream_t s)
 {
     Level &F = ctx->L[l], &C = ctx->L[l - 1];
     const void *cnew = C.q[C.cur];
     const void *cold = use_old ? C.q[C.cur ^ 1] : cnew;
-    if (ctx->esz == 8)
+    if (ctx->prob.precision == WP_MIXED) {
+        // eta in FP64, then hu and hv in FP32
+        launch_ring_fill<double>(cells, n, (double *)F.q[F.cur], F.nx, (const double *)cold, (const double *)cnew,
+                                 C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s, 0, 1);
+        launch_ring_fill<float>(cells, n, (float *)((char *)F.q[F.cur] + mixed_tail(F)), F.nx,
+                                (const float *)((const char *)cold + mixed_tail(C)),
+                                (const float *)((const char *)cnew + mixed_tail(C)), C.nx, C.ny, F.ratio, alpha,
+                                ctx->prob.bc, s, 1, 2);
+    } else if (ctx->esz == 8)
         launch_ring_fill<double>(cells, n, (double *)F.q[F.cur], F.nx, (const double *)cold, (const double *)cnew,
                                  C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
     else
@@ -129,7 +141,14 @@ int fill_ring(wp_ctx *ctx, int l, double alpha, hipStream_t s)
     // by coarse parent: each parent's slopes formed once for all its ring children
     const void *cnew = C.q[C.cur];
     const void *cold = C.prev_valid ? C.q[C.cur ^ 1] : cnew;
-    if (ctx->esz == 8)
+    if (ctx->prob.precision == WP_MIXED) {
+        launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)F.q[F.cur], F.nx, (const double *)cold,
+                                        (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s, 0, 1);
+        launch_ring_fill_blocks<float>(F.ringb_dev, F.nringb, (float *)((char *)F.q[F.cur] + mixed_tail(F)), F.nx,
+                                       (const float *)((const char *)cold + mixed_tail(C)),
+                                       (const float *)((const char *)cnew + mixed_tail(C)), C.nx, C.ny, F.ratio,
+                                       alpha, ctx->prob.bc, s, 1, 2);
+    } else if (ctx->esz == 8)
         launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)F.q[F.cur], F.nx, (const double *)cold,
                                         (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
     else
@@ -145,7 +164,12 @@ int average_down(wp_ctx *ctx, int l, hipStream_t s)
     Level &F = ctx->L[l], &C = ctx->L[l - 1];
     if (F.ncover == 0) return WP_OK;
     const long long csf = (long long)F.nx * F.ny, csc = (long long)C.nx * C.ny;
-    if (ctx->esz == 8)
+    if (ctx->prob.precision == WP_MIXED) {
+        launch_average<double>(F.cover_dev, F.ncover, (const double *)F.q[F.cur], F.nx, csf, (double *)C.q[C.cur],
+                               C.nx, csc, F.ratio, s, 1);
+        launch_average<float>(F.cover_dev, F.ncover, (const float *)((const char *)F.q[F.cur] + mixed_tail(F)), F.nx,
+                              csf, (float *)((char *)C.q[C.cur] + mixed_tail(C)), C.nx, csc, F.ratio, s, 2);
+    } else if (ctx->esz == 8)
         launch_average<double>(F.cover_dev, F.ncover, (const double *)F.q[F.cur], F.nx, csf, (double *)C.q[C.cur],
                                C.nx, csc, F.ratio, s);
     else

@@ -96,8 +96,9 @@ __global__ __launch_bounds__(256) void flag_kernel(const TQ *__restrict__ q, lon
 __global__ __launch_bounds__(256) void flag_mixed_kernel(const double *__restrict__ eta, const float *__restrict__ hu,
                                                          const float *__restrict__ hv, int nx,
                                                          const float *__restrict__ snaps, long long sstride,
-                                                         long long hcs, int n_lo, int n_hi, double tol,
-                                                         const Tile *__restrict__ tiles, uint8_t *__restrict__ flags,
+                                                         long long hcs, int NX, int NY, int ratio, int n_lo, int n_hi,
+                                                         double tol, const Tile *__restrict__ tiles,
+                                                         uint8_t *__restrict__ flags,
                                                          unsigned long long *__restrict__ count)
 {
     const Tile tl = tiles[blockIdx.x];
@@ -107,12 +108,16 @@ __global__ __launch_bounds__(256) void flag_mixed_kernel(const double *__restric
         const int i = tl.i0 + k % tl.ni, j = tl.j0 + k / tl.ni;
         const long long idx = (long long)j * nx + i;
         const double a = eta[idx], b = hu[idx], c = hv[idx];
+        int i0 = i, j0 = j;
+        double wx = 0.0, wy = 0.0;
+        bracket(i, ratio, NX, i0, wx);
+        bracket(j, ratio, NY, j0, wy);
         double best = 0.0;
         for (int n = n_lo; n <= n_hi; ++n) {
             const float *sn = snaps + (long long)n * sstride;
-            double ip = (double)sn[idx] * a;
-            ip = ip + (double)sn[idx + hcs] * b;
-            ip = ip + (double)sn[idx + 2 * hcs] * c;
+            double ip = interp(sn, NX, NY, ratio, i0, wx, j0, wy) * a;
+            ip = ip + interp(sn + hcs, NX, NY, ratio, i0, wx, j0, wy) * b;
+            ip = ip + interp(sn + 2 * hcs, NX, NY, ratio, i0, wx, j0, wy) * c;
             best = fmax(best, fabs(ip));
         }
         const uint8_t f = best > tol ? 1 : 0;
@@ -419,14 +424,15 @@ void launch_flag(const TQ *q, long long cs, int nx, int ny, int m, const TH *sna
 }
 
 void launch_flag_mixed(const double *eta, const float *hu, const float *hv, long long cs, int nx, int ny,
-                       const float *snaps, long long snap_stride, long long hcs, int n_lo, int n_hi, double tol,
-                       const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s)
+                       const float *snaps, long long snap_stride, long long hcs, int NX, int NY, int ratio, int n_lo,
+                       int n_hi, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
+                       unsigned long long *count, hipStream_t s)
 {
     (void)cs;
     (void)ny;
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(flag_mixed_kernel, dim3(ntiles), dim3(256), 0, s, eta, hu, hv, nx, snaps, snap_stride, hcs,
-                       n_lo, n_hi, tol, tiles, flags, count);
+    hipLaunchKernelGGL(flag_mixed_kernel, dim3(ntiles), dim3(256), 0, s, eta, hu, hv, nx, snaps, snap_stride, hcs, NX,
+                       NY, ratio, n_lo, n_hi, tol, tiles, flags, count);
 }
 
 template <typename TA>

@@ -35,7 +35,36 @@ int wp_swe_init(wp_ctx *ctx, const wp_coefficients *coef)
         e = hipMemcpy(ctx->cbar, cf.data(), cells * 4, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "wave speed upload");
+    ctx->L[0].B = (double *)ctx->Bdev;
+    // finer levels: each cell takes the value of the level-0 cell containing
+    // it until wp_set_bathymetry gives the level's own cell averages
+    for (size_t l = 1; l < ctx->L.size(); ++l) {
+        Level &lv = ctx->L[l];
+        const int r = lv.nx / l0.nx;
+        std::vector<double> Bl((size_t)lv.nx * lv.ny);
+        for (int j = 0; j < lv.ny; ++j)
+            for (int i = 0; i < lv.nx; ++i) Bl[(size_t)j * lv.nx + i] = coef->B[(size_t)(j / r) * l0.nx + i / r];
+        lv.B = (double *)wp_dalloc(ctx, Bl.size() * sizeof(double));
+        if (!lv.B) return wp_fail(ctx, WP_ENOMEM, "bathymetry of level %zu", l);
+        int rc;
+        if ((rc = wp_host_copy(ctx, lv.B, Bl.data(), Bl.size() * sizeof(double), true)) != WP_OK) return rc;
+    }
     return WP_OK;
+}
+
+extern "C" int wp_set_bathymetry(wp_ctx *ctx, int level, const double *B)
+{
+    if (!ctx) return WP_EINVAL;
+    if (ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "bathymetry is for shallow water");
+    if (level < 1 || level >= (int)ctx->L.size())
+        return wp_fail(ctx, WP_EINVAL, "level %d: refined levels 1..%d only", level, (int)ctx->L.size() - 1);
+    if (!B) return wp_fail(ctx, WP_EINVAL, "null bathymetry");
+    Level &lv = ctx->L[level];
+    const size_t cells = (size_t)lv.nx * lv.ny;
+    for (size_t k = 0; k < cells; ++k)
+        if (!std::isfinite(B[k]) || !(B[k] < 0.0))
+            return wp_fail(ctx, WP_EINVAL, "bathymetry must be below sea level everywhere (no dry cells), cell %zu", k);
+    return wp_host_copy(ctx, lv.B, B, cells * sizeof(double), true);
 }
 
 int wp_swe_adj_init(wp_ctx *ctx)
@@ -56,7 +85,7 @@ static int prep_fwd(wp_ctx *ctx, Level &lv, double dt)
         I.hu[b] = (T *)(base + cells * sizeof(ETA));
         I.hv[b] = (T *)(base + cells * (sizeof(ETA) + sizeof(T)));
     }
-    I.B = (const double *)ctx->Bdev;
+    I.B = lv.B;
     I.nx = lv.nx;
     I.ny = lv.ny;
     for (int k = 0; k < 4; ++k) I.bc[k] = ctx->prob.bc[k];

@@ -64,6 +64,7 @@ struct Level {
     double *freg_dev = nullptr;
     int nfaces = 0, nfgroups = 0;
     size_t faces_cap = 0, fgroups_cap = 0, freg_cap = 0;
+    double *B = nullptr;                 // shallow water: bathymetry cell averages of this level (FP64)
     // false after a tile-table rebuild failed (its tables are empty): steps
     // and flags of the level fail with WP_ESTATE until a rebuild succeeds
     bool tables_ok = true;

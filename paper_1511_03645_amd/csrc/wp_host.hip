@@ -469,8 +469,8 @@ extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef,
     if (G.nx0 < 4 || (ctx->kind2d && G.ny0 < 4)) return bail(wp_fail(ctx, WP_EINVAL, "grid must be at least 4 cells per side"));
     if (!(G.xhi > G.xlo) || (ctx->kind2d && !(G.yhi > G.ylo))) return bail(wp_fail(ctx, WP_EINVAL, "empty domain"));
     if (G.num_levels < 1 || G.num_levels > WP_MAX_LEVELS) return bail(wp_fail(ctx, WP_EINVAL, "num_levels out of range"));
-    if (G.num_levels > 1 && P.kind != WP_ACOUSTICS_2D)
-        return bail(wp_fail(ctx, WP_EINVAL, "refinement levels are supported for 2D acoustics"));
+    if (G.num_levels > 1 && P.kind == WP_ACOUSTICS_1D)
+        return bail(wp_fail(ctx, WP_EINVAL, "refinement levels are supported in 2D"));
     long long cells_l = (long long)G.nx0 * (ctx->kind2d ? G.ny0 : 1);
     for (int l = 0; l + 1 < G.num_levels; ++l) {
         if (G.ratio[l] < 2 || G.ratio[l] > 8 || (G.ratio[l] & (G.ratio[l] - 1)))
@@ -1387,8 +1387,8 @@ static int flag_launch(wp_ctx *ctx, int level, double tol, int n_lo, int n_hi, u
     if (ctx->prob.precision == WP_MIXED) {
         launch_flag_mixed((const double *)lv.q[lv.cur], (const float *)((char *)lv.q[lv.cur] + cells * 8),
                           (const float *)((char *)lv.q[lv.cur] + cells * 12), cells, lv.nx, lv.ny,
-                          (const float *)ctx->snaps, sstride, hcs, n_lo, n_hi, tol, lv.ftiles_dev, lv.nftiles,
-                          lv.flags, count, s);
+                          (const float *)ctx->snaps, sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol,
+                          lv.ftiles_dev, lv.nftiles, lv.flags, count, s);
     } else if (ctx->esz == 8) {
         launch_flag<double, double>((const double *)lv.q[lv.cur], cells, lv.nx, lv.ny, ctx->m,
                                     (const double *)ctx->snaps, sstride, hcs, a0.nx, a0.ny, ratio, n_lo, n_hi, tol,

@@ -150,8 +150,9 @@ void launch_flag(const TQ *q, long long cs, int nx, int ny, int m, const TH *sna
                  long long hcs, int NX, int NY, int ratio, int n_lo, int n_hi, double tol, const Tile *tiles,
                  int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
 void launch_flag_mixed(const double *eta, const float *hu, const float *hv, long long cs, int nx, int ny,
-                       const float *snaps, long long snap_stride, long long hcs, int n_lo, int n_hi, double tol,
-                       const Tile *tiles, int ntiles, uint8_t *flags, unsigned long long *count, hipStream_t s);
+                       const float *snaps, long long snap_stride, long long hcs, int NX, int NY, int ratio, int n_lo,
+                       int n_hi, double tol, const Tile *tiles, int ntiles, uint8_t *flags,
+                       unsigned long long *count, hipStream_t s);
 
 // Comparison flags: the undivided difference of every component to its four
 // face neighbours (boundary rule across the domain edge, bc[4]), and the
@@ -193,18 +194,20 @@ void launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s);
 // Refinement transfers: fill fine cells (linear indices into the fine canvas)
 // from the coarse level at two times (time weight alpha), and average fine
 // children onto covered coarse cells (linear coarse indices).
+// k0, nk: the components filled (the pointers address component k0's plane).
 template <typename T>
 void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, const T *cold, const T *cnew, int NX,
-                      int NY, int r, double alpha, const int *bc, hipStream_t s);
+                      int NY, int r, double alpha, const int *bc, hipStream_t s, int k0 = 0, int nk = 3);
 // The ring fill by coarse parent: blocks[3e] the parent's linear index,
 // blocks[3e + 1], blocks[3e + 2] the low and high words of the mask of its
 // ring children (child (ii, jj) at bit ii + r jj; r <= 8).
 template <typename T>
 void launch_ring_fill_blocks(const int *blocks, long long nblocks, T *fine, int nxf, const T *cold, const T *cnew,
-                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s);
+                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s, int k0 = 0,
+                             int nk = 3);
 template <typename T>
 void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
-                    long long csc, int r, hipStream_t s);
+                    long long csc, int r, hipStream_t s, int nk = 3);
 
 // Refluxing of the adjoint hierarchy (conservative f-wave form): add the
 // fluxes of the fine edges of every face (r per face, from the canvas the
