@@ -91,12 +91,15 @@ __global__ __launch_bounds__(256) void ring_fill_kernel(const int *__restrict__ 
 // coarse cell, 64-bit mask of its r x r children in the ring, child (ii, jj)
 // at bit ii + r jj).  The parent's slopes at both times are formed once and
 // every ring child is written from them, with the arithmetic of
-// ring_fill_kernel.
+// ring_fill_kernel.  fine2 (optional): a second canvas that takes the ring at
+// time weight alpha2 from the same slopes (the ring of the next substep, whose
+// input canvas the current substep writes only inside the patches).
 template <typename T>
 __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__ blocks, long long nblocks,
                                                          T *__restrict__ fine, int nxf, const T *__restrict__ cold,
                                                          const T *__restrict__ cnew, int NX, int NY, int r, T alpha,
-                                                         int bc0, int bc1, int bc2, int bc3, int k0, int nk)
+                                                         int bc0, int bc1, int bc2, int bc3, int k0, int nk,
+                                                         T *__restrict__ fine2, T alpha2)
 {
     const int bc[4] = {bc0, bc1, bc2, bc3};
     const long long csf = (long long)nxf * (NY * r);
@@ -124,13 +127,16 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
                 sy[t] = minmod(cval(C, k, kc, ic, jc + 1, NX, NY, bc, csc) - c0[t],
                                c0[t] - cval(C, k, kc, ic, jc - 1, NX, NY, bc, csc));
             }
+          for (int o = 0; o < (fine2 ? 2 : 1); ++o) {
+            T *__restrict__ out = o ? fine2 : fine;
+            const T al = o ? alpha2 : alpha;
             auto child = [&](int ii, int jj) {
                 // a power-of-two ratio divides exactly as its reciprocal multiplies
                 const T xi = (pow2 ? (T(ii) + T(0.5)) * inv_r : (T(ii) + T(0.5)) / T(r)) - T(0.5);
                 const T eta = (pow2 ? (T(jj) + T(0.5)) * inv_r : (T(jj) + T(0.5)) / T(r)) - T(0.5);
                 const T a = (c0[0] + xi * sx[0]) + eta * sy[0];
                 const T v = (c0[1] + xi * sx[1]) + eta * sy[1];
-                return (T(1) - alpha) * a + alpha * v;
+                return (T(1) - al) * a + al * v;
             };
             if (r == 4) {
                 // a full row of four children (along a patch's lower or upper
@@ -140,7 +146,7 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
                 for (int jj = 0; jj < 4; ++jj) {
                     const unsigned rm = (unsigned)(mask >> (4 * jj)) & 0xfu;
                     if (!rm) continue;
-                    T *dst = fine + k * csf + (long long)(jc * 4 + jj) * nxf + (long long)ic * 4;
+                    T *dst = out + k * csf + (long long)(jc * 4 + jj) * nxf + (long long)ic * 4;
                     if (rm == 0xfu) {
                         typedef T T4 __attribute__((ext_vector_type(4)));
                         T4 q;
@@ -158,9 +164,10 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
                 for (unsigned long long m = mask; m; m &= m - 1) {
                     const int b = __builtin_ctzll(m);
                     const int ii = pow2 ? (b & (r - 1)) : b % r, jj = pow2 ? (b >> lr) : b / r;
-                    fine[k * csf + (long long)(jc * r + jj) * nxf + (ic * r + ii)] = child(ii, jj);
+                    out[k * csf + (long long)(jc * r + jj) * nxf + (ic * r + ii)] = child(ii, jj);
                 }
             }
+          }
         }
     }
 }
@@ -215,11 +222,12 @@ void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, cons
 
 template <typename T>
 void launch_ring_fill_blocks(const int *blocks, long long nblocks, T *fine, int nxf, const T *cold, const T *cnew,
-                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s, int k0, int nk)
+                             int NX, int NY, int r, double alpha, const int *bc, hipStream_t s, int k0, int nk,
+                             T *fine2, double alpha2)
 {
     if (nblocks <= 0) return;
     hipLaunchKernelGGL((ring_block_kernel<T>), dim3(grid_for(nk * nblocks)), dim3(256), 0, s, blocks, nblocks, fine,
-                       nxf, cold, cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3], k0, nk);
+                       nxf, cold, cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3], k0, nk, fine2, (T)alpha2);
 }
 
 template <typename T>
@@ -236,9 +244,10 @@ template void launch_ring_fill<double>(const int *, long long, double *, int, co
 template void launch_ring_fill<float>(const int *, long long, float *, int, const float *, const float *, int, int,
                                       int, double, const int *, hipStream_t, int, int);
 template void launch_ring_fill_blocks<double>(const int *, long long, double *, int, const double *, const double *,
-                                              int, int, int, double, const int *, hipStream_t, int, int);
+                                              int, int, int, double, const int *, hipStream_t, int, int, double *,
+                                              double);
 template void launch_ring_fill_blocks<float>(const int *, long long, float *, int, const float *, const float *, int,
-                                             int, int, double, const int *, hipStream_t, int, int);
+                                             int, int, double, const int *, hipStream_t, int, int, float *, double);
 template void launch_average<double>(const int *, long long, const double *, int, long long, double *, int,
                                      long long, int, hipStream_t, int);
 template void launch_average<float>(const int *, long long, const float *, int, long long, float *, int, long long,

@@ -133,27 +133,43 @@ int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double a
     return WP_OK;
 }
 
-int fill_ring(wp_ctx *ctx, int l, double alpha, hipStream_t s)
+// The ring of level l at time weight alpha in its current canvas; with
+// `next`, also the ring at alpha2 in its other canvas (that of the next
+// substep, which the current one writes only inside the patches).
+int fill_ring(wp_ctx *ctx, int l, double alpha, hipStream_t s, bool next = false, double alpha2 = 0.0)
 {
     Level &F = ctx->L[l], &C = ctx->L[l - 1];
     if (F.nring == 0) return WP_OK;
-    if (F.nringb == 0) return fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, C.prev_valid, s);
+    if (F.nringb == 0) {
+        int rc = fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha, C.prev_valid, s);
+        if (rc == WP_OK && next) {
+            F.cur ^= 1;
+            rc = fill_from_coarse(ctx, l, F.ring_dev, F.nring, alpha2, C.prev_valid, s);
+            F.cur ^= 1;
+        }
+        return rc;
+    }
     // by coarse parent: each parent's slopes formed once for all its ring children
     const void *cnew = C.q[C.cur];
     const void *cold = C.prev_valid ? C.q[C.cur ^ 1] : cnew;
+    char *f1 = (char *)F.q[F.cur], *f2 = next ? (char *)F.q[F.cur ^ 1] : nullptr;
     if (ctx->prob.precision == WP_MIXED) {
-        launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)F.q[F.cur], F.nx, (const double *)cold,
-                                        (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s, 0, 1);
-        launch_ring_fill_blocks<float>(F.ringb_dev, F.nringb, (float *)((char *)F.q[F.cur] + mixed_tail(F)), F.nx,
+        launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)f1, F.nx, (const double *)cold,
+                                        (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s, 0, 1,
+                                        (double *)f2, alpha2);
+        launch_ring_fill_blocks<float>(F.ringb_dev, F.nringb, (float *)(f1 + mixed_tail(F)), F.nx,
                                        (const float *)((const char *)cold + mixed_tail(C)),
                                        (const float *)((const char *)cnew + mixed_tail(C)), C.nx, C.ny, F.ratio,
-                                       alpha, ctx->prob.bc, s, 1, 2);
+                                       alpha, ctx->prob.bc, s, 1, 2, f2 ? (float *)(f2 + mixed_tail(F)) : nullptr,
+                                       alpha2);
     } else if (ctx->esz == 8)
-        launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)F.q[F.cur], F.nx, (const double *)cold,
-                                        (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
+        launch_ring_fill_blocks<double>(F.ringb_dev, F.nringb, (double *)f1, F.nx, (const double *)cold,
+                                        (const double *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s, 0, 3,
+                                        (double *)f2, alpha2);
     else
-        launch_ring_fill_blocks<float>(F.ringb_dev, F.nringb, (float *)F.q[F.cur], F.nx, (const float *)cold,
-                                       (const float *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s);
+        launch_ring_fill_blocks<float>(F.ringb_dev, F.nringb, (float *)f1, F.nx, (const float *)cold,
+                                       (const float *)cnew, C.nx, C.ny, F.ratio, alpha, ctx->prob.bc, s, 0, 3,
+                                       (float *)f2, alpha2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return wp_fail(ctx, WP_EDEVICE, "coarse-to-fine launch: %s", hipGetErrorString(e));
     return WP_OK;
@@ -295,8 +311,13 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
     // below (which does not step meanwhile), and the average of the finer
     // level touches no ring cell (proper nesting)
     const bool has_children = l + 1 < (int)ctx->L.size() && !ctx->L[l + 1].patches.empty();
-    if (launch && l > 0 && !(sub > 0 && has_children) &&
-        (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio, s)) != WP_OK)
+    // a level without children takes the rings of two substeps in one fill:
+    // an even substep's fill also writes the next substep's ring into the
+    // other canvas, which this substep's step writes only inside the patches
+    const bool paired = !has_children && lv.ratio % 2 == 0;
+    if (launch && l > 0 && !(sub > 0 && has_children) && !(paired && sub % 2 == 1) &&
+        (rc = fill_ring(ctx, l, (double)sub / (double)lv.ratio, s, paired,
+                        (double)(sub + 1) / (double)lv.ratio)) != WP_OK)
         return rc;
     if (launch) {
         if ((rc = wp_step_level(ctx, lv, dt, ctx->equation, s, -1)) != WP_OK) return rc;

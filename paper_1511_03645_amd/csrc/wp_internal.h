@@ -201,10 +201,12 @@ void launch_ring_fill(const int *cells, long long ncells, T *fine, int nxf, cons
 // The ring fill by coarse parent: blocks[3e] the parent's linear index,
 // blocks[3e + 1], blocks[3e + 2] the low and high words of the mask of its
 // ring children (child (ii, jj) at bit ii + r jj; r <= 8).
+// fine2 (optional): a second canvas filled at time weight alpha2 from the
+// same slopes.
 template <typename T>
 void launch_ring_fill_blocks(const int *blocks, long long nblocks, T *fine, int nxf, const T *cold, const T *cnew,
                              int NX, int NY, int r, double alpha, const int *bc, hipStream_t s, int k0 = 0,
-                             int nk = 3);
+                             int nk = 3, T *fine2 = nullptr, double alpha2 = 0.0);
 template <typename T>
 void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
                     long long csc, int r, hipStream_t s, int nk = 3);
