@@ -401,6 +401,7 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
         w = wp.from_config(cfg, num_levels=3, ratios=tuple(ratios))
         w.set_state(cfg["q0"])
         torch.cuda.synchronize()
+        w.host_times(reset=True)
         t0 = time.perf_counter()
         if mode in ("adjoint", "richardson_adjoint"):
             w.adjoint_run(F, dt, N, every)
@@ -428,9 +429,15 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         cyc = N // regrid_every
+        ht = w.host_times()
         del w
+        # host time per regrid cycle (two regrids and two coarse steps): the
+        # flag copies include waiting for the steps queued before them
+        per_cycle = {k: round(ht[k] / cyc, 4) for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms")}
         return {"seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref), "cell_updates": ups,
-                "mean_cells_level1": fine_cells[0] / cyc, "mean_cells_level2": fine_cells[1] / cyc}, g
+                "mean_cells_level1": fine_cells[0] / cyc, "mean_cells_level2": fine_cells[1] / cyc,
+                "per_cycle_host_ms": per_cycle, "captures": int(ht["captures"]),
+                "graph_updates": int(ht["graph_updates"])}, g
 
     runs = []
     for mode, tol in (("adjoint", 1e-3), ("richardson_adjoint", 1e-5), ("richardson_adjoint", 1e-6),
@@ -449,6 +456,117 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
             "gauge": {"cell": [gi, gj], "samples": len(ga),
                       "max_abs_diff_rel": float(np.abs(ga - gd).max() / max(np.abs(gd).max(), 1e-300)),
                       "between": "adjoint tol 1e-3 and difference tol 0.002, level-0 p every regrid"}}
+
+
+def swe_flagging_compare(n0=256, ratios=(4, 2), regrid_every=2, buffer=2):
+    """The shallow-water analogue of the paper's tsunami comparison (Sec. 5.3,
+    Table 2): the synthetic 2048 km ocean on a coarse n0^2 grid with two
+    refinement levels (ratios 4, 2: 1 km cells on the finest, the resolution
+    of the uniform workload), levels 0 and 1 flagged every `regrid_every`
+    coarse steps and the level above rebuilt from the flags, either by the
+    adjoint of the coastal gauge box (its solve included in the time) or by
+    surface flagging, |eta| above a tolerance.  Accuracy: J (eta over the
+    gauge box at T, on the coarse grid) and the sea surface at a point gauge
+    in the box every coarse step, against a uniform run on the finest grid
+    (FP64, the same problem)."""
+    import torch
+    import paper_1511_03645_amd as wp
+    from wp_synth import swe2d, swe2d_amr
+    cfg = swe2d_amr(n0=n0, ratios=ratios)
+    N, every, dt, F = cfg["nsteps"], cfg["snap_every"], cfg["dt"], cfg["functional"]
+    R = ratios[0] * ratios[1]
+    nf = n0 * R
+    ref = swe2d(n=nf, seed=3)
+    assert np.array_equal(ref["B"], cfg["B_levels"][-1])
+    ref = dict(ref, dt=dt / R, nsteps=N * R)
+    gx, gy = cfg["gauge"]
+    # point gauge: the finest-grid cell that holds the gauge
+    gi, gj = int(gx // (cfg["dx"] / R)), int(gy // (cfg["dy"] / R))
+    wf = wp.from_config(ref)
+    wf.set_state(ref["q0"])
+    cell = dict(kind="box", component=0, x0=(gi + 0.25) * 1000.0, x1=(gi + 0.75) * 1000.0,
+                y0=(gj + 0.25) * 1000.0, y1=(gj + 0.75) * 1000.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g_ref = [wf.functional_value(cell, 0) / 1e6]
+    for _ in range(N):
+        wf.run_graph(R, dt / R, 1)
+        g_ref.append(wf.functional_value(cell, 0) / 1e6)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    qf = wf.get_state()
+    del wf
+    wc = wp.from_config(cfg)
+    wc.set_state(qf.reshape(3, n0, R, n0, R).mean(axis=(2, 4)))
+    J_ref = wc.functional_value(F, 0)
+    del wc, qf
+    g_ref = np.array(g_ref)
+
+    def gauge(w):
+        """eta at the gauge from the finest level whose patch holds it."""
+        for l in (2, 1):
+            rr = R if l == 2 else ratios[0]
+            i, j = gi // (R // rr), gj // (R // rr)
+            for k, (i0, j0, nx, ny) in enumerate(w.get_patches(l)):
+                if i0 <= i < i0 + nx and j0 <= j < j0 + ny:
+                    return float(w.get_state(level=l, patch=k)[0, j - j0, i - i0])
+        return float(w.get_state(0)[0, gj // R, gi // R])
+
+    def run(mode, tol, record=False):
+        w = wp.from_config(cfg, num_levels=3, ratios=tuple(ratios))
+        for l, B in enumerate(cfg["B_levels"]):
+            w.set_bathymetry(l + 1, B)
+        w.set_state(cfg["q0"])
+        torch.cuda.synchronize()
+        w.host_times(reset=True)
+        t0 = time.perf_counter()
+        if mode == "adjoint":
+            w.adjoint_run(F, dt, N, every)
+        t, cells, g = 0.0, [0, 0], [gauge(w)] if record else []
+        for _ in range(N // regrid_every):
+            for l in (0, 1):
+                if mode == "adjoint":
+                    w.flag_adjoint(l, tol, t, cfg["t_s"], cfg["t_f"], want_flags=False, want_count=False)
+                else:
+                    w.flag_surface(l, tol, want_flags=False, want_count=False)
+                w.regrid(l, None, buffer=buffer)
+            cells[0] += sum(p[2] * p[3] for p in w.get_patches(1))
+            cells[1] += sum(p[2] * p[3] for p in w.get_patches(2))
+            w.advance(regrid_every, dt)
+            if record:
+                g.append(gauge(w))
+            t += regrid_every * dt
+        J = w.functional_value(F, 0)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        cyc = N // regrid_every
+        ht = w.host_times()
+        del w
+        res = {"flag": mode, "tol": tol, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
+               "mean_cells_level1": cells[0] / cyc, "mean_cells_level2": cells[1] / cyc,
+               "per_cycle_host_ms": {k: round(ht[k] / cyc, 4)
+                                     for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms")},
+               "captures": int(ht["captures"]), "graph_updates": int(ht["graph_updates"])}
+        if record:
+            # the gauge every regrid cycle against the reference at the same times
+            g = np.array(g)
+            gr = g_ref[::regrid_every][:len(g)]
+            res = {"gauge_max_err_rel": float(np.abs(g - gr).max() / np.abs(gr).max())}
+        return res
+
+    runs = []
+    for mode, tol in (("adjoint", 1e-3), ("adjoint", 1e-4), ("surface", 0.05), ("surface", 0.02)):
+        run(mode, tol)                      # warm-up
+        res = run(mode, tol)
+        res.update(run(mode, tol, record=True))   # the gauge, in a run of its own (host reads)
+        runs.append(res)
+    return {"workload": f"swe2d 2048 km ocean, coarse {n0}^2, ratios {ratios[0]},{ratios[1]} (finest 1 km), "
+                        f"{N} coarse steps to {cfg['t_f']:.0f} s, flag + regrid of levels 0 and 1 every "
+                        f"{regrid_every} coarse steps, buffer {buffer}, FP64",
+            "J_reference": J_ref, "reference": f"uniform {nf}^2 FP64, {N * R} steps, {t_ref:.3f} s (gauge reads "
+                                               f"included)",
+            "gauge": {"cell_finest": [gi, gj], "samples": len(g_ref), "ref_max_abs_eta": float(np.abs(g_ref).max())},
+            "runs": runs}
 
 
 def richardson_compare(n0=256, ratio=4, regrid_every=2, buffer=3):
@@ -771,6 +889,13 @@ def main():
         for r in ar["forward_flagged_with"]:
             print(f"[bench]   forward flagged with the {r['snapshots']}: J rel err {r['J_rel_err']:.2e}, "
                   f"level-1 cells {r['mean_cells_level1']:.0f}", file=sys.stderr, flush=True)
+    if not args.no_swe and not args.no_flagging:
+        print("[bench] shallow water with refinement: adjoint vs surface flagging", file=sys.stderr, flush=True)
+        out["swe_flagging"] = swe_flagging_compare()
+        for r in out["swe_flagging"]["runs"]:
+            print(f"[bench]   {r['flag']:8s} tol {r['tol']:g}: {r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
+                  f"gauge err {r['gauge_max_err_rel']:.2e}, level-2 cells {r['mean_cells_level2']:.0f}, "
+                  f"captures {r['captures']} ({r['graph_updates']} in place)", file=sys.stderr, flush=True)
     if not args.no_swe:
         print("[bench] shallow water 2048^2: FP64 vs mixed", file=sys.stderr, flush=True)
         out["swe"] = swe_compare(1, 1, max_steps=args.max_steps)

@@ -407,6 +407,17 @@ int wp_inner_product_noalloc(const void *a, const void *b, int precision, long l
 int wp_get_time(const wp_ctx *ctx, int level, double *t);
 int wp_set_time(wp_ctx *ctx, int level, double t);
 
+/* Host time the handle has spent, in milliseconds, cumulative since
+ * creation or the last reset: ms[0] copying a level's flags to the host for a
+ * regrid (including the wait for the work before them), ms[1] clustering and
+ * nesting, ms[2] rebuilding and uploading the tables of the new patches,
+ * ms[3] capturing launch sequences (and instantiating or updating their
+ * graphs); ms[4] the number of captures and ms[5] how many of them updated
+ * the existing graph in place instead of instantiating a new one.  The first
+ * min(n, 6) entries are written (the rest of n zeroed); reset = 1 clears the
+ * counters afterwards. */
+int wp_host_times(wp_ctx *ctx, double *ms, int n, int reset);
+
 /* Wait for all work of the handle and report latched device conditions. */
 int wp_sync(wp_ctx *ctx);
 

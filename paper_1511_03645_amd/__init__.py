@@ -114,6 +114,7 @@ _SIGS = {
     "wp_get_time": (_I, [_P, _I, ctypes.POINTER(_D)]),
     "wp_set_time": (_I, [_P, _I, _D]),
     "wp_sync": (_I, [_P]),
+    "wp_host_times": (_I, [_P, ctypes.POINTER(_D), _I, _I]),
     "wp_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_D), ctypes.POINTER(_P)]),
     "wp_batch_destroy": (None, [_P]),
     "wp_batch_step": (_I, [_P, _I, _I]),
@@ -513,6 +514,14 @@ class WavePatch:
 
     def set_time(self, t, level=0):
         self._check(lib().wp_set_time(self.h, level, t))
+
+    def host_times(self, reset=False):
+        """wp_host_times: dict of cumulative host milliseconds (flag copy,
+        clustering, table upload, capture) and capture counts."""
+        v = (_D * 6)()
+        self._check(lib().wp_host_times(self.h, v, 6, int(reset)))
+        keys = ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms", "captures", "graph_updates")
+        return dict(zip(keys, list(v)))
 
     def sync(self):
         self._check(lib().wp_sync(self.h))

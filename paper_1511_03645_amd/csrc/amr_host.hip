@@ -523,8 +523,11 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
         // the window's rows in one linear copy, then its columns
         std::vector<uint8_t> rows((size_t)C.nx * wh), fl((size_t)ww * wh);
         int rcf;
-        if ((rcf = wp_host_copy(ctx, rows.data(), C.flags + (size_t)wj0 * C.nx, rows.size(), false)) != WP_OK)
-            return rcf;
+        ctx->host_ms[HT_FLAG_COPY] -= wp_now_ms();
+        rcf = wp_host_copy(ctx, rows.data(), C.flags + (size_t)wj0 * C.nx, rows.size(), false);
+        ctx->host_ms[HT_FLAG_COPY] += wp_now_ms();
+        if (rcf != WP_OK) return rcf;
+        ctx->host_ms[HT_CLUSTER] -= wp_now_ms();
         for (int j = 0; j < wh; ++j)
             std::copy_n(&rows[(size_t)j * C.nx + wi0], ww, &fl[(size_t)j * ww]);
         for (size_t k = 0; k < fl.size(); ++k) fl[k] = (fl[k] && allowed[k]) ? 1 : 0;
@@ -536,8 +539,12 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
         if (ww > 0 && wh > 0)
             wp_cluster_boxes(dil.data(), allowed.data(), ww, wh, 0.7, std::max(1, 64 / r), std::max(1, 8 / r), boxes);
         for (wp_patch &p : boxes) p = wp_patch{(p.ilo + wi0) * r, (p.jlo + wj0) * r, p.nx * r, p.ny * r};
+        ctx->host_ms[HT_CLUSTER] += wp_now_ms();
     }
-    return install(ctx, level + 1, boxes);
+    ctx->host_ms[HT_UPLOAD] -= wp_now_ms();
+    const int rci = install(ctx, level + 1, boxes);
+    ctx->host_ms[HT_UPLOAD] += wp_now_ms();
+    return rci;
 }
 
 extern "C" int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int cap, int *np)

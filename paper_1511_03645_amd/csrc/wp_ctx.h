@@ -8,6 +8,12 @@
 
 constexpr int RED_BLOCKS = 1024;
 
+// slots of wp_ctx::host_ms (wp_host_times)
+enum { HT_FLAG_COPY = 0, HT_CLUSTER, HT_UPLOAD, HT_CAPTURE, HT_NCAPTURE, HT_NUPDATE, WP_HOST_TIMES };
+
+// milliseconds since an arbitrary origin (steady clock)
+double wp_now_ms();
+
 // One refinement level: a canvas covering the whole domain at the level's
 // resolution (double-buffered), the patches that are active on it and the
 // tile tables of its launches.
@@ -111,6 +117,8 @@ struct wp_ctx {
     void *phi_dev = nullptr;             // adjoint initial data of the cached functional
     wp_functional phi_key{};
     bool phi_valid = false;
+    // host time spent (ms, cumulative; see wp_host_times) and event counts
+    double host_ms[WP_HOST_TIMES] = {0};
     std::string err;
     int equation = 0;                    // system the level hierarchy's steps solve: 0 forward, 1 adjoint
     bool reflux = false;                 // flux correction at coarse-fine edges (adjoint system only)

@@ -3,6 +3,7 @@
 // and functionals.  Kernels live in acoustics.hip, swe.hip, flag_reduce.hip
 // and amr.hip; Berger-Rigoutsos clustering in cluster.cpp.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -962,8 +963,25 @@ int wp_step_level(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s,
 // ---------------------------------------------------------------------------
 // graphs: captured on an internal stream, replayed on the handle stream
 // ---------------------------------------------------------------------------
+double wp_now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+extern "C" int wp_host_times(wp_ctx *ctx, double *ms, int n, int reset)
+{
+    if (!ctx) return WP_EINVAL;
+    if (n < 0 || (n > 0 && !ms)) return wp_fail(ctx, WP_EINVAL, "bad output");
+    for (int k = 0; k < n && k < WP_HOST_TIMES; ++k) ms[k] = ctx->host_ms[k];
+    for (int k = WP_HOST_TIMES; k < n; ++k) ms[k] = 0.0;
+    if (reset)
+        for (double &v : ctx->host_ms) v = 0.0;
+    return WP_OK;
+}
+
 int wp_graph_begin(wp_ctx *ctx, hipStream_t &s)
 {
+    ctx->host_ms[HT_CAPTURE] -= wp_now_ms();
     if (!ctx->cap_stream) {
         if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return wp_fail(ctx, WP_EDEVICE, "capture stream creation failed");
@@ -974,17 +992,33 @@ int wp_graph_begin(wp_ctx *ctx, hipStream_t &s)
     return WP_OK;
 }
 
+// A sequence captured again with the same launches (new tile tables, sizes
+// or time weights after a regrid) updates the instantiated graph in place;
+// another shape of sequence is instantiated anew.
 int wp_graph_end(wp_ctx *ctx, hipStream_t s, hipGraphExec_t &exec)
 {
     hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(s, &g) != hipSuccess || !g)
+    if (hipStreamEndCapture(s, &g) != hipSuccess || !g) {
+        ctx->host_ms[HT_CAPTURE] += wp_now_ms();
         return wp_fail(ctx, WP_EDEVICE, "stream capture end: %s", hipGetErrorString(hipGetLastError()));
+    }
+    ctx->host_ms[HT_NCAPTURE] += 1.0;
     if (exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+            (void)hipGraphDestroy(g);
+            ctx->host_ms[HT_NUPDATE] += 1.0;
+            ctx->host_ms[HT_CAPTURE] += wp_now_ms();
+            return WP_OK;
+        }
+        (void)hipGetLastError();
         (void)hipGraphExecDestroy(exec);
         exec = nullptr;
     }
     hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
+    ctx->host_ms[HT_CAPTURE] += wp_now_ms();
     if (e != hipSuccess) {
         exec = nullptr;
         return wp_fail(ctx, WP_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
