@@ -68,6 +68,18 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
+def counter_record(cells, rows):
+    """The committed counter summary of the dominant kernel, or None if the
+    kernel source, the grid or the tile height differ from those it was taken
+    with."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    if c.get("source_sha") != source_sha() or c.get("cells") != cells or c.get("tile_rows") != rows:
+        return None
+    return c
+
+
 def traffic_from_counters(cells, rows):
     """HBM bytes per forward-kernel launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
@@ -847,6 +859,17 @@ def main():
                      "alg_bytes_per_cell_update": ALG_BYTES[64], "tile_rows": job.pair_rows or job.rows},
         "J": J64,
     }
+    rec = counter_record(job.cells, job.pair_rows or job.rows) if spl == 2 else None
+    if rec is not None:
+        # what the counters say limits the kernel: DRAM traffic and VALU issue
+        # against their peaks (neither saturated: memory latency at the
+        # launch's waves per SIMD)
+        tr = out["roofline"]["traffic"]
+        out["roofline"]["measured"] = {
+            "dram_GBs": tr / (launch_ms * 1e-3) / 1e9, "dram_frac": tr / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "valu_issue_frac": rec.get("valu_issue"), "waves_per_simd": rec.get("waves", 0) / 1024,
+            "limiter": "memory latency (VALU issue and DRAM bandwidth both below half of peak)",
+            "source": "profiles/acou2d_pair_fp64_1024_counters.json, profiles/kernel_counters_all_workloads.md"}
     if not args.no_fp32:
         job32 = Job(cfg, wp.FP32)
         sec32, J32 = timed(job32, args.steps, args.warmup, time_kernels=True)
