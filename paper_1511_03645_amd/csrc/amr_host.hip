@@ -7,91 +7,12 @@
 #include <cmath>
 #include <vector>
 
+#include "regrid_lists.h"
 #include "wp_ctx.h"
 
 using namespace wp;
 
 namespace {
-
-// Cells inside the level's domain, within two cells (box halo) of a patch and
-// inside none, as linear indices j * nx + i in increasing order.
-// The bounding box of the patches grown by `halo` cells, clipped to nx x ny,
-// as (i0, j0, w, h); empty when there are no patches.
-struct Window {
-    int i0 = 0, j0 = 0, w = 0, h = 0;
-    Window(const std::vector<wp_patch> &P, int halo, int nx, int ny)
-    {
-        if (P.empty()) return;
-        int a = nx, b = ny, c = 0, d = 0;
-        for (const wp_patch &p : P) {
-            a = std::min(a, p.ilo);
-            b = std::min(b, p.jlo);
-            c = std::max(c, p.ilo + p.nx);
-            d = std::max(d, p.jlo + p.ny);
-        }
-        i0 = std::max(a - halo, 0);
-        j0 = std::max(b - halo, 0);
-        w = std::min(c + halo, nx) - i0;
-        h = std::min(d + halo, ny) - j0;
-    }
-    size_t at(int i, int j) const { return (size_t)(j - j0) * w + (i - i0); }
-};
-
-std::vector<int> ring_list(const std::vector<wp_patch> &P, int nx, int ny)
-{
-    const Window W(P, 2, nx, ny);
-    std::vector<uint8_t> m((size_t)W.w * W.h, 0);   // 1 inside a patch, 2 ring
-    for (const wp_patch &p : P)
-        for (int j = p.jlo; j < p.jlo + p.ny; ++j) std::fill_n(&m[W.at(p.ilo, j)], p.nx, (uint8_t)1);
-    for (const wp_patch &p : P)
-        for (int j = std::max(p.jlo - 2, 0); j < std::min(p.jlo + p.ny + 2, ny); ++j)
-            for (int i = std::max(p.ilo - 2, 0); i < std::min(p.ilo + p.nx + 2, nx); ++i)
-                if (m[W.at(i, j)] == 0) m[W.at(i, j)] = 2;
-    std::vector<int> out;
-    for (const wp_patch &p : P)   // gather from the halos only, then order
-        for (int j = std::max(p.jlo - 2, 0); j < std::min(p.jlo + p.ny + 2, ny); ++j)
-            for (int i = std::max(p.ilo - 2, 0); i < std::min(p.ilo + p.nx + 2, nx); ++i)
-                if (m[W.at(i, j)] == 2) {
-                    m[W.at(i, j)] = 3;
-                    out.push_back(j * nx + i);
-                }
-    std::sort(out.begin(), out.end());
-    return out;
-}
-std::vector<int> ring_blocks(const std::vector<int> &ring, int nx, int r, int NX)
-{
-    std::vector<std::pair<int, unsigned long long>> par;
-    for (int lin : ring) {
-        const int I = lin % nx, J = lin / nx;
-        const int pc = (J / r) * NX + I / r;
-        const unsigned long long bit = 1ULL << ((I % r) + r * (J % r));
-        par.emplace_back(pc, bit);
-    }
-    std::sort(par.begin(), par.end());
-    std::vector<int> out;
-    for (size_t k = 0; k < par.size();) {
-        unsigned long long m = 0;
-        size_t e = k;
-        for (; e < par.size() && par[e].first == par[k].first; ++e) m |= par[e].second;
-        out.push_back(par[k].first);
-        out.push_back((int)(unsigned)(m & 0xffffffffULL));
-        out.push_back((int)(unsigned)(m >> 32));
-        k = e;
-    }
-    return out;
-}
-
-// Coarse cells (linear indices on a canvas NX wide) covered by ratio-aligned
-// fine patches.
-std::vector<int> cover_list(const std::vector<wp_patch> &P, int r, int NX)
-{
-    std::vector<int> out;
-    for (const wp_patch &p : P)
-        for (int jc = p.jlo / r; jc < (p.jlo + p.ny) / r; ++jc)
-            for (int ic = p.ilo / r; ic < (p.ilo + p.nx) / r; ++ic) out.push_back(jc * NX + ic);
-    std::sort(out.begin(), out.end());
-    return out;
-}
 
 int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n, size_t &cap, const char *what)
 {
@@ -103,11 +24,12 @@ int upload_ints(wp_ctx *ctx, const std::vector<int> &v, int *&dev, long long &n,
     return rc;
 }
 
+// Byte offset of the float planes (hu, hv) of a mixed-precision canvas: they
+// follow the FP64 eta plane.
+inline size_t mixed_tail(const Level &lv) { return (size_t)lv.nx * lv.ny * sizeof(double); }
+
 // Fine cells `cells` of level l from level l-1 at time weight alpha between
 // the canvas before its last step (cold) and its current one (cnew).
-// Byte offset of the float planes (hu, hv) of a mixed-precision canvas of
-// `cells` cells: they follow the FP64 eta plane.
-inline size_t mixed_tail(const Level &lv) { return (size_t)lv.nx * lv.ny * sizeof(double); }
 
 int fill_from_coarse(wp_ctx *ctx, int l, const int *cells, long long n, double alpha, bool use_old, hipStream_t s)
 {
@@ -197,59 +119,27 @@ int average_down(wp_ctx *ctx, int l, hipStream_t s)
 }
 
 // The faces of refluxing between level f's patches and the level f-1 cells
-// that none of them covers (see Level), in the order: patch by patch, for
-// each coarse row of a patch its west then east face, then for each coarse
-// column its south then north face; then sorted by coarse cell (stably).
+// that none of them covers (see Level and reflux_faces).
 int build_faces(wp_ctx *ctx, int f)
 {
     Level &F = ctx->L[f], &C = ctx->L[f - 1];
-    const int r = F.ratio;
     F.nfaces = F.nfgroups = 0;
-    if (F.patches.empty()) return WP_OK;
-    std::vector<uint8_t> covered((size_t)C.nx * C.ny, 0);
-    for (const wp_patch &p : F.patches)
-        for (int J = p.jlo / r; J < (p.jlo + p.ny) / r; ++J)
-            std::fill_n(&covered[(size_t)J * C.nx + p.ilo / r], p.nx / r, (uint8_t)1);
-    std::vector<std::array<int, 4>> faces;
-    auto add = [&](int I, int J, int axis, bool before, int fi, int fj) {
-        if (I < 0 || J < 0 || I >= C.nx || J >= C.ny || covered[(size_t)J * C.nx + I]) return;
-        faces.push_back({J * C.nx + I, axis | (before ? 2 : 0), fi, fj});
-    };
-    for (const wp_patch &p : F.patches) {
-        const int I0 = p.ilo / r, J0 = p.jlo / r, W = p.nx / r, H = p.ny / r;
-        for (int J = J0; J < J0 + H; ++J) {
-            add(I0 - 1, J, 0, true, p.ilo, J * r);
-            add(I0 + W, J, 0, false, p.ilo + p.nx - 1, J * r);
-        }
-        for (int I = I0; I < I0 + W; ++I) {
-            add(I, J0 - 1, 1, true, I * r, p.jlo);
-            add(I, J0 + H, 1, false, I * r, p.jlo + p.ny - 1);
-        }
-    }
-    std::stable_sort(faces.begin(), faces.end(),
-                     [](const std::array<int, 4> &a, const std::array<int, 4> &b) { return a[0] < b[0]; });
     std::vector<int> flat, groups;
-    for (size_t k = 0; k < faces.size(); ++k) {
-        flat.insert(flat.end(), faces[k].begin(), faces[k].end());
-        if (k == 0 || faces[k][0] != faces[k - 1][0]) {
-            groups.push_back((int)k);
-            groups.push_back(0);
-        }
-        ++groups.back();
-    }
-    if (faces.empty()) return WP_OK;
+    reflux_faces(F.patches, F.ratio, C.nx, C.ny, flat, groups);
+    if (flat.empty()) return WP_OK;
+    const size_t nf = flat.size() / 4;
     int rc;
     long long n = 0;
     if ((rc = upload_ints(ctx, flat, F.faces_dev, n, F.faces_cap, "reflux faces")) != WP_OK) return rc;
     if ((rc = upload_ints(ctx, groups, F.fgroups_dev, n, F.fgroups_cap, "reflux groups")) != WP_OK) return rc;
-    const size_t reg_bytes = sizeof(double) * 3 * faces.size();
+    const size_t reg_bytes = sizeof(double) * 3 * nf;
     if (F.freg_cap < reg_bytes || !F.freg_dev) {
         if (F.freg_dev) wp_dfree(ctx, F.freg_dev);
         F.freg_dev = (double *)wp_dalloc(ctx, reg_bytes + reg_bytes / 2);
         F.freg_cap = F.freg_dev ? reg_bytes + reg_bytes / 2 : 0;
         if (!F.freg_dev) return wp_fail(ctx, WP_ENOMEM, "reflux registers");
     }
-    F.nfaces = (int)faces.size();
+    F.nfaces = (int)nf;
     F.nfgroups = (int)(groups.size() / 2);
     return WP_OK;
 }
@@ -371,19 +261,8 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     Level &F = ctx->L[f], &C = ctx->L[f - 1];
     int rc;
     // new cells outside every old patch: space interpolation from the level
-    // below at its current time
-    const Window W(boxes, 0, F.nx, F.ny);
-    std::vector<uint8_t> old((size_t)W.w * W.h, 0);
-    for (const wp_patch &p : F.patches) {   // the old patches, clipped to the new boxes' window
-        const int a = std::max(p.ilo, W.i0), b = std::min(p.ilo + p.nx, W.i0 + W.w);
-        for (int j = std::max(p.jlo, W.j0); j < std::min(p.jlo + p.ny, W.j0 + W.h) && a < b; ++j)
-            std::fill_n(&old[W.at(a, j)], b - a, (uint8_t)1);
-    }
-    std::vector<int> fresh;
-    for (const wp_patch &p : boxes)
-        for (int j = p.jlo; j < p.jlo + p.ny; ++j)
-            for (int i = p.ilo; i < p.ilo + p.nx; ++i)
-                if (!old[W.at(i, j)]) fresh.push_back(j * F.nx + i);
+    // below at its current time (each cell on its own, so in any order)
+    const std::vector<int> fresh = fresh_cells(boxes, F.patches, F.nx, F.ny);
     if (!fresh.empty()) {
         long long n = 0;
         if ((rc = upload_ints(ctx, fresh, ctx->fresh_dev, n, ctx->fresh_cap, "new cell")) != WP_OK) return rc;
@@ -392,14 +271,15 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     F.patches = boxes;
     if ((rc = wp_upload_tiles(ctx, F)) != WP_OK) return rc;
     {
-        const std::vector<int> ring = ring_list(F.patches, F.nx, F.ny);
-        if ((rc = upload_ints(ctx, ring, F.ring_dev, F.nring, F.ring_cap, "ring")) != WP_OK) return rc;
+        const std::vector<std::array<int, 3>> runs = ring_runs(F.patches, F.nx, F.ny);
+        if ((rc = upload_ints(ctx, run_cells(runs, F.nx), F.ring_dev, F.nring, F.ring_cap, "ring")) != WP_OK)
+            return rc;
         std::vector<int> blocks;
-        if (F.ratio <= 8) blocks = ring_blocks(ring, F.nx, F.ratio, C.nx);
+        if (F.ratio <= 8) blocks = ring_block_list(runs, F.ratio, C.nx);
         if ((rc = upload_ints(ctx, blocks, F.ringb_dev, F.nringb, F.ringb_cap, "ring block")) != WP_OK) return rc;
         F.nringb /= 3;
     }
-    if ((rc = upload_ints(ctx, cover_list(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, F.cover_cap, "cover")) !=
+    if ((rc = upload_ints(ctx, cover_cells(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, F.cover_cap, "cover")) !=
         WP_OK)
         return rc;
     if ((rc = build_faces(ctx, f)) != WP_OK) return rc;

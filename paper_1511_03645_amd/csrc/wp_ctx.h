@@ -60,7 +60,7 @@ struct Level {
     long long ncover = 0;
     // allocated sizes (bytes) of the tables above: a smaller table is written
     // into the same block
-    size_t tiles_cap = 0, ftiles_cap = 0, ring_cap = 0, ringb_cap = 0, cover_cap = 0;
+    size_t tiles_cap = 0, ftiles_cap = 0, ptiles_cap = 0, ring_cap = 0, ringb_cap = 0, cover_cap = 0;
     // refluxing (adjoint hierarchy): the edges between this level's patches
     // and level-1 cells that no patch of this level covers, as int4
     // {coarse cell, axis | (coarse cell before the edge) << 1, first fine

@@ -135,16 +135,22 @@ void wp_classify_tiles(const wp_ctx *ctx, const Level &lv, std::vector<Tile> &ti
     // the footprint's materials are those of the level-0 rows and columns
     // its resolved rows and columns fall in
     const int r = lv.nx / ctx->grid.nx0, ry = lv.ny / ctx->grid.ny0;
+    // the level-0 indices of the footprint [lo, hi] on an axis of n cells
+    // (ratio q): the in-domain part is one contiguous range, the ghost cells
+    // are resolved one by one
+    auto footprint = [](int lo, int hi, int n, int q, int blo, int bhi, std::vector<int> &out) {
+        out.clear();
+        const int a = std::max(lo, 0), b = std::min(hi, n - 1);
+        for (int k = a / q; a <= b && k <= b / q; ++k) out.push_back(k);
+        for (int i = lo; i < std::min(0, hi + 1); ++i) out.push_back(host_resolve(i, n, blo, bhi) / q);
+        for (int i = std::max(n, lo); i <= hi; ++i) out.push_back(host_resolve(i, n, blo, bhi) / q);
+        std::sort(out.begin(), out.end());
+        out.erase(std::unique(out.begin(), out.end()), out.end());
+    };
     std::vector<int> cols, rws;
     for (auto &t : tiles) {
-        cols.clear();
-        rws.clear();
-        for (int i = t.i0 - halo; i <= t.i0 + t.ni + halo - 1; ++i) cols.push_back(host_resolve(i, lv.nx, bc[0], bc[1]) / r);
-        for (int j = t.j0 - halo; j <= t.j0 + t.nj + halo - 1; ++j) rws.push_back(host_resolve(j, lv.ny, bc[2], bc[3]) / ry);
-        std::sort(cols.begin(), cols.end());
-        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-        std::sort(rws.begin(), rws.end());
-        rws.erase(std::unique(rws.begin(), rws.end()), rws.end());
+        footprint(t.i0 - halo, t.i0 + t.ni + halo - 1, lv.nx, r, bc[0], bc[1], cols);
+        footprint(t.j0 - halo, t.j0 + t.nj + halo - 1, lv.ny, ry, bc[2], bc[3], rws);
         int m0 = -1;
         bool uni = true;
         for (size_t b = 0; b < rws.size() && uni; ++b)
@@ -185,8 +191,6 @@ bool wp_pair_capable(const wp_ctx *ctx, const Level &lv)
 // first, each group in XCD order.
 static int upload_pair_tiles(wp_ctx *ctx, Level &lv)
 {
-    if (lv.ptiles_dev) wp_dfree(ctx, lv.ptiles_dev);
-    lv.ptiles_dev = nullptr;
     lv.nptiles = lv.npuni = lv.pair_rows = 0;
     if (!wp_pair_capable(ctx, lv)) return WP_OK;
     const long long cells = (long long)lv.nx * lv.ny;
@@ -202,10 +206,10 @@ static int upload_pair_tiles(wp_ctx *ctx, Level &lv)
     wp_xcd_order(uni);
     t = mixed;
     t.insert(t.end(), uni.begin(), uni.end());
-    lv.ptiles_dev = (Tile *)wp_dalloc(ctx, sizeof(Tile) * std::max<size_t>(1, t.size()));
-    if (!lv.ptiles_dev) return wp_fail(ctx, WP_ENOMEM, "tile table allocation failed");
-    if (!t.empty() && hipMemcpy(lv.ptiles_dev, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return wp_fail(ctx, WP_EDEVICE, "tile upload failed");
+    void *d = lv.ptiles_dev;
+    const int rc = wp_upload(ctx, t.data(), sizeof(Tile) * t.size(), d, lv.ptiles_cap, "pair tile table");
+    lv.ptiles_dev = (Tile *)d;
+    if (rc != WP_OK) return rc;
     lv.nptiles = (int)t.size();
     lv.npuni = (int)uni.size();
     lv.pair_rows = rows;
