@@ -108,7 +108,10 @@ typedef struct {
 } wp_coefficients;
 
 /* Domain and refinement hierarchy (Sec. 3): num_levels levels, ratio[l]
- * refining level l to level l+1 in space and in time. */
+ * (2 .. 16) refining level l to level l+1 in space and in time.  Each level
+ * is held as one canvas of the whole domain at its resolution, so the
+ * finest level's cell count nx0 ny0 (ratio[0] ... ratio[num_levels-2])^2 is
+ * bounded (wp_create fails with WP_EINVAL above 2^32 / (5 x element size)). */
 typedef struct {
     double xlo, xhi, ylo, yhi;
     int nx0, ny0;
@@ -413,9 +416,10 @@ int wp_set_time(wp_ctx *ctx, int level, double t);
  * nesting, ms[2] rebuilding and uploading the tables of the new patches,
  * ms[3] capturing launch sequences (and instantiating or updating their
  * graphs); ms[4] the number of captures and ms[5] how many of them updated
- * the existing graph in place instead of instantiating a new one.  The first
- * min(n, 6) entries are written (the rest of n zeroed); reset = 1 clears the
- * counters afterwards. */
+ * the existing graph in place instead of instantiating a new one; ms[6] the
+ * part of ms[2] spent in host-to-device copies of the tables (staging, copy,
+ * wait).  The first min(n, 7) entries are written (the rest of n zeroed);
+ * reset = 1 clears the counters afterwards. */
 int wp_host_times(wp_ctx *ctx, double *ms, int n, int reset);
 
 /* Wait for all work of the handle and report latched device conditions. */

@@ -517,10 +517,11 @@ class WavePatch:
 
     def host_times(self, reset=False):
         """wp_host_times: dict of cumulative host milliseconds (flag copy,
-        clustering, table upload, capture) and capture counts."""
-        v = (_D * 6)()
-        self._check(lib().wp_host_times(self.h, v, 6, int(reset)))
-        keys = ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms", "captures", "graph_updates")
+        clustering, table rebuild and upload, capture, and the upload's
+        host-to-device copies) and capture counts."""
+        v = (_D * 7)()
+        self._check(lib().wp_host_times(self.h, v, 7, int(reset)))
+        keys = ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms", "captures", "graph_updates", "h2d_ms")
         return dict(zip(keys, list(v)))
 
     def sync(self):

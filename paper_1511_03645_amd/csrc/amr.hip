@@ -177,7 +177,10 @@ __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ ce
                                                       const T *__restrict__ fine, int nxf, long long csf,
                                                       T *__restrict__ coarse, int NX, long long csc, int r, int nk)
 {
-    const T inv = T(1) / T(r * r);   // exact for the power-of-two ratios
+    // the mean as the sum over r^2: a power-of-two ratio's reciprocal
+    // multiplies exactly as it divides
+    const bool pow2 = (r & (r - 1)) == 0;
+    const T inv = T(1) / T(r * r);
     for (long long n = blockIdx.x * 256LL + threadIdx.x; n < ncells; n += (long long)gridDim.x * 256) {
         const int lin = cells[n];
         const int ic = lin % NX, jc = lin / NX;
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ ce
                 for (int jj = 0; jj < r; ++jj)
                     for (int ii = 0; ii < r; ++ii) s += fine[k * csf + (long long)(r * jc + jj) * nxf + (r * ic + ii)];
             }
-            coarse[k * csc + lin] = s * inv;
+            coarse[k * csc + lin] = pow2 ? s * inv : s / T(r * r);
         }
     }
 }

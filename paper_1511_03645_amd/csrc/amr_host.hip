@@ -271,11 +271,17 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     F.patches = boxes;
     if ((rc = wp_upload_tiles(ctx, F)) != WP_OK) return rc;
     {
+        // ratios up to 8 fill the ring by coarse parent, larger ones cell by cell
         const std::vector<std::array<int, 3>> runs = ring_runs(F.patches, F.nx, F.ny);
-        if ((rc = upload_ints(ctx, run_cells(runs, F.nx), F.ring_dev, F.nring, F.ring_cap, "ring")) != WP_OK)
-            return rc;
-        std::vector<int> blocks;
-        if (F.ratio <= 8) blocks = ring_block_list(runs, F.ratio, C.nx);
+        F.nring = 0;
+        for (const auto &u : runs) F.nring += u[2] - u[1];
+        std::vector<int> blocks, cells;
+        if (F.ratio <= 8)
+            blocks = ring_block_list(runs, F.ratio, C.nx);
+        else
+            cells = run_cells(runs, F.nx);
+        long long n = 0;
+        if ((rc = upload_ints(ctx, cells, F.ring_dev, n, F.ring_cap, "ring")) != WP_OK) return rc;
         if ((rc = upload_ints(ctx, blocks, F.ringb_dev, F.nringb, F.ringb_cap, "ring block")) != WP_OK) return rc;
         F.nringb /= 3;
     }
@@ -372,7 +378,7 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
     }
     if (C.patches.empty()) wi0 = wj0 = wi1 = wj1 = 0;
     const int ww = wi1 - wi0, wh = wj1 - wj0;
-    std::vector<uint8_t> allowed;
+    std::vector<uint8_t> &allowed = ctx->rg_allowed;
     wp_nesting_mask(C.patches, C.nx, C.ny, wi0, wj0, ww, wh, allowed);
     auto in_window = [&](int i, int j) { return i >= wi0 && i < wi1 && j >= wj0 && j < wj1; };
     std::vector<wp_patch> boxes;
@@ -401,7 +407,9 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
         if (buffer < 0) return wp_fail(ctx, WP_EINVAL, "buffer must be non-negative");
         if (!C.flags_valid) return wp_fail(ctx, WP_ESTATE, "level %d has no flags (flag it first)", level);
         // the window's rows in one linear copy, then its columns
-        std::vector<uint8_t> rows((size_t)C.nx * wh), fl((size_t)ww * wh);
+        std::vector<uint8_t> &rows = ctx->rg_rows, &fl = ctx->rg_flags;
+        rows.resize((size_t)C.nx * wh);
+        fl.resize((size_t)ww * wh);
         int rcf;
         ctx->host_ms[HT_FLAG_COPY] -= wp_now_ms();
         rcf = wp_host_copy(ctx, rows.data(), C.flags + (size_t)wj0 * C.nx, rows.size(), false);
@@ -413,7 +421,7 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
         for (size_t k = 0; k < fl.size(); ++k) fl[k] = (fl[k] && allowed[k]) ? 1 : 0;
         // flags outside the window are outside the nesting region, so the
         // window's dilation restricted to it is the whole level's
-        std::vector<uint8_t> dil;
+        std::vector<uint8_t> &dil = ctx->rg_dil;
         wp_dilate(fl, ww, wh, buffer, dil);
         for (size_t k = 0; k < dil.size(); ++k) dil[k] = (dil[k] && allowed[k]) ? 1 : 0;
         if (ww > 0 && wh > 0)

@@ -24,26 +24,46 @@ namespace {
 // entry instead of a scan of the box.  Coordinates are window-relative.
 struct Sat {
     int nx, ny;
-    std::vector<int> F, B;   // (nx + 1) x (ny + 1), entry (i, j) sums cells [0, i) x [0, j)
+    const int *F, *B;   // (nx + 1) x (ny + 1), entry (i, j) sums cells [0, i) x [0, j)
     Sat(const uint8_t *f, const uint8_t *ok, size_t pitch, int i0, int j0, int nx_, int ny_) : nx(nx_), ny(ny_)
     {
+        // the tables live on between calls (no page faults, no clearing: the
+        // zero row and column are set, every other entry is written); each
+        // row's running sums first, then added to the row above
+        static thread_local std::vector<int> tf, tb, rf, rb;
         const size_t W = (size_t)nx + 1;
-        F.assign(W * (ny + 1), 0);
-        B.assign(W * (ny + 1), 0);
+        if (tf.size() < W * (ny + 1)) {
+            tf.resize(W * (ny + 1));
+            tb.resize(W * (ny + 1));
+        }
+        if (rf.size() < (size_t)nx) {
+            rf.resize(nx);
+            rb.resize(nx);
+        }
+        int *Fw = tf.data(), *Bw = tb.data();
+        std::fill_n(Fw, W, 0);
+        std::fill_n(Bw, W, 0);
         for (int j = 0; j < ny; ++j) {
             const uint8_t *fr = f + (size_t)(j0 + j) * pitch + i0;
             const uint8_t *okr = ok ? ok + (size_t)(j0 + j) * pitch + i0 : nullptr;
-            int rf = 0, rb = 0;
+            int sf = 0, sb = 0;
             for (int i = 0; i < nx; ++i) {
                 const bool a = !okr || okr[i];
-                rf += a && fr[i];
-                rb += !a;
-                F[(j + 1) * W + i + 1] = F[j * W + i + 1] + rf;
-                B[(j + 1) * W + i + 1] = B[j * W + i + 1] + rb;
+                sf += a && fr[i];
+                sb += !a;
+                rf[i] = sf;
+                rb[i] = sb;
             }
+            const int *fa = Fw + j * W + 1, *ba = Bw + j * W + 1;
+            int *fo = Fw + (j + 1) * W, *bo = Bw + (j + 1) * W;
+            fo[0] = bo[0] = 0;
+            for (int i = 0; i < nx; ++i) fo[i + 1] = fa[i] + rf[i];
+            for (int i = 0; i < nx; ++i) bo[i + 1] = ba[i] + rb[i];
         }
+        F = Fw;
+        B = Bw;
     }
-    static int box(const std::vector<int> &S, size_t W, int i0, int j0, int i1, int j1)
+    static int box(const int *S, size_t W, int i0, int j0, int i1, int j1)
     {
         return S[j1 * W + i1] - S[j0 * W + i1] - S[j1 * W + i0] + S[j0 * W + i0];
     }
@@ -166,48 +186,67 @@ void wp_nesting_mask(const std::vector<wp_patch> &patches, int nx, int ny, int w
     // inside (no neighbour there), domain cells outside the window are in no
     // patch; then a 3 x 3 erosion, along rows and then along columns
     const int pw = ww + 2, ph = wh + 2;
-    std::vector<uint8_t> in((size_t)pw * ph, 0), row((size_t)pw * ph, 0);
+    static thread_local std::vector<uint8_t> in, row;
+    in.assign((size_t)pw * ph, 0);
+    row.resize((size_t)pw * ph);
+    // only the frame around the window can lie outside the domain
     for (int b = 0; b < ph; ++b)
-        for (int a = 0; a < pw; ++a) {
+        for (int a = 0; a < pw; a += (b == 0 || b == ph - 1) ? 1 : pw - 1) {
             const int i = wi0 - 1 + a, j = wj0 - 1 + b;
             if (i < 0 || i >= nx || j < 0 || j >= ny) in[(size_t)b * pw + a] = 1;
         }
     for (const auto &p : patches)
         for (int j = p.jlo; j < p.jlo + p.ny; ++j)
             std::fill_n(&in[(size_t)(j - wj0 + 1) * pw + (p.ilo - wi0 + 1)], p.nx, (uint8_t)1);
-    for (int b = 0; b < ph; ++b)
-        for (int a = 1; a < pw - 1; ++a) {
-            const uint8_t *x = &in[(size_t)b * pw + a];
-            row[(size_t)b * pw + a] = x[-1] & x[0] & x[1];
-        }
+    for (int b = 0; b < ph; ++b) {
+        const uint8_t *x = &in[(size_t)b * pw];
+        uint8_t *y = &row[(size_t)b * pw];
+        for (int a = 1; a < pw - 1; ++a) y[a] = x[a - 1] & x[a] & x[a + 1];
+    }
     mask.assign((size_t)ww * wh, 0);
-    for (int b = 1; b < ph - 1; ++b)
-        for (int a = 1; a < pw - 1; ++a) {
-            const size_t k = (size_t)b * pw + a;
-            mask[(size_t)(b - 1) * ww + (a - 1)] = in[k] & row[k - pw] & row[k] & row[k + pw];
-        }
+    for (int b = 1; b < ph - 1; ++b) {
+        const uint8_t *x = &in[(size_t)b * pw + 1], *up = &row[(size_t)(b - 1) * pw + 1];
+        const uint8_t *mid = &row[(size_t)b * pw + 1], *dn = &row[(size_t)(b + 1) * pw + 1];
+        uint8_t *m = &mask[(size_t)(b - 1) * ww];
+        for (int a = 0; a < ww; ++a) m[a] = x[a] & up[a] & mid[a] & dn[a];
+    }
 }
 
 // Box dilation by k cells (flag buffering around flagged cells) of an
 // nx x ny image: a running count along each row, then along each column.
 void wp_dilate(const std::vector<uint8_t> &f, int nx, int ny, int k, std::vector<uint8_t> &out)
 {
-    out = f;
-    if (k <= 0) return;
-    std::vector<uint8_t> rows((size_t)nx * ny, 0);
-    std::vector<int> pre(std::max(nx, ny) + 1);
+    if (k <= 0) {
+        out = f;
+        return;
+    }
+    out.resize((size_t)nx * ny);
+    static thread_local std::vector<uint8_t> rows;
+    rows.resize((size_t)nx * ny);
+    std::vector<int> pre(nx + 1);
     for (int j = 0; j < ny; ++j) {
         const uint8_t *r = &f[(size_t)j * nx];
+        uint8_t *o = &rows[(size_t)j * nx];
         pre[0] = 0;
         for (int i = 0; i < nx; ++i) pre[i + 1] = pre[i] + (r[i] != 0);
-        for (int i = 0; i < nx; ++i)
-            rows[(size_t)j * nx + i] = pre[std::min(i + k + 1, nx)] - pre[std::max(i - k, 0)] > 0;
+        for (int i = 0; i < nx; ++i) o[i] = pre[std::min(i + k + 1, nx)] - pre[std::max(i - k, 0)] > 0;
     }
-    for (int i = 0; i < nx; ++i) {
-        pre[0] = 0;
-        for (int j = 0; j < ny; ++j) pre[j + 1] = pre[j] + rows[(size_t)j * nx + i];
-        for (int j = 0; j < ny; ++j)
-            out[(size_t)j * nx + i] = pre[std::min(j + k + 1, ny)] - pre[std::max(j - k, 0)] > 0;
+    // along columns: per column the count of row-dilated cells in rows
+    // j - k .. j + k, slid down one row at a time
+    std::vector<int> cnt(nx, 0);
+    for (int j = 0; j < std::min(k, ny); ++j)
+        for (int i = 0; i < nx; ++i) cnt[i] += rows[(size_t)j * nx + i];
+    for (int j = 0; j < ny; ++j) {
+        if (j + k < ny) {
+            const uint8_t *a = &rows[(size_t)(j + k) * nx];
+            for (int i = 0; i < nx; ++i) cnt[i] += a[i];
+        }
+        if (j - k - 1 >= 0) {
+            const uint8_t *d = &rows[(size_t)(j - k - 1) * nx];
+            for (int i = 0; i < nx; ++i) cnt[i] -= d[i];
+        }
+        uint8_t *o = &out[(size_t)j * nx];
+        for (int i = 0; i < nx; ++i) o[i] = cnt[i] > 0;
     }
 }
 

@@ -9,7 +9,7 @@
 constexpr int RED_BLOCKS = 1024;
 
 // slots of wp_ctx::host_ms (wp_host_times)
-enum { HT_FLAG_COPY = 0, HT_CLUSTER, HT_UPLOAD, HT_CAPTURE, HT_NCAPTURE, HT_NUPDATE, WP_HOST_TIMES };
+enum { HT_FLAG_COPY = 0, HT_CLUSTER, HT_UPLOAD, HT_CAPTURE, HT_NCAPTURE, HT_NUPDATE, HT_H2D, WP_HOST_TIMES };
 
 // milliseconds since an arbitrary origin (steady clock)
 double wp_now_ms();
@@ -52,6 +52,8 @@ struct Level {
     // patch, within two cells of one), filled from the level below before
     // each step; coarse cells covered by the patches (linear indices on the
     // level below), overwritten by the average of their children
+    // (nring cells; ring_dev lists them only for ratios above 8, smaller
+    // ratios take ringb_dev)
     int *ring_dev = nullptr;
     long long nring = 0;
     int *ringb_dev = nullptr;            // the ring by coarse parent (see launch_ring_fill_blocks)
@@ -119,6 +121,9 @@ struct wp_ctx {
     bool phi_valid = false;
     // host time spent (ms, cumulative; see wp_host_times) and event counts
     double host_ms[WP_HOST_TIMES] = {0};
+    // host images of a regrid (flag rows, window flags, nesting mask,
+    // buffered flags), kept between regrids
+    std::vector<uint8_t> rg_rows, rg_flags, rg_allowed, rg_dil;
     std::string err;
     int equation = 0;                    // system the level hierarchy's steps solve: 0 forward, 1 adjoint
     bool reflux = false;                 // flux correction at coarse-fine edges (adjoint system only)

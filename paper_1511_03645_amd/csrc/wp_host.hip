@@ -478,8 +478,8 @@ extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef,
         return bail(wp_fail(ctx, WP_EINVAL, "refinement levels are supported in 2D"));
     long long cells_l = (long long)G.nx0 * (ctx->kind2d ? G.ny0 : 1);
     for (int l = 0; l + 1 < G.num_levels; ++l) {
-        if (G.ratio[l] < 2 || G.ratio[l] > 8 || (G.ratio[l] & (G.ratio[l] - 1)))
-            return bail(wp_fail(ctx, WP_EINVAL, "refinement ratios must be 2, 4 or 8"));
+        if (G.ratio[l] < 2 || G.ratio[l] > 16)
+            return bail(wp_fail(ctx, WP_EINVAL, "refinement ratios must be between 2 and 16"));
         cells_l *= (long long)G.ratio[l] * G.ratio[l];
     }
     // kernels address a canvas with 32-bit byte offsets; a dropped store
@@ -680,7 +680,11 @@ int wp_upload(wp_ctx *ctx, const void *src, size_t bytes, void *&dev, size_t &ca
         cap = dev ? want : 0;
         if (!dev) return wp_fail(ctx, WP_ENOMEM, "%s allocation failed", what);
     }
-    return wp_host_copy(ctx, dev, src, bytes, true);
+    if (bytes == 0) return WP_OK;
+    ctx->host_ms[HT_H2D] -= wp_now_ms();
+    const int rc = wp_host_copy(ctx, dev, src, bytes, true);
+    ctx->host_ms[HT_H2D] += wp_now_ms();
+    return rc;
 }
 
 int wp_host_copy(wp_ctx *ctx, void *dst, const void *src, size_t bytes, bool to_device)

@@ -189,6 +189,7 @@ REFLUX_LAYOUTS = [
     (32, [2, 2], [[(16, 16, 24, 20), (40, 12, 12, 28)], [(36, 40, 24, 16)]], (1, 1, 1, 1)),
     (24, [4], [[(8, 8, 32, 24), (40, 8, 16, 48)]], (0, 0, 0, 0)),
     (16, [2, 4], [[(4, 4, 20, 16)], [(24, 24, 40, 32), (64, 24, 8, 8)]], (0, 1, 1, 0)),
+    (20, [3], [[(6, 6, 24, 18), (33, 9, 15, 36)]], (1, 1, 1, 1)),
 ]
 
 

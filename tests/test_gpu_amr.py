@@ -62,6 +62,13 @@ LAYOUTS = [
     (24, [4], [[(8, 8, 32, 24), (40, 8, 16, 48)]], (0, 0, 0, 0)),
     (20, [2], [[(0, 0, 12, 40), (12, 30, 28, 10)]], (1, 0, 1, 1)),
     (16, [2, 4], [[(4, 4, 20, 16)], [(24, 24, 40, 32), (64, 24, 8, 8)]], (0, 1, 0, 0)),
+    # ratios that are not powers of two (odd ones fill the ring one substep
+    # at a time), and one above 8 (the ring filled cell by cell)
+    (20, [3], [[(6, 6, 24, 18), (33, 9, 15, 36)]], (0, 0, 0, 0)),
+    (16, [5], [[(0, 0, 25, 20), (40, 30, 35, 40)]], (1, 0, 1, 1)),
+    (12, [3, 2], [[(6, 6, 18, 15)], [(14, 14, 20, 12), (36, 20, 6, 8)]], (0, 1, 0, 0)),
+    (10, [2, 6], [[(4, 4, 12, 10)], [(30, 36, 42, 30)]], (1, 1, 0, 0)),
+    (8, [12], [[(24, 12, 36, 48)]], (0, 0, 0, 0)),
 ]
 
 

@@ -22,6 +22,8 @@ LAYOUTS = [
     (32, (2, 2), [[(40, 8, 20, 32), (8, 8, 16, 16)], [(88, 24, 24, 32)]], (0, 0, 0, 0)),
     (24, (4,), [[(40, 16, 36, 48), (16, 60, 24, 20)]], (1, 0, 1, 0)),
     (16, (2, 4), [[(4, 4, 20, 16)], [(24, 24, 40, 32), (64, 24, 8, 8)]], (0, 1, 0, 1)),
+    (18, (3,), [[(9, 9, 24, 18), (36, 27, 12, 21)]], (1, 0, 0, 1)),
+    (12, (2, 3), [[(4, 4, 12, 10)], [(18, 18, 24, 21)]], (0, 0, 0, 0)),
 ]
 
 

@@ -237,7 +237,17 @@ def test_adjoint_hierarchy_keeps_the_duality_pairing():
         assert np.allclose(a * flip, f, rtol=0, atol=1e-13 * np.abs(f).max())
 
 
-def test_berger_oliger_time_weights_keep_an_exact_linear_solution():
+# level 1 covers coarse cells 12..19, so its nesting region is level-1 cells
+# 12 r + 1 .. 20 r - 2; the level-2 patches touch it on the left and on the
+# right (ratio 2: level-2 cells 50 and 77; ratio 3: 111 and 176)
+BO_LAYOUTS = [
+    (2, [(24, 24, 16, 16)], [(50, 50, 12, 12), (62, 56, 10, 8), (72, 64, 6, 10)]),
+    (3, [(36, 36, 24, 24)], [(111, 114, 24, 30), (135, 126, 24, 21), (159, 135, 18, 30)]),
+]
+
+
+@pytest.mark.parametrize("r,p1,p2", BO_LAYOUTS)
+def test_berger_oliger_time_weights_keep_an_exact_linear_solution(r, p1, p2):
     """p = 0.75 x - 0.5 t, u = 0.5 x - 0.75 t, v = 0 solves 2D acoustics with
     rho = K = 1, and the limited wave-propagation step reproduces it exactly
     (every jump is the same, so every limiter ratio is 1 and the scheme is
@@ -247,23 +257,19 @@ def test_berger_oliger_time_weights_keep_an_exact_linear_solution():
     solution only if every ghost fill uses the time of the fine substep it
     serves: the k-th of the r substeps at (1 - k/r, k/r), and a level's own
     ring, refilled at the end of its step for the finer level's slopes, at
-    the weight of that level's new time.  Three levels of ratio 2, the
-    level-2 patch against level 1's nesting edge, so the level-2 ring's
-    slopes read level-1 ring cells, on both sides; the coarse domain is wide enough that the
-    outflow boundary (inexact for a linear field) stays away from the
-    patches for the steps taken."""
+    the weight of that level's new time.  Three levels of ratio 2, and of
+    ratio 3 (whose interpolation weights and time weights are not binary
+    fractions), the level-2 patches against level 1's nesting edge, so the
+    level-2 ring's slopes read level-1 ring cells, on both sides; the coarse
+    domain is wide enough that the outflow boundary (inexact for a linear
+    field) stays away from the patches for the steps taken."""
     n = 32
     cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=-2.0, xhi=2.0, ylo=-2.0, yhi=2.0, dx=4.0 / n, dy=4.0 / n,
                rho=np.ones((n, n)), K=np.ones((n, n)), bc=[0, 0, 0, 0], order=2, limiter=1, transverse=1,
                g=9.81)
-    r = 2
-    # level 1 covers coarse cells 12..19, so its nesting region is level-1
-    # cells 25..38; level-2 patches touch it on the left (level-2 cell 50)
-    # and on the right (level-2 cell 77).  A ring error can only steepen or
-    # flatten one of the two one-sided slopes that minmod compares; the two
-    # sides see it with opposite sign, so one of them picks it up.
-    p1 = [(24, 24, 16, 16)]
-    p2 = [(50, 50, 12, 12), (62, 56, 10, 8), (72, 64, 6, 10)]
+    # A ring error can only steepen or flatten one of the two one-sided
+    # slopes that minmod compares; the two sides see it with opposite sign,
+    # so one of them picks it up.
     H = amr.Hierarchy(cfg, [r, r], [p1, p2])
 
     def exact(l, t):
