@@ -525,10 +525,11 @@ def swe_flagging_compare(n0=256, ratios=(4, 2), regrid_every=2, buffer=2):
                     return float(w.get_state(level=l, patch=k)[0, j - j0, i - i0])
         return float(w.get_state(0)[0, gj // R, gi // R])
 
-    def run(mode, tol, record=False):
+    def run(mode, tol, record=False, reflux=False):
         w = wp.from_config(cfg, num_levels=3, ratios=tuple(ratios))
         for l, B in enumerate(cfg["B_levels"]):
             w.set_bathymetry(l + 1, B)
+        w.set_reflux(reflux)
         w.set_state(cfg["q0"])
         torch.cuda.synchronize()
         w.host_times(reset=True)
@@ -555,7 +556,7 @@ def swe_flagging_compare(n0=256, ratios=(4, 2), regrid_every=2, buffer=2):
         cyc = N // regrid_every
         ht = w.host_times()
         del w
-        res = {"flag": mode, "tol": tol, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
+        res = {"flag": mode, "tol": tol, "reflux": reflux, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
                "mean_cells_level1": cells[0] / cyc, "mean_cells_level2": cells[1] / cyc,
                "per_cycle_host_ms": {k: round(ht[k] / cyc, 4)
                                      for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "h2d_ms", "capture_ms")},
@@ -568,10 +569,12 @@ def swe_flagging_compare(n0=256, ratios=(4, 2), regrid_every=2, buffer=2):
         return res
 
     runs = []
-    for mode, tol in (("adjoint", 1e-3), ("adjoint", 1e-4), ("surface", 0.05), ("surface", 0.02)):
-        run(mode, tol)                      # warm-up
-        res = run(mode, tol)
-        res.update(run(mode, tol, record=True))   # the gauge, in a run of its own (host reads)
+    # the last two with the flux correction at coarse-fine edges
+    for mode, tol, rf in (("adjoint", 1e-3, False), ("adjoint", 1e-4, False), ("surface", 0.05, False),
+                          ("surface", 0.02, False), ("adjoint", 1e-4, True), ("surface", 0.02, True)):
+        run(mode, tol, reflux=rf)                      # warm-up
+        res = run(mode, tol, reflux=rf)
+        res.update(run(mode, tol, record=True, reflux=rf))   # the gauge, in a run of its own (host reads)
         runs.append(res)
     return {"workload": f"swe2d 2048 km ocean, coarse {n0}^2, ratios {ratios[0]},{ratios[1]} (finest 1 km), "
                         f"{N} coarse steps to {cfg['t_f']:.0f} s, flag + regrid of levels 0 and 1 every "
@@ -917,7 +920,8 @@ def main():
         print("[bench] shallow water with refinement: adjoint vs surface flagging", file=sys.stderr, flush=True)
         out["swe_flagging"] = swe_flagging_compare()
         for r in out["swe_flagging"]["runs"]:
-            print(f"[bench]   {r['flag']:8s} tol {r['tol']:g}: {r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
+            print(f"[bench]   {r['flag']:8s} tol {r['tol']:g}{' refluxed' if r['reflux'] else ''}: "
+                  f"{r['seconds']:.3f} s, J rel err {r['J_rel_err']:.2e}, "
                   f"gauge err {r['gauge_max_err_rel']:.2e}, level-2 cells {r['mean_cells_level2']:.0f}, "
                   f"captures {r['captures']} ({r['graph_updates']} in place)", file=sys.stderr, flush=True)
     if not args.no_swe:

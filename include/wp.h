@@ -214,23 +214,30 @@ int wp_set_equation(wp_ctx *ctx, int adjoint);
 int wp_get_equation(const wp_ctx *ctx, int *adjoint);
 
 /* Flux correction at coarse-fine edges (refluxing) for the Berger-Oliger
- * steps of wp_advance while the hierarchy solves the adjoint system.  The
- * reversed adjoint is solved in f-wave form, which is in conservation form
- * (Sec. 3 contrasts it with the forward problem): every edge carries one flux
- * F = f(Q_left) + A^-dQ + Ftilde = f(Q_right) - A^+dQ + Ftilde with
- * f = -A^T q (x) or -B^T q (y), Ftilde the limited correction flux with its
- * transverse terms.  After the r substeps of a level l+1 and its average
- * onto level l, every level-l cell C that shares an edge with a level-l+1
- * patch and lies in none is corrected by
+ * steps of wp_advance, for the systems in conservation form (Sec. 3 contrasts
+ * the adjoint with the forward acoustics): the 2D acoustics hierarchy while
+ * it solves the adjoint system, and the shallow-water hierarchy (eq. swe).
+ * An edge carries the flux F = f(Q_left) + A^-dQ + Ftilde, seen from the
+ * cell left of / below it, or f(Q_right) - A^+dQ + Ftilde from the other
+ * side, Ftilde the limited correction flux with its transverse terms.  The
+ * reversed adjoint is in f-wave form with f = -A^T q (x) or -B^T q (y), so
+ * both sides agree.  Shallow water: the f-waves split the flux difference
+ * less the bathymetry source, and f is the physical flux with the
+ * hydrostatic pressure of the sea at rest taken out (1/2 g eta (eta - 2B) in
+ * place of 1/2 g h^2); the sides agree in mass, and in every component on a
+ * flat bottom, and every flux of a lake at rest is zero.  After the r
+ * substeps of a level l+1 and its average onto level l, every level-l cell C
+ * that shares an edge with a level-l+1 patch and lies in none is corrected by
  *     Q_C += s dt_l/h_l (F_coarse - sum of the fine fluxes / r^2),
  * s = +1 when C lies left of / below the edge, the fine sum taken over the r
  * fine edges along it and the r substeps, each flux evaluated (in FP64) from
- * the state its step started from.  The composite sum of a conserved
- * component then changes only through the domain boundary (e.g. p with
- * walls all round).  wp_step_patches does no correction.  on: 0 or 1;
- * WP_ESTATE for on = 1 while the forward system is selected (its wave form
- * is not conservative; wp_set_equation(0) turns refluxing off), WP_EINVAL
- * for another kind than 2D acoustics. */
+ * the state its step started from and seen from C's side of the edge (for a
+ * fine edge, its ghost cell there).  The composite sum of a conserved
+ * component then changes only through the domain boundary (p of the adjoint,
+ * or the water volume, with walls all round).  wp_step_patches does no
+ * correction.  on: 0 or 1; WP_ESTATE for on = 1 while the acoustics forward
+ * system is selected (its wave form is not conservative; wp_set_equation(0)
+ * turns refluxing off), WP_EINVAL for a 1D problem. */
 int wp_set_reflux(wp_ctx *ctx, int on);
 int wp_get_reflux(const wp_ctx *ctx, int *on);
 

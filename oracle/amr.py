@@ -183,10 +183,11 @@ class Hierarchy:
             if equation != "forward":
                 raise ValueError("the shallow-water hierarchy solves the forward problem")
             self.which = 2
-        # flux bookkeeping at coarse-fine edges: only the adjoint is in
-        # conservation form (Sec. 3 contrasts it with the forward problem)
-        if reflux and self.which != 1:
-            raise ValueError("refluxing needs the conservative (adjoint, f-wave) form")
+        # flux bookkeeping at coarse-fine edges: the adjoint acoustics and the
+        # shallow-water equations are in conservation form (Sec. 3 contrasts
+        # the adjoint with the forward acoustics, which are not)
+        if reflux and self.which not in (1, 2):
+            raise ValueError("refluxing needs a conservative form (the adjoint, or shallow water)")
         self.reflux = reflux
         self.edges = [None] * (len(self.ratios) + 1)
         nx0, ny0 = cfg["nx"], cfg["ny"]
@@ -315,9 +316,11 @@ class Hierarchy:
                 self.sub[l + 1] = k
                 self.advance(l + 1, dt / r)
                 if self.reflux:
+                    # shallow water: the fine edges as the ghost cells on the
+                    # coarse cell's side saw them
                     for n, f in enumerate(faces):
                         for e in f["fine"]:
-                            fine[n] = fine[n] + self._edge_flux(l + 1, e)
+                            fine[n] = fine[n] + self._edge_flux(l + 1, e, flip=self.swe)
             average_down(self.q[l + 1], self.q[l], r, self.patches[l + 1])
             if self.reflux:
                 self.apply_reflux(l, dt, faces, coarse, fine)
@@ -334,20 +337,45 @@ class Hierarchy:
             return np.array([-q[1] / rho, -K * q[0], 0.0])
         return np.array([-q[2] / rho, 0.0, -K * q[0]])
 
-    def _edge_flux(self, l, e):
-        """Numerical flux through an edge of level l in its last step, from
-        the cell on the patch side: the cell's flux plus what the edge gave
-        it, F = f(Q_left) + A-dQ + F~ = f(Q_right) - A+dQ + F~ (f-wave form:
-        A-dQ + A+dQ is the flux difference, so both sides agree)."""
+    def _swe_flux(self, l, axis, i, j):
+        """Shallow-water flux through a face normal to `axis` at cell (i, j)
+        of level l from its state at the start of the level's last step,
+        with the hydrostatic pressure of the sea at rest (eta = 0) taken out:
+        1/2 g h^2 - 1/2 g B^2 = 1/2 g eta (eta - 2 B) in place of 1/2 g h^2
+        (eq. swe).  The shift is constant where B is, so flux differences on
+        a flat bottom are unchanged, and it is zero for a lake at rest."""
+        q = self.q_old[l][:, j, i]
+        B = self.B[l][j, i]
+        g = self.cfg.get("g", 9.81)
+        h = q[0] - B
+        n, t = (1, 2) if axis == 0 else (2, 1)
+        f = np.zeros(3)
+        f[0] = q[n]
+        f[n] = q[n] * (q[n] / h) + 0.5 * g * q[0] * (q[0] - 2.0 * B)
+        f[t] = q[n] * (q[t] / h)
+        return f
+
+    def _edge_flux(self, l, e, flip=False):
+        """Numerical flux through an edge of level l in its last step, as the
+        cell on side e[4] of it (-1: left of / below the edge; flip: the
+        other side) sees it: the cell's flux plus what the edge gave it,
+        F = f(Q_left) + A-dQ + F~ or f(Q_right) - A+dQ + F~.  In the f-wave
+        form A-dQ + A+dQ is the flux difference, so for the adjoint both
+        sides agree; for shallow water they differ by the bathymetry source
+        of the edge, and refluxing takes the side of the coarse cell it
+        corrects (for an edge of the finer level, its ghost cell there)."""
         pidx, axis, li, lj, cell_side = e
+        if flip:
+            cell_side = -cell_side
         (i0, j0, w, h), xe, ye = self.edges[l][pidx]
         arr = xe if axis == 0 else ye
         am, ap, F = arr[0][:, lj, li], arr[1][:, lj, li], arr[2][:, lj, li]
+        flux = self._swe_flux if self.swe else self._flux
         if cell_side < 0:   # the cell is left of / below the edge
             ci, cj = (i0 + li - 1, j0 + lj) if axis == 0 else (i0 + li, j0 + lj - 1)
-            return self._flux(l, axis, ci, cj) + am + F
+            return flux(l, axis, ci, cj) + am + F
         ci, cj = i0 + li, j0 + lj
-        return self._flux(l, axis, ci, cj) - ap + F
+        return flux(l, axis, ci, cj) - ap + F
 
     def _patch_of(self, l, i, j):
         for n, (i0, j0, w, h) in enumerate(self.patches[l]):

@@ -394,7 +394,8 @@ class WavePatch:
         return bool(v.value)
 
     def set_reflux(self, on):
-        """wp_set_reflux: flux correction at coarse-fine edges of the adjoint hierarchy."""
+        """wp_set_reflux: flux correction at coarse-fine edges of the adjoint
+        acoustics hierarchy or of the shallow-water hierarchy."""
         self._check(lib().wp_set_reflux(self.h, int(on)))
 
     def get_reflux(self):

@@ -151,7 +151,11 @@ int reflux_fine(wp_ctx *ctx, int f, double dtf, bool first, hipStream_t s)
 {
     Level &F = ctx->L[f];
     const wp_problem &P = ctx->prob;
-    if (ctx->esz == 8)
+    if (!ctx->is_acoustics)
+        launch_reflux_swe_fine(P.precision, F.faces_dev, F.nfaces, F.q[F.cur ^ 1], F.B, F.nx, F.ny, P.bc, P.g,
+                               F.ratio, dtf / F.dx, dtf / F.dy, P.order, P.limiter, P.transverse, first, F.freg_dev,
+                               s);
+    else if (ctx->esz == 8)
         launch_reflux_fine<double>(F.faces_dev, F.nfaces, (const double *)F.q[F.cur ^ 1], F.mat, F.nx, F.ny, P.bc,
                                    ctx->mtab64, F.ratio, dtf / F.dx, dtf / F.dy, P.order, P.limiter, P.transverse,
                                    first, F.freg_dev, s);
@@ -168,7 +172,11 @@ int reflux_apply(wp_ctx *ctx, int c, double dt, hipStream_t s)
 {
     Level &C = ctx->L[c], &F = ctx->L[c + 1];
     const wp_problem &P = ctx->prob;
-    if (ctx->esz == 8)
+    if (!ctx->is_acoustics)
+        launch_reflux_swe_apply(P.precision, F.fgroups_dev, F.nfgroups, F.faces_dev, F.freg_dev, C.q[C.cur ^ 1],
+                                C.q[C.cur], C.B, C.nx, C.ny, P.bc, P.g, F.ratio, dt / C.dx, dt / C.dy, P.order,
+                                P.limiter, P.transverse, s);
+    else if (ctx->esz == 8)
         launch_reflux_apply<double>(F.fgroups_dev, F.nfgroups, F.faces_dev, F.freg_dev, (const double *)C.q[C.cur ^ 1],
                                     (double *)C.q[C.cur], C.mat, C.nx, C.ny, P.bc, ctx->mtab64, F.ratio, dt / C.dx,
                                     dt / C.dy, P.order, P.limiter, P.transverse, s);
@@ -222,9 +230,9 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
         // this level's ring at its new time, read by the finer level's
         // interpolation next to the ring
         if (launch && l > 0 && (rc = fill_ring(ctx, l, (double)(sub + 1) / (double)lv.ratio, s)) != WP_OK) return rc;
-        // refluxing of the adjoint system (conservative form) at the edges
-        // between the finer level's patches and this level
-        const bool rf = ctx->reflux && ctx->equation == 1 && ctx->L[l + 1].nfaces > 0;
+        // refluxing of a conservative system (the acoustics adjoint, shallow
+        // water) at the edges between the finer level's patches and this level
+        const bool rf = ctx->reflux && (ctx->equation == 1 || !ctx->is_acoustics) && ctx->L[l + 1].nfaces > 0;
         for (int k = 0; k < r; ++k) {
             if ((rc = bo_advance(ctx, l + 1, dt / r, k, s, launch)) != WP_OK) return rc;
             if (launch && rf && (rc = reflux_fine(ctx, l + 1, dt / r, k == 0, s)) != WP_OK) return rc;

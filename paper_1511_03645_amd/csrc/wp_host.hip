@@ -1139,9 +1139,8 @@ extern "C" int wp_set_reflux(wp_ctx *ctx, int on)
 {
     if (!ctx) return WP_EINVAL;
     if (on != 0 && on != 1) return wp_fail(ctx, WP_EINVAL, "on must be 0 or 1");
-    if (on && !(ctx->is_acoustics && ctx->kind2d))
-        return wp_fail(ctx, WP_EINVAL, "refluxing is for the 2D acoustics adjoint hierarchy");
-    if (on && ctx->equation != 1)
+    if (on && !ctx->kind2d) return wp_fail(ctx, WP_EINVAL, "refluxing is for 2D hierarchies");
+    if (on && ctx->is_acoustics && ctx->equation != 1)
         return wp_fail(ctx, WP_ESTATE, "refluxing needs the adjoint system (the forward one is not conservative)");
     if (ctx->reflux != (on == 1)) {
         ctx->reflux = on == 1;

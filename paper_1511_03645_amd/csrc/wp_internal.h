@@ -211,7 +211,7 @@ template <typename T>
 void launch_average(const int *cells, long long ncells, const T *fine, int nxf, long long csf, T *coarse, int NX,
                     long long csc, int r, hipStream_t s, int nk = 3);
 
-// Refluxing of the adjoint hierarchy (conservative f-wave form): add the
+// Refluxing of the adjoint acoustics hierarchy (conservative f-wave form): add the
 // fluxes of the fine edges of every face (r per face, from the canvas the
 // fine step started from) to its register (first: start from zero); then
 // correct every coarse cell by s dt/h (F_coarse - register / r^2), the
@@ -225,5 +225,16 @@ template <typename T>
 void launch_reflux_apply(const int *groups, int ngroups, const int *faces, const double *reg, const T *coarse_old,
                          T *coarse_cur, const uint8_t *mat, int nx, int ny, const int *bc, const double *mtab64,
                          int r, double nux, double nuy, int order, int limiter, int transverse, hipStream_t s);
+// The same for the shallow-water hierarchy (csrc/reflux_swe.hip): canvases
+// of the given precision (WP_FP64, WP_MIXED: eta FP64 and the momenta FP32,
+// WP_FP32), the level's bathymetry B in FP64, every flux seen from the
+// coarse cell's side of its edge.
+void launch_reflux_swe_fine(int precision, const int *faces, int nfaces, const void *fine_old, const double *B,
+                            int nx, int ny, const int *bc, double g, int r, double nux, double nuy, int order,
+                            int limiter, int transverse, bool first, double *reg, hipStream_t s);
+void launch_reflux_swe_apply(int precision, const int *groups, int ngroups, const int *faces, const double *reg,
+                             const void *coarse_old, void *coarse_cur, const double *B, int nx, int ny, const int *bc,
+                             double g, int r, double nux, double nuy, int order, int limiter, int transverse,
+                             hipStream_t s);
 
 }  // namespace wp

@@ -40,11 +40,14 @@ def sea_state(cfg, n, B, seed):
     return q
 
 
-def build(n0, ratios, boxes, bc, precision=wp.FP64, seed=5):
+def build(n0, ratios, boxes, bc, precision=wp.FP64, seed=5, reflux=False):
     cfg = swe2d_amr(n0=n0, ratios=ratios)
     cfg["bc"] = list(bc)
-    H = amr.Hierarchy(cfg, ratios, [], B_levels=cfg["B_levels"])
+    H = amr.Hierarchy(cfg, ratios, [], B_levels=cfg["B_levels"], reflux=reflux)
     w = wp.from_config(cfg, precision=precision, num_levels=len(ratios) + 1, ratios=tuple(ratios))
+    if reflux:
+        w.set_reflux(True)
+        assert w.get_reflux() is True
     for l, B in enumerate(cfg["B_levels"]):
         w.set_bathymetry(l + 1, B)
     q0 = sea_state(cfg, n0, cfg["B"], seed)
@@ -159,3 +162,74 @@ def test_swe_refined_level_flags_match_oracle():
     boxes2 = amr.regrid_boxes(fa, H.patches[1], ratios[1], 2, *H.n[1])
     w.regrid(1, None, buffer=2)
     assert [tuple(p) for p in w.get_patches(2)] == [tuple(b) for b in boxes2]
+
+
+REFLUX_LAYOUTS = [
+    # walls all round: the water volume is conserved
+    (32, (2, 2), [[(40, 8, 20, 32), (8, 8, 16, 16)], [(88, 24, 24, 32)]], (1, 1, 1, 1)),
+    (18, (3,), [[(9, 9, 24, 18), (36, 27, 12, 21)]], (1, 1, 1, 1)),
+    (24, (4,), [[(40, 16, 36, 48), (16, 60, 24, 20)]], (1, 0, 1, 0)),
+]
+
+
+@pytest.mark.parametrize("n0,ratios,boxes,bc", REFLUX_LAYOUTS)
+def test_refluxed_swe_hierarchy_matches_oracle(n0, ratios, boxes, bc):
+    """The flux correction at coarse-fine edges of the shallow-water
+    hierarchy (wp_set_reflux) against the oracle's refluxed hierarchy, every
+    level's patches after a captured pair of coarse steps and an eager one;
+    with walls all round the composite sum of eta (the water volume less a
+    constant) stays constant to round-off."""
+    print(f"case refluxed swe amr n0={n0} ratios={ratios} bc={bc}", flush=True)
+    cfg, H, w = build(n0, ratios, boxes, bc, reflux=True)
+    for l in range(1, len(ratios) + 1):
+        nl = H.n[l][0]
+        ql = sea_state(cfg, nl, H.B[l], seed=60 + l)
+        H.set_level(l, ql)
+        w.set_state(ql, level=l)
+    dt = cfg["dt"]
+    for _ in range(2):
+        H.advance(0, dt)
+    w.advance(2, dt)
+    compare(w, H, 1e-12, "refluxed, two coarse steps")
+    # the finer levels start from states of their own, so the level-0
+    # canvas is the composite state only once the first average has run
+    s2 = float(w.get_state(level=0)[0].sum())
+    H.advance(0, dt)
+    w.advance(1, dt)
+    compare(w, H, 1e-12, "refluxed, three coarse steps")
+    if bc == (1, 1, 1, 1):
+        eta = w.get_state(level=0)[0]
+        assert abs(float(eta.sum()) - s2) <= 1e-13 * float(np.abs(eta).sum())
+
+
+@pytest.mark.parametrize("prec", [wp.FP64, wp.MIXED])
+def test_refluxed_swe_lake_at_rest_is_exact(prec):
+    n0, ratios, boxes, bc = REFLUX_LAYOUTS[0]
+    cfg = swe2d_amr(n0=n0, ratios=ratios)
+    cfg["bc"] = list(bc)
+    w = wp.from_config(cfg, precision=prec, num_levels=3, ratios=ratios)
+    w.set_reflux(True)
+    for l, B in enumerate(cfg["B_levels"]):
+        w.set_bathymetry(l + 1, B)
+    w.set_state(np.zeros((3, n0, n0)), level=0)
+    for l, b in enumerate(boxes):
+        w.regrid(l, b)
+    w.advance(2, cfg["dt"])
+    w.advance(1, cfg["dt"])
+    assert not w.get_state(level=0).any()
+    for l in (1, 2):
+        for k in range(len(w.get_patches(l))):
+            assert not w.get_state(level=l, patch=k).any(), f"level {l} patch {k} moved"
+
+
+def test_refluxed_swe_mixed_error_stated():
+    n0, ratios, boxes, bc = REFLUX_LAYOUTS[0]
+    cfg, H, w = build(n0, ratios, boxes, bc, precision=wp.MIXED, reflux=True)
+    for _ in range(4):
+        H.advance(0, cfg["dt"])
+    w.advance(4, cfg["dt"])
+    got = w.get_state(level=0)
+    errs = [np.abs(got[k] - H.q[0][k]).max() / np.abs(H.q[0][k]).max() for k in range(3)]
+    print("mixed precision refluxed SWE hierarchy, 4 coarse steps: level-0 error / max|q| (eta, hu, hv) = "
+          "%.2e %.2e %.2e" % tuple(errs))
+    assert max(errs) < 1e-4

@@ -383,13 +383,17 @@ def _swe_levels(n0=32, ratios=(2, 2)):
     return swe2d_amr(n0=n0, ratios=ratios)
 
 
-def test_swe_hierarchy_keeps_a_lake_at_rest_exactly():
+@pytest.mark.parametrize("reflux", [False, True])
+def test_swe_hierarchy_keeps_a_lake_at_rest_exactly(reflux):
     """eta = 0, hu = hv = 0 over the shelf on three levels, each with its own
     cell-integrated bathymetry: the well-balanced steps, the ring filled from
     eta (not h), the averages of eta and the regrid interpolation of eta keep
-    every level exactly at rest, bit for bit."""
+    every level exactly at rest, bit for bit; with refluxing too (the flux
+    with the hydrostatic pressure of the sea at rest taken out is zero at
+    rest, where 1/2 g h^2 would differ between a coarse cell and the ghost
+    cells beside it)."""
     cfg = _swe_levels()
-    H = amr.Hierarchy(cfg, cfg["ratios"], [], B_levels=cfg["B_levels"])
+    H = amr.Hierarchy(cfg, cfg["ratios"], [], B_levels=cfg["B_levels"], reflux=reflux)
     H.regrid(0, [(40, 8, 20, 32), (8, 8, 16, 16)])
     H.regrid(1, [(88, 24, 24, 32)])
     for l in range(3):
@@ -403,6 +407,69 @@ def test_swe_hierarchy_keeps_a_lake_at_rest_exactly():
     # the same with h interpolated instead of eta would not: eta = 0 and
     # B differing between a coarse cell and its children give h jumps
     assert np.abs(H.B[1][:, :].reshape(64, 32, 2).mean(axis=2)[::2] - H.B[0]).max() > 0.0
+
+
+def _swe_reflux_hierarchy(reflux, bc, flat, seed=5):
+    """Three levels (ratios 2, 2) of the ocean with a seeded surface and
+    currents, the finer levels interpolated at regrid; flat: a constant depth
+    of 3000 m instead of the shelf."""
+    cfg = _swe_levels()
+    cfg["bc"] = list(bc)
+    if flat:
+        cfg["B"] = np.full_like(cfg["B"], -3000.0)
+        cfg["B_levels"] = [np.full_like(b, -3000.0) for b in cfg["B_levels"]]
+    H = amr.Hierarchy(cfg, (2, 2), [], B_levels=cfg["B_levels"], reflux=reflux)
+    n = cfg["nx"]
+    r = random_state(3, n, n, seed=seed)
+    q = np.zeros((3, n, n))
+    q[0] = cfg["q0"][0] + 0.3 * r[0]
+    h = q[0] - cfg["B"]
+    q[1] = 0.05 * r[1] * h
+    q[2] = 0.05 * r[2] * h
+    H.set_level(0, q)
+    H.regrid(0, [(40, 8, 20, 32), (8, 8, 16, 16)])
+    H.regrid(1, [(88, 24, 24, 32)])
+    return H, cfg
+
+
+def _composite_drift(H, cfg, steps=3):
+    """Largest change of the composite sums (the level-0 canvas after the
+    averages) of eta, hu, hv over `steps` coarse steps after the first."""
+    H.advance(0, cfg["dt"])
+    s0 = H.q[0].sum(axis=(1, 2))
+    d = np.zeros(3)
+    for _ in range(steps):
+        H.advance(0, cfg["dt"])
+        d = np.maximum(d, np.abs(H.q[0].sum(axis=(1, 2)) - s0))
+    return d, np.abs(H.q[0]).sum(axis=(1, 2))
+
+
+def test_swe_reflux_conserves_mass_over_the_shelf():
+    """Walls all round: no water crosses the boundary, so the sum of eta
+    (the water volume less a constant) is conserved on a uniform grid; on
+    three levels over the shelf the composite keeps it to round-off only with
+    the flux correction.  Momentum is not conserved here (the bathymetry
+    source and the walls' pressure)."""
+    for reflux in (True, False):
+        H, cfg = _swe_reflux_hierarchy(reflux, [amr.BC_WALL] * 4, flat=False)
+        d, scale = _composite_drift(H, cfg)
+        if reflux:
+            assert d[0] < 1e-13 * scale[0], d
+        else:
+            assert d[0] > 1e-3 * scale[0], d
+
+
+def test_swe_reflux_conserves_mass_and_momentum_over_a_flat_bottom():
+    """Periodic boundaries and a flat bottom: eta, hu and hv are all
+    conserved on a uniform grid; on three levels the composite sums keep them
+    to round-off only with the flux correction."""
+    for reflux in (True, False):
+        H, cfg = _swe_reflux_hierarchy(reflux, [amr.BC_PERIODIC] * 4, flat=True)
+        d, scale = _composite_drift(H, cfg)
+        if reflux:
+            assert (d < 1e-14 * scale).all(), (d, scale)
+        else:
+            assert (d > 1e-4 * scale).all(), (d, scale)
 
 
 def test_swe_full_cover_fine_level_equals_uniform_fine_run():
