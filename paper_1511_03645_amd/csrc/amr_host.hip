@@ -124,7 +124,7 @@ int build_faces(wp_ctx *ctx, int f)
 {
     Level &F = ctx->L[f], &C = ctx->L[f - 1];
     F.nfaces = F.nfgroups = 0;
-    std::vector<int> flat, groups;
+    std::vector<int> &flat = ctx->rg_list[0], &groups = ctx->rg_list[1];
     reflux_faces(F.patches, F.ratio, C.nx, C.ny, flat, groups);
     if (flat.empty()) return WP_OK;
     const size_t nf = flat.size() / 4;
@@ -270,7 +270,8 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     int rc;
     // new cells outside every old patch: space interpolation from the level
     // below at its current time (each cell on its own, so in any order)
-    const std::vector<int> fresh = fresh_cells(boxes, F.patches, F.nx, F.ny);
+    std::vector<int> &fresh = ctx->rg_list[0];
+    fresh_cells(boxes, F.patches, F.nx, F.ny, fresh);
     if (!fresh.empty()) {
         long long n = 0;
         if ((rc = upload_ints(ctx, fresh, ctx->fresh_dev, n, ctx->fresh_cap, "new cell")) != WP_OK) return rc;
@@ -280,22 +281,24 @@ int install(wp_ctx *ctx, int f, const std::vector<wp_patch> &boxes)
     if ((rc = wp_upload_tiles(ctx, F)) != WP_OK) return rc;
     {
         // ratios up to 8 fill the ring by coarse parent, larger ones cell by cell
-        const std::vector<std::array<int, 3>> runs = ring_runs(F.patches, F.nx, F.ny);
+        std::vector<std::array<int, 3>> &runs = ctx->rg_runs;
+        ring_runs(F.patches, F.nx, F.ny, runs);
         F.nring = 0;
         for (const auto &u : runs) F.nring += u[2] - u[1];
-        std::vector<int> blocks, cells;
+        std::vector<int> &blocks = ctx->rg_list[0], &cells = ctx->rg_list[1];
+        blocks.clear();
+        cells.clear();
         if (F.ratio <= 8)
-            blocks = ring_block_list(runs, F.ratio, C.nx);
+            ring_block_list(runs, F.ratio, C.nx, blocks);
         else
-            cells = run_cells(runs, F.nx);
+            run_cells(runs, F.nx, cells);
         long long n = 0;
         if ((rc = upload_ints(ctx, cells, F.ring_dev, n, F.ring_cap, "ring")) != WP_OK) return rc;
         if ((rc = upload_ints(ctx, blocks, F.ringb_dev, F.nringb, F.ringb_cap, "ring block")) != WP_OK) return rc;
         F.nringb /= 3;
     }
-    if ((rc = upload_ints(ctx, cover_cells(F.patches, F.ratio, C.nx), F.cover_dev, F.ncover, F.cover_cap, "cover")) !=
-        WP_OK)
-        return rc;
+    cover_cells(F.patches, F.ratio, C.nx, ctx->rg_list[0]);
+    if ((rc = upload_ints(ctx, ctx->rg_list[0], F.cover_dev, F.ncover, F.cover_cap, "cover")) != WP_OK) return rc;
     if ((rc = build_faces(ctx, f)) != WP_OK) return rc;
     F.t = C.t;
     F.prev_valid = false;

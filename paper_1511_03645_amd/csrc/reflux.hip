@@ -212,35 +212,45 @@ __device__ void edge_flux(const View<T> &V, int dir, int ie, int je, bool right,
 // Face record: x = coarse cell (linear index on the coarse canvas), y = axis
 // | (s > 0) << 1, z, w = the first of the r fine cells beside the edge (on
 // the fine side); the fine cells run along y (axis 0) or x (axis 1).
+// G = 2^lg >= r lanes per face: lane jj of a face's group takes its fine
+// edge jj, and the group's first lane adds the r fluxes to the register in
+// edge order.
 template <typename T>
 __global__ __launch_bounds__(256) void reflux_fine_kernel(const int4 *__restrict__ faces, int nfaces, View<T> V,
-                                                          int r, double nux, double nuy, int order, int limiter,
-                                                          int transverse, int first, double *__restrict__ reg)
+                                                          int r, int lg, double nux, double nuy, int order,
+                                                          int limiter, int transverse, int first,
+                                                          double *__restrict__ reg)
 {
-    const int f = blockIdx.x * 256 + threadIdx.x;
-    if (f >= nfaces) return;
-    const int4 e = faces[f];
-    const int axis = e.y & 1;
-    const bool coarse_before = (e.y >> 1) & 1;   // the coarse cell lies before the edge
-    double acc[3];
-    for (int k = 0; k < 3; ++k) acc[k] = first ? 0.0 : reg[3 * f + k];
-    for (int jj = 0; jj < r; ++jj) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int G = 1 << lg;
+    const int f = t >> lg, jj = t & (G - 1);
+    double F[3] = {0.0, 0.0, 0.0};
+    if (f < nfaces && jj < r) {
+        const int4 e = faces[f];
+        const int axis = e.y & 1;
+        const bool coarse_before = (e.y >> 1) & 1;   // the coarse cell lies before the edge
         const int fi = e.z + (axis == 1 ? jj : 0), fj = e.w + (axis == 0 ? jj : 0);
         // the fine cell is after the edge when the coarse cell is before it
         const int ie = coarse_before ? fi : fi + (axis == 0 ? 1 : 0);
         const int je = coarse_before ? fj : fj + (axis == 1 ? 1 : 0);
-        double F[3];
         edge_flux(V, axis, ie, je, coarse_before, axis == 0 ? nux : nuy, axis == 0 ? nuy : nux, order, limiter,
                   transverse, F);
-        for (int k = 0; k < 3; ++k) acc[k] = acc[k] + F[k];
     }
-    for (int k = 0; k < 3; ++k) reg[3 * f + k] = acc[k];
+    const int base = (threadIdx.x & (WAVE - 1)) & ~(G - 1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (!first && f < nfaces && jj == 0)
+        for (int k = 0; k < 3; ++k) acc[k] = reg[3 * f + k];
+    for (int q = 0; q < r; ++q)
+        for (int k = 0; k < 3; ++k) acc[k] = acc[k] + __shfl(F[k], base + q);
+    if (f < nfaces && jj == 0)
+        for (int k = 0; k < 3; ++k) reg[3 * f + k] = acc[k];
 }
 
-// One thread per coarse cell (groups: first face, count; faces sorted by
-// cell): every face of the cell in turn, the coarse flux recomputed from the
-// canvas the coarse step started from (old), the correction added to the
-// current canvas.
+// Four lanes per coarse cell (groups: first face, count; faces sorted by
+// cell; a cell has at most one face per side): lane k recomputes the coarse
+// flux of the cell's face k from the canvas the coarse step started from
+// (old), and the first lane adds the corrections to the current canvas face
+// by face.
 template <typename T>
 __global__ __launch_bounds__(256) void reflux_apply_kernel(const int2 *__restrict__ groups, int ngroups,
                                                            const int4 *__restrict__ faces,
@@ -249,27 +259,48 @@ __global__ __launch_bounds__(256) void reflux_apply_kernel(const int2 *__restric
                                                            double dtdx, double dtdy, int order, int limiter,
                                                            int transverse)
 {
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    if (g >= ngroups) return;
-    const int2 grp = groups[g];
-    const int C = faces[grp.x].x;
-    const int I = C % old.nx, J = C / old.nx;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int g = t >> 2, k4 = t & 3;
+    int2 grp = make_int2(0, 0);
+    int I = 0, J = 0, C = 0;
+    if (g < ngroups) {
+        grp = groups[g];
+        C = faces[grp.x].x;
+        I = C % old.nx;
+        J = C / old.nx;
+    }
+    // the coarse flux through face n of the cell, as the cell sees it
+    auto coarse_flux = [&](int n, double F[3]) {
+        const int4 e = faces[n];
+        const int axis = e.y & 1;
+        const bool before = (e.y >> 1) & 1;
+        // the edge after the coarse cell when it lies before it, else the one before it
+        const int ie = before ? I + (axis == 0 ? 1 : 0) : I;
+        const int je = before ? J + (axis == 1 ? 1 : 0) : J;
+        edge_flux(old, axis, ie, je, !before, axis == 0 ? nux : nuy, axis == 0 ? nuy : nux, order, limiter,
+                  transverse, F);
+    };
+    double F[3] = {0.0, 0.0, 0.0};
+    if (g < ngroups && k4 < grp.y) coarse_flux(grp.x + k4, F);
+    const int base = (threadIdx.x & (WAVE - 1)) & ~3;
+    double Fk[4][3];
+    for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < 3; ++k) Fk[q][k] = __shfl(F[k], base + q);
+    if (g >= ngroups || k4 != 0) return;
     double q[3];
     for (int k = 0; k < 3; ++k) q[k] = (double)cur[k * old.cs + C];
     const double rr = (double)(r * r);
     for (int n = grp.x; n < grp.x + grp.y; ++n) {
         const int4 e = faces[n];
         const int axis = e.y & 1;
-        const bool before = (e.y >> 1) & 1;
-        const double sgn = before ? 1.0 : -1.0;
-        // the edge after the coarse cell when it lies before it, else the one before it
-        const int ie = before ? I + (axis == 0 ? 1 : 0) : I;
-        const int je = before ? J + (axis == 1 ? 1 : 0) : J;
-        double F[3];
-        edge_flux(old, axis, ie, je, !before, axis == 0 ? nux : nuy, axis == 0 ? nuy : nux, order, limiter,
-                  transverse, F);
+        const double sgn = ((e.y >> 1) & 1) ? 1.0 : -1.0;
+        double Fn[3];
+        if (n - grp.x < 4)
+            for (int k = 0; k < 3; ++k) Fn[k] = Fk[n - grp.x][k];
+        else
+            coarse_flux(n, Fn);
         const double h = axis == 0 ? dtdx : dtdy;
-        for (int k = 0; k < 3; ++k) q[k] += sgn * h * (F[k] - reg[3 * n + k] / rr);
+        for (int k = 0; k < 3; ++k) q[k] += sgn * h * (Fn[k] - reg[3 * n + k] / rr);
     }
     for (int k = 0; k < 3; ++k) cur[k * old.cs + C] = (T)q[k];
 }
@@ -297,8 +328,12 @@ void launch_reflux_fine(const int *faces, int nfaces, const T *fine_old, const u
 {
     if (nfaces <= 0) return;
     const View<T> V = make_view(fine_old, mat, nx, ny, bc, mtab64);
-    hipLaunchKernelGGL((reflux_fine_kernel<T>), dim3((nfaces + 255) / 256), dim3(256), 0, s, (const int4 *)faces,
-                       nfaces, V, r, nux, nuy, order, limiter, transverse, first ? 1 : 0, reg);
+    int lg = 0;
+    while ((1 << lg) < r) ++lg;
+    const long long threads = (long long)nfaces << lg;
+    hipLaunchKernelGGL((reflux_fine_kernel<T>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                       (const int4 *)faces, nfaces, V, r, lg, nux, nuy, order, limiter, transverse, first ? 1 : 0,
+                       reg);
 }
 
 template <typename T>
@@ -308,7 +343,8 @@ void launch_reflux_apply(const int *groups, int ngroups, const int *faces, const
 {
     if (ngroups <= 0) return;
     const View<T> V = make_view(coarse_old, mat, nx, ny, bc, mtab64);
-    hipLaunchKernelGGL((reflux_apply_kernel<T>), dim3((ngroups + 255) / 256), dim3(256), 0, s, (const int2 *)groups,
+    hipLaunchKernelGGL((reflux_apply_kernel<T>), dim3((unsigned)((4LL * ngroups + 255) / 256)), dim3(256), 0, s,
+                       (const int2 *)groups,
                        ngroups, (const int4 *)faces, reg, V, coarse_cur, r, nux, nuy, nux, nuy, order, limiter,
                        transverse);
 }

@@ -243,38 +243,139 @@ __device__ void sw_edge_flux(const SweView<E, T> &V, int dir, int ie, int je, bo
     for (int k = 0; k < 3; ++k) F[k] = right ? (f[k] - e.ap[k]) + F[k] : (f[k] + e.am[k]) + F[k];
 }
 
+// The flux of sw_edge_flux formed by the eight lanes base .. base + 7 of a
+// wave together, every one of them with the same edge: each solves one edge
+// of its stencil (part 0 the edge itself, 1 and 2 its neighbours along the
+// normal for the limiter, 3 .. 6 the transverse edges, which they also
+// split along dir), and part 0 gathers the rest and forms F in the order of
+// sw_edge_flux.  Every lane of the wave calls it (it shuffles); on = false
+// for lanes without an edge.  F is set on part 0 only.
+template <typename E, typename T>
+__device__ void sw_edge_flux8(const SweView<E, T> &V, bool on, int part, int dir, int ie, int je, bool right,
+                              double nu, double nut, int order, int limiter, int transverse, double F[3])
+{
+    const int di = dir == 0 ? 1 : 0, dj = dir == 0 ? 0 : 1;   // along the normal
+    const int tdir = 1 - dir;
+    const int ti = dir == 0 ? 0 : 1, tj = dir == 0 ? 1 : 0;   // across the normal
+    // this lane's edge of the stencil
+    int edir = dir, ei = ie, ej = je;
+    int side = 0, c = 0;
+    if (part == 1) {
+        ei = ie - di;
+        ej = je - dj;
+    } else if (part == 2) {
+        ei = ie + di;
+        ej = je + dj;
+    } else if (part >= 3) {
+        const int q = part - 3, outer = q >> 1, inner = q & 1;
+        side = dir == 0 ? outer : inner;
+        c = dir == 0 ? inner : outer;
+        const int ci = ie - (c == 0 ? di : 0), cj = je - (c == 0 ? dj : 0);
+        edir = tdir;
+        ei = ci + side * ti;
+        ej = cj + side * tj;
+    }
+    const bool need = on && part <= 6 && (part == 0 || (part <= 2 ? order >= 2 : transverse != 0));
+    Edge e;
+    double pay[9];
+    for (int k = 0; k < 9; ++k) pay[k] = 0.0;
+    if (need) {
+        e = sw_edge(V, edir, ei, ej);
+        if (part == 1 || part == 2) {
+            for (int p = 0; p < 3; ++p)
+                for (int k = 0; k < 3; ++k) pay[3 * p + k] = e.w[p][k];
+        } else if (part >= 3) {
+            // side 0: the transverse edge below / left of the cell (its
+            // A^+dQ lives in the cell); side 1: above / right (A^-dQ); the
+            // cell before the edge gives its up-going part, the cell after
+            // it its down-going part
+            double bm[3], bp[3];
+            sw_tsplit(dir, side == 0 ? e.ap : e.am, e.roe, bm, bp);
+            for (int k = 0; k < 3; ++k) pay[k] = c == 0 ? bp[k] : bm[k];
+        }
+    }
+    const int base = (threadIdx.x & (WAVE - 1)) & ~7;
+    double wl[9], wr[9], tp[4][3];
+    for (int k = 0; k < 9; ++k) {
+        wl[k] = __shfl(pay[k], base + 1);
+        wr[k] = __shfl(pay[k], base + 2);
+    }
+    for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < 3; ++k) tp[q][k] = __shfl(pay[k], base + 3 + q);
+    if (!on || part != 0) return;
+    for (int k = 0; k < 3; ++k) F[k] = 0.0;
+    if (order >= 2) {
+        for (int p = 0; p < 3; ++p) {
+            const double *wu = e.s[p] > 0.0 ? wl + 3 * p : wr + 3 * p;
+            const double phi = sw_limiter(e.w[p], wu, limiter);
+            const double as = fabs(e.s[p]);
+            const double coef = e.s[p] > 0.0 ? 1.0 : (e.s[p] < 0.0 ? -1.0 : 0.0);
+            for (int k = 0; k < 3; ++k) F[k] += 0.5 * coef * (1.0 - nu * as) * (phi * e.w[p][k]);
+        }
+    }
+    if (transverse)
+        for (int q = 0; q < 4; ++q)
+            for (int k = 0; k < 3; ++k) F[k] -= 0.5 * nut * tp[q][k];
+    double qc[3], B;
+    sw_cell(V, right ? ie : ie - di, right ? je : je - dj, qc, B);
+    const int n = dir == 0 ? 1 : 2, t = dir == 0 ? 2 : 1;
+    const double h = qc[0] - B;
+    double f[3];
+    f[0] = qc[n];
+    f[n] = qc[n] * (qc[n] / h) + 0.5 * V.g * qc[0] * (qc[0] - 2.0 * B);
+    f[t] = qc[n] * (qc[t] / h);
+    for (int k = 0; k < 3; ++k) F[k] = right ? (f[k] - e.ap[k]) + F[k] : (f[k] + e.am[k]) + F[k];
+}
+
 // Face records as for the adjoint (x = coarse cell, y = axis | (coarse cell
 // before the edge) << 1, z, w = the first of the r fine cells beside the
-// edge on the fine side): the r fine edges of every face, seen from their
-// ghost cells on the coarse side, added to its register.
-template <typename E, typename T>
+// edge on the fine side).  Each fine edge takes P lanes (8: its stencil's
+// solves on lanes of their own, for r up to 8; 1: one lane), the G = 2^lg
+// >= r edges of a face consecutive; the edges are seen from their ghost cells
+// on the coarse side, and the face's first lane adds their r fluxes to its
+// register in edge order.
+template <typename E, typename T, int P>
 __global__ __launch_bounds__(256) void reflux_swe_fine_kernel(const int4 *__restrict__ faces, int nfaces,
-                                                              SweView<E, T> V, int r, double nux, double nuy,
+                                                              SweView<E, T> V, int r, int lg, double nux, double nuy,
                                                               int order, int limiter, int transverse, int first,
                                                               double *__restrict__ reg)
 {
-    const int f = blockIdx.x * 256 + threadIdx.x;
-    if (f >= nfaces) return;
-    const int4 e = faces[f];
-    const int axis = e.y & 1;
-    const bool coarse_before = (e.y >> 1) & 1;
-    double acc[3];
-    for (int k = 0; k < 3; ++k) acc[k] = first ? 0.0 : reg[3 * f + k];
-    for (int jj = 0; jj < r; ++jj) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int G = 1 << lg;
+    const int part = t % P, slot = t / P;
+    const int f = slot >> lg, jj = slot & (G - 1);
+    const bool on = f < nfaces && jj < r;
+    int axis = 0, ie = 0, je = 0;
+    bool coarse_before = false;
+    if (on) {
+        const int4 e = faces[f];
+        axis = e.y & 1;
+        coarse_before = (e.y >> 1) & 1;
         const int fi = e.z + (axis == 1 ? jj : 0), fj = e.w + (axis == 0 ? jj : 0);
-        const int ie = coarse_before ? fi : fi + (axis == 0 ? 1 : 0);
-        const int je = coarse_before ? fj : fj + (axis == 1 ? 1 : 0);
-        double F[3];
-        sw_edge_flux(V, axis, ie, je, !coarse_before, axis == 0 ? nux : nuy, axis == 0 ? nuy : nux, order, limiter,
-                     transverse, F);
-        for (int k = 0; k < 3; ++k) acc[k] = acc[k] + F[k];
+        ie = coarse_before ? fi : fi + (axis == 0 ? 1 : 0);
+        je = coarse_before ? fj : fj + (axis == 1 ? 1 : 0);
     }
-    for (int k = 0; k < 3; ++k) reg[3 * f + k] = acc[k];
+    double F[3] = {0.0, 0.0, 0.0};
+    const double nu = axis == 0 ? nux : nuy, nut = axis == 0 ? nuy : nux;
+    if constexpr (P == 8)
+        sw_edge_flux8(V, on, part, axis, ie, je, !coarse_before, nu, nut, order, limiter, transverse, F);
+    else if (on)
+        sw_edge_flux(V, axis, ie, je, !coarse_before, nu, nut, order, limiter, transverse, F);
+    const int base = (threadIdx.x & (WAVE - 1)) & ~(G * P - 1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool lead = f < nfaces && jj == 0 && part == 0;
+    if (!first && lead)
+        for (int k = 0; k < 3; ++k) acc[k] = reg[3 * f + k];
+    for (int q = 0; q < r; ++q)
+        for (int k = 0; k < 3; ++k) acc[k] = acc[k] + __shfl(F[k], base + q * P);
+    if (lead)
+        for (int k = 0; k < 3; ++k) reg[3 * f + k] = acc[k];
 }
 
-// One thread per coarse cell: each of its faces in turn, the coarse flux
-// recomputed from the canvas the coarse step started from, the correction
-// added to the current canvas.
+// Four faces per coarse cell (a cell has at most one face per side), eight
+// lanes per face: the lanes of face k recompute its coarse flux from the
+// canvas the coarse step started from, and the cell's first lane adds the
+// corrections to the current canvas face by face.
 template <typename E, typename T>
 __global__ __launch_bounds__(256) void reflux_swe_apply_kernel(const int2 *__restrict__ groups, int ngroups,
                                                                const int4 *__restrict__ faces,
@@ -284,25 +385,55 @@ __global__ __launch_bounds__(256) void reflux_swe_apply_kernel(const int2 *__res
                                                                double dtdx, double dtdy, int order, int limiter,
                                                                int transverse)
 {
-    const int g = blockIdx.x * 256 + threadIdx.x;
-    if (g >= ngroups) return;
-    const int2 grp = groups[g];
-    const int C = faces[grp.x].x;
-    const int I = C % old.nx, J = C / old.nx;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int part = t & 7, g = t >> 5, k4 = (t >> 3) & 3;
+    int2 grp = make_int2(0, 0);
+    int I = 0, J = 0, C = 0;
+    if (g < ngroups) {
+        grp = groups[g];
+        C = faces[grp.x].x;
+        I = C % old.nx;
+        J = C / old.nx;
+    }
+    // the coarse edge of face n of the cell, as the cell sees it
+    auto coarse_edge = [&](int n, int &axis, int &ie, int &je, bool &right) {
+        const int4 e = faces[n];
+        axis = e.y & 1;
+        const bool before = (e.y >> 1) & 1;
+        ie = before ? I + (axis == 0 ? 1 : 0) : I;
+        je = before ? J + (axis == 1 ? 1 : 0) : J;
+        right = !before;
+    };
+    const bool on = g < ngroups && k4 < grp.y;
+    int axis = 0, ie = 0, je = 0;
+    bool right = false;
+    if (on) coarse_edge(grp.x + k4, axis, ie, je, right);
+    double F[3] = {0.0, 0.0, 0.0};
+    sw_edge_flux8(old, on, part, axis, ie, je, right, axis == 0 ? nux : nuy, axis == 0 ? nuy : nux, order, limiter,
+                  transverse, F);
+    const int base = (threadIdx.x & (WAVE - 1)) & ~31;
+    double Fk[4][3];
+    for (int q = 0; q < 4; ++q)
+        for (int k = 0; k < 3; ++k) Fk[q][k] = __shfl(F[k], base + 8 * q);
+    if (g >= ngroups || k4 != 0 || part != 0) return;
     double q[3] = {(double)eta[C], (double)hu[C], (double)hv[C]};
     const double rr = (double)(r * r);
     for (int n = grp.x; n < grp.x + grp.y; ++n) {
         const int4 e = faces[n];
-        const int axis = e.y & 1;
-        const bool before = (e.y >> 1) & 1;
-        const double sgn = before ? 1.0 : -1.0;
-        const int ie = before ? I + (axis == 0 ? 1 : 0) : I;
-        const int je = before ? J + (axis == 1 ? 1 : 0) : J;
-        double F[3];
-        sw_edge_flux(old, axis, ie, je, !before, axis == 0 ? nux : nuy, axis == 0 ? nuy : nux, order, limiter,
-                     transverse, F);
-        const double h = axis == 0 ? dtdx : dtdy;
-        for (int k = 0; k < 3; ++k) q[k] += sgn * h * (F[k] - reg[3 * n + k] / rr);
+        const int ax = e.y & 1;
+        const double sgn = ((e.y >> 1) & 1) ? 1.0 : -1.0;
+        double Fn[3];
+        if (n - grp.x < 4) {
+            for (int k = 0; k < 3; ++k) Fn[k] = Fk[n - grp.x][k];
+        } else {
+            int a2, i2, j2;
+            bool r2;
+            coarse_edge(n, a2, i2, j2, r2);
+            sw_edge_flux(old, a2, i2, j2, r2, a2 == 0 ? nux : nuy, a2 == 0 ? nuy : nux, order, limiter, transverse,
+                         Fn);
+        }
+        const double h = ax == 0 ? dtdx : dtdy;
+        for (int k = 0; k < 3; ++k) q[k] += sgn * h * (Fn[k] - reg[3 * n + k] / rr);
     }
     eta[C] = (E)q[0];
     hu[C] = (T)q[1];
@@ -331,8 +462,20 @@ void fine_launch(const int *faces, int nfaces, const void *q, const double *B, i
                  double *reg, hipStream_t s)
 {
     const SweView<E, T> V = make_swe_view<E, T>(q, B, nx, ny, bc, g);
-    hipLaunchKernelGGL((reflux_swe_fine_kernel<E, T>), dim3((nfaces + 255) / 256), dim3(256), 0, s,
-                       (const int4 *)faces, nfaces, V, r, nux, nuy, order, limiter, transverse, first ? 1 : 0, reg);
+    int lg = 0;
+    while ((1 << lg) < r) ++lg;
+    // eight lanes per edge while a face's edges fit in one wave
+    if (r <= 8) {
+        const long long threads = ((long long)nfaces << lg) * 8;
+        hipLaunchKernelGGL((reflux_swe_fine_kernel<E, T, 8>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                           s, (const int4 *)faces, nfaces, V, r, lg, nux, nuy, order, limiter, transverse,
+                           first ? 1 : 0, reg);
+    } else {
+        const long long threads = (long long)nfaces << lg;
+        hipLaunchKernelGGL((reflux_swe_fine_kernel<E, T, 1>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                           s, (const int4 *)faces, nfaces, V, r, lg, nux, nuy, order, limiter, transverse,
+                           first ? 1 : 0, reg);
+    }
 }
 
 template <typename E, typename T>
@@ -344,7 +487,8 @@ void apply_launch(const int *groups, int ngroups, const int *faces, const double
     const long long cells = (long long)nx * ny;
     E *eta = (E *)q_cur;
     T *hu = (T *)((char *)q_cur + cells * sizeof(E));
-    hipLaunchKernelGGL((reflux_swe_apply_kernel<E, T>), dim3((ngroups + 255) / 256), dim3(256), 0, s,
+    hipLaunchKernelGGL((reflux_swe_apply_kernel<E, T>), dim3((unsigned)((32LL * ngroups + 255) / 256)), dim3(256),
+                       0, s,
                        (const int2 *)groups, ngroups, (const int4 *)faces, reg, V, eta, hu, hu + cells, r, nux, nuy,
                        nux, nuy, order, limiter, transverse);
 }

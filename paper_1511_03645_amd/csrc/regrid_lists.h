@@ -3,8 +3,10 @@
 // cells under a level's patches, the coarse-fine faces of refluxing), built
 // from per-row column intervals of the patches rather than from masks of the
 // level: the work grows with the patches' rows and perimeters, not with the
-// level's area.  Host code only (no HIP), so it also builds with a plain C++
-// compiler.
+// level's area.  The lists are written into the caller's vectors and the
+// temporaries are kept per thread, so a caller that keeps its vectors
+// between regrids allocates nothing once they have grown.  Host code only
+// (no HIP), so it also builds with a plain C++ compiler.
 #pragma once
 
 #include <algorithm>
@@ -50,33 +52,38 @@ struct Spans {
     }
 };
 
-// Rectangles with no cells are skipped.
-inline Spans make_spans(const std::vector<Rect> &R)
+// The union of R into s (its blocks reused); rectangles with no cells are
+// skipped.
+inline void make_spans(const std::vector<Rect> &R, Spans &s)
 {
-    Spans s;
+    s.j0 = 0;
+    s.nrows = 0;
+    s.off.assign(1, 0);
+    s.iv.clear();
     int lo = INT_MAX, hi = INT_MIN;
     for (const Rect &r : R)
         if (r.i0 < r.i1 && r.j0 < r.j1) {
             lo = std::min(lo, r.j0);
             hi = std::max(hi, r.j1);
         }
-    if (lo >= hi) return s;
+    if (lo >= hi) return;
     s.j0 = lo;
     s.nrows = hi - lo;
     // bucket the rectangles' row intervals by row (counting sort), then sort
     // and merge each row's
-    std::vector<int> start((size_t)s.nrows + 1, 0);
+    static thread_local std::vector<int> start, pos;
+    static thread_local std::vector<std::pair<int, int>> raw;
+    start.assign((size_t)s.nrows + 1, 0);
     for (const Rect &r : R)
         if (r.i0 < r.i1 && r.j0 < r.j1)
             for (int j = r.j0; j < r.j1; ++j) ++start[j - lo + 1];
     for (int k = 0; k < s.nrows; ++k) start[k + 1] += start[k];
-    std::vector<std::pair<int, int>> raw((size_t)start[s.nrows]);
-    std::vector<int> pos(start.begin(), start.end() - 1);
+    raw.resize((size_t)start[s.nrows]);
+    pos.assign(start.begin(), start.end() - 1);
     for (const Rect &r : R)
         if (r.i0 < r.i1 && r.j0 < r.j1)
             for (int j = r.j0; j < r.j1; ++j) raw[pos[j - lo]++] = {r.i0, r.i1};
     s.off.assign((size_t)s.nrows + 1, 0);
-    s.iv.reserve(raw.size());
     for (int k = 0; k < s.nrows; ++k) {
         auto a = raw.begin() + start[k], b = raw.begin() + start[k + 1];
         std::sort(a, b);
@@ -88,7 +95,6 @@ inline Spans make_spans(const std::vector<Rect> &R)
         }
         s.off[k + 1] = (int)s.iv.size();
     }
-    return s;
 }
 
 // Call emit(a, b) for each maximal run [a, b) of row j that lies in A and
@@ -111,48 +117,56 @@ template <class F> void row_difference(const Spans &A, const Spans &B, int j, F 
     }
 }
 
-inline std::vector<Rect> patch_rects(const std::vector<wp_patch> &P, int grow, int nx, int ny)
+// The patches grown by `grow` cells and clipped to nx x ny.
+inline void patch_rects(const std::vector<wp_patch> &P, int grow, int nx, int ny, std::vector<Rect> &R)
 {
-    std::vector<Rect> R;
-    R.reserve(P.size());
+    R.clear();
     for (const wp_patch &p : P)
         R.push_back(Rect{std::max(p.ilo - grow, 0), std::max(p.jlo - grow, 0), std::min(p.ilo + p.nx + grow, nx),
                          std::min(p.jlo + p.ny + grow, ny)});
-    return R;
+}
+
+// Union of the patches grown by `grow`, clipped, into s.
+inline void patch_spans(const std::vector<wp_patch> &P, int grow, int nx, int ny, Spans &s)
+{
+    static thread_local std::vector<Rect> R;
+    patch_rects(P, grow, nx, ny, R);
+    make_spans(R, s);
 }
 
 // The ghost ring of a level's patches: cells inside the level's nx x ny
 // domain, within two cells (either direction, corners included) of a patch
 // and inside none, as runs (j, a, b) of cells [a, b) of row j, in increasing
 // j * nx + a.
-inline std::vector<std::array<int, 3>> ring_runs(const std::vector<wp_patch> &P, int nx, int ny)
+inline void ring_runs(const std::vector<wp_patch> &P, int nx, int ny, std::vector<std::array<int, 3>> &out)
 {
-    const Spans halo = make_spans(patch_rects(P, 2, nx, ny)), in = make_spans(patch_rects(P, 0, nx, ny));
-    std::vector<std::array<int, 3>> out;
+    static thread_local Spans halo, in;
+    patch_spans(P, 2, nx, ny, halo);
+    patch_spans(P, 0, nx, ny, in);
+    out.clear();
     for (int j = halo.j0; j < halo.j0 + halo.nrows; ++j)
         row_difference(halo, in, j, [&](int a, int b) { out.push_back({j, a, b}); });
-    return out;
 }
 // The cells of runs (j, a, b) as linear indices j * nx + i, in run order.
-inline std::vector<int> run_cells(const std::vector<std::array<int, 3>> &runs, int nx)
+inline void run_cells(const std::vector<std::array<int, 3>> &runs, int nx, std::vector<int> &out)
 {
     size_t n = 0;
     for (const auto &u : runs) n += (size_t)(u[2] - u[1]);
-    std::vector<int> out(n);
+    out.resize(n);
     size_t k = 0;
     for (const auto &u : runs)
         for (int i = u[1]; i < u[2]; ++i) out[k++] = u[0] * nx + i;
-    return out;
 }
 
 // The ring grouped by the cell of the level below (ratio r, NX wide) that
 // contains its cells: for each such cell in increasing linear index, (its
 // index, the low and high 32 bits of the mask of its fine cells in the ring,
 // bit (i % r) + r (j % r)).  Needs r <= 8.
-inline std::vector<int> ring_block_list(const std::vector<std::array<int, 3>> &runs, int r, int NX)
+inline void ring_block_list(const std::vector<std::array<int, 3>> &runs, int r, int NX, std::vector<int> &out)
 {
-    std::vector<int> out;
-    std::vector<unsigned long long> acc((size_t)NX, 0);
+    out.clear();
+    static thread_local std::vector<unsigned long long> acc;
+    acc.assign((size_t)NX, 0);
     for (size_t k = 0; k < runs.size();) {
         // the runs of the r fine rows of one coarse row are contiguous
         const int J = runs[k][0] / r;
@@ -174,37 +188,37 @@ inline std::vector<int> ring_block_list(const std::vector<std::array<int, 3>> &r
                 acc[I] = 0;
             }
     }
-    return out;
 }
 
 // Coarse cells (linear indices on a canvas NX wide, increasing) covered by
 // ratio-aligned, non-overlapping fine patches.
-inline Spans cover_spans(const std::vector<wp_patch> &P, int r)
+inline void cover_cells(const std::vector<wp_patch> &P, int r, int NX, std::vector<int> &out)
 {
-    std::vector<Rect> R;
-    R.reserve(P.size());
+    static thread_local std::vector<Rect> R;
+    static thread_local Spans s;
+    static thread_local std::vector<std::array<int, 3>> runs;
+    R.clear();
     for (const wp_patch &p : P) R.push_back(Rect{p.ilo / r, p.jlo / r, (p.ilo + p.nx) / r, (p.jlo + p.ny) / r});
-    return make_spans(R);
-}
-inline std::vector<int> cover_cells(const std::vector<wp_patch> &P, int r, int NX)
-{
-    const Spans s = cover_spans(P, r);
-    std::vector<std::array<int, 3>> runs;
+    make_spans(R, s);
+    runs.clear();
     for (int j = s.j0; j < s.j0 + s.nrows; ++j)
         for (const std::pair<int, int> *a = s.row_begin(j); a != s.row_end(j); ++a) runs.push_back({j, a->first, a->second});
-    return run_cells(runs, NX);
+    run_cells(runs, NX, out);
 }
 
 // Cells of the new patches `boxes` outside every old patch (linear indices
 // on a level nx wide, increasing).
-inline std::vector<int> fresh_cells(const std::vector<wp_patch> &boxes, const std::vector<wp_patch> &old, int nx,
-                                    int ny)
+inline void fresh_cells(const std::vector<wp_patch> &boxes, const std::vector<wp_patch> &old, int nx, int ny,
+                        std::vector<int> &out)
 {
-    const Spans nw = make_spans(patch_rects(boxes, 0, nx, ny)), od = make_spans(patch_rects(old, 0, nx, ny));
-    std::vector<std::array<int, 3>> runs;
+    static thread_local Spans nw, od;
+    static thread_local std::vector<std::array<int, 3>> runs;
+    patch_spans(boxes, 0, nx, ny, nw);
+    patch_spans(old, 0, nx, ny, od);
+    runs.clear();
     for (int j = nw.j0; j < nw.j0 + nw.nrows; ++j)
         row_difference(nw, od, j, [&](int a, int b) { runs.push_back({j, a, b}); });
-    return run_cells(runs, nx);
+    run_cells(runs, nx, out);
 }
 
 // The coarse-fine faces of refluxing between ratio-r patches P and the cells
@@ -230,15 +244,18 @@ inline void reflux_faces(const std::vector<wp_patch> &P, int r, int NX, int NY, 
         wj1 = std::max(wj1, (p.jlo + p.ny) / r);
     }
     const int ww = wi1 - wi0;
-    std::vector<uint8_t> cov((size_t)ww * (wj1 - wj0), 0);
+    static thread_local std::vector<uint8_t> cov;
+    cov.assign((size_t)ww * (wj1 - wj0), 0);
     for (const wp_patch &p : P)
         for (int J = p.jlo / r; J < (p.jlo + p.ny) / r; ++J)
             std::fill_n(&cov[(size_t)(J - wj0) * ww + (p.ilo / r - wi0)], p.nx / r, (uint8_t)1);
     auto covered = [&](int I, int J) {
         return I >= wi0 && I < wi1 && J >= wj0 && J < wj1 && cov[(size_t)(J - wj0) * ww + (I - wi0)];
     };
-    std::vector<std::array<int, 4>> faces;
-    faces.reserve(P.size() * 8);
+    static thread_local std::vector<std::array<int, 4>> faces, sorted;
+    static thread_local std::vector<unsigned long long> key;
+    static thread_local std::vector<int> start, pos;
+    faces.clear();
     auto add = [&](int I, int J, int axis, bool before, int fi, int fj) {
         if (I < 0 || J < 0 || I >= NX || J >= NY || covered(I, J)) return;
         faces.push_back({J * NX + I, axis | (before ? 2 : 0), fi, fj});
@@ -262,15 +279,15 @@ inline void reflux_faces(const std::vector<wp_patch> &P, int r, int NX, int NY, 
         jlo = std::min(jlo, f[0] / NX);
         jhi = std::max(jhi, f[0] / NX);
     }
-    std::vector<int> start((size_t)(jhi - jlo) + 2, 0);
+    start.assign((size_t)(jhi - jlo) + 2, 0);
     for (const auto &f : faces) ++start[f[0] / NX - jlo + 1];
     for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
-    std::vector<unsigned long long> key(faces.size());
-    std::vector<int> pos(start.begin(), start.end() - 1);
+    key.resize(faces.size());
+    pos.assign(start.begin(), start.end() - 1);
     for (size_t k = 0; k < faces.size(); ++k)
         key[pos[faces[k][0] / NX - jlo]++] = ((unsigned long long)(faces[k][0] % NX) << 32) | k;
     for (size_t k = 0; k + 1 < start.size(); ++k) std::sort(key.begin() + start[k], key.begin() + start[k + 1]);
-    std::vector<std::array<int, 4>> sorted(faces.size());
+    sorted.resize(faces.size());
     for (size_t k = 0; k < key.size(); ++k) sorted[k] = faces[key[k] & 0xffffffffULL];
     flat.resize(4 * sorted.size());
     for (size_t k = 0; k < sorted.size(); ++k) {

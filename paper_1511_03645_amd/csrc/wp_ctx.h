@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <array>
 #include <vector>
 
 #include "wp_internal.h"
@@ -124,6 +125,9 @@ struct wp_ctx {
     // host images of a regrid (flag rows, window flags, nesting mask,
     // buffered flags), kept between regrids
     std::vector<uint8_t> rg_rows, rg_flags, rg_allowed, rg_dil;
+    // the lists a regrid builds and uploads (one at a time), kept likewise
+    std::vector<int> rg_list[2];
+    std::vector<std::array<int, 3>> rg_runs;
     std::string err;
     int equation = 0;                    // system the level hierarchy's steps solve: 0 forward, 1 adjoint
     bool reflux = false;                 // flux correction at coarse-fine edges (adjoint system only)

@@ -33,11 +33,18 @@ int main()
     while (std::scanf("%d %d %d %d %d", &nx, &ny, &r, &NX, &NY) == 5) {
         std::vector<wp_patch> P, Q;
         if (!get(P) || !get(Q)) return 1;
-        const auto runs = wp::ring_runs(P, nx, ny);
-        put(wp::run_cells(runs, nx));
-        put(r <= 8 ? wp::ring_block_list(runs, r, NX) : std::vector<int>());
-        put(wp::cover_cells(P, r, NX));
-        put(wp::fresh_cells(P, Q, nx, ny));
+        std::vector<std::array<int, 3>> runs;
+        std::vector<int> v;
+        wp::ring_runs(P, nx, ny, runs);
+        wp::run_cells(runs, nx, v);
+        put(v);
+        v.clear();
+        if (r <= 8) wp::ring_block_list(runs, r, NX, v);
+        put(v);
+        wp::cover_cells(P, r, NX, v);
+        put(v);
+        wp::fresh_cells(P, Q, nx, ny, v);
+        put(v);
         std::vector<int> flat, groups;
         wp::reflux_faces(P, r, NX, NY, flat, groups);
         put(flat);
