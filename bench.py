@@ -446,7 +446,8 @@ def flagging_compare(n0=256, ratios=(4, 4), regrid_every=2, buffer=3):
         # host time per regrid cycle (two regrids and two coarse steps): the
         # flag copies include waiting for the steps queued before them
         per_cycle = {k: round(ht[k] / cyc, 4)
-                     for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "h2d_ms", "capture_ms")}
+                     for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "h2d_ms", "tiles_ms",
+                               "capture_ms")}
         return {"seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref), "cell_updates": ups,
                 "mean_cells_level1": fine_cells[0] / cyc, "mean_cells_level2": fine_cells[1] / cyc,
                 "per_cycle_host_ms": per_cycle, "captures": int(ht["captures"]),
@@ -559,7 +560,8 @@ def swe_flagging_compare(n0=256, ratios=(4, 2), regrid_every=2, buffer=2):
         res = {"flag": mode, "tol": tol, "reflux": reflux, "seconds": sec, "J_rel_err": abs(J - J_ref) / abs(J_ref),
                "mean_cells_level1": cells[0] / cyc, "mean_cells_level2": cells[1] / cyc,
                "per_cycle_host_ms": {k: round(ht[k] / cyc, 4)
-                                     for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "h2d_ms", "capture_ms")},
+                                     for k in ("flag_copy_ms", "cluster_ms", "upload_ms", "h2d_ms", "tiles_ms",
+                               "capture_ms")},
                "captures": int(ht["captures"]), "graph_updates": int(ht["graph_updates"])}
         if record:
             # the gauge every regrid cycle against the reference at the same times

@@ -425,8 +425,9 @@ int wp_set_time(wp_ctx *ctx, int level, double t);
  * graphs); ms[4] the number of captures and ms[5] how many of them updated
  * the existing graph in place instead of instantiating a new one; ms[6] the
  * part of ms[2] spent in host-to-device copies of the tables (staging, copy,
- * wait).  The first min(n, 7) entries are written (the rest of n zeroed);
- * reset = 1 clears the counters afterwards. */
+ * wait); ms[7] the time spent rebuilding tile tables (their copies
+ * included), most of it within ms[2].  The first min(n, 8) entries are
+ * written (the rest of n zeroed); reset = 1 clears the counters afterwards. */
 int wp_host_times(wp_ctx *ctx, double *ms, int n, int reset);
 
 /* Wait for all work of the handle and report latched device conditions. */

@@ -518,11 +518,12 @@ class WavePatch:
 
     def host_times(self, reset=False):
         """wp_host_times: dict of cumulative host milliseconds (flag copy,
-        clustering, table rebuild and upload, capture, and the upload's
-        host-to-device copies) and capture counts."""
-        v = (_D * 7)()
-        self._check(lib().wp_host_times(self.h, v, 7, int(reset)))
-        keys = ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms", "captures", "graph_updates", "h2d_ms")
+        clustering, table rebuild and upload, capture, the upload's
+        host-to-device copies, tile-table rebuilds) and capture counts."""
+        v = (_D * 8)()
+        self._check(lib().wp_host_times(self.h, v, 8, int(reset)))
+        keys = ("flag_copy_ms", "cluster_ms", "upload_ms", "capture_ms", "captures", "graph_updates", "h2d_ms",
+                "tiles_ms")
         return dict(zip(keys, list(v)))
 
     def sync(self):

@@ -10,7 +10,7 @@
 constexpr int RED_BLOCKS = 1024;
 
 // slots of wp_ctx::host_ms (wp_host_times)
-enum { HT_FLAG_COPY = 0, HT_CLUSTER, HT_UPLOAD, HT_CAPTURE, HT_NCAPTURE, HT_NUPDATE, HT_H2D, WP_HOST_TIMES };
+enum { HT_FLAG_COPY = 0, HT_CLUSTER, HT_UPLOAD, HT_CAPTURE, HT_NCAPTURE, HT_NUPDATE, HT_H2D, HT_TILES, WP_HOST_TIMES };
 
 // milliseconds since an arbitrary origin (steady clock)
 double wp_now_ms();

@@ -257,7 +257,9 @@ static int upload_tiles(wp_ctx *ctx, Level &lv);
 
 int wp_upload_tiles(wp_ctx *ctx, Level &lv)
 {
+    ctx->host_ms[HT_TILES] -= wp_now_ms();
     const int rc = upload_tiles(ctx, lv);
+    ctx->host_ms[HT_TILES] += wp_now_ms();
     lv.tables_ok = rc == WP_OK;
     if (rc != WP_OK) lv.ntiles = lv.nftiles = lv.nptiles = lv.nuni = lv.npuni = 0;
     return rc;
