@@ -148,10 +148,11 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
 // stamp (optional): workgroup b writes its start and end on the device's
 // constant-rate clock to stamp[2b] and stamp[2b + 1] (one slot each, no
 // contention), from which the launch's own duration is read back.
-// DUAL (unrolled heights only): a tile may carry a second narrow tile for
-// lanes 32..63.  A cell's update reads two lanes either side, so the two
-// halves, each with its own two halo lanes, never see each other's outputs;
-// rows, columns and the output range become per-lane.
+// DUAL (unrolled heights only): a tile may carry a second tile for the lanes
+// after its own (its columns and two halo lanes either side).  A cell's
+// update reads two lanes either side, so the two tiles, each with its own
+// halo lanes, never see each other's outputs; rows, columns and the output
+// range become per-lane.
 template <typename T, bool ADJ, bool FULL, int RT, int KIND, bool DUAL>
 __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int parity,
@@ -165,12 +166,13 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
     const AcouInst<T> *__restrict__ Ip = insts + tl.inst;
     int lane = threadIdx.x;
     if constexpr (DUAL) {
-        if (tl.nib > 0 && lane >= WAVE / 2) {
+        const int split = tl.ni + 4;   // the first lane of the second tile
+        if (tl.nib > 0 && lane >= split) {
             tl.i0 = tl.i0b;
             tl.j0 = tl.j0b;
             tl.ni = tl.nib;
             tl.nj = tl.njb;
-            lane -= WAVE / 2;
+            lane -= split;
         }
     }
     MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);

@@ -221,33 +221,49 @@ bool wp_pair_ready(const wp_ctx *ctx, const Level &lv)
     return ctx->pair_rows != 0 && lv.ptiles_dev && lv.nptiles > 0;
 }
 
-// Narrow tiles (at most HALF_STRIP wide) of the same material and march
-// direction share a wave two by two, one in each half; true if any did.
+// Tiles of the same material and march direction share a wave two by two
+// when their columns fit side by side (at most TWO_TILE_COLS together); true
+// if any did.
 static bool pair_narrow(std::vector<Tile> &t)
 {
+    // per (material, direction), widest first: each tile is paired with the
+    // narrowest one left if that fits beside it; a pair takes the place of
+    // its wider tile in the list
+    std::map<std::pair<int, int>, std::vector<size_t>> groups;
+    for (size_t k = 0; k < t.size(); ++k)
+        if (t[k].ni < TWO_TILE_COLS) groups[std::make_pair(t[k].mat, t[k].down)].push_back(k);
+    std::vector<long long> partner(t.size(), -1);   // index of the tile riding with k, or -2 if k rides
+    bool any = false;
+    for (auto &g : groups) {
+        std::vector<size_t> &v = g.second;
+        std::stable_sort(v.begin(), v.end(), [&](size_t a, size_t b) { return t[a].ni > t[b].ni; });
+        size_t lo = 0, hi = v.size();
+        while (lo + 1 < hi) {
+            if (t[v[lo]].ni + t[v[hi - 1]].ni <= TWO_TILE_COLS) {
+                const size_t a = std::min(v[lo], v[hi - 1]), b = std::max(v[lo], v[hi - 1]);
+                // the wider of the two takes the lower lanes
+                const bool wide_first = t[a].ni >= t[b].ni;
+                partner[wide_first ? a : b] = (long long)(wide_first ? b : a);
+                partner[wide_first ? b : a] = -2;
+                --hi;
+                any = true;
+            }
+            ++lo;
+        }
+    }
     std::vector<Tile> out;
     out.reserve(t.size());
-    std::map<std::pair<int, int>, size_t> open;   // (mat, down) -> narrow tile waiting for a partner
-    bool any = false;
-    for (const Tile &x : t) {
-        if (x.ni > HALF_STRIP) {
-            out.push_back(x);
-            continue;
+    for (size_t k = 0; k < t.size(); ++k) {
+        if (partner[k] == -2) continue;
+        Tile x = t[k];
+        if (partner[k] >= 0) {
+            const Tile &y = t[(size_t)partner[k]];
+            x.i0b = y.i0;
+            x.j0b = y.j0;
+            x.nib = y.ni;
+            x.njb = y.nj;
         }
-        const auto key = std::make_pair(x.mat, x.down);
-        const auto it = open.find(key);
-        if (it == open.end()) {
-            open[key] = out.size();
-            out.push_back(x);
-            continue;
-        }
-        Tile &a = out[it->second];
-        a.i0b = x.i0;
-        a.j0b = x.j0;
-        a.nib = x.ni;
-        a.njb = x.nj;
-        open.erase(it);
-        any = true;
+        out.push_back(x);
     }
     t.swap(out);
     return any;

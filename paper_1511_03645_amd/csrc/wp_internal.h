@@ -28,13 +28,15 @@ struct Tile {
     int down;  // 2D acoustics: march the rows downwards (alternates between
                // vertically adjacent tiles, so the halo rows they share are
                // read by both at about the same time)
-    // a second narrow tile (nib > 0) in the upper half of the wave (one-step
-    // 2D acoustics): lanes 32..63 take (i0b, j0b, nib, njb), lanes 0..31 the
-    // first; same instance, material and direction
+    // a second tile (nib > 0) in the upper lanes of the wave (one-step 2D
+    // acoustics): lanes 0 .. ni + 3 take the first, with its two halo
+    // columns either side, lanes ni + 4 .. 63 (i0b, j0b, nib, njb); same
+    // instance, material and direction, ni + nib <= TWO_TILE_COLS
     int i0b = 0, j0b = 0, nib = 0, njb = 0;
 };
-// widest tile of a half wave: 32 lanes less a two-column halo on each side
-constexpr int HALF_STRIP = WAVE / 2 - 4;
+// output columns two tiles of one wave may have together: 64 lanes less a
+// two-column halo either side of each
+constexpr int TWO_TILE_COLS = WAVE - 8;
 
 // Per-instance description of a 2D (or 1D) acoustics level canvas.  The
 // canvas covers the whole domain at the level's resolution with no ghost
