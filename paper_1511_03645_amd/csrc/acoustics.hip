@@ -29,11 +29,16 @@ using namespace march;
 // A tile flagged `down` is marched from its top row downwards: that is the
 // upward march of the problem reflected in y (rows taken in reverse order, v
 // negated on load and on store), which the method treats identically.
-template <typename T, bool ADJ, bool UNI, int RT, typename LD>
+// AVG: each result row also goes to LDS (avb: [4 rows][3 components][64
+// lanes]); when a block of four rows is complete, the first lane of every
+// four output lanes sums its 4 x 4 block row by row and writes the mean onto
+// the cell of the level below (tiles start on rows and columns of multiples
+// of 4, so a block lies in one tile).
+template <typename T, bool ADJ, bool UNI, int RT, bool AVG, typename LD>
 __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &tl, int nx, T nux, T nuy,
                                            unsigned csb, unsigned out_off0, bool out_lane,
                                            __amdgpu_buffer_rsrc_t qw, __amdgpu_buffer_rsrc_t sw, bool snap,
-                                           const LD &ld, int &bad)
+                                           const LD &ld, int &bad, const AvgTo<T> &avg, T *avb, int col)
 {
     constexpr int NR = RT + 4;
     constexpr int FIRST = 3 + PREFETCH < NR ? 3 + PREFETCH : NR;   // rows requested before the march
@@ -73,6 +78,32 @@ __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &
             bstore(sw, off, 2u * csb, vn);
         }
         bad |= keep & !(isfinite(pn) & isfinite(un) & isfinite(vn));
+        if constexpr (AVG) {
+            // row t of the tile; a block is complete at its last row in
+            // marching order (the same for both tiles of a wave: same
+            // direction, rows starting on multiples of 4)
+            const int t = j - j0;
+            const int lane = threadIdx.x;
+            avb[((t & 3) * 3 + 0) * WAVE + lane] = pn;
+            avb[((t & 3) * 3 + 1) * WAVE + lane] = un;
+            avb[((t & 3) * 3 + 2) * WAVE + lane] = vn;
+            if ((t & 3) == (down ? 0 : 3)) {
+                __syncthreads();
+                const int b0 = t & ~3;   // first row of the block
+                const bool lead = out_lane && ((col - tl.i0) & 3) == 0 && b0 < tl.nj;
+                if (lead) {
+                    const T inv = T(1) / T(16);
+                    const long long c = (long long)((j0 + b0) >> 2) * avg.nx + (col >> 2);
+                    for (int k = 0; k < 3; ++k) {
+                        T sum = T(0);
+                        for (int jj = 0; jj < 4; ++jj)
+                            for (int ii = 0; ii < 4; ++ii) sum += avb[(jj * 3 + k) * WAVE + lane + ii];
+                        avg.q[k * avg.cs + c] = sum * inv;
+                    }
+                }
+                __syncthreads();
+            }
+        }
     }
 }
 
@@ -80,11 +111,12 @@ __device__ __forceinline__ void march_tile(const Media<T, UNI> &md, const Tile &
 // above (full method: second order, MC limiter, transverse terms).  RT = 0
 // (runtime height, any options): a rolling window of rows prefetched two
 // rows ahead.
-template <typename T, bool ADJ, bool UNI, bool FULL, int RT>
+template <typename T, bool ADJ, bool UNI, bool FULL, int RT, bool AVG = false>
 __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt, const Tile &tl, int lane, int nx,
                                       int ny, int bc2, int bc3, int cx, T sx, unsigned csb, T nux, T nuy,
                                       __amdgpu_buffer_rsrc_t qr, __amdgpu_buffer_rsrc_t qw,
-                                      __amdgpu_buffer_rsrc_t mr, __amdgpu_buffer_rsrc_t sw, bool snap, int &bad)
+                                      __amdgpu_buffer_rsrc_t mr, __amdgpu_buffer_rsrc_t sw, bool snap, int &bad,
+                                      const AvgTo<T> &avg = AvgTo<T>{nullptr, 0, 0}, T *avb = nullptr)
 {
     const bool out_lane = lane >= 2 && lane < 2 + tl.ni;
     const unsigned out_off0 = (unsigned)(tl.i0 - 2 + lane) * (unsigned)sizeof(T);
@@ -103,7 +135,8 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
         r.m = UNI ? 0 : (int)__builtin_amdgcn_raw_buffer_load_b8(mr, idx, 0, 0);
     };
     if constexpr (RT > 0) {
-        march_tile<T, ADJ, UNI, RT>(md, tl, nx, nux, nuy, csb, out_off0, out_lane, qw, sw, snap, ld, bad);
+        march_tile<T, ADJ, UNI, RT, AVG>(md, tl, nx, nux, nuy, csb, out_off0, out_lane, qw, sw, snap, ld, bad, avg,
+                                         avb, tl.i0 - 2 + lane);
     } else {
         // FULL: second order, MC limiter and transverse terms fixed at compile time
         const bool second = FULL ? true : op_rt.second;
@@ -153,13 +186,17 @@ __device__ __forceinline__ void march(const Media<T, UNI> &md, const Opts &op_rt
 // update reads two lanes either side, so the two tiles, each with its own
 // halo lanes, never see each other's outputs; rows, columns and the output
 // range become per-lane.
-template <typename T, bool ADJ, bool FULL, int RT, int KIND, bool DUAL>
+// AVG (with DUAL, heights 4, 8, 16): also the means of the results' 4 x 4
+// blocks onto the level below (see march_tile), through LDS after the
+// material tables.
+template <typename T, bool ADJ, bool FULL, int RT, int KIND, bool DUAL, bool AVG = false>
 __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restrict__ insts,
                                                       const Tile *__restrict__ tiles, int parity,
                                                       int snap_index, int *__restrict__ status,
-                                                      unsigned long long *__restrict__ stamp)
+                                                      unsigned long long *__restrict__ stamp, AvgTo<T> avg)
 {
     static_assert(!DUAL || RT > 0, "two tiles per wave need the unrolled march");
+    static_assert(!AVG || (RT > 0 && RT % 4 == 0 && acou_mixed_rows(RT) % 4 == 0), "averaging needs rows of 4");
     if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x] = (unsigned long long)wall_clock64();
     extern __shared__ __align__(16) unsigned char smem[];
     Tile tl = tiles[blockIdx.x];
@@ -177,6 +214,9 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
     }
     MCon<T> *mc = reinterpret_cast<MCon<T> *>(smem);
     T *pt = reinterpret_cast<T *>(smem + sizeof(MCon<T>) * MAXMAT);
+    // the averaging rows after the tables (acou_smem's size, 16-aligned)
+    T *avb = reinterpret_cast<T *>(
+        smem + ((sizeof(MCon<T>) * MAXMAT + sizeof(T) * 3 * (size_t)Ip->nmat * Ip->nmat + 15) & ~(size_t)15));
     build_tables(*Ip, mc, pt, threadIdx.x);
     __syncthreads();
 
@@ -201,13 +241,13 @@ __global__ __launch_bounds__(WAVE) void acou2d_kernel(const AcouInst<T> *__restr
         // one material: folded constants, wave-uniform, kept in SGPRs
         Media<T, true> md;
         md.u = make_unicon<T, ADJ>(mc[tl.mat], pt[(tl.mat * Ip->nmat + tl.mat) * 3], nux, nuy);
-        march<T, ADJ, true, FULL, RT>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw, snap,
-                                      bad);
+        march<T, ADJ, true, FULL, RT, AVG>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr, qw, mr, sw,
+                                           snap, bad, avg, avb);
     } else if (KIND != 1) {
         // mixed tiles are acou_mixed_rows(RT) high
         Media<T, false> md{mc, pt, Ip->nmat};
-        march<T, ADJ, false, FULL, acou_mixed_rows(RT)>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy, qr,
-                                                        qw, mr, sw, snap, bad);
+        march<T, ADJ, false, FULL, acou_mixed_rows(RT), AVG>(md, op, tl, lane, nx, ny, bc2, bc3, cx, sx, csb, nux, nuy,
+                                                             qr, qw, mr, sw, snap, bad, avg, avb);
     }
     if (__any(bad) && threadIdx.x == 0) atomicOr(status, ST_NONFINITE);
     if (stamp && threadIdx.x == 0) stamp[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
@@ -294,16 +334,34 @@ static size_t acou_smem(int nmat)
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint, int nmat_max,
                    bool full, int rows, int kind, int snap_index, int *status, hipStream_t s, unsigned long long *stamp,
-                   bool dual)
+                   bool dual, const AvgTo<T> *avg)
 {
     if (ntiles <= 0) return;
     const size_t sm = acou_smem<T>(nmat_max);
     const dim3 g(ntiles), b(WAVE);
+    const AvgTo<T> none{nullptr, 0, 0};
+    if (avg && acou2d_can_average(dual, full, rows, 4) && !adjoint) {
+        // the averaging rows after the tables, 16-aligned
+        const size_t sma = ((sm + 15) & ~(size_t)15) + sizeof(T) * 12 * WAVE;
+#define WP_AVG(RT, KIND)                                                                                       \
+    hipLaunchKernelGGL((acou2d_kernel<T, false, true, RT, KIND, true, true>), g, b, sma, s, insts, tiles, parity, \
+                       snap_index, status, stamp, *avg)
+#define WP_AVG_RT(KIND)                 \
+    switch (rows) {                     \
+    case 4: WP_AVG(4, KIND); break;     \
+    case 8: WP_AVG(8, KIND); break;     \
+    default: WP_AVG(16, KIND); break;   \
+    }
+        if (kind == 1) { WP_AVG_RT(1) } else { WP_AVG_RT(0) }
+#undef WP_AVG_RT
+#undef WP_AVG
+        return;
+    }
     if (dual) {
         // forward steps of refined levels with narrow patches, unrolled heights
 #define WP_DUAL(RT, KIND)                                                                                     \
     hipLaunchKernelGGL((acou2d_kernel<T, false, true, RT, KIND, true>), g, b, sm, s, insts, tiles, parity, \
-                       snap_index, status, stamp)
+                       snap_index, status, stamp, none)
 #define WP_DUAL_RT(KIND)                      \
     switch (rows) {                           \
     case 4: WP_DUAL(4, KIND); break;          \
@@ -319,7 +377,7 @@ void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int 
     }
 #define WP_LAUNCH(ADJ, FULL, RT, KIND)                                                                       \
     hipLaunchKernelGGL((acou2d_kernel<T, ADJ, FULL, RT, KIND, false>), g, b, sm, s, insts, tiles, parity, snap_index, \
-                       status, stamp)
+                       status, stamp, none)
     // tile heights 4, 6, 8, 12 and 16 have a compile-time march; any other
     // height takes the runtime march
 #define WP_BY_RT(ADJ, KIND)                              \
@@ -355,9 +413,9 @@ void launch_acou1d(const AcouInst<T> *inst_dev, const AcouInst<T> &h, int parity
 }
 
 template void launch_acou2d<double>(const AcouInst<double> *, const Tile *, int, int, int, int, bool, int, int,
-                                    int, int *, hipStream_t, unsigned long long *, bool);
+                                    int, int *, hipStream_t, unsigned long long *, bool, const AvgTo<double> *);
 template void launch_acou2d<float>(const AcouInst<float> *, const Tile *, int, int, int, int, bool, int, int,
-                                   int, int *, hipStream_t, unsigned long long *, bool);
+                                   int, int *, hipStream_t, unsigned long long *, bool, const AvgTo<float> *);
 template void launch_acou1d<double>(const AcouInst<double> *, const AcouInst<double> &, int, int, int, int *,
                                     hipStream_t);
 template void launch_acou1d<float>(const AcouInst<float> *, const AcouInst<float> &, int, int, int, int *,

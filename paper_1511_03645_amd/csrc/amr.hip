@@ -181,28 +181,29 @@ __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ ce
     // multiplies exactly as it divides
     const bool pow2 = (r & (r - 1)) == 0;
     const T inv = T(1) / T(r * r);
-    for (long long n = blockIdx.x * 256LL + threadIdx.x; n < ncells; n += (long long)gridDim.x * 256) {
+    // one thread per (component, coarse cell), component-major
+    for (long long w = blockIdx.x * 256LL + threadIdx.x; w < nk * ncells; w += (long long)gridDim.x * 256) {
+        const int k = (int)(w / ncells);
+        const long long n = w - (long long)k * ncells;
         const int lin = cells[n];
         const int ic = lin % NX, jc = lin / NX;
-        for (int k = 0; k < nk; ++k) {
-            T s = T(0);
-            if (r == 4) {
-                // each row of four children in one aligned vector load, summed
-                // in the same order
-                typedef T T4 __attribute__((ext_vector_type(4)));
-                for (int jj = 0; jj < 4; ++jj) {
-                    const T4 q = *reinterpret_cast<const T4 *>(fine + k * csf + (long long)(4 * jc + jj) * nxf + 4 * ic);
-                    s += q.x;
-                    s += q.y;
-                    s += q.z;
-                    s += q.w;
-                }
-            } else {
-                for (int jj = 0; jj < r; ++jj)
-                    for (int ii = 0; ii < r; ++ii) s += fine[k * csf + (long long)(r * jc + jj) * nxf + (r * ic + ii)];
+        T s = T(0);
+        if (r == 4) {
+            // each row of four children in one aligned vector load, summed
+            // in the same order
+            typedef T T4 __attribute__((ext_vector_type(4)));
+            for (int jj = 0; jj < 4; ++jj) {
+                const T4 q = *reinterpret_cast<const T4 *>(fine + k * csf + (long long)(4 * jc + jj) * nxf + 4 * ic);
+                s += q.x;
+                s += q.y;
+                s += q.z;
+                s += q.w;
             }
-            coarse[k * csc + lin] = pow2 ? s * inv : s / T(r * r);
+        } else {
+            for (int jj = 0; jj < r; ++jj)
+                for (int ii = 0; ii < r; ++ii) s += fine[k * csf + (long long)(r * jc + jj) * nxf + (r * ic + ii)];
         }
+        coarse[k * csc + lin] = pow2 ? s * inv : s / T(r * r);
     }
 }
 
@@ -238,8 +239,8 @@ void launch_average(const int *cells, long long ncells, const T *fine, int nxf, 
                     long long csc, int r, hipStream_t s, int nk)
 {
     if (ncells <= 0) return;
-    hipLaunchKernelGGL((average_kernel<T>), dim3(grid_for(ncells)), dim3(256), 0, s, cells, ncells, fine, nxf, csf,
-                       coarse, NX, csc, r, nk);
+    hipLaunchKernelGGL((average_kernel<T>), dim3(grid_for((long long)nk * ncells)), dim3(256), 0, s, cells, ncells,
+                       fine, nxf, csf, coarse, NX, csc, r, nk);
 }
 
 template void launch_ring_fill<double>(const int *, long long, double *, int, const double *, const double *, int,

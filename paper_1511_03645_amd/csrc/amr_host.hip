@@ -233,11 +233,21 @@ int bo_advance(wp_ctx *ctx, int l, double dt, int sub, hipStream_t s, bool launc
         // refluxing of a conservative system (the acoustics adjoint, shallow
         // water) at the edges between the finer level's patches and this level
         const bool rf = ctx->reflux && (ctx->equation == 1 || !ctx->is_acoustics) && ctx->L[l + 1].nfaces > 0;
+        // a finer level without children of its own averages its last
+        // substep's results onto this level in the step itself, where the
+        // launch can (acou2d_can_average)
+        Level &G = ctx->L[l + 1];
+        const bool g_leaf = l + 2 >= (int)ctx->L.size() || ctx->L[l + 2].patches.empty();
+        G.averaged = false;
         for (int k = 0; k < r; ++k) {
-            if ((rc = bo_advance(ctx, l + 1, dt / r, k, s, launch)) != WP_OK) return rc;
+            G.avg_onto = launch && g_leaf && k == r - 1 ? &lv : nullptr;
+            rc = bo_advance(ctx, l + 1, dt / r, k, s, launch);
+            G.avg_onto = nullptr;
+            if (rc != WP_OK) return rc;
             if (launch && rf && (rc = reflux_fine(ctx, l + 1, dt / r, k == 0, s)) != WP_OK) return rc;
         }
-        if (launch && (rc = average_down(ctx, l + 1, s)) != WP_OK) return rc;
+        if (launch && !G.averaged && (rc = average_down(ctx, l + 1, s)) != WP_OK) return rc;
+        G.averaged = false;
         if (launch && rf && (rc = reflux_apply(ctx, l, dt, s)) != WP_OK) return rc;
     }
     return WP_OK;

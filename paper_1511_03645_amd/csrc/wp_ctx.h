@@ -74,6 +74,10 @@ struct Level {
     int nfaces = 0, nfgroups = 0;
     size_t faces_cap = 0, fgroups_cap = 0, freg_cap = 0;
     double *B = nullptr;                 // shallow water: bathymetry cell averages of this level (FP64)
+    // set for one step: average the step's results onto this level (the
+    // level below, see launch_acou2d); averaged: the step did
+    Level *avg_onto = nullptr;
+    bool averaged = false;
     // false after a tile-table rebuild failed (its tables are empty): steps
     // and flags of the level fail with WP_ESTATE until a rebuild succeeds
     bool tables_ok = true;

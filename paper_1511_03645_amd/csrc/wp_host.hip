@@ -897,8 +897,18 @@ static int acou_step(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t
         // one launch: a single-material level runs the lean kernel, any other
         // the kernel that picks the path per tile
         if (lv.dual && adjoint) return wp_fail(ctx, WP_ESTATE, "adjoint step on a level with two tiles per wave");
+        // the average onto the level below, when asked and the launch can
+        AvgTo<T> avg{nullptr, 0, 0};
+        lv.averaged = false;
+        if (lv.avg_onto && !adjoint && acou2d_can_average(lv.dual, full, lv.tile_rows, lv.ratio)) {
+            avg = AvgTo<T>{(T *)lv.avg_onto->q[lv.avg_onto->cur], lv.avg_onto->nx,
+                           (long long)lv.avg_onto->nx * lv.avg_onto->ny};
+            lv.averaged = true;
+        }
+        lv.avg_onto = nullptr;
         launch_acou2d<T>(I, lv.tiles_dev, lv.ntiles, lv.cur, adjoint, ctx->nmat, full, lv.tile_rows,
-                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream, ctx->stamp_next, lv.dual);
+                         lv.nuni == lv.ntiles ? 1 : 0, snap_index, ctx->status, stream, ctx->stamp_next, lv.dual,
+                         lv.averaged ? &avg : nullptr);
         ctx->stamp_next = nullptr;   // consumed by this launch only
     }
     else

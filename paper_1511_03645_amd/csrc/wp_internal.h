@@ -106,11 +106,30 @@ __device__ __forceinline__ unsigned long long *count_slot(unsigned long long *c)
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_CFL = 2;
 
-// dual: some tiles hold a second half-wave tile (forward, unrolled heights)
+// The level below a refined level of ratio 4 (its current canvas: three
+// planes of cs elements, rows nx long), which a step can average its results
+// onto (see launch_acou2d).
+template <typename T>
+struct AvgTo {
+    T *q;
+    int nx;
+    long long cs;
+};
+
+// dual: some tiles hold a second tile in the wave's upper lanes (forward,
+// unrolled heights).  avg (dual, rows 4, 8 or 16, a level of ratio 4 whose
+// tiles start on rows and columns of multiples of 4): also write the mean of
+// each 4 x 4 block of the results onto the cell of the level below that
+// contains it, summed row by row as launch_average sums.
 template <typename T>
 void launch_acou2d(const AcouInst<T> *insts, const Tile *tiles, int ntiles, int parity, int adjoint,
                    int nmat_max, bool full, int rows, int kind, int snap_index, int *status, hipStream_t s,
-                   unsigned long long *stamp = nullptr, bool dual = false);
+                   unsigned long long *stamp = nullptr, bool dual = false, const AvgTo<T> *avg = nullptr);
+// whether launch_acou2d can average a step of a level with these settings
+inline bool acou2d_can_average(bool dual, bool full, int rows, int ratio)
+{
+    return dual && full && ratio == 4 && (rows == 4 || rows == 8 || rows == 16);
+}
 // Two steps per launch on a single-level canvas (tiles PAIR_STRIP wide,
 // 4..64 rows high: 8, 10 and 12 unrolled, others rolled; no periodic
 // boundary); q^{n+2} lands in
