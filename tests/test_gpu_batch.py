@@ -114,3 +114,46 @@ def test_batch_two_step_launches_equal_single_instances():
         assert ws.num_snapshots() == wb.num_snapshots() == 6
         for n in range(6):
             assert np.array_equal(ws.get_snapshot(n), wb.get_snapshot(n)), f"instance {k} snapshot {n}"
+
+
+@pytest.mark.timeout(600)
+def test_batch_full_size_workload():
+    """The 64-instance workload at full size in the benchmark's launch
+    configuration (seed 4, sides 128..1024, 256 adjoint steps with a snapshot
+    every 8, then 256 forward steps, all instances in one launch per step):
+    every instance's J against a single-instance FP64 run to 1e-12, and the
+    three smallest instances and the median one against the oracle (final
+    state, last snapshot, J; the oracle takes minutes on the largest)."""
+    cfgs = acoustics2d_batch(count=64, seed=4)
+    S, every = cfgs[0]["nsteps"], cfgs[0]["snap_every"]
+    assert (len(cfgs), S, every) == (64, 256, 8)
+    print("case batch full size: 64 instances, 256 + 256 steps", flush=True)
+    ws = [wp.from_config(c, precision=wp.FP64) for c in cfgs]
+    b = wp.Batch(ws, [c["dt"] for c in cfgs])
+    b.adjoint_run([c["functional"] for c in cfgs], S, every)
+    for w, c in zip(ws, cfgs):
+        w.set_state(c["q0"])
+    b.step(S)
+    Jb = [w.functional_value(c["functional"], 0) for w, c in zip(ws, cfgs)]
+    for k, c in enumerate(cfgs):
+        v = wp.from_config(c, precision=wp.FP64)
+        v.set_state(c["q0"])
+        v.run_graph(S, c["dt"], 1)
+        Js = v.functional_value(c["functional"], 0)
+        scale = float(np.abs(c["q0"]).max()) * c["dx"] * c["dy"] * c["nx"] * c["ny"]
+        assert abs(Jb[k] - Js) <= 1e-12 * max(abs(Js), 1e-12 * scale), (k, Jb[k], Js)
+    order = sorted(range(len(cfgs)), key=lambda k: cfgs[k]["nx"] * cfgs[k]["ny"])
+    oracle.set_threads(16)
+    for k in order[:3] + [order[len(order) // 2]]:
+        c = cfgs[k]
+        print(f"case batch full size vs oracle: instance {k} ({c['nx']}^2)", flush=True)
+        ref, _, _ = oracle.run(c, "acoustics_fwd", c["q0"], S)
+        got = ws[k].get_state()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), f"instance {k} state"
+        snaps, _ = oracle.adjoint_run(c, nsteps=S, snap_every=every)
+        last = len(snaps) - 1
+        assert ws[k].num_snapshots() == len(snaps)
+        s = ws[k].get_snapshot(last)
+        assert np.abs(s - snaps[last]).max() <= 1e-12 * np.abs(snaps[last]).max(), f"instance {k} snapshot"
+        Jo = oracle.functional(c, ref)
+        assert abs(Jb[k] - Jo) <= 1e-12 * max(abs(Jo), 1e-300), (k, Jb[k], Jo)
