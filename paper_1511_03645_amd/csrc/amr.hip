@@ -3,6 +3,8 @@
 // interpolated in space (minmod-limited linear slopes per direction, the
 // physical boundary by the boundary rule) and in time (linear between the two
 // coarse times), and fine-to-coarse averaging of covered coarse cells.
+#include <climits>
+
 #include "wp_internal.h"
 
 namespace wp {
@@ -172,6 +174,82 @@ __global__ __launch_bounds__(256) void ring_block_kernel(const int *__restrict__
     }
 }
 
+// ring_block_kernel for ratio 4, with the same arithmetic: the component is
+// blockIdx.y (no index division), parents away from the physical boundary
+// load their five-point stencils directly, and the child offsets are
+// compile-time constants, which keeps the kernel short and its register
+// count low.
+template <typename T>
+__global__ __launch_bounds__(256) void ring_block4_kernel(const int *__restrict__ blocks, int nblocks,
+                                                          T *__restrict__ fine, int nxf, const T *__restrict__ cold,
+                                                          const T *__restrict__ cnew, int NX, int NY, T alpha,
+                                                          int bc0, int bc1, int bc2, int bc3, int k0,
+                                                          T *__restrict__ fine2, T alpha2)
+{
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= nblocks) return;
+    const int k = blockIdx.y, kc = k0 + k;
+    const long long csf = (long long)nxf * (NY * 4);
+    const long long csc = (long long)NX * NY;
+    const int lin = blocks[3 * n];
+    const unsigned mask = (unsigned)blocks[3 * n + 1];
+    const int jc = lin / NX, ic = lin - jc * NX;
+    T c0[2], sx[2], sy[2];
+    if (ic > 0 && ic < NX - 1 && jc > 0 && jc < NY - 1) {
+        for (int t = 0; t < 2; ++t) {
+            const T *C = (t == 0 ? cold : cnew) + k * csc + (long long)jc * NX + ic;
+            c0[t] = C[0];
+            sx[t] = minmod(C[1] - c0[t], c0[t] - C[-1]);
+            sy[t] = minmod(C[NX] - c0[t], c0[t] - C[-NX]);
+        }
+    } else {
+        const int bc[4] = {bc0, bc1, bc2, bc3};
+        for (int t = 0; t < 2; ++t) {
+            const T *C = t == 0 ? cold : cnew;
+            c0[t] = C[k * csc + (long long)jc * NX + ic];
+            sx[t] = minmod(cval(C, k, kc, ic + 1, jc, NX, NY, bc, csc) - c0[t],
+                           c0[t] - cval(C, k, kc, ic - 1, jc, NX, NY, bc, csc));
+            sy[t] = minmod(cval(C, k, kc, ic, jc + 1, NX, NY, bc, csc) - c0[t],
+                           c0[t] - cval(C, k, kc, ic, jc - 1, NX, NY, bc, csc));
+        }
+    }
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    for (int o = 0; o < (fine2 ? 2 : 1); ++o) {
+        T *__restrict__ out = o ? fine2 : fine;
+        const T al = o ? alpha2 : alpha;
+        auto child = [&](int ii, int jj) {
+            const T xi = (T(ii) + T(0.5)) * T(0.25) - T(0.5);
+            const T eta = (T(jj) + T(0.5)) * T(0.25) - T(0.5);
+            const T a = (c0[0] + xi * sx[0]) + eta * sy[0];
+            const T v = (c0[1] + xi * sx[1]) + eta * sy[1];
+            return (T(1) - al) * a + al * v;
+        };
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const unsigned rm = mask >> (4 * jj) & 0xfu;
+            if (!rm) continue;
+            // aligned: the fine row length and the component stride are
+            // multiples of 4 elements, the canvas 256-byte aligned
+            T *dst = out + k * csf + (long long)(jc * 4 + jj) * nxf + (long long)ic * 4;
+            if (rm == 0xfu) {
+                // a full row of four children (a patch's lower or upper edge)
+                *reinterpret_cast<T4 *>(dst) = T4{child(0, jj), child(1, jj), child(2, jj), child(3, jj)};
+            } else if (rm == 0x3u) {
+                // the two children beside a patch's left edge
+                *reinterpret_cast<T2 *>(dst) = T2{child(0, jj), child(1, jj)};
+            } else if (rm == 0xcu) {
+                // ... or beside its right edge
+                *reinterpret_cast<T2 *>(dst + 2) = T2{child(2, jj), child(3, jj)};
+            } else {
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii)
+                    if (rm >> ii & 1u) dst[ii] = child(ii, jj);
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void average_kernel(const int *__restrict__ cells, long long ncells,
                                                       const T *__restrict__ fine, int nxf, long long csf,
@@ -230,6 +308,12 @@ void launch_ring_fill_blocks(const int *blocks, long long nblocks, T *fine, int 
                              T *fine2, double alpha2)
 {
     if (nblocks <= 0) return;
+    if (r == 4 && nblocks <= INT_MAX - 255) {
+        hipLaunchKernelGGL((ring_block4_kernel<T>), dim3((unsigned)((nblocks + 255) / 256), (unsigned)nk), dim3(256), 0,
+                           s, blocks, (int)nblocks, fine, nxf, cold, cnew, NX, NY, (T)alpha, bc[0], bc[1], bc[2],
+                           bc[3], k0, fine2, (T)alpha2);
+        return;
+    }
     hipLaunchKernelGGL((ring_block_kernel<T>), dim3(grid_for(nk * nblocks)), dim3(256), 0, s, blocks, nblocks, fine,
                        nxf, cold, cnew, NX, NY, r, (T)alpha, bc[0], bc[1], bc[2], bc[3], k0, nk, fine2, (T)alpha2);
 }
