@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped cleanly where no GPU is present, rather than failing
-    # on import; on a GPU machine they run and must find the native library.
+    # on import; on a machine with a GPU they run and must find the native library.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
