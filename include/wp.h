@@ -41,6 +41,10 @@
  *     WP_ENONFINITE by the next call that synchronises (wp_sync, wp_get_state,
  *     wp_functional_value, ...).  Such a step has already been applied.
  *   - A handle must not be used from two threads at once.
+ *   - No C++ exception leaves a call: a host allocation that fails inside a
+ *     call returns WP_ENOMEM (with its message in wp_last_error); after such
+ *     a failure the handle's state is unspecified apart from wp_last_error
+ *     and wp_destroy.
  */
 #ifndef WP_H
 #define WP_H
@@ -57,7 +61,7 @@ extern "C" {
 typedef enum {
     WP_OK = 0,
     WP_EINVAL = -1,      /* invalid argument or unsupported combination */
-    WP_ENOMEM = -2,      /* device allocation failed */
+    WP_ENOMEM = -2,      /* device or host allocation failed */
     WP_EDEVICE = -3,     /* a HIP runtime call failed */
     WP_ECFL = -4,        /* Courant number above problem.cfl_max */
     WP_ENONFINITE = -5,  /* NaN or Inf produced */
@@ -156,9 +160,11 @@ typedef struct wp_ctx wp_ctx;
 /* Create a solver instance: validates the arguments, uploads the
  * coefficients, allocates one state canvas pair per level and sets level 0
  * to a single patch covering the domain (finer levels start empty).
- * stream: a hipStream_t (NULL: the null stream).  On failure *out is NULL;
- * WP_EINVAL among others for a level-0 grid of fewer than 4 cells on a side
- * (nx0; also ny0 in 2D). */
+ * stream: a hipStream_t (NULL: the null stream).  On failure *out is NULL
+ * if out, problem, coef or grid is NULL; otherwise it holds a handle whose
+ * wp_last_error() says what failed and which the caller releases with
+ * wp_destroy.  WP_EINVAL among others for a level-0 grid of fewer than 4
+ * cells on a side (nx0; also ny0 in 2D). */
 int wp_create(const wp_problem *problem, const wp_coefficients *coef, const wp_grid *grid,
               const wp_allocator *alloc, void *stream, wp_ctx **out);
 void wp_destroy(wp_ctx *ctx);

@@ -216,11 +216,11 @@ def cluster(flags, allowed=None, efficiency=0.7, maxside=16, minside=2):
     args = (f.ctypes.data, None if a is None else a.ctypes.data, nx, ny, float(efficiency), int(maxside), int(minside))
     rc = lib().wp_cluster(*args, None, 0, ctypes.byref(n))
     if rc != WP_OK:
-        raise WPError(rc, "wp_cluster: invalid arguments")
+        raise WPError(rc, "wp_cluster: " + lib().wp_status_string(rc).decode())
     arr = (wp_patch * max(1, n.value))()
     rc = lib().wp_cluster(*args, arr, n.value, ctypes.byref(n))
     if rc != WP_OK:
-        raise WPError(rc, "wp_cluster: invalid arguments")
+        raise WPError(rc, "wp_cluster: " + lib().wp_status_string(rc).decode())
     return [(p.ilo, p.jlo, p.nx, p.ny) for p in arr[:n.value]]
 
 

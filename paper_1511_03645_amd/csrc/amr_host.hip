@@ -7,6 +7,7 @@
 #include <cmath>
 #include <vector>
 
+#include "abi_guard.h"
 #include "regrid_lists.h"
 #include "wp_ctx.h"
 
@@ -345,6 +346,7 @@ int wp_fill_coarse_ghosts(wp_ctx *ctx, int level, double t)
 // (re-captured when dt0, the tile tables or the parities change).
 extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (nsteps < 0) return wp_fail(ctx, WP_EINVAL, "nsteps must be non-negative");
     int rc;
@@ -379,10 +381,12 @@ extern "C" int wp_advance(wp_ctx *ctx, int nsteps, double dt0)
     }
     if (nsteps & 1) return bo_advance(ctx, 0, dt0, 0, ctx->stream, true);
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int npatches, int buffer)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (level < 0 || level + 1 >= (int)ctx->L.size())
         return wp_fail(ctx, WP_EINVAL, "level %d has no finer level", level);
@@ -454,6 +458,7 @@ extern "C" int wp_regrid(wp_ctx *ctx, int level, const wp_patch *patches, int np
     const int rci = install(ctx, level + 1, boxes);
     ctx->host_ms[HT_UPLOAD] += wp_now_ms();
     return rci;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_patches(const wp_ctx *ctx, int level, wp_patch *out, int cap, int *np)

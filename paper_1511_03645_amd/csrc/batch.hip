@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "abi_guard.h"
 #include "wp_ctx.h"
 
 using namespace wp;
@@ -157,6 +158,7 @@ static int check_status(wp_batch *b)
 
 extern "C" int wp_batch_create(wp_ctx *const *instances, int n, const double *dts, wp_batch **out)
 {
+    WP_ABI_TRY
     if (!out) return WP_EINVAL;
     *out = nullptr;
     if (!instances || !dts || n < 1) return WP_EINVAL;
@@ -201,6 +203,7 @@ extern "C" int wp_batch_create(wp_ctx *const *instances, int n, const double *dt
     if ((rc = build_side(b, 0)) != WP_OK) return rc;
     if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, WP_EDEVICE, "batch create sync");
     return WP_OK;
+    WP_ABI_CATCH(nullptr)
 }
 
 extern "C" void wp_batch_destroy(wp_batch *b)
@@ -268,15 +271,18 @@ static int run_side(wp_batch *b, int adjoint, int nsteps, int snap_every)
 
 extern "C" int wp_batch_step(wp_batch *b, int nsteps, int adjoint)
 {
+    WP_ABI_TRY
     if (!b) return WP_EINVAL;
     if (nsteps < 0) return bfail(b, WP_EINVAL, "nsteps must be non-negative");
     if (adjoint && !b->desc[1]) return bfail(b, WP_ESTATE, "no batched adjoint set up (wp_batch_adjoint_run)");
     if (nsteps == 0) return WP_OK;
     return run_side(b, adjoint ? 1 : 0, nsteps, 0);
+    WP_ABI_CATCH(b ? &b->err : nullptr)
 }
 
 extern "C" int wp_batch_adjoint_run(wp_batch *b, const wp_functional *J, int nsteps, int snap_every)
 {
+    WP_ABI_TRY
     if (!b || !J) return b ? bfail(b, WP_EINVAL, "null functional array") : WP_EINVAL;
     int rc;
     std::vector<wp_snapshot_spec> sp(b->inst.size());
@@ -288,4 +294,5 @@ extern "C" int wp_batch_adjoint_run(wp_batch *b, const wp_functional *J, int nst
     if ((rc = run_side(b, 1, nsteps, snap_every)) != WP_OK) return rc;
     for (size_t k = 0; k < b->inst.size(); ++k) wp_adjoint_finish(b->inst[k], &sp[k]);
     return check_status(b);
+    WP_ABI_CATCH(b ? &b->err : nullptr)
 }

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <vector>
 
+#include "abi_guard.h"
 #include "wp.h"
 
 namespace {
@@ -32,11 +33,13 @@ struct Sat {
         // row's running sums first, then added to the row above
         static thread_local std::vector<int> tf, tb, rf, rb;
         const size_t W = (size_t)nx + 1;
-        if (tf.size() < W * (ny + 1)) {
+        // the second of each pair is tested: a failed allocation of it leaves
+        // the first grown and the test still true on the next call
+        if (tb.size() < W * (ny + 1)) {
             tf.resize(W * (ny + 1));
             tb.resize(W * (ny + 1));
         }
-        if (rf.size() < (size_t)nx) {
+        if (rb.size() < (size_t)nx) {
             rf.resize(nx);
             rb.resize(nx);
         }
@@ -285,6 +288,7 @@ void wp_cluster_boxes(const uint8_t *flags, const uint8_t *allowed, int nx, int 
 extern "C" int wp_cluster(const uint8_t *flags, const uint8_t *allowed, int nx, int ny, double efficiency,
                           int maxside, int minside, wp_patch *out, int cap, int *npatches)
 {
+    WP_ABI_TRY
     if (!flags || nx < 1 || ny < 1 || maxside < 1 || minside < 1 || !npatches || (cap > 0 && !out))
         return WP_EINVAL;
     std::vector<wp_patch> boxes;
@@ -292,4 +296,5 @@ extern "C" int wp_cluster(const uint8_t *flags, const uint8_t *allowed, int nx, 
     *npatches = (int)boxes.size();
     for (int k = 0; k < (int)boxes.size() && k < cap; ++k) out[k] = boxes[k];
     return WP_OK;
+    WP_ABI_CATCH(nullptr)
 }

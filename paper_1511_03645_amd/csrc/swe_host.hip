@@ -4,6 +4,7 @@
 #include <cstring>
 #include <vector>
 
+#include "abi_guard.h"
 #include "wp_ctx.h"
 
 using namespace wp;
@@ -54,6 +55,7 @@ int wp_swe_init(wp_ctx *ctx, const wp_coefficients *coef)
 
 extern "C" int wp_set_bathymetry(wp_ctx *ctx, int level, const double *B)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "bathymetry is for shallow water");
     if (level < 1 || level >= (int)ctx->L.size())
@@ -65,6 +67,7 @@ extern "C" int wp_set_bathymetry(wp_ctx *ctx, int level, const double *B)
         if (!std::isfinite(B[k]) || !(B[k] < 0.0))
             return wp_fail(ctx, WP_EINVAL, "bathymetry must be below sea level everywhere (no dry cells), cell %zu", k);
     return wp_host_copy(ctx, lv.B, B, cells * sizeof(double), true);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 int wp_swe_adj_init(wp_ctx *ctx)

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "abi_guard.h"
 #include "richardson_level.h"
 #include "wp_ctx.h"
 
@@ -453,10 +454,12 @@ int wp_alloc_level(wp_ctx *ctx, Level &lv)
 extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef, const wp_grid *grid,
                          const wp_allocator *alloc, void *stream, wp_ctx **out)
 {
+    WP_ABI_TRY
     if (!out) return WP_EINVAL;
     *out = nullptr;
     if (!problem || !coef || !grid) return WP_EINVAL;
     wp_ctx *ctx = new wp_ctx();
+    *out = ctx;   // handed back on failure too, for wp_last_error; the caller destroys it
     ctx->prob = *problem;
     ctx->grid = *grid;
     ctx->stream = (hipStream_t)stream;
@@ -551,6 +554,7 @@ extern "C" int wp_create(const wp_problem *problem, const wp_coefficients *coef,
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(wp_fail(ctx, WP_EDEVICE, "create sync"));
     *out = ctx;
     return WP_OK;
+    WP_ABI_CATCH(out && *out ? &(*out)->err : nullptr)
 }
 
 extern "C" void wp_destroy(wp_ctx *ctx)
@@ -588,10 +592,12 @@ extern "C" const char *wp_status_string(int s)
 
 extern "C" int wp_set_stream(wp_ctx *ctx, void *stream)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
     ctx->stream = (hipStream_t)stream;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_level_info(const wp_ctx *ctx, int level, int *nx, int *ny, int *npatches)
@@ -775,20 +781,24 @@ static int box_of(wp_ctx *ctx, int level, int patch, int &i0, int &j0, int &w, i
 
 extern "C" int wp_set_state(wp_ctx *ctx, int level, int patch, const void *src, int on_device)
 {
+    WP_ABI_TRY
     if (!ctx || !src) return ctx ? wp_fail(ctx, WP_EINVAL, "null source") : WP_EINVAL;
     int i0, j0, w, h, rc;
     if ((rc = box_of(ctx, level, patch, i0, j0, w, h)) != WP_OK) return rc;
     ctx->L[level].prev_valid = false;   // the other canvas no longer precedes this state
     return copy_box(ctx, ctx->L[level], i0, j0, w, h, const_cast<void *>(src), on_device, true);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_state(wp_ctx *ctx, int level, int patch, void *dst, int on_device)
 {
+    WP_ABI_TRY
     if (!ctx || !dst) return ctx ? wp_fail(ctx, WP_EINVAL, "null destination") : WP_EINVAL;
     int i0, j0, w, h, rc;
     if ((rc = box_of(ctx, level, patch, i0, j0, w, h)) != WP_OK) return rc;
     if ((rc = copy_box(ctx, ctx->L[level], i0, j0, w, h, dst, on_device, false)) != WP_OK) return rc;
     return wp_check_status(ctx);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 int wp_check_status(wp_ctx *ctx)
@@ -806,10 +816,12 @@ int wp_check_status(wp_ctx *ctx)
 
 extern "C" int wp_sync(wp_ctx *ctx)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "sync: %s", hipGetErrorString(hipGetLastError()));
     return wp_check_status(ctx);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_time(const wp_ctx *ctx, int level, double *t)
@@ -823,14 +835,17 @@ extern "C" int wp_get_time(const wp_ctx *ctx, int level, double *t)
 
 extern "C" int wp_set_time(wp_ctx *ctx, int level, double t)
 {
+    WP_ABI_TRY
     if (!ctx || level < 0 || level >= (int)ctx->L.size()) return WP_EINVAL;
     ctx->L[level].t = t;
     ctx->L[level].prev_valid = false;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_set_tile_rows(wp_ctx *ctx, int rows)
 {
+    WP_ABI_TRY
     if (!ctx || rows < 0 || rows > 4096) return WP_EINVAL;
     ctx->tile_rows = rows;
     int rc;
@@ -838,6 +853,7 @@ extern "C" int wp_set_tile_rows(wp_ctx *ctx, int rows)
         if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
     if (ctx->adj_ready && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_tile_rows(const wp_ctx *ctx, int *rows)
@@ -950,6 +966,7 @@ int wp_step_pair(wp_ctx *ctx, Level &lv, double dt, int adjoint, hipStream_t s, 
 
 extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
 {
+    WP_ABI_TRY
     if (!ctx || !(rows == -1 || rows == 0 || (rows >= 4 && rows <= 64))) return WP_EINVAL;
     ctx->pair_rows = rows;
     int rc;
@@ -957,6 +974,7 @@ extern "C" int wp_set_step_pairs(wp_ctx *ctx, int rows)
         if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
     if (ctx->adj_ready && (rc = wp_upload_tiles(ctx, ctx->adj)) != WP_OK) return rc;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_step_pairs(const wp_ctx *ctx, int *rows)
@@ -1006,6 +1024,7 @@ double wp_now_ms()
 
 extern "C" int wp_host_times(wp_ctx *ctx, double *ms, int n, int reset)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (n < 0 || (n > 0 && !ms)) return wp_fail(ctx, WP_EINVAL, "bad output");
     for (int k = 0; k < n && k < WP_HOST_TIMES; ++k) ms[k] = ctx->host_ms[k];
@@ -1013,6 +1032,7 @@ extern "C" int wp_host_times(wp_ctx *ctx, double *ms, int n, int reset)
     if (reset)
         for (double &v : ctx->host_ms) v = 0.0;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 int wp_graph_begin(wp_ctx *ctx, hipStream_t &s)
@@ -1073,6 +1093,7 @@ int wp_graph_launch(wp_ctx *ctx, hipGraphExec_t exec)
 
 extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (nsteps < 1 || replays < 0) return wp_fail(ctx, WP_EINVAL, "nsteps must be >= 1 and replays >= 0");
     if (ctx->L.size() != 1) return wp_fail(ctx, WP_EINVAL, "graph replay is for single-level instances (use wp_advance)");
@@ -1125,10 +1146,12 @@ extern "C" int wp_run_graph(wp_ctx *ctx, int nsteps, double dt, int replays)
         lv.prev_valid = true;
     }
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level %d out of range", level);
     Level &lv = ctx->L[level];
@@ -1144,6 +1167,7 @@ extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
     lv.prev_valid = true;
     lv.t += dt;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // The system the level hierarchy steps.  The adjoint acoustics update uses
@@ -1151,6 +1175,7 @@ extern "C" int wp_step_patches(wp_ctx *ctx, int level, double dt)
 // tables are rebuilt (which also re-captures every cached sequence).
 extern "C" int wp_set_equation(wp_ctx *ctx, int adjoint)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (adjoint != 0 && adjoint != 1) return wp_fail(ctx, WP_EINVAL, "equation must be 0 (forward) or 1 (adjoint)");
     if (!ctx->is_acoustics) return wp_fail(ctx, WP_EINVAL, "the adjoint hierarchy is for acoustics");
@@ -1161,10 +1186,12 @@ extern "C" int wp_set_equation(wp_ctx *ctx, int adjoint)
     for (Level &lv : ctx->L)
         if (!lv.patches.empty() && (rc = wp_upload_tiles(ctx, lv)) != WP_OK) return rc;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_set_reflux(wp_ctx *ctx, int on)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (on != 0 && on != 1) return wp_fail(ctx, WP_EINVAL, "on must be 0 or 1");
     if (on && !ctx->kind2d) return wp_fail(ctx, WP_EINVAL, "refluxing is for 2D hierarchies");
@@ -1175,6 +1202,7 @@ extern "C" int wp_set_reflux(wp_ctx *ctx, int on)
         ++ctx->topo_gen;   // captured Berger-Oliger sequences gain or lose the correction
     }
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_reflux(const wp_ctx *ctx, int *on)
@@ -1327,6 +1355,7 @@ void wp_adjoint_finish(wp_ctx *ctx, const wp_snapshot_spec *sp)
 
 extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snapshot_spec *sp)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     int rc;
     if ((rc = wp_adjoint_setup(ctx, J, sp)) != WP_OK) return rc;
@@ -1364,12 +1393,14 @@ extern "C" int wp_adjoint_run(wp_ctx *ctx, const wp_functional *J, const wp_snap
     if ((rc = wp_graph_launch(ctx, ctx->adj_exec)) != WP_OK) return rc;
     wp_adjoint_finish(ctx, sp);
     return wp_sync(ctx);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_num_snapshots(const wp_ctx *ctx) { return ctx ? ctx->nsnap : 0; }
 
 extern "C" int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (n < 0 || n >= ctx->nsnap) return wp_fail(ctx, WP_ERANGE, "snapshot %d of %d", n, ctx->nsnap);
     if (!dst) return wp_fail(ctx, WP_EINVAL, "null destination");
@@ -1379,12 +1410,14 @@ extern "C" int wp_get_snapshot(wp_ctx *ctx, int n, void *dst, int on_device)
         hipStreamSynchronize(ctx->stream) != hipSuccess)
         return wp_fail(ctx, WP_EDEVICE, "snapshot read");
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // A snapshot store computed elsewhere (e.g. the level-0 composite of an
 // adjoint solved with refinement) replaces the store of the last adjoint run.
 extern "C" int wp_set_snapshots(wp_ctx *ctx, const void *src, int nsnap, double ds, int on_device)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (!src) return wp_fail(ctx, WP_EINVAL, "null source");
     if (nsnap < 1) return wp_fail(ctx, WP_EINVAL, "at least one snapshot is needed");
@@ -1415,6 +1448,7 @@ extern "C" int wp_set_snapshots(wp_ctx *ctx, const void *src, int nsnap, double 
     ctx->snap_ds = ds;
     ctx->adj_tf = ds * (nsnap - 1);
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // ---------------------------------------------------------------------------
@@ -1476,6 +1510,7 @@ static int flag_launch(wp_ctx *ctx, int level, double tol, int n_lo, int n_hi, u
 extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, double t_s, double t_f, uint8_t *flags,
                                int on_device, int64_t *nflagged)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level out of range");
     int n_lo, n_hi, rc;
@@ -1490,10 +1525,12 @@ extern "C" int wp_flag_adjoint(wp_ctx *ctx, int level, double tol, double t, dou
     if (flags && !on_device && (rc = wp_host_copy(ctx, flags, lv.flags, (size_t)cells, false)) != WP_OK) return rc;
     if (nflagged && (rc = wp_read_counts(ctx, ctx->count, 1, nflagged)) != WP_OK) return rc;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_get_flags(wp_ctx *ctx, int level, uint8_t *dst, int on_device)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level out of range");
     if (!dst) return wp_fail(ctx, WP_EINVAL, "null destination");
@@ -1506,6 +1543,7 @@ extern "C" int wp_get_flags(wp_ctx *ctx, int level, uint8_t *dst, int on_device)
         return WP_OK;
     }
     return wp_host_copy(ctx, dst, lv.flags, cells, false);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // The comparison flags (Sec. 5.2.4, Sec. 5.3) on every patch of a level, with
@@ -1565,12 +1603,16 @@ static int flag_standard(wp_ctx *ctx, int level, bool surface, double tol, uint8
 extern "C" int wp_flag_difference(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device,
                                   int64_t *nflagged)
 {
+    WP_ABI_TRY
     return flag_standard(ctx, level, false, tol, flags, on_device, nflagged);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 extern "C" int wp_flag_surface(wp_ctx *ctx, int level, double tol, uint8_t *flags, int on_device, int64_t *nflagged)
 {
+    WP_ABI_TRY
     return flag_standard(ctx, level, true, tol, flags, on_device, nflagged);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // Richardson error estimate and flag (the estimator that Sec. 1 describes
@@ -1634,6 +1676,7 @@ static void rich_valid(const Level &lv, int margin, std::vector<uint8_t> &valid)
 extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighted, double tol, double t, double t_s,
                                   double t_f, uint8_t *flags, int on_device, int64_t *nflagged, double *estimate)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (level < 0 || level >= (int)ctx->L.size()) return wp_fail(ctx, WP_EINVAL, "level %d out of range", level);
     if (ctx->L[level].patches.empty()) return wp_fail(ctx, WP_EINVAL, "level %d has no patches", level);
@@ -1738,6 +1781,7 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
     if (estimate && (rc = wp_host_copy(ctx, estimate, ctx->richE, ebytes, false)) != WP_OK) return rc;
     if (nflagged && (rc = wp_read_counts(ctx, ctx->count, 1, nflagged)) != WP_OK) return rc;
     return WP_OK;
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // The flagged forward run as one captured sequence: a clear of the event
@@ -1748,6 +1792,7 @@ extern "C" int wp_flag_richardson(wp_ctx *ctx, int level, double dt, int weighte
 extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_every, double tol, double t_s,
                                   double t_f, int64_t *counts, float *step_ms)
 {
+    WP_ABI_TRY
     if (!ctx) return WP_EINVAL;
     if (ctx->L.size() != 1) return wp_fail(ctx, WP_EINVAL, "flagged forward runs are for single-level instances");
     if (ctx->equation != 0) return wp_fail(ctx, WP_ESTATE, "flagged forward run on a hierarchy set to the adjoint system");
@@ -1884,6 +1929,7 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
         }
     }
     return wp_check_status(ctx);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
 
 // ---------------------------------------------------------------------------
@@ -1891,6 +1937,7 @@ extern "C" int wp_forward_flagged(wp_ctx *ctx, double dt, int nsteps, int flag_e
 // ---------------------------------------------------------------------------
 extern "C" int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int which, int snapshot, double *out)
 {
+    WP_ABI_TRY
     if (!ctx || !out) return ctx ? wp_fail(ctx, WP_EINVAL, "null output") : WP_EINVAL;
     Level &l0 = ctx->L[0];
     const long long cells = (long long)l0.nx * l0.ny;
@@ -1945,4 +1992,5 @@ extern "C" int wp_functional_value(wp_ctx *ctx, const wp_functional *J, int whic
     if ((rc2 = wp_host_copy(ctx, &v, ctx->red_out, sizeof v, false)) != WP_OK) return rc2;
     *out = v * dA;
     return wp_check_status(ctx);
+    WP_ABI_CATCH(ctx ? &ctx->err : nullptr)
 }
