@@ -69,24 +69,26 @@ inline void make_spans(const std::vector<Rect> &R, Spans &s)
     if (lo >= hi) return;
     s.j0 = lo;
     s.nrows = hi - lo;
-    // bucket the rectangles' row intervals by row (counting sort), then sort
-    // and merge each row's
-    static thread_local std::vector<int> start, pos;
+    // bucket the rectangles' row intervals by row (counting sort, stable),
+    // the rectangles taken in increasing i0 so that every row's intervals
+    // arrive sorted, then merge each row's
+    static thread_local std::vector<int> start, pos, ord;
     static thread_local std::vector<std::pair<int, int>> raw;
+    ord.clear();
+    for (int k = 0; k < (int)R.size(); ++k)
+        if (R[k].i0 < R[k].i1 && R[k].j0 < R[k].j1) ord.push_back(k);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return R[a].i0 != R[b].i0 ? R[a].i0 < R[b].i0 : a < b; });
     start.assign((size_t)s.nrows + 1, 0);
-    for (const Rect &r : R)
-        if (r.i0 < r.i1 && r.j0 < r.j1)
-            for (int j = r.j0; j < r.j1; ++j) ++start[j - lo + 1];
+    for (int k : ord)
+        for (int j = R[k].j0; j < R[k].j1; ++j) ++start[j - lo + 1];
     for (int k = 0; k < s.nrows; ++k) start[k + 1] += start[k];
     raw.resize((size_t)start[s.nrows]);
     pos.assign(start.begin(), start.end() - 1);
-    for (const Rect &r : R)
-        if (r.i0 < r.i1 && r.j0 < r.j1)
-            for (int j = r.j0; j < r.j1; ++j) raw[pos[j - lo]++] = {r.i0, r.i1};
+    for (int k : ord)
+        for (int j = R[k].j0; j < R[k].j1; ++j) raw[pos[j - lo]++] = {R[k].i0, R[k].i1};
     s.off.assign((size_t)s.nrows + 1, 0);
     for (int k = 0; k < s.nrows; ++k) {
         auto a = raw.begin() + start[k], b = raw.begin() + start[k + 1];
-        std::sort(a, b);
         for (auto it = a; it != b; ++it) {
             if ((int)s.iv.size() > s.off[k] && it->first <= s.iv.back().second)
                 s.iv.back().second = std::max(s.iv.back().second, it->second);
@@ -166,27 +168,35 @@ inline void ring_block_list(const std::vector<std::array<int, 3>> &runs, int r, 
 {
     out.clear();
     static thread_local std::vector<unsigned long long> acc;
+    static thread_local std::vector<int> touched;
     acc.assign((size_t)NX, 0);
+    // indices are non-negative: a power-of-two ratio divides by a shift
+    const bool pow2 = (r & (r - 1)) == 0;
+    int lr = 0;
+    while ((1 << lr) < r) ++lr;
+    auto div = [&](int x) { return pow2 ? x >> lr : x / r; };
     for (size_t k = 0; k < runs.size();) {
-        // the runs of the r fine rows of one coarse row are contiguous
-        const int J = runs[k][0] / r;
-        int lo = NX, hi = -1;
-        for (; k < runs.size() && runs[k][0] / r == J; ++k) {
+        // the runs of the r fine rows of one coarse row are contiguous; the
+        // coarse cells they touch are collected and sorted, so that a row
+        // with runs far apart costs its runs, not the width between them
+        const int J = div(runs[k][0]);
+        touched.clear();
+        for (; k < runs.size() && div(runs[k][0]) == J; ++k) {
             const int j = runs[k][0], a = runs[k][1], b = runs[k][2];
-            for (int I = a / r; I <= (b - 1) / r; ++I) {
+            const int shift = r * (j - J * r);
+            for (int I = div(a); I <= div(b - 1); ++I) {
                 const int x0 = std::max(a, I * r) - I * r, x1 = std::min(b, I * r + r) - I * r;
-                acc[I] |= (((1ULL << (x1 - x0)) - 1) << x0) << (r * (j % r));
+                if (!acc[I]) touched.push_back(I);
+                acc[I] |= (((1ULL << (x1 - x0)) - 1) << x0) << shift;
             }
-            lo = std::min(lo, a / r);
-            hi = std::max(hi, (b - 1) / r);
         }
-        for (int I = lo; I <= hi; ++I)
-            if (acc[I]) {
-                out.push_back(J * NX + I);
-                out.push_back((int)(unsigned)(acc[I] & 0xffffffffULL));
-                out.push_back((int)(unsigned)(acc[I] >> 32));
-                acc[I] = 0;
-            }
+        std::sort(touched.begin(), touched.end());
+        for (int I : touched) {
+            out.push_back(J * NX + I);
+            out.push_back((int)(unsigned)(acc[I] & 0xffffffffULL));
+            out.push_back((int)(unsigned)(acc[I] >> 32));
+            acc[I] = 0;
+        }
     }
 }
 
