@@ -10,7 +10,10 @@ the benchmark measures, against the FP64 oracle (Sec. 2, 3, 4, 5.1.2):
   events) against the oracle's stored results (tests/golden/c1_job_oracle.json,
   written by tests/golden/make_c1_job.py from the oracle alone): every
   event's flag canvas through its digest, the final state and snapshots at
-  sampled cells, J.
+  sampled cells, J;
+* one whole 2048 x 2048 shallow-water job (2380 adjoint + 2380 forward
+  steps, 238 flag events) likewise (tests/golden/c3_job_oracle.json, written
+  by tests/golden/make_c3_job.py).
 
 Bars: FP64 values within 1e-12 of the oracle's scale; flags bit-exact outside
 the band |m - tol| <= 1e-12 S, S = max(1, max|q| max|qhat|)."""
@@ -23,12 +26,13 @@ import pytest
 
 import oracle
 import paper_1511_03645_amd as wp
-from wp_synth import acoustics1d, acoustics2d
+from wp_synth import acoustics1d, acoustics2d, swe2d
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_job_oracle.json")
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_job_oracle.json")
 
 
 def close64(a, b, what, scale=None):
@@ -194,3 +198,54 @@ def test_c1_full_job_matches_stored_oracle():
         assert abs(counts[k] - ev["count"]) <= len(ev["band"]), f"event {k}"
     assert _digest(v.get_flags(0), gold["events"][-1]["band"]) == gold["events"][-1]["sha256"]
     assert np.array_equal(v.get_state(), q)
+
+
+@pytest.mark.timeout(600)
+def test_c3_full_job_matches_stored_oracle():
+    """One whole job of the 2048 x 2048 shallow-water workload in the
+    benchmark's launch configuration (FP64, the default tiles, the flag every
+    10 steps, one captured sequence per run) against the oracle's stored
+    results of the same job, as for C1.  The scale of a snapshot or state is
+    its largest value over all three components, as for every FP64 output:
+    the adjoint's momenta (about 1% of its surface component) are updated by
+    terms of the surface component's size, whose rounding sets their error."""
+    gold = json.load(open(GOLDEN_C3))
+    cfg = swe2d(gold["n"], seed=gold["seed"])
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    cfg = dict(cfg, t_f=N * dt, t_s=N * dt)
+    assert (N, every, dt, cfg["tol"]) == (gold["nsteps"], gold["every"], gold["dt"], gold["tol"])
+    print(f"case C3 full job: {N} + {N} steps, {N // every} flag events", flush=True)
+    w = wp.from_config(cfg)
+    w.adjoint_run(cfg["functional"], dt, N, every)
+    for s in gold["snapshots"]:
+        got = w.get_snapshot(s["n"])
+        idx = np.asarray(s["cells"])
+        for c in range(3):
+            close64(got[c].ravel()[idx], np.asarray(s["values"][c]), f"snapshot {s['n']} component {c}",
+                    scale=gold["snapshot_scale"])
+    w.set_state(cfg["q0"])
+    w.set_time(0.0)
+    for k, ev in enumerate(gold["events"]):
+        counts, _ = w.forward_flagged(dt, every, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+        band = ev["band"]
+        ok = _digest(w.get_flags(0), band) == ev["sha256"]
+        assert ok, (f"event {k} (t = {ev['t']:.1f}): flag canvas differs from the oracle's outside the band "
+                    f"({counts[0]} flagged, oracle {ev['count']})")
+        assert abs(counts[0] - ev["count"]) <= len(band)
+        if k % 50 == 0:
+            print(f"  event {k}: {counts[0]} flagged", flush=True)
+    q = w.get_state()
+    idx = np.asarray(gold["final"]["cells"])
+    for c in range(3):
+        close64(q[c].ravel()[idx], np.asarray(gold["final"]["values"][c]), f"final state component {c}",
+                scale=gold["final"]["scale"])
+    J = w.functional_value(cfg["functional"], which=0)
+    assert abs(J - gold["J"]) <= TOL64 * abs(gold["J"]), (J, gold["J"])
+    # the benchmark's form: the whole forward run as one captured sequence
+    w.set_state(cfg["q0"])
+    w.set_time(0.0)
+    counts, _ = w.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
+    for k, ev in enumerate(gold["events"]):
+        assert abs(counts[k] - ev["count"]) <= len(ev["band"]), f"event {k}"
+    assert _digest(w.get_flags(0), gold["events"][-1]["band"]) == gold["events"][-1]["sha256"]
+    assert np.array_equal(w.get_state(), q)
