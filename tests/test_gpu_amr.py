@@ -69,6 +69,9 @@ LAYOUTS = [
     (12, [3, 2], [[(6, 6, 18, 15)], [(14, 14, 20, 12), (36, 20, 6, 8)]], (0, 1, 0, 0)),
     (10, [2, 6], [[(4, 4, 12, 10)], [(30, 36, 42, 30)]], (1, 1, 0, 0)),
     (8, [12], [[(24, 12, 36, 48)]], (0, 0, 0, 0)),
+    # ratio 4 with patches on all four domain edges: ring parents on the
+    # boundary take their slopes through the boundary rule
+    (16, [4], [[(0, 0, 24, 20), (40, 44, 24, 20)]], (1, 1, 0, 1)),
 ]
 
 

@@ -24,6 +24,8 @@ LAYOUTS = [
     (16, (2, 4), [[(4, 4, 20, 16)], [(24, 24, 40, 32), (64, 24, 8, 8)]], (0, 1, 0, 1)),
     (18, (3,), [[(9, 9, 24, 18), (36, 27, 12, 21)]], (1, 0, 0, 1)),
     (12, (2, 3), [[(4, 4, 12, 10)], [(18, 18, 24, 21)]], (0, 0, 0, 0)),
+    # ratio 4 with patches on all four domain edges (walls and extrapolation)
+    (16, (4,), [[(0, 0, 24, 20), (40, 44, 24, 20)]], (1, 0, 1, 1)),
 ]
 
 
