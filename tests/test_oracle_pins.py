@@ -550,3 +550,113 @@ def test_swe_transverse_split_is_the_jacobian_split_at_a_moving_state(seed):
             scale = np.abs(d).max() * (abs(u) + abs(v) + c)
             assert np.abs(bm - Am @ d).max() < 1e-12 * scale, (tdir, bm, Am @ d)
             assert np.abs(bp - Ap @ d).max() < 1e-12 * scale, (tdir, bp, Ap @ d)
+
+
+# ---------------------------------------------------------------------------
+# transverse splits with the coefficients varying across the transverse edges
+# ---------------------------------------------------------------------------
+def _eig_pairs(which, a, tdir):
+    """The left-going eigenvector, its speed, the right-going one, its speed
+    and the zero-speed one of cell coefficients `a` along direction tdir, for
+    the system each solver propagates (forward acoustics: A or B of Sec. 5.2;
+    the time-reversed adjoints: -A^T, -B^T; Sec. 5.3 for the linearised
+    shallow water, a = (hbar, c))."""
+    n, t = (1, 2) if tdir == 0 else (2, 1)
+    e = np.zeros(3)
+    e[t] = 1.0
+    rm, rp = np.zeros(3), np.zeros(3)
+    if which == "acoustics_fwd":
+        Z, c = a[0], a[1]
+        rm[0], rm[n] = -Z, 1.0
+        rp[0], rp[n] = Z, 1.0
+    elif which == "acoustics_adj":
+        Z, c = a[0], a[1]
+        rm[0], rm[n] = 1.0, Z
+        rp[0], rp[n] = 1.0, -Z
+    else:   # lswe_adj
+        c = a[1]
+        rm[0], rm[n] = c, 1.0
+        rp[0], rp[n] = -c, 1.0
+    return rm, -c, rp, c, e
+
+
+@pytest.mark.parametrize("which", ["acoustics_fwd", "acoustics_adj", "lswe_adj"])
+def test_transverse_split_is_the_transverse_riemann_problem_of_each_edge(which):
+    """Coefficients that differ in the three cells a transverse split touches
+    (below, own, above): the part of d sent across the lower edge is the
+    left-going wave of the Riemann problem there, d decomposed into the lower
+    cell's left-going and the own cell's right-going eigenvectors (and the
+    zero-speed one), times the lower cell's speed; the part sent across the
+    upper edge likewise with the own cell's left-going and the upper cell's
+    right-going eigenvectors (Sec. 3, the transverse Riemann problem).  The
+    decompositions are solved here with a library solver."""
+    rng = np.random.default_rng(77)
+    for _ in range(20):
+        cells = []
+        for _k in range(3):
+            if which == "lswe_adj":
+                hbar = rng.uniform(50.0, 4000.0)
+                cells.append([hbar, math.sqrt(9.81 * hbar), 0.0, 0.0])
+            else:
+                rho, K = rng.uniform(0.5, 3.0), rng.uniform(0.5, 5.0)
+                cells.append([math.sqrt(rho * K), math.sqrt(K / rho), rho, K])
+        lo, own, hi = cells
+        d = rng.normal(size=3)
+        for tdir in (0, 1):
+            bm, bp = oracle.transverse_split(which, tdir, d, lo, own, hi)
+            rm_lo, sm_lo, _, _, e = _eig_pairs(which, lo, tdir)
+            _, _, rp_own, _, _ = _eig_pairs(which, own, tdir)
+            beta = np.linalg.solve(np.column_stack([rm_lo, rp_own, e]), d)
+            want_m = sm_lo * beta[0] * rm_lo
+            rm_own, _, _, _, _ = _eig_pairs(which, own, tdir)
+            _, _, rp_hi, sp_hi, _ = _eig_pairs(which, hi, tdir)
+            gam = np.linalg.solve(np.column_stack([rm_own, rp_hi, e]), d)
+            want_p = sp_hi * gam[1] * rp_hi
+            scale = np.abs(d).max() * max(abs(sm_lo), sp_hi) * max(1.0, np.abs(rm_lo).max(), np.abs(rp_hi).max())
+            assert np.abs(bm - want_m).max() <= 1e-13 * scale, (which, tdir, bm, want_m)
+            assert np.abs(bp - want_p).max() <= 1e-13 * scale, (which, tdir, bp, want_p)
+
+
+# ---------------------------------------------------------------------------
+# the MC limiter through the characteristic decomposition
+# ---------------------------------------------------------------------------
+def _scalar_mc_step(w, nu):
+    """One step of the flux-limited Lax-Wendroff method for w_t + s w_x = 0,
+    s > 0, Courant number nu, periodic, MC limiter phi(theta) = max(0,
+    min((1 + theta)/2, 2, 2 theta)) with theta the upwind jump over the
+    edge's jump (the textbook high-resolution method in flux-limiter form)."""
+    dw = w - np.roll(w, 1)                 # jump at edge i - 1/2
+    up = np.roll(dw, 1)                    # jump at edge i - 3/2 (upwind)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        theta = np.where(dw != 0.0, up / np.where(dw != 0.0, dw, 1.0), 0.0)
+    phi = np.maximum(0.0, np.minimum(np.minimum((1.0 + theta) / 2.0, 2.0), 2.0 * theta))
+    phi = np.where(dw != 0.0, phi, 0.0)
+    F = 0.5 * nu * (1.0 - nu) * phi * dw   # limited correction at edge i - 1/2 (times dx/dt)
+    return w - nu * dw - (np.roll(F, -1) - F)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_1d_step_is_two_limited_scalar_advections(seed):
+    """Constant rho and K in 1D: the waves are multiples of the two fixed
+    eigenvectors, so a step of the method is the textbook MC-limited scalar
+    method applied to each characteristic variable, w2 = (p + Z u)/(2Z)
+    moving right at c and w1 = (Z u - p)/(2Z) moving left.  Rough random data
+    puts every ratio theta in play, the limiter's cap of 2 (theta >= 3)
+    included."""
+    rng = np.random.default_rng(300 + seed)
+    rho, K = 1.3, 2.1
+    Z, c = math.sqrt(rho * K), math.sqrt(K / rho)
+    nx = 96
+    cfg = mk(nx=nx, rho=np.full(nx, rho), K=np.full(nx, K))
+    nu = 0.8
+    dt = nu * cfg["dx"] / c
+    q0 = rng.normal(size=(2, 1, nx))
+    q1, _, _ = oracle.run(cfg, "acoustics_fwd", q0, 1, dt=dt)
+    p, u = q0[0, 0], q0[1, 0]
+    w2 = (p + Z * u) / (2 * Z)
+    w1 = (Z * u - p) / (2 * Z)
+    w2n = _scalar_mc_step(w2, nu)
+    w1n = _scalar_mc_step(w1[::-1], nu)[::-1]
+    # q = w1 (-Z, 1) + w2 (Z, 1)
+    want = np.stack([Z * (w2n - w1n), w1n + w2n])
+    assert np.abs(q1[:, 0] - want).max() <= 1e-13 * np.abs(q0).max() * (1 + Z)
