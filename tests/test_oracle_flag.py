@@ -405,3 +405,43 @@ def test_weighted_level_flag_reduces_to_level_zero_flag():
                                            ds=1.0, ratio=2)
     want = 2.0 * np.abs(np.repeat(np.repeat(E[0], 2, 0), 2, 1))
     assert np.allclose(m, want, rtol=0, atol=1e-15)
+
+
+def test_functional_of_a_constant_state_is_the_region_area():
+    """J of a state that is 1 in the functional's component over cells of
+    unequal sides (dx != dy, neither 1) is the area of the cells whose centres
+    the region holds: the indicator is a closed set (centres on the box edge
+    count) and each cell weighs dx dy (eq. J)."""
+    dx, dy = 0.25, 0.4
+    nx, ny = 12, 10
+    # box edges through cell centres: x in [0.375, 1.875] holds centres
+    # 0.375 .. 1.875 (7 columns), y in [0.6, 2.2] holds 0.6 .. 2.2 (5 rows)
+    f = dict(kind="box", x0=0.375, x1=1.875, y0=0.6, y1=2.2, cx=0, cy=0, r=0, component=2)
+    cfg = dict(kind="acoustics2d", nx=nx, ny=ny, xlo=0.0, xhi=nx * dx, ylo=0.0, yhi=ny * dy, dx=dx, dy=dy,
+               functional=f)
+    q = np.zeros((3, ny, nx))
+    q[2] = 1.0
+    assert oracle.functional(cfg, q) == pytest.approx(7 * 5 * dx * dy, rel=1e-15)
+    q[2] = 0.0
+    q[0] = 1.0   # another component: no contribution
+    assert oracle.functional(cfg, q) == 0.0
+    # 1D interval with edges on centres: cells of width dx only
+    f1 = dict(kind="interval", x0=0.375, x1=1.125, y0=0, y1=0, cx=0, cy=0, r=0, component=0)
+    cfg1 = dict(kind="acoustics1d", nx=nx, ny=1, xlo=0.0, xhi=nx * dx, ylo=0.0, yhi=1.0, dx=dx, dy=1.0,
+                functional=f1)
+    assert oracle.functional(cfg1, np.ones((2, 1, nx))) == pytest.approx(4 * dx, rel=1e-15)
+
+
+def test_adjoint_flag_is_strict_at_the_tolerance():
+    """A cell is flagged when its measure exceeds the tolerance (Sec. 4,
+    Sec. 5.1: the inner product larger than the tolerance); a measure exactly
+    equal to it is not flagged, one just above it is."""
+    tol = 0.375
+    q = np.zeros((3, 2, 3))
+    q[0] = 1.0
+    snap = np.zeros((1, 3, 2, 3))
+    snap[0, 0] = tol
+    snap[0, 0, 1, 2] = tol * (1 + 2 ** -50)
+    fl, mval = oracle.flag(q, snap, 0.0, 0.0, 0.0, 1.0, tol)
+    assert mval[0, 0] == tol
+    assert fl.sum() == 1 and fl[1, 2] == 1

@@ -660,3 +660,34 @@ def test_1d_step_is_two_limited_scalar_advections(seed):
     # q = w1 (-Z, 1) + w2 (Z, 1)
     want = np.stack([Z * (w2n - w1n), w1n + w2n])
     assert np.abs(q1[:, 0] - want).max() <= 1e-13 * np.abs(q0).max() * (1 + Z)
+
+
+# ---------------------------------------------------------------------------
+# walls: the method of images
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["acoustics_fwd", "acoustics_adj"])
+def test_wall_is_the_mirror_image_of_the_doubled_domain(which):
+    """A wall at x = 0 acts as a mirror: the problem on [0, 1] with walls
+    equals, on [0, 1], the problem on [-1, 1] whose data and materials are
+    mirrored about x = 0 (p and v even, u odd), with walls at both far ends.
+    Checked in 2D and in 1D, over several steps, to round-off."""
+    rng = np.random.default_rng(11)
+    n, ny = 24, 16
+    for dim in (2, 1):
+        kind = "acoustics2d" if dim == 2 else "acoustics1d"
+        rows = ny if dim == 2 else 1
+        m = 3 if dim == 2 else 2
+        rho = rng.uniform(0.5, 2.0, size=(rows, n))
+        K = rng.uniform(0.5, 3.0, size=(rows, n))
+        q = rng.normal(size=(m, rows, n))
+        half = mk(kind, nx=n, ny=ny, xlo=0.0, xhi=1.0, rho=rho, K=K, bc=(BC_WALL,) * 4)
+        full = mk(kind, nx=2 * n, ny=ny, xlo=-1.0, xhi=1.0, rho=np.concatenate([rho[:, ::-1], rho], axis=1),
+                  K=np.concatenate([K[:, ::-1], K], axis=1), bc=(BC_WALL,) * 4)
+        sign = np.ones((m, 1, 1))
+        sign[1] = -1.0                      # u is odd about the wall
+        qf = np.concatenate([sign * q[:, :, ::-1], q], axis=2)
+        cmax = float(np.sqrt(K / rho).max())
+        dt = 0.8 * min(half["dx"], half["dy"] if dim == 2 else 1.0) / cmax
+        a, _, _ = oracle.run(half, which, q, 6, dt=dt)
+        b, _, _ = oracle.run(full, which, qf, 6, dt=dt)
+        assert np.abs(a - b[:, :, n:]).max() <= 1e-12 * np.abs(q).max(), (which, dim)
