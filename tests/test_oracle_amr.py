@@ -315,6 +315,30 @@ def _reflux_hierarchy(reflux, patches, ratios=(2, 2), n=32, seed=21):
 RF_PATCHES = [[(16, 16, 24, 20), (40, 12, 12, 28)], [(36, 40, 24, 16)]]
 
 
+def test_reflux_conserves_the_composite_sum_on_rectangular_cells():
+    """The same conservation with cells twice as wide as high (dx = 2 dy):
+    each correction divides by the width of the cell across its face (dx for
+    x-faces, dy for y-faces), so the composite sum of p~ dA is kept to
+    round-off only with that width."""
+    from wp_synth import random_media
+    n = 32
+    rho, K = random_media(n, n, seed=21)
+    cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=-2.0, xhi=2.0, ylo=-1.0, yhi=1.0, dx=4.0 / n, dy=2.0 / n,
+               rho=rho, K=K, bc=[amr.BC_WALL] * 4, order=2, limiter=1, transverse=1)
+    dt = 0.8 * cfg["dy"] / float(np.sqrt(K / rho).max())
+    H = amr.Hierarchy(cfg, (2, 2), RF_PATCHES, equation="adjoint", reflux=True)
+    q0 = random_state(3, n, n, seed=5)
+    H.set_level(0, q0)
+    for l in (1, 2):
+        r = H.n[l][0] // n
+        H.set_level(l, np.repeat(np.repeat(q0, r, axis=1), r, axis=2))
+    s0 = H.q[0][0].sum()
+    scale = np.abs(H.q[0][0]).sum()
+    for _ in range(4):
+        H.advance(0, dt)
+        assert abs(H.q[0][0].sum() - s0) < 1e-14 * scale
+
+
 def test_reflux_conserves_the_composite_sum_on_a_walled_domain():
     """With walls the reversed adjoint flux of p~, -u~/rho, vanishes at the
     boundary, so sum p~ dA is conserved on a uniform grid.  On three levels
@@ -490,3 +514,57 @@ def test_swe_full_cover_fine_level_equals_uniform_fine_run():
     ref, _, _ = oracle.run(fine, "swe", q1, 6, dt=cfg["dt"] / r)
     assert np.array_equal(H.q[1], ref)
     assert np.abs(ref[0]).max() > 1e-3
+
+
+
+def test_limited_interpolation_creates_no_new_extrema():
+    """Each fine value of the space interpolation lies between the smallest
+    and largest of its coarse parent and the parent's four face neighbours
+    (minmod-limited slopes: at a coarse extremum the slope is zero, elsewhere
+    each direction moves less than half the smaller neighbouring jump), on
+    rough random data where unlimited slopes overshoot."""
+    ny, nx = 12, 14
+    C = random_state(3, ny, nx, seed=9)
+    for r in (2, 4):
+        cells = [(I, J) for J in range(r, (ny - 1) * r) for I in range(r, (nx - 1) * r)]
+        v = amr.coarse_to_fine(C, C, 0.0, r, cells, BC)
+        for (I, J), val in zip(cells, v):
+            ic, jc = I // r, J // r
+            nb = C[:, [jc, jc, jc, jc - 1, jc + 1], [ic, ic - 1, ic + 1, ic, ic]]
+            assert np.all(val >= nb.min(axis=1) - 1e-15) and np.all(val <= nb.max(axis=1) + 1e-15), (I, J)
+
+
+def test_nesting_mask_of_boxes_in_closed_form():
+    """A box away from the domain edge nests the box shrunk by one cell on
+    every side; two boxes sharing an edge nest their union shrunk by one
+    cell on its outer sides only; a box on the domain edge is not shrunk
+    there."""
+    nx, ny = 20, 16
+    m = amr.nesting_mask([(4, 3, 8, 6)], nx, ny)
+    want = np.zeros((ny, nx), dtype=bool)
+    want[4:8, 5:11] = True
+    assert np.array_equal(m, want)
+    m = amr.nesting_mask([(4, 3, 8, 6), (12, 3, 5, 6)], nx, ny)
+    want = np.zeros((ny, nx), dtype=bool)
+    want[4:8, 5:16] = True
+    assert np.array_equal(m, want)
+    m = amr.nesting_mask([(0, 0, 6, 5)], nx, ny)
+    want = np.zeros((ny, nx), dtype=bool)
+    want[0:4, 0:5] = True
+    assert np.array_equal(m, want)
+
+
+def test_dilation_of_a_cell_is_a_box():
+    """Dilating one flagged cell by k flags the (2k + 1) x (2k + 1) box
+    around it, clipped to the image."""
+    for k in (1, 2, 3):
+        f = np.zeros((15, 17), dtype=bool)
+        f[7, 8] = True
+        want = np.zeros_like(f)
+        want[7 - k:8 + k, 8 - k:9 + k] = True
+        assert np.array_equal(amr.dilate(f, k), want)
+        f = np.zeros((15, 17), dtype=bool)
+        f[0, 16] = True
+        want = np.zeros_like(f)
+        want[0:k + 1, 16 - k:17] = True
+        assert np.array_equal(amr.dilate(f, k), want)
