@@ -445,3 +445,19 @@ def test_adjoint_flag_is_strict_at_the_tolerance():
     fl, mval = oracle.flag(q, snap, 0.0, 0.0, 0.0, 1.0, tol)
     assert mval[0, 0] == tol
     assert fl.sum() == 1 and fl[1, 2] == 1
+
+
+def test_richardson_valid_cells_of_a_box():
+    """For one patch away from the level's edge, a coarse cell keeps its
+    estimate exactly when its 2 x 2 block lies at least `margin` fine cells
+    inside the patch on every side."""
+    nx = ny = 40
+    i0, j0, w, h = 6, 9, 22, 18
+    for margin in (2, 3, 4):
+        v = oracle.richardson_valid([(i0, j0, w, h)], nx, ny, margin)
+        want = np.zeros((ny // 2, nx // 2), dtype=bool)
+        for J in range(ny // 2):
+            for I in range(nx // 2):
+                want[J, I] = (2 * I - margin >= i0 and 2 * I + 1 + margin <= i0 + w - 1 and
+                              2 * J - margin >= j0 and 2 * J + 1 + margin <= j0 + h - 1)
+        assert np.array_equal(v, want), margin

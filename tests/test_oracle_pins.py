@@ -691,3 +691,42 @@ def test_wall_is_the_mirror_image_of_the_doubled_domain(which):
         a, _, _ = oracle.run(half, which, q, 6, dt=dt)
         b, _, _ = oracle.run(full, which, qf, 6, dt=dt)
         assert np.abs(a - b[:, :, n:]).max() <= 1e-12 * np.abs(q).max(), (which, dim)
+
+
+def test_courant_number_is_the_largest_speed_over_each_direction_width():
+    """The Courant number a step reports is max |s| dt / dx over x-edges and
+    max |s| dt / dy over y-edges: with c = 1 everywhere and dy = dx / 2 it is
+    dt / dy, and dt / dx in 1D."""
+    n = 16
+    cfg = mk("acoustics2d", nx=n, ny=n, xlo=0.0, xhi=2.0, ylo=0.0, yhi=1.0)
+    dt = 0.3 * cfg["dy"]
+    q = np.random.default_rng(2).normal(size=(3, n, n))
+    _, _, cfl = oracle.run(cfg, "acoustics_fwd", q, 1, dt=dt)
+    assert cfl == pytest.approx(dt / cfg["dy"], rel=1e-15)
+    cfg1 = mk(nx=n, xlo=0.0, xhi=2.0)
+    _, _, cfl1 = oracle.run(cfg1, "acoustics_fwd", q[:2, :1], 1, dt=dt)
+    assert cfl1 == pytest.approx(dt / cfg1["dx"], rel=1e-15)
+
+
+def test_swe_step_commutes_with_reflection():
+    """Reflecting the shallow-water problem in x (eta, hv and the bathymetry
+    mirrored, hu mirrored with its sign changed) reflects its solution: the
+    normal and transverse solves at each edge use both of the edge's cells
+    symmetrically (a Roe state taken from one side only would break this)."""
+    from wp_synth import swe2d
+    cfg = swe2d(n=32, seed=3)
+    rng = np.random.default_rng(8)
+    q = cfg["q0"].copy()
+    q[0] += rng.normal(size=q[0].shape) * 0.5
+    h = q[0] - cfg["B"]
+    q[1] = h * rng.normal(size=h.shape) * 0.3
+    q[2] = h * rng.normal(size=h.shape) * 0.3
+    mir = dict(cfg, B=cfg["B"][:, ::-1].copy(), bc=[cfg["bc"][1], cfg["bc"][0], cfg["bc"][2], cfg["bc"][3]])
+    qm = q[:, :, ::-1].copy()
+    qm[1] = -qm[1]
+    a, _, _ = oracle.run(cfg, "swe", q, 3)
+    b, _, _ = oracle.run(mir, "swe", qm, 3)
+    b = b[:, :, ::-1]
+    b[1] = -b[1]
+    for k in range(3):
+        assert np.abs(a[k] - b[k]).max() <= 1e-12 * max(np.abs(a[k]).max(), np.abs(q[k]).max()), k
