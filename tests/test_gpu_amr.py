@@ -72,6 +72,9 @@ LAYOUTS = [
     # ratio 4 with patches on all four domain edges: ring parents on the
     # boundary take their slopes through the boundary rule
     (16, [4], [[(0, 0, 24, 20), (40, 44, 24, 20)]], (1, 1, 0, 1)),
+    # ratio 8: a parent's ring children span all 64 bits of its mask
+    (8, [8], [[(0, 16, 24, 32), (40, 8, 16, 24)]], (1, 0, 0, 1)),
+    (6, [2, 8], [[(2, 2, 6, 6)], [(24, 24, 32, 32)]], (0, 0, 1, 0)),
 ]
 
 
