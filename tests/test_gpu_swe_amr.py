@@ -26,6 +26,9 @@ LAYOUTS = [
     (12, (2, 3), [[(4, 4, 12, 10)], [(18, 18, 24, 21)]], (0, 0, 0, 0)),
     # ratio 4 with patches on all four domain edges (walls and extrapolation)
     (16, (4,), [[(0, 0, 24, 20), (40, 44, 24, 20)]], (1, 0, 1, 1)),
+    # ratio 8 (ring masks of 64 bits), alone and above a ratio-2 level
+    (8, (8,), [[(16, 16, 24, 32)]], (0, 1, 0, 0)),
+    (12, (2, 8), [[(6, 6, 12, 10)], [(64, 64, 64, 48)]], (0, 0, 0, 0)),
 ]
 
 
