@@ -98,6 +98,34 @@ def test_regrid_init_and_berger_oliger_match_oracle(n, ratios, boxes, bc):
         assert abs(w.get_time(l) - H.t[l]) <= 1e-12 * max(H.t[l], 1.0)
 
 
+@pytest.mark.parametrize("rows", [4, 6, 12, 16])
+@pytest.mark.parametrize("layout", [0, 2, 9])
+def test_refined_levels_at_every_compiled_tile_height(layout, rows):
+    """The hierarchies of ratio 4 (one level, and 2 then 4) and 8 stepped with
+    each compiled tile height of the refined-level kernel (two tiles per wave
+    where their columns fit; at heights 4 and 16 the finest level's last
+    substep also averages onto the level below in the step), against the
+    oracle; the default height (8) is the main layout test."""
+    n, ratios, boxes, bc = LAYOUTS[layout]
+    print(f"case amr rows={rows} n={n} ratios={ratios}", flush=True)
+    cfg, H, w = build(n, ratios, boxes, bc, seed=n + rows)
+    w.set_tile_rows(rows)
+    assert w.get_tile_rows() == rows
+    for l in range(1, len(ratios) + 1):
+        nl = H.n[l][0]
+        ql = random_state(3, nl, nl, seed=200 + l) * 0.5
+        H.set_level(l, ql)
+        w.set_state(ql, level=l)
+    dt = dt_of(cfg)
+    for _ in range(2):
+        H.advance(0, dt)
+    w.advance(2, dt)          # the captured pair of coarse steps
+    compare(w, H, f"rows {rows}, two coarse steps")
+    H.advance(0, dt)
+    w.advance(1, dt)
+    compare(w, H, f"rows {rows}, three coarse steps")
+
+
 def test_step_patches_interpolates_ghosts_in_time():
     """Level 1 stepped through wp_step_patches: its ghost ring is the coarse
     interpolation at the time weight its time gives between the coarse
