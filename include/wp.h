@@ -455,7 +455,8 @@ typedef struct wp_batch wp_batch;
 int wp_batch_create(wp_ctx *const *instances, int n, const double *dts, wp_batch **out);
 void wp_batch_destroy(wp_batch *b);
 /* nsteps steps of every instance, forward (adjoint = 0) or of the adjoint
- * states set up by wp_batch_adjoint_begin (adjoint = 1). */
+ * states that wp_batch_adjoint_run set up (adjoint = 1; WP_ESTATE before
+ * any). */
 int wp_batch_step(wp_batch *b, int nsteps, int adjoint);
 /* Adjoint runs of every instance in the batch: J[k], snapshot spec with
  * per-instance dt from the batch; every instance runs spec->nsteps steps. */
@@ -463,7 +464,12 @@ int wp_batch_adjoint_run(wp_batch *b, const wp_functional *J, int nsteps, int sn
 const char *wp_batch_last_error(const wp_batch *b);
 
 /* Tile shape of the patch-update kernels: rows per tile for the 2D
- * kernels (0: the built-in choice).  Exposed for the autotuner. */
+ * kernels (0: the built-in choice; 0 to 4096, WP_EINVAL otherwise), applied
+ * to every level's tile tables at once.  Heights 4, 6, 8, 12 and 16 take a
+ * compiled march (on refined levels two narrow tiles may share a wave, and
+ * at 4, 8 and 16 the finest level of ratio 4 also averages its last
+ * substep onto the level below in the step); other heights take the rolled
+ * march.  Exposed for the autotuner. */
 int wp_set_tile_rows(wp_ctx *ctx, int rows);
 int wp_get_tile_rows(const wp_ctx *ctx, int *rows);
 
