@@ -13,7 +13,10 @@ the benchmark measures, against the FP64 oracle (Sec. 2, 3, 4, 5.1.2):
   sampled cells, J;
 * one whole 2048 x 2048 shallow-water job (2380 adjoint + 2380 forward
   steps, 238 flag events) likewise (tests/golden/c3_job_oracle.json, written
-  by tests/golden/make_c3_job.py).
+  by tests/golden/make_c3_job.py);
+* one whole three-level job (coarse 256 x 256, ratios 4, 4, 2000 patches,
+  190 coarse steps, every level flagged at 19 events) likewise
+  (tests/golden/c2_job_oracle.json, written by tests/golden/make_c2_job.py).
 
 Bars: FP64 values within 1e-12 of the oracle's scale; flags bit-exact outside
 the band |m - tol| <= 1e-12 S, S = max(1, max|q| max|qhat|)."""
@@ -26,13 +29,14 @@ import pytest
 
 import oracle
 import paper_1511_03645_amd as wp
-from wp_synth import acoustics1d, acoustics2d, swe2d
+from wp_synth import acoustics1d, acoustics2d, acoustics2d_amr, swe2d
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_job_oracle.json")
 GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_job_oracle.json")
+GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_job_oracle.json")
 
 
 def close64(a, b, what, scale=None):
@@ -249,3 +253,60 @@ def test_c3_full_job_matches_stored_oracle():
         assert abs(counts[k] - ev["count"]) <= len(ev["band"]), f"event {k}"
     assert _digest(w.get_flags(0), gold["events"][-1]["band"]) == gold["events"][-1]["sha256"]
     assert np.array_equal(w.get_state(), q)
+
+
+@pytest.mark.timeout(600)
+def test_c2_full_job_matches_stored_oracle():
+    """One whole job of the three-level workload (coarse 256 x 256, ratios 4,
+    4, 400 + 1600 patches, 190 coarse steps) in the benchmark's launch
+    configuration (the adjoint run on the coarse grid, pairs of coarse steps
+    replayed as one graph, every level flagged every 10 coarse steps) against
+    the oracle's stored results of the same job: every level's flags at every
+    event by digest (patch cells outside the band), the counts, every level's
+    final state at sampled patch cells, and J."""
+    gold = json.load(open(GOLDEN_C2))
+    cfg = acoustics2d_amr(n0=gold["n0"], seed=gold["seed"])
+    h = cfg["hierarchy"]
+    N, every, dt = cfg["nsteps"], cfg["snap_every"], cfg["dt"]
+    cfg = dict(cfg, t_f=N * dt, t_s=N * dt)
+    assert (N, every, dt, cfg["tol"]) == (gold["nsteps"], gold["every"], gold["dt"], gold["tol"])
+    print(f"case C2 full job: {N} coarse steps, {N // every} flag events", flush=True)
+    w = wp.from_config(cfg, num_levels=3, ratios=tuple(h["ratios"]))
+    w.set_state(cfg["q0"])
+    w.regrid(0, h["levels"][1])
+    w.regrid(1, h["levels"][2])
+    init = [w.get_state(level=l) for l in range(3)]
+    own = []
+    for l in range(3):
+        n = init[l].shape[1]
+        m = np.zeros((n, n), dtype=bool)
+        for (i0, j0, a, b) in w.get_patches(l):
+            m[j0:j0 + b, i0:i0 + a] = True
+        own.append(m)
+    w.adjoint_run(cfg["functional"], dt, N, every)
+    for l in range(3):
+        w.set_state(init[l], level=l)
+        w.set_time(0.0, level=l)
+    t = 0.0
+    for k, ev in enumerate(gold["events"]):
+        for l in range(3):
+            fl, count = w.flag_adjoint(l, cfg["tol"], t, cfg["t_s"], cfg["t_f"])
+            e = ev["levels"][l]
+            f = np.where(own[l], fl, 0).astype(np.uint8)
+            assert _digest(f, e["band"]) == e["sha256"], (
+                f"event {k} level {l}: flags differ from the oracle's outside the band "
+                f"({count} flagged, oracle {e['count']})")
+            assert abs(count - e["count"]) <= len(e["band"]), (k, l, count, e["count"])
+        w.advance(every, dt)
+        t += every * dt
+        if k % 5 == 0:
+            print(f"  event {k}: counts {[e['count'] for e in ev['levels']]}", flush=True)
+    for l in range(3):
+        q = w.get_state(level=l)
+        fin = gold["final"][l]
+        idx = np.asarray(fin["cells"])
+        for c in range(3):
+            close64(q[c].ravel()[idx], np.asarray(fin["values"][c]), f"level {l} final component {c}",
+                    scale=fin["scale"])
+    J = w.functional_value(cfg["functional"], which=0)
+    assert abs(J - gold["J"]) <= TOL64 * abs(gold["J"]), (J, gold["J"])
