@@ -461,3 +461,37 @@ def test_richardson_valid_cells_of_a_box():
                 want[J, I] = (2 * I - margin >= i0 and 2 * I + 1 + margin <= i0 + w - 1 and
                               2 * J - margin >= j0 and 2 * J + 1 + margin <= j0 + h - 1)
         assert np.array_equal(v, want), margin
+
+
+def test_adjoint_snapshots_start_from_phi():
+    """The time-reversed adjoint starts from phi (Sec. 4: qhat at t_f is the
+    functional's phi): snapshot 0 is phi itself, and a run of N steps with a
+    snapshot every k holds N / k + 1 of them."""
+    from wp_synth import acoustics2d
+    cfg = acoustics2d(64, seed=1)
+    snaps, _ = oracle.adjoint_run(cfg, nsteps=20, snap_every=5)
+    assert snaps.shape[0] == 5
+    assert np.array_equal(snaps[0], oracle.phi(cfg))
+    assert not np.array_equal(snaps[1], snaps[0])
+
+
+def test_richardson_flag_is_strict():
+    """On a constant state the estimate is zero everywhere, so a tolerance of
+    0 flags nothing (the measure must exceed the tolerance), weighted or not."""
+    from wp_synth import acoustics2d
+    cfg = acoustics2d(32, seed=1)
+    q = np.ones((3, 32, 32)) * 0.25
+    fl, m, _ = oracle.richardson_flag(cfg, q, cfg["dt"], 0.0)
+    assert np.all(m == 0.0) and fl.sum() == 0
+
+
+def test_disc_functional_is_a_closed_disc():
+    """Cell centres at exactly the disc's radius belong to it: on a grid of
+    cells 0.25 wide, a disc of radius 0.5 centred on a cell centre holds the
+    centre, its 4 neighbours at 0.25, 4 diagonal ones at 0.25 sqrt 2, and the
+    4 at exactly 0.5 (13 cells)."""
+    n, dx = 16, 0.25
+    f = dict(kind="disc", cx=2.125, cy=1.875, r=0.5, x0=0, x1=0, y0=0, y1=0, component=1)
+    cfg = dict(kind="acoustics2d", nx=n, ny=n, xlo=0.0, xhi=n * dx, ylo=0.0, yhi=n * dx, dx=dx, dy=dx, functional=f)
+    ph = oracle.phi(cfg)
+    assert ph[1].sum() == 13 and ph[0].sum() == 0 and ph[2].sum() == 0
