@@ -173,6 +173,40 @@ def test_swe_refined_level_flags_match_oracle():
     assert [tuple(p) for p in w.get_patches(2)] == [tuple(b) for b in boxes2]
 
 
+def test_mixed_precision_adjoint_flags_match_oracle_on_the_same_inputs():
+    """The mixed-precision adjoint flag (eta in FP64, the momenta and the
+    snapshots in FP32, the measure in FP64) on level 0 and on the refined
+    level 1 (snapshots bilinear to its cells), against the oracle's flag
+    taken on the same inputs: the states and snapshots the GPU holds, read
+    back exactly.  Flags equal outside the band, counts equal."""
+    n0, ratios, boxes, bc = LAYOUTS[0]
+    cfg, H, w = build(n0, ratios, boxes[:1], bc, precision=wp.MIXED)
+    # a gauge box wide enough to hold level-0 cell centres of this coarse grid
+    gx, gy = cfg["gauge"]
+    cfg["functional"] = dict(cfg["functional"], x0=gx - 150e3, x1=gx + 40e3, y0=gy - 150e3, y1=gy + 150e3)
+    w.advance(2, cfg["dt"])
+    nsteps, every = 20, 5
+    w.adjoint_run(cfg["functional"], cfg["dt"], nsteps, every)
+    snaps = np.stack([w.get_snapshot(n) for n in range(nsteps // every + 1)])
+    tf = nsteps * cfg["dt"]
+    t = 0.0                  # the window over every snapshot (t_s = 0)
+    for level, ratio in ((0, 1), (1, ratios[0])):
+        q = w.get_state(level=level)
+        _, m_all = oracle.flag(q, snaps, t, 0.0, tf, every * cfg["dt"], 0.0, ratio=ratio)
+        inside = np.zeros(q.shape[1:], dtype=bool)
+        for (i0, j0, nx, ny) in w.get_patches(level):
+            inside[j0:j0 + ny, i0:i0 + nx] = True
+        pos = m_all[inside & (m_all > 0)]
+        assert pos.size > 100, (level, pos.size)
+        tol = float(np.median(pos))
+        ref = ((m_all > tol) & inside).astype(np.uint8)
+        fl, n = w.flag_adjoint(level, tol, t, 0.0, tf)
+        S = max(1.0, float(np.abs(q[:, inside]).max()) * float(np.abs(snaps).max()))
+        band = np.abs(m_all - tol) <= 1e-12 * S
+        assert np.array_equal(fl[~band & inside], ref[~band & inside]), level
+        assert abs(n - int(ref.sum())) <= int((band & inside).sum()) and n > 0, (level, n, int(ref.sum()))
+
+
 REFLUX_LAYOUTS = [
     # walls all round: the water volume is conserved
     (32, (2, 2), [[(40, 8, 20, 32), (8, 8, 16, 16)], [(88, 24, 24, 32)]], (1, 1, 1, 1)),
