@@ -214,3 +214,38 @@ def test_flagged_run_recaptured_when_the_store_spacing_changes():
     got, _ = a.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
     ref, _ = b.forward_flagged(dt, N, every, cfg["tol"], cfg["t_s"], cfg["t_f"])
     assert got == ref and sum(ref) > 0
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_fp32_flags_match_oracle_on_the_same_inputs(fused):
+    """The FP32 path's adjoint flag (the measure in FP64 from FP32 states and
+    snapshots), fused into the first two-step launch of a flag block or
+    taken by wp_flag_adjoint, against the oracle's flag on the same inputs:
+    the state at the event and the snapshots the GPU holds, read back
+    exactly.  Flags equal outside the band, counts equal."""
+    cfg = acoustics2d(n=256, seed=1)
+    every, nsteps = 10, 60
+    tf = nsteps * cfg["dt"]
+    w = wp.from_config(cfg, precision=wp.FP32)
+    assert w.get_step_pairs() > 0
+    w.adjoint_run(cfg["functional"], cfg["dt"], nsteps, every)
+    snaps = np.stack([w.get_snapshot(k) for k in range(nsteps // every + 1)])
+    # a state with structure everywhere the adjoint reaches
+    w.set_state(random_state(3, 256, 256, seed=17))
+    t = 20 * cfg["dt"]
+    w.set_time(t)
+    q = w.get_state()
+    _, m_all = oracle.flag(q, snaps, t, 0.0, tf, every * cfg["dt"], 0.0)
+    pos = m_all[m_all > 0]
+    assert pos.size > 1000
+    tol = float(np.median(pos))
+    ref = (m_all > tol).astype(np.uint8)
+    if fused:
+        counts, _ = w.forward_flagged(cfg["dt"], every, every, tol, 0.0, tf)
+        fl, n = w.get_flags(0), counts[0]
+    else:
+        fl, n = w.flag_adjoint(0, tol, t, 0.0, tf)
+    S = max(1.0, float(np.abs(q).max()) * float(np.abs(snaps).max()))
+    band = np.abs(m_all - tol) <= 1e-12 * S
+    assert np.array_equal(fl[~band], ref[~band])
+    assert abs(n - int(ref.sum())) <= int(band.sum()) and n > 0
