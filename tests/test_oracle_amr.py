@@ -568,3 +568,77 @@ def test_dilation_of_a_cell_is_a_box():
         want = np.zeros_like(f)
         want[0:k + 1, 16 - k:17] = True
         assert np.array_equal(amr.dilate(f, k), want)
+
+
+def _edge_source_sum(H, l, covered=None):
+    """Sum over the distinct edges of level l's patches (those between two
+    cells that are not covered by a finer level, when `covered` is given) of
+    S_e L_e, S_e = F_left - F_right the difference of the edge's flux as its
+    two cells saw it in the level's last step (f-hat of the cell's state plus
+    the fluctuation it received plus the correction flux: eq. swe's
+    bathymetry source of the edge, zero for a conservation law), L_e the
+    face length."""
+    nx, ny = H.n[l]
+    dx, dy = H.dx[l]
+    seen = set()
+    tot = np.zeros(3)
+    for pidx, ((i0, j0, w, h), xe, ye) in enumerate(H.edges[l]):
+        for axis, (ni, nj), L in ((0, (w + 1, h), dy), (1, (w, h + 1), dx)):
+            for lj in range(nj):
+                for li in range(ni):
+                    gi, gj = (i0 + li) % nx, (j0 + lj) % ny
+                    key = (axis, gi, gj)
+                    if key in seen:
+                        continue
+                    seen.add(key)
+                    if covered is not None:
+                        ai, aj = ((gi - 1) % nx, gj) if axis == 0 else (gi, (gj - 1) % ny)
+                        if covered[gj, gi] or covered[aj, ai]:
+                            continue
+                    S = (H._edge_flux(l, (pidx, axis, li, lj, -1)) - H._edge_flux(l, (pidx, axis, li, lj, +1)))
+                    tot += S * L
+    return tot
+
+
+def test_swe_reflux_balances_the_composite_with_every_edge_source():
+    """Over a sloping bottom momentum is not conserved: on a uniform grid
+    each step changes the sum of Q dA by -dt times the sum over edges of the
+    edge's bathymetry source S_e (the two sides' views of its flux differ by
+    it) times the face length.  On two levels with the flux correction the
+    composite sum changes by exactly the sources of the composite's edges:
+    coarse edges between uncovered cells, and every edge of the finer level
+    in each substep, those along the coarse-fine boundary included (the
+    correction takes their flux from the coarse cell's side, so their sources
+    stay in the balance).  Periodic boundaries, no edge on the domain's
+    boundary."""
+    cfg = _swe_levels(n0=32, ratios=(2,))
+    cfg["bc"] = [amr.BC_PERIODIC] * 4
+    H = amr.Hierarchy(cfg, (2,), [], B_levels=cfg["B_levels"], reflux=True)
+    n = cfg["nx"]
+    r = random_state(3, n, n, seed=6)
+    q = np.zeros((3, n, n))
+    q[0] = cfg["q0"][0] + 0.3 * r[0]
+    h = q[0] - cfg["B"]
+    q[1] = 0.05 * r[1] * h
+    q[2] = 0.05 * r[2] * h
+    H.set_level(0, q)
+    H.regrid(0, [(40, 8, 20, 32), (8, 8, 16, 16)])
+    covered = np.zeros((n, n), dtype=bool)
+    for (i0, j0, w, hh) in H.patches[1]:
+        covered[j0 // 2:(j0 + hh) // 2, i0 // 2:(i0 + w) // 2] = True
+    acc = np.zeros(3)
+    step = H.step_level
+
+    def counted_step(l, dt, alpha=None):
+        step(l, dt, alpha)
+        acc[:] += -dt * _edge_source_sum(H, l, covered if l == 0 else None)
+    H.step_level = counted_step
+    dA = H.dx[0][0] * H.dx[0][1]
+    for _ in range(2):
+        acc[:] = 0.0
+        s0 = H.q[0].sum(axis=(1, 2)) * dA
+        H.advance(0, cfg["dt"])
+        change = H.q[0].sum(axis=(1, 2)) * dA - s0
+        scale = np.abs(H.q[0]).sum(axis=(1, 2)) * dA
+        assert np.abs(acc[1:]).max() > 1e-9 * scale[1:].max(), acc     # the sources matter
+        assert (np.abs(change - acc) <= 1e-13 * scale).all(), (change, acc, scale)
